@@ -1,0 +1,213 @@
+/*
+ * aeb.h -- C ABI of the MI355X Monte Carlo library for emergency-braking (AEB)
+ * evaluation under uncertainty.
+ *
+ * The operations follow "Real-Time GPU-Accelerated Monte Carlo Evaluation of
+ * Safety-Critical AEB Systems Under Uncertainty" (Karjol, Alawneh):
+ *   - per-sample parameter vectors xi^(i) drawn from a fixed seed (Sec. IV-A..C);
+ *   - a rollout of the longitudinal model of eq. (1)-(9) per sample until the
+ *     vehicle stops (eq. (3), (10)), integrated with a fixed step (Sec. IV-D);
+ *   - the statistics of Sec. VI: P(collision | H0) = P(D_stop > H0) (eq. (20)),
+ *     the collision-risk curve and minimum safe headways (Sec. VI-C), moments of
+ *     the stopping distance (Sec. VI-B, Table I).
+ * Extensions beyond the paper, all named in its future-work section (Sec. VIII):
+ *   brake dead time, rolling resistance, a decelerating lead vehicle, and an
+ *   FP32 form with compensated summation (mixed precision).
+ *
+ * Conventions
+ *   - Every function returns AEB_OK (0) or a negative AEB_E* code; no C++
+ *     exception crosses this boundary.  aeb_last_error() gives a message for the
+ *     last failure on the calling thread.
+ *   - Pointers documented as "device" must point at memory of the current HIP
+ *     device (hipMalloc'd, e.g. by torch); "host" pointers at ordinary memory.
+ *     The caller owns every pointer it passes; the library never frees them.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the legacy default
+ *     stream).  Device work is enqueued on it; functions documented as
+ *     "asynchronous" return before the work completes.
+ *   - All functions act on the HIP device that is current on the calling thread.
+ *   - The library keeps a per-device scratch arena for sorting and reduction
+ *     partials; it grows on demand (hipMalloc) and lives until process exit.
+ */
+#ifndef AEB_H
+#define AEB_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---- */
+#define AEB_OK 0
+#define AEB_EINVAL (-1)    /* an argument or scenario failed validation */
+#define AEB_ENOMEM (-2)    /* a device or host allocation failed, or a request exceeds capacity */
+#define AEB_EAGAIN (-3)    /* not ready yet (serving: request pending, queue full) */
+#define AEB_EDEVICE (-4)   /* a HIP runtime call failed */
+#define AEB_ENOTFOUND (-5) /* unknown ticket */
+
+/* ---- enumerations ---- */
+enum { AEB_EULER = 0, AEB_RK4 = 1 };                 /* integrator (Sec. IV-D) */
+enum { AEB_OBS_NONE = 0, AEB_OBS_STATIONARY = 1, AEB_OBS_LEAD = 2 };
+enum { AEB_DIST_CONST = 0, AEB_DIST_UNIFORM = 1, AEB_DIST_NORMAL = 2, AEB_DIST_TRUNC_NORMAL = 3 };
+enum { AEB_FP64 = 0, AEB_FP32C = 1 };                /* arithmetic of the rollout */
+/* status byte of one sample: low two bits = why it ended, bit 2 = collision latched */
+enum { AEB_END_STOP = 1, AEB_END_IMPACT = 2, AEB_END_HORIZON = 3, AEB_COLLIDED = 4 };
+/* counter slots of the random parameters, one generator stream each */
+enum {
+  AEB_SLOT_V0 = 0, AEB_SLOT_MU = 1, AEB_SLOT_MASS = 2, AEB_SLOT_GRADE = 3, AEB_SLOT_CDA = 4,
+  AEB_SLOT_CRR = 5, AEB_SLOT_TAU = 6, AEB_SLOT_GAP = 7, AEB_SLOT_LEAD = 8
+};
+
+/* Distribution of one uncertain parameter (eq. (11)-(15) use NORMAL).
+ * CONST: value p0.  UNIFORM: p0 + (p1 - p0) u.  NORMAL: p0 + p1 z with z the
+ * cosine branch of Box-Muller.  TRUNC_NORMAL: NORMAL redrawn (attempt j uses
+ * its own counter, j < 16) until it falls in [lo, hi], then clamped. */
+typedef struct {
+  int32_t kind;
+  int32_t reserved;
+  double p0, p1, lo, hi;
+} aeb_dist;
+
+/* One braking scenario (Sec. III-IV).  Units SI; angles in radians.
+ *   seed, scenario_id: key and counter words of the generator; sample i of a
+ *     scenario is a pure function of (seed, scenario_id, i).
+ *   n_samples: N, 1 <= N <= 2^31 - 1.
+ *   integrator: AEB_EULER (explicit Euler, four fused multiply-adds per step
+ *     unless nofma) or AEB_RK4 (classical RK4, no fused operations).
+ *   obstacle: NONE (only the stopping distance), STATIONARY (obstacle at the
+ *     sampled gap; the rollout runs to a stop with the collision flag latched,
+ *     or ends at impact if impact_exit), LEAD (lead vehicle starting at the
+ *     sampled gap with the ego's initial speed and braking at the sampled
+ *     lead_decel until it stands still; the rollout ends at impact).  LEAD needs
+ *     AEB_EULER.
+ *   dt, horizon: step and T_max; the rollout takes at most llround(horizon/dt)
+ *     steps.  dead_time: the brake command is zero for the first
+ *     llround(dead_time/dt) steps and a_cmd afterwards.
+ *   g, rho, h_cog, wheelbase: eq. (4)-(5) constants.
+ *   v0 .. lead_decel: distributions; cda is the product C_d A_f (m^2), grade is
+ *     theta, tau the actuator time constant of eq. (6). */
+typedef struct {
+  uint64_t seed;
+  uint64_t scenario_id;
+  int64_t n_samples;
+  int32_t integrator;
+  int32_t obstacle;
+  int32_t impact_exit;
+  int32_t nofma;
+  double dt, horizon, dead_time, a_cmd, g, rho, h_cog, wheelbase;
+  aeb_dist v0, mu, mass, grade, cda, crr, tau, gap, lead_decel;
+} aeb_scenario;
+
+/* Structure-of-arrays parameter columns, each `n` doubles (host or device,
+ * as the called function states).  sin_grade/cos_grade hold sin/cos of grade. */
+typedef struct {
+  double *v0, *mu, *mass, *grade, *sin_grade, *cos_grade, *cda, *crr, *tau, *gap, *lead_decel;
+  int64_t n;
+} aeb_params;
+
+/* Per-sample outputs (device), each `n` elements:
+ *   dist: position x at exit (the stopping distance D_stop when status is STOP);
+ *   status: AEB_END_* | AEB_COLLIDED;  steps: integration steps taken;
+ *   margin: min over steps of (gap + x_lead) - x;
+ *   v_impact: ego minus lead speed at the first step with x > gap + x_lead, else 0. */
+typedef struct {
+  double* dist;
+  uint8_t* status;
+  int32_t* steps;
+  double* margin;
+  float* v_impact;
+  int64_t n;
+} aeb_outputs;
+
+#define AEB_MAX_RISK 16
+#define AEB_MAX_MARGIN_Q 4
+#define AEB_MAX_GRID 1024
+
+/* What aeb_reduce computes beyond the counts and moments:
+ *   risk[j] (0 <= r < 1): minimum safe headway H(r) = the smallest sample value v
+ *     with #{D_i > v} <= floor(r N), D censored to +inf unless status is STOP;
+ *   margin_q[j] (0 <= p < 1): lower quantile = the (floor(p N)+1)-th smallest margin;
+ *   grid: n_grid (0 or 2..1024) headways H0_j = grid_lo + j (grid_hi - grid_lo)/(n_grid-1)
+ *     for the collision-risk curve P(D > H0_j). */
+typedef struct {
+  int32_t n_risk, n_margin_q, n_grid, reserved;
+  double risk[AEB_MAX_RISK];
+  double margin_q[AEB_MAX_MARGIN_Q];
+  double grid_lo, grid_hi;
+} aeb_reduce_req;
+
+/* Statistics of one batch of outputs.  Counts are exact; p_collision and
+ * risk_p are count/N with one correctly rounded division; mean/sd are over
+ * STOP samples (sd with N_stop - 1; NaN when undefined); headway/margin_q are
+ * exact order statistics of the outputs. */
+typedef struct {
+  int64_t n, n_collide, n_stop, n_impact, n_horizon;
+  double p_collision, mean_dist, sd_dist, dist_min, dist_max;
+  double headway[AEB_MAX_RISK];
+  double margin_min, margin_mean;
+  double margin_q[AEB_MAX_MARGIN_Q];
+  float v_impact_max;
+  int32_t reserved;
+  int64_t risk_count[AEB_MAX_GRID];
+  double risk_p[AEB_MAX_GRID];
+} aeb_stats;
+
+/* Message of the last failure on this thread ("" if none). */
+const char* aeb_last_error(void);
+
+/* Library ABI version (increments on incompatible changes). */
+int aeb_version(void);
+
+/* Validate a scenario: AEB_OK or AEB_EINVAL (with aeb_last_error() set).
+ * Rejects N outside [1, 2^31-1]; dt, horizon not positive and finite;
+ * horizon/dt outside [1, 2^31-1]; negative dead_time; wheelbase <= 0; unknown
+ * enums; non-finite distribution parameters, sd < 0, uniform p0 > p1,
+ * truncation lo >= hi; a tau distribution that can reach 0 (or, for Euler,
+ * values below dt); RK4 combined with a lead vehicle. */
+int aeb_validate(const aeb_scenario* scn);
+
+/* Raw generator output (Sec. IV-B "fixed seed"; Philox4x32-10 of Salmon et
+ * al., SC'11): for sample i in [first, first+count) the call with counter
+ * (i, slot | attempt << 8, lo32(scenario_id), hi32(scenario_id)) and key
+ * (lo32(seed), hi32(seed)) yields words o0..o3; out[2k] and out[2k+1] are
+ * ((w >> 12) + 0.5) * 2^-52 for w = o1:o0 and o3:o2.  `out` is host memory
+ * (on_device = 0, computed on the host) or device memory (on_device = 1,
+ * computed by a kernel, asynchronous on `stream`).  The two sides give
+ * bit-identical values.  i must stay below 2^32. */
+int aeb_uniforms(uint64_t seed, uint64_t scenario_id, int64_t first, int64_t count, uint32_t slot,
+                 uint32_t attempt, double* out, int on_device, void* stream);
+
+/* Draw parameter vectors xi^(i) for samples [first, first+count) into `out`
+ * (columns of at least `count` doubles; out->n is ignored).  on_device = 0:
+ * the paper's plain method (Sec. IV-C) -- drawn on the host (all host cores,
+ * host libm), `out` host memory, synchronous.  on_device = 1: drawn by a
+ * kernel into device columns, asynchronous on `stream`; uniforms are
+ * bit-identical to the host's, transcendentals may differ by a few ulp. */
+int aeb_sample_params(const aeb_scenario* scn, int64_t first, int64_t count, const aeb_params* out,
+                      int on_device, void* stream);
+
+/* Roll out all scn->n_samples samples (Sec. IV-D, V): per sample, integrate
+ * eq. (7)-(9) from x = 0, v = v0, a = 0 until v <= 0 (STOP), the obstacle is
+ * passed (IMPACT, if the rollout ends there) or the horizon is reached
+ * (HORIZON), and write one entry of each output column.
+ *   params: device parameter columns with params->n == n_samples (the plain
+ *     method), or NULL to draw each sample's parameters inside the kernel from
+ *     the counter generator (no per-sample input traffic).
+ *   precision: AEB_FP64 (results equal to a sequential FP64 evaluation of the
+ *     same steps) or AEB_FP32C (FP32 state with compensated distance
+ *     accumulation; FP64 derived constants and final distance).
+ *   out: device output columns with out->n == n_samples.
+ * Asynchronous on `stream`.  May grow the scratch arena on first use. */
+int aeb_rollout(const aeb_scenario* scn, const aeb_params* params, int precision,
+                const aeb_outputs* out, void* stream);
+
+/* Statistics of `out` (device columns, out->n >= 1) as described for
+ * aeb_stats/aeb_reduce_req.  Kernels run on `stream`; the function waits for
+ * them and fills *host_out before returning. */
+int aeb_reduce(const aeb_outputs* out, const aeb_reduce_req* req, aeb_stats* host_out,
+               void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AEB_H */

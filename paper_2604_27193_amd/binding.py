@@ -1,0 +1,263 @@
+"""ctypes binding of ``libaeb.so`` (declared in include/aeb.h).
+
+Argument marshalling only: scenario dicts become ``aeb_scenario`` structs,
+torch tensors become raw device pointers, the current torch stream becomes
+the HIP stream.  Every computation runs in the library's HIP kernels (or, for
+``sample_params(..., device=False)``, in the library's host sampler, which is
+the paper's CPU sampling step).  If the library is not built, loading fails
+with an error; there is no fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libaeb.so")
+
+COLUMNS = ("v0", "mu", "mass", "grade", "sin_grade", "cos_grade", "cda", "crr", "tau", "gap",
+           "lead_decel")
+DISTS = ("v0", "mu", "mass", "grade", "cda", "crr", "tau", "gap", "lead_decel")
+INTEGRATORS = {"euler": 0, "rk4": 1}
+OBSTACLES = {"none": 0, "stationary": 1, "lead": 2}
+DIST_KINDS = {"const": 0, "uniform": 1, "normal": 2, "trunc_normal": 3}
+PRECISIONS = {"fp64": 0, "fp32c": 1}
+
+OK, EINVAL, ENOMEM, EAGAIN, EDEVICE, ENOTFOUND = 0, -1, -2, -3, -4, -5
+END_STOP, END_IMPACT, END_HORIZON, COLLIDED = 1, 2, 3, 4
+
+EXPORTS = ("aeb_last_error", "aeb_version", "aeb_validate", "aeb_uniforms", "aeb_sample_params",
+           "aeb_rollout", "aeb_reduce")
+
+
+class AebError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"aeb error {code}: {msg}")
+        self.code = code
+
+
+class Dist(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("p0", C.c_double),
+                ("p1", C.c_double), ("lo", C.c_double), ("hi", C.c_double)]
+
+
+class Scenario(C.Structure):
+    _fields_ = ([("seed", C.c_uint64), ("scenario_id", C.c_uint64), ("n_samples", C.c_int64),
+                 ("integrator", C.c_int32), ("obstacle", C.c_int32),
+                 ("impact_exit", C.c_int32), ("nofma", C.c_int32)]
+                + [(f, C.c_double) for f in ("dt", "horizon", "dead_time", "a_cmd", "g", "rho",
+                                             "h_cog", "wheelbase")]
+                + [(f, Dist) for f in DISTS])
+
+
+class Params(C.Structure):
+    _fields_ = [(f, C.c_void_p) for f in COLUMNS] + [("n", C.c_int64)]
+
+
+class Outputs(C.Structure):
+    _fields_ = [("dist", C.c_void_p), ("status", C.c_void_p), ("steps", C.c_void_p),
+                ("margin", C.c_void_p), ("v_impact", C.c_void_p), ("n", C.c_int64)]
+
+
+class ReduceReq(C.Structure):
+    _fields_ = [("n_risk", C.c_int32), ("n_margin_q", C.c_int32), ("n_grid", C.c_int32),
+                ("reserved", C.c_int32), ("risk", C.c_double * 16),
+                ("margin_q", C.c_double * 4), ("grid_lo", C.c_double), ("grid_hi", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_collide", C.c_int64), ("n_stop", C.c_int64),
+                ("n_impact", C.c_int64), ("n_horizon", C.c_int64),
+                ("p_collision", C.c_double), ("mean_dist", C.c_double), ("sd_dist", C.c_double),
+                ("dist_min", C.c_double), ("dist_max", C.c_double),
+                ("headway", C.c_double * 16), ("margin_min", C.c_double),
+                ("margin_mean", C.c_double), ("margin_q", C.c_double * 4),
+                ("v_impact_max", C.c_float), ("reserved", C.c_int32),
+                ("risk_count", C.c_int64 * 1024), ("risk_p", C.c_double * 1024)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the built library (build it with __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        L.aeb_last_error.restype = C.c_char_p
+        L.aeb_validate.argtypes = [P(Scenario)]
+        L.aeb_uniforms.argtypes = [C.c_uint64, C.c_uint64, C.c_int64, C.c_int64, C.c_uint32,
+                                   C.c_uint32, C.c_void_p, C.c_int, C.c_void_p]
+        L.aeb_sample_params.argtypes = [P(Scenario), C.c_int64, C.c_int64, P(Params), C.c_int,
+                                        C.c_void_p]
+        L.aeb_rollout.argtypes = [P(Scenario), P(Params), C.c_int, P(Outputs), C.c_void_p]
+        L.aeb_reduce.argtypes = [P(Outputs), P(ReduceReq), P(Stats), C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise AebError(rc, lib().aeb_last_error().decode())
+    return rc
+
+
+def _dist(spec):
+    d = Dist()
+    d.kind = DIST_KINDS[spec[0]]
+    vals = [float(v) for v in spec[1:]] + [0.0] * (4 - len(spec[1:]))
+    d.p0, d.p1, d.lo, d.hi = vals
+    if spec[0] == "const":
+        d.p1 = 0.0
+    return d
+
+
+def scenario(d):
+    """Marshal a scenario dict (see workloads.py) into ``aeb_scenario``."""
+    s = Scenario()
+    s.seed = int(d["seed"]) & 0xFFFFFFFFFFFFFFFF
+    s.scenario_id = int(d["scenario_id"]) & 0xFFFFFFFFFFFFFFFF
+    s.n_samples = int(d["n_samples"])
+    s.integrator = INTEGRATORS[d["integrator"]]
+    s.obstacle = OBSTACLES[d["obstacle"]]
+    s.impact_exit = int(bool(d.get("impact_exit", False)))
+    s.nofma = int(bool(d.get("nofma", False)))
+    for f in ("dt", "horizon", "dead_time", "a_cmd", "g", "rho", "h_cog", "wheelbase"):
+        setattr(s, f, float(d[f]))
+    for f in DISTS:
+        setattr(s, f, _dist(d[f]))
+    return s
+
+
+def validate(d):
+    return lib().aeb_validate(C.byref(scenario(d)))
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def uniforms(seed, scenario_id, first, count, slot, attempt=0, device=True, stream=None):
+    """(count, 2) float64 uniforms: a torch tensor on cuda:0 or a host numpy array."""
+    if device:
+        torch = _torch()
+        out = torch.empty((count, 2), dtype=torch.float64, device="cuda")
+        _check(lib().aeb_uniforms(seed, scenario_id, first, count, slot, attempt,
+                                  C.c_void_p(out.data_ptr()), 1, _stream(stream)))
+        return out
+    out = np.empty((count, 2), dtype=np.float64)
+    _check(lib().aeb_uniforms(seed, scenario_id, first, count, slot, attempt,
+                              C.c_void_p(out.ctypes.data), 0, None))
+    return out
+
+
+def alloc_params(n, device=True, pinned=False):
+    """Dict of eleven float64 columns: cuda tensors, pinned host tensors or numpy arrays."""
+    if device or pinned:
+        torch = _torch()
+        if device:
+            return {c: torch.empty(n, dtype=torch.float64, device="cuda") for c in COLUMNS}
+        return {c: torch.empty(n, dtype=torch.float64, pin_memory=True) for c in COLUMNS}
+    return {c: np.empty(n, dtype=np.float64) for c in COLUMNS}
+
+
+def _ptr(a):
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _params_struct(cols, n):
+    p = Params()
+    for c in COLUMNS:
+        setattr(p, c, _ptr(cols[c]))
+    p.n = n
+    return p
+
+
+def sample_params(d, first=0, count=None, device=True, out=None, stream=None):
+    """Draw parameter columns: on the GPU (device=True) or on the host cores."""
+    if count is None:
+        count = int(d["n_samples"]) - first
+    if out is None:
+        out = alloc_params(count, device=device)
+    s = scenario(d)
+    st = _stream(stream) if device else None
+    _check(lib().aeb_sample_params(C.byref(s), first, count, C.byref(_params_struct(out, count)),
+                                   1 if device else 0, st))
+    return out
+
+
+def alloc_outputs(n):
+    torch = _torch()
+    return {"dist": torch.empty(n, dtype=torch.float64, device="cuda"),
+            "status": torch.empty(n, dtype=torch.uint8, device="cuda"),
+            "steps": torch.empty(n, dtype=torch.int32, device="cuda"),
+            "margin": torch.empty(n, dtype=torch.float64, device="cuda"),
+            "v_impact": torch.empty(n, dtype=torch.float32, device="cuda")}
+
+
+def _outputs_struct(out):
+    o = Outputs()
+    for k in ("dist", "status", "steps", "margin", "v_impact"):
+        setattr(o, k, out[k].data_ptr())
+    o.n = out["dist"].numel()
+    return o
+
+
+def rollout(d, params=None, precision="fp64", out=None, stream=None):
+    """Roll out every sample of scenario `d` on the GPU; params=None draws in-kernel."""
+    n = int(d["n_samples"])
+    if out is None:
+        out = alloc_outputs(n)
+    s = scenario(d)
+    pp = C.byref(_params_struct(params, n)) if params is not None else None
+    _check(lib().aeb_rollout(C.byref(s), pp, PRECISIONS[precision],
+                             C.byref(_outputs_struct(out)), _stream(stream)))
+    return out
+
+
+def reduce_request(risk=(), margin_q=(), grid=None):
+    req = ReduceReq()
+    req.n_risk = len(risk)
+    for j, r in enumerate(risk):
+        req.risk[j] = r
+    req.n_margin_q = len(margin_q)
+    for j, p in enumerate(margin_q):
+        req.margin_q[j] = p
+    if grid is not None:
+        req.grid_lo, req.grid_hi, req.n_grid = float(grid[0]), float(grid[1]), int(grid[2])
+    return req
+
+
+def stats_dict(st, n_risk, n_mq, n_grid):
+    return {
+        "n": st.n, "n_collide": st.n_collide, "n_stop": st.n_stop, "n_impact": st.n_impact,
+        "n_horizon": st.n_horizon, "p_collision": st.p_collision, "mean_dist": st.mean_dist,
+        "sd_dist": st.sd_dist, "dist_min": st.dist_min, "dist_max": st.dist_max,
+        "headway": list(st.headway)[:n_risk], "margin_min": st.margin_min,
+        "margin_mean": st.margin_mean, "margin_q": list(st.margin_q)[:n_mq],
+        "v_impact_max": st.v_impact_max,
+        "risk_count": np.array(st.risk_count[:n_grid], dtype=np.int64),
+        "risk_p": np.array(st.risk_p[:n_grid], dtype=np.float64),
+    }
+
+
+def reduce(out, risk=(), margin_q=(), grid=None, stream=None):
+    """Statistics of device outputs (blocks until they are on the host)."""
+    req = reduce_request(risk, margin_q, grid)
+    st = Stats()
+    _check(lib().aeb_reduce(C.byref(_outputs_struct(out)), C.byref(req), C.byref(st),
+                            _stream(stream)))
+    return stats_dict(st, req.n_risk, req.n_margin_q, req.n_grid)

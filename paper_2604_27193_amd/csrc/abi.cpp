@@ -1,0 +1,267 @@
+// abi.cpp -- the C ABI of include/aeb.h: argument checking, scenario
+// validation, the host-side sampler of the plain method (Sec. IV-C) and
+// dispatch to the kernel launchers.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include <sched.h>
+
+#include "aeb.h"
+#include "aeb_common.h"
+#include "aeb_runtime.h"
+
+namespace aeb {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+// ---------------------------------------------------------------------------
+// scratch arena
+// ---------------------------------------------------------------------------
+namespace {
+struct Arena {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+std::mutex g_arena_mu;
+Arena g_arena[64];
+}  // namespace
+
+void* scratch(size_t bytes, hipStream_t stream) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    set_error("scratch: no current HIP device");
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_arena_mu);
+  Arena& a = g_arena[dev];
+  if (a.bytes >= bytes) return a.ptr;
+  // work queued on any stream may still use the old block
+  if (a.ptr) {
+    (void)stream;
+    if (hipDeviceSynchronize() != hipSuccess || hipFree(a.ptr) != hipSuccess) {
+      set_error("scratch: could not release the previous arena");
+      return nullptr;
+    }
+    a.ptr = nullptr;
+    a.bytes = 0;
+  }
+  size_t want = bytes < (size_t(1) << 20) ? (size_t(1) << 20) : bytes;
+  want = (want + 4095) & ~size_t(4095);
+  if (hipMalloc(&a.ptr, want) != hipSuccess) {
+    a.ptr = nullptr;
+    set_error("scratch: hipMalloc of " + std::to_string(want) + " bytes failed");
+    return nullptr;
+  }
+  a.bytes = want;
+  return a.ptr;
+}
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+static bool dist_ok(const aeb_dist& d) {
+  switch (d.kind) {
+    case AEB_DIST_CONST:
+      return std::isfinite(d.p0);
+    case AEB_DIST_UNIFORM:
+      return std::isfinite(d.p0) && std::isfinite(d.p1) && d.p0 <= d.p1;
+    case AEB_DIST_NORMAL:
+      return std::isfinite(d.p0) && std::isfinite(d.p1) && d.p1 >= 0.0;
+    case AEB_DIST_TRUNC_NORMAL:
+      return std::isfinite(d.p0) && std::isfinite(d.p1) && d.p1 >= 0.0 && std::isfinite(d.lo) &&
+             std::isfinite(d.hi) && d.lo < d.hi;
+    default:
+      return false;
+  }
+}
+
+// lowest value a distribution can produce
+static double support_min(const aeb_dist& d) {
+  switch (d.kind) {
+    case AEB_DIST_CONST:
+    case AEB_DIST_UNIFORM:
+      return d.p0;
+    case AEB_DIST_TRUNC_NORMAL:
+      return d.lo;
+    default:
+      return d.p1 == 0.0 ? d.p0 : -INFINITY;
+  }
+}
+
+int validate(const aeb_scenario& s) {
+  if (s.n_samples < 1 || s.n_samples > 0x7fffffffLL) return fail(AEB_EINVAL, "n_samples out of [1, 2^31-1]");
+  if (s.integrator != AEB_EULER && s.integrator != AEB_RK4) return fail(AEB_EINVAL, "unknown integrator");
+  if (s.obstacle < AEB_OBS_NONE || s.obstacle > AEB_OBS_LEAD) return fail(AEB_EINVAL, "unknown obstacle");
+  if (s.integrator == AEB_RK4 && s.obstacle == AEB_OBS_LEAD)
+    return fail(AEB_EINVAL, "the lead-vehicle model needs the Euler integrator");
+  if (s.impact_exit != 0 && s.impact_exit != 1) return fail(AEB_EINVAL, "impact_exit must be 0 or 1");
+  if (s.nofma != 0 && s.nofma != 1) return fail(AEB_EINVAL, "nofma must be 0 or 1");
+  if (!(s.dt > 0.0) || !std::isfinite(s.dt)) return fail(AEB_EINVAL, "dt must be positive");
+  if (!(s.horizon > 0.0) || !std::isfinite(s.horizon)) return fail(AEB_EINVAL, "horizon must be positive");
+  if (!(s.dead_time >= 0.0) || !std::isfinite(s.dead_time)) return fail(AEB_EINVAL, "dead_time must be >= 0");
+  double steps = s.horizon / s.dt;
+  if (!(steps >= 1.0) || steps > 2147483647.0) return fail(AEB_EINVAL, "horizon/dt out of [1, 2^31-1]");
+  if (!std::isfinite(s.a_cmd) || !std::isfinite(s.g) || !std::isfinite(s.rho) || !std::isfinite(s.h_cog))
+    return fail(AEB_EINVAL, "non-finite physical constant");
+  if (!(s.wheelbase > 0.0) || !std::isfinite(s.wheelbase)) return fail(AEB_EINVAL, "wheelbase must be positive");
+  const aeb_dist* all[9] = {&s.v0, &s.mu, &s.mass, &s.grade, &s.cda, &s.crr, &s.tau, &s.gap, &s.lead_decel};
+  static const char* names[9] = {"v0", "mu", "mass", "grade", "cda", "crr", "tau", "gap", "lead_decel"};
+  for (int k = 0; k < 9; ++k)
+    if (!dist_ok(*all[k])) return fail(AEB_EINVAL, std::string("invalid distribution for ") + names[k]);
+  double tmin = support_min(s.tau);
+  if (!(tmin > 0.0)) return fail(AEB_EINVAL, "tau distribution can reach 0");
+  if (s.integrator == AEB_EULER && tmin < s.dt)
+    return fail(AEB_EINVAL, "explicit Euler needs tau >= dt for every sample");
+  return AEB_OK;
+}
+
+int64_t horizon_steps(const aeb_scenario& s) { return std::llround(s.horizon / s.dt); }
+int64_t dead_steps(const aeb_scenario& s) { return std::llround(s.dead_time / s.dt); }
+
+static int host_threads() {
+  cpu_set_t set;
+  if (sched_getaffinity(0, sizeof(set), &set) == 0) {
+    int c = CPU_COUNT(&set);
+    if (c > 0) return c;
+  }
+  unsigned h = std::thread::hardware_concurrency();
+  return h ? static_cast<int>(h) : 1;
+}
+
+static bool params_complete(const aeb_params* p) {
+  return p && p->v0 && p->mu && p->mass && p->grade && p->sin_grade && p->cos_grade && p->cda &&
+         p->crr && p->tau && p->gap && p->lead_decel;
+}
+
+static bool outputs_complete(const aeb_outputs* o) {
+  return o && o->dist && o->status && o->steps && o->margin && o->v_impact;
+}
+
+}  // namespace aeb
+
+using namespace aeb;
+
+extern "C" {
+
+const char* aeb_last_error(void) { return g_err.c_str(); }
+
+int aeb_version(void) { return 1; }
+
+int aeb_validate(const aeb_scenario* scn) {
+  if (!scn) return fail(AEB_EINVAL, "null scenario");
+  int rc = validate(*scn);
+  if (rc == AEB_OK) g_err.clear();
+  return rc;
+}
+
+int aeb_uniforms(uint64_t seed, uint64_t scenario_id, int64_t first, int64_t count, uint32_t slot,
+                 uint32_t attempt, double* out, int on_device, void* stream) {
+  if (!out || first < 0 || count < 0 || first + count > (int64_t(1) << 32) || slot > 255 ||
+      attempt > 0xFFFFFF)
+    return fail(AEB_EINVAL, "aeb_uniforms: bad arguments");
+  if (count == 0) return AEB_OK;
+  if (on_device)
+    return launch_uniforms(seed, scenario_id, first, count, slot, attempt, out,
+                           static_cast<hipStream_t>(stream));
+  for (int64_t k = 0; k < count; ++k) {
+    U2 u = uniform2(seed, scenario_id, static_cast<uint64_t>(first + k), slot, attempt);
+    out[2 * k] = u.a;
+    out[2 * k + 1] = u.b;
+  }
+  return AEB_OK;
+}
+
+int aeb_sample_params(const aeb_scenario* scn, int64_t first, int64_t count, const aeb_params* out,
+                      int on_device, void* stream) {
+  if (!scn || !params_complete(out)) return fail(AEB_EINVAL, "aeb_sample_params: null argument");
+  int rc = validate(*scn);
+  if (rc != AEB_OK) return rc;
+  if (first < 0 || count < 0 || first + count > (int64_t(1) << 32))
+    return fail(AEB_EINVAL, "aeb_sample_params: sample range out of [0, 2^32)");
+  if (count == 0) return AEB_OK;
+  if (on_device) return launch_sample(*scn, first, count, *out, static_cast<hipStream_t>(stream));
+  // the paper's plain method: draw on the host with host libm, all cores
+  const aeb_scenario s = *scn;
+  const aeb_params p = *out;
+  auto work = [&](int64_t lo, int64_t hi) {
+    for (int64_t k = lo; k < hi; ++k) {
+      Sample q = draw_sample(s, static_cast<uint64_t>(first + k));
+      p.v0[k] = q.v0;
+      p.mu[k] = q.mu;
+      p.mass[k] = q.mass;
+      p.grade[k] = q.grade;
+      p.sin_grade[k] = q.sin_grade;
+      p.cos_grade[k] = q.cos_grade;
+      p.cda[k] = q.cda;
+      p.crr[k] = q.crr;
+      p.tau[k] = q.tau;
+      p.gap[k] = q.gap;
+      p.lead_decel[k] = q.lead_decel;
+    }
+  };
+  int nt = host_threads();
+  if (count < 4096) nt = 1;
+  if (nt > 256) nt = 256;
+  if (nt == 1) {
+    work(0, count);
+  } else {
+    std::vector<std::thread> th;
+    th.reserve(nt);
+    for (int t = 0; t < nt; ++t) th.emplace_back(work, count * t / nt, count * (t + 1) / nt);
+    for (auto& t : th) t.join();
+  }
+  return AEB_OK;
+}
+
+int aeb_rollout(const aeb_scenario* scn, const aeb_params* params, int precision,
+                const aeb_outputs* out, void* stream) {
+  if (!scn || !outputs_complete(out)) return fail(AEB_EINVAL, "aeb_rollout: null argument");
+  int rc = validate(*scn);
+  if (rc != AEB_OK) return rc;
+  if (precision != AEB_FP64 && precision != AEB_FP32C) return fail(AEB_EINVAL, "unknown precision");
+  if (out->n != scn->n_samples) return fail(AEB_EINVAL, "outputs length differs from n_samples");
+  ParamSrc src{};
+  if (params) {
+    if (!params_complete(params)) return fail(AEB_EINVAL, "aeb_rollout: incomplete parameter columns");
+    if (params->n != scn->n_samples) return fail(AEB_EINVAL, "parameter length differs from n_samples");
+    src = ParamSrc{params->v0, params->mu,  params->mass, params->sin_grade, params->cos_grade,
+                   params->cda, params->crr, params->tau, params->gap, params->lead_decel};
+  }
+  OutCols oc{out->dist, out->status, out->steps, out->margin, out->v_impact};
+  return launch_rollout(*scn, params ? &src : nullptr, precision, oc, scn->n_samples,
+                        static_cast<hipStream_t>(stream));
+}
+
+int aeb_reduce(const aeb_outputs* out, const aeb_reduce_req* req, aeb_stats* host_out, void* stream) {
+  if (!outputs_complete(out) || !req || !host_out) return fail(AEB_EINVAL, "aeb_reduce: null argument");
+  if (out->n < 1 || out->n > 0x7fffffffLL) return fail(AEB_EINVAL, "aeb_reduce: n out of [1, 2^31-1]");
+  if (req->n_risk < 0 || req->n_risk > AEB_MAX_RISK || req->n_margin_q < 0 ||
+      req->n_margin_q > AEB_MAX_MARGIN_Q || req->n_grid < 0 || req->n_grid > AEB_MAX_GRID ||
+      req->n_grid == 1)
+    return fail(AEB_EINVAL, "aeb_reduce: request sizes out of range");
+  for (int j = 0; j < req->n_risk; ++j)
+    if (!(req->risk[j] >= 0.0 && req->risk[j] < 1.0)) return fail(AEB_EINVAL, "risk level outside [0,1)");
+  for (int j = 0; j < req->n_margin_q; ++j)
+    if (!(req->margin_q[j] >= 0.0 && req->margin_q[j] < 1.0))
+      return fail(AEB_EINVAL, "margin quantile outside [0,1)");
+  if (req->n_grid >= 2 && !(req->grid_lo < req->grid_hi && std::isfinite(req->grid_lo) &&
+                            std::isfinite(req->grid_hi)))
+    return fail(AEB_EINVAL, "headway grid needs finite grid_lo < grid_hi");
+  OutCols oc{out->dist, out->status, out->steps, out->margin, out->v_impact};
+  return launch_reduce(oc, out->n, *req, host_out, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

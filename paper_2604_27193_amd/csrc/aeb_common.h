@@ -1,0 +1,156 @@
+// aeb_common.h -- arithmetic shared by the host sampler and the kernels of
+// the library: the counter-based generator, the parameter distributions and
+// the per-sample constants of the force balance.
+//
+// Everything here is __host__ __device__ and compiled with -ffp-contract=off,
+// so host and device evaluate the same expression trees; only libm
+// (log, cos, sin, sqrt) differs between host and device.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "aeb.h"
+
+namespace aeb {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Ten rounds of: two
+// 32x32->64 products of counter words 0 and 2 with fixed multipliers; the new
+// counter takes the low halves in place and xors the high halves into the
+// other words together with the round key; the key then advances by the Weyl
+// constants.
+// ---------------------------------------------------------------------------
+struct Ctr {
+  uint32_t w[4];
+};
+
+__host__ __device__ inline void mulhilo(uint32_t a, uint32_t b, uint32_t& hi, uint32_t& lo) {
+  uint64_t p = static_cast<uint64_t>(a) * static_cast<uint64_t>(b);
+  hi = static_cast<uint32_t>(p >> 32);
+  lo = static_cast<uint32_t>(p);
+}
+
+__host__ __device__ inline Ctr philox4x32_10(Ctr c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint32_t hi_a, lo_a, hi_b, lo_b;
+    mulhilo(0xD2511F53u, c.w[0], hi_a, lo_a);
+    mulhilo(0xCD9E8D57u, c.w[2], hi_b, lo_b);
+    Ctr n;
+    n.w[0] = hi_b ^ c.w[1] ^ k0;
+    n.w[1] = lo_b;
+    n.w[2] = hi_a ^ c.w[3] ^ k1;
+    n.w[3] = lo_a;
+    c = n;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Two uniforms in (0,1) from one call: 52 top bits of each 64-bit half plus 1/2.
+struct U2 {
+  double a, b;
+};
+
+__host__ __device__ inline double unit52(uint64_t w) {
+  return (static_cast<double>(w >> 12) + 0.5) * 0x1p-52;
+}
+
+__host__ __device__ inline U2 uniform2(uint64_t seed, uint64_t sid, uint64_t i, uint32_t slot,
+                                       uint32_t attempt) {
+  Ctr c;
+  c.w[0] = static_cast<uint32_t>(i);
+  c.w[1] = slot | (attempt << 8);
+  c.w[2] = static_cast<uint32_t>(sid);
+  c.w[3] = static_cast<uint32_t>(sid >> 32);
+  Ctr o = philox4x32_10(c, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
+  U2 u;
+  u.a = unit52((static_cast<uint64_t>(o.w[1]) << 32) | o.w[0]);
+  u.b = unit52((static_cast<uint64_t>(o.w[3]) << 32) | o.w[2]);
+  return u;
+}
+
+// Box-Muller, cosine branch.
+__host__ __device__ inline double box_muller(U2 u) {
+  const double two_pi = 6.283185307179586;
+  double l = log(u.a);
+  double rad = sqrt(-2.0 * l);
+  double th = two_pi * u.b;
+  return rad * cos(th);
+}
+
+__host__ __device__ inline double draw(const aeb_dist& d, uint64_t seed, uint64_t sid, uint64_t i,
+                                       uint32_t slot) {
+  if (d.kind == AEB_DIST_CONST) return d.p0;
+  if (d.kind == AEB_DIST_UNIFORM) {
+    U2 u = uniform2(seed, sid, i, slot, 0);
+    return d.p0 + (d.p1 - d.p0) * u.a;
+  }
+  if (d.kind == AEB_DIST_NORMAL) {
+    U2 u = uniform2(seed, sid, i, slot, 0);
+    return d.p0 + d.p1 * box_muller(u);
+  }
+  // truncated normal: up to 16 counter-indexed attempts, then clamp
+  double val = d.p0;
+  for (uint32_t j = 0; j < 16; ++j) {
+    U2 u = uniform2(seed, sid, i, slot, j);
+    val = d.p0 + d.p1 * box_muller(u);
+    if (val >= d.lo && val <= d.hi) return val;
+  }
+  return val < d.lo ? d.lo : d.hi;
+}
+
+// One realised parameter vector.
+struct Sample {
+  double v0, mu, mass, grade, sin_grade, cos_grade, cda, crr, tau, gap, lead_decel;
+};
+
+__host__ __device__ inline Sample draw_sample(const aeb_scenario& s, uint64_t i) {
+  Sample p;
+  p.v0 = draw(s.v0, s.seed, s.scenario_id, i, AEB_SLOT_V0);
+  p.mu = draw(s.mu, s.seed, s.scenario_id, i, AEB_SLOT_MU);
+  p.mass = draw(s.mass, s.seed, s.scenario_id, i, AEB_SLOT_MASS);
+  p.grade = draw(s.grade, s.seed, s.scenario_id, i, AEB_SLOT_GRADE);
+  p.sin_grade = sin(p.grade);
+  p.cos_grade = cos(p.grade);
+  p.cda = draw(s.cda, s.seed, s.scenario_id, i, AEB_SLOT_CDA);
+  p.crr = draw(s.crr, s.seed, s.scenario_id, i, AEB_SLOT_CRR);
+  p.tau = draw(s.tau, s.seed, s.scenario_id, i, AEB_SLOT_TAU);
+  p.gap = draw(s.gap, s.seed, s.scenario_id, i, AEB_SLOT_GAP);
+  p.lead_decel = draw(s.lead_decel, s.seed, s.scenario_id, i, AEB_SLOT_LEAD);
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// Per-sample constants of eq. (4)-(6).
+//   kd   = ((rho/2) CdA) / m              drag deceleration per v^2
+//   c    = g sin(th) + (Crr g) cos(th)    grade plus rolling resistance
+//   alim = -(mu g / (1 + (mu h) / L))     eq. (5) solved with signed a < 0
+// ---------------------------------------------------------------------------
+struct Consts {
+  double kd, c, alim;
+};
+
+__host__ __device__ inline Consts derive(const aeb_scenario& s, double mu, double mass,
+                                         double sin_g, double cos_g, double cda, double crr) {
+  Consts k;
+  double half_rho = 0.5 * s.rho;
+  double drag_num = half_rho * cda;
+  k.kd = drag_num / mass;
+  double grade_term = s.g * sin_g;
+  double roll_coef = crr * s.g;
+  double roll_term = roll_coef * cos_g;
+  k.c = grade_term + roll_term;
+  double mu_g = mu * s.g;
+  double mu_h = mu * s.h_cog;
+  double transfer = mu_h / s.wheelbase;
+  double denom = 1.0 + transfer;
+  k.alim = -(mu_g / denom);
+  return k;
+}
+
+}  // namespace aeb

@@ -1,0 +1,61 @@
+// aeb_runtime.h -- internal declarations of the library: error reporting,
+// the per-device scratch arena, scenario validation and the kernel launchers
+// that the C ABI (abi.cpp) calls.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "aeb.h"
+#include "aeb_common.h"
+
+namespace aeb {
+
+// thread-local message behind aeb_last_error()
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+#define AEB_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return ::aeb::fail(AEB_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Grow-only device scratch, one per device; never shrinks before exit.
+// Returns nullptr (with the error set) if the allocation fails.
+void* scratch(size_t bytes, hipStream_t stream);
+
+int validate(const aeb_scenario& s);
+
+// llround(horizon/dt), llround(dead_time/dt)
+int64_t horizon_steps(const aeb_scenario& s);
+int64_t dead_steps(const aeb_scenario& s);
+
+// Kernel-side view of the parameter source: device columns or the generator.
+struct ParamSrc {
+  const double *v0, *mu, *mass, *sin_g, *cos_g, *cda, *crr, *tau, *gap, *lead;
+};
+
+struct OutCols {
+  double* dist;
+  uint8_t* status;
+  int32_t* steps;
+  double* margin;
+  float* vimp;
+};
+
+// launchers (kernels_*.hip); all asynchronous on `stream`
+int launch_uniforms(uint64_t seed, uint64_t sid, int64_t first, int64_t count, uint32_t slot,
+                    uint32_t attempt, double* out, hipStream_t stream);
+int launch_sample(const aeb_scenario& s, int64_t first, int64_t count, const aeb_params& out,
+                  hipStream_t stream);
+int launch_rollout(const aeb_scenario& s, const ParamSrc* src, int precision, const OutCols& out,
+                   int64_t n, hipStream_t stream);
+int launch_reduce(const OutCols& out, int64_t n, const aeb_reduce_req& req, aeb_stats* host_out,
+                  hipStream_t stream);
+
+}  // namespace aeb

@@ -1,0 +1,177 @@
+// kernels_rollout.hip -- the Monte Carlo rollout (Sec. V): one sample per
+// lane, parameters loaded from SoA columns (coalesced) or drawn in registers
+// from the counter generator, outputs stored SoA.
+#include <hip/hip_runtime.h>
+
+#include "aeb_common.h"
+#include "aeb_runtime.h"
+#include "fast_path.h"
+#include "rollout_steps.h"
+
+namespace aeb {
+
+// sample i's parameters from the columns or the generator
+template <bool DEVRNG>
+__device__ inline Lane load_lane(const aeb_scenario& s, const ParamSrc& src, int64_t i) {
+  Lane L;
+  double mu, mass, sg, cg, cda, crr;
+  if (DEVRNG) {
+    Sample q = draw_sample(s, static_cast<uint64_t>(i));
+    L.v0 = q.v0;
+    mu = q.mu;
+    mass = q.mass;
+    sg = q.sin_grade;
+    cg = q.cos_grade;
+    cda = q.cda;
+    crr = q.crr;
+    L.tau = q.tau;
+    L.gap = q.gap;
+    L.lead = q.lead_decel;
+  } else {
+    L.v0 = src.v0[i];
+    mu = src.mu[i];
+    mass = src.mass[i];
+    sg = src.sin_g[i];
+    cg = src.cos_g[i];
+    cda = src.cda[i];
+    crr = src.crr[i];
+    L.tau = src.tau[i];
+    L.gap = src.gap[i];
+    L.lead = src.lead[i];
+  }
+  L.k = derive(s, mu, mass, sg, cg, cda, crr);
+  return L;
+}
+
+__device__ inline void store(const OutCols& o, int64_t i, const Result& r) {
+  o.dist[i] = r.dist;
+  o.margin[i] = r.margin;
+  o.steps[i] = r.steps;
+  o.status[i] = r.status;
+  o.vimp[i] = r.vimp;
+}
+
+template <int INTEG, int OBS, bool NOFMA, bool DEVRNG>
+__global__ __launch_bounds__(256) void k_rollout_fp64(aeb_scenario s, ParamSrc src, OutCols out,
+                                                      int64_t n, int64_t nd, int64_t nmax) {
+  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Lane L = load_lane<DEVRNG>(s, src, i);
+  Result r = (INTEG == AEB_EULER) ? euler_fp64<OBS, NOFMA>(L, s.dt, s.a_cmd, nd, nmax, s.impact_exit)
+                                  : rk4_fp64<OBS>(L, s.dt, s.a_cmd, nd, nmax, s.impact_exit);
+  store(out, i, r);
+}
+
+// FP32 compensated rollout; samples whose outcome single precision cannot
+// decide are appended to `fix` (count at fix[0], indices after it).
+template <int OBS, bool DEVRNG>
+__global__ __launch_bounds__(256) void k_rollout_fp32c(aeb_scenario s, ParamSrc src, OutCols out,
+                                                       int64_t n, int64_t nd, int64_t nmax,
+                                                       double band_abs, double band_rel, uint32_t* fix) {
+  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Lane L = load_lane<DEVRNG>(s, src, i);
+  bool boundary = false;
+  const double band = band_abs + band_rel * fabs(L.gap);
+  Result r = euler_fp32c<OBS>(L, s.dt, s.a_cmd, nd, nmax, s.impact_exit, band, boundary);
+  store(out, i, r);
+  if (boundary) {
+    uint32_t slot = atomicAdd(fix, 1u);
+    fix[1 + slot] = static_cast<uint32_t>(i);
+  }
+}
+
+// FP64 recomputation of the samples listed in fix[1 .. fix[0]]
+template <int OBS, bool DEVRNG>
+__global__ __launch_bounds__(256) void k_fixup_fp64(aeb_scenario s, ParamSrc src, OutCols out,
+                                                    int64_t nd, int64_t nmax, const uint32_t* fix) {
+  const uint32_t cnt = fix[0];
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < cnt; j += gridDim.x * blockDim.x) {
+    int64_t i = fix[1 + j];
+    Lane L = load_lane<DEVRNG>(s, src, i);
+    Result r = euler_fp64<OBS, false>(L, s.dt, s.a_cmd, nd, nmax, s.impact_exit);
+    store(out, i, r);
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------
+template <int INTEG, int OBS, bool NOFMA>
+static void go_fp64(const aeb_scenario& s, const ParamSrc* src, const OutCols& out, int64_t n,
+                    int64_t nd, int64_t nmax, hipStream_t st) {
+  dim3 grid(static_cast<unsigned>((n + 255) / 256)), block(256);
+  ParamSrc p = src ? *src : ParamSrc{};
+  if (src)
+    hipLaunchKernelGGL((k_rollout_fp64<INTEG, OBS, NOFMA, false>), grid, block, 0, st, s, p, out, n,
+                       nd, nmax);
+  else
+    hipLaunchKernelGGL((k_rollout_fp64<INTEG, OBS, NOFMA, true>), grid, block, 0, st, s, p, out, n,
+                       nd, nmax);
+}
+
+template <int OBS>
+static int go_fp32c(const aeb_scenario& s, const ParamSrc* src, const OutCols& out, int64_t n,
+                    int64_t nd, int64_t nmax, hipStream_t st) {
+  uint32_t* fix = static_cast<uint32_t*>(scratch(sizeof(uint32_t) * (n + 1), st));
+  if (!fix) return AEB_ENOMEM;
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, fix, int64_t(1), 0u);
+  dim3 grid(static_cast<unsigned>((n + 255) / 256)), block(256);
+  ParamSrc p = src ? *src : ParamSrc{};
+  // single-precision distance and clearance errors stay below ~1e-4 m; outcomes
+  // within 1 mm (+1e-5 of the gap) of the boundary are recomputed in FP64
+  const double band_abs = 1e-3, band_rel = 1e-5;
+  if (src) {
+    hipLaunchKernelGGL((k_rollout_fp32c<OBS, false>), grid, block, 0, st, s, p, out, n, nd, nmax,
+                       band_abs, band_rel, fix);
+    hipLaunchKernelGGL((k_fixup_fp64<OBS, false>), dim3(64), block, 0, st, s, p, out, nd, nmax, fix);
+  } else {
+    hipLaunchKernelGGL((k_rollout_fp32c<OBS, true>), grid, block, 0, st, s, p, out, n, nd, nmax,
+                       band_abs, band_rel, fix);
+    hipLaunchKernelGGL((k_fixup_fp64<OBS, true>), dim3(64), block, 0, st, s, p, out, nd, nmax, fix);
+  }
+  return AEB_OK;
+}
+
+int launch_rollout(const aeb_scenario& s, const ParamSrc* src, int precision, const OutCols& out,
+                   int64_t n, hipStream_t st) {
+  const int64_t nd = dead_steps(s), nmax = horizon_steps(s);
+  if (fast_path_applies(s, precision)) return launch_rollout_fast(s, src, precision, out, n, st);
+  if (precision == AEB_FP32C) {
+    if (s.integrator != AEB_EULER)
+      return fail(AEB_EINVAL, "the FP32 compensated form is available for the Euler integrator");
+    int rc = AEB_OK;
+    switch (s.obstacle) {
+      case AEB_OBS_NONE: rc = go_fp32c<AEB_OBS_NONE>(s, src, out, n, nd, nmax, st); break;
+      case AEB_OBS_STATIONARY: rc = go_fp32c<AEB_OBS_STATIONARY>(s, src, out, n, nd, nmax, st); break;
+      default: rc = go_fp32c<AEB_OBS_LEAD>(s, src, out, n, nd, nmax, st); break;
+    }
+    if (rc != AEB_OK) return rc;
+  } else if (s.integrator == AEB_RK4) {
+    if (s.obstacle == AEB_OBS_NONE)
+      go_fp64<AEB_RK4, AEB_OBS_NONE, false>(s, src, out, n, nd, nmax, st);
+    else
+      go_fp64<AEB_RK4, AEB_OBS_STATIONARY, false>(s, src, out, n, nd, nmax, st);
+  } else if (s.nofma) {
+    switch (s.obstacle) {
+      case AEB_OBS_NONE: go_fp64<AEB_EULER, AEB_OBS_NONE, true>(s, src, out, n, nd, nmax, st); break;
+      case AEB_OBS_STATIONARY: go_fp64<AEB_EULER, AEB_OBS_STATIONARY, true>(s, src, out, n, nd, nmax, st); break;
+      default: go_fp64<AEB_EULER, AEB_OBS_LEAD, true>(s, src, out, n, nd, nmax, st); break;
+    }
+  } else {
+    switch (s.obstacle) {
+      case AEB_OBS_NONE: go_fp64<AEB_EULER, AEB_OBS_NONE, false>(s, src, out, n, nd, nmax, st); break;
+      case AEB_OBS_STATIONARY: go_fp64<AEB_EULER, AEB_OBS_STATIONARY, false>(s, src, out, n, nd, nmax, st); break;
+      default: go_fp64<AEB_EULER, AEB_OBS_LEAD, false>(s, src, out, n, nd, nmax, st); break;
+    }
+  }
+  AEB_HIP(hipGetLastError());
+  return AEB_OK;
+}
+
+}  // namespace aeb

@@ -1,0 +1,85 @@
+"""The C-ABI library on the host: it loads, exports every declared entry
+point, validates like the reference, and its host sampler (the paper's CPU
+sampling step, Sec. IV-C) reproduces the reference's draws bit for bit.
+No GPU call is made here."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2604_27193_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2604_27193_amd import binding
+    binding.lib()
+    return binding
+
+
+def declared_functions():
+    hdr = open(os.path.join(ROOT, "include", "aeb.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    return sorted(set(re.findall(r"\b(aeb_[a-z0-9_]+)\s*\(", hdr)))
+
+
+def test_every_declared_symbol_is_exported(B):
+    names = declared_functions()
+    assert "aeb_rollout" in names and "aeb_reduce" in names and "aeb_sample_params" in names
+    L = B.lib()
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_exports_listed_in_binding(B):
+    assert set(B.EXPORTS) <= set(declared_functions())
+
+
+def test_version(B):
+    assert B.lib().aeb_version() >= 1
+
+
+def test_validation_agrees_with_reference(B, orc):
+    from test_oracle_validate import BAD
+    for change in BAD:
+        d = W.single(100)
+        d.update(change)
+        assert B.validate(d) == B.EINVAL, change
+        assert B.lib().aeb_last_error().decode() != ""
+    for d in (W.single(10_000), W.paper_preset(), W.sweep(n=10)[17], W.uneven_batch(5)[2]):
+        assert B.validate(d) == B.OK == orc.validate(d)
+
+
+@pytest.mark.parametrize("seed,sid,slot,attempt", [(42, 0, 0, 0), (7, 123456789012, 8, 5)])
+def test_host_uniforms_bitwise(B, orc, seed, sid, slot, attempt):
+    got = B.uniforms(seed, sid, 1000, 50_000, slot, attempt, device=False)
+    want = orc.uniforms(seed, sid, 1000, 50_000, slot, attempt)
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+@pytest.mark.parametrize("d", [W.single(20_000), W.paper_preset(5000), W.sweep(n=3000)[37],
+                               W.uneven_batch(4)[1]])
+def test_host_sampler_bitwise(B, orc, d):
+    n = min(int(d["n_samples"]), 20_000)
+    got = B.sample_params(d, 0, n, device=False)
+    want = orc.sample(d, 0, n)
+    for c in B.COLUMNS:
+        assert np.array_equal(got[c].view(np.uint64), want[c].view(np.uint64)), c
+
+
+def test_host_sampler_subrange(B, orc):
+    d = W.single(10_000)
+    got = B.sample_params(d, 4321, 777, device=False)
+    want = orc.sample(d, 4321, 777)
+    for c in B.COLUMNS:
+        assert np.array_equal(got[c], want[c]), c
+
+
+def test_host_sampler_rejects_invalid(B):
+    with pytest.raises(B.AebError):
+        B.sample_params(dict(W.single(10), dt=0.0), 0, 10, device=False)
+    with pytest.raises(B.AebError):
+        B.sample_params(W.single(10), -1, 10, device=False)

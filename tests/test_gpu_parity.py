@@ -1,0 +1,259 @@
+"""GPU parity: every result of the HIP path against the FP64 reference on the
+same seeded inputs.
+
+Bars (the reference is exact FP64 of the same steps):
+  * uniforms: bit-identical;
+  * FP64 rollout: per-sample relative distance error <= 1e-12, status and step
+    counts identical (the host-sampled plain method is expected bit-exact);
+  * FP32 compensated rollout: relative distance error <= 1e-4, collision flags
+    identical (samples near the boundary are recomputed in FP64), v_impact
+    within 0.05 m/s;
+  * reduction: counts, order statistics and the risk curve identical, moments
+    within 1e-12 relative.
+"""
+import numpy as np
+import pytest
+
+from paper_2604_27193_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+REL64 = 1e-12
+REL32 = 1e-4
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2604_27193_amd import binding
+    binding.lib()
+    return binding
+
+
+def to_np(out):
+    import torch
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def upload(cols):
+    import torch
+    return {k: torch.from_numpy(np.ascontiguousarray(v)).to("cuda") for k, v in cols.items()}
+
+
+def rel_err(a, b):
+    return np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
+
+
+def check_fp64(got, ref, exact=False):
+    assert np.array_equal(got["status"], ref["status"])
+    assert np.array_equal(got["steps"], ref["steps"])
+    assert rel_err(got["dist"], ref["dist"]).max() <= REL64
+    m = np.abs(got["margin"] - ref["margin"])
+    assert np.all(m <= REL64 * np.maximum(np.abs(ref["margin"]), np.abs(ref["dist"])) + 1e-12)
+    assert np.all(np.abs(got["v_impact"] - ref["v_impact"]) <= 1e-6 * np.abs(ref["v_impact"]) + 1e-7)
+    if exact:
+        assert np.array_equal(got["dist"].view(np.uint64), ref["dist"].view(np.uint64))
+
+
+def plain(B, d):
+    host = B.sample_params(d, device=False)
+    return B.rollout(d, params=upload(host))
+
+
+# ---------------------------------------------------------------------------
+# generator and sampler
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed,sid,slot,attempt,n", [(42, 0, 0, 0, 1_000_000),
+                                                     (7, 2**33 + 9, 8, 3, 100_003)])
+def test_device_uniforms_bitwise(B, orc, seed, sid, slot, attempt, n):
+    got = B.uniforms(seed, sid, 5, n, slot, attempt, device=True).cpu().numpy()
+    want = orc.uniforms(seed, sid, 5, n, slot, attempt)
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+def test_device_sampler_matches_reference(B, orc):
+    d = W.single(50_000)
+    got = {k: v.cpu().numpy() for k, v in B.sample_params(d, device=True).items()}
+    want = orc.sample(d)
+    for c in ("mu", "crr", "tau"):                     # uniform draws: bit-identical
+        assert np.array_equal(got[c], want[c]), c
+    for c in ("v0", "mass", "grade", "sin_grade", "cos_grade", "cda", "gap"):
+        assert rel_err(got[c], want[c] + (want[c] == 0)).max() <= 1e-14, c
+
+
+# ---------------------------------------------------------------------------
+# FP64 rollout
+# ---------------------------------------------------------------------------
+def test_plain_fp64_config0_exact(B, orc):
+    d = W.single(10_000)
+    got = to_np(plain(B, d))
+    ref = orc.run(d)
+    check_fp64(got, ref, exact=True)
+
+
+@pytest.mark.parametrize("n,seed", [(1, 3), (63, 4), (64, 5), (257, 6), (4097, 7)])
+def test_plain_fp64_ragged_sizes(B, orc, n, seed):
+    d = W.single(n, seed=seed)
+    check_fp64(to_np(plain(B, d)), orc.run(d), exact=True)
+
+
+def test_device_rng_fp64(B, orc):
+    d = W.single(20_000, seed=11, scenario_id=5)
+    got = to_np(B.rollout(d, params=None))
+    check_fp64(got, orc.run(d))
+
+
+@pytest.mark.parametrize("variant", ["nofma", "impact_exit", "none", "rk4", "rk4_stationary",
+                                     "paper_euler"])
+def test_fp64_variants(B, orc, variant):
+    if variant == "nofma":
+        d = W.single(3000, nofma=True)
+    elif variant == "impact_exit":
+        d = W.single(3000, impact_exit=True)
+    elif variant == "none":
+        d = W.single(3000, obstacle="none")
+    elif variant == "rk4":
+        d = W.paper_preset(2000)
+    elif variant == "rk4_stationary":
+        d = W.single(2000, integrator="rk4")
+    else:
+        d = W.paper_preset(3000, integrator="euler")
+    check_fp64(to_np(plain(B, d)), orc.run(d), exact=True)
+
+
+@pytest.mark.parametrize("k", [0, 37, 100, 255])
+def test_lead_vehicle_fp64(B, orc, k):
+    d = W.sweep(n=1500)[k]
+    check_fp64(to_np(plain(B, d)), orc.run(d), exact=True)
+    check_fp64(to_np(B.rollout(d)), orc.run(d))
+
+
+def test_uneven_scenarios_fp64(B, orc):
+    for d in W.uneven_batch(6, max_samples=1500):
+        check_fp64(to_np(B.rollout(d)), orc.run(d))
+
+
+def test_full_size_sampled(B, orc):
+    """Config-1 size, launch shape of the benchmark; 1,500 sampled indices."""
+    d = W.single(1_048_576)
+    got = to_np(plain(B, d))
+    rng = np.random.default_rng(2024)
+    idx = np.unique(np.concatenate([rng.integers(0, d["n_samples"], 1500),
+                                    [0, 1, d["n_samples"] - 1]]))
+    for i in idx:
+        r = orc.run(d, first=int(i), count=1)
+        assert got["status"][i] == r["status"][0] and got["steps"][i] == r["steps"][0]
+        assert got["dist"][i] == r["dist"][0], i
+    # properties that hold at any size
+    st = got["status"]
+    col = (st & B.COLLIDED) != 0
+    host = B.sample_params(d, device=False)
+    assert np.array_equal(col, got["dist"] > host["gap"])
+    assert np.all(st & 3 == B.END_STOP)
+
+
+def test_repeat_is_bitwise_deterministic(B):
+    d = W.single(30_000)
+    params = upload(B.sample_params(d, device=False))
+    first = to_np(B.rollout(d, params=params))
+    s0 = B.reduce(B.rollout(d, params=params), risk=(0.05,), grid=(40, 90, 51))
+    for _ in range(5):
+        again = to_np(B.rollout(d, params=params))
+        for k in first:
+            assert np.array_equal(first[k], again[k])
+        s1 = B.reduce(B.rollout(d, params=params), risk=(0.05,), grid=(40, 90, 51))
+        assert s1["mean_dist"] == s0["mean_dist"] and s1["sd_dist"] == s0["sd_dist"]
+
+
+def test_invalid_arguments_raise(B):
+    import torch
+    with pytest.raises(B.AebError):
+        B.rollout(dict(W.single(10), n_samples=0))
+    d = W.single(100)
+    out = B.alloc_outputs(99)
+    with pytest.raises(B.AebError):
+        B.rollout(d, out=out)
+    with pytest.raises(B.AebError):
+        B.rollout(dict(d, integrator="rk4", obstacle="lead"))
+    torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------------------
+# FP32 compensated rollout
+# ---------------------------------------------------------------------------
+def check_fp32c(got, ref):
+    rel = rel_err(got["dist"], ref["dist"])
+    assert rel.max() <= REL32, rel.max()
+    assert np.array_equal(got["status"] & B_COLLIDED, ref["status"] & B_COLLIDED)
+    assert np.array_equal(got["status"] & 3, ref["status"] & 3)
+    col = (ref["status"] & B_COLLIDED) != 0
+    assert np.all(np.abs(got["v_impact"][col] - ref["v_impact"][col]) <= 0.05)
+    assert np.all(np.abs(got["steps"] - ref["steps"]) <= 2)
+    return rel
+
+
+B_COLLIDED = 4
+
+
+@pytest.mark.parametrize("mode", ["plain", "devrng"])
+def test_fp32c_config0(B, orc, mode):
+    d = W.single(10_000)
+    params = upload(B.sample_params(d, device=False)) if mode == "plain" else None
+    got = to_np(B.rollout(d, params=params, precision="fp32c"))
+    rel = check_fp32c(got, orc.run(d))
+    print(f"fp32c config0 {mode}: max rel {rel.max():.2e} mean {rel.mean():.2e}")
+
+
+@pytest.mark.parametrize("k", [0, 40, 130, 255])
+def test_fp32c_lead(B, orc, k):
+    d = W.sweep(n=1000)[k]
+    got = to_np(B.rollout(d, precision="fp32c"))
+    check_fp32c(got, orc.run(d))
+
+
+def test_fp32c_variants(B, orc):
+    for d in (W.single(2000, obstacle="none"), W.single(2000, impact_exit=True),
+              W.paper_preset(2000, integrator="euler"), *W.uneven_batch(3, max_samples=1000)):
+        check_fp32c(to_np(B.rollout(d, precision="fp32c")), orc.run(d))
+
+
+# ---------------------------------------------------------------------------
+# reduction
+# ---------------------------------------------------------------------------
+RISK = (0.0, 0.5, 0.05, 0.01, 0.001)
+MQ = (0.0, 0.01, 0.1, 0.5)
+GRID = (30.0, 110.0, 161)
+
+
+def compare_stats(got, want):
+    for k in ("n", "n_collide", "n_stop", "n_impact", "n_horizon", "p_collision", "margin_min",
+              "v_impact_max", "dist_min", "dist_max"):
+        assert got[k] == want[k] or (np.isnan(got[k]) and np.isnan(want[k])), k
+    assert got["headway"] == want["headway"]
+    assert got["margin_q"] == want["margin_q"]
+    assert np.array_equal(got["risk_count"], want["risk_count"])
+    assert np.array_equal(got["risk_p"], want["risk_p"])
+    for k in ("mean_dist", "sd_dist", "margin_mean"):
+        if np.isnan(want[k]):
+            assert np.isnan(got[k])
+        else:
+            assert abs(got[k] - want[k]) <= 1e-12 * max(abs(want[k]), 1.0), k
+
+
+def test_reduce_on_rollout(B, orc):
+    d = W.single(10_000)
+    out = plain(B, d)
+    got = B.reduce(out, risk=RISK, margin_q=MQ, grid=GRID)
+    want = orc.reduce(orc.run(d), risk=RISK, margin_q=MQ, grid=GRID)
+    compare_stats(got, want)
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (777, 2), (65_537, 3), (300_001, 4)])
+def test_reduce_on_synthetic(B, orc, n, seed):
+    from test_oracle_reduce import synthetic
+    syn = synthetic(n, seed, ties=(seed % 2 == 0))
+    got = B.reduce(upload(syn), risk=RISK, margin_q=MQ, grid=GRID)
+    want = orc.reduce(syn, risk=RISK, margin_q=MQ, grid=GRID)
+    compare_stats(got, want)
