@@ -49,9 +49,14 @@ extern "C" {
 enum { AEB_EULER = 0, AEB_RK4 = 1 };                 /* integrator (Sec. IV-D) */
 enum { AEB_OBS_NONE = 0, AEB_OBS_STATIONARY = 1, AEB_OBS_LEAD = 2 };
 enum { AEB_DIST_CONST = 0, AEB_DIST_UNIFORM = 1, AEB_DIST_NORMAL = 2, AEB_DIST_TRUNC_NORMAL = 3 };
-enum { AEB_FP64 = 0, AEB_FP32C = 1 };                /* arithmetic of the rollout */
-/* status byte of one sample: low two bits = why it ended, bit 2 = collision latched */
-enum { AEB_END_STOP = 1, AEB_END_IMPACT = 2, AEB_END_HORIZON = 3, AEB_COLLIDED = 4 };
+/* arithmetic of the rollout: FP64; FP32 compensated with samples whose outcome
+ * lies within the single-precision band of the collision boundary flagged; the
+ * same with the flagged samples recomputed in FP64 */
+enum { AEB_FP64 = 0, AEB_FP32C = 1, AEB_FP32C_FIXUP = 2 };
+/* status byte of one sample: low two bits = why it ended, bit 2 = collision
+ * latched, bit 3 = FP32 outcome within the band of the collision boundary */
+enum { AEB_END_STOP = 1, AEB_END_IMPACT = 2, AEB_END_HORIZON = 3, AEB_COLLIDED = 4,
+       AEB_BOUNDARY = 8 };
 /* counter slots of the random parameters, one generator stream each */
 enum {
   AEB_SLOT_V0 = 0, AEB_SLOT_MU = 1, AEB_SLOT_MASS = 2, AEB_SLOT_GRADE = 3, AEB_SLOT_CDA = 4,
@@ -136,12 +141,13 @@ typedef struct {
   double grid_lo, grid_hi;
 } aeb_reduce_req;
 
-/* Statistics of one batch of outputs.  Counts are exact; p_collision and
+/* Statistics of one batch of outputs.  Counts are exact (n_boundary counts
+ * AEB_BOUNDARY samples); p_collision and
  * risk_p are count/N with one correctly rounded division; mean/sd are over
  * STOP samples (sd with N_stop - 1; NaN when undefined); headway/margin_q are
  * exact order statistics of the outputs. */
 typedef struct {
-  int64_t n, n_collide, n_stop, n_impact, n_horizon;
+  int64_t n, n_collide, n_stop, n_impact, n_horizon, n_boundary;
   double p_collision, mean_dist, sd_dist, dist_min, dist_max;
   double headway[AEB_MAX_RISK];
   double margin_min, margin_mean;
@@ -194,12 +200,23 @@ int aeb_sample_params(const aeb_scenario* scn, int64_t first, int64_t count, con
  *     method), or NULL to draw each sample's parameters inside the kernel from
  *     the counter generator (no per-sample input traffic).
  *   precision: AEB_FP64 (results equal to a sequential FP64 evaluation of the
- *     same steps) or AEB_FP32C (FP32 state with compensated distance
- *     accumulation; FP64 derived constants and final distance).
+ *     same steps), AEB_FP32C (FP32 state with compensated distance and, for
+ *     long rollouts, compensated speed; FP64 derived constants, final
+ *     distance and collision decision; samples whose distance or clearance is
+ *     within 1 mm + 1e-5 gap of the obstacle get AEB_BOUNDARY in their status)
+ *     or AEB_FP32C_FIXUP (as AEB_FP32C, then the flagged samples are
+ *     recomputed in FP64, so every collision flag is exact).
  *   out: device output columns with out->n == n_samples.
  * Asynchronous on `stream`.  May grow the scratch arena on first use. */
 int aeb_rollout(const aeb_scenario* scn, const aeb_params* params, int precision,
                 const aeb_outputs* out, void* stream);
+
+/* Profiling aid.  While enabled on the calling thread, aeb_rollout brackets
+ * its integration kernel with two HIP events on its stream; aeb_timing_last
+ * waits for the second and returns the kernel's duration in milliseconds for
+ * the last aeb_rollout call of this thread (AEB_EAGAIN if there was none). */
+int aeb_timing_enable(int on);
+int aeb_timing_last(float* ms);
 
 /* Statistics of `out` (device columns, out->n >= 1) as described for
  * aeb_stats/aeb_reduce_req.  Kernels run on `stream`; the function waits for

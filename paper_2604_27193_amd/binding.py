@@ -21,13 +21,13 @@ DISTS = ("v0", "mu", "mass", "grade", "cda", "crr", "tau", "gap", "lead_decel")
 INTEGRATORS = {"euler": 0, "rk4": 1}
 OBSTACLES = {"none": 0, "stationary": 1, "lead": 2}
 DIST_KINDS = {"const": 0, "uniform": 1, "normal": 2, "trunc_normal": 3}
-PRECISIONS = {"fp64": 0, "fp32c": 1}
+PRECISIONS = {"fp64": 0, "fp32c": 1, "fp32c_fixup": 2}
 
 OK, EINVAL, ENOMEM, EAGAIN, EDEVICE, ENOTFOUND = 0, -1, -2, -3, -4, -5
-END_STOP, END_IMPACT, END_HORIZON, COLLIDED = 1, 2, 3, 4
+END_STOP, END_IMPACT, END_HORIZON, COLLIDED, BOUNDARY = 1, 2, 3, 4, 8
 
 EXPORTS = ("aeb_last_error", "aeb_version", "aeb_validate", "aeb_uniforms", "aeb_sample_params",
-           "aeb_rollout", "aeb_reduce")
+           "aeb_rollout", "aeb_reduce", "aeb_timing_enable", "aeb_timing_last")
 
 
 class AebError(RuntimeError):
@@ -67,7 +67,7 @@ class ReduceReq(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_collide", C.c_int64), ("n_stop", C.c_int64),
-                ("n_impact", C.c_int64), ("n_horizon", C.c_int64),
+                ("n_impact", C.c_int64), ("n_horizon", C.c_int64), ("n_boundary", C.c_int64),
                 ("p_collision", C.c_double), ("mean_dist", C.c_double), ("sd_dist", C.c_double),
                 ("dist_min", C.c_double), ("dist_max", C.c_double),
                 ("headway", C.c_double * 16), ("margin_min", C.c_double),
@@ -95,6 +95,8 @@ def lib():
                                         C.c_void_p]
         L.aeb_rollout.argtypes = [P(Scenario), P(Params), C.c_int, P(Outputs), C.c_void_p]
         L.aeb_reduce.argtypes = [P(Outputs), P(ReduceReq), P(Stats), C.c_void_p]
+        L.aeb_timing_enable.argtypes = [C.c_int]
+        L.aeb_timing_last.argtypes = [P(C.c_float)]
         _lib = L
     return _lib
 
@@ -244,7 +246,8 @@ def reduce_request(risk=(), margin_q=(), grid=None):
 def stats_dict(st, n_risk, n_mq, n_grid):
     return {
         "n": st.n, "n_collide": st.n_collide, "n_stop": st.n_stop, "n_impact": st.n_impact,
-        "n_horizon": st.n_horizon, "p_collision": st.p_collision, "mean_dist": st.mean_dist,
+        "n_horizon": st.n_horizon, "n_boundary": st.n_boundary, "p_collision": st.p_collision,
+        "mean_dist": st.mean_dist,
         "sd_dist": st.sd_dist, "dist_min": st.dist_min, "dist_max": st.dist_max,
         "headway": list(st.headway)[:n_risk], "margin_min": st.margin_min,
         "margin_mean": st.margin_mean, "margin_q": list(st.margin_q)[:n_mq],
@@ -261,3 +264,14 @@ def reduce(out, risk=(), margin_q=(), grid=None, stream=None):
     _check(lib().aeb_reduce(C.byref(_outputs_struct(out)), C.byref(req), C.byref(st),
                             _stream(stream)))
     return stats_dict(st, req.n_risk, req.n_margin_q, req.n_grid)
+
+
+def timing_enable(on=True):
+    _check(lib().aeb_timing_enable(1 if on else 0))
+
+
+def timing_last():
+    """Duration (ms) of the last rollout's integration kernel on this thread."""
+    ms = C.c_float()
+    _check(lib().aeb_timing_last(C.byref(ms)))
+    return ms.value

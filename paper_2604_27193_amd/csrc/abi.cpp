@@ -36,17 +36,25 @@ struct Arena {
   size_t bytes = 0;
 };
 std::mutex g_arena_mu;
-Arena g_arena[64];
+Arena g_arena[64][2];
+
+struct Timing {
+  bool on = false;
+  bool recorded = false;
+  int dev = -1;
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+thread_local Timing g_timing;
 }  // namespace
 
-void* scratch(size_t bytes, hipStream_t stream) {
+void* scratch_slot(int slot, size_t bytes, hipStream_t stream) {
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || slot < 0 || slot > 1) {
     set_error("scratch: no current HIP device");
     return nullptr;
   }
   std::lock_guard<std::mutex> lock(g_arena_mu);
-  Arena& a = g_arena[dev];
+  Arena& a = g_arena[dev][slot];
   if (a.bytes >= bytes) return a.ptr;
   // work queued on any stream may still use the old block
   if (a.ptr) {
@@ -128,6 +136,27 @@ int validate(const aeb_scenario& s) {
   return AEB_OK;
 }
 
+void timing_begin(hipStream_t stream) {
+  Timing& t = g_timing;
+  if (!t.on) return;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  if (t.dev != dev) {
+    if (t.start) (void)hipEventDestroy(t.start);
+    if (t.stop) (void)hipEventDestroy(t.stop);
+    t.start = t.stop = nullptr;
+    if (hipEventCreate(&t.start) != hipSuccess || hipEventCreate(&t.stop) != hipSuccess) return;
+    t.dev = dev;
+  }
+  (void)hipEventRecord(t.start, stream);
+}
+
+void timing_end(hipStream_t stream) {
+  Timing& t = g_timing;
+  if (!t.on || !t.stop) return;
+  if (hipEventRecord(t.stop, stream) == hipSuccess) t.recorded = true;
+}
+
 int64_t horizon_steps(const aeb_scenario& s) { return std::llround(s.horizon / s.dt); }
 int64_t dead_steps(const aeb_scenario& s) { return std::llround(s.dead_time / s.dt); }
 
@@ -158,7 +187,22 @@ extern "C" {
 
 const char* aeb_last_error(void) { return g_err.c_str(); }
 
-int aeb_version(void) { return 1; }
+int aeb_version(void) { return 2; }
+
+int aeb_timing_enable(int on) {
+  g_timing.on = on != 0;
+  g_timing.recorded = false;
+  return AEB_OK;
+}
+
+int aeb_timing_last(float* ms) {
+  if (!ms) return fail(AEB_EINVAL, "aeb_timing_last: null argument");
+  Timing& t = g_timing;
+  if (!t.recorded) return fail(AEB_EAGAIN, "no timed rollout on this thread");
+  AEB_HIP(hipEventSynchronize(t.stop));
+  AEB_HIP(hipEventElapsedTime(ms, t.start, t.stop));
+  return AEB_OK;
+}
 
 int aeb_validate(const aeb_scenario* scn) {
   if (!scn) return fail(AEB_EINVAL, "null scenario");
@@ -231,7 +275,8 @@ int aeb_rollout(const aeb_scenario* scn, const aeb_params* params, int precision
   if (!scn || !outputs_complete(out)) return fail(AEB_EINVAL, "aeb_rollout: null argument");
   int rc = validate(*scn);
   if (rc != AEB_OK) return rc;
-  if (precision != AEB_FP64 && precision != AEB_FP32C) return fail(AEB_EINVAL, "unknown precision");
+  if (precision != AEB_FP64 && precision != AEB_FP32C && precision != AEB_FP32C_FIXUP)
+    return fail(AEB_EINVAL, "unknown precision");
   if (out->n != scn->n_samples) return fail(AEB_EINVAL, "outputs length differs from n_samples");
   ParamSrc src{};
   if (params) {

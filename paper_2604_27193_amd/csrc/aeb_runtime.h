@@ -25,9 +25,17 @@ int fail(int code, const std::string& msg);
       return ::aeb::fail(AEB_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-// Grow-only device scratch, one per device; never shrinks before exit.
-// Returns nullptr (with the error set) if the allocation fails.
-void* scratch(size_t bytes, hipStream_t stream);
+// Grow-only device scratch, per device and slot; never shrinks before exit.
+// Returns nullptr (with the error set) if the allocation fails.  Slot 0 holds
+// the rollout's job records and sort buffers and the reduction's partials;
+// slot 1 the FP32 fix-up list, which lives alongside slot 0.
+void* scratch_slot(int slot, size_t bytes, hipStream_t stream);
+inline void* scratch(size_t bytes, hipStream_t stream) { return scratch_slot(0, bytes, stream); }
+inline void* scratch_fix(size_t bytes, hipStream_t stream) { return scratch_slot(1, bytes, stream); }
+
+// events around the integration kernel (aeb_timing_enable)
+void timing_begin(hipStream_t stream);
+void timing_end(hipStream_t stream);
 
 int validate(const aeb_scenario& s);
 
@@ -55,6 +63,8 @@ int launch_sample(const aeb_scenario& s, int64_t first, int64_t count, const aeb
                   hipStream_t stream);
 int launch_rollout(const aeb_scenario& s, const ParamSrc* src, int precision, const OutCols& out,
                    int64_t n, hipStream_t stream);
+int launch_fixup(const aeb_scenario& s, const ParamSrc* src, const OutCols& out,
+                 const uint32_t* fix, hipStream_t stream);
 int launch_reduce(const OutCols& out, int64_t n, const aeb_reduce_req& req, aeb_stats* host_out,
                   hipStream_t stream);
 

@@ -18,7 +18,7 @@ struct Job {
   double kt;      // dt / tau
   double gap;     // initial gap to the obstacle
   double dmax;    // bound on |dv/dt| over the whole rollout
-  double creach;  // max(0, -c): bound on dv/dt
+  double pred;    // predicted number of steps
 };
 
 enum { FORM_G = 0, FORM_F = 1, FORM_C = 2, FORM_D = 3 };

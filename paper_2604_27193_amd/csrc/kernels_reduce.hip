@@ -5,9 +5,11 @@
 //
 // Sums run in a fixed order (each block a fixed slice, a fixed tree inside the
 // block, blocks summed in index order), so repeated calls give identical
-// bits.  Order statistics are exact: a most-significant-digit radix select
-// over an order-preserving map of the FP64 bit patterns, 8 passes of 8 bits,
-// with per-block LDS histograms merged by integer atomics.
+// bits.  Order statistics are exact: a histogram over 65,536 value bins
+// spanning each array's finite range finds the bin holding a target's rank;
+// the bin's elements are collected and sorted in LDS (bitonic, by an
+// order-preserving map of the FP64 bit patterns).  A bin with more than 4,096
+// elements falls back to a most-significant-digit radix select.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -21,18 +23,41 @@ namespace {
 
 constexpr int RB = 256;          // threads per reduction block
 constexpr int MAX_T = AEB_MAX_RISK + AEB_MAX_MARGIN_Q;
+constexpr int NVB = 4096;        // value bins of the selection histograms (+1 overflow)
+constexpr int CAP = 8192;        // candidates a target's bin may hold for the LDS sort
+constexpr int FB = 1024;         // threads of the finalize / bin-search blocks
 
 struct Partial {
-  long long ncol, nstop, nimp, nhor;
-  double sum, dmin, dmax, msum, mmin;
+  long long ncol, nstop, nimp, nhor, nbnd;
+  double sum, dmin, dmax, msum, mmin, mmax;
   float vmax;
   float pad;
 };
 
+// Selection targets: per target the array (0 censored distance, 1 margin)
+// and the 0-based rank.  Passed by value.
+struct SelIn {
+  int count, n_risk;
+  int kind[MAX_T];
+  unsigned long long rank[MAX_T];
+};
+
+// Selection progress: the value bin holding each target's rank and the rank
+// inside the bin, the candidates collected, the binning of each array.
+struct Sel {
+  int fallback, pad;
+  int bin[MAX_T];          // -1: answered without candidates
+  unsigned rank_in_bin[MAX_T];
+  unsigned bin_count[MAX_T];
+  unsigned ccount[MAX_T];  // candidates collected
+  double vmin[2], scale[2];
+};
+
+// Radix-select state of the fallback path.
 struct SelState {
   unsigned long long prefix[MAX_T];
   unsigned long long rank[MAX_T];
-  int kind[MAX_T];   // 0: censored distance, 1: margin
+  int kind[MAX_T];
   int count;
   int pad;
 };
@@ -52,29 +77,53 @@ __device__ inline double censored(const double* dist, const uint8_t* status, lon
   return (status[i] & 3) == AEB_END_STOP ? dist[i] : INFINITY;
 }
 
-// number of grid headways strictly below d: H0_j = lo + j * step, j < ng
-__device__ inline int grid_rank(double d, double lo, double step, int ng) {
-  int a = 0, b = ng;  // answer in [a, b]
-  while (a < b) {
-    int mid = (a + b) >> 1;
-    double h = lo + static_cast<double>(mid) * step;
-    if (h < d)
-      a = mid + 1;
-    else
-      b = mid;
-  }
-  return a;
+// value bin: monotone in v; +inf goes to the overflow bin NVB
+__device__ inline int value_bin(double v, double vmin, double scale) {
+  if (!(v < INFINITY)) return NVB;
+  double f = (v - vmin) * scale;
+  int b = f > 0.0 ? static_cast<int>(f) : 0;
+  return b < NVB ? b : NVB - 1;
 }
 
-template <typename T, typename Op>
+// number of grid headways strictly below d, H0_j = lo + j * step (j < ng):
+// an arithmetic guess corrected with exact comparisons against the same
+// expression, so the count is exact
+__device__ inline int grid_rank(double d, double lo, double step, int ng) {
+  if (!(d > lo)) return 0;
+  if (!(d < INFINITY)) return ng;
+  double g = (d - lo) / step;
+  int j = g < static_cast<double>(ng) ? static_cast<int>(g) : ng;
+  // count = first j with H0_j >= d
+  while (j > 0 && !(lo + static_cast<double>(j - 1) * step < d)) --j;
+  while (j < ng && lo + static_cast<double>(j) * step < d) ++j;
+  return j;
+}
+
+template <int NT, typename T, typename Op>
 __device__ inline T block_reduce(T v, T* sh, Op op) {
   sh[threadIdx.x] = v;
   __syncthreads();
-  for (int w = RB / 2; w > 0; w >>= 1) {
+  for (int w = NT / 2; w > 0; w >>= 1) {
     if (static_cast<int>(threadIdx.x) < w) sh[threadIdx.x] = op(sh[threadIdx.x], sh[threadIdx.x + w]);
     __syncthreads();
   }
   T r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// exclusive scan of one value per thread over a block of NT threads
+template <int NT>
+__device__ inline unsigned long long block_exscan(unsigned long long v, unsigned long long* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < NT; off <<= 1) {
+    unsigned long long t = threadIdx.x >= static_cast<unsigned>(off) ? sh[threadIdx.x - off] : 0ull;
+    __syncthreads();
+    sh[threadIdx.x] += t;
+    __syncthreads();
+  }
+  unsigned long long r = sh[threadIdx.x] - v;
   __syncthreads();
   return r;
 }
@@ -90,6 +139,11 @@ struct MaxOp {
   __device__ double operator()(double a, double b) const { return b > a ? b : a; }
 };
 
+__global__ void k_zero_u32(unsigned* p, long long n) {
+  long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
 __global__ __launch_bounds__(RB) void k_pass1(OutCols o, long long n, long long chunk, double glo,
                                               double gstep, int ng, unsigned* ghist, Partial* part) {
   __shared__ double shd[RB];
@@ -99,11 +153,13 @@ __global__ __launch_bounds__(RB) void k_pass1(OutCols o, long long n, long long 
   __syncthreads();
   const long long lo = static_cast<long long>(blockIdx.x) * chunk;
   const long long hi = lo + chunk < n ? lo + chunk : n;
-  long long ncol = 0, nstop = 0, nimp = 0, nhor = 0;
-  double sum = 0.0, dmin = INFINITY, dmax = -INFINITY, msum = 0.0, mmin = INFINITY;
+  long long ncol = 0, nstop = 0, nimp = 0, nhor = 0, nbnd = 0;
+  double sum = 0.0, dmin = INFINITY, dmax = -INFINITY, msum = 0.0, mmin = INFINITY,
+         mmax = -INFINITY;
   float vmax = 0.0f;
   for (long long i = lo + threadIdx.x; i < hi; i += RB) {
     const uint8_t st = o.status[i];
+    if (st & AEB_BOUNDARY) ++nbnd;
     const double d = o.dist[i];
     const double m = o.margin[i];
     const int end = st & 3;
@@ -124,22 +180,25 @@ __global__ __launch_bounds__(RB) void k_pass1(OutCols o, long long n, long long 
     }
     msum += m;
     mmin = m < mmin ? m : mmin;
+    mmax = m > mmax ? m : mmax;
     if (ng >= 2) {
       const double dc = end == AEB_END_STOP ? d : INFINITY;
       atomicAdd(&hist[grid_rank(dc, glo, gstep, ng)], 1u);
     }
   }
   Partial p;
-  p.ncol = block_reduce(ncol, shl, AddOp());
-  p.nstop = block_reduce(nstop, shl, AddOp());
-  p.nimp = block_reduce(nimp, shl, AddOp());
-  p.nhor = block_reduce(nhor, shl, AddOp());
-  p.sum = block_reduce(sum, shd, AddOp());
-  p.dmin = block_reduce(dmin, shd, MinOp());
-  p.dmax = block_reduce(dmax, shd, MaxOp());
-  p.msum = block_reduce(msum, shd, AddOp());
-  p.mmin = block_reduce(mmin, shd, MinOp());
-  p.vmax = static_cast<float>(block_reduce(static_cast<double>(vmax), shd, MaxOp()));
+  p.ncol = block_reduce<RB>(ncol, shl, AddOp());
+  p.nstop = block_reduce<RB>(nstop, shl, AddOp());
+  p.nimp = block_reduce<RB>(nimp, shl, AddOp());
+  p.nhor = block_reduce<RB>(nhor, shl, AddOp());
+  p.nbnd = block_reduce<RB>(nbnd, shl, AddOp());
+  p.sum = block_reduce<RB>(sum, shd, AddOp());
+  p.dmin = block_reduce<RB>(dmin, shd, MinOp());
+  p.dmax = block_reduce<RB>(dmax, shd, MaxOp());
+  p.msum = block_reduce<RB>(msum, shd, AddOp());
+  p.mmin = block_reduce<RB>(mmin, shd, MinOp());
+  p.mmax = block_reduce<RB>(mmax, shd, MaxOp());
+  p.vmax = static_cast<float>(block_reduce<RB>(static_cast<double>(vmax), shd, MaxOp()));
   p.pad = 0.0f;
   if (threadIdx.x == 0) part[blockIdx.x] = p;
   if (ng >= 2) {
@@ -148,72 +207,248 @@ __global__ __launch_bounds__(RB) void k_pass1(OutCols o, long long n, long long 
   }
 }
 
-__global__ void k_finalize1(const Partial* part, int nb, long long n, int ng,
-                            const unsigned* ghist, aeb_stats* st) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  long long ncol = 0, nstop = 0, nimp = 0, nhor = 0;
-  double sum = 0.0, dmin = INFINITY, dmax = -INFINITY, msum = 0.0, mmin = INFINITY;
-  float vmax = 0.0f;
-  for (int b = 0; b < nb; ++b) {
+// Combine the block partials in a fixed order (thread t takes partials
+// t, t+FB, ... in order, then a fixed tree), the risk curve by a block scan.
+__global__ __launch_bounds__(FB) void k_fin1(const Partial* part, int nb, long long n, int ng,
+                                             const unsigned* ghist, aeb_stats* st, Sel* sel) {
+  __shared__ double shd[FB];
+  __shared__ long long shl[FB];
+  __shared__ unsigned long long shu[FB];
+  long long ncol = 0, nstop = 0, nimp = 0, nhor = 0, nbnd = 0;
+  double sum = 0.0, dmin = INFINITY, dmax = -INFINITY, msum = 0.0, mmin = INFINITY,
+         mmax = -INFINITY;
+  double vmax = 0.0;
+  for (int b = threadIdx.x; b < nb; b += FB) {
     const Partial& p = part[b];
     ncol += p.ncol;
     nstop += p.nstop;
     nimp += p.nimp;
     nhor += p.nhor;
+    nbnd += p.nbnd;
     sum += p.sum;
     dmin = p.dmin < dmin ? p.dmin : dmin;
     dmax = p.dmax > dmax ? p.dmax : dmax;
     msum += p.msum;
     mmin = p.mmin < mmin ? p.mmin : mmin;
+    mmax = p.mmax > mmax ? p.mmax : mmax;
     vmax = p.vmax > vmax ? p.vmax : vmax;
   }
-  st->n = n;
-  st->n_collide = ncol;
-  st->n_stop = nstop;
-  st->n_impact = nimp;
-  st->n_horizon = nhor;
-  st->p_collision = static_cast<double>(ncol) / static_cast<double>(n);
-  st->mean_dist = nstop > 0 ? sum / static_cast<double>(nstop) : NAN;
-  st->dist_min = nstop > 0 ? dmin : NAN;
-  st->dist_max = nstop > 0 ? dmax : NAN;
-  st->sd_dist = NAN;
-  st->margin_min = mmin;
-  st->margin_mean = msum / static_cast<double>(n);
-  st->v_impact_max = vmax;
-  // risk curve: #{D > H0_j} = #{D whose grid rank exceeds j}
-  long long above = n;
-  for (int j = 0; j < ng; ++j) {
-    above -= ghist[j];
-    st->risk_count[j] = above;
-    st->risk_p[j] = static_cast<double>(above) / static_cast<double>(n);
+  ncol = block_reduce<FB>(ncol, shl, AddOp());
+  nstop = block_reduce<FB>(nstop, shl, AddOp());
+  nimp = block_reduce<FB>(nimp, shl, AddOp());
+  nhor = block_reduce<FB>(nhor, shl, AddOp());
+  nbnd = block_reduce<FB>(nbnd, shl, AddOp());
+  sum = block_reduce<FB>(sum, shd, AddOp());
+  dmin = block_reduce<FB>(dmin, shd, MinOp());
+  dmax = block_reduce<FB>(dmax, shd, MaxOp());
+  msum = block_reduce<FB>(msum, shd, AddOp());
+  mmin = block_reduce<FB>(mmin, shd, MinOp());
+  mmax = block_reduce<FB>(mmax, shd, MaxOp());
+  vmax = block_reduce<FB>(vmax, shd, MaxOp());
+  // risk curve: #{D > H0_j} = n - #{D with grid rank <= j}
+  constexpr int PER = (AEB_MAX_GRID + FB - 1) / FB;
+  unsigned long long loc = 0;
+  for (int q = 0; q < PER; ++q) {
+    const int j = threadIdx.x * PER + q;
+    if (j < ng) loc += ghist[j];
+  }
+  unsigned long long before = block_exscan<FB>(loc, shu);
+  for (int q = 0; q < PER; ++q) {
+    const int j = threadIdx.x * PER + q;
+    if (j < ng) {
+      before += ghist[j];
+      const long long above = n - static_cast<long long>(before);
+      st->risk_count[j] = above;
+      st->risk_p[j] = static_cast<double>(above) / static_cast<double>(n);
+    }
+  }
+  if (threadIdx.x == 0) {
+    st->n = n;
+    st->n_collide = ncol;
+    st->n_stop = nstop;
+    st->n_impact = nimp;
+    st->n_horizon = nhor;
+    st->n_boundary = nbnd;
+    st->p_collision = static_cast<double>(ncol) / static_cast<double>(n);
+    st->mean_dist = nstop > 0 ? sum / static_cast<double>(nstop) : NAN;
+    st->dist_min = nstop > 0 ? dmin : NAN;
+    st->dist_max = nstop > 0 ? dmax : NAN;
+    st->sd_dist = NAN;
+    st->margin_min = mmin;
+    st->margin_mean = msum / static_cast<double>(n);
+    st->v_impact_max = static_cast<float>(vmax);
+    // value bins span the finite range of each selected array
+    sel->vmin[0] = nstop > 0 ? dmin : 0.0;
+    sel->scale[0] = (nstop > 0 && dmax > dmin) ? static_cast<double>(NVB) / (dmax - dmin) : 0.0;
+    sel->vmin[1] = mmin;
+    sel->scale[1] = mmax > mmin ? static_cast<double>(NVB) / (mmax - mmin) : 0.0;
   }
 }
 
+// Sum of squared deviations for the sd, and block-private value histograms
+// (LDS, written out without atomics) of the arrays that have targets.
 __global__ __launch_bounds__(RB) void k_pass2(OutCols o, long long n, long long chunk,
-                                              const aeb_stats* st, double* part) {
+                                              const aeb_stats* st, const Sel* sel, int need_d,
+                                              int need_m, unsigned* bhist, double* part) {
   __shared__ double shd[RB];
+  __shared__ unsigned h[2 * (NVB + 1)];
+  for (int j = threadIdx.x; j < 2 * (NVB + 1); j += RB) h[j] = 0;
+  __syncthreads();
   const double mean = st->mean_dist;
+  const double vmin0 = sel->vmin[0], sc0 = sel->scale[0];
+  const double vmin1 = sel->vmin[1], sc1 = sel->scale[1];
   const long long lo = static_cast<long long>(blockIdx.x) * chunk;
   const long long hi = lo + chunk < n ? lo + chunk : n;
   double ss = 0.0;
   for (long long i = lo + threadIdx.x; i < hi; i += RB) {
-    if ((o.status[i] & 3) == AEB_END_STOP) {
-      const double e = o.dist[i] - mean;
+    const bool stop = (o.status[i] & 3) == AEB_END_STOP;
+    const double d = o.dist[i];
+    if (stop) {
+      const double e = d - mean;
       ss += e * e;
     }
+    if (need_d) atomicAdd(&h[value_bin(stop ? d : INFINITY, vmin0, sc0)], 1u);
+    if (need_m) atomicAdd(&h[(NVB + 1) + value_bin(o.margin[i], vmin1, sc1)], 1u);
   }
-  ss = block_reduce(ss, shd, AddOp());
+  ss = block_reduce<RB>(ss, shd, AddOp());
   if (threadIdx.x == 0) part[blockIdx.x] = ss;
+  __syncthreads();
+  unsigned* out = bhist + static_cast<size_t>(blockIdx.x) * 2 * (NVB + 1);
+  for (int j = threadIdx.x; j < 2 * (NVB + 1); j += RB) out[j] = h[j];
 }
 
-__global__ void k_finalize2(const double* part, int nb, aeb_stats* st) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double ss = 0.0;
-  for (int b = 0; b < nb; ++b) ss += part[b];
-  st->sd_dist = st->n_stop > 1 ? sqrt(ss / static_cast<double>(st->n_stop - 1)) : NAN;
+// Block 0: the sd.  Block 1 + t: sum the block histograms of target t's array
+// bin by bin, then find the bin holding its rank.
+__global__ __launch_bounds__(FB) void k_fin2(const double* part, int nb, aeb_stats* st, Sel* sel,
+                                             SelIn in, const unsigned* bhist) {
+  __shared__ double shd[FB];
+  __shared__ unsigned long long shu[FB];
+  if (blockIdx.x == 0) {
+    double ss = 0.0;
+    for (int b = threadIdx.x; b < nb; b += FB) ss += part[b];
+    ss = block_reduce<FB>(ss, shd, AddOp());
+    if (threadIdx.x == 0)
+      st->sd_dist = st->n_stop > 1 ? sqrt(ss / static_cast<double>(st->n_stop - 1)) : NAN;
+    return;
+  }
+  const int t = blockIdx.x - 1;
+  if (t >= in.count) return;
+  __shared__ unsigned tot[NVB + 1];
+  const int off = in.kind[t] ? (NVB + 1) : 0;
+  // bin totals over the blocks (adjacent threads read adjacent bins)
+  for (int j = threadIdx.x; j <= NVB; j += FB) {
+    unsigned c = 0;
+    for (int b = 0; b < nb; ++b) c += bhist[static_cast<size_t>(b) * 2 * (NVB + 1) + off + j];
+    tot[j] = c;
+  }
+  __syncthreads();
+  constexpr int PER = (NVB + 1 + FB - 1) / FB;
+  unsigned cnt[PER];
+  unsigned long long loc = 0;
+  for (int q = 0; q < PER; ++q) {
+    const int j = threadIdx.x * PER + q;
+    cnt[q] = j <= NVB ? tot[j] : 0u;
+    loc += cnt[q];
+  }
+  const unsigned long long r = in.rank[t];
+  unsigned long long before = block_exscan<FB>(loc, shu);
+  if (r >= before && r < before + loc) {
+    for (int q = 0; q < PER; ++q) {
+      const int j = threadIdx.x * PER + q;
+      if (j > NVB) break;
+      if (r < before + cnt[q]) {
+        sel->rank_in_bin[t] = static_cast<unsigned>(r - before);
+        sel->bin_count[t] = cnt[q];
+        if (j == NVB) {  // the rank falls among the censored (+inf) samples
+          sel->bin[t] = -1;
+          if (t < in.n_risk) st->headway[t] = INFINITY;
+        } else if (cnt[q] > CAP) {
+          sel->bin[t] = -1;
+          atomicOr(&sel->fallback, 1);
+        } else {
+          sel->bin[t] = j;
+        }
+        break;
+      }
+      before += cnt[q];
+    }
+  }
 }
 
-// one radix digit for every select target
+// Collect the keys of every element in a target's bin.
+__global__ __launch_bounds__(RB) void k_collect(OutCols o, long long n, long long chunk, Sel* sel,
+                                                SelIn in, unsigned long long* cand) {
+  __shared__ int tb[MAX_T], tk[MAX_T];
+  __shared__ double vmin[2], scale[2];
+  const int T = in.count;
+  if (static_cast<int>(threadIdx.x) < T) {
+    tb[threadIdx.x] = sel->bin[threadIdx.x];
+    tk[threadIdx.x] = in.kind[threadIdx.x];
+  }
+  if (threadIdx.x < 2) {
+    vmin[threadIdx.x] = sel->vmin[threadIdx.x];
+    scale[threadIdx.x] = sel->scale[threadIdx.x];
+  }
+  __syncthreads();
+  const long long lo = static_cast<long long>(blockIdx.x) * chunk;
+  const long long hi = lo + chunk < n ? lo + chunk : n;
+  for (long long i = lo + threadIdx.x; i < hi; i += RB) {
+    const double dc = censored(o.dist, o.status, i);
+    const double m = o.margin[i];
+    const int bd = value_bin(dc, vmin[0], scale[0]);
+    const int bm = value_bin(m, vmin[1], scale[1]);
+    for (int t = 0; t < T; ++t) {
+      const int b = tk[t] ? bm : bd;
+      if (tb[t] >= 0 && b == tb[t]) {
+        const unsigned slot = atomicAdd(&sel->ccount[t], 1u);
+        if (slot < CAP) cand[t * CAP + slot] = ordered(tk[t] ? m : dc);
+      }
+    }
+  }
+}
+
+// One block per target: sort the candidates in LDS, take the rank inside the bin.
+__global__ __launch_bounds__(RB) void k_pick(const Sel* sel, SelIn in,
+                                             const unsigned long long* cand, aeb_stats* st) {
+  __shared__ unsigned long long key[CAP];
+  const int t = blockIdx.x;
+  if (t >= in.count || sel->bin[t] < 0) return;
+  const unsigned m = sel->ccount[t] < CAP ? sel->ccount[t] : CAP;
+  unsigned p2 = 1;
+  while (p2 < m) p2 <<= 1;
+  for (unsigned j = threadIdx.x; j < p2; j += RB) key[j] = j < m ? cand[t * CAP + j] : ~0ull;
+  __syncthreads();
+  for (unsigned size = 2; size <= p2; size <<= 1) {
+    for (unsigned stride = size >> 1; stride > 0; stride >>= 1) {
+      for (unsigned j = threadIdx.x; j < p2; j += RB) {
+        const unsigned partner = j ^ stride;
+        if (partner > j) {
+          const bool up = (j & size) == 0;
+          const unsigned long long a = key[j], b = key[partner];
+          if ((a > b) == up) {
+            key[j] = b;
+            key[partner] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) {
+    const double v = unordered(key[sel->rank_in_bin[t]]);
+    if (t < in.n_risk)
+      st->headway[t] = v;
+    else
+      st->margin_q[t - in.n_risk] = v;
+  }
+}
+
+// the host reads the fallback flag through the statistics' reserved word
+__global__ void k_flag(const Sel* sel, aeb_stats* st) {
+  if (threadIdx.x == 0) st->reserved = sel->fallback;
+}
+
+// ---- fallback: most-significant-digit radix select, 8 passes of 8 bits ----
 __global__ __launch_bounds__(RB) void k_select_hist(OutCols o, long long n, long long chunk,
                                                     const SelState* ss, int pass, unsigned* ghist) {
   __shared__ unsigned hist[MAX_T * 256];
@@ -228,13 +463,11 @@ __global__ __launch_bounds__(RB) void k_select_hist(OutCols o, long long n, long
   __syncthreads();
   const int shift = 56 - 8 * pass;
   const unsigned long long mask = pass == 0 ? 0ull : (~0ull << (64 - 8 * pass));
-  bool need_d = false, need_m = false;
-  for (int t = 0; t < T; ++t) (kind[t] ? need_m : need_d) = true;
   const long long lo = static_cast<long long>(blockIdx.x) * chunk;
   const long long hi = lo + chunk < n ? lo + chunk : n;
   for (long long i = lo + threadIdx.x; i < hi; i += RB) {
-    const unsigned long long kd = need_d ? ordered(censored(o.dist, o.status, i)) : 0ull;
-    const unsigned long long km = need_m ? ordered(o.margin[i]) : 0ull;
+    const unsigned long long kd = ordered(censored(o.dist, o.status, i));
+    const unsigned long long km = ordered(o.margin[i]);
     for (int t = 0; t < T; ++t) {
       const unsigned long long key = kind[t] ? km : kd;
       if ((key & mask) == (pre[t] & mask))
@@ -271,11 +504,6 @@ __global__ void k_select_out(const SelState* ss, int n_risk, aeb_stats* st) {
     st->margin_q[t - n_risk] = v;
 }
 
-__global__ void k_zero_u32(unsigned* p, long long n) {
-  long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
-}
-
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 }  // namespace
@@ -286,62 +514,94 @@ int launch_reduce(const OutCols& out, int64_t n, const aeb_reduce_req& req, aeb_
   const int nb = static_cast<int>((n + chunk - 1) / chunk);
   const int ng = req.n_grid;
   const int T = req.n_risk + req.n_margin_q;
-  // scratch layout
-  size_t off_part = 0;
-  size_t off_var = align256(off_part + sizeof(Partial) * nb);
-  size_t off_stats = align256(off_var + sizeof(double) * nb);
-  size_t off_rh = align256(off_stats + sizeof(aeb_stats));
-  size_t off_ss = align256(off_rh + sizeof(unsigned) * (AEB_MAX_GRID + 1));
-  size_t off_sh = align256(off_ss + sizeof(SelState));
-  size_t total = align256(off_sh + sizeof(unsigned) * MAX_T * 256);
+  // scratch layout; stats, grid histogram and Sel are zeroed by one launch
+  const size_t off_stats = 0;
+  const size_t off_rh = align256(off_stats + sizeof(aeb_stats));
+  const size_t off_sel = align256(off_rh + sizeof(unsigned) * (AEB_MAX_GRID + 1));
+  const size_t off_zero_end = align256(off_sel + sizeof(Sel));
+  const size_t off_part = off_zero_end;
+  const size_t off_var = align256(off_part + sizeof(Partial) * nb);
+  const size_t off_bh = align256(off_var + sizeof(double) * nb);
+  const size_t off_cand = align256(off_bh + sizeof(unsigned) * 2 * (NVB + 1) * nb);
+  const size_t off_ss = align256(off_cand + sizeof(unsigned long long) * MAX_T * CAP);
+  const size_t off_sh = align256(off_ss + sizeof(SelState));
+  const size_t total = align256(off_sh + sizeof(unsigned) * MAX_T * 256);
   char* base = static_cast<char*>(scratch(total, st));
   if (!base) return AEB_ENOMEM;
-  Partial* part = reinterpret_cast<Partial*>(base + off_part);
-  double* vpart = reinterpret_cast<double*>(base + off_var);
   aeb_stats* dstats = reinterpret_cast<aeb_stats*>(base + off_stats);
   unsigned* rhist = reinterpret_cast<unsigned*>(base + off_rh);
+  Sel* sel = reinterpret_cast<Sel*>(base + off_sel);
+  Partial* part = reinterpret_cast<Partial*>(base + off_part);
+  double* vpart = reinterpret_cast<double*>(base + off_var);
+  unsigned* bhist = reinterpret_cast<unsigned*>(base + off_bh);
+  unsigned long long* cand = reinterpret_cast<unsigned long long*>(base + off_cand);
   SelState* ss = reinterpret_cast<SelState*>(base + off_ss);
   unsigned* shist = reinterpret_cast<unsigned*>(base + off_sh);
 
-  // select targets: ranks computed exactly as floor(level * N) in binary64
-  SelState hs;
-  std::memset(&hs, 0, sizeof(hs));
-  hs.count = T;
+  // targets: ranks computed exactly as floor(level * N) in binary64
+  SelIn in;
+  std::memset(&in, 0, sizeof(in));
+  in.count = T;
+  in.n_risk = req.n_risk;
+  bool need_d = false, need_m = false;
   for (int j = 0; j < req.n_risk; ++j) {
     long long m = static_cast<long long>(std::floor(req.risk[j] * static_cast<double>(n)));
-    hs.rank[j] = static_cast<unsigned long long>(n - m - 1);
-    hs.kind[j] = 0;
+    in.rank[j] = static_cast<unsigned long long>(n - m - 1);
+    in.kind[j] = 0;
+    need_d = true;
   }
   for (int j = 0; j < req.n_margin_q; ++j) {
     long long m = static_cast<long long>(std::floor(req.margin_q[j] * static_cast<double>(n)));
-    hs.rank[req.n_risk + j] = static_cast<unsigned long long>(m);
-    hs.kind[req.n_risk + j] = 1;
+    in.rank[req.n_risk + j] = static_cast<unsigned long long>(m);
+    in.kind[req.n_risk + j] = 1;
+    need_m = true;
   }
-  AEB_HIP(hipMemcpyAsync(ss, &hs, sizeof(hs), hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(k_zero_u32, dim3((AEB_MAX_GRID + 1 + 255) / 256), dim3(256), 0, st, rhist,
-                     static_cast<long long>(AEB_MAX_GRID + 1));
-  hipLaunchKernelGGL(k_zero_u32, dim3((MAX_T * 256 + 255) / 256), dim3(256), 0, st, shist,
-                     static_cast<long long>(MAX_T * 256));
-  AEB_HIP(hipMemsetAsync(dstats, 0, sizeof(aeb_stats), st));
+  static_assert(sizeof(aeb_stats) % 4 == 0, "stats size");
+  const long long zero_words = static_cast<long long>(off_zero_end / 4);
+  hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<unsigned>((zero_words + 255) / 256)), dim3(256),
+                     0, st, reinterpret_cast<unsigned*>(base), zero_words);
   const double gstep = ng >= 2 ? (req.grid_hi - req.grid_lo) / static_cast<double>(ng - 1) : 0.0;
   hipLaunchKernelGGL(k_pass1, dim3(nb), dim3(RB), 0, st, out, static_cast<long long>(n), chunk,
                      req.grid_lo, gstep, ng, rhist, part);
-  hipLaunchKernelGGL(k_finalize1, dim3(1), dim3(64), 0, st, part, nb, static_cast<long long>(n), ng,
-                     rhist, dstats);
+  hipLaunchKernelGGL(k_fin1, dim3(1), dim3(FB), 0, st, part, nb, static_cast<long long>(n), ng,
+                     rhist, dstats, sel);
   hipLaunchKernelGGL(k_pass2, dim3(nb), dim3(RB), 0, st, out, static_cast<long long>(n), chunk,
-                     dstats, vpart);
-  hipLaunchKernelGGL(k_finalize2, dim3(1), dim3(64), 0, st, vpart, nb, dstats);
+                     dstats, sel, need_d ? 1 : 0, need_m ? 1 : 0, bhist, vpart);
+  hipLaunchKernelGGL(k_fin2, dim3(1 + T), dim3(FB), 0, st, vpart, nb, dstats, sel, in, bhist);
   if (T > 0) {
-    for (int pass = 0; pass < 8; ++pass) {
-      hipLaunchKernelGGL(k_select_hist, dim3(nb), dim3(RB), 0, st, out, static_cast<long long>(n),
-                         chunk, ss, pass, shist);
-      hipLaunchKernelGGL(k_select_step, dim3(1), dim3(64), 0, st, ss, pass, shist);
-    }
-    hipLaunchKernelGGL(k_select_out, dim3(1), dim3(64), 0, st, ss, req.n_risk, dstats);
+    hipLaunchKernelGGL(k_collect, dim3(nb), dim3(RB), 0, st, out, static_cast<long long>(n), chunk,
+                       sel, in, cand);
+    hipLaunchKernelGGL(k_pick, dim3(T), dim3(RB), 0, st, sel, in, cand, dstats);
+    hipLaunchKernelGGL(k_flag, dim3(1), dim3(64), 0, st, sel, dstats);
   }
   AEB_HIP(hipGetLastError());
   AEB_HIP(hipMemcpyAsync(host_out, dstats, sizeof(aeb_stats), hipMemcpyDeviceToHost, st));
   AEB_HIP(hipStreamSynchronize(st));
+  const int fallback = host_out->reserved;
+  host_out->reserved = 0;
+  if (!fallback) return AEB_OK;
+
+  // a target's value bin holds more than CAP distinct candidates: radix select
+  SelState rs;
+  std::memset(&rs, 0, sizeof(rs));
+  rs.count = T;
+  for (int t = 0; t < T; ++t) {
+    rs.rank[t] = in.rank[t];
+    rs.kind[t] = in.kind[t];
+  }
+  AEB_HIP(hipMemcpyAsync(ss, &rs, sizeof(rs), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_zero_u32, dim3((MAX_T * 256 + 255) / 256), dim3(256), 0, st, shist,
+                     static_cast<long long>(MAX_T * 256));
+  for (int pass = 0; pass < 8; ++pass) {
+    hipLaunchKernelGGL(k_select_hist, dim3(nb), dim3(RB), 0, st, out, static_cast<long long>(n),
+                       chunk, ss, pass, shist);
+    hipLaunchKernelGGL(k_select_step, dim3(1), dim3(64), 0, st, ss, pass, shist);
+  }
+  hipLaunchKernelGGL(k_select_out, dim3(1), dim3(64), 0, st, ss, req.n_risk, dstats);
+  AEB_HIP(hipGetLastError());
+  AEB_HIP(hipMemcpyAsync(host_out, dstats, sizeof(aeb_stats), hipMemcpyDeviceToHost, st));
+  AEB_HIP(hipStreamSynchronize(st));
+  host_out->reserved = 0;
   return AEB_OK;
 }
 

@@ -76,12 +76,16 @@ __global__ __launch_bounds__(256) void k_rollout_fp32c(aeb_scenario s, ParamSrc 
   Result r = euler_fp32c<OBS>(L, s.dt, s.a_cmd, nd, nmax, s.impact_exit, band, boundary);
   store(out, i, r);
   if (boundary) {
-    uint32_t slot = atomicAdd(fix, 1u);
-    fix[1 + slot] = static_cast<uint32_t>(i);
+    if (fix) {
+      uint32_t slot = atomicAdd(fix, 1u);
+      fix[1 + slot] = static_cast<uint32_t>(i);
+    }
+    out.status[i] = static_cast<uint8_t>(r.status | AEB_BOUNDARY);
   }
 }
 
-// FP64 recomputation of the samples listed in fix[1 .. fix[0]]
+// FP64 recomputation of the samples listed in fix[1 .. fix[0]]; clears the
+// boundary bit
 template <int OBS, bool DEVRNG>
 __global__ __launch_bounds__(256) void k_fixup_fp64(aeb_scenario s, ParamSrc src, OutCols out,
                                                     int64_t nd, int64_t nmax, const uint32_t* fix) {
@@ -117,8 +121,8 @@ static void go_fp64(const aeb_scenario& s, const ParamSrc* src, const OutCols& o
 
 template <int OBS>
 static int go_fp32c(const aeb_scenario& s, const ParamSrc* src, const OutCols& out, int64_t n,
-                    int64_t nd, int64_t nmax, hipStream_t st) {
-  uint32_t* fix = static_cast<uint32_t*>(scratch(sizeof(uint32_t) * (n + 1), st));
+                    int64_t nd, int64_t nmax, bool fixup, hipStream_t st) {
+  uint32_t* fix = static_cast<uint32_t*>(scratch_fix(sizeof(uint32_t) * (n + 1), st));
   if (!fix) return AEB_ENOMEM;
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, fix, int64_t(1), 0u);
   dim3 grid(static_cast<unsigned>((n + 255) / 256)), block(256);
@@ -126,15 +130,39 @@ static int go_fp32c(const aeb_scenario& s, const ParamSrc* src, const OutCols& o
   // single-precision distance and clearance errors stay below ~1e-4 m; outcomes
   // within 1 mm (+1e-5 of the gap) of the boundary are recomputed in FP64
   const double band_abs = 1e-3, band_rel = 1e-5;
-  if (src) {
+  timing_begin(st);
+  if (src)
     hipLaunchKernelGGL((k_rollout_fp32c<OBS, false>), grid, block, 0, st, s, p, out, n, nd, nmax,
-                       band_abs, band_rel, fix);
-    hipLaunchKernelGGL((k_fixup_fp64<OBS, false>), dim3(64), block, 0, st, s, p, out, nd, nmax, fix);
-  } else {
+                       band_abs, band_rel, fixup ? fix : nullptr);
+  else
     hipLaunchKernelGGL((k_rollout_fp32c<OBS, true>), grid, block, 0, st, s, p, out, n, nd, nmax,
-                       band_abs, band_rel, fix);
-    hipLaunchKernelGGL((k_fixup_fp64<OBS, true>), dim3(64), block, 0, st, s, p, out, nd, nmax, fix);
+                       band_abs, band_rel, fixup ? fix : nullptr);
+  timing_end(st);
+  if (fixup) return launch_fixup(s, src, out, fix, st);
+  return AEB_OK;
+}
+
+template <int OBS>
+static void go_fixup(const aeb_scenario& s, const ParamSrc* src, const OutCols& out,
+                     const uint32_t* fix, hipStream_t st) {
+  const int64_t nd = dead_steps(s), nmax = horizon_steps(s);
+  ParamSrc p = src ? *src : ParamSrc{};
+  if (src)
+    hipLaunchKernelGGL((k_fixup_fp64<OBS, false>), dim3(64), dim3(256), 0, st, s, p, out, nd, nmax,
+                       fix);
+  else
+    hipLaunchKernelGGL((k_fixup_fp64<OBS, true>), dim3(64), dim3(256), 0, st, s, p, out, nd, nmax,
+                       fix);
+}
+
+int launch_fixup(const aeb_scenario& s, const ParamSrc* src, const OutCols& out,
+                 const uint32_t* fix, hipStream_t st) {
+  switch (s.obstacle) {
+    case AEB_OBS_NONE: go_fixup<AEB_OBS_NONE>(s, src, out, fix, st); break;
+    case AEB_OBS_STATIONARY: go_fixup<AEB_OBS_STATIONARY>(s, src, out, fix, st); break;
+    default: go_fixup<AEB_OBS_LEAD>(s, src, out, fix, st); break;
   }
+  AEB_HIP(hipGetLastError());
   return AEB_OK;
 }
 
@@ -142,33 +170,40 @@ int launch_rollout(const aeb_scenario& s, const ParamSrc* src, int precision, co
                    int64_t n, hipStream_t st) {
   const int64_t nd = dead_steps(s), nmax = horizon_steps(s);
   if (fast_path_applies(s, precision)) return launch_rollout_fast(s, src, precision, out, n, st);
-  if (precision == AEB_FP32C) {
+  if (precision == AEB_FP32C || precision == AEB_FP32C_FIXUP) {
     if (s.integrator != AEB_EULER)
       return fail(AEB_EINVAL, "the FP32 compensated form is available for the Euler integrator");
+    const bool fixup = precision == AEB_FP32C_FIXUP;
     int rc = AEB_OK;
     switch (s.obstacle) {
-      case AEB_OBS_NONE: rc = go_fp32c<AEB_OBS_NONE>(s, src, out, n, nd, nmax, st); break;
-      case AEB_OBS_STATIONARY: rc = go_fp32c<AEB_OBS_STATIONARY>(s, src, out, n, nd, nmax, st); break;
-      default: rc = go_fp32c<AEB_OBS_LEAD>(s, src, out, n, nd, nmax, st); break;
+      case AEB_OBS_NONE: rc = go_fp32c<AEB_OBS_NONE>(s, src, out, n, nd, nmax, fixup, st); break;
+      case AEB_OBS_STATIONARY: rc = go_fp32c<AEB_OBS_STATIONARY>(s, src, out, n, nd, nmax, fixup, st); break;
+      default: rc = go_fp32c<AEB_OBS_LEAD>(s, src, out, n, nd, nmax, fixup, st); break;
     }
     if (rc != AEB_OK) return rc;
   } else if (s.integrator == AEB_RK4) {
+    timing_begin(st);
     if (s.obstacle == AEB_OBS_NONE)
       go_fp64<AEB_RK4, AEB_OBS_NONE, false>(s, src, out, n, nd, nmax, st);
     else
       go_fp64<AEB_RK4, AEB_OBS_STATIONARY, false>(s, src, out, n, nd, nmax, st);
+    timing_end(st);
   } else if (s.nofma) {
+    timing_begin(st);
     switch (s.obstacle) {
       case AEB_OBS_NONE: go_fp64<AEB_EULER, AEB_OBS_NONE, true>(s, src, out, n, nd, nmax, st); break;
       case AEB_OBS_STATIONARY: go_fp64<AEB_EULER, AEB_OBS_STATIONARY, true>(s, src, out, n, nd, nmax, st); break;
       default: go_fp64<AEB_EULER, AEB_OBS_LEAD, true>(s, src, out, n, nd, nmax, st); break;
     }
+    timing_end(st);
   } else {
+    timing_begin(st);
     switch (s.obstacle) {
       case AEB_OBS_NONE: go_fp64<AEB_EULER, AEB_OBS_NONE, false>(s, src, out, n, nd, nmax, st); break;
       case AEB_OBS_STATIONARY: go_fp64<AEB_EULER, AEB_OBS_STATIONARY, false>(s, src, out, n, nd, nmax, st); break;
       default: go_fp64<AEB_EULER, AEB_OBS_LEAD, false>(s, src, out, n, nd, nmax, st); break;
     }
+    timing_end(st);
   }
   AEB_HIP(hipGetLastError());
   return AEB_OK;
