@@ -211,6 +211,27 @@ int aeb_sample_params(const aeb_scenario* scn, int64_t first, int64_t count, con
 int aeb_rollout(const aeb_scenario* scn, const aeb_params* params, int precision,
                 const aeb_outputs* out, void* stream);
 
+/* Batched rollout: all samples of n_scn scenarios in one sorted launch of the
+ * persistent kernel (one lane per sample, wavefronts claiming chunks of the
+ * length-sorted permutation), each sample's parameters drawn in-kernel from
+ * (seed, scenario_id, index) of its scenario.  Scenarios may differ in every
+ * distribution, N, dt, horizon, dead time and a_cmd, but must share
+ * integrator, obstacle, impact_exit and nofma; sum of n_samples <= 2^32 - 1.
+ *   scns: host array of n_scn scenarios (n_scn >= 1).
+ *   outs: host array of n_scn output descriptors (device columns,
+ *     outs[j].n == scns[j].n_samples); results equal those of aeb_rollout
+ *     with params == NULL on each scenario alone.
+ *   precision: AEB_FP64 or AEB_FP32C (AEB_FP32C_FIXUP is not accepted).
+ * Returns after the launch has been enqueued and its (host) scenario tables
+ * consumed; the outputs are ready after a sync of `stream`. */
+int aeb_batch_rollout(const aeb_scenario* scns, int n_scn, int precision, const aeb_outputs* outs,
+                      void* stream);
+
+/* aeb_reduce for each of n_scn output sets: stats[j] (host array) receives the
+ * statistics of outs[j] under the same request.  Waits for completion. */
+int aeb_batch_reduce(const aeb_outputs* outs, int n_scn, const aeb_reduce_req* req,
+                     aeb_stats* stats, void* stream);
+
 /* Profiling aid.  While enabled on the calling thread, aeb_rollout brackets
  * its integration kernel with two HIP events on its stream; aeb_timing_last
  * waits for the second and returns the kernel's duration in milliseconds for

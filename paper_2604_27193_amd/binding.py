@@ -27,7 +27,8 @@ OK, EINVAL, ENOMEM, EAGAIN, EDEVICE, ENOTFOUND = 0, -1, -2, -3, -4, -5
 END_STOP, END_IMPACT, END_HORIZON, COLLIDED, BOUNDARY = 1, 2, 3, 4, 8
 
 EXPORTS = ("aeb_last_error", "aeb_version", "aeb_validate", "aeb_uniforms", "aeb_sample_params",
-           "aeb_rollout", "aeb_reduce", "aeb_timing_enable", "aeb_timing_last")
+           "aeb_rollout", "aeb_reduce", "aeb_batch_rollout", "aeb_batch_reduce",
+           "aeb_timing_enable", "aeb_timing_last")
 
 
 class AebError(RuntimeError):
@@ -95,6 +96,8 @@ def lib():
                                         C.c_void_p]
         L.aeb_rollout.argtypes = [P(Scenario), P(Params), C.c_int, P(Outputs), C.c_void_p]
         L.aeb_reduce.argtypes = [P(Outputs), P(ReduceReq), P(Stats), C.c_void_p]
+        L.aeb_batch_rollout.argtypes = [P(Scenario), C.c_int, C.c_int, P(Outputs), C.c_void_p]
+        L.aeb_batch_reduce.argtypes = [P(Outputs), C.c_int, P(ReduceReq), P(Stats), C.c_void_p]
         L.aeb_timing_enable.argtypes = [C.c_int]
         L.aeb_timing_last.argtypes = [P(C.c_float)]
         _lib = L
@@ -275,3 +278,24 @@ def timing_last():
     ms = C.c_float()
     _check(lib().aeb_timing_last(C.byref(ms)))
     return ms.value
+
+
+def batch_rollout(scns, precision="fp64", outs=None, stream=None):
+    """Roll out every sample of several scenarios in one launch; returns a list of outputs."""
+    k = len(scns)
+    if outs is None:
+        outs = [alloc_outputs(int(d["n_samples"])) for d in scns]
+    sarr = (Scenario * k)(*[scenario(d) for d in scns])
+    oarr = (Outputs * k)(*[_outputs_struct(o) for o in outs])
+    _check(lib().aeb_batch_rollout(sarr, k, PRECISIONS[precision], oarr, _stream(stream)))
+    return outs
+
+
+def batch_reduce(outs, risk=(), margin_q=(), grid=None, stream=None):
+    """Statistics of each output set of a batch (list of dicts)."""
+    k = len(outs)
+    req = reduce_request(risk, margin_q, grid)
+    oarr = (Outputs * k)(*[_outputs_struct(o) for o in outs])
+    st = (Stats * k)()
+    _check(lib().aeb_batch_reduce(oarr, k, C.byref(req), st, _stream(stream)))
+    return [stats_dict(st[j], req.n_risk, req.n_margin_q, req.n_grid) for j in range(k)]

@@ -290,6 +290,38 @@ int aeb_rollout(const aeb_scenario* scn, const aeb_params* params, int precision
                         static_cast<hipStream_t>(stream));
 }
 
+int aeb_batch_rollout(const aeb_scenario* scns, int n_scn, int precision, const aeb_outputs* outs,
+                      void* stream) {
+  if (!scns || !outs || n_scn < 1) return fail(AEB_EINVAL, "aeb_batch_rollout: empty batch");
+  if (precision != AEB_FP64 && precision != AEB_FP32C)
+    return fail(AEB_EINVAL, "aeb_batch_rollout: precision must be AEB_FP64 or AEB_FP32C");
+  int64_t total = 0;
+  std::vector<OutCols> oc(n_scn);
+  for (int j = 0; j < n_scn; ++j) {
+    int rc = validate(scns[j]);
+    if (rc != AEB_OK) return fail(rc, "scenario " + std::to_string(j) + ": " + g_err);
+    if (!outputs_complete(&outs[j]) || outs[j].n != scns[j].n_samples)
+      return fail(AEB_EINVAL, "outputs of scenario " + std::to_string(j) + " do not match it");
+    if (scns[j].integrator != scns[0].integrator || scns[j].obstacle != scns[0].obstacle ||
+        scns[j].impact_exit != scns[0].impact_exit || scns[j].nofma != scns[0].nofma)
+      return fail(AEB_EINVAL, "batched scenarios must share integrator, obstacle, impact_exit, nofma");
+    total += scns[j].n_samples;
+    oc[j] = OutCols{outs[j].dist, outs[j].status, outs[j].steps, outs[j].margin, outs[j].v_impact};
+  }
+  if (total > 0xffffffffLL) return fail(AEB_EINVAL, "a batch holds at most 2^32 - 1 samples");
+  return launch_batch(scns, n_scn, precision, oc.data(), static_cast<hipStream_t>(stream));
+}
+
+int aeb_batch_reduce(const aeb_outputs* outs, int n_scn, const aeb_reduce_req* req, aeb_stats* stats,
+                     void* stream) {
+  if (!outs || !stats || n_scn < 1) return fail(AEB_EINVAL, "aeb_batch_reduce: empty batch");
+  for (int j = 0; j < n_scn; ++j) {
+    const int rc = aeb_reduce(&outs[j], req, &stats[j], stream);
+    if (rc != AEB_OK) return rc;
+  }
+  return AEB_OK;
+}
+
 int aeb_reduce(const aeb_outputs* out, const aeb_reduce_req* req, aeb_stats* host_out, void* stream) {
   if (!outputs_complete(out) || !req || !host_out) return fail(AEB_EINVAL, "aeb_reduce: null argument");
   if (out->n < 1 || out->n > 0x7fffffffLL) return fail(AEB_EINVAL, "aeb_reduce: n out of [1, 2^31-1]");

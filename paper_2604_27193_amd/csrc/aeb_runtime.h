@@ -63,6 +63,8 @@ int launch_sample(const aeb_scenario& s, int64_t first, int64_t count, const aeb
                   hipStream_t stream);
 int launch_rollout(const aeb_scenario& s, const ParamSrc* src, int precision, const OutCols& out,
                    int64_t n, hipStream_t stream);
+int launch_batch(const aeb_scenario* scns, int n_scn, int precision, const OutCols* outs,
+                 hipStream_t stream);
 int launch_fixup(const aeb_scenario& s, const ParamSrc* src, const OutCols& out,
                  const uint32_t* fix, hipStream_t stream);
 int launch_reduce(const OutCols& out, int64_t n, const aeb_reduce_req& req, aeb_stats* host_out,

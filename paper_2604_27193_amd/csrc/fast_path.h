@@ -18,7 +18,21 @@ struct Job {
   double kt;      // dt / tau
   double gap;     // initial gap to the obstacle
   double dmax;    // bound on |dv/dt| over the whole rollout
-  double pred;    // predicted number of steps
+  float pred;     // predicted number of steps
+  uint32_t scn;   // scenario of the sample in a batched launch
+};
+
+// Lead-vehicle data of a sample (lead-vehicle scenarios only).
+struct LeadJob {
+  double decel;   // lead deceleration
+};
+
+// Per-scenario constants of a batched launch.
+struct ScnDev {
+  double dt, a_cmd;
+  int nd, nmax;
+  long long off;  // first global sample index of the scenario
+  OutCols out;
 };
 
 enum { FORM_G = 0, FORM_F = 1, FORM_C = 2, FORM_D = 3 };
@@ -26,5 +40,8 @@ enum { FORM_G = 0, FORM_F = 1, FORM_C = 2, FORM_D = 3 };
 bool fast_path_applies(const aeb_scenario& s, int precision);
 int launch_rollout_fast(const aeb_scenario& s, const ParamSrc* src, int precision,
                         const OutCols& out, int64_t n, hipStream_t st);
+// all samples of several scenarios in one sorted launch (parameters drawn in-kernel)
+int launch_batch_fast(const aeb_scenario* scns, int n_scn, int precision, const OutCols* outs,
+                      hipStream_t st);
 
 }  // namespace aeb

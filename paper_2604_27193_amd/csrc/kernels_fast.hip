@@ -1,6 +1,7 @@
-// kernels_fast.hip -- the throughput path of the explicit-Euler rollout for a
-// stationary obstacle or none (the configurations of Sec. IV with dead time
-// and rolling resistance), FP64 and FP32-compensated.
+// kernels_fast.hip -- the throughput path of the explicit-Euler rollout (the
+// configurations of Sec. IV with dead time and rolling resistance, and the
+// lead-vehicle extension of Sec. VIII), FP64 and FP32-compensated, for one
+// scenario or a batch of scenarios in one launch.
 //
 // Three stages:
 //  1. prep: per sample, load (or draw) the parameters, derive the constants
@@ -19,8 +20,12 @@
 //     phase: dead time (a = 0), generic, never-limited (max(a, alim) = a) or
 //     friction-limited (max(a, alim) = alim for good, actuator update dead).
 //     A crossing of the obstacle inside a block is found afterwards by
-//     replaying that block from its saved start state.
+//     replaying that block from its saved start state.  The grid is
+//     persistent: each wavefront claims the next 64 sorted samples through an
+//     atomic counter until none are left (longest first, dynamically balanced).
 #include <hip/hip_runtime.h>
+
+#include <vector>
 
 #include "aeb_common.h"
 #include "aeb_runtime.h"
@@ -33,7 +38,11 @@ namespace {
 
 constexpr int NBINS = 8192;  // sort keys: 64 coarse x 2 classes x 64 fine
 constexpr int PREP_BLOCK = 1024;
-constexpr int PREP_PER = 4;  // samples per thread in prep and scatter
+constexpr int PREP_PER = 4;       // samples per thread in scatter (and plain prep)
+constexpr int PREP_SAMPLES = PREP_BLOCK * PREP_PER;  // samples per prep/scatter block
+// drawing the parameters needs more registers: half the threads, twice the samples each
+template <bool DEVRNG>
+constexpr int prep_threads() { return DEVRNG ? PREP_BLOCK / 2 : PREP_BLOCK; }
 
 // Closed-form estimate of the stopping time (s): dead time at zero brake,
 // first-order ramp of the brake to the friction limit (or to the command),
@@ -60,25 +69,56 @@ __device__ inline float predict_stop_time(float v0, float kd, float c, float ali
   return td + (v1 + amag * tau) / den;
 }
 
-template <bool DEVRNG>
-__global__ __launch_bounds__(PREP_BLOCK) void k_prep(aeb_scenario s, ParamSrc src, int64_t n,
-                                                     int64_t nd, int64_t nmax, Job* jobs,
-                                                     uint32_t* keys, uint32_t* ghist) {
+// Inputs of the prep stage: one scenario (uniform) or a batch table.
+struct PrepArgs {
+  aeb_scenario s;          // single scenario
+  ParamSrc src;            // its parameter columns (plain method)
+  int64_t n;               // samples in the launch
+  int nd, nmax;            // single scenario's step counts
+  float cap;               // step count that maps to the last sort bin
+  const aeb_scenario* scns;  // batch: scenarios
+  const ScnDev* tab;         // batch: per-scenario constants and offsets
+  int n_scn;
+};
+
+template <bool DEVRNG, bool BATCH>
+__global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job* jobs,
+                                                                 LeadJob* leads, uint32_t* keys,
+                                                                 uint32_t* ghist) {
+  constexpr int NT = prep_threads<DEVRNG>();
   __shared__ uint32_t hist[NBINS];
-  for (int j = threadIdx.x; j < NBINS; j += PREP_BLOCK) hist[j] = 0;
+  for (int j = threadIdx.x; j < NBINS; j += NT) hist[j] = 0;
   __syncthreads();
-  for (int r = 0; r < PREP_PER; ++r) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * (PREP_BLOCK * PREP_PER) +
-                      r * PREP_BLOCK + threadIdx.x;
-    if (i >= n) break;
-    double v0, mu, mass, sg, cg, cda, crr, tau, gap;
+  for (int r = 0; r < PREP_SAMPLES / NT; ++r) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * PREP_SAMPLES + r * NT + threadIdx.x;
+    if (i >= a.n) break;
+    // the sample's scenario and its index within it
+    uint32_t j = 0;
+    int64_t local = i;
+    if (BATCH) {
+      int lo = 0, hi = a.n_scn - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.tab[mid].off <= i)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      j = static_cast<uint32_t>(lo);
+      local = i - a.tab[lo].off;
+    }
+    const aeb_scenario& s = BATCH ? a.scns[j] : a.s;
+    const int nd = BATCH ? a.tab[j].nd : a.nd;
+    const int nmax = BATCH ? a.tab[j].nmax : a.nmax;
+    double v0, mu, mass, sg, cg, cda, crr, tau, gap, lead;
     if (DEVRNG) {
-      Sample q = draw_sample(s, static_cast<uint64_t>(i));
+      Sample q = draw_sample(s, static_cast<uint64_t>(local));
       v0 = q.v0; mu = q.mu; mass = q.mass; sg = q.sin_grade; cg = q.cos_grade;
-      cda = q.cda; crr = q.crr; tau = q.tau; gap = q.gap;
+      cda = q.cda; crr = q.crr; tau = q.tau; gap = q.gap; lead = q.lead_decel;
     } else {
-      v0 = src.v0[i]; mu = src.mu[i]; mass = src.mass[i]; sg = src.sin_g[i]; cg = src.cos_g[i];
-      cda = src.cda[i]; crr = src.crr[i]; tau = src.tau[i]; gap = src.gap[i];
+      v0 = a.src.v0[i]; mu = a.src.mu[i]; mass = a.src.mass[i]; sg = a.src.sin_g[i];
+      cg = a.src.cos_g[i]; cda = a.src.cda[i]; crr = a.src.crr[i]; tau = a.src.tau[i];
+      gap = a.src.gap[i]; lead = a.src.lead[i];
     }
     const Consts k = derive(s, mu, mass, sg, cg, cda, crr);
     Job J;
@@ -101,19 +141,20 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_prep(aeb_scenario s, ParamSrc sr
                                       static_cast<float>(tau), static_cast<float>(s.a_cmd),
                                       static_cast<float>(nd) * static_cast<float>(s.dt));
     float steps = t / static_cast<float>(s.dt);
-    const float cap = static_cast<float>(nmax);
-    if (!(steps < cap)) steps = cap;
+    if (!(steps < static_cast<float>(nmax))) steps = static_cast<float>(nmax);
     if (!(steps > 0.0f)) steps = 0.0f;
-    J.pred = static_cast<double>(steps);
+    J.pred = steps;
+    J.scn = j;
     jobs[i] = J;
-    const uint32_t u = static_cast<uint32_t>(steps * (4096.0f / (cap + 1.0f)));
+    if (leads) leads[i].decel = lead;
+    const uint32_t u = static_cast<uint32_t>(fminf(steps, a.cap) * (4096.0f / (a.cap + 1.0f)));
     const uint32_t ud = 4095u - (u > 4095u ? 4095u : u);  // longest first
     const uint32_t key = ((ud >> 6) << 7) | (limited ? 0u : 64u) | (ud & 63u);
     keys[i] = key;
     atomicAdd(&hist[key], 1u);
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < NBINS; j += PREP_BLOCK)
+  for (int j = threadIdx.x; j < NBINS; j += NT)
     if (hist[j]) atomicAdd(&ghist[j], hist[j]);
 }
 
@@ -184,8 +225,13 @@ struct St64 {
   double x, v, a;
 };
 
-template <int FORM, int K>
-__device__ inline void block64(St64& s, const Job& J, double dt, double cmd) {
+// lead vehicle and the running minimum of the clearance (gap + x_lead) - x
+struct Ld64 {
+  double xl, vl, gmin;
+};
+
+template <int FORM, int K, bool LEAD>
+__device__ inline void block64(St64& s, Ld64& l, const Job& J, double al, double dt, double cmd) {
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     const double q = s.v * s.v;
@@ -203,141 +249,257 @@ __device__ inline void block64(St64& s, const Job& J, double dt, double cmd) {
     }
     s.x = fma(dt, s.v, s.x);
     s.v = fma(dt, acc, s.v);
+    if (LEAD) {
+      l.xl = fma(dt, l.vl, l.xl);
+      l.vl = fmax(fma(-dt, al, l.vl), 0.0);
+      l.gmin = fmin(l.gmin, (J.gap + l.xl) - s.x);
+    }
   }
 }
 
-__device__ inline void step64(St64& s, const Job& J, double dt, double cmd) {
+template <bool LEAD>
+__device__ inline void step64(St64& s, Ld64& l, const Job& J, double al, double dt, double cmd) {
   const double q = s.v * s.v;
   const double acc = fma(J.nkd, q, fmax(s.a, J.alim)) - J.c;
   s.a = fma(J.kt, cmd - s.a, s.a);
   s.x = fma(dt, s.v, s.x);
   s.v = fma(dt, acc, s.v);
+  if (LEAD) {
+    l.xl = fma(dt, l.vl, l.xl);
+    l.vl = fmax(fma(-dt, al, l.vl), 0.0);
+  }
 }
 
-template <int OBS, int K>
-__global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
-                                                   const uint32_t* __restrict__ perm, int64_t n,
-                                                   double dt, double a_cmd, int nd, int nmax,
-                                                   int impact_exit, OutCols out) {
-  const int64_t pos = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  const bool valid = pos < n;
-  const uint32_t idx = valid ? perm[pos] : 0u;
-  Job J;
-  if (valid) {
-    J = jobs[idx];
+// A block of B steps may run unchecked when it does not straddle the command
+// switch and ends before the horizon step (the horizon test fires at k+1 == nmax).
+template <int B>
+__device__ inline bool block_fits(int k, int nd, int nmax) {
+  return !(k < nd && k + B > nd) && (k + B < nmax);
+}
+
+// Scenario constants a lane works with: uniform kernel arguments for one
+// scenario, the scenario table in a batch.
+struct Ctx {
+  double dt, a_cmd;
+  int nd, nmax, impact_exit;
+  OutCols out;
+  const ScnDev* tab;
+};
+
+struct LaneScn {
+  double dt, a_cmd;
+  int nd, nmax;
+  OutCols out;
+  int64_t local;
+};
+
+template <bool BATCH>
+__device__ inline LaneScn lane_scn(const Ctx& c, const Job& J, uint32_t g) {
+  LaneScn r;
+  if (BATCH) {
+    const ScnDev& t = c.tab[J.scn];
+    r.dt = t.dt;
+    r.a_cmd = t.a_cmd;
+    r.nd = t.nd;
+    r.nmax = t.nmax;
+    r.out = t.out;
+    r.local = static_cast<int64_t>(g) - t.off;
   } else {
-    J = Job{1.0, 0.0, 0.0, -1.0, 0.5, 1e30, 1.0, 0.0};
+    r.dt = c.dt;
+    r.a_cmd = c.a_cmd;
+    r.nd = c.nd;
+    r.nmax = c.nmax;
+    r.out = c.out;
+    r.local = g;
   }
-  // never limited: a >= a_cmd - (rounding) > alim, so max(a, alim) = a
-  const bool lane_free = J.alim < a_cmd - 1e-6;
-  // limited for good once a <= alim: a never climbs above max(a, a_cmd) < alim
-  const bool lane_limited = J.alim > a_cmd + 1e-9;
-  const double thr = static_cast<double>(K) * dt * J.dmax;   // v above this cannot reach 0 in K steps
-  St64 s{0.0, J.v0, 0.0};
-  bool active = valid, collided = false, pend = false, clamped = false;
-  St64 sv{0.0, 0.0, 0.0};
-  int sk = 0;
-  int end = 0, steps = 0;
-  double dist = 0.0;
-  float vimp = 0.0f;
-  int k = 0;
-  // every lane has ended by step nmax (the horizon test fires at k + 1 == nmax)
-  while (k < nmax) {
-    if (!__any(active)) break;
-    const bool near = active && (s.v <= thr);
-    const bool straddle = (k < nd) && (k + K > nd);
-    const bool horizon = k + K >= nmax;  // a block never ends on the last step
-    if (!straddle && !horizon && !__any(near)) {
-      const double cmd = k >= nd ? a_cmd : 0.0;
-      // keep the start state of a block in which the lane may pass the obstacle
-      if (OBS == AEB_OBS_STATIONARY && !collided) {
-        sv = s;
-        sk = k;
-      }
-      if (k + K <= nd) {
-        block64<FORM_D, K>(s, J, dt, cmd);
-      } else if (__all(!active || clamped)) {
-        block64<FORM_C, K>(s, J, dt, cmd);
-      } else if (__all(!active || lane_free)) {
-        block64<FORM_F, K>(s, J, dt, cmd);
-      } else {
-        block64<FORM_G, K>(s, J, dt, cmd);
-        clamped = clamped || (lane_limited && s.a <= J.alim);
-      }
-      k += K;
-      if (OBS == AEB_OBS_STATIONARY && active && !collided && s.x > J.gap) {
-        collided = true;
-        pend = true;
-        if (impact_exit) active = false;
-      }
+  return r;
+}
+
+// claim the next 64 sorted positions for this wavefront
+__device__ inline int64_t claim(unsigned long long* counter) {
+  unsigned long long base = 0;
+  if ((threadIdx.x & 63) == 0) base = atomicAdd(counter, 64ull);
+  const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(base));
+  const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(base >> 32));
+  return static_cast<int64_t>((static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
+// Lane state and per-lane flags of the FP64 integration.
+struct Lane64 {
+  St64 s, sv;  // state, and start state of the block where the obstacle was passed
+  Ld64 l, lv;  // lead vehicle, and its state at that block start
+  int sk;      // step index at that block start
+  bool active, collided, pend, clamped, free_lane, limited;
+};
+
+template <int OBS, int B>
+__device__ inline void run_block64(Lane64& L, const Job& J, double al, const LaneScn& c, int k,
+                                   int impact_exit) {
+  constexpr bool LEAD = OBS == AEB_OBS_LEAD;
+  const double cmd = k >= c.nd ? c.a_cmd : 0.0;
+  if (OBS != AEB_OBS_NONE && !L.collided) {
+    L.sv = L.s;
+    L.lv = L.l;
+    L.sk = k;
+  }
+  if (__all(!L.active || k + B <= c.nd)) {
+    block64<FORM_D, B, LEAD>(L.s, L.l, J, al, c.dt, cmd);
+  } else if (__all(!L.active || L.clamped)) {
+    block64<FORM_C, B, LEAD>(L.s, L.l, J, al, c.dt, cmd);
+  } else if (__all(!L.active || L.free_lane)) {
+    block64<FORM_F, B, LEAD>(L.s, L.l, J, al, c.dt, cmd);
+  } else {
+    block64<FORM_G, B, LEAD>(L.s, L.l, J, al, c.dt, cmd);
+    L.clamped = L.clamped || (L.limited && k + B > c.nd && L.s.a <= J.alim);
+  }
+  if (OBS == AEB_OBS_STATIONARY && L.active && !L.collided && L.s.x > J.gap) {
+    L.collided = true;
+    L.pend = true;
+    if (impact_exit) L.active = false;
+  }
+  if (LEAD && L.active && L.l.gmin < 0.0) {  // the lead was reached inside the block
+    L.collided = true;
+    L.pend = true;
+    L.active = false;
+  }
+}
+
+template <int OBS, int K, bool BATCH>
+__global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
+                                                   const LeadJob* __restrict__ leads,
+                                                   const uint32_t* __restrict__ perm, int64_t n,
+                                                   Ctx ctx, unsigned long long* counter) {
+  constexpr int KS = 4;  // short blocks close to the stop
+  constexpr bool LEAD = OBS == AEB_OBS_LEAD;
+  for (;;) {
+    const int64_t base = claim(counter);
+    if (base >= n) break;
+    const int64_t pos = base + (threadIdx.x & 63);
+    const bool valid = pos < n;
+    const uint32_t g = valid ? perm[pos] : 0u;
+    Job J;
+    if (valid) {
+      J = jobs[g];
     } else {
-      const double cmd = k >= nd ? a_cmd : 0.0;
-      if (active) {
-        step64(s, J, dt, cmd);
-        if (k >= nd) clamped = clamped || (lane_limited && s.a <= J.alim);
-        if (OBS == AEB_OBS_STATIONARY && !collided && s.x > J.gap) {
-          collided = true;
-          vimp = static_cast<float>(s.v);
-          if (impact_exit) {
-            active = false;
+      J = Job{1.0, 0.0, 0.0, -1.0, 0.5, 1e30, 1.0, 0.0f, 0u};
+    }
+    const double al = (LEAD && valid) ? leads[g].decel : 0.0;
+    const LaneScn c = lane_scn<BATCH>(ctx, J, g);
+    // v above these cannot reach 0 within a block (|dv/dt| <= dmax)
+    const double thr_k = static_cast<double>(K) * c.dt * J.dmax;
+    const double thr_s = static_cast<double>(KS) * c.dt * J.dmax;
+    Lane64 L;
+    L.s = St64{0.0, J.v0, 0.0};
+    L.l = Ld64{0.0, LEAD ? J.v0 : 0.0, J.gap};
+    L.sv = L.s;
+    L.lv = L.l;
+    L.sk = 0;
+    L.active = valid;
+    L.collided = L.pend = L.clamped = false;
+    // never limited: a >= a_cmd - (rounding) > alim, so max(a, alim) = a
+    L.free_lane = J.alim < c.a_cmd - 1e-6;
+    // limited for good once a <= alim: a never climbs above max(a, a_cmd) < alim
+    L.limited = J.alim > c.a_cmd + 1e-9;
+    int end = 0, steps = 0;
+    double dist = 0.0, margin = J.gap;
+    float vimp = 0.0f;
+    int k = 0;
+    // every lane has ended by its step nmax (the horizon test fires at k + 1 == nmax)
+    for (;;) {
+      if (!__any(L.active)) break;
+      if (__all(!L.active || (block_fits<K>(k, c.nd, c.nmax) && L.s.v > thr_k))) {
+        run_block64<OBS, K>(L, J, al, c, k, ctx.impact_exit);
+        k += K;
+      } else if (__all(!L.active || (block_fits<KS>(k, c.nd, c.nmax) && L.s.v > thr_s))) {
+        run_block64<OBS, KS>(L, J, al, c, k, ctx.impact_exit);
+        k += KS;
+      } else {
+        const double cmd = k >= c.nd ? c.a_cmd : 0.0;
+        if (L.active) {
+          step64<LEAD>(L.s, L.l, J, al, c.dt, cmd);
+          if (k >= c.nd) L.clamped = L.clamped || (L.limited && L.s.a <= J.alim);
+          bool impact = false;
+          if (LEAD) {
+            const double gk = (J.gap + L.l.xl) - L.s.x;
+            L.l.gmin = fmin(L.l.gmin, gk);
+            impact = gk < 0.0;
+          } else if (OBS == AEB_OBS_STATIONARY) {
+            impact = L.s.x > J.gap;
+          }
+          if (impact && !L.collided) {
+            L.collided = true;
+            vimp = static_cast<float>(L.s.v - L.l.vl);
+          }
+          if (impact && (LEAD || ctx.impact_exit)) {
+            L.active = false;
             end = AEB_END_IMPACT;
             steps = k + 1;
-            dist = s.x;
+            dist = L.s.x;
+          }
+          if (L.active) {
+            if (L.s.v <= 0.0) {
+              L.active = false;
+              end = AEB_END_STOP;
+              steps = k + 1;
+              dist = L.s.x;
+            } else if (k + 1 == c.nmax) {
+              L.active = false;
+              end = AEB_END_HORIZON;
+              steps = k + 1;
+              dist = L.s.x;
+            }
           }
         }
-        if (active) {
-          if (s.v <= 0.0) {
-            active = false;
-            end = AEB_END_STOP;
-            steps = k + 1;
-            dist = s.x;
-          } else if (k + 1 == nmax) {
-            active = false;
-            end = AEB_END_HORIZON;
-            steps = k + 1;
-            dist = s.x;
+        k += 1;
+      }
+    }
+    // replay the block in which each pending lane passed the obstacle
+    if (OBS != AEB_OBS_NONE && __any(L.pend)) {
+      St64 r = L.sv;
+      Ld64 rl = L.lv;
+      int kr = L.sk;
+      // the replay is bit-identical to the block, so the crossing recurs within it
+      for (int it = 0; it <= K; ++it) {
+        if (!__any(L.pend)) break;
+        if (L.pend) {
+          const double cmd = kr >= c.nd ? c.a_cmd : 0.0;
+          step64<LEAD>(r, rl, J, al, c.dt, cmd);
+          ++kr;
+          bool impact;
+          if (LEAD) {
+            const double gk = (J.gap + rl.xl) - r.x;
+            rl.gmin = fmin(rl.gmin, gk);
+            impact = gk < 0.0;
+          } else {
+            impact = r.x > J.gap;
+          }
+          if (impact) {
+            L.pend = false;
+            vimp = static_cast<float>(r.v - rl.vl);
+            if (LEAD || ctx.impact_exit) {
+              end = AEB_END_IMPACT;
+              steps = kr;
+              dist = r.x;
+              L.l.gmin = rl.gmin;
+            }
           }
         }
       }
-      k += 1;
     }
-  }
-  if (active) {  // unreachable: kept so that no lane can leave without a result
-    end = AEB_END_HORIZON;
-    steps = k;
-    dist = s.x;
-  }
-  // replay the block in which each pending lane passed the obstacle
-  if (OBS == AEB_OBS_STATIONARY && __any(pend)) {
-    St64 r = sv;
-    int kr = sk;
-    // the replay is bit-identical to the block, so the crossing recurs within K steps
-    for (int it = 0; it <= K; ++it) {
-      if (!__any(pend)) break;
-      if (pend) {
-        const double cmd = kr >= nd ? a_cmd : 0.0;
-        step64(r, J, dt, cmd);
-        ++kr;
-        if (r.x > J.gap) {
-          pend = false;
-          vimp = static_cast<float>(r.v);
-          if (impact_exit) {
-            end = AEB_END_IMPACT;
-            steps = kr;
-            dist = r.x;
-          }
-        }
+    if (L.pend) vimp = __builtin_nanf("");  // unreachable; makes a broken replay visible
+    if (valid) {
+      if (LEAD) {
+        margin = L.l.gmin;
+      } else {
+        const double mg = J.gap - dist;
+        margin = mg < J.gap ? mg : J.gap;
       }
+      c.out.dist[c.local] = dist;
+      c.out.margin[c.local] = margin;
+      c.out.steps[c.local] = steps;
+      c.out.status[c.local] = static_cast<uint8_t>(end | (L.collided ? AEB_COLLIDED : 0));
+      c.out.vimp[c.local] = L.collided ? vimp : 0.0f;
     }
-  }
-  if (pend) vimp = __builtin_nanf("");  // unreachable; makes a broken replay visible
-  if (valid) {
-    const double mg = J.gap - dist;
-    out.dist[idx] = dist;
-    out.margin[idx] = mg < J.gap ? mg : J.gap;
-    out.steps[idx] = steps;
-    out.status[idx] = static_cast<uint8_t>(end | (collided ? AEB_COLLIDED : 0));
-    out.vimp[idx] = collided ? vimp : 0.0f;
   }
 }
 
@@ -364,16 +526,16 @@ __device__ inline float speed32(const St32& s) {
 }
 
 template <int FORM, int K, bool SPLIT>
-__device__ inline void block32(St32& s, const L32& c) {
+__device__ inline void block32(St32& s, const L32& c, float tk) {
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     const float v = speed32<SPLIT>(s);
     const float q = v * v;
     float m;
     if (FORM == FORM_G)
-      m = fmaxf(s.e + c.tb, c.alc);
+      m = fmaxf(s.e + tk, c.alc);
     else if (FORM == FORM_F)
-      m = s.e + c.tb;
+      m = s.e + tk;
     else if (FORM == FORM_C)
       m = c.alc;
     else
@@ -386,7 +548,15 @@ __device__ inline void block32(St32& s, const L32& c) {
       s.vb = fmaf(c.dt, acc, s.vb);
     if (FORM == FORM_G || FORM == FORM_F) s.e = fmaf(c.nkt, s.e, s.e);
   }
-  if (SPLIT) {
+}
+
+// Every 32 steps (by step index, so the rounding of a lane never depends on
+// how its wavefront grouped the steps) the speed base absorbs its increment
+// and the position's block sum goes into the Kahan pair.
+constexpr int FLUSH = 32;
+
+__device__ inline void flush32(St32& s, bool split) {
+  if (split) {
     const float t = s.vb + s.vi;
     s.vi = s.vi - (t - s.vb);
     s.vb = t;
@@ -410,180 +580,212 @@ __device__ inline void step32(St32& s, const L32& c, bool braking) {
 }
 
 // Without compensation the speed's rounding grows with the step count; a
-// wavefront whose lanes are predicted to run longer than this carries it.
+// lane predicted to run longer than this carries it.
 constexpr double SPLIT_STEPS = 6000.0;
 
+// Speed compensation is a per-lane property (its predicted length), so a
+// lane's arithmetic never depends on its wavefront; a wavefront holding both
+// kinds runs each form under its lane mask.
 template <int FORM, int K>
-__device__ inline void block32_any(St32& s, const L32& c, bool split) {
-  if (split)
-    block32<FORM, K, true>(s, c);
-  else
-    block32<FORM, K, false>(s, c);
+__device__ inline void block32_any(St32& s, const L32& c, float tk, bool split) {
+  if (__all(split)) {
+    block32<FORM, K, true>(s, c, tk);
+  } else if (__all(!split)) {
+    block32<FORM, K, false>(s, c, tk);
+  } else {
+    if (split) block32<FORM, K, true>(s, c, tk);
+    if (!split) block32<FORM, K, false>(s, c, tk);
+  }
 }
 
-template <int OBS, int K>
+struct Lane32 {
+  St32 s, sv;  // state, and start state of the block where the obstacle was passed
+  int sk, sb;  // step index at that block start, and the block's length
+  bool active, crossed, pend, clamped, free_lane;
+};
+
+template <int OBS, int B>
+__device__ inline void run_block32(Lane32& L, const L32& c, bool split, int nd, int k,
+                                   int impact_exit) {
+  if (OBS == AEB_OBS_STATIONARY && !L.crossed) {
+    L.sv = L.s;
+    L.sk = k;
+    L.sb = B;
+  }
+  // blocks never straddle nd: the lane's target is fixed for the block
+  const float tk = k >= nd ? c.tb : c.td;
+  if (__all(!L.active || k + B <= nd)) {
+    block32_any<FORM_D, B>(L.s, c, tk, split);
+  } else if (__all(!L.active || L.clamped)) {
+    block32_any<FORM_C, B>(L.s, c, tk, split);
+  } else if (__all(!L.active || L.free_lane)) {
+    block32_any<FORM_F, B>(L.s, c, tk, split);
+  } else {
+    block32_any<FORM_G, B>(L.s, c, tk, split);
+    L.clamped = L.clamped || (k + B > nd && L.s.e + c.tb <= c.alc);
+  }
+  if ((k + B) % FLUSH == 0) flush32(L.s, split);
+  if (OBS == AEB_OBS_STATIONARY && L.active && !L.crossed &&
+      (L.s.X.hi - L.s.X.lo) + L.s.p > c.gapf) {
+    L.crossed = true;
+    L.pend = true;
+    if (impact_exit) L.active = false;
+  }
+}
+
+template <int OBS, int K, bool BATCH>
 __global__ __launch_bounds__(256) void k_roll_fp32c(const Job* __restrict__ jobs,
                                                     const uint32_t* __restrict__ perm, int64_t n,
-                                                    double dt, double a_cmd, int nd, int nmax,
-                                                    int impact_exit, double band_abs,
-                                                    double band_rel, OutCols out, uint32_t* fix) {
-  const int64_t pos = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  const bool valid = pos < n;
-  const uint32_t idx = valid ? perm[pos] : 0u;
-  Job J;
-  if (valid) {
-    J = jobs[idx];
-  } else {
-    J = Job{1.0, 0.0, 0.0, -1.0, 0.5, 1e30, 1.0, 0.0};
-  }
-  L32 c;  // (the speed read below is base + increment; the increment is 0 without compensation)
-  c.dt = static_cast<float>(dt);
-  c.nkd = static_cast<float>(J.nkd);
-  c.nkt = static_cast<float>(-J.kt);
-  c.alc = static_cast<float>(J.alim - J.c);
-  c.tb = static_cast<float>(a_cmd - J.c);
-  c.td = static_cast<float>(0.0 - J.c);
-  c.tdm = fmaxf(c.td, c.alc);
-  c.ejump = static_cast<float>(-a_cmd);
-  c.thr = static_cast<float>(static_cast<double>(K) * dt * J.dmax);
-  c.gapf = static_cast<float>(J.gap);
-  const double band = band_abs + band_rel * fabs(J.gap);
-  const bool lane_free = J.alim < a_cmd - 1e-6;
-  const bool split = __any(valid && J.pred > SPLIT_STEPS);  // wave-uniform
-  St32 s;
-  s.vb = static_cast<float>(J.v0);
-  s.vi = split ? static_cast<float>(J.v0 - static_cast<double>(s.vb)) : 0.0f;
-  s.e = 0.0f;
-  s.p = 0.0f;
-  bool active = valid, crossed = false, clamped = false, boundary = false, pend = false;
-  St32 sv = s;  // start state of the block in which the lane passed the obstacle
-  int sk = 0;
-  int end = 0, steps = 0;
-  double dist = 0.0;
-  float vimp = 0.0f;
-  int k = 0;
-  while (k < nmax) {
-    if (!__any(active)) break;
-    // the command switches on at step nd: e = a - cmd jumps by -a_cmd.  Blocks
-    // never straddle nd, so every lane passes through k == nd at a loop top.
-    if (k == nd) s.e += c.ejump;
-    const bool near = active && (speed32<true>(s) <= c.thr);
-    const bool straddle = (k < nd) && (k + K > nd);
-    const bool horizon = k + K >= nmax;
-    if (!straddle && !horizon && !__any(near)) {
-      if (OBS == AEB_OBS_STATIONARY && !crossed) {
-        sv = s;
-        sk = k;
-      }
-      if (k + K <= nd) {
-        block32_any<FORM_D, K>(s, c, split);
-      } else if (__all(!active || clamped)) {
-        block32_any<FORM_C, K>(s, c, split);
-      } else if (__all(!active || lane_free)) {
-        block32_any<FORM_F, K>(s, c, split);
-      } else {
-        block32_any<FORM_G, K>(s, c, split);
-        clamped = clamped || (s.e + c.tb <= c.alc);
-      }
-      k += K;
-      if (OBS == AEB_OBS_STATIONARY && active && !crossed && s.X.hi - s.X.lo > c.gapf) {
-        crossed = true;
-        pend = true;
-        if (impact_exit) active = false;
-      }
+                                                    Ctx ctx, double band_abs, double band_rel,
+                                                    uint32_t* fix, unsigned long long* counter) {
+  constexpr int KS = 4;
+  static_assert(K == FLUSH && K % KS == 0, "flush points must fall on block ends");
+  for (;;) {
+    const int64_t base = claim(counter);
+    if (base >= n) break;
+    const int64_t pos = base + (threadIdx.x & 63);
+    const bool valid = pos < n;
+    const uint32_t g = valid ? perm[pos] : 0u;
+    Job J;
+    if (valid) {
+      J = jobs[g];
     } else {
-      if (active) {
-        const float vb = speed32<true>(s);
-        if (split)
-          step32<true>(s, c, k >= nd);
-        else
-          step32<false>(s, c, k >= nd);
-        if (k >= nd) clamped = clamped || (s.e + c.tb <= c.alc);
-        const float v = speed32<true>(s);
-        if (OBS == AEB_OBS_STATIONARY && !crossed && (s.X.hi - s.X.lo) + s.p > c.gapf) {
-          crossed = true;
-          vimp = v;
-          if (impact_exit) {
-            active = false;
-            end = AEB_END_IMPACT;
-            steps = k + 1;
-            dist = s.X.value(s.p);
-            const double step_len = static_cast<double>(c.dt) * static_cast<double>(vb);
-            boundary = (dist - J.gap < band) || (J.gap - (dist - step_len) < band);
+      J = Job{1.0, 0.0, 0.0, -1.0, 0.5, 1e30, 1.0, 0.0f, 0u};
+    }
+    const LaneScn sc = lane_scn<BATCH>(ctx, J, g);
+    const int nd = sc.nd, nmax = sc.nmax;
+    L32 c;  // (the speed read below is base + increment; the increment is 0 without compensation)
+    c.dt = static_cast<float>(sc.dt);
+    c.nkd = static_cast<float>(J.nkd);
+    c.nkt = static_cast<float>(-J.kt);
+    c.alc = static_cast<float>(J.alim - J.c);
+    c.tb = static_cast<float>(sc.a_cmd - J.c);
+    c.td = static_cast<float>(0.0 - J.c);
+    c.tdm = fmaxf(c.td, c.alc);
+    c.ejump = static_cast<float>(-sc.a_cmd);
+    c.thr = static_cast<float>(static_cast<double>(K) * sc.dt * J.dmax);
+    c.gapf = static_cast<float>(J.gap);
+    const float thr_s = static_cast<float>(static_cast<double>(KS) * sc.dt * J.dmax);
+    const double band = band_abs + band_rel * fabs(J.gap);
+    const bool split = J.pred > SPLIT_STEPS;  // per lane
+    Lane32 L;
+    L.s.vb = static_cast<float>(J.v0);
+    L.s.vi = split ? static_cast<float>(J.v0 - static_cast<double>(L.s.vb)) : 0.0f;
+    L.s.e = 0.0f;
+    L.s.p = 0.0f;
+    L.sv = L.s;
+    L.sk = 0;
+    L.sb = K;
+    L.active = valid;
+    L.crossed = L.pend = L.clamped = false;
+    L.free_lane = J.alim < sc.a_cmd - 1e-6;
+    const int impact_exit = ctx.impact_exit;
+    bool boundary = false;
+    int end = 0, steps = 0;
+    double dist = 0.0;
+    float vimp = 0.0f;
+    int k = 0;
+    for (;;) {
+      if (!__any(L.active)) break;
+      // the command switches on at step nd: e = a - cmd jumps by -a_cmd.  Blocks
+      // never straddle nd, so every lane passes through k == nd at a loop top.
+      if (k == nd) L.s.e += c.ejump;
+      const float v_now = speed32<true>(L.s);
+      // blocks start on multiples of their length, so flush points fall on block ends
+      if (k % K == 0 && __all(!L.active || (block_fits<K>(k, nd, nmax) && v_now > c.thr))) {
+        run_block32<OBS, K>(L, c, split, nd, k, impact_exit);
+        k += K;
+      } else if (k % KS == 0 &&
+                 __all(!L.active || (block_fits<KS>(k, nd, nmax) && v_now > thr_s))) {
+        run_block32<OBS, KS>(L, c, split, nd, k, impact_exit);
+        k += KS;
+      } else {
+        if (L.active) {
+          const float vb = v_now;
+          if (split) step32<true>(L.s, c, k >= nd);
+          if (!split) step32<false>(L.s, c, k >= nd);
+          if ((k + 1) % FLUSH == 0) flush32(L.s, split);
+          if (k >= nd) L.clamped = L.clamped || (L.s.e + c.tb <= c.alc);
+          const float v = speed32<true>(L.s);
+          if (OBS == AEB_OBS_STATIONARY && !L.crossed && (L.s.X.hi - L.s.X.lo) + L.s.p > c.gapf) {
+            L.crossed = true;
+            vimp = v;
+            if (impact_exit) {
+              L.active = false;
+              end = AEB_END_IMPACT;
+              steps = k + 1;
+              dist = L.s.X.value(L.s.p);
+              const double step_len = static_cast<double>(c.dt) * static_cast<double>(vb);
+              boundary = (dist - J.gap < band) || (J.gap - (dist - step_len) < band);
+            }
+          }
+          if (L.active) {
+            if (v <= 0.0f) {
+              L.active = false;
+              end = AEB_END_STOP;
+              steps = k + 1;
+              dist = L.s.X.value(L.s.p);
+            } else if (k + 1 == nmax) {
+              L.active = false;
+              end = AEB_END_HORIZON;
+              steps = k + 1;
+              dist = L.s.X.value(L.s.p);
+            }
           }
         }
-        if (active) {
-          if (v <= 0.0f) {
-            active = false;
-            end = AEB_END_STOP;
-            steps = k + 1;
-            dist = s.X.value(s.p);
-          } else if (k + 1 == nmax) {
-            active = false;
-            end = AEB_END_HORIZON;
-            steps = k + 1;
-            dist = s.X.value(s.p);
+        k += 1;
+      }
+    }
+    // replay the block in which each pending lane passed the obstacle, single
+    // steps with the per-step test; the crossing recurs within the block (at its
+    // last step at the latest, where the block-end test fired)
+    if (OBS == AEB_OBS_STATIONARY && __any(L.pend)) {
+      St32 r = L.sv;
+      int kr = L.sk;
+      for (int it = 0; it < K; ++it) {
+        if (!__any(L.pend)) break;
+        if (L.pend) {
+          const float vb = speed32<true>(r);
+          if (split) step32<true>(r, c, kr >= nd);
+          if (!split) step32<false>(r, c, kr >= nd);
+          ++kr;
+          if (kr % FLUSH == 0) flush32(r, split);
+          const float v = speed32<true>(r);
+          if ((r.X.hi - r.X.lo) + r.p > c.gapf || it == L.sb - 1) {
+            L.pend = false;
+            vimp = v;
+            if (impact_exit) {
+              end = AEB_END_IMPACT;
+              steps = kr;
+              dist = r.X.value(r.p);
+              const double step_len = static_cast<double>(c.dt) * static_cast<double>(vb);
+              boundary = (dist - J.gap < band) || (J.gap - (dist - step_len) < band);
+            }
           }
         }
       }
-      k += 1;
     }
-  }
-  if (active) {  // unreachable: kept so that no lane can leave without a result
-    end = AEB_END_HORIZON;
-    steps = k;
-    dist = s.X.value(s.p);
-  }
-  // replay the block in which each pending lane passed the obstacle, single
-  // steps with the per-step test; the crossing recurs within the block (at its
-  // last step at the latest, where the block-end test fired)
-  if (OBS == AEB_OBS_STATIONARY && __any(pend)) {
-    St32 r = sv;
-    int kr = sk;
-    for (int it = 0; it < K; ++it) {
-      if (!__any(pend)) break;
-      if (pend) {
-        const float vb = speed32<true>(r);
-        if (split)
-          step32<true>(r, c, kr >= nd);
-        else
-          step32<false>(r, c, kr >= nd);
-        ++kr;
-        const float v = speed32<true>(r);
-        if ((r.X.hi - r.X.lo) + r.p > c.gapf || it == K - 1) {
-          pend = false;
-          vimp = v;
-          if (impact_exit) {
-            end = AEB_END_IMPACT;
-            steps = kr;
-            dist = r.X.value(r.p);
-            const double step_len = static_cast<double>(c.dt) * static_cast<double>(vb);
-            boundary = (dist - J.gap < band) || (J.gap - (dist - step_len) < band);
-          }
-        }
+    bool collided = L.crossed;
+    if (OBS == AEB_OBS_STATIONARY && !impact_exit) {
+      // the flag is decided in FP64 on the compensated distance
+      collided = dist > J.gap;
+      boundary = fabs(J.gap - dist) < band;
+      if (collided != L.crossed) vimp = 0.0f;
+    } else if (OBS == AEB_OBS_STATIONARY && !L.crossed) {
+      boundary = J.gap - dist < band;
+    }
+    if (valid) {
+      const double mg = J.gap - dist;
+      sc.out.dist[sc.local] = dist;
+      sc.out.margin[sc.local] = mg < J.gap ? mg : J.gap;
+      sc.out.steps[sc.local] = steps;
+      sc.out.status[sc.local] = static_cast<uint8_t>(end | (collided ? AEB_COLLIDED : 0) |
+                                                     (boundary ? AEB_BOUNDARY : 0));
+      sc.out.vimp[sc.local] = collided ? vimp : 0.0f;
+      if (boundary && fix) {
+        const uint32_t slot = atomicAdd(fix, 1u);
+        fix[1 + slot] = g;
       }
-    }
-  }
-  bool collided = crossed;
-  if (OBS == AEB_OBS_STATIONARY && !impact_exit) {
-    // the flag is decided in FP64 on the compensated distance
-    collided = dist > J.gap;
-    boundary = fabs(J.gap - dist) < band;
-    if (collided != crossed) vimp = 0.0f;
-  } else if (OBS == AEB_OBS_STATIONARY && !crossed) {
-    boundary = J.gap - dist < band;
-  }
-  if (valid) {
-    const double mg = J.gap - dist;
-    out.dist[idx] = dist;
-    out.margin[idx] = mg < J.gap ? mg : J.gap;
-    out.steps[idx] = steps;
-    out.status[idx] = static_cast<uint8_t>(end | (collided ? AEB_COLLIDED : 0) |
-                                           (boundary ? AEB_BOUNDARY : 0));
-    out.vimp[idx] = collided ? vimp : 0.0f;
-    if (boundary && fix) {
-      const uint32_t slot = atomicAdd(fix, 1u);
-      fix[1 + slot] = idx;
     }
   }
 }
@@ -591,78 +793,206 @@ __global__ __launch_bounds__(256) void k_roll_fp32c(const Job* __restrict__ jobs
 }  // namespace
 
 bool fast_path_applies(const aeb_scenario& s, int precision) {
-  if (s.integrator != AEB_EULER || s.obstacle == AEB_OBS_LEAD) return false;
+  if (s.integrator != AEB_EULER) return false;
   if (precision == AEB_FP64) return !s.nofma;
-  return precision == AEB_FP32C || precision == AEB_FP32C_FIXUP;
+  return (precision == AEB_FP32C || precision == AEB_FP32C_FIXUP) && s.obstacle != AEB_OBS_LEAD;
 }
 
-int launch_rollout_fast(const aeb_scenario& s, const ParamSrc* src, int precision,
-                        const OutCols& out, int64_t n, hipStream_t st) {
-  (void)precision;
-  const int64_t nd = dead_steps(s), nmax = horizon_steps(s);
-  if (nmax > 0x7fffffff || nd > 0x7fffffff)
-    return fail(AEB_EINVAL, "step counts beyond 2^31");
-  // scratch: jobs | keys | perm | histogram
+namespace {
+
+constexpr int KBLOCK = 32;
+
+// persistent grid: as many workgroups as fit on the device at once
+template <typename Kern>
+unsigned persistent_grid(Kern kern, int64_t n) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 4;
+  const int64_t need = (n + 255) / 256;
+  const int64_t grid = static_cast<int64_t>(cus) * per_cu;
+  return static_cast<unsigned>(need < grid ? need : grid);
+}
+
+struct Bufs {
+  Job* jobs;
+  LeadJob* leads;
+  uint32_t* keys;
+  uint32_t* perm;
+  uint32_t* hist;
+  unsigned long long* counter;
+  ScnDev* tab;
+  aeb_scenario* scns;
+};
+
+// scratch: jobs | leads | keys | perm | histogram | counter | scenario tables
+int scratch_bufs(int64_t n, int n_scn, bool lead, hipStream_t st, Bufs& b) {
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
   const size_t off_jobs = 0;
-  const size_t off_keys = (off_jobs + sizeof(Job) * n + 255) & ~size_t(255);
-  const size_t off_perm = (off_keys + sizeof(uint32_t) * n + 255) & ~size_t(255);
-  const size_t off_hist = (off_perm + sizeof(uint32_t) * n + 255) & ~size_t(255);
-  const size_t total = off_hist + sizeof(uint32_t) * NBINS;
+  const size_t off_leads = up(off_jobs + sizeof(Job) * n);
+  const size_t off_keys = up(off_leads + (lead ? sizeof(LeadJob) * n : 0));
+  const size_t off_perm = up(off_keys + sizeof(uint32_t) * n);
+  const size_t off_hist = up(off_perm + sizeof(uint32_t) * n);
+  const size_t off_cnt = up(off_hist + sizeof(uint32_t) * NBINS);
+  const size_t off_tab = up(off_cnt + sizeof(unsigned long long));
+  const size_t off_scn = up(off_tab + sizeof(ScnDev) * n_scn);
+  const size_t total = off_scn + sizeof(aeb_scenario) * n_scn;
   char* base = static_cast<char*>(scratch(total, st));
   if (!base) return AEB_ENOMEM;
-  Job* jobs = reinterpret_cast<Job*>(base + off_jobs);
-  uint32_t* keys = reinterpret_cast<uint32_t*>(base + off_keys);
-  uint32_t* perm = reinterpret_cast<uint32_t*>(base + off_perm);
-  uint32_t* hist = reinterpret_cast<uint32_t*>(base + off_hist);
-  const unsigned nblk = static_cast<unsigned>((n + 255) / 256);
-  const unsigned pblk = static_cast<unsigned>((n + PREP_BLOCK * PREP_PER - 1) / (PREP_BLOCK * PREP_PER));
-  hipLaunchKernelGGL(k_zero, dim3(NBINS / 256), dim3(256), 0, st, hist, int64_t(NBINS));
-  ParamSrc p = src ? *src : ParamSrc{};
-  if (src)
-    hipLaunchKernelGGL(k_prep<false>, dim3(pblk), dim3(PREP_BLOCK), 0, st, s, p, n, nd, nmax, jobs,
-                       keys, hist);
-  else
-    hipLaunchKernelGGL(k_prep<true>, dim3(pblk), dim3(PREP_BLOCK), 0, st, s, p, n, nd, nmax, jobs,
-                       keys, hist);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, hist);
-  hipLaunchKernelGGL(k_scatter, dim3(pblk), dim3(PREP_BLOCK), 0, st, keys, n, hist, perm);
-  constexpr int K = 32;
-  const int ind = static_cast<int>(nd), inmax = static_cast<int>(nmax);
-  if (precision != AEB_FP64) {
-    uint32_t* fix = nullptr;
-    if (precision == AEB_FP32C_FIXUP) {
-      fix = static_cast<uint32_t*>(scratch_fix(sizeof(uint32_t) * (n + 1), st));
-      if (!fix) return AEB_ENOMEM;
-      hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, fix, int64_t(1));
-    }
-    // FP32 errors stay below ~1e-4 m; outcomes within 1 mm (+1e-5 of the gap)
-    // of the boundary are flagged (and, in the fix-up mode, recomputed in FP64)
-    const double band_abs = 1e-3, band_rel = 1e-5;
+  b.jobs = reinterpret_cast<Job*>(base + off_jobs);
+  b.leads = lead ? reinterpret_cast<LeadJob*>(base + off_leads) : nullptr;
+  b.keys = reinterpret_cast<uint32_t*>(base + off_keys);
+  b.perm = reinterpret_cast<uint32_t*>(base + off_perm);
+  b.hist = reinterpret_cast<uint32_t*>(base + off_hist);
+  b.counter = reinterpret_cast<unsigned long long*>(base + off_cnt);
+  b.tab = reinterpret_cast<ScnDev*>(base + off_tab);
+  b.scns = reinterpret_cast<aeb_scenario*>(base + off_scn);
+  return AEB_OK;
+}
+
+// sort the prepared keys into the permutation; zero the claim counter
+void sort_keys(const Bufs& b, int64_t n, hipStream_t st) {
+  const unsigned pblk = static_cast<unsigned>((n + PREP_SAMPLES - 1) / PREP_SAMPLES);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, b.hist);
+  hipLaunchKernelGGL(k_scatter, dim3(pblk), dim3(PREP_BLOCK), 0, st, b.keys, n, b.hist, b.perm);
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(b.counter),
+                     int64_t(2));
+}
+
+template <bool BATCH>
+int integrate(const aeb_scenario& s0, int precision, const Bufs& b, int64_t n, const Ctx& ctx,
+              const ParamSrc* src, hipStream_t st) {
+  const int obs = s0.obstacle;
+  if (precision == AEB_FP64) {
     timing_begin(st);
-    if (s.obstacle == AEB_OBS_STATIONARY)
-      hipLaunchKernelGGL((k_roll_fp32c<AEB_OBS_STATIONARY, K>), dim3(nblk), dim3(256), 0, st, jobs,
-                         perm, n, s.dt, s.a_cmd, ind, inmax, s.impact_exit, band_abs, band_rel, out,
-                         fix);
-    else
-      hipLaunchKernelGGL((k_roll_fp32c<AEB_OBS_NONE, K>), dim3(nblk), dim3(256), 0, st, jobs, perm,
-                         n, s.dt, s.a_cmd, ind, inmax, s.impact_exit, band_abs, band_rel, out, fix);
-    timing_end(st);
-    if (fix) {
-      int rc = launch_fixup(s, src, out, fix, st);
-      if (rc != AEB_OK) return rc;
+    if (obs == AEB_OBS_STATIONARY) {
+      auto kern = k_roll_fp64<AEB_OBS_STATIONARY, KBLOCK, BATCH>;
+      hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, n)), dim3(256), 0, st, b.jobs, b.leads,
+                         b.perm, n, ctx, b.counter);
+    } else if (obs == AEB_OBS_LEAD) {
+      auto kern = k_roll_fp64<AEB_OBS_LEAD, KBLOCK, BATCH>;
+      hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, n)), dim3(256), 0, st, b.jobs, b.leads,
+                         b.perm, n, ctx, b.counter);
+    } else {
+      auto kern = k_roll_fp64<AEB_OBS_NONE, KBLOCK, BATCH>;
+      hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, n)), dim3(256), 0, st, b.jobs, b.leads,
+                         b.perm, n, ctx, b.counter);
     }
+    timing_end(st);
     AEB_HIP(hipGetLastError());
     return AEB_OK;
   }
+  uint32_t* fix = nullptr;
+  if (precision == AEB_FP32C_FIXUP) {
+    if (BATCH) return fail(AEB_EINVAL, "the FP64 fix-up mode is not available for batches");
+    fix = static_cast<uint32_t*>(scratch_fix(sizeof(uint32_t) * (n + 1), st));
+    if (!fix) return AEB_ENOMEM;
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, fix, int64_t(1));
+  }
+  // FP32 errors stay below ~1e-4 m; outcomes within 1 mm (+1e-5 of the gap)
+  // of the boundary are flagged (and, in the fix-up mode, recomputed in FP64)
+  const double band_abs = 1e-3, band_rel = 1e-5;
   timing_begin(st);
-  if (s.obstacle == AEB_OBS_STATIONARY)
-    hipLaunchKernelGGL((k_roll_fp64<AEB_OBS_STATIONARY, K>), dim3(nblk), dim3(256), 0, st, jobs,
-                       perm, n, s.dt, s.a_cmd, ind, inmax, s.impact_exit, out);
-  else
-    hipLaunchKernelGGL((k_roll_fp64<AEB_OBS_NONE, K>), dim3(nblk), dim3(256), 0, st, jobs, perm, n,
-                       s.dt, s.a_cmd, ind, inmax, s.impact_exit, out);
+  if (obs == AEB_OBS_STATIONARY) {
+    auto kern = k_roll_fp32c<AEB_OBS_STATIONARY, KBLOCK, BATCH>;
+    hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, n)), dim3(256), 0, st, b.jobs, b.perm, n,
+                       ctx, band_abs, band_rel, fix, b.counter);
+  } else {
+    auto kern = k_roll_fp32c<AEB_OBS_NONE, KBLOCK, BATCH>;
+    hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, n)), dim3(256), 0, st, b.jobs, b.perm, n,
+                       ctx, band_abs, band_rel, fix, b.counter);
+  }
   timing_end(st);
   AEB_HIP(hipGetLastError());
+  if (fix) return launch_fixup(s0, src, ctx.out, fix, st);
+  return AEB_OK;
+}
+
+}  // namespace
+
+int launch_rollout_fast(const aeb_scenario& s, const ParamSrc* src, int precision,
+                        const OutCols& out, int64_t n, hipStream_t st) {
+  const int64_t nd = dead_steps(s), nmax = horizon_steps(s);
+  if (nmax > 0x7fffffff || nd > 0x7fffffff) return fail(AEB_EINVAL, "step counts beyond 2^31");
+  const bool lead = s.obstacle == AEB_OBS_LEAD;
+  Bufs b;
+  if (scratch_bufs(n, 0, lead, st, b) != AEB_OK) return AEB_ENOMEM;
+  const unsigned pblk = static_cast<unsigned>((n + PREP_SAMPLES - 1) / PREP_SAMPLES);
+  hipLaunchKernelGGL(k_zero, dim3(NBINS / 256), dim3(256), 0, st, b.hist, int64_t(NBINS));
+  PrepArgs pa{};
+  pa.s = s;
+  pa.src = src ? *src : ParamSrc{};
+  pa.n = n;
+  pa.nd = static_cast<int>(nd);
+  pa.nmax = static_cast<int>(nmax);
+  pa.cap = static_cast<float>(nmax);
+  if (src)
+    hipLaunchKernelGGL((k_prep<false, false>), dim3(pblk), dim3(PREP_BLOCK), 0, st, pa, b.jobs,
+                       b.leads, b.keys, b.hist);
+  else
+    hipLaunchKernelGGL((k_prep<true, false>), dim3(pblk), dim3(PREP_BLOCK / 2), 0, st, pa, b.jobs,
+                       b.leads, b.keys, b.hist);
+  sort_keys(b, n, st);
+  Ctx ctx{};
+  ctx.dt = s.dt;
+  ctx.a_cmd = s.a_cmd;
+  ctx.nd = static_cast<int>(nd);
+  ctx.nmax = static_cast<int>(nmax);
+  ctx.impact_exit = s.impact_exit;
+  ctx.out = out;
+  ctx.tab = nullptr;
+  return integrate<false>(s, precision, b, n, ctx, src, st);
+}
+
+int launch_batch_fast(const aeb_scenario* scns, int n_scn, int precision, const OutCols* outs,
+                      hipStream_t st) {
+  int64_t total = 0, cap = 1;
+  std::vector<ScnDev> tab(n_scn);
+  for (int j = 0; j < n_scn; ++j) {
+    const int64_t nd = dead_steps(scns[j]), nmax = horizon_steps(scns[j]);
+    if (nmax > 0x7fffffff || nd > 0x7fffffff) return fail(AEB_EINVAL, "step counts beyond 2^31");
+    tab[j].dt = scns[j].dt;
+    tab[j].a_cmd = scns[j].a_cmd;
+    tab[j].nd = static_cast<int>(nd);
+    tab[j].nmax = static_cast<int>(nmax);
+    tab[j].off = total;
+    tab[j].out = outs[j];
+    total += scns[j].n_samples;
+    if (nmax > cap) cap = nmax;
+  }
+  if (total > 0xffffffffLL) return fail(AEB_EINVAL, "a batch holds at most 2^32 - 1 samples");
+  const bool lead = scns[0].obstacle == AEB_OBS_LEAD;
+  Bufs b;
+  if (scratch_bufs(total, n_scn, lead, st, b) != AEB_OK) return AEB_ENOMEM;
+  // the tables travel with the stream; the host copies stay alive until the
+  // stream has consumed them
+  AEB_HIP(hipMemcpyAsync(b.tab, tab.data(), sizeof(ScnDev) * n_scn, hipMemcpyHostToDevice, st));
+  AEB_HIP(hipMemcpyAsync(b.scns, scns, sizeof(aeb_scenario) * n_scn, hipMemcpyHostToDevice, st));
+  const unsigned pblk = static_cast<unsigned>((total + PREP_SAMPLES - 1) / PREP_SAMPLES);
+  hipLaunchKernelGGL(k_zero, dim3(NBINS / 256), dim3(256), 0, st, b.hist, int64_t(NBINS));
+  PrepArgs pa{};
+  pa.n = total;
+  pa.cap = static_cast<float>(cap);
+  pa.scns = b.scns;
+  pa.tab = b.tab;
+  pa.n_scn = n_scn;
+  hipLaunchKernelGGL((k_prep<true, true>), dim3(pblk), dim3(PREP_BLOCK / 2), 0, st, pa, b.jobs,
+                     b.leads, b.keys, b.hist);
+  sort_keys(b, total, st);
+  Ctx ctx{};
+  ctx.impact_exit = scns[0].impact_exit;
+  ctx.tab = b.tab;
+  int rc = integrate<true>(scns[0], precision, b, total, ctx, nullptr, st);
+  if (rc != AEB_OK) return rc;
+  // keep the host tables valid until the copies have run
+  AEB_HIP(hipStreamSynchronize(st));
   return AEB_OK;
 }
 

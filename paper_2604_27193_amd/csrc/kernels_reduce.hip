@@ -317,10 +317,19 @@ __global__ __launch_bounds__(RB) void k_pass2(OutCols o, long long n, long long 
   for (int j = threadIdx.x; j < 2 * (NVB + 1); j += RB) out[j] = h[j];
 }
 
-// Block 0: the sd.  Block 1 + t: sum the block histograms of target t's array
-// bin by bin, then find the bin holding its rank.
+// bin totals of the block-private histograms: one thread per bin, adjacent
+// threads read adjacent bins of each block's histogram
+__global__ __launch_bounds__(256) void k_bin_totals(const unsigned* bhist, int nb, unsigned* btot) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= 2 * (NVB + 1)) return;
+  unsigned c = 0;
+  for (int b = 0; b < nb; ++b) c += bhist[static_cast<size_t>(b) * 2 * (NVB + 1) + j];
+  btot[j] = c;
+}
+
+// Block 0: the sd.  Block 1 + t: find the value bin holding target t's rank.
 __global__ __launch_bounds__(FB) void k_fin2(const double* part, int nb, aeb_stats* st, Sel* sel,
-                                             SelIn in, const unsigned* bhist) {
+                                             SelIn in, const unsigned* btot) {
   __shared__ double shd[FB];
   __shared__ unsigned long long shu[FB];
   if (blockIdx.x == 0) {
@@ -333,15 +342,7 @@ __global__ __launch_bounds__(FB) void k_fin2(const double* part, int nb, aeb_sta
   }
   const int t = blockIdx.x - 1;
   if (t >= in.count) return;
-  __shared__ unsigned tot[NVB + 1];
-  const int off = in.kind[t] ? (NVB + 1) : 0;
-  // bin totals over the blocks (adjacent threads read adjacent bins)
-  for (int j = threadIdx.x; j <= NVB; j += FB) {
-    unsigned c = 0;
-    for (int b = 0; b < nb; ++b) c += bhist[static_cast<size_t>(b) * 2 * (NVB + 1) + off + j];
-    tot[j] = c;
-  }
-  __syncthreads();
+  const unsigned* tot = btot + (in.kind[t] ? (NVB + 1) : 0);
   constexpr int PER = (NVB + 1 + FB - 1) / FB;
   unsigned cnt[PER];
   unsigned long long loc = 0;
@@ -510,7 +511,9 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 int launch_reduce(const OutCols& out, int64_t n, const aeb_reduce_req& req, aeb_stats* host_out,
                   hipStream_t st) {
-  const long long chunk = n <= 65536 ? 1024 : 4096;
+  // element passes take 1,024-element slices (enough blocks to fill the chip);
+  // the histogram pass 4,096 (fewer block histograms to merge)
+  const long long chunk = 1024;
   const int nb = static_cast<int>((n + chunk - 1) / chunk);
   const int ng = req.n_grid;
   const int T = req.n_risk + req.n_margin_q;
@@ -521,8 +524,11 @@ int launch_reduce(const OutCols& out, int64_t n, const aeb_reduce_req& req, aeb_
   const size_t off_zero_end = align256(off_sel + sizeof(Sel));
   const size_t off_part = off_zero_end;
   const size_t off_var = align256(off_part + sizeof(Partial) * nb);
-  const size_t off_bh = align256(off_var + sizeof(double) * nb);
-  const size_t off_cand = align256(off_bh + sizeof(unsigned) * 2 * (NVB + 1) * nb);
+  const long long chunk2 = chunk * 4;
+  const int nb2 = static_cast<int>((n + chunk2 - 1) / chunk2);
+  const size_t off_bh = align256(off_var + sizeof(double) * (nb > nb2 ? nb : nb2));
+  const size_t off_bt = align256(off_bh + sizeof(unsigned) * 2 * (NVB + 1) * nb2);
+  const size_t off_cand = align256(off_bt + sizeof(unsigned) * 2 * (NVB + 1));
   const size_t off_ss = align256(off_cand + sizeof(unsigned long long) * MAX_T * CAP);
   const size_t off_sh = align256(off_ss + sizeof(SelState));
   const size_t total = align256(off_sh + sizeof(unsigned) * MAX_T * 256);
@@ -534,6 +540,7 @@ int launch_reduce(const OutCols& out, int64_t n, const aeb_reduce_req& req, aeb_
   Partial* part = reinterpret_cast<Partial*>(base + off_part);
   double* vpart = reinterpret_cast<double*>(base + off_var);
   unsigned* bhist = reinterpret_cast<unsigned*>(base + off_bh);
+  unsigned* btot = reinterpret_cast<unsigned*>(base + off_bt);
   unsigned long long* cand = reinterpret_cast<unsigned long long*>(base + off_cand);
   SelState* ss = reinterpret_cast<SelState*>(base + off_ss);
   unsigned* shist = reinterpret_cast<unsigned*>(base + off_sh);
@@ -565,9 +572,12 @@ int launch_reduce(const OutCols& out, int64_t n, const aeb_reduce_req& req, aeb_
                      req.grid_lo, gstep, ng, rhist, part);
   hipLaunchKernelGGL(k_fin1, dim3(1), dim3(FB), 0, st, part, nb, static_cast<long long>(n), ng,
                      rhist, dstats, sel);
-  hipLaunchKernelGGL(k_pass2, dim3(nb), dim3(RB), 0, st, out, static_cast<long long>(n), chunk,
+  hipLaunchKernelGGL(k_pass2, dim3(nb2), dim3(RB), 0, st, out, static_cast<long long>(n), chunk2,
                      dstats, sel, need_d ? 1 : 0, need_m ? 1 : 0, bhist, vpart);
-  hipLaunchKernelGGL(k_fin2, dim3(1 + T), dim3(FB), 0, st, vpart, nb, dstats, sel, in, bhist);
+  if (T > 0)
+    hipLaunchKernelGGL(k_bin_totals, dim3((2 * (NVB + 1) + 255) / 256), dim3(256), 0, st, bhist, nb2,
+                       btot);
+  hipLaunchKernelGGL(k_fin2, dim3(1 + T), dim3(FB), 0, st, vpart, nb2, dstats, sel, in, btot);
   if (T > 0) {
     hipLaunchKernelGGL(k_collect, dim3(nb), dim3(RB), 0, st, out, static_cast<long long>(n), chunk,
                        sel, in, cand);

@@ -166,6 +166,19 @@ int launch_fixup(const aeb_scenario& s, const ParamSrc* src, const OutCols& out,
   return AEB_OK;
 }
 
+// Batches the block-structured path cannot take (RK4, the unfused Euler form,
+// FP32 with a lead vehicle) run scenario by scenario.
+int launch_batch(const aeb_scenario* scns, int n_scn, int precision, const OutCols* outs,
+                 hipStream_t st) {
+  if (fast_path_applies(scns[0], precision) && precision != AEB_FP32C_FIXUP)
+    return launch_batch_fast(scns, n_scn, precision, outs, st);
+  for (int j = 0; j < n_scn; ++j) {
+    const int rc = launch_rollout(scns[j], nullptr, precision, outs[j], scns[j].n_samples, st);
+    if (rc != AEB_OK) return rc;
+  }
+  return AEB_OK;
+}
+
 int launch_rollout(const aeb_scenario& s, const ParamSrc* src, int precision, const OutCols& out,
                    int64_t n, hipStream_t st) {
   const int64_t nd = dead_steps(s), nmax = horizon_steps(s);

@@ -1,0 +1,92 @@
+"""GPU parity of the batched rollout: many scenarios of uneven sizes, steps,
+horizons and obstacles in one launch, each scenario against the FP64
+reference, and each equal to the same scenario rolled out alone."""
+import numpy as np
+import pytest
+
+from paper_2604_27193_amd import workloads as W
+from test_gpu_parity import check_fp32c, check_fp64, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2604_27193_amd import binding
+    binding.lib()
+    return binding
+
+
+def test_batch_lead_sweep_fp64(B, orc):
+    scns = W.sweep(n=800)[::21]
+    outs = B.batch_rollout(scns)
+    for d, o in zip(scns, outs):
+        check_fp64(to_np(o), orc.run(d))
+
+
+def test_batch_uneven_fp64(B, orc):
+    scns = W.uneven_batch(24, max_samples=1200)
+    assert len({d["dt"] for d in scns}) == 3
+    outs = B.batch_rollout(scns)
+    for d, o in zip(scns, outs):
+        check_fp64(to_np(o), orc.run(d))
+
+
+def test_batch_uneven_fp32c(B, orc):
+    scns = W.uneven_batch(24, max_samples=1200)
+    outs = B.batch_rollout(scns, precision="fp32c")
+    for d, o in zip(scns, outs):
+        check_fp32c(to_np(o), orc.run(d))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_batch_equals_alone(B, prec):
+    scns = W.uneven_batch(10, max_samples=3000) + [W.single(2000, seed=5, scenario_id=77)]
+    outs = B.batch_rollout(scns, precision=prec)
+    for d, o in zip(scns, outs):
+        alone = to_np(B.rollout(d, precision=prec))
+        got = to_np(o)
+        for k in alone:
+            assert np.array_equal(got[k], alone[k]), (prec, k)
+
+
+def test_batch_tiny_and_ragged(B, orc):
+    base = W.single(1)
+    scns = [dict(base, n_samples=n, scenario_id=j) for j, n in enumerate([1, 2, 63, 65, 129, 1])]
+    outs = B.batch_rollout(scns)
+    for d, o in zip(scns, outs):
+        check_fp64(to_np(o), orc.run(d))
+
+
+def test_batch_reduce_matches_reference(B, orc):
+    scns = W.uneven_batch(5, max_samples=2500)
+    outs = B.batch_rollout(scns)
+    risk, mq, grid = (0.5, 0.05, 0.01), (0.0, 0.5), (20.0, 120.0, 101)
+    stats = B.batch_reduce(outs, risk=risk, margin_q=mq, grid=grid)
+    for d, st in zip(scns, stats):
+        ref = orc.reduce(orc.run(d), risk=risk, margin_q=mq, grid=grid)
+        assert st["n_collide"] == ref["n_collide"] and st["p_collision"] == ref["p_collision"]
+        assert st["headway"] == ref["headway"] and st["margin_q"] == ref["margin_q"]
+        assert np.array_equal(st["risk_count"], ref["risk_count"])
+        assert abs(st["mean_dist"] - ref["mean_dist"]) <= 1e-12 * ref["mean_dist"]
+
+
+def test_batch_fallback_paths(B, orc):
+    # RK4 and FP32 with a lead vehicle run scenario by scenario
+    rk = [W.paper_preset(700, seed=s, scenario_id=s) for s in (1, 2, 3)]
+    for d, o in zip(rk, B.batch_rollout(rk)):
+        check_fp64(to_np(o), orc.run(d))
+    lead = W.sweep(n=600)[40:43]
+    for d, o in zip(lead, B.batch_rollout(lead, precision="fp32c")):
+        check_fp32c(to_np(o), orc.run(d))
+
+
+def test_batch_rejects_bad_batches(B):
+    with pytest.raises(B.AebError):
+        B.batch_rollout([W.single(10), W.single(10, obstacle="none")])
+    with pytest.raises(B.AebError):
+        B.batch_rollout([W.single(10)], precision="fp32c_fixup")
+    with pytest.raises(B.AebError):
+        B.batch_rollout([W.single(10), dict(W.single(10), dt=-1.0)])
