@@ -80,6 +80,56 @@ def cpu_baseline(d, budget_samples):
                       f"{el:.2f} s wall"}
 
 
+def serving_leg(B, W, precision, rates, duration, arena_gib=4):
+    """Poisson request streams (sizes 25k/100k/1M at 70/25/5 %, 530 ms deadline)
+    paced in real time into one server; latency = completion - arrival on the
+    server's clock."""
+    import numpy as np
+    res = {}
+    with B.Server(int(arena_gib * (1 << 30)), precision=precision, max_slots=256, n_streams=3,
+                  tick_us=200, max_tick_samples=1 << 22, risk=RISK, margin_q=MARGIN_Q,
+                  grid=GRID) as srv:
+        # warm the kernels once
+        srv.wait(srv.submit(W.single(25_000, seed=1, scenario_id=1)))
+        for rate in rates:
+            stream = W.serving_stream(rate, duration=duration)
+            pending, done = {}, []
+            t0 = time.perf_counter()
+            k = 0
+            while k < len(stream) or pending:
+                now = time.perf_counter() - t0
+                while k < len(stream) and stream[k][0] <= now:
+                    _, d, dl = stream[k]
+                    pending[srv.submit(d, deadline=dl)] = int(d["n_samples"])
+                    k += 1
+                for t in list(pending):
+                    r = srv.poll(t)
+                    if r is not None:
+                        done.append((pending.pop(t), r[1]))
+                if k < len(stream):
+                    time.sleep(max(0.0, min(2e-4, stream[k][0] - (time.perf_counter() - t0))))
+                else:
+                    time.sleep(1e-4)
+            wall = time.perf_counter() - t0
+            lat = np.array([tm["done"] - tm["arrive"] for _, tm in done])
+            lat25 = np.array([tm["done"] - tm["arrive"] for n, tm in done if n == 25_000])
+            samples = sum(n for n, _ in done)
+            res[str(rate)] = {
+                "requests": len(done), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                "p50_25k_ms": float(np.percentile(lat25, 50) * 1e3) if lat25.size else None,
+                "p99_25k_ms": float(np.percentile(lat25, 99) * 1e3) if lat25.size else None,
+                "max_ms": float(lat.max() * 1e3),
+                "deadline_miss_rate": float(np.mean([tm["missed"] for _, tm in done])),
+                "rollouts_per_s": samples / wall,
+            }
+            log(f"bench: serving {precision} {rate} req/s: {res[str(rate)]}")
+        info = srv.info()
+    res["ticks"] = info["ticks"]
+    res["arena_peak_bytes"] = info["arena_peak"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +138,8 @@ def main():
     ap.add_argument("--n", type=int, default=1_048_576)
     ap.add_argument("--cpu-samples", type=int, default=262_144)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="length of each serving stream (0: no serving leg)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic for scaling hardware byte counters)")
@@ -150,6 +202,13 @@ def main():
     achieved = flops64 / kavg64 / 1e12
     value = args.steps * n / wall64
 
+    serving = None
+    if args.serve_seconds > 0:
+        log("bench: serving streams")
+        serving = {"precision": "fp32c", "deadline_ms": 530.0,
+                   "duration_s": args.serve_seconds,
+                   "rates": serving_leg(B, W, "fp32c", (50, 200, 800), args.serve_seconds)}
+
     cpu = None
     if not args.no_cpu:
         log("bench: cpu baseline (oracle)")
@@ -199,6 +258,7 @@ def main():
             "collision_flags_equal_fp64_outside_band": flags_equal,
             "speedup_vs_fp64_kernel": kavg64 / kavg32,
         },
+        "serving": serving,
         "plain_method_host": {"sampling_s": t_sample, "h2d_s": t_h2d,
                               "h2d_GBps": 11 * 8 * n / t_h2d / 1e9},
         "stats": {"p_collision": st64["p_collision"], "mean_dist": st64["mean_dist"],

@@ -245,6 +245,99 @@ int aeb_timing_last(float* ms);
 int aeb_reduce(const aeb_outputs* out, const aeb_reduce_req* req, aeb_stats* host_out,
                void* stream);
 
+/* ---- serving: continuous batching of evaluation requests ----
+ *
+ * Sec. VI bounds one Monte Carlo evaluation by 530 ms (700 ms of braking
+ * budget minus perception and decision time).  A server takes requests (one
+ * scenario each, parameters drawn in-kernel from its seed and id) as they
+ * arrive, admits them in arrival order while their device footprint fits the
+ * free part of a caller-provided arena and a slot is free, packs admitted
+ * requests of one kind (integrator, obstacle, impact_exit, nofma) into one
+ * sorted multi-scenario launch followed by one reduction per request, and
+ * rotates launches over its streams so that work overlaps on the device.  A
+ * request's statistics equal those of aeb_rollout (params == NULL) plus
+ * aeb_reduce on the same scenario alone, bit for bit.  A worker thread of
+ * the server drives admission, launches and completion; all entry points
+ * are thread-safe. */
+typedef struct aeb_server aeb_server;
+
+/* Server configuration.
+ *   arena, arena_bytes: device memory of the current device, owned by the
+ *     caller (e.g. a torch tensor) and untouched by anyone else until
+ *     aeb_server_destroy returns; the server carves its per-stream launch
+ *     scratch (aeb_server_fixed_bytes) from the front and request
+ *     footprints from the rest.
+ *   max_slots: requests admitted or running at once (1..1024).
+ *   precision: AEB_FP64 or AEB_FP32C.
+ *   n_streams: launch streams (1..8), created by the server at the default
+ *     priority; one launch in flight per stream.
+ *   tick_us: while a launch is in flight, admitted requests wait up to this
+ *     long (0..1e6 us) for others to share their launch.
+ *   max_queue: waiting requests beyond which submit returns AEB_EAGAIN.
+ *   max_tick_samples: samples per launch (1..2^31-1); also the largest
+ *     request.
+ *   req: the statistics computed for every request (as for aeb_reduce). */
+typedef struct {
+  void* arena;
+  uint64_t arena_bytes;
+  int32_t max_slots;
+  int32_t precision;
+  int32_t n_streams;
+  int32_t tick_us;
+  int32_t max_queue;
+  int32_t reserved;
+  int64_t max_tick_samples;
+  aeb_reduce_req req;
+} aeb_server_cfg;
+
+/* Timestamps of one request, in seconds on the server's steady clock since
+ * its creation: arrival (submit), admission, launch, and completion as seen
+ * by the worker; missed = done - arrive exceeded the request's deadline. */
+typedef struct {
+  double arrive, admit, start, done;
+  int32_t missed, reserved;
+} aeb_req_timing;
+
+/* Counters of a server: requests submitted, completed (including failed),
+ * failed, past their deadline; launches; requests now queued, admitted,
+ * running; arena bytes held by requests now and at most. */
+typedef struct {
+  uint64_t submitted, completed, failed, missed, ticks;
+  uint64_t queued, admitted, running;
+  uint64_t arena_in_use, arena_peak, arena_request_bytes, fixed_bytes;
+} aeb_server_info;
+
+/* Arena bytes a server with this configuration keeps for its streams (the
+ * rest holds request footprints), and the footprint of one request of
+ * n_samples samples. */
+int aeb_server_fixed_bytes(const aeb_server_cfg* cfg, uint64_t* bytes);
+int aeb_serve_footprint(const aeb_server_cfg* cfg, int64_t n_samples, uint64_t* bytes);
+
+/* Create a server on the current device (AEB_EINVAL for a bad
+ * configuration, AEB_ENOMEM if the arena cannot hold the fixed part plus one
+ * request of max_tick_samples samples). */
+int aeb_server_create(const aeb_server_cfg* cfg, aeb_server** out);
+
+/* Finish all accepted requests, stop the worker, release the streams and
+ * pinned staging; results not polled yet are dropped.  NULL is accepted. */
+int aeb_server_destroy(aeb_server* srv);
+
+/* Queue one evaluation (non-blocking).  AEB_EINVAL: invalid scenario or one
+ * the batched path cannot run (RK4, nofma, FP32C with a lead vehicle);
+ * AEB_ENOMEM: its footprint exceeds the request part of the arena or its
+ * sample count max_tick_samples; AEB_EAGAIN: the queue is full.  deadline_s:
+ * latency budget used for miss accounting (e.g. 0.530). */
+int aeb_serve_submit(aeb_server* srv, const aeb_scenario* scn, double deadline_s,
+                     uint64_t* ticket);
+
+/* Collect a request: AEB_OK with *out (and *timing, if not NULL) filled once
+ * it is done, after which the ticket is forgotten; AEB_EAGAIN while pending;
+ * AEB_ENOTFOUND for an unknown or already collected ticket; the request's
+ * own error if its execution failed. */
+int aeb_serve_poll(aeb_server* srv, uint64_t ticket, aeb_stats* out, aeb_req_timing* timing);
+
+int aeb_server_info_get(aeb_server* srv, aeb_server_info* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,7 +28,9 @@ END_STOP, END_IMPACT, END_HORIZON, COLLIDED, BOUNDARY = 1, 2, 3, 4, 8
 
 EXPORTS = ("aeb_last_error", "aeb_version", "aeb_validate", "aeb_uniforms", "aeb_sample_params",
            "aeb_rollout", "aeb_reduce", "aeb_batch_rollout", "aeb_batch_reduce",
-           "aeb_timing_enable", "aeb_timing_last")
+           "aeb_timing_enable", "aeb_timing_last", "aeb_server_fixed_bytes",
+           "aeb_serve_footprint", "aeb_server_create", "aeb_server_destroy", "aeb_serve_submit",
+           "aeb_serve_poll", "aeb_server_info_get")
 
 
 class AebError(RuntimeError):
@@ -80,6 +82,24 @@ class Stats(C.Structure):
 _lib = None
 
 
+class ServerCfg(C.Structure):
+    _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_uint64), ("max_slots", C.c_int32),
+                ("precision", C.c_int32), ("n_streams", C.c_int32), ("tick_us", C.c_int32),
+                ("max_queue", C.c_int32), ("reserved", C.c_int32),
+                ("max_tick_samples", C.c_int64), ("req", ReduceReq)]
+
+
+class ReqTiming(C.Structure):
+    _fields_ = [("arrive", C.c_double), ("admit", C.c_double), ("start", C.c_double),
+                ("done", C.c_double), ("missed", C.c_int32), ("reserved", C.c_int32)]
+
+
+class ServerInfo(C.Structure):
+    _fields_ = [(f, C.c_uint64) for f in (
+        "submitted", "completed", "failed", "missed", "ticks", "queued", "admitted", "running",
+        "arena_in_use", "arena_peak", "arena_request_bytes", "fixed_bytes")]
+
+
 def lib():
     """Load the built library (build it with __graft_entry__.build())."""
     global _lib
@@ -100,6 +120,13 @@ def lib():
         L.aeb_batch_reduce.argtypes = [P(Outputs), C.c_int, P(ReduceReq), P(Stats), C.c_void_p]
         L.aeb_timing_enable.argtypes = [C.c_int]
         L.aeb_timing_last.argtypes = [P(C.c_float)]
+        L.aeb_server_fixed_bytes.argtypes = [P(ServerCfg), P(C.c_uint64)]
+        L.aeb_serve_footprint.argtypes = [P(ServerCfg), C.c_int64, P(C.c_uint64)]
+        L.aeb_server_create.argtypes = [P(ServerCfg), P(C.c_void_p)]
+        L.aeb_server_destroy.argtypes = [C.c_void_p]
+        L.aeb_serve_submit.argtypes = [C.c_void_p, P(Scenario), C.c_double, P(C.c_uint64)]
+        L.aeb_serve_poll.argtypes = [C.c_void_p, C.c_uint64, P(Stats), P(ReqTiming)]
+        L.aeb_server_info_get.argtypes = [C.c_void_p, P(ServerInfo)]
         _lib = L
     return _lib
 
@@ -299,3 +326,102 @@ def batch_reduce(outs, risk=(), margin_q=(), grid=None, stream=None):
     st = (Stats * k)()
     _check(lib().aeb_batch_reduce(oarr, k, C.byref(req), st, _stream(stream)))
     return [stats_dict(st[j], req.n_risk, req.n_margin_q, req.n_grid) for j in range(k)]
+
+
+class Server:
+    """Continuous-batching evaluation server on the current device.  The arena
+    is a torch uint8 tensor owned by this object (device memory handed to the
+    library, which never frees it)."""
+
+    def __init__(self, arena_bytes, precision="fp64", max_slots=256, n_streams=2, tick_us=200,
+                 max_queue=4096, max_tick_samples=1 << 22, risk=(), margin_q=(), grid=None):
+        torch = _torch()
+        self.cfg = ServerCfg()
+        self.cfg.max_slots = max_slots
+        self.cfg.precision = PRECISIONS[precision]
+        self.cfg.n_streams = n_streams
+        self.cfg.tick_us = tick_us
+        self.cfg.max_queue = max_queue
+        self.cfg.max_tick_samples = max_tick_samples
+        self.cfg.req = reduce_request(risk, margin_q, grid)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda")
+        self.cfg.arena = self.arena.data_ptr()
+        self.cfg.arena_bytes = int(arena_bytes)
+        torch.cuda.synchronize()
+        h = C.c_void_p()
+        _check(lib().aeb_server_create(C.byref(self.cfg), C.byref(h)))
+        self.h = h
+
+    @staticmethod
+    def fixed_bytes(precision="fp64", max_slots=256, n_streams=2, max_tick_samples=1 << 22,
+                    risk=(), margin_q=(), grid=None):
+        cfg = ServerCfg(max_slots=max_slots, precision=PRECISIONS[precision],
+                        n_streams=n_streams, tick_us=0, max_queue=1,
+                        max_tick_samples=max_tick_samples,
+                        req=reduce_request(risk, margin_q, grid))
+        b = C.c_uint64()
+        _check(lib().aeb_server_fixed_bytes(C.byref(cfg), C.byref(b)))
+        return b.value
+
+    def footprint(self, n_samples):
+        b = C.c_uint64()
+        _check(lib().aeb_serve_footprint(C.byref(self.cfg), int(n_samples), C.byref(b)))
+        return b.value
+
+    def submit(self, d, deadline=0.530):
+        """Queue one scenario; returns its ticket (raises AebError on refusal)."""
+        t = C.c_uint64()
+        _check(lib().aeb_serve_submit(self.h, C.byref(scenario(d)), float(deadline),
+                                      C.byref(t)))
+        return t.value
+
+    def try_submit(self, d, deadline=0.530):
+        """(return code, ticket) without raising."""
+        t = C.c_uint64()
+        rc = lib().aeb_serve_submit(self.h, C.byref(scenario(d)), float(deadline), C.byref(t))
+        return rc, t.value
+
+    def poll(self, ticket):
+        """None while pending; else (stats dict, timing dict).  Raises on errors."""
+        st, tm = Stats(), ReqTiming()
+        rc = lib().aeb_serve_poll(self.h, int(ticket), C.byref(st), C.byref(tm))
+        if rc == EAGAIN:
+            return None
+        _check(rc)
+        req = self.cfg.req
+        timing = {"arrive": tm.arrive, "admit": tm.admit, "start": tm.start, "done": tm.done,
+                  "missed": bool(tm.missed)}
+        return stats_dict(st, req.n_risk, req.n_margin_q, req.n_grid), timing
+
+    def wait(self, ticket, timeout=60.0, sleep=1e-4):
+        import time
+        t_end = time.monotonic() + timeout
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if time.monotonic() > t_end:
+                raise TimeoutError(f"ticket {ticket} still pending after {timeout} s")
+            time.sleep(sleep)
+
+    def info(self):
+        inf = ServerInfo()
+        _check(lib().aeb_server_info_get(self.h, C.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in ServerInfo._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(lib().aeb_server_destroy(self.h))
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -183,6 +183,26 @@ static bool outputs_complete(const aeb_outputs* o) {
 
 using namespace aeb;
 
+namespace aeb {
+
+int check_reduce_req(const aeb_reduce_req& req) {
+  if (req.n_risk < 0 || req.n_risk > AEB_MAX_RISK || req.n_margin_q < 0 ||
+      req.n_margin_q > AEB_MAX_MARGIN_Q || req.n_grid < 0 || req.n_grid > AEB_MAX_GRID ||
+      req.n_grid == 1)
+    return fail(AEB_EINVAL, "aeb_reduce: request sizes out of range");
+  for (int j = 0; j < req.n_risk; ++j)
+    if (!(req.risk[j] >= 0.0 && req.risk[j] < 1.0)) return fail(AEB_EINVAL, "risk level outside [0,1)");
+  for (int j = 0; j < req.n_margin_q; ++j)
+    if (!(req.margin_q[j] >= 0.0 && req.margin_q[j] < 1.0))
+      return fail(AEB_EINVAL, "margin quantile outside [0,1)");
+  if (req.n_grid >= 2 && !(req.grid_lo < req.grid_hi && std::isfinite(req.grid_lo) &&
+                            std::isfinite(req.grid_hi)))
+    return fail(AEB_EINVAL, "headway grid needs finite grid_lo < grid_hi");
+  return AEB_OK;
+}
+
+}  // namespace aeb
+
 extern "C" {
 
 const char* aeb_last_error(void) { return g_err.c_str(); }
@@ -325,18 +345,8 @@ int aeb_batch_reduce(const aeb_outputs* outs, int n_scn, const aeb_reduce_req* r
 int aeb_reduce(const aeb_outputs* out, const aeb_reduce_req* req, aeb_stats* host_out, void* stream) {
   if (!outputs_complete(out) || !req || !host_out) return fail(AEB_EINVAL, "aeb_reduce: null argument");
   if (out->n < 1 || out->n > 0x7fffffffLL) return fail(AEB_EINVAL, "aeb_reduce: n out of [1, 2^31-1]");
-  if (req->n_risk < 0 || req->n_risk > AEB_MAX_RISK || req->n_margin_q < 0 ||
-      req->n_margin_q > AEB_MAX_MARGIN_Q || req->n_grid < 0 || req->n_grid > AEB_MAX_GRID ||
-      req->n_grid == 1)
-    return fail(AEB_EINVAL, "aeb_reduce: request sizes out of range");
-  for (int j = 0; j < req->n_risk; ++j)
-    if (!(req->risk[j] >= 0.0 && req->risk[j] < 1.0)) return fail(AEB_EINVAL, "risk level outside [0,1)");
-  for (int j = 0; j < req->n_margin_q; ++j)
-    if (!(req->margin_q[j] >= 0.0 && req->margin_q[j] < 1.0))
-      return fail(AEB_EINVAL, "margin quantile outside [0,1)");
-  if (req->n_grid >= 2 && !(req->grid_lo < req->grid_hi && std::isfinite(req->grid_lo) &&
-                            std::isfinite(req->grid_hi)))
-    return fail(AEB_EINVAL, "headway grid needs finite grid_lo < grid_hi");
+  const int rc = check_reduce_req(*req);
+  if (rc != AEB_OK) return rc;
   OutCols oc{out->dist, out->status, out->steps, out->margin, out->v_impact};
   return launch_reduce(oc, out->n, *req, host_out, static_cast<hipStream_t>(stream));
 }

@@ -70,4 +70,16 @@ int launch_fixup(const aeb_scenario& s, const ParamSrc* src, const OutCols& out,
 int launch_reduce(const OutCols& out, int64_t n, const aeb_reduce_req& req, aeb_stats* host_out,
                   hipStream_t stream);
 
+// The reduction in two parts on caller-provided scratch (reduce_scratch_bytes):
+// reduce_enqueue queues the kernels and the copy of the statistics into
+// host_out (pinned memory keeps it asynchronous); once the stream has run
+// them, a non-zero host_out->reserved asks for reduce_fallback (synchronous),
+// which recomputes the order statistics by radix select.
+size_t reduce_scratch_bytes(int64_t n, const aeb_reduce_req& req);
+int reduce_enqueue(const OutCols& out, int64_t n, const aeb_reduce_req& req, void* scratch_base,
+                   aeb_stats* host_out, hipStream_t stream);
+int reduce_fallback(const OutCols& out, int64_t n, const aeb_reduce_req& req, void* scratch_base,
+                    aeb_stats* host_out, hipStream_t stream);
+int check_reduce_req(const aeb_reduce_req& req);
+
 }  // namespace aeb

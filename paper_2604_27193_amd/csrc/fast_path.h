@@ -44,4 +44,15 @@ int launch_rollout_fast(const aeb_scenario& s, const ParamSrc* src, int precisio
 int launch_batch_fast(const aeb_scenario* scns, int n_scn, int precision, const OutCols* outs,
                       hipStream_t st);
 
+// The same launch on caller-provided device scratch (batch_scratch_bytes) with
+// the scenario table already filled (fill_batch_table).  `scns` and `tab` are
+// copied to the device asynchronously: they must stay valid until the stream
+// has run the copies (pinned host memory lets the caller keep going).
+size_t batch_scratch_bytes(int64_t total, int n_scn, bool lead);
+int fill_batch_table(const aeb_scenario* scns, int n_scn, const OutCols* outs, ScnDev* tab,
+                     int64_t* total, int64_t* cap);
+int launch_batch_fast_into(const aeb_scenario* scns, int n_scn, int precision,
+                           const ScnDev* tab, int64_t total, int64_t cap, void* scratch_base,
+                           hipStream_t st);
+
 }  // namespace aeb

@@ -270,13 +270,6 @@ __device__ inline void step64(St64& s, Ld64& l, const Job& J, double al, double 
   }
 }
 
-// A block of B steps may run unchecked when it does not straddle the command
-// switch and ends before the horizon step (the horizon test fires at k+1 == nmax).
-template <int B>
-__device__ inline bool block_fits(int k, int nd, int nmax) {
-  return !(k < nd && k + B > nd) && (k + B < nmax);
-}
-
 // Scenario constants a lane works with: uniform kernel arguments for one
 // scenario, the scenario table in a batch.
 struct Ctx {
@@ -289,12 +282,10 @@ struct Ctx {
 struct LaneScn {
   double dt, a_cmd;
   int nd, nmax;
-  OutCols out;
-  int64_t local;
 };
 
 template <bool BATCH>
-__device__ inline LaneScn lane_scn(const Ctx& c, const Job& J, uint32_t g) {
+__device__ inline LaneScn lane_scn(const Ctx& c, const Job& J) {
   LaneScn r;
   if (BATCH) {
     const ScnDev& t = c.tab[J.scn];
@@ -302,17 +293,47 @@ __device__ inline LaneScn lane_scn(const Ctx& c, const Job& J, uint32_t g) {
     r.a_cmd = t.a_cmd;
     r.nd = t.nd;
     r.nmax = t.nmax;
-    r.out = t.out;
-    r.local = static_cast<int64_t>(g) - t.off;
   } else {
     r.dt = c.dt;
     r.a_cmd = c.a_cmd;
     r.nd = c.nd;
     r.nmax = c.nmax;
-    r.out = c.out;
-    r.local = g;
   }
   return r;
+}
+
+// Output columns and the sample's index in them (read only at the store, so
+// that the pointers are not held through the integration).
+template <bool BATCH>
+__device__ inline OutCols lane_out(const Ctx& c, const Job& J, uint32_t g, int64_t& local) {
+  if (BATCH) {
+    const ScnDev& t = c.tab[J.scn];
+    local = static_cast<int64_t>(g) - t.off;
+    return t.out;
+  }
+  local = g;
+  return c.out;
+}
+
+// Largest step index a block may end on without a per-step test: a block
+// never straddles the command switch nd and ends before the last step
+// nmax - 1 (the horizon test fires after that step).  The launch-wide
+// limit of a wavefront is the minimum over its active lanes; it only grows
+// as k passes a lane's nd or lanes finish, so it is refreshed once k reaches it.
+__device__ inline int lane_lim(int k, int nd, int nmax) {
+  return k < nd ? min(nd, nmax - 1) : nmax - 1;
+}
+
+__device__ inline int wave_min(int x) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) x = min(x, __shfl_xor(x, o));
+  return __builtin_amdgcn_readfirstlane(x);
+}
+
+template <bool BATCH>
+__device__ inline int wave_lim(bool active, int k, int nd, int nmax) {
+  if (!BATCH) return lane_lim(k, nd, nmax);  // nd, nmax are uniform
+  return wave_min(active ? lane_lim(k, nd, nmax) : INT_MAX);
 }
 
 // claim the next 64 sorted positions for this wavefront
@@ -332,17 +353,19 @@ struct Lane64 {
   bool active, collided, pend, clamped, free_lane, limited;
 };
 
+// wnd: the smallest nd of the wavefront's lanes (the whole block is dead time
+// for every lane when k + B <= wnd)
 template <int OBS, int B>
 __device__ inline void run_block64(Lane64& L, const Job& J, double al, const LaneScn& c, int k,
-                                   int impact_exit) {
+                                   int wnd, int impact_exit) {
   constexpr bool LEAD = OBS == AEB_OBS_LEAD;
   const double cmd = k >= c.nd ? c.a_cmd : 0.0;
   if (OBS != AEB_OBS_NONE && !L.collided) {
     L.sv = L.s;
-    L.lv = L.l;
+    if (LEAD) L.lv = L.l;
     L.sk = k;
   }
-  if (__all(!L.active || k + B <= c.nd)) {
+  if (k + B <= wnd) {
     block64<FORM_D, B, LEAD>(L.s, L.l, J, al, c.dt, cmd);
   } else if (__all(!L.active || L.clamped)) {
     block64<FORM_C, B, LEAD>(L.s, L.l, J, al, c.dt, cmd);
@@ -384,7 +407,8 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
       J = Job{1.0, 0.0, 0.0, -1.0, 0.5, 1e30, 1.0, 0.0f, 0u};
     }
     const double al = (LEAD && valid) ? leads[g].decel : 0.0;
-    const LaneScn c = lane_scn<BATCH>(ctx, J, g);
+    const LaneScn c = lane_scn<BATCH>(ctx, J);
+    const int wnd = BATCH ? wave_min(valid ? c.nd : INT_MAX) : c.nd;
     // v above these cannot reach 0 within a block (|dv/dt| <= dmax)
     const double thr_k = static_cast<double>(K) * c.dt * J.dmax;
     const double thr_s = static_cast<double>(KS) * c.dt * J.dmax;
@@ -403,15 +427,16 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
     int end = 0, steps = 0;
     double dist = 0.0, margin = J.gap;
     float vimp = 0.0f;
-    int k = 0;
+    int k = 0, wl = -1;
     // every lane has ended by its step nmax (the horizon test fires at k + 1 == nmax)
     for (;;) {
       if (!__any(L.active)) break;
-      if (__all(!L.active || (block_fits<K>(k, c.nd, c.nmax) && L.s.v > thr_k))) {
-        run_block64<OBS, K>(L, J, al, c, k, ctx.impact_exit);
+      if (!BATCH || k >= wl) wl = wave_lim<BATCH>(L.active, k, c.nd, c.nmax);
+      if (k + K <= wl && !__any(L.active && L.s.v <= thr_k)) {
+        run_block64<OBS, K>(L, J, al, c, k, wnd, ctx.impact_exit);
         k += K;
-      } else if (__all(!L.active || (block_fits<KS>(k, c.nd, c.nmax) && L.s.v > thr_s))) {
-        run_block64<OBS, KS>(L, J, al, c, k, ctx.impact_exit);
+      } else if (k + KS <= wl && !__any(L.active && L.s.v <= thr_s)) {
+        run_block64<OBS, KS>(L, J, al, c, k, wnd, ctx.impact_exit);
         k += KS;
       } else {
         const double cmd = k >= c.nd ? c.a_cmd : 0.0;
@@ -428,7 +453,7 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
           }
           if (impact && !L.collided) {
             L.collided = true;
-            vimp = static_cast<float>(L.s.v - L.l.vl);
+            vimp = static_cast<float>(LEAD ? L.s.v - L.l.vl : L.s.v);
           }
           if (impact && (LEAD || ctx.impact_exit)) {
             L.active = false;
@@ -475,7 +500,7 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
           }
           if (impact) {
             L.pend = false;
-            vimp = static_cast<float>(r.v - rl.vl);
+            vimp = static_cast<float>(LEAD ? r.v - rl.vl : r.v);
             if (LEAD || ctx.impact_exit) {
               end = AEB_END_IMPACT;
               steps = kr;
@@ -494,11 +519,13 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
         const double mg = J.gap - dist;
         margin = mg < J.gap ? mg : J.gap;
       }
-      c.out.dist[c.local] = dist;
-      c.out.margin[c.local] = margin;
-      c.out.steps[c.local] = steps;
-      c.out.status[c.local] = static_cast<uint8_t>(end | (L.collided ? AEB_COLLIDED : 0));
-      c.out.vimp[c.local] = L.collided ? vimp : 0.0f;
+      int64_t i;
+      const OutCols o = lane_out<BATCH>(ctx, J, g, i);
+      o.dist[i] = dist;
+      o.margin[i] = margin;
+      o.steps[i] = steps;
+      o.status[i] = static_cast<uint8_t>(end | (L.collided ? AEB_COLLIDED : 0));
+      o.vimp[i] = L.collided ? vimp : 0.0f;
     }
   }
 }
@@ -605,7 +632,7 @@ struct Lane32 {
 };
 
 template <int OBS, int B>
-__device__ inline void run_block32(Lane32& L, const L32& c, bool split, int nd, int k,
+__device__ inline void run_block32(Lane32& L, const L32& c, bool split, int nd, int k, int wnd,
                                    int impact_exit) {
   if (OBS == AEB_OBS_STATIONARY && !L.crossed) {
     L.sv = L.s;
@@ -614,7 +641,7 @@ __device__ inline void run_block32(Lane32& L, const L32& c, bool split, int nd, 
   }
   // blocks never straddle nd: the lane's target is fixed for the block
   const float tk = k >= nd ? c.tb : c.td;
-  if (__all(!L.active || k + B <= nd)) {
+  if (k + B <= wnd) {
     block32_any<FORM_D, B>(L.s, c, tk, split);
   } else if (__all(!L.active || L.clamped)) {
     block32_any<FORM_C, B>(L.s, c, tk, split);
@@ -652,8 +679,9 @@ __global__ __launch_bounds__(256) void k_roll_fp32c(const Job* __restrict__ jobs
     } else {
       J = Job{1.0, 0.0, 0.0, -1.0, 0.5, 1e30, 1.0, 0.0f, 0u};
     }
-    const LaneScn sc = lane_scn<BATCH>(ctx, J, g);
+    const LaneScn sc = lane_scn<BATCH>(ctx, J);
     const int nd = sc.nd, nmax = sc.nmax;
+    const int wnd = BATCH ? wave_min(valid ? nd : INT_MAX) : nd;
     L32 c;  // (the speed read below is base + increment; the increment is 0 without compensation)
     c.dt = static_cast<float>(sc.dt);
     c.nkd = static_cast<float>(J.nkd);
@@ -684,20 +712,20 @@ __global__ __launch_bounds__(256) void k_roll_fp32c(const Job* __restrict__ jobs
     int end = 0, steps = 0;
     double dist = 0.0;
     float vimp = 0.0f;
-    int k = 0;
+    int k = 0, wl = -1;
     for (;;) {
       if (!__any(L.active)) break;
+      if (!BATCH || k >= wl) wl = wave_lim<BATCH>(L.active, k, nd, nmax);
       // the command switches on at step nd: e = a - cmd jumps by -a_cmd.  Blocks
       // never straddle nd, so every lane passes through k == nd at a loop top.
       if (k == nd) L.s.e += c.ejump;
       const float v_now = speed32<true>(L.s);
       // blocks start on multiples of their length, so flush points fall on block ends
-      if (k % K == 0 && __all(!L.active || (block_fits<K>(k, nd, nmax) && v_now > c.thr))) {
-        run_block32<OBS, K>(L, c, split, nd, k, impact_exit);
+      if (k % K == 0 && k + K <= wl && !__any(L.active && v_now <= c.thr)) {
+        run_block32<OBS, K>(L, c, split, nd, k, wnd, impact_exit);
         k += K;
-      } else if (k % KS == 0 &&
-                 __all(!L.active || (block_fits<KS>(k, nd, nmax) && v_now > thr_s))) {
-        run_block32<OBS, KS>(L, c, split, nd, k, impact_exit);
+      } else if (k % KS == 0 && k + KS <= wl && !__any(L.active && v_now <= thr_s)) {
+        run_block32<OBS, KS>(L, c, split, nd, k, wnd, impact_exit);
         k += KS;
       } else {
         if (L.active) {
@@ -776,12 +804,14 @@ __global__ __launch_bounds__(256) void k_roll_fp32c(const Job* __restrict__ jobs
     }
     if (valid) {
       const double mg = J.gap - dist;
-      sc.out.dist[sc.local] = dist;
-      sc.out.margin[sc.local] = mg < J.gap ? mg : J.gap;
-      sc.out.steps[sc.local] = steps;
-      sc.out.status[sc.local] = static_cast<uint8_t>(end | (collided ? AEB_COLLIDED : 0) |
-                                                     (boundary ? AEB_BOUNDARY : 0));
-      sc.out.vimp[sc.local] = collided ? vimp : 0.0f;
+      int64_t i;
+      const OutCols o = lane_out<BATCH>(ctx, J, g, i);
+      o.dist[i] = dist;
+      o.margin[i] = mg < J.gap ? mg : J.gap;
+      o.steps[i] = steps;
+      o.status[i] = static_cast<uint8_t>(end | (collided ? AEB_COLLIDED : 0) |
+                                         (boundary ? AEB_BOUNDARY : 0));
+      o.vimp[i] = collided ? vimp : 0.0f;
       if (boundary && fix) {
         const uint32_t slot = atomicAdd(fix, 1u);
         fix[1 + slot] = g;
@@ -833,7 +863,7 @@ struct Bufs {
 };
 
 // scratch: jobs | leads | keys | perm | histogram | counter | scenario tables
-int scratch_bufs(int64_t n, int n_scn, bool lead, hipStream_t st, Bufs& b) {
+size_t bufs_layout(int64_t n, int n_scn, bool lead, char* base, Bufs* b) {
   auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
   const size_t off_jobs = 0;
   const size_t off_leads = up(off_jobs + sizeof(Job) * n);
@@ -843,17 +873,24 @@ int scratch_bufs(int64_t n, int n_scn, bool lead, hipStream_t st, Bufs& b) {
   const size_t off_cnt = up(off_hist + sizeof(uint32_t) * NBINS);
   const size_t off_tab = up(off_cnt + sizeof(unsigned long long));
   const size_t off_scn = up(off_tab + sizeof(ScnDev) * n_scn);
-  const size_t total = off_scn + sizeof(aeb_scenario) * n_scn;
-  char* base = static_cast<char*>(scratch(total, st));
+  const size_t total = up(off_scn + sizeof(aeb_scenario) * n_scn);
+  if (b) {
+    b->jobs = reinterpret_cast<Job*>(base + off_jobs);
+    b->leads = lead ? reinterpret_cast<LeadJob*>(base + off_leads) : nullptr;
+    b->keys = reinterpret_cast<uint32_t*>(base + off_keys);
+    b->perm = reinterpret_cast<uint32_t*>(base + off_perm);
+    b->hist = reinterpret_cast<uint32_t*>(base + off_hist);
+    b->counter = reinterpret_cast<unsigned long long*>(base + off_cnt);
+    b->tab = reinterpret_cast<ScnDev*>(base + off_tab);
+    b->scns = reinterpret_cast<aeb_scenario*>(base + off_scn);
+  }
+  return total;
+}
+
+int scratch_bufs(int64_t n, int n_scn, bool lead, hipStream_t st, Bufs& b) {
+  char* base = static_cast<char*>(scratch(bufs_layout(n, n_scn, lead, nullptr, nullptr), st));
   if (!base) return AEB_ENOMEM;
-  b.jobs = reinterpret_cast<Job*>(base + off_jobs);
-  b.leads = lead ? reinterpret_cast<LeadJob*>(base + off_leads) : nullptr;
-  b.keys = reinterpret_cast<uint32_t*>(base + off_keys);
-  b.perm = reinterpret_cast<uint32_t*>(base + off_perm);
-  b.hist = reinterpret_cast<uint32_t*>(base + off_hist);
-  b.counter = reinterpret_cast<unsigned long long*>(base + off_cnt);
-  b.tab = reinterpret_cast<ScnDev*>(base + off_tab);
-  b.scns = reinterpret_cast<aeb_scenario*>(base + off_scn);
+  bufs_layout(n, n_scn, lead, base, &b);
   return AEB_OK;
 }
 
@@ -951,10 +988,13 @@ int launch_rollout_fast(const aeb_scenario& s, const ParamSrc* src, int precisio
   return integrate<false>(s, precision, b, n, ctx, src, st);
 }
 
-int launch_batch_fast(const aeb_scenario* scns, int n_scn, int precision, const OutCols* outs,
-                      hipStream_t st) {
+size_t batch_scratch_bytes(int64_t total, int n_scn, bool lead) {
+  return bufs_layout(total, n_scn, lead, nullptr, nullptr);
+}
+
+int fill_batch_table(const aeb_scenario* scns, int n_scn, const OutCols* outs, ScnDev* tab,
+                     int64_t* total_out, int64_t* cap_out) {
   int64_t total = 0, cap = 1;
-  std::vector<ScnDev> tab(n_scn);
   for (int j = 0; j < n_scn; ++j) {
     const int64_t nd = dead_steps(scns[j]), nmax = horizon_steps(scns[j]);
     if (nmax > 0x7fffffff || nd > 0x7fffffff) return fail(AEB_EINVAL, "step counts beyond 2^31");
@@ -968,12 +1008,18 @@ int launch_batch_fast(const aeb_scenario* scns, int n_scn, int precision, const 
     if (nmax > cap) cap = nmax;
   }
   if (total > 0xffffffffLL) return fail(AEB_EINVAL, "a batch holds at most 2^32 - 1 samples");
+  *total_out = total;
+  *cap_out = cap;
+  return AEB_OK;
+}
+
+int launch_batch_fast_into(const aeb_scenario* scns, int n_scn, int precision,
+                           const ScnDev* tab, int64_t total, int64_t cap, void* scratch_base,
+                           hipStream_t st) {
   const bool lead = scns[0].obstacle == AEB_OBS_LEAD;
   Bufs b;
-  if (scratch_bufs(total, n_scn, lead, st, b) != AEB_OK) return AEB_ENOMEM;
-  // the tables travel with the stream; the host copies stay alive until the
-  // stream has consumed them
-  AEB_HIP(hipMemcpyAsync(b.tab, tab.data(), sizeof(ScnDev) * n_scn, hipMemcpyHostToDevice, st));
+  bufs_layout(total, n_scn, lead, static_cast<char*>(scratch_base), &b);
+  AEB_HIP(hipMemcpyAsync(b.tab, tab, sizeof(ScnDev) * n_scn, hipMemcpyHostToDevice, st));
   AEB_HIP(hipMemcpyAsync(b.scns, scns, sizeof(aeb_scenario) * n_scn, hipMemcpyHostToDevice, st));
   const unsigned pblk = static_cast<unsigned>((total + PREP_SAMPLES - 1) / PREP_SAMPLES);
   hipLaunchKernelGGL(k_zero, dim3(NBINS / 256), dim3(256), 0, st, b.hist, int64_t(NBINS));
@@ -989,9 +1035,22 @@ int launch_batch_fast(const aeb_scenario* scns, int n_scn, int precision, const 
   Ctx ctx{};
   ctx.impact_exit = scns[0].impact_exit;
   ctx.tab = b.tab;
-  int rc = integrate<true>(scns[0], precision, b, total, ctx, nullptr, st);
+  return integrate<true>(scns[0], precision, b, total, ctx, nullptr, st);
+}
+
+int launch_batch_fast(const aeb_scenario* scns, int n_scn, int precision, const OutCols* outs,
+                      hipStream_t st) {
+  std::vector<ScnDev> tab(n_scn);
+  int64_t total = 0, cap = 1;
+  int rc = fill_batch_table(scns, n_scn, outs, tab.data(), &total, &cap);
   if (rc != AEB_OK) return rc;
-  // keep the host tables valid until the copies have run
+  const bool lead = scns[0].obstacle == AEB_OBS_LEAD;
+  void* base = scratch(batch_scratch_bytes(total, n_scn, lead), st);
+  if (!base) return AEB_ENOMEM;
+  rc = launch_batch_fast_into(scns, n_scn, precision, tab.data(), total, cap, base, st);
+  if (rc != AEB_OK) return rc;
+  // the tables are copied from pageable host memory: keep them valid until
+  // the copies have run
   AEB_HIP(hipStreamSynchronize(st));
   return AEB_OK;
 }

@@ -509,41 +509,58 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 }  // namespace
 
-int launch_reduce(const OutCols& out, int64_t n, const aeb_reduce_req& req, aeb_stats* host_out,
-                  hipStream_t st) {
+namespace {
+
+// Scratch layout of one reduction: stats, risk-grid histogram and selection
+// state first (zeroed by one launch), then the block partials, the selection
+// histograms, the candidates and the radix-select state.
+struct RLayout {
+  long long chunk, chunk2;
+  int nb, nb2, T;
+  size_t off_rh, off_sel, off_zero_end, off_var, off_bh, off_bt, off_cand, off_ss, off_sh, total;
+};
+
+RLayout layout(int64_t n, const aeb_reduce_req& req) {
+  RLayout L;
   // element passes take 1,024-element slices (enough blocks to fill the chip);
   // the histogram pass 4,096 (fewer block histograms to merge)
-  const long long chunk = 1024;
-  const int nb = static_cast<int>((n + chunk - 1) / chunk);
+  L.chunk = 1024;
+  L.chunk2 = L.chunk * 4;
+  L.nb = static_cast<int>((n + L.chunk - 1) / L.chunk);
+  L.nb2 = static_cast<int>((n + L.chunk2 - 1) / L.chunk2);
+  L.T = req.n_risk + req.n_margin_q;
+  const int tc = L.T > 0 ? L.T : 1;
+  L.off_rh = align256(sizeof(aeb_stats));
+  L.off_sel = align256(L.off_rh + sizeof(unsigned) * (AEB_MAX_GRID + 1));
+  L.off_zero_end = align256(L.off_sel + sizeof(Sel));
+  L.off_var = align256(L.off_zero_end + sizeof(Partial) * L.nb);
+  L.off_bh = align256(L.off_var + sizeof(double) * (L.nb > L.nb2 ? L.nb : L.nb2));
+  L.off_bt = align256(L.off_bh + sizeof(unsigned) * 2 * (NVB + 1) * L.nb2);
+  L.off_cand = align256(L.off_bt + sizeof(unsigned) * 2 * (NVB + 1));
+  L.off_ss = align256(L.off_cand + sizeof(unsigned long long) * tc * CAP);
+  L.off_sh = align256(L.off_ss + sizeof(SelState));
+  L.total = align256(L.off_sh + sizeof(unsigned) * tc * 256);
+  return L;
+}
+
+}  // namespace
+
+size_t reduce_scratch_bytes(int64_t n, const aeb_reduce_req& req) { return layout(n, req).total; }
+
+int reduce_enqueue(const OutCols& out, int64_t n, const aeb_reduce_req& req, void* scratch_base,
+                   aeb_stats* host_out, hipStream_t st) {
+  const RLayout L = layout(n, req);
   const int ng = req.n_grid;
-  const int T = req.n_risk + req.n_margin_q;
-  // scratch layout; stats, grid histogram and Sel are zeroed by one launch
-  const size_t off_stats = 0;
-  const size_t off_rh = align256(off_stats + sizeof(aeb_stats));
-  const size_t off_sel = align256(off_rh + sizeof(unsigned) * (AEB_MAX_GRID + 1));
-  const size_t off_zero_end = align256(off_sel + sizeof(Sel));
-  const size_t off_part = off_zero_end;
-  const size_t off_var = align256(off_part + sizeof(Partial) * nb);
-  const long long chunk2 = chunk * 4;
-  const int nb2 = static_cast<int>((n + chunk2 - 1) / chunk2);
-  const size_t off_bh = align256(off_var + sizeof(double) * (nb > nb2 ? nb : nb2));
-  const size_t off_bt = align256(off_bh + sizeof(unsigned) * 2 * (NVB + 1) * nb2);
-  const size_t off_cand = align256(off_bt + sizeof(unsigned) * 2 * (NVB + 1));
-  const size_t off_ss = align256(off_cand + sizeof(unsigned long long) * MAX_T * CAP);
-  const size_t off_sh = align256(off_ss + sizeof(SelState));
-  const size_t total = align256(off_sh + sizeof(unsigned) * MAX_T * 256);
-  char* base = static_cast<char*>(scratch(total, st));
-  if (!base) return AEB_ENOMEM;
-  aeb_stats* dstats = reinterpret_cast<aeb_stats*>(base + off_stats);
-  unsigned* rhist = reinterpret_cast<unsigned*>(base + off_rh);
-  Sel* sel = reinterpret_cast<Sel*>(base + off_sel);
-  Partial* part = reinterpret_cast<Partial*>(base + off_part);
-  double* vpart = reinterpret_cast<double*>(base + off_var);
-  unsigned* bhist = reinterpret_cast<unsigned*>(base + off_bh);
-  unsigned* btot = reinterpret_cast<unsigned*>(base + off_bt);
-  unsigned long long* cand = reinterpret_cast<unsigned long long*>(base + off_cand);
-  SelState* ss = reinterpret_cast<SelState*>(base + off_ss);
-  unsigned* shist = reinterpret_cast<unsigned*>(base + off_sh);
+  const int T = L.T;
+  char* base = static_cast<char*>(scratch_base);
+  aeb_stats* dstats = reinterpret_cast<aeb_stats*>(base);
+  unsigned* rhist = reinterpret_cast<unsigned*>(base + L.off_rh);
+  Sel* sel = reinterpret_cast<Sel*>(base + L.off_sel);
+  Partial* part = reinterpret_cast<Partial*>(base + L.off_zero_end);
+  double* vpart = reinterpret_cast<double*>(base + L.off_var);
+  unsigned* bhist = reinterpret_cast<unsigned*>(base + L.off_bh);
+  unsigned* btot = reinterpret_cast<unsigned*>(base + L.off_bt);
+  unsigned long long* cand = reinterpret_cast<unsigned long long*>(base + L.off_cand);
 
   // targets: ranks computed exactly as floor(level * N) in binary64
   SelIn in;
@@ -564,47 +581,59 @@ int launch_reduce(const OutCols& out, int64_t n, const aeb_reduce_req& req, aeb_
     need_m = true;
   }
   static_assert(sizeof(aeb_stats) % 4 == 0, "stats size");
-  const long long zero_words = static_cast<long long>(off_zero_end / 4);
+  const long long zero_words = static_cast<long long>(L.off_zero_end / 4);
   hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<unsigned>((zero_words + 255) / 256)), dim3(256),
                      0, st, reinterpret_cast<unsigned*>(base), zero_words);
   const double gstep = ng >= 2 ? (req.grid_hi - req.grid_lo) / static_cast<double>(ng - 1) : 0.0;
-  hipLaunchKernelGGL(k_pass1, dim3(nb), dim3(RB), 0, st, out, static_cast<long long>(n), chunk,
+  hipLaunchKernelGGL(k_pass1, dim3(L.nb), dim3(RB), 0, st, out, static_cast<long long>(n), L.chunk,
                      req.grid_lo, gstep, ng, rhist, part);
-  hipLaunchKernelGGL(k_fin1, dim3(1), dim3(FB), 0, st, part, nb, static_cast<long long>(n), ng,
+  hipLaunchKernelGGL(k_fin1, dim3(1), dim3(FB), 0, st, part, L.nb, static_cast<long long>(n), ng,
                      rhist, dstats, sel);
-  hipLaunchKernelGGL(k_pass2, dim3(nb2), dim3(RB), 0, st, out, static_cast<long long>(n), chunk2,
-                     dstats, sel, need_d ? 1 : 0, need_m ? 1 : 0, bhist, vpart);
+  hipLaunchKernelGGL(k_pass2, dim3(L.nb2), dim3(RB), 0, st, out, static_cast<long long>(n),
+                     L.chunk2, dstats, sel, need_d ? 1 : 0, need_m ? 1 : 0, bhist, vpart);
   if (T > 0)
-    hipLaunchKernelGGL(k_bin_totals, dim3((2 * (NVB + 1) + 255) / 256), dim3(256), 0, st, bhist, nb2,
-                       btot);
-  hipLaunchKernelGGL(k_fin2, dim3(1 + T), dim3(FB), 0, st, vpart, nb2, dstats, sel, in, btot);
+    hipLaunchKernelGGL(k_bin_totals, dim3((2 * (NVB + 1) + 255) / 256), dim3(256), 0, st, bhist,
+                       L.nb2, btot);
+  hipLaunchKernelGGL(k_fin2, dim3(1 + T), dim3(FB), 0, st, vpart, L.nb2, dstats, sel, in, btot);
   if (T > 0) {
-    hipLaunchKernelGGL(k_collect, dim3(nb), dim3(RB), 0, st, out, static_cast<long long>(n), chunk,
-                       sel, in, cand);
+    hipLaunchKernelGGL(k_collect, dim3(L.nb), dim3(RB), 0, st, out, static_cast<long long>(n),
+                       L.chunk, sel, in, cand);
     hipLaunchKernelGGL(k_pick, dim3(T), dim3(RB), 0, st, sel, in, cand, dstats);
     hipLaunchKernelGGL(k_flag, dim3(1), dim3(64), 0, st, sel, dstats);
   }
   AEB_HIP(hipGetLastError());
   AEB_HIP(hipMemcpyAsync(host_out, dstats, sizeof(aeb_stats), hipMemcpyDeviceToHost, st));
-  AEB_HIP(hipStreamSynchronize(st));
-  const int fallback = host_out->reserved;
-  host_out->reserved = 0;
-  if (!fallback) return AEB_OK;
+  return AEB_OK;
+}
 
-  // a target's value bin holds more than CAP distinct candidates: radix select
+int reduce_fallback(const OutCols& out, int64_t n, const aeb_reduce_req& req, void* scratch_base,
+                    aeb_stats* host_out, hipStream_t st) {
+  // a target's value bin held more than CAP distinct candidates: radix select
+  const RLayout L = layout(n, req);
+  const int T = L.T;
+  char* base = static_cast<char*>(scratch_base);
+  aeb_stats* dstats = reinterpret_cast<aeb_stats*>(base);
+  SelState* ss = reinterpret_cast<SelState*>(base + L.off_ss);
+  unsigned* shist = reinterpret_cast<unsigned*>(base + L.off_sh);
   SelState rs;
   std::memset(&rs, 0, sizeof(rs));
   rs.count = T;
-  for (int t = 0; t < T; ++t) {
-    rs.rank[t] = in.rank[t];
-    rs.kind[t] = in.kind[t];
+  for (int j = 0; j < req.n_risk; ++j) {
+    long long m = static_cast<long long>(std::floor(req.risk[j] * static_cast<double>(n)));
+    rs.rank[j] = static_cast<unsigned long long>(n - m - 1);
+    rs.kind[j] = 0;
+  }
+  for (int j = 0; j < req.n_margin_q; ++j) {
+    long long m = static_cast<long long>(std::floor(req.margin_q[j] * static_cast<double>(n)));
+    rs.rank[req.n_risk + j] = static_cast<unsigned long long>(m);
+    rs.kind[req.n_risk + j] = 1;
   }
   AEB_HIP(hipMemcpyAsync(ss, &rs, sizeof(rs), hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(k_zero_u32, dim3((MAX_T * 256 + 255) / 256), dim3(256), 0, st, shist,
-                     static_cast<long long>(MAX_T * 256));
+  hipLaunchKernelGGL(k_zero_u32, dim3((T * 256 + 255) / 256), dim3(256), 0, st, shist,
+                     static_cast<long long>(T * 256));
   for (int pass = 0; pass < 8; ++pass) {
-    hipLaunchKernelGGL(k_select_hist, dim3(nb), dim3(RB), 0, st, out, static_cast<long long>(n),
-                       chunk, ss, pass, shist);
+    hipLaunchKernelGGL(k_select_hist, dim3(L.nb), dim3(RB), 0, st, out, static_cast<long long>(n),
+                       L.chunk, ss, pass, shist);
     hipLaunchKernelGGL(k_select_step, dim3(1), dim3(64), 0, st, ss, pass, shist);
   }
   hipLaunchKernelGGL(k_select_out, dim3(1), dim3(64), 0, st, ss, req.n_risk, dstats);
@@ -613,6 +642,19 @@ int launch_reduce(const OutCols& out, int64_t n, const aeb_reduce_req& req, aeb_
   AEB_HIP(hipStreamSynchronize(st));
   host_out->reserved = 0;
   return AEB_OK;
+}
+
+int launch_reduce(const OutCols& out, int64_t n, const aeb_reduce_req& req, aeb_stats* host_out,
+                  hipStream_t st) {
+  void* base = scratch(reduce_scratch_bytes(n, req), st);
+  if (!base) return AEB_ENOMEM;
+  int rc = reduce_enqueue(out, n, req, base, host_out, st);
+  if (rc != AEB_OK) return rc;
+  AEB_HIP(hipStreamSynchronize(st));
+  const int fallback = host_out->reserved;
+  host_out->reserved = 0;
+  if (!fallback) return AEB_OK;
+  return reduce_fallback(out, n, req, base, host_out, st);
 }
 
 }  // namespace aeb
