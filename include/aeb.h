@@ -245,6 +245,69 @@ int aeb_timing_last(float* ms);
 int aeb_reduce(const aeb_outputs* out, const aeb_reduce_req* req, aeb_stats* host_out,
                void* stream);
 
+/* ---- launch shapes and the autotuner ----
+ *
+ * The block-structured integration kernel (Sec. V's one-thread-per-sample
+ * mapping, reorganised as described for aeb_rollout) has three launch
+ * parameters per precision (AEB_FP64, AEB_FP32C) and obstacle kind: k, the
+ * steps per unchecked block (16, 32 or 64; FP32C 16 or 32), the workgroup
+ * size (64, 128, 256), and waves_per_simd (0: one workgroup per `block`
+ * samples in one pass; 1..32: a persistent grid of that many wavefronts per
+ * SIMD claiming 64-sample chunks).  Results do not depend on them.  The
+ * table starts from built-in defaults; if the environment variable
+ * AEB_TUNE_CACHE names a cache file it is loaded at first use. */
+int aeb_tune_get(int precision, int obstacle, int32_t* k, int32_t* block,
+                 int32_t* waves_per_simd);
+int aeb_tune_set(int precision, int obstacle, int32_t k, int32_t block, int32_t waves_per_simd);
+
+/* Load a cache written by aeb_autotune (AEB_EINVAL for a missing or malformed
+ * file; entries are validated before any is used). */
+int aeb_tune_load(const char* path);
+
+/* Time every candidate shape on `calib` (parameters drawn in-kernel; a few
+ * launches each, synchronous on `stream`), keep the fastest for (precision,
+ * calib->obstacle), return its time for the whole rollout call in *best_ms
+ * (may be NULL) and, if cache_path is not NULL, write the table as JSON. */
+int aeb_autotune(const aeb_scenario* calib, int precision, const char* cache_path, void* stream,
+                 float* best_ms);
+
+/* ---- recorded launch sequences (HIP graphs) ----
+ *
+ * The steady-state evaluation of one scenario (or of a fixed mix of
+ * scenarios) on fixed buffers -- the rollout of Sec. IV-D/V plus, if `req` is
+ * given, the statistics of Sec. VI per output set -- recorded once and then
+ * replayed with a single launch, which removes the per-kernel launch cost of
+ * repeated evaluations.  Each replay recomputes everything from the inputs
+ * (parameter columns as they are at replay time, or the in-kernel generator)
+ * and gives the same results as the eager calls.  The graph owns its device
+ * scratch (allocated at creation) and, for batches, pinned copies of the
+ * scenario tables.  Only the block-structured Euler path is recorded (FP64 or
+ * FP32C; no RK4, no nofma, no FP32 lead vehicle): AEB_EINVAL otherwise. */
+typedef struct aeb_graph aeb_graph;
+
+/* One scenario: params (device columns, or NULL for the in-kernel generator),
+ * out (device outputs, n_samples long), req (NULL: rollout only) and
+ * host_stats: pinned host memory (hipHostMalloc) that each replay's
+ * statistics are copied into; valid after aeb_graph_finish. */
+int aeb_graph_create(const aeb_scenario* scn, const aeb_params* params, int precision,
+                     const aeb_outputs* out, const aeb_reduce_req* req, aeb_stats* host_stats,
+                     aeb_graph** graph);
+
+/* A fixed mix of n_scn scenarios as one batched launch (as aeb_batch_rollout)
+ * followed by one reduction per scenario into host_stats[j] (pinned, n_scn). */
+int aeb_graph_create_batch(const aeb_scenario* scns, int n_scn, int precision,
+                           const aeb_outputs* outs, const aeb_reduce_req* req,
+                           aeb_stats* host_stats, aeb_graph** graph);
+
+/* Enqueue one replay on `stream` (asynchronous). */
+int aeb_graph_launch(aeb_graph* graph, void* stream);
+
+/* Wait for `stream`; where a replay's order statistics needed the radix
+ * fallback (rare), compute it; afterwards host_stats holds the statistics. */
+int aeb_graph_finish(aeb_graph* graph, void* stream);
+
+int aeb_graph_destroy(aeb_graph* graph);
+
 /* ---- serving: continuous batching of evaluation requests ----
  *
  * Sec. VI bounds one Monte Carlo evaluation by 530 ms (700 ms of braking

@@ -30,7 +30,9 @@ EXPORTS = ("aeb_last_error", "aeb_version", "aeb_validate", "aeb_uniforms", "aeb
            "aeb_rollout", "aeb_reduce", "aeb_batch_rollout", "aeb_batch_reduce",
            "aeb_timing_enable", "aeb_timing_last", "aeb_server_fixed_bytes",
            "aeb_serve_footprint", "aeb_server_create", "aeb_server_destroy", "aeb_serve_submit",
-           "aeb_serve_poll", "aeb_server_info_get")
+           "aeb_serve_poll", "aeb_server_info_get", "aeb_graph_create", "aeb_graph_create_batch",
+           "aeb_graph_launch", "aeb_graph_finish", "aeb_graph_destroy", "aeb_tune_get",
+           "aeb_tune_set", "aeb_tune_load", "aeb_autotune")
 
 
 class AebError(RuntimeError):
@@ -127,6 +129,17 @@ def lib():
         L.aeb_serve_submit.argtypes = [C.c_void_p, P(Scenario), C.c_double, P(C.c_uint64)]
         L.aeb_serve_poll.argtypes = [C.c_void_p, C.c_uint64, P(Stats), P(ReqTiming)]
         L.aeb_server_info_get.argtypes = [C.c_void_p, P(ServerInfo)]
+        L.aeb_graph_create.argtypes = [P(Scenario), P(Params), C.c_int, P(Outputs),
+                                       P(ReduceReq), C.c_void_p, P(C.c_void_p)]
+        L.aeb_graph_create_batch.argtypes = [P(Scenario), C.c_int, C.c_int, P(Outputs),
+                                             P(ReduceReq), C.c_void_p, P(C.c_void_p)]
+        L.aeb_graph_launch.argtypes = [C.c_void_p, C.c_void_p]
+        L.aeb_graph_finish.argtypes = [C.c_void_p, C.c_void_p]
+        L.aeb_graph_destroy.argtypes = [C.c_void_p]
+        L.aeb_tune_get.argtypes = [C.c_int, C.c_int, P(C.c_int32), P(C.c_int32), P(C.c_int32)]
+        L.aeb_tune_set.argtypes = [C.c_int, C.c_int, C.c_int32, C.c_int32, C.c_int32]
+        L.aeb_tune_load.argtypes = [C.c_char_p]
+        L.aeb_autotune.argtypes = [P(Scenario), C.c_int, C.c_char_p, C.c_void_p, P(C.c_float)]
         _lib = L
     return _lib
 
@@ -425,3 +438,87 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+class Graph:
+    """A recorded rollout (+ statistics) of one scenario, or of a fixed mix of
+    scenarios in one batched launch, replayed with one launch.  Outputs are
+    the device tensors given (or allocated here); statistics land in pinned
+    host memory owned by this object."""
+
+    def __init__(self, d, params=None, precision="fp64", out=None, risk=(), margin_q=(),
+                 grid=None, stats=True, batch=False):
+        torch = _torch()
+        scns = list(d) if batch else [d]
+        k = len(scns)
+        if out is None:
+            out = [alloc_outputs(int(x["n_samples"])) for x in scns] if batch else \
+                alloc_outputs(int(scns[0]["n_samples"]))
+        self.out = out
+        outs = out if batch else [out]
+        self.req = reduce_request(risk, margin_q, grid) if stats else None
+        self._pin = torch.empty(C.sizeof(Stats) * k, dtype=torch.uint8, pin_memory=True)
+        self._stats = (Stats * k).from_address(self._pin.data_ptr())
+        h = C.c_void_p()
+        req = C.byref(self.req) if stats else None
+        if batch:
+            sarr = (Scenario * k)(*[scenario(x) for x in scns])
+            oarr = (Outputs * k)(*[_outputs_struct(o) for o in outs])
+            _check(lib().aeb_graph_create_batch(sarr, k, PRECISIONS[precision], oarr, req,
+                                                self._pin.data_ptr(), C.byref(h)))
+        else:
+            prm = C.byref(_params_struct(params, int(scns[0]["n_samples"]))) if params else None
+            _check(lib().aeb_graph_create(C.byref(scenario(scns[0])), prm,
+                                          PRECISIONS[precision],
+                                          C.byref(_outputs_struct(outs[0])), req,
+                                          self._pin.data_ptr(), C.byref(h)))
+        self.k, self.batch, self.h = k, batch, h
+
+    def launch(self, stream=None):
+        _check(lib().aeb_graph_launch(self.h, _stream(stream)))
+
+    def finish(self, stream=None):
+        """Wait for the stream; returns the statistics (list for a batch)."""
+        _check(lib().aeb_graph_finish(self.h, _stream(stream)))
+        if self.req is None:
+            return None
+        r = self.req
+        st = [stats_dict(self._stats[j], r.n_risk, r.n_margin_q, r.n_grid) for j in range(self.k)]
+        return st if self.batch else st[0]
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(lib().aeb_graph_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tune_get(precision="fp64", obstacle="stationary"):
+    """(k, block, waves_per_simd) of the integration kernel's launch."""
+    k, b, w = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().aeb_tune_get(PRECISIONS[precision], OBSTACLES[obstacle], C.byref(k), C.byref(b),
+                              C.byref(w)))
+    return k.value, b.value, w.value
+
+
+def tune_set(precision, obstacle, k, block, waves_per_simd):
+    _check(lib().aeb_tune_set(PRECISIONS[precision], OBSTACLES[obstacle], k, block,
+                              waves_per_simd))
+
+
+def tune_load(path):
+    _check(lib().aeb_tune_load(os.fsencode(path)))
+
+
+def autotune(d, precision="fp64", cache_path=None, stream=None):
+    """Time every launch shape on scenario d; keeps the fastest; returns its ms."""
+    ms = C.c_float()
+    _check(lib().aeb_autotune(C.byref(scenario(d)), PRECISIONS[precision],
+                              os.fsencode(cache_path) if cache_path else None, _stream(stream),
+                              C.byref(ms)))
+    return ms.value

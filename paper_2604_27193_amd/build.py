@@ -1,6 +1,6 @@
 """Build the HIP library ``libaeb.so`` for gfx950 in-tree.
 
-One hipcc invocation compiles every source under ``csrc/`` with
+Every source under ``csrc/`` is compiled (in parallel) with
 ``-ffp-contract=off`` (no implicit multiply-add fusion: the kernels' fused
 operations are the explicit ``fma`` calls) and packed FP32 instructions
 disabled.
@@ -30,15 +30,27 @@ def sources():
 
 
 def build(force: bool = True, extra=()) -> str:
-    """Compile the library; returns the path of the shared object."""
+    """Compile the library (one object per source, in parallel, then one
+    link); returns the path of the shared object."""
     srcs = sources()
     deps = srcs + glob.glob(os.path.join(CSRC, "*.h")) + [os.path.join(INCLUDE, "aeb.h")]
     if not force and os.path.exists(LIB):
         if os.path.getmtime(LIB) >= max(os.path.getmtime(p) for p in deps):
             return LIB
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    cflags = [f for f in FLAGS if f not in ("-shared",)]
+    procs, objs = [], []
+    for src in srcs:
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        objs.append(obj)
+        procs.append((src, subprocess.Popen(["hipcc", *cflags, *extra, "-c", "-o", obj, src])))
+    bad = [src for src, p in procs if p.wait() != 0]
+    if bad:
+        raise subprocess.CalledProcessError(1, "hipcc", output=f"failed: {bad}")
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["hipcc", *FLAGS, *extra, "-o", tmp, *srcs]
-    subprocess.run(cmd, check=True)
+    subprocess.run(["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-pthread", *extra,
+                    "-o", tmp, *objs], check=True)
     os.replace(tmp, LIB)
     return LIB
 

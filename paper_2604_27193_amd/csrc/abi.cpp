@@ -136,6 +136,14 @@ int validate(const aeb_scenario& s) {
   return AEB_OK;
 }
 
+bool timing_suspend(bool off) {
+  const bool was = g_timing.on;
+  if (off) g_timing.on = false;
+  return was;
+}
+
+void timing_resume(bool was) { g_timing.on = was; }
+
 void timing_begin(hipStream_t stream) {
   Timing& t = g_timing;
   if (!t.on) return;

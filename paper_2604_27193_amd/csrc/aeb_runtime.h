@@ -36,6 +36,9 @@ inline void* scratch_fix(size_t bytes, hipStream_t stream) { return scratch_slot
 // events around the integration kernel (aeb_timing_enable)
 void timing_begin(hipStream_t stream);
 void timing_end(hipStream_t stream);
+// switch the hooks off on this thread (returns the previous state) / back on
+bool timing_suspend(bool off);
+void timing_resume(bool was);
 
 int validate(const aeb_scenario& s);
 

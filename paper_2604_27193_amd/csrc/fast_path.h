@@ -40,6 +40,11 @@ enum { FORM_G = 0, FORM_F = 1, FORM_C = 2, FORM_D = 3 };
 bool fast_path_applies(const aeb_scenario& s, int precision);
 int launch_rollout_fast(const aeb_scenario& s, const ParamSrc* src, int precision,
                         const OutCols& out, int64_t n, hipStream_t st);
+// the same on caller-provided device scratch of rollout_scratch_bytes(s, n)
+// bytes (precision AEB_FP64 or AEB_FP32C)
+size_t rollout_scratch_bytes(const aeb_scenario& s, int64_t n);
+int launch_rollout_fast_into(const aeb_scenario& s, const ParamSrc* src, int precision,
+                             const OutCols& out, int64_t n, void* scratch_base, hipStream_t st);
 // all samples of several scenarios in one sorted launch (parameters drawn in-kernel)
 int launch_batch_fast(const aeb_scenario* scns, int n_scn, int precision, const OutCols* outs,
                       hipStream_t st);

@@ -1,0 +1,261 @@
+// graph.cpp -- recorded launch sequences (aeb_graph_*): a steady-state rollout
+// plus reduction of one scenario, or of a fixed mix of scenarios in one
+// batched launch, captured once into a HIP graph and replayed with one
+// launch.  The graph owns its device scratch (allocated at creation, so no
+// later call can move it) and, for batches, pinned copies of the scenario
+// tables that its copy nodes read at every replay.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "aeb_runtime.h"
+#include "fast_path.h"
+
+struct aeb_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  char* scratch = nullptr;           // device: rollout scratch, then one reduce scratch per set
+  aeb::ScnDev* tab = nullptr;        // pinned (batches)
+  aeb_scenario* scns = nullptr;      // pinned (batches)
+  std::vector<aeb::OutCols> outs;
+  std::vector<int64_t> ns;
+  std::vector<size_t> red_off;       // offset of each set's reduce scratch
+  aeb_stats* host_stats = nullptr;   // caller's pinned statistics, one per set
+  bool reduce = false;
+  aeb_reduce_req req{};
+};
+
+namespace aeb {
+namespace {
+
+size_t up256(size_t b) { return (b + 255) & ~size_t(255); }
+
+bool outputs_ok(const aeb_outputs* o) {
+  return o && o->dist && o->status && o->steps && o->margin && o->v_impact;
+}
+
+void destroy(aeb_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->scratch) (void)hipFree(g->scratch);
+  if (g->tab) (void)hipHostFree(g->tab);
+  if (g->scns) (void)hipHostFree(g->scns);
+  delete g;
+}
+
+bool pinned(const void* p) {
+  unsigned flags = 0;
+  return hipHostGetFlags(&flags, const_cast<void*>(p)) == hipSuccess;
+}
+
+// Capture `enqueue` (which queues work on the given stream) into g's graph.
+template <typename F>
+int capture(aeb_graph* g, F enqueue) {
+  hipStream_t st = nullptr;
+  AEB_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  const bool was = timing_suspend(true);
+  int rc = AEB_OK;
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    rc = fail(AEB_EDEVICE, "hipStreamBeginCapture failed");
+  } else {
+    rc = enqueue(st);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &graph);
+    if (rc == AEB_OK && e != hipSuccess)
+      rc = fail(AEB_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    g->graph = graph;
+  }
+  timing_resume(was);
+  (void)hipStreamDestroy(st);
+  if (rc != AEB_OK) return rc;
+  AEB_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+  return AEB_OK;
+}
+
+int enqueue_reduces(aeb_graph* g, hipStream_t st) {
+  if (!g->reduce) return AEB_OK;
+  for (size_t j = 0; j < g->outs.size(); ++j) {
+    const int rc = reduce_enqueue(g->outs[j], g->ns[j], g->req, g->scratch + g->red_off[j],
+                                  &g->host_stats[j], st);
+    if (rc != AEB_OK) return rc;
+  }
+  return AEB_OK;
+}
+
+// lay out the reduce scratch after `base` bytes; returns the total
+size_t plan_reduces(aeb_graph* g, size_t base) {
+  size_t off = up256(base);
+  g->red_off.clear();
+  for (size_t j = 0; j < g->outs.size(); ++j) {
+    g->red_off.push_back(off);
+    if (g->reduce) off += up256(reduce_scratch_bytes(g->ns[j], g->req));
+  }
+  return off;
+}
+
+int check_common(int precision, const aeb_reduce_req* req, aeb_stats* host_stats) {
+  if (precision != AEB_FP64 && precision != AEB_FP32C)
+    return fail(AEB_EINVAL, "graphs take AEB_FP64 or AEB_FP32C");
+  if (req) {
+    const int rc = check_reduce_req(*req);
+    if (rc != AEB_OK) return rc;
+    if (!host_stats || !pinned(host_stats))
+      return fail(AEB_EINVAL, "graph statistics need pinned host memory (hipHostMalloc)");
+  }
+  return AEB_OK;
+}
+
+}  // namespace
+}  // namespace aeb
+
+using namespace aeb;
+
+extern "C" {
+
+int aeb_graph_create(const aeb_scenario* scn, const aeb_params* params, int precision,
+                     const aeb_outputs* out, const aeb_reduce_req* req, aeb_stats* host_stats,
+                     aeb_graph** out_graph) {
+  if (!out_graph) return fail(AEB_EINVAL, "aeb_graph_create: null output");
+  *out_graph = nullptr;
+  if (!scn || !outputs_ok(out)) return fail(AEB_EINVAL, "aeb_graph_create: null argument");
+  int rc = validate(*scn);
+  if (rc != AEB_OK) return rc;
+  rc = check_common(precision, req, host_stats);
+  if (rc != AEB_OK) return rc;
+  if (!fast_path_applies(*scn, precision))
+    return fail(AEB_EINVAL, "graphs record the block-structured Euler path (no RK4, no nofma, "
+                            "no FP32 lead vehicle)");
+  if (out->n != scn->n_samples) return fail(AEB_EINVAL, "outputs length differs from n_samples");
+  ParamSrc src{};
+  if (params) {
+    if (!params->v0 || !params->mu || !params->mass || !params->sin_grade ||
+        !params->cos_grade || !params->cda || !params->crr || !params->tau || !params->gap ||
+        !params->lead_decel || params->n != scn->n_samples)
+      return fail(AEB_EINVAL, "aeb_graph_create: incomplete parameter columns");
+    src = ParamSrc{params->v0, params->mu,  params->mass, params->sin_grade, params->cos_grade,
+                   params->cda, params->crr, params->tau, params->gap, params->lead_decel};
+  }
+  aeb_graph* g = new (std::nothrow) aeb_graph;
+  if (!g) return fail(AEB_ENOMEM, "host allocation failed");
+  g->outs.push_back(OutCols{out->dist, out->status, out->steps, out->margin, out->v_impact});
+  g->ns.push_back(scn->n_samples);
+  g->reduce = req != nullptr;
+  if (req) g->req = *req;
+  g->host_stats = host_stats;
+  const size_t roll = rollout_scratch_bytes(*scn, scn->n_samples);
+  const size_t total = plan_reduces(g, roll);
+  if (hipMalloc(reinterpret_cast<void**>(&g->scratch), total) != hipSuccess) {
+    destroy(g);
+    return fail(AEB_ENOMEM, "graph scratch allocation failed");
+  }
+  const aeb_scenario s = *scn;
+  rc = capture(g, [&](hipStream_t st) {
+    int r = launch_rollout_fast_into(s, params ? &src : nullptr, precision, g->outs[0],
+                                     s.n_samples, g->scratch, st);
+    if (r != AEB_OK) return r;
+    return enqueue_reduces(g, st);
+  });
+  if (rc != AEB_OK) {
+    destroy(g);
+    return rc;
+  }
+  *out_graph = g;
+  return AEB_OK;
+}
+
+int aeb_graph_create_batch(const aeb_scenario* scns, int n_scn, int precision,
+                           const aeb_outputs* outs, const aeb_reduce_req* req,
+                           aeb_stats* host_stats, aeb_graph** out_graph) {
+  if (!out_graph) return fail(AEB_EINVAL, "aeb_graph_create_batch: null output");
+  *out_graph = nullptr;
+  if (!scns || !outs || n_scn < 1) return fail(AEB_EINVAL, "aeb_graph_create_batch: empty batch");
+  int rc = check_common(precision, req, host_stats);
+  if (rc != AEB_OK) return rc;
+  for (int j = 0; j < n_scn; ++j) {
+    rc = validate(scns[j]);
+    if (rc != AEB_OK) return rc;
+    if (!outputs_ok(&outs[j]) || outs[j].n != scns[j].n_samples)
+      return fail(AEB_EINVAL, "outputs of scenario " + std::to_string(j) + " do not match it");
+    if (scns[j].integrator != scns[0].integrator || scns[j].obstacle != scns[0].obstacle ||
+        scns[j].impact_exit != scns[0].impact_exit || scns[j].nofma != scns[0].nofma)
+      return fail(AEB_EINVAL, "batched scenarios must share integrator, obstacle, impact_exit, nofma");
+  }
+  if (!fast_path_applies(scns[0], precision))
+    return fail(AEB_EINVAL, "graphs record the block-structured Euler path");
+  aeb_graph* g = new (std::nothrow) aeb_graph;
+  if (!g) return fail(AEB_ENOMEM, "host allocation failed");
+  for (int j = 0; j < n_scn; ++j) {
+    g->outs.push_back(
+        OutCols{outs[j].dist, outs[j].status, outs[j].steps, outs[j].margin, outs[j].v_impact});
+    g->ns.push_back(scns[j].n_samples);
+  }
+  g->reduce = req != nullptr;
+  if (req) g->req = *req;
+  g->host_stats = host_stats;
+  if (hipHostMalloc(reinterpret_cast<void**>(&g->tab), sizeof(ScnDev) * n_scn,
+                    hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&g->scns), sizeof(aeb_scenario) * n_scn,
+                    hipHostMallocDefault) != hipSuccess) {
+    destroy(g);
+    return fail(AEB_ENOMEM, "pinned table allocation failed");
+  }
+  std::memcpy(g->scns, scns, sizeof(aeb_scenario) * n_scn);
+  int64_t total = 0, cap = 1;
+  rc = fill_batch_table(g->scns, n_scn, g->outs.data(), g->tab, &total, &cap);
+  if (rc != AEB_OK) {
+    destroy(g);
+    return rc;
+  }
+  const bool lead = scns[0].obstacle == AEB_OBS_LEAD;
+  const size_t roll = batch_scratch_bytes(total, n_scn, lead);
+  const size_t bytes = plan_reduces(g, roll);
+  if (hipMalloc(reinterpret_cast<void**>(&g->scratch), bytes) != hipSuccess) {
+    destroy(g);
+    return fail(AEB_ENOMEM, "graph scratch allocation failed");
+  }
+  rc = capture(g, [&](hipStream_t st) {
+    int r = launch_batch_fast_into(g->scns, n_scn, precision, g->tab, total, cap, g->scratch, st);
+    if (r != AEB_OK) return r;
+    return enqueue_reduces(g, st);
+  });
+  if (rc != AEB_OK) {
+    destroy(g);
+    return rc;
+  }
+  *out_graph = g;
+  return AEB_OK;
+}
+
+int aeb_graph_launch(aeb_graph* g, void* stream) {
+  if (!g || !g->exec) return fail(AEB_EINVAL, "aeb_graph_launch: null graph");
+  AEB_HIP(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+  return AEB_OK;
+}
+
+int aeb_graph_finish(aeb_graph* g, void* stream) {
+  if (!g) return fail(AEB_EINVAL, "aeb_graph_finish: null graph");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  AEB_HIP(hipStreamSynchronize(st));
+  if (!g->reduce) return AEB_OK;
+  for (size_t j = 0; j < g->outs.size(); ++j) {
+    aeb_stats& s = g->host_stats[j];
+    if (s.reserved) {
+      const int rc = reduce_fallback(g->outs[j], g->ns[j], g->req, g->scratch + g->red_off[j],
+                                     &s, st);
+      if (rc != AEB_OK) return rc;
+    }
+    s.reserved = 0;
+  }
+  return AEB_OK;
+}
+
+int aeb_graph_destroy(aeb_graph* g) {
+  destroy(g);
+  return AEB_OK;
+}
+
+}  // extern "C"

@@ -31,6 +31,7 @@
 #include "aeb_runtime.h"
 #include "fast_path.h"
 #include "rollout_steps.h"
+#include "tune.h"
 
 namespace aeb {
 
@@ -345,6 +346,17 @@ __device__ inline int64_t claim(unsigned long long* counter) {
   return static_cast<int64_t>((static_cast<unsigned long long>(hi) << 32) | lo);
 }
 
+// The next 64 sorted positions of a wavefront: claimed from the counter in a
+// persistent launch, else the wavefront's own slice of its workgroup (first
+// pass only).
+__device__ inline int64_t next_chunk(unsigned long long* counter, int persistent, int pass,
+                                     int64_t n) {
+  if (persistent) return claim(counter);
+  if (pass > 0) return n;
+  return static_cast<int64_t>(blockIdx.x) * blockDim.x +
+         __builtin_amdgcn_readfirstlane(threadIdx.x & ~63u);
+}
+
 // Lane state and per-lane flags of the FP64 integration.
 struct Lane64 {
   St64 s, sv;  // state, and start state of the block where the obstacle was passed
@@ -391,11 +403,12 @@ template <int OBS, int K, bool BATCH>
 __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
                                                    const LeadJob* __restrict__ leads,
                                                    const uint32_t* __restrict__ perm, int64_t n,
-                                                   Ctx ctx, unsigned long long* counter) {
+                                                   Ctx ctx, unsigned long long* counter,
+                                                   int persistent) {
   constexpr int KS = 4;  // short blocks close to the stop
   constexpr bool LEAD = OBS == AEB_OBS_LEAD;
-  for (;;) {
-    const int64_t base = claim(counter);
+  for (int pass = 0;; ++pass) {
+    const int64_t base = next_chunk(counter, persistent, pass, n);
     if (base >= n) break;
     const int64_t pos = base + (threadIdx.x & 63);
     const bool valid = pos < n;
@@ -664,11 +677,12 @@ template <int OBS, int K, bool BATCH>
 __global__ __launch_bounds__(256) void k_roll_fp32c(const Job* __restrict__ jobs,
                                                     const uint32_t* __restrict__ perm, int64_t n,
                                                     Ctx ctx, double band_abs, double band_rel,
-                                                    uint32_t* fix, unsigned long long* counter) {
+                                                    uint32_t* fix, unsigned long long* counter,
+                                                    int persistent) {
   constexpr int KS = 4;
-  static_assert(K == FLUSH && K % KS == 0, "flush points must fall on block ends");
-  for (;;) {
-    const int64_t base = claim(counter);
+  static_assert(FLUSH % K == 0 && K % KS == 0, "flush points must fall on block ends");
+  for (int pass = 0;; ++pass) {
+    const int64_t base = next_chunk(counter, persistent, pass, n);
     if (base >= n) break;
     const int64_t pos = base + (threadIdx.x & 63);
     const bool valid = pos < n;
@@ -830,11 +844,15 @@ bool fast_path_applies(const aeb_scenario& s, int precision) {
 
 namespace {
 
-constexpr int KBLOCK = 32;
+// Launch shape of the integration kernel from the tuning table: workgroup
+// size, and either one pass over ceil(n / block) workgroups or a persistent
+// grid of `waves_per_simd` wavefronts per SIMD claiming work from the counter.
+struct Shape {
+  unsigned grid, block;
+  int persistent;
+};
 
-// persistent grid: as many workgroups as fit on the device at once
-template <typename Kern>
-unsigned persistent_grid(Kern kern, int64_t n) {
+Shape shape(const TuneCfg& t, int64_t n) {
   static int cus = 0;
   if (cus == 0) {
     int dev = 0;
@@ -842,13 +860,18 @@ unsigned persistent_grid(Kern kern, int64_t n) {
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       cus = 256;
   }
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess ||
-      per_cu < 1)
-    per_cu = 4;
-  const int64_t need = (n + 255) / 256;
-  const int64_t grid = static_cast<int64_t>(cus) * per_cu;
-  return static_cast<unsigned>(need < grid ? need : grid);
+  Shape sh;
+  sh.block = static_cast<unsigned>(t.block);
+  const int64_t need = (n + t.block - 1) / t.block;
+  if (t.waves_per_simd > 0) {
+    const int64_t grid = static_cast<int64_t>(cus) * 4 * t.waves_per_simd * 64 / t.block;
+    sh.grid = static_cast<unsigned>(need < grid ? need : grid);
+    sh.persistent = 1;
+  } else {
+    sh.grid = static_cast<unsigned>(need);
+    sh.persistent = 0;
+  }
+  return sh;
 }
 
 struct Bufs {
@@ -903,25 +926,47 @@ void sort_keys(const Bufs& b, int64_t n, hipStream_t st) {
                      int64_t(2));
 }
 
+template <int OBS, int K, bool BATCH>
+void go64(const Shape& sh, const Bufs& b, int64_t n, const Ctx& ctx, hipStream_t st) {
+  hipLaunchKernelGGL((k_roll_fp64<OBS, K, BATCH>), dim3(sh.grid), dim3(sh.block), 0, st, b.jobs,
+                     b.leads, b.perm, n, ctx, b.counter, sh.persistent);
+}
+
+template <int OBS, bool BATCH>
+void go64k(int k, const Shape& sh, const Bufs& b, int64_t n, const Ctx& ctx, hipStream_t st) {
+  if (k == 16)
+    go64<OBS, 16, BATCH>(sh, b, n, ctx, st);
+  else if (k == 64)
+    go64<OBS, 64, BATCH>(sh, b, n, ctx, st);
+  else
+    go64<OBS, 32, BATCH>(sh, b, n, ctx, st);
+}
+
+template <int OBS, bool BATCH>
+void go32k(int k, const Shape& sh, const Bufs& b, int64_t n, const Ctx& ctx, double band_abs,
+           double band_rel, uint32_t* fix, hipStream_t st) {
+  if (k == 16)
+    hipLaunchKernelGGL((k_roll_fp32c<OBS, 16, BATCH>), dim3(sh.grid), dim3(sh.block), 0, st,
+                       b.jobs, b.perm, n, ctx, band_abs, band_rel, fix, b.counter, sh.persistent);
+  else
+    hipLaunchKernelGGL((k_roll_fp32c<OBS, 32, BATCH>), dim3(sh.grid), dim3(sh.block), 0, st,
+                       b.jobs, b.perm, n, ctx, band_abs, band_rel, fix, b.counter, sh.persistent);
+}
+
 template <bool BATCH>
 int integrate(const aeb_scenario& s0, int precision, const Bufs& b, int64_t n, const Ctx& ctx,
               const ParamSrc* src, hipStream_t st) {
   const int obs = s0.obstacle;
+  const TuneCfg t = tune_get(precision == AEB_FP64 ? AEB_FP64 : AEB_FP32C, obs);
+  const Shape sh = shape(t, n);
   if (precision == AEB_FP64) {
     timing_begin(st);
-    if (obs == AEB_OBS_STATIONARY) {
-      auto kern = k_roll_fp64<AEB_OBS_STATIONARY, KBLOCK, BATCH>;
-      hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, n)), dim3(256), 0, st, b.jobs, b.leads,
-                         b.perm, n, ctx, b.counter);
-    } else if (obs == AEB_OBS_LEAD) {
-      auto kern = k_roll_fp64<AEB_OBS_LEAD, KBLOCK, BATCH>;
-      hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, n)), dim3(256), 0, st, b.jobs, b.leads,
-                         b.perm, n, ctx, b.counter);
-    } else {
-      auto kern = k_roll_fp64<AEB_OBS_NONE, KBLOCK, BATCH>;
-      hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, n)), dim3(256), 0, st, b.jobs, b.leads,
-                         b.perm, n, ctx, b.counter);
-    }
+    if (obs == AEB_OBS_STATIONARY)
+      go64k<AEB_OBS_STATIONARY, BATCH>(t.k, sh, b, n, ctx, st);
+    else if (obs == AEB_OBS_LEAD)
+      go64k<AEB_OBS_LEAD, BATCH>(t.k, sh, b, n, ctx, st);
+    else
+      go64k<AEB_OBS_NONE, BATCH>(t.k, sh, b, n, ctx, st);
     timing_end(st);
     AEB_HIP(hipGetLastError());
     return AEB_OK;
@@ -937,15 +982,10 @@ int integrate(const aeb_scenario& s0, int precision, const Bufs& b, int64_t n, c
   // of the boundary are flagged (and, in the fix-up mode, recomputed in FP64)
   const double band_abs = 1e-3, band_rel = 1e-5;
   timing_begin(st);
-  if (obs == AEB_OBS_STATIONARY) {
-    auto kern = k_roll_fp32c<AEB_OBS_STATIONARY, KBLOCK, BATCH>;
-    hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, n)), dim3(256), 0, st, b.jobs, b.perm, n,
-                       ctx, band_abs, band_rel, fix, b.counter);
-  } else {
-    auto kern = k_roll_fp32c<AEB_OBS_NONE, KBLOCK, BATCH>;
-    hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, n)), dim3(256), 0, st, b.jobs, b.perm, n,
-                       ctx, band_abs, band_rel, fix, b.counter);
-  }
+  if (obs == AEB_OBS_STATIONARY)
+    go32k<AEB_OBS_STATIONARY, BATCH>(t.k, sh, b, n, ctx, band_abs, band_rel, fix, st);
+  else
+    go32k<AEB_OBS_NONE, BATCH>(t.k, sh, b, n, ctx, band_abs, band_rel, fix, st);
   timing_end(st);
   AEB_HIP(hipGetLastError());
   if (fix) return launch_fixup(s0, src, ctx.out, fix, st);
@@ -954,13 +994,17 @@ int integrate(const aeb_scenario& s0, int precision, const Bufs& b, int64_t n, c
 
 }  // namespace
 
-int launch_rollout_fast(const aeb_scenario& s, const ParamSrc* src, int precision,
-                        const OutCols& out, int64_t n, hipStream_t st) {
+size_t rollout_scratch_bytes(const aeb_scenario& s, int64_t n) {
+  return bufs_layout(n, 0, s.obstacle == AEB_OBS_LEAD, nullptr, nullptr);
+}
+
+int launch_rollout_fast_into(const aeb_scenario& s, const ParamSrc* src, int precision,
+                             const OutCols& out, int64_t n, void* scratch_base, hipStream_t st) {
   const int64_t nd = dead_steps(s), nmax = horizon_steps(s);
   if (nmax > 0x7fffffff || nd > 0x7fffffff) return fail(AEB_EINVAL, "step counts beyond 2^31");
   const bool lead = s.obstacle == AEB_OBS_LEAD;
   Bufs b;
-  if (scratch_bufs(n, 0, lead, st, b) != AEB_OK) return AEB_ENOMEM;
+  bufs_layout(n, 0, lead, static_cast<char*>(scratch_base), &b);
   const unsigned pblk = static_cast<unsigned>((n + PREP_SAMPLES - 1) / PREP_SAMPLES);
   hipLaunchKernelGGL(k_zero, dim3(NBINS / 256), dim3(256), 0, st, b.hist, int64_t(NBINS));
   PrepArgs pa{};
@@ -986,6 +1030,13 @@ int launch_rollout_fast(const aeb_scenario& s, const ParamSrc* src, int precisio
   ctx.out = out;
   ctx.tab = nullptr;
   return integrate<false>(s, precision, b, n, ctx, src, st);
+}
+
+int launch_rollout_fast(const aeb_scenario& s, const ParamSrc* src, int precision,
+                        const OutCols& out, int64_t n, hipStream_t st) {
+  void* base = scratch(rollout_scratch_bytes(s, n), st);
+  if (!base) return AEB_ENOMEM;
+  return launch_rollout_fast_into(s, src, precision, out, n, base, st);
 }
 
 size_t batch_scratch_bytes(int64_t total, int n_scn, bool lead) {

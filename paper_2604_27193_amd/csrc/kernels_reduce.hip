@@ -5,11 +5,12 @@
 //
 // Sums run in a fixed order (each block a fixed slice, a fixed tree inside the
 // block, blocks summed in index order), so repeated calls give identical
-// bits.  Order statistics are exact: a histogram over 65,536 value bins
-// spanning each array's finite range finds the bin holding a target's rank;
-// the bin's elements are collected and sorted in LDS (bitonic, by an
-// order-preserving map of the FP64 bit patterns).  A bin with more than 4,096
-// elements falls back to a most-significant-digit radix select.
+// bits.  Order statistics are exact: a histogram over 4,096 value bins
+// spanning each array's finite range (plus one bin for the censored +inf
+// values) finds the bin holding a target's rank; the bin's elements are
+// collected and sorted in LDS (bitonic, by an order-preserving map of the
+// FP64 bit patterns).  A bin with more than 8,192 elements falls back to a
+// most-significant-digit radix select (8 passes of 8 bits).
 #include <hip/hip_runtime.h>
 
 #include <cmath>

@@ -83,3 +83,40 @@ def test_host_sampler_rejects_invalid(B):
         B.sample_params(dict(W.single(10), dt=0.0), 0, 10, device=False)
     with pytest.raises(B.AebError):
         B.sample_params(W.single(10), -1, 10, device=False)
+
+
+def test_tune_table_validation(B, tmp_path):
+    keep = B.tune_get("fp64", "stationary")
+    B.tune_set("fp64", "stationary", 64, 128, 4)
+    assert B.tune_get("fp64", "stationary") == (64, 128, 4)
+    for bad in ((48, 256, 0), (32, 512, 0), (32, 256, -1), (32, 256, 33)):
+        with pytest.raises(B.AebError):
+            B.tune_set("fp64", "stationary", *bad)
+    with pytest.raises(B.AebError):
+        B.tune_set("fp32c", "none", 64, 256, 0)      # FP32 blocks must divide its flush period
+    B.tune_set("fp64", "stationary", *keep)
+
+
+def test_tune_cache_load(B, tmp_path):
+    keep = [B.tune_get(p, o) for p in ("fp64", "fp32c") for o in ("none", "stationary", "lead")]
+    good = tmp_path / "tune.json"
+    good.write_text('{"format": 1, "entries": [\n'
+                    '  {"precision": 0, "obstacle": 1, "k": 16, "block": 64, "waves_per_simd": 8, "ms": 1.0},\n'
+                    '  {"precision": 1, "obstacle": 0, "k": 16, "block": 128, "waves_per_simd": 0, "ms": 2.0}\n'
+                    ']}\n')
+    B.tune_load(str(good))
+    assert B.tune_get("fp64", "stationary") == (16, 64, 8)
+    assert B.tune_get("fp32c", "none") == (16, 128, 0)
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"entries": [{"precision": 0, "obstacle": 0, "k": 16, "block": 64, '
+                   '"waves_per_simd": 0}, {"precision": 1, "obstacle": 0, "k": 64, "block": 64, '
+                   '"waves_per_simd": 0}]}')
+    before = B.tune_get("fp64", "none")
+    with pytest.raises(B.AebError):
+        B.tune_load(str(bad))
+    assert B.tune_get("fp64", "none") == before      # nothing applied from a bad file
+    with pytest.raises(B.AebError):
+        B.tune_load(str(tmp_path / "missing.json"))
+    for (p, o), t in zip([(p, o) for p in ("fp64", "fp32c") for o in ("none", "stationary", "lead")],
+                         keep):
+        B.tune_set(p, o, *t)

@@ -1,0 +1,74 @@
+"""GPU tests of the launch shapes: every shape the table accepts gives the
+same bits; the autotuner times them, keeps one and writes a loadable cache."""
+import json
+
+import numpy as np
+import pytest
+
+from paper_2604_27193_amd import workloads as W
+from test_gpu_parity import to_np
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(16, 64, 0), (16, 256, 8), (32, 128, 4), (32, 256, 0), (64, 64, 4), (64, 256, 8)]
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2604_27193_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.mark.parametrize("prec,obs", [("fp64", "stationary"), ("fp64", "lead"),
+                                      ("fp64", "none"), ("fp32c", "stationary")])
+def test_results_do_not_depend_on_shape(B, prec, obs):
+    if obs == "lead":
+        d = W.sweep(n=20000)[70]
+    else:
+        d = W.single(20000, seed=4, scenario_id=2, obstacle=obs)
+    keep = B.tune_get(prec, obs)
+    try:
+        ref = to_np(B.rollout(d, precision=prec))
+        for k, blk, w in SHAPES:
+            if prec == "fp32c" and k == 64:
+                continue
+            B.tune_set(prec, obs, k, blk, w)
+            got = to_np(B.rollout(d, precision=prec))
+            for c in ref:
+                assert np.array_equal(ref[c], got[c]), (k, blk, w, c)
+    finally:
+        B.tune_set(prec, obs, *keep)
+
+
+def test_batch_does_not_depend_on_shape(B):
+    scns = W.uneven_batch(8, max_samples=2000)
+    keep = B.tune_get("fp64", "stationary")
+    try:
+        ref = [to_np(o) for o in B.batch_rollout(scns)]
+        B.tune_set("fp64", "stationary", 16, 64, 8)
+        got = [to_np(o) for o in B.batch_rollout(scns)]
+    finally:
+        B.tune_set("fp64", "stationary", *keep)
+    for a, b in zip(ref, got):
+        for c in a:
+            assert np.array_equal(a[c], b[c]), c
+
+
+def test_autotune_writes_a_loadable_cache(B, tmp_path):
+    keep = B.tune_get("fp64", "stationary")
+    path = tmp_path / "tune.json"
+    try:
+        ms = B.autotune(W.single(65536, seed=8), "fp64", cache_path=str(path))
+        assert ms > 0.0
+        chosen = B.tune_get("fp64", "stationary")
+        entries = json.loads(path.read_text())["entries"]
+        e = [x for x in entries if x["precision"] == 0 and x["obstacle"] == 1][0]
+        assert (e["k"], e["block"], e["waves_per_simd"]) == chosen
+        B.tune_set("fp64", "stationary", *keep)
+        B.tune_load(str(path))
+        assert B.tune_get("fp64", "stationary") == chosen
+    finally:
+        B.tune_set("fp64", "stationary", *keep)
