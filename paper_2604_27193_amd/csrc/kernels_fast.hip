@@ -438,11 +438,15 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
     // limited for good once a <= alim: a never climbs above max(a, a_cmd) < alim
     L.limited = J.alim > c.a_cmd + 1e-9;
     int end = 0, steps = 0;
+    // margin: with a lead vehicle the running minimum of the clearance, taken
+    // when the lane ends (later blocks keep integrating an ended lane's state)
     double dist = 0.0, margin = J.gap;
     float vimp = 0.0f;
     int k = 0, wl = -1;
     // every lane has ended by its step nmax (the horizon test fires at k + 1 == nmax)
     for (;;) {
+      // the step index is the same in every lane: keep it (and the branches on it) scalar
+      k = __builtin_amdgcn_readfirstlane(k);
       if (!__any(L.active)) break;
       if (!BATCH || k >= wl) wl = wave_lim<BATCH>(L.active, k, c.nd, c.nmax);
       if (k + K <= wl && !__any(L.active && L.s.v <= thr_k)) {
@@ -487,6 +491,7 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
               dist = L.s.x;
             }
           }
+          if (LEAD && !L.active) margin = L.l.gmin;
         }
         k += 1;
       }
@@ -518,7 +523,7 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
               end = AEB_END_IMPACT;
               steps = kr;
               dist = r.x;
-              L.l.gmin = rl.gmin;
+              margin = rl.gmin;
             }
           }
         }
@@ -526,9 +531,7 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
     }
     if (L.pend) vimp = __builtin_nanf("");  // unreachable; makes a broken replay visible
     if (valid) {
-      if (LEAD) {
-        margin = L.l.gmin;
-      } else {
+      if (!LEAD) {
         const double mg = J.gap - dist;
         margin = mg < J.gap ? mg : J.gap;
       }
@@ -728,6 +731,8 @@ __global__ __launch_bounds__(256) void k_roll_fp32c(const Job* __restrict__ jobs
     float vimp = 0.0f;
     int k = 0, wl = -1;
     for (;;) {
+      // the step index is the same in every lane: keep it (and the branches on it) scalar
+      k = __builtin_amdgcn_readfirstlane(k);
       if (!__any(L.active)) break;
       if (!BATCH || k >= wl) wl = wave_lim<BATCH>(L.active, k, nd, nmax);
       // the command switches on at step nd: e = a - cmd jumps by -a_cmd.  Blocks
@@ -834,12 +839,260 @@ __global__ __launch_bounds__(256) void k_roll_fp32c(const Job* __restrict__ jobs
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP32 compensated form with a lead vehicle.  The clearance is integrated
+// directly, c' = c + dt (v_lead - v), as an in-block sum plus a Kahan pair,
+// so no two large positions are ever subtracted; both speeds are a float
+// base plus an in-block increment.  A lane's clearance after a step is read
+// after that step's flush (every 32 steps by index) in every path, and its
+// running minimum is the margin.  A crossing inside a block (minimum below
+// zero) is replayed from the block's start state; the rollout ends there.
+// ---------------------------------------------------------------------------
+struct Ld32 {
+  float vb, vi;  // lead speed: base + increment (read clamped at 0)
+  float pg;      // in-block clearance sum
+  Kahan32 G;     // clearance
+  float gmin;    // running minimum of the clearance after each step
+};
+
+__device__ inline float lead_speed(const Ld32& l) { return fmaxf(l.vb + l.vi, 0.0f); }
+__device__ inline float clearance(const Ld32& l) { return (l.G.hi - l.G.lo) + l.pg; }
+
+__device__ inline void flush32l(St32& s, Ld32& l) {
+  flush32(s, true);
+  const float t = l.vb + l.vi;
+  l.vi = l.vi - (t - l.vb);
+  l.vb = t;
+  l.G.add(l.pg);
+  l.pg = 0.0f;
+}
+
+// one step of ego and lead (the ego's form as in block32, speed always split)
+template <int FORM>
+__device__ inline void step32l(St32& s, Ld32& l, const L32& c, float tk, float al) {
+  const float v = s.vb + s.vi;
+  const float vl = lead_speed(l);
+  const float q = v * v;
+  float m;
+  if (FORM == FORM_G)
+    m = fmaxf(s.e + tk, c.alc);
+  else if (FORM == FORM_F)
+    m = s.e + tk;
+  else if (FORM == FORM_C)
+    m = c.alc;
+  else
+    m = c.tdm;
+  const float acc = fmaf(c.nkd, q, m);
+  s.p = fmaf(c.dt, v, s.p);
+  l.pg = fmaf(c.dt, vl - v, l.pg);
+  l.vi = fmaf(-c.dt, al, l.vi);
+  s.vi = fmaf(c.dt, acc, s.vi);
+  if (FORM == FORM_G || FORM == FORM_F) s.e = fmaf(c.nkt, s.e, s.e);
+}
+
+template <int FORM, int K>
+__device__ inline void block32l(St32& s, Ld32& l, const L32& c, float tk, float al,
+                                bool flush_end) {
+  float ghl = l.G.hi - l.G.lo;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    step32l<FORM>(s, l, c, tk, al);
+    if (j == K - 1 && flush_end) {
+      flush32l(s, l);
+      ghl = l.G.hi - l.G.lo;
+    }
+    l.gmin = fminf(l.gmin, ghl + l.pg);
+  }
+}
+
+struct Lane32L {
+  St32 s, sv;
+  Ld32 l, lv;
+  int sk;
+  bool active, pend, clamped, free_lane;
+};
+
+template <int B>
+__device__ inline void run_block32l(Lane32L& L, const L32& c, float al, int nd, int k, int wnd) {
+  L.sv = L.s;
+  L.lv = L.l;
+  L.sk = k;
+  const float tk = k >= nd ? c.tb : c.td;
+  const bool fl = (k + B) % FLUSH == 0;
+  if (k + B <= wnd) {
+    block32l<FORM_D, B>(L.s, L.l, c, tk, al, fl);
+  } else if (__all(!L.active || L.clamped)) {
+    block32l<FORM_C, B>(L.s, L.l, c, tk, al, fl);
+  } else if (__all(!L.active || L.free_lane)) {
+    block32l<FORM_F, B>(L.s, L.l, c, tk, al, fl);
+  } else {
+    block32l<FORM_G, B>(L.s, L.l, c, tk, al, fl);
+    L.clamped = L.clamped || (k + B > nd && L.s.e + c.tb <= c.alc);
+  }
+  if (L.active && L.l.gmin < 0.0f) {  // the lead was reached inside the block
+    L.pend = true;
+    L.active = false;
+  }
+}
+
+template <int K, bool BATCH>
+__global__ __launch_bounds__(256) void k_roll_fp32c_lead(const Job* __restrict__ jobs,
+                                                         const LeadJob* __restrict__ leads,
+                                                         const uint32_t* __restrict__ perm,
+                                                         int64_t n, Ctx ctx, double band_abs,
+                                                         double band_rel,
+                                                         unsigned long long* counter,
+                                                         int persistent) {
+  constexpr int KS = 4;
+  static_assert(FLUSH % K == 0 && K % KS == 0, "flush points must fall on block ends");
+  for (int pass = 0;; ++pass) {
+    const int64_t base = next_chunk(counter, persistent, pass, n);
+    if (base >= n) break;
+    const int64_t pos = base + (threadIdx.x & 63);
+    const bool valid = pos < n;
+    const uint32_t g = valid ? perm[pos] : 0u;
+    Job J;
+    if (valid) {
+      J = jobs[g];
+    } else {
+      J = Job{1.0, 0.0, 0.0, -1.0, 0.5, 1e30, 1.0, 0.0f, 0u};
+    }
+    const float al = valid ? static_cast<float>(leads[g].decel) : 0.0f;
+    const LaneScn sc = lane_scn<BATCH>(ctx, J);
+    const int nd = sc.nd, nmax = sc.nmax;
+    const int wnd = BATCH ? wave_min(valid ? nd : INT_MAX) : nd;
+    L32 c;
+    c.dt = static_cast<float>(sc.dt);
+    c.nkd = static_cast<float>(J.nkd);
+    c.nkt = static_cast<float>(-J.kt);
+    c.alc = static_cast<float>(J.alim - J.c);
+    c.tb = static_cast<float>(sc.a_cmd - J.c);
+    c.td = static_cast<float>(0.0 - J.c);
+    c.tdm = fmaxf(c.td, c.alc);
+    c.ejump = static_cast<float>(-sc.a_cmd);
+    c.thr = static_cast<float>(static_cast<double>(K) * sc.dt * J.dmax);
+    c.gapf = static_cast<float>(J.gap);
+    const float thr_s = static_cast<float>(static_cast<double>(KS) * sc.dt * J.dmax);
+    const double band = band_abs + band_rel * fabs(J.gap);
+    Lane32L L;
+    L.s.vb = static_cast<float>(J.v0);
+    L.s.vi = static_cast<float>(J.v0 - static_cast<double>(L.s.vb));
+    L.s.e = 0.0f;
+    L.s.p = 0.0f;
+    L.l.vb = L.s.vb;
+    L.l.vi = L.s.vi;
+    L.l.pg = 0.0f;
+    L.l.G.hi = c.gapf;
+    L.l.G.lo = static_cast<float>(static_cast<double>(c.gapf) - J.gap);
+    L.l.gmin = clearance(L.l);
+    L.sv = L.s;
+    L.lv = L.l;
+    L.sk = 0;
+    L.active = valid;
+    L.pend = L.clamped = false;
+    L.free_lane = J.alim < sc.a_cmd - 1e-6;
+    bool boundary = false, collided = false;
+    int end = 0, steps = 0;
+    double dist = 0.0;
+    float vimp = 0.0f;
+    float gprev = L.l.gmin;
+    float gm_end = L.l.gmin;  // running minimum of the clearance when the lane ended
+    int k = 0, wl = -1;
+    for (;;) {
+      k = __builtin_amdgcn_readfirstlane(k);
+      if (!__any(L.active)) break;
+      if (!BATCH || k >= wl) wl = wave_lim<BATCH>(L.active, k, nd, nmax);
+      if (k == nd) L.s.e += c.ejump;
+      const float v_now = L.s.vb + L.s.vi;
+      if (k % K == 0 && k + K <= wl && !__any(L.active && v_now <= c.thr)) {
+        run_block32l<K>(L, c, al, nd, k, wnd);
+        k += K;
+      } else if (k % KS == 0 && k + KS <= wl && !__any(L.active && v_now <= thr_s)) {
+        run_block32l<KS>(L, c, al, nd, k, wnd);
+        k += KS;
+      } else {
+        if (L.active) {
+          const float gp = clearance(L.l);
+          step32l<FORM_G>(L.s, L.l, c, k >= nd ? c.tb : c.td, al);
+          if ((k + 1) % FLUSH == 0) flush32l(L.s, L.l);
+          if (k >= nd) L.clamped = L.clamped || (L.s.e + c.tb <= c.alc);
+          const float gk = clearance(L.l);
+          L.l.gmin = fminf(L.l.gmin, gk);
+          const float v = L.s.vb + L.s.vi;
+          if (gk < 0.0f) {
+            L.active = false;
+            collided = true;
+            vimp = v - lead_speed(L.l);
+            end = AEB_END_IMPACT;
+            steps = k + 1;
+            dist = L.s.X.value(L.s.p);
+            boundary = (static_cast<double>(gp) < band) || (static_cast<double>(gk) > -band);
+          } else if (v <= 0.0f) {
+            L.active = false;
+            end = AEB_END_STOP;
+            steps = k + 1;
+            dist = L.s.X.value(L.s.p);
+          } else if (k + 1 == nmax) {
+            L.active = false;
+            end = AEB_END_HORIZON;
+            steps = k + 1;
+            dist = L.s.X.value(L.s.p);
+          }
+          if (!L.active) gm_end = L.l.gmin;
+        }
+        k += 1;
+      }
+    }
+    // replay the block in which each pending lane reached the lead: the same
+    // steps one at a time, with the clearance read after each (post-flush)
+    if (__any(L.pend)) {
+      St32 r = L.sv;
+      Ld32 rl = L.lv;
+      int kr = L.sk;
+      gprev = clearance(rl);
+      for (int it = 0; it < K; ++it) {
+        if (!__any(L.pend)) break;
+        if (L.pend) {
+          step32l<FORM_G>(r, rl, c, kr >= nd ? c.tb : c.td, al);
+          ++kr;
+          if (kr % FLUSH == 0) flush32l(r, rl);
+          const float gk = clearance(rl);
+          rl.gmin = fminf(rl.gmin, gk);
+          if (gk < 0.0f) {
+            L.pend = false;
+            collided = true;
+            vimp = (r.vb + r.vi) - lead_speed(rl);
+            end = AEB_END_IMPACT;
+            steps = kr;
+            dist = r.X.value(r.p);
+            boundary = (static_cast<double>(gprev) < band) || (static_cast<double>(gk) > -band);
+            gm_end = rl.gmin;
+          }
+          gprev = gk;
+        }
+      }
+    }
+    if (L.pend) vimp = __builtin_nanf("");  // unreachable; makes a broken replay visible
+    if (!collided) boundary = static_cast<double>(gm_end) < band;
+    if (valid) {
+      int64_t i;
+      const OutCols o = lane_out<BATCH>(ctx, J, g, i);
+      o.dist[i] = dist;
+      o.margin[i] = static_cast<double>(gm_end);
+      o.steps[i] = steps;
+      o.status[i] = static_cast<uint8_t>(end | (collided ? AEB_COLLIDED : 0) |
+                                         (boundary ? AEB_BOUNDARY : 0));
+      o.vimp[i] = collided ? vimp : 0.0f;
+    }
+  }
+}
+
 }  // namespace
 
 bool fast_path_applies(const aeb_scenario& s, int precision) {
   if (s.integrator != AEB_EULER) return false;
   if (precision == AEB_FP64) return !s.nofma;
-  return (precision == AEB_FP32C || precision == AEB_FP32C_FIXUP) && s.obstacle != AEB_OBS_LEAD;
+  return precision == AEB_FP32C || (precision == AEB_FP32C_FIXUP && s.obstacle != AEB_OBS_LEAD);
 }
 
 namespace {
@@ -982,7 +1235,16 @@ int integrate(const aeb_scenario& s0, int precision, const Bufs& b, int64_t n, c
   // of the boundary are flagged (and, in the fix-up mode, recomputed in FP64)
   const double band_abs = 1e-3, band_rel = 1e-5;
   timing_begin(st);
-  if (obs == AEB_OBS_STATIONARY)
+  if (obs == AEB_OBS_LEAD) {
+    if (t.k == 16)
+      hipLaunchKernelGGL((k_roll_fp32c_lead<16, BATCH>), dim3(sh.grid), dim3(sh.block), 0, st,
+                         b.jobs, b.leads, b.perm, n, ctx, band_abs, band_rel, b.counter,
+                         sh.persistent);
+    else
+      hipLaunchKernelGGL((k_roll_fp32c_lead<32, BATCH>), dim3(sh.grid), dim3(sh.block), 0, st,
+                         b.jobs, b.leads, b.perm, n, ctx, band_abs, band_rel, b.counter,
+                         sh.persistent);
+  } else if (obs == AEB_OBS_STATIONARY)
     go32k<AEB_OBS_STATIONARY, BATCH>(t.k, sh, b, n, ctx, band_abs, band_rel, fix, st);
   else
     go32k<AEB_OBS_NONE, BATCH>(t.k, sh, b, n, ctx, band_abs, band_rel, fix, st);

@@ -90,3 +90,21 @@ def test_batch_rejects_bad_batches(B):
         B.batch_rollout([W.single(10)], precision="fp32c_fixup")
     with pytest.raises(B.AebError):
         B.batch_rollout([W.single(10), dict(W.single(10), dt=-1.0)])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_batch_lead_mixed_horizons(B, orc, prec):
+    # lanes of near-equal predicted length but different horizons share
+    # wavefronts: a lane ending at its horizon while its neighbours go on must
+    # keep the margin it had when it ended
+    base = W.sweep(n=3000)[160]
+    scns = [dict(base, scenario_id=900 + j, horizon=h) for j, h in
+            enumerate((0.8, 0.85, 0.9, 3.0))]
+    outs = B.batch_rollout(scns, precision=prec)
+    for d, o in zip(scns, outs):
+        got, ref = to_np(o), orc.run(d)
+        if prec == "fp64":
+            check_fp64(got, ref)
+        else:
+            check_fp32c(got, ref, margin_abs=2e-3)
+        assert ((ref["status"] & 3) == 3).any()        # some lanes end at the horizon
