@@ -40,6 +40,23 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per launch of the integration kernel from the committed
+    counter summary, or None if the kernel source changed since."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "rollout_fp64_1M_hbm_traffic.md")
+    try:
+        txt = open(path).read()
+        src = re.search(r"kernel_source: (\S+)", txt).group(1)
+        sha = re.search(r"source_sha1: ([0-9a-f]+)", txt).group(1)
+        traffic = int(re.search(r"traffic_bytes_per_launch: (\d+)", txt).group(1))
+        now = hashlib.sha1(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+    except (OSError, AttributeError):
+        return None
+    return traffic if now == sha else None
+
+
 def time_steps(B, torch, d, params, precision, out, steps, warmup):
     """Warm up, then time `steps` steps of rollout + reduce.  Returns the wall
     time, per-step integration-kernel times (library HIP events around that
@@ -78,6 +95,45 @@ def cpu_baseline(d, budget_samples):
     return {"value": n / el, "unit": "rollouts/s", "cores": threads, "kind": "oracle",
             "sample": f"samples 0..{n - 1} of the same scenario, {threads} threads, "
                       f"{el:.2f} s wall"}
+
+
+def batch_leg(B, W, torch, reps=2):
+    """Batched launches: the 256-scenario lead-vehicle sweep (100,000 samples
+    each) and 1,000 scenarios of uneven size, horizon and step; parameters
+    drawn in-kernel; rollouts/s of the batched rollout call (events on the
+    stream), FP64 and FP32C, and the error of the FP32C P(collision)."""
+    import numpy as np
+    res = {}
+    for name, scns in (("sweep_256x100k_lead", W.sweep(n=100_000)),
+                       ("uneven_1000", W.uneven_batch(1000))):
+        total = sum(int(d["n_samples"]) for d in scns)
+        outs = [B.alloc_outputs(int(d["n_samples"])) for d in scns]
+        entry = {"scenarios": len(scns), "samples": total}
+        pcol = {}
+        for prec in ("fp64", "fp32c"):
+            B.batch_rollout(scns, precision=prec, outs=outs)
+            torch.cuda.synchronize()
+            ms = []
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                B.batch_rollout(scns, precision=prec, outs=outs)
+                e1.record()
+                torch.cuda.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            t = float(np.min(ms))
+            entry[prec] = {"ms": t, "rollouts_per_s": total / (t * 1e-3)}
+            pcol[prec] = np.array([float(((o["status"] & 4) != 0).double().mean().item())
+                                   for o in outs])
+            log(f"bench: batch {name} {prec}: {entry[prec]}")
+        entry["fp32c_max_abs_err_p_collision"] = float(np.max(np.abs(pcol["fp32c"] -
+                                                                     pcol["fp64"])))
+        entry["fp32c_speedup"] = entry["fp64"]["ms"] / entry["fp32c"]["ms"]
+        res[name] = entry
+        del outs
+        torch.cuda.empty_cache()
+    return res
 
 
 def serving_leg(B, W, precision, rates, duration, arena_gib=4):
@@ -138,6 +194,7 @@ def main():
     ap.add_argument("--n", type=int, default=1_048_576)
     ap.add_argument("--cpu-samples", type=int, default=262_144)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch leg")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="length of each serving stream (0: no serving leg)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
@@ -202,6 +259,11 @@ def main():
     achieved = flops64 / kavg64 / 1e12
     value = args.steps * n / wall64
 
+    batch = None
+    if not args.no_batch:
+        log("bench: batched launches")
+        batch = batch_leg(B, W, torch)
+
     serving = None
     if args.serve_seconds > 0:
         log("bench: serving streams")
@@ -235,7 +297,10 @@ def main():
         },
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+            "traffic": measured_traffic() if n == 1_048_576 else None,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+            "algorithmic_bytes_per_launch": 93 * n,
             "kernel": "k_roll_fp64 (block-structured explicit Euler, FP64)",
             "kernel_ms": kavg64 * 1e3, "flops_per_launch": flops64,
             "steps_per_launch": steps_total, "flops_per_step": EULER_FLOPS_PER_STEP,
@@ -258,6 +323,7 @@ def main():
             "collision_flags_equal_fp64_outside_band": flags_equal,
             "speedup_vs_fp64_kernel": kavg64 / kavg32,
         },
+        "batch": batch,
         "serving": serving,
         "plain_method_host": {"sampling_s": t_sample, "h2d_s": t_h2d,
                               "h2d_GBps": 11 * 8 * n / t_h2d / 1e9},

@@ -346,15 +346,18 @@ __device__ inline int64_t claim(unsigned long long* counter) {
   return static_cast<int64_t>((static_cast<unsigned long long>(hi) << 32) | lo);
 }
 
-// The next 64 sorted positions of a wavefront: claimed from the counter in a
-// persistent launch, else the wavefront's own slice of its workgroup (first
-// pass only).
+// The next 64 sorted positions of a wavefront.  First pass: the wavefront's
+// own slice of its workgroup's range.  Later passes of a persistent launch:
+// chunks claimed from the counter beyond the range the whole grid covered in
+// its first pass (so the launch does not start with every wavefront
+// contending for one atomic); a one-pass launch stops after the first.
 __device__ inline int64_t next_chunk(unsigned long long* counter, int persistent, int pass,
                                      int64_t n) {
-  if (persistent) return claim(counter);
-  if (pass > 0) return n;
-  return static_cast<int64_t>(blockIdx.x) * blockDim.x +
-         __builtin_amdgcn_readfirstlane(threadIdx.x & ~63u);
+  if (pass == 0)
+    return static_cast<int64_t>(blockIdx.x) * blockDim.x +
+           __builtin_amdgcn_readfirstlane(threadIdx.x & ~63u);
+  if (!persistent) return n;
+  return claim(counter) + static_cast<int64_t>(gridDim.x) * blockDim.x;
 }
 
 // Lane state and per-lane flags of the FP64 integration.
