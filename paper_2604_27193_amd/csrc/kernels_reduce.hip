@@ -129,6 +129,15 @@ __device__ inline unsigned long long block_exscan(unsigned long long v, unsigned
   return r;
 }
 
+// Reduction of one value per lane over a wavefront by an xor butterfly: with
+// a commutative op every lane ends with the same bits, in a fixed order.
+template <typename T, typename Op>
+__device__ inline T wave_reduce(T v, Op op) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o));
+  return v;
+}
+
 struct AddOp {
   template <typename T>
   __device__ T operator()(T a, T b) const { return a + b; }
@@ -145,10 +154,24 @@ __global__ void k_zero_u32(unsigned* p, long long n) {
   if (i < n) p[i] = 0u;
 }
 
+__device__ inline void combine(Partial& a, const Partial& b) {
+  a.ncol += b.ncol;
+  a.nstop += b.nstop;
+  a.nimp += b.nimp;
+  a.nhor += b.nhor;
+  a.nbnd += b.nbnd;
+  a.sum += b.sum;
+  a.dmin = b.dmin < a.dmin ? b.dmin : a.dmin;
+  a.dmax = b.dmax > a.dmax ? b.dmax : a.dmax;
+  a.msum += b.msum;
+  a.mmin = b.mmin < a.mmin ? b.mmin : a.mmin;
+  a.mmax = b.mmax > a.mmax ? b.mmax : a.mmax;
+  a.vmax = b.vmax > a.vmax ? b.vmax : a.vmax;
+}
+
 __global__ __launch_bounds__(RB) void k_pass1(OutCols o, long long n, long long chunk, double glo,
                                               double gstep, int ng, unsigned* ghist, Partial* part) {
-  __shared__ double shd[RB];
-  __shared__ long long shl[RB];
+  __shared__ Partial wp[RB / 64];
   __shared__ unsigned hist[AEB_MAX_GRID + 1];
   for (int j = threadIdx.x; j <= ng; j += RB) hist[j] = 0;
   __syncthreads();
@@ -187,21 +210,28 @@ __global__ __launch_bounds__(RB) void k_pass1(OutCols o, long long n, long long 
       atomicAdd(&hist[grid_rank(dc, glo, gstep, ng)], 1u);
     }
   }
+  // wavefront partials, then the block's waves combined in index order
   Partial p;
-  p.ncol = block_reduce<RB>(ncol, shl, AddOp());
-  p.nstop = block_reduce<RB>(nstop, shl, AddOp());
-  p.nimp = block_reduce<RB>(nimp, shl, AddOp());
-  p.nhor = block_reduce<RB>(nhor, shl, AddOp());
-  p.nbnd = block_reduce<RB>(nbnd, shl, AddOp());
-  p.sum = block_reduce<RB>(sum, shd, AddOp());
-  p.dmin = block_reduce<RB>(dmin, shd, MinOp());
-  p.dmax = block_reduce<RB>(dmax, shd, MaxOp());
-  p.msum = block_reduce<RB>(msum, shd, AddOp());
-  p.mmin = block_reduce<RB>(mmin, shd, MinOp());
-  p.mmax = block_reduce<RB>(mmax, shd, MaxOp());
-  p.vmax = static_cast<float>(block_reduce<RB>(static_cast<double>(vmax), shd, MaxOp()));
+  p.ncol = wave_reduce(ncol, AddOp());
+  p.nstop = wave_reduce(nstop, AddOp());
+  p.nimp = wave_reduce(nimp, AddOp());
+  p.nhor = wave_reduce(nhor, AddOp());
+  p.nbnd = wave_reduce(nbnd, AddOp());
+  p.sum = wave_reduce(sum, AddOp());
+  p.dmin = wave_reduce(dmin, MinOp());
+  p.dmax = wave_reduce(dmax, MaxOp());
+  p.msum = wave_reduce(msum, AddOp());
+  p.mmin = wave_reduce(mmin, MinOp());
+  p.mmax = wave_reduce(mmax, MaxOp());
+  p.vmax = static_cast<float>(wave_reduce(static_cast<double>(vmax), MaxOp()));
   p.pad = 0.0f;
-  if (threadIdx.x == 0) part[blockIdx.x] = p;
+  if ((threadIdx.x & 63) == 0) wp[threadIdx.x >> 6] = p;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Partial q = wp[0];
+    for (int w = 1; w < RB / 64; ++w) combine(q, wp[w]);
+    part[blockIdx.x] = q;
+  }
   if (ng >= 2) {
     for (int j = threadIdx.x; j <= ng; j += RB)
       if (hist[j]) atomicAdd(&ghist[j], hist[j]);
@@ -212,8 +242,7 @@ __global__ __launch_bounds__(RB) void k_pass1(OutCols o, long long n, long long 
 // t, t+FB, ... in order, then a fixed tree), the risk curve by a block scan.
 __global__ __launch_bounds__(FB) void k_fin1(const Partial* part, int nb, long long n, int ng,
                                              const unsigned* ghist, aeb_stats* st, Sel* sel) {
-  __shared__ double shd[FB];
-  __shared__ long long shl[FB];
+  __shared__ Partial wp[FB / 64];
   __shared__ unsigned long long shu[FB];
   long long ncol = 0, nstop = 0, nimp = 0, nhor = 0, nbnd = 0;
   double sum = 0.0, dmin = INFINITY, dmax = -INFINITY, msum = 0.0, mmin = INFINITY,
@@ -234,18 +263,37 @@ __global__ __launch_bounds__(FB) void k_fin1(const Partial* part, int nb, long l
     mmax = p.mmax > mmax ? p.mmax : mmax;
     vmax = p.vmax > vmax ? p.vmax : vmax;
   }
-  ncol = block_reduce<FB>(ncol, shl, AddOp());
-  nstop = block_reduce<FB>(nstop, shl, AddOp());
-  nimp = block_reduce<FB>(nimp, shl, AddOp());
-  nhor = block_reduce<FB>(nhor, shl, AddOp());
-  nbnd = block_reduce<FB>(nbnd, shl, AddOp());
-  sum = block_reduce<FB>(sum, shd, AddOp());
-  dmin = block_reduce<FB>(dmin, shd, MinOp());
-  dmax = block_reduce<FB>(dmax, shd, MaxOp());
-  msum = block_reduce<FB>(msum, shd, AddOp());
-  mmin = block_reduce<FB>(mmin, shd, MinOp());
-  mmax = block_reduce<FB>(mmax, shd, MaxOp());
-  vmax = block_reduce<FB>(vmax, shd, MaxOp());
+  {
+    Partial p;
+    p.ncol = wave_reduce(ncol, AddOp());
+    p.nstop = wave_reduce(nstop, AddOp());
+    p.nimp = wave_reduce(nimp, AddOp());
+    p.nhor = wave_reduce(nhor, AddOp());
+    p.nbnd = wave_reduce(nbnd, AddOp());
+    p.sum = wave_reduce(sum, AddOp());
+    p.dmin = wave_reduce(dmin, MinOp());
+    p.dmax = wave_reduce(dmax, MaxOp());
+    p.msum = wave_reduce(msum, AddOp());
+    p.mmin = wave_reduce(mmin, MinOp());
+    p.mmax = wave_reduce(mmax, MaxOp());
+    p.vmax = static_cast<float>(wave_reduce(vmax, MaxOp()));
+    if ((threadIdx.x & 63) == 0) wp[threadIdx.x >> 6] = p;
+    __syncthreads();
+    Partial q = wp[0];
+    for (int w = 1; w < FB / 64; ++w) combine(q, wp[w]);
+    ncol = q.ncol;
+    nstop = q.nstop;
+    nimp = q.nimp;
+    nhor = q.nhor;
+    nbnd = q.nbnd;
+    sum = q.sum;
+    dmin = q.dmin;
+    dmax = q.dmax;
+    msum = q.msum;
+    mmin = q.mmin;
+    mmax = q.mmax;
+    vmax = q.vmax;
+  }
   // risk curve: #{D > H0_j} = n - #{D with grid rank <= j}
   constexpr int PER = (AEB_MAX_GRID + FB - 1) / FB;
   unsigned long long loc = 0;
@@ -291,7 +339,7 @@ __global__ __launch_bounds__(FB) void k_fin1(const Partial* part, int nb, long l
 __global__ __launch_bounds__(RB) void k_pass2(OutCols o, long long n, long long chunk,
                                               const aeb_stats* st, const Sel* sel, int need_d,
                                               int need_m, unsigned* bhist, double* part) {
-  __shared__ double shd[RB];
+  __shared__ double shd[RB / 64];
   __shared__ unsigned h[2 * (NVB + 1)];
   for (int j = threadIdx.x; j < 2 * (NVB + 1); j += RB) h[j] = 0;
   __syncthreads();
@@ -311,21 +359,30 @@ __global__ __launch_bounds__(RB) void k_pass2(OutCols o, long long n, long long 
     if (need_d) atomicAdd(&h[value_bin(stop ? d : INFINITY, vmin0, sc0)], 1u);
     if (need_m) atomicAdd(&h[(NVB + 1) + value_bin(o.margin[i], vmin1, sc1)], 1u);
   }
-  ss = block_reduce<RB>(ss, shd, AddOp());
-  if (threadIdx.x == 0) part[blockIdx.x] = ss;
+  ss = wave_reduce(ss, AddOp());
+  if ((threadIdx.x & 63) == 0) shd[threadIdx.x >> 6] = ss;
   __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = shd[0];
+    for (int w = 1; w < RB / 64; ++w) t += shd[w];
+    part[blockIdx.x] = t;
+  }
   unsigned* out = bhist + static_cast<size_t>(blockIdx.x) * 2 * (NVB + 1);
   for (int j = threadIdx.x; j < 2 * (NVB + 1); j += RB) out[j] = h[j];
 }
 
-// bin totals of the block-private histograms: one thread per bin, adjacent
-// threads read adjacent bins of each block's histogram
+// Bin totals of the block-private histograms: a 2-D grid, each thread sums
+// BT_ROWS blocks' counts of one bin (adjacent threads, adjacent bins) and adds
+// them to the zeroed totals (integer adds: order-free).
+constexpr int BT_ROWS = 16;
 __global__ __launch_bounds__(256) void k_bin_totals(const unsigned* bhist, int nb, unsigned* btot) {
   const int j = blockIdx.x * 256 + threadIdx.x;
   if (j >= 2 * (NVB + 1)) return;
+  const int b0 = blockIdx.y * BT_ROWS;
+  const int b1 = b0 + BT_ROWS < nb ? b0 + BT_ROWS : nb;
   unsigned c = 0;
-  for (int b = 0; b < nb; ++b) c += bhist[static_cast<size_t>(b) * 2 * (NVB + 1) + j];
-  btot[j] = c;
+  for (int b = b0; b < b1; ++b) c += bhist[static_cast<size_t>(b) * 2 * (NVB + 1) + j];
+  if (c) atomicAdd(&btot[j], c);
 }
 
 // Block 0: the sd.  Block 1 + t: find the value bin holding target t's rank.
@@ -409,35 +466,90 @@ __global__ __launch_bounds__(RB) void k_collect(OutCols o, long long n, long lon
   }
 }
 
-// One block per target: sort the candidates in LDS, take the rank inside the bin.
+// One block per target: the element of rank r among the bin's candidates by
+// a most-significant-digit radix select in LDS, starting at the first byte
+// in which the candidates differ (they share the bin's leading bits).
 __global__ __launch_bounds__(RB) void k_pick(const Sel* sel, SelIn in,
                                              const unsigned long long* cand, aeb_stats* st) {
   __shared__ unsigned long long key[CAP];
+  __shared__ unsigned hist[256];
+  __shared__ unsigned long long wlo[RB / 64], whi[RB / 64];
+  __shared__ unsigned long long s_prefix;
+  __shared__ unsigned s_rank;
   const int t = blockIdx.x;
   if (t >= in.count || sel->bin[t] < 0) return;
   const unsigned m = sel->ccount[t] < CAP ? sel->ccount[t] : CAP;
-  unsigned p2 = 1;
-  while (p2 < m) p2 <<= 1;
-  for (unsigned j = threadIdx.x; j < p2; j += RB) key[j] = j < m ? cand[t * CAP + j] : ~0ull;
+  unsigned long long lo = ~0ull, hi = 0ull;
+  for (unsigned j = threadIdx.x; j < m; j += RB) {
+    const unsigned long long k = cand[t * CAP + j];
+    key[j] = k;
+    lo = k < lo ? k : lo;
+    hi = k > hi ? k : hi;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long a = __shfl_xor(lo, o), b = __shfl_xor(hi, o);
+    lo = a < lo ? a : lo;
+    hi = b > hi ? b : hi;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    wlo[threadIdx.x >> 6] = lo;
+    whi[threadIdx.x >> 6] = hi;
+  }
   __syncthreads();
-  for (unsigned size = 2; size <= p2; size <<= 1) {
-    for (unsigned stride = size >> 1; stride > 0; stride >>= 1) {
-      for (unsigned j = threadIdx.x; j < p2; j += RB) {
-        const unsigned partner = j ^ stride;
-        if (partner > j) {
-          const bool up = (j & size) == 0;
-          const unsigned long long a = key[j], b = key[partner];
-          if ((a > b) == up) {
-            key[j] = b;
-            key[partner] = a;
+  lo = wlo[0];
+  hi = whi[0];
+  for (int w = 1; w < RB / 64; ++w) {
+    lo = wlo[w] < lo ? wlo[w] : lo;
+    hi = whi[w] > hi ? whi[w] : hi;
+  }
+  const unsigned long long diff = lo ^ hi;
+  const int first = diff ? __clzll(static_cast<long long>(diff)) / 8 : 8;  // first differing byte
+  if (threadIdx.x == 0) {
+    s_prefix = first == 0 ? 0ull : (lo & (~0ull << (64 - 8 * first)));
+    s_rank = sel->rank_in_bin[t];
+  }
+  __syncthreads();
+  for (int pass = first; pass < 8; ++pass) {
+    const int shift = 56 - 8 * pass;
+    const unsigned long long mask = pass == 0 ? 0ull : (~0ull << (64 - 8 * pass));
+    const unsigned long long pre = s_prefix;
+    hist[threadIdx.x] = 0;  // RB == 256 bins
+    __syncthreads();
+    for (unsigned j = threadIdx.x; j < m; j += RB) {
+      const unsigned long long k = key[j];
+      if ((k & mask) == pre) atomicAdd(&hist[(k >> shift) & 255ull], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      // wave 0: digit whose cumulative count passes the rank (4 bins per lane)
+      const int l = threadIdx.x;
+      unsigned c[4], tot = 0;
+      for (int q = 0; q < 4; ++q) {
+        c[q] = hist[4 * l + q];
+        tot += c[q];
+      }
+      unsigned inc = tot;  // inclusive scan over lanes
+      for (int o = 1; o < 64; o <<= 1) {
+        const unsigned v = __shfl_up(inc, o);
+        if (l >= o) inc += v;
+      }
+      const unsigned r = s_rank;
+      unsigned before = inc - tot;
+      if (r >= before && r < inc) {
+        for (int q = 0; q < 4; ++q) {
+          if (r < before + c[q]) {
+            s_prefix = pre | (static_cast<unsigned long long>(4 * l + q) << shift);
+            s_rank = r - before;
+            break;
           }
+          before += c[q];
         }
       }
-      __syncthreads();
     }
+    __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double v = unordered(key[sel->rank_in_bin[t]]);
+    const double v = unordered(first == 8 ? lo : s_prefix);
     if (t < in.n_risk)
       st->headway[t] = v;
     else
@@ -512,9 +624,10 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 namespace {
 
-// Scratch layout of one reduction: stats, risk-grid histogram and selection
-// state first (zeroed by one launch), then the block partials, the selection
-// histograms, the candidates and the radix-select state.
+// Scratch layout of one reduction: stats, risk-grid histogram, selection
+// state and the selection bin totals first (zeroed by one launch), then the
+// block partials, the block selection histograms, the candidates and the
+// radix-select state.
 struct RLayout {
   long long chunk, chunk2;
   int nb, nb2, T;
@@ -533,11 +646,11 @@ RLayout layout(int64_t n, const aeb_reduce_req& req) {
   const int tc = L.T > 0 ? L.T : 1;
   L.off_rh = align256(sizeof(aeb_stats));
   L.off_sel = align256(L.off_rh + sizeof(unsigned) * (AEB_MAX_GRID + 1));
-  L.off_zero_end = align256(L.off_sel + sizeof(Sel));
+  L.off_bt = align256(L.off_sel + sizeof(Sel));
+  L.off_zero_end = align256(L.off_bt + sizeof(unsigned) * 2 * (NVB + 1));
   L.off_var = align256(L.off_zero_end + sizeof(Partial) * L.nb);
   L.off_bh = align256(L.off_var + sizeof(double) * (L.nb > L.nb2 ? L.nb : L.nb2));
-  L.off_bt = align256(L.off_bh + sizeof(unsigned) * 2 * (NVB + 1) * L.nb2);
-  L.off_cand = align256(L.off_bt + sizeof(unsigned) * 2 * (NVB + 1));
+  L.off_cand = align256(L.off_bh + sizeof(unsigned) * 2 * (NVB + 1) * L.nb2);
   L.off_ss = align256(L.off_cand + sizeof(unsigned long long) * tc * CAP);
   L.off_sh = align256(L.off_ss + sizeof(SelState));
   L.total = align256(L.off_sh + sizeof(unsigned) * tc * 256);
@@ -593,8 +706,9 @@ int reduce_enqueue(const OutCols& out, int64_t n, const aeb_reduce_req& req, voi
   hipLaunchKernelGGL(k_pass2, dim3(L.nb2), dim3(RB), 0, st, out, static_cast<long long>(n),
                      L.chunk2, dstats, sel, need_d ? 1 : 0, need_m ? 1 : 0, bhist, vpart);
   if (T > 0)
-    hipLaunchKernelGGL(k_bin_totals, dim3((2 * (NVB + 1) + 255) / 256), dim3(256), 0, st, bhist,
-                       L.nb2, btot);
+    hipLaunchKernelGGL(k_bin_totals,
+                       dim3((2 * (NVB + 1) + 255) / 256, (L.nb2 + BT_ROWS - 1) / BT_ROWS),
+                       dim3(256), 0, st, bhist, L.nb2, btot);
   hipLaunchKernelGGL(k_fin2, dim3(1 + T), dim3(FB), 0, st, vpart, L.nb2, dstats, sel, in, btot);
   if (T > 0) {
     hipLaunchKernelGGL(k_collect, dim3(L.nb), dim3(RB), 0, st, out, static_cast<long long>(n),
