@@ -596,10 +596,10 @@ __device__ inline void block32(St32& s, const L32& c, float tk) {
   }
 }
 
-// Every 32 steps (by step index, so the rounding of a lane never depends on
+// Every 64 steps (by step index, so the rounding of a lane never depends on
 // how its wavefront grouped the steps) the speed base absorbs its increment
 // and the position's block sum goes into the Kahan pair.
-constexpr int FLUSH = 32;
+constexpr int FLUSH = 64;
 
 __device__ inline void flush32(St32& s, bool split) {
   if (split) {
@@ -847,7 +847,7 @@ __global__ __launch_bounds__(256) void k_roll_fp32c(const Job* __restrict__ jobs
 // directly, c' = c + dt (v_lead - v), as an in-block sum plus a Kahan pair,
 // so no two large positions are ever subtracted; both speeds are a float
 // base plus an in-block increment.  A lane's clearance after a step is read
-// after that step's flush (every 32 steps by index) in every path, and its
+// after that step's flush (every 64 steps by index) in every path, and its
 // running minimum is the margin.  A crossing inside a block (minimum below
 // zero) is replayed from the block's start state; the rollout ends there.
 // ---------------------------------------------------------------------------
@@ -1204,6 +1204,9 @@ void go32k(int k, const Shape& sh, const Bufs& b, int64_t n, const Ctx& ctx, dou
   if (k == 16)
     hipLaunchKernelGGL((k_roll_fp32c<OBS, 16, BATCH>), dim3(sh.grid), dim3(sh.block), 0, st,
                        b.jobs, b.perm, n, ctx, band_abs, band_rel, fix, b.counter, sh.persistent);
+  else if (k == 64)
+    hipLaunchKernelGGL((k_roll_fp32c<OBS, 64, BATCH>), dim3(sh.grid), dim3(sh.block), 0, st,
+                       b.jobs, b.perm, n, ctx, band_abs, band_rel, fix, b.counter, sh.persistent);
   else
     hipLaunchKernelGGL((k_roll_fp32c<OBS, 32, BATCH>), dim3(sh.grid), dim3(sh.block), 0, st,
                        b.jobs, b.perm, n, ctx, band_abs, band_rel, fix, b.counter, sh.persistent);
@@ -1241,6 +1244,10 @@ int integrate(const aeb_scenario& s0, int precision, const Bufs& b, int64_t n, c
   if (obs == AEB_OBS_LEAD) {
     if (t.k == 16)
       hipLaunchKernelGGL((k_roll_fp32c_lead<16, BATCH>), dim3(sh.grid), dim3(sh.block), 0, st,
+                         b.jobs, b.leads, b.perm, n, ctx, band_abs, band_rel, b.counter,
+                         sh.persistent);
+    else if (t.k == 64)
+      hipLaunchKernelGGL((k_roll_fp32c_lead<64, BATCH>), dim3(sh.grid), dim3(sh.block), 0, st,
                          b.jobs, b.leads, b.perm, n, ctx, band_abs, band_rel, b.counter,
                          sh.persistent);
     else

@@ -6,7 +6,7 @@
 namespace aeb {
 
 struct TuneCfg {
-  int k;               // steps per unchecked block (FP64: 16, 32, 64; FP32C: 16, 32)
+  int k;               // steps per unchecked block (16, 32, 64)
   int block;           // threads per workgroup (64, 128, 256)
   int waves_per_simd;  // 0: one pass, one workgroup per `block` samples; else a persistent
                        // grid of this many wavefronts per SIMD claiming 64-sample chunks

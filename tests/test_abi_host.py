@@ -93,7 +93,7 @@ def test_tune_table_validation(B, tmp_path):
         with pytest.raises(B.AebError):
             B.tune_set("fp64", "stationary", *bad)
     with pytest.raises(B.AebError):
-        B.tune_set("fp32c", "none", 64, 256, 0)      # FP32 blocks must divide its flush period
+        B.tune_set("fp32c", "none", 128, 256, 0)     # blocks must divide the FP32 flush period
     B.tune_set("fp64", "stationary", *keep)
 
 
@@ -109,7 +109,7 @@ def test_tune_cache_load(B, tmp_path):
     assert B.tune_get("fp32c", "none") == (16, 128, 0)
     bad = tmp_path / "bad.json"
     bad.write_text('{"entries": [{"precision": 0, "obstacle": 0, "k": 16, "block": 64, '
-                   '"waves_per_simd": 0}, {"precision": 1, "obstacle": 0, "k": 64, "block": 64, '
+                   '"waves_per_simd": 0}, {"precision": 1, "obstacle": 0, "k": 48, "block": 64, '
                    '"waves_per_simd": 0}]}')
     before = B.tune_get("fp64", "none")
     with pytest.raises(B.AebError):

@@ -33,8 +33,6 @@ def test_results_do_not_depend_on_shape(B, prec, obs):
     try:
         ref = to_np(B.rollout(d, precision=prec))
         for k, blk, w in SHAPES:
-            if prec == "fp32c" and k == 64:
-                continue
             B.tune_set(prec, obs, k, blk, w)
             got = to_np(B.rollout(d, precision=prec))
             for c in ref:
