@@ -146,7 +146,7 @@ def batch_leg(B, W, torch, reps=2):
         total = sum(int(d["n_samples"]) for d in scns)
         outs = [B.alloc_outputs(int(d["n_samples"])) for d in scns]
         entry = {"scenarios": len(scns), "samples": total}
-        pcol = {}
+        pcol, p99 = {}, {}
         for prec in ("fp64", "fp32c"):
             B.batch_rollout(scns, precision=prec, outs=outs)
             torch.cuda.synchronize()
@@ -163,9 +163,12 @@ def batch_leg(B, W, torch, reps=2):
             entry[prec] = {"ms": t, "rollouts_per_s": total / (t * 1e-3)}
             pcol[prec] = np.array([float(((o["status"] & 4) != 0).double().mean().item())
                                    for o in outs])
+            p99[prec] = np.array([float(torch.quantile(o["dist"], 0.99).item()) for o in outs])
             log(f"bench: batch {name} {prec}: {entry[prec]}")
         entry["fp32c_max_abs_err_p_collision"] = float(np.max(np.abs(pcol["fp32c"] -
                                                                      pcol["fp64"])))
+        entry["fp32c_max_rel_err_p99_dist"] = float(np.max(np.abs(p99["fp32c"] - p99["fp64"]) /
+                                                           np.abs(p99["fp64"])))
         entry["fp32c_speedup"] = entry["fp64"]["ms"] / entry["fp32c"]["ms"]
         res[name] = entry
         del outs

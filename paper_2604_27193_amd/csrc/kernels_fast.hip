@@ -766,7 +766,7 @@ __global__ __launch_bounds__(256) void k_roll_fp32c(const Job* __restrict__ jobs
               steps = k + 1;
               dist = L.s.X.value(L.s.p);
               const double step_len = static_cast<double>(c.dt) * static_cast<double>(vb);
-              boundary = (dist - J.gap < band) || (J.gap - (dist - step_len) < band);
+              boundary = fabs(dist - J.gap) < band || fabs(J.gap - (dist - step_len)) < band;
             }
           }
           if (L.active) {
@@ -809,7 +809,7 @@ __global__ __launch_bounds__(256) void k_roll_fp32c(const Job* __restrict__ jobs
               steps = kr;
               dist = r.X.value(r.p);
               const double step_len = static_cast<double>(c.dt) * static_cast<double>(vb);
-              boundary = (dist - J.gap < band) || (J.gap - (dist - step_len) < band);
+              boundary = fabs(dist - J.gap) < band || fabs(J.gap - (dist - step_len)) < band;
             }
           }
         }
@@ -917,9 +917,12 @@ struct Lane32L {
 
 template <int B>
 __device__ inline void run_block32l(Lane32L& L, const L32& c, float al, int nd, int k, int wnd) {
-  L.sv = L.s;
-  L.lv = L.l;
-  L.sk = k;
+  // a lane that has ended keeps the start state of the block it ended in
+  if (L.active) {
+    L.sv = L.s;
+    L.lv = L.l;
+    L.sk = k;
+  }
   const float tk = k >= nd ? c.tb : c.td;
   const bool fl = (k + B) % FLUSH == 0;
   if (k + B <= wnd) {
@@ -1029,7 +1032,7 @@ __global__ __launch_bounds__(256) void k_roll_fp32c_lead(const Job* __restrict__
             end = AEB_END_IMPACT;
             steps = k + 1;
             dist = L.s.X.value(L.s.p);
-            boundary = (static_cast<double>(gp) < band) || (static_cast<double>(gk) > -band);
+            boundary = fabs(static_cast<double>(gp)) < band || fabs(static_cast<double>(gk)) < band;
           } else if (v <= 0.0f) {
             L.active = false;
             end = AEB_END_STOP;
@@ -1068,7 +1071,7 @@ __global__ __launch_bounds__(256) void k_roll_fp32c_lead(const Job* __restrict__
             end = AEB_END_IMPACT;
             steps = kr;
             dist = r.X.value(r.p);
-            boundary = (static_cast<double>(gprev) < band) || (static_cast<double>(gk) > -band);
+            boundary = fabs(static_cast<double>(gprev)) < band || fabs(static_cast<double>(gk)) < band;
             gm_end = rl.gmin;
           }
           gprev = gk;

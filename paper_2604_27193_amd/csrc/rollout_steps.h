@@ -292,7 +292,7 @@ __device__ inline Result euler_fp32c(const Lane& L, double dt, double a_cmd, int
         collided = true;
         vimp = vc - vlc;
         end = AEB_END_IMPACT;
-        boundary = (gprev < bandf) || (g > -bandf);
+        boundary = fabsf(gprev) < bandf || fabsf(g) < bandf;
         break;
       }
       gprev = g;
@@ -304,7 +304,7 @@ __device__ inline Result euler_fp32c(const Lane& L, double dt, double a_cmd, int
           end = AEB_END_IMPACT;
           // the crossing step is in doubt if either side of it is within the band
           const double xe = X.value(p);
-          boundary = (xe - L.gap < band) || (L.gap - (xe - static_cast<double>(dtf * vb)) < band);
+          boundary = fabs(xe - L.gap) < band || fabs(L.gap - (xe - static_cast<double>(dtf * vb))) < band;
           break;
         }
       }

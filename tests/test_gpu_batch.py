@@ -108,3 +108,60 @@ def test_batch_lead_mixed_horizons(B, orc, prec):
         else:
             check_fp32c(got, ref, margin_abs=2e-3)
         assert ((ref["status"] & 3) == 3).any()        # some lanes end at the horizon
+
+
+def _subset_stats(status, dist):
+    col = (status & 4) != 0
+    return col.mean(), np.percentile(dist, 99)
+
+
+def test_sweep_full_size_subset(B, orc):
+    """The 256-scenario lead-vehicle sweep at 100,000 samples each in one
+    launch: on the first 1,000 samples of every scenario, FP64 equals the
+    reference and FP32C's per-scenario P(collision) and p99 distance are
+    within the stated tolerance of it."""
+    import torch
+    scns = W.sweep(n=100_000)
+    got = {}
+    for prec in ("fp64", "fp32c"):
+        outs = B.batch_rollout(scns, precision=prec)
+        torch.cuda.synchronize()
+        got[prec] = [{k: v[:1000].cpu().numpy() for k, v in o.items()} for o in outs]
+        del outs
+        torch.cuda.empty_cache()
+    worst_p, worst_q = 0.0, 0.0
+    threads = orc.host_threads()
+    for j, d in enumerate(scns):
+        ref = orc.run(d, first=0, count=1000, threads=threads)
+        check_fp64(got["fp64"][j], ref)
+        g32 = got["fp32c"][j]
+        check_fp32c(g32, ref, margin_abs=2e-3)
+        p_ref, q_ref = _subset_stats(ref["status"], ref["dist"])
+        p_32, q_32 = _subset_stats(g32["status"], g32["dist"])
+        nb = int(((g32["status"] & 8) != 0).sum())
+        assert abs(p_32 - p_ref) <= nb / 1000.0 + 1e-12, j
+        # nb boundary samples may end differently (at the lead or not), which
+        # moves an order statistic by at most nb ranks (unbounded past the ends)
+        srt = np.sort(ref["dist"])
+        lo = srt[989 - nb] * (1 - 1e-4) if 989 - nb >= 0 else -np.inf
+        hi = srt[990 + nb] * (1 + 1e-4) if 990 + nb <= 999 else np.inf
+        assert lo <= q_32 <= hi, (j, nb, q_32, q_ref)
+        worst_p, worst_q = max(worst_p, abs(p_32 - p_ref)), max(worst_q, abs(q_32 - q_ref) / q_ref)
+    print(f"sweep subset: max |dP| {worst_p:.2e}, max rel p99 error {worst_q:.2e}")
+
+
+def test_uneven_full_size_sampled(B, orc):
+    """The 1,000-scenario uneven batch at full size (about 1.4e8 samples) in
+    one launch: the first and last sample of every scenario against the
+    reference."""
+    import torch
+    scns = W.uneven_batch(1000)
+    outs = B.batch_rollout(scns)
+    torch.cuda.synchronize()
+    for d, o in zip(scns, outs):
+        n = int(d["n_samples"])
+        for i in (0, n - 1):
+            ref = orc.run(d, first=i, count=1)
+            assert int(o["status"][i].item()) == int(ref["status"][0])
+            assert int(o["steps"][i].item()) == int(ref["steps"][0])
+            assert abs(float(o["dist"][i].item()) - ref["dist"][0]) <= 1e-12 * abs(ref["dist"][0])

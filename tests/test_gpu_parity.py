@@ -192,6 +192,10 @@ def check_fp32c(got, ref, fixup=False, margin_abs=None):
     as within the boundary band (none of which remain after the FP64 fix-up);
     optionally the margin within margin_abs metres."""
     bnd = (got["status"] & B_BOUNDARY) != 0
+    # a flagged sample lies at the boundary: its reference clearance (margin)
+    # is within a step's travel of zero, and its own margin agrees with it
+    assert np.all(np.abs(ref["margin"][bnd]) <= 0.1), ref["margin"][bnd]
+    assert np.all(np.abs(got["margin"][bnd] - ref["margin"][bnd]) <= 0.1)
     if margin_abs is not None:
         ok_m = ~bnd
         assert np.all(np.abs(got["margin"] - ref["margin"])[ok_m] <= margin_abs)
