@@ -946,7 +946,7 @@ __global__ __launch_bounds__(256) void k_roll_fp32c_lead(const Job* __restrict__
                                                          const LeadJob* __restrict__ leads,
                                                          const uint32_t* __restrict__ perm,
                                                          int64_t n, Ctx ctx, double band_abs,
-                                                         double band_rel,
+                                                         double band_rel, uint32_t* fix,
                                                          unsigned long long* counter,
                                                          int persistent) {
   constexpr int KS = 4;
@@ -1089,6 +1089,10 @@ __global__ __launch_bounds__(256) void k_roll_fp32c_lead(const Job* __restrict__
       o.status[i] = static_cast<uint8_t>(end | (collided ? AEB_COLLIDED : 0) |
                                          (boundary ? AEB_BOUNDARY : 0));
       o.vimp[i] = collided ? vimp : 0.0f;
+      if (boundary && fix) {
+        const uint32_t slot = atomicAdd(fix, 1u);
+        fix[1 + slot] = g;
+      }
     }
   }
 }
@@ -1098,7 +1102,7 @@ __global__ __launch_bounds__(256) void k_roll_fp32c_lead(const Job* __restrict__
 bool fast_path_applies(const aeb_scenario& s, int precision) {
   if (s.integrator != AEB_EULER) return false;
   if (precision == AEB_FP64) return !s.nofma;
-  return precision == AEB_FP32C || (precision == AEB_FP32C_FIXUP && s.obstacle != AEB_OBS_LEAD);
+  return precision == AEB_FP32C || precision == AEB_FP32C_FIXUP;
 }
 
 namespace {
@@ -1247,15 +1251,15 @@ int integrate(const aeb_scenario& s0, int precision, const Bufs& b, int64_t n, c
   if (obs == AEB_OBS_LEAD) {
     if (t.k == 16)
       hipLaunchKernelGGL((k_roll_fp32c_lead<16, BATCH>), dim3(sh.grid), dim3(sh.block), 0, st,
-                         b.jobs, b.leads, b.perm, n, ctx, band_abs, band_rel, b.counter,
+                         b.jobs, b.leads, b.perm, n, ctx, band_abs, band_rel, fix, b.counter,
                          sh.persistent);
     else if (t.k == 64)
       hipLaunchKernelGGL((k_roll_fp32c_lead<64, BATCH>), dim3(sh.grid), dim3(sh.block), 0, st,
-                         b.jobs, b.leads, b.perm, n, ctx, band_abs, band_rel, b.counter,
+                         b.jobs, b.leads, b.perm, n, ctx, band_abs, band_rel, fix, b.counter,
                          sh.persistent);
     else
       hipLaunchKernelGGL((k_roll_fp32c_lead<32, BATCH>), dim3(sh.grid), dim3(sh.block), 0, st,
-                         b.jobs, b.leads, b.perm, n, ctx, band_abs, band_rel, b.counter,
+                         b.jobs, b.leads, b.perm, n, ctx, band_abs, band_rel, fix, b.counter,
                          sh.persistent);
   } else if (obs == AEB_OBS_STATIONARY)
     go32k<AEB_OBS_STATIONARY, BATCH>(t.k, sh, b, n, ctx, band_abs, band_rel, fix, st);

@@ -62,28 +62,6 @@ __global__ __launch_bounds__(256) void k_rollout_fp64(aeb_scenario s, ParamSrc s
   store(out, i, r);
 }
 
-// FP32 compensated rollout; samples whose outcome single precision cannot
-// decide are appended to `fix` (count at fix[0], indices after it).
-template <int OBS, bool DEVRNG>
-__global__ __launch_bounds__(256) void k_rollout_fp32c(aeb_scenario s, ParamSrc src, OutCols out,
-                                                       int64_t n, int64_t nd, int64_t nmax,
-                                                       double band_abs, double band_rel, uint32_t* fix) {
-  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  Lane L = load_lane<DEVRNG>(s, src, i);
-  bool boundary = false;
-  const double band = band_abs + band_rel * fabs(L.gap);
-  Result r = euler_fp32c<OBS>(L, s.dt, s.a_cmd, nd, nmax, s.impact_exit, band, boundary);
-  store(out, i, r);
-  if (boundary) {
-    if (fix) {
-      uint32_t slot = atomicAdd(fix, 1u);
-      fix[1 + slot] = static_cast<uint32_t>(i);
-    }
-    out.status[i] = static_cast<uint8_t>(r.status | AEB_BOUNDARY);
-  }
-}
-
 // FP64 recomputation of the samples listed in fix[1 .. fix[0]]; clears the
 // boundary bit
 template <int OBS, bool DEVRNG>
@@ -96,11 +74,6 @@ __global__ __launch_bounds__(256) void k_fixup_fp64(aeb_scenario s, ParamSrc src
     Result r = euler_fp64<OBS, false>(L, s.dt, s.a_cmd, nd, nmax, s.impact_exit);
     store(out, i, r);
   }
-}
-
-__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
-  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -117,29 +90,6 @@ static void go_fp64(const aeb_scenario& s, const ParamSrc* src, const OutCols& o
   else
     hipLaunchKernelGGL((k_rollout_fp64<INTEG, OBS, NOFMA, true>), grid, block, 0, st, s, p, out, n,
                        nd, nmax);
-}
-
-template <int OBS>
-static int go_fp32c(const aeb_scenario& s, const ParamSrc* src, const OutCols& out, int64_t n,
-                    int64_t nd, int64_t nmax, bool fixup, hipStream_t st) {
-  uint32_t* fix = static_cast<uint32_t*>(scratch_fix(sizeof(uint32_t) * (n + 1), st));
-  if (!fix) return AEB_ENOMEM;
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, fix, int64_t(1), 0u);
-  dim3 grid(static_cast<unsigned>((n + 255) / 256)), block(256);
-  ParamSrc p = src ? *src : ParamSrc{};
-  // single-precision distance and clearance errors stay below ~1e-4 m; outcomes
-  // within 1 mm (+1e-5 of the gap) of the boundary are recomputed in FP64
-  const double band_abs = 1e-3, band_rel = 1e-5;
-  timing_begin(st);
-  if (src)
-    hipLaunchKernelGGL((k_rollout_fp32c<OBS, false>), grid, block, 0, st, s, p, out, n, nd, nmax,
-                       band_abs, band_rel, fixup ? fix : nullptr);
-  else
-    hipLaunchKernelGGL((k_rollout_fp32c<OBS, true>), grid, block, 0, st, s, p, out, n, nd, nmax,
-                       band_abs, band_rel, fixup ? fix : nullptr);
-  timing_end(st);
-  if (fixup) return launch_fixup(s, src, out, fix, st);
-  return AEB_OK;
 }
 
 template <int OBS>
@@ -166,8 +116,8 @@ int launch_fixup(const aeb_scenario& s, const ParamSrc* src, const OutCols& out,
   return AEB_OK;
 }
 
-// Batches the block-structured path cannot take (RK4, the unfused Euler form,
-// FP32 with a lead vehicle) run scenario by scenario.
+// Batches the block-structured path cannot take (RK4, the unfused Euler form)
+// run scenario by scenario.
 int launch_batch(const aeb_scenario* scns, int n_scn, int precision, const OutCols* outs,
                  hipStream_t st) {
   if (fast_path_applies(scns[0], precision) && precision != AEB_FP32C_FIXUP)
@@ -184,16 +134,8 @@ int launch_rollout(const aeb_scenario& s, const ParamSrc* src, int precision, co
   const int64_t nd = dead_steps(s), nmax = horizon_steps(s);
   if (fast_path_applies(s, precision)) return launch_rollout_fast(s, src, precision, out, n, st);
   if (precision == AEB_FP32C || precision == AEB_FP32C_FIXUP) {
-    if (s.integrator != AEB_EULER)
-      return fail(AEB_EINVAL, "the FP32 compensated form is available for the Euler integrator");
-    const bool fixup = precision == AEB_FP32C_FIXUP;
-    int rc = AEB_OK;
-    switch (s.obstacle) {
-      case AEB_OBS_NONE: rc = go_fp32c<AEB_OBS_NONE>(s, src, out, n, nd, nmax, fixup, st); break;
-      case AEB_OBS_STATIONARY: rc = go_fp32c<AEB_OBS_STATIONARY>(s, src, out, n, nd, nmax, fixup, st); break;
-      default: rc = go_fp32c<AEB_OBS_LEAD>(s, src, out, n, nd, nmax, fixup, st); break;
-    }
-    if (rc != AEB_OK) return rc;
+    // every Euler case takes the block-structured path
+    return fail(AEB_EINVAL, "the FP32 compensated form is available for the Euler integrator");
   } else if (s.integrator == AEB_RK4) {
     timing_begin(st);
     if (s.obstacle == AEB_OBS_NONE)

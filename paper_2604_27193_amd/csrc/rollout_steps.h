@@ -3,9 +3,10 @@
 // after every step, impact (strict x > gap + x_lead), then stop (v <= 0),
 // then horizon.
 //
-// FP64 forms are the library's exact path: explicit Euler with four fused
-// multiply-adds (or none when NOFMA), RK4 without fused operations.  The FP32
-// form is the compensated served variant.
+// FP64 forms: explicit Euler with four fused multiply-adds (or none when
+// NOFMA), RK4 without fused operations.  These checked per-step forms serve
+// RK4, the unfused Euler form and the FP64 recomputation of FP32 boundary
+// samples; the explicit-Euler throughput path is kernels_fast.hip.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -184,22 +185,8 @@ __device__ inline Result rk4_fp64(const Lane& L, double dt, double a_cmd, int64_
   return r;
 }
 
-// ---------------------------------------------------------------------------
-// FP32 compensated Euler.  The same model rewritten for single precision:
-//   * the actuator is carried as its deviation from the command, e = a - cmd,
-//     which decays as e' = fma(-dt/tau, e, e) (the rate keeps the precision of
-//     dt/tau; a product with 1 - dt/tau would not);
-//   * the brake term with grade and rolling folded in is
-//     max(e + (cmd - c), alim - c), so acc = fma(-kd, v v, that);
-//   * each speed is a float base plus a small in-block increment; the base
-//     absorbs the increment every KB steps with an exact two-sum, so rounding
-//     never accumulates at the scale of the speed itself;
-//   * positions are summed in blocks of KB increments dt*v, each block sum
-//     added to a Kahan pair; the clearance to a lead vehicle likewise.
-// Distances, the collision decision and the margin are finished in FP64.
-// `boundary` reports an outcome that single precision cannot decide; the
-// caller recomputes such samples in FP64.
-// ---------------------------------------------------------------------------
+// Kahan-compensated FP32 sum (the FP32 compensated form of kernels_fast.hip
+// keeps its distance and lead clearance in these).
 struct Kahan32 {
   float hi = 0.0f, lo = 0.0f;
   __device__ inline void add(float y_in) {
@@ -212,136 +199,5 @@ struct Kahan32 {
     return (static_cast<double>(hi) - static_cast<double>(lo)) + static_cast<double>(partial);
   }
 };
-
-// base + increment with an exact carry (|base| >= |increment| assumed)
-struct Split32 {
-  float base, inc;
-  __device__ inline void carry() {
-    float t = base + inc;
-    inc = inc - (t - base);
-    base = t;
-  }
-};
-
-__device__ inline Split32 split_of(double v) {
-  Split32 s;
-  s.base = static_cast<float>(v);
-  s.inc = static_cast<float>(v - static_cast<double>(s.base));
-  return s;
-}
-
-template <int OBS>
-__device__ inline Result euler_fp32c(const Lane& L, double dt, double a_cmd, int64_t nd,
-                                     int64_t nmax, int impact_exit, double band, bool& boundary) {
-  constexpr int KB = 32;
-  const double kt = dt / L.tau;
-  const float dtf = static_cast<float>(dt);
-  const float nkd = static_cast<float>(-L.k.kd);
-  const float nkt = static_cast<float>(-kt);
-  const float alc = static_cast<float>(L.k.alim - L.k.c);
-  const float t_dead = static_cast<float>(0.0 - L.k.c);    // cmd - c before the command
-  const float t_brake = static_cast<float>(a_cmd - L.k.c);  // cmd - c after it
-  const float e_jump = static_cast<float>(-a_cmd);          // e = a - cmd jumps when cmd does
-  const float gapf = static_cast<float>(L.gap);
-  const float al = static_cast<float>(L.lead);
-  const float bandf = static_cast<float>(band);
-  Split32 V = split_of(L.v0), VL = split_of(L.v0);
-  float vc = V.base + V.inc, vlc = vc;
-  float e = 0.0f;
-  float p = 0.0f, pg = 0.0f;
-  Kahan32 X, G;
-  G.hi = gapf;
-  G.lo = static_cast<float>(static_cast<double>(gapf) - L.gap);
-  float gmin = gapf, gprev = gapf;
-  bool collided = false;
-  float vimp = 0.0f;
-  int end = 0;
-  int64_t step = 0;
-  boundary = false;
-  for (;;) {
-    if (step == nd) e += e_jump;
-    const float tc = step >= nd ? t_brake : t_dead;
-    const float q = vc * vc;
-    const float m = fmaxf(e + tc, alc);
-    const float acc = fmaf(nkd, q, m);
-    const float vb = vc;
-    p = fmaf(dtf, vc, p);
-    if (OBS == AEB_OBS_LEAD) {
-      pg = fmaf(dtf, vlc - vc, pg);
-      VL.inc = fmaf(-dtf, al, VL.inc);
-    }
-    V.inc = fmaf(dtf, acc, V.inc);
-    e = fmaf(nkt, e, e);
-    ++step;
-    if ((step & (KB - 1)) == 0) {
-      X.add(p);
-      p = 0.0f;
-      V.carry();
-      if (OBS == AEB_OBS_LEAD) {
-        G.add(pg);
-        pg = 0.0f;
-        VL.carry();
-      }
-    }
-    vc = V.base + V.inc;
-    if (OBS == AEB_OBS_LEAD) {
-      vlc = fmaxf(VL.base + VL.inc, 0.0f);
-      const float g = (G.hi - G.lo) + pg;
-      gmin = fminf(gmin, g);
-      if (g < 0.0f) {
-        collided = true;
-        vimp = vc - vlc;
-        end = AEB_END_IMPACT;
-        boundary = fabsf(gprev) < bandf || fabsf(g) < bandf;
-        break;
-      }
-      gprev = g;
-    } else if (OBS == AEB_OBS_STATIONARY && !collided) {
-      if ((X.hi - X.lo) + p > gapf) {
-        collided = true;
-        vimp = vc;
-        if (impact_exit) {
-          end = AEB_END_IMPACT;
-          // the crossing step is in doubt if either side of it is within the band
-          const double xe = X.value(p);
-          boundary = fabs(xe - L.gap) < band || fabs(L.gap - (xe - static_cast<double>(dtf * vb))) < band;
-          break;
-        }
-      }
-    }
-    if (vc <= 0.0f) {
-      end = AEB_END_STOP;
-      break;
-    }
-    if (step == nmax) {
-      end = AEB_END_HORIZON;
-      break;
-    }
-  }
-  Result res;
-  res.dist = X.value(p);
-  res.steps = static_cast<int32_t>(step);
-  if (OBS == AEB_OBS_LEAD) {
-    res.margin = static_cast<double>(gmin);
-    if (!collided) boundary = boundary || (gmin < bandf);
-  } else {
-    const double mg = L.gap - res.dist;
-    res.margin = mg < L.gap ? mg : L.gap;
-    if (OBS == AEB_OBS_STATIONARY) {
-      // the flag is decided in FP64 on the compensated distance
-      const double clear = L.gap - res.dist;
-      if (impact_exit) {
-        if (!collided) boundary = clear < band;
-      } else {
-        collided = res.dist > L.gap;
-        boundary = fabs(clear) < band;
-        if (!collided) vimp = 0.0f;
-      }
-    }
-  }
-  res.status = static_cast<uint8_t>(end | (collided ? AEB_COLLIDED : 0));
-  res.vimp = collided ? vimp : 0.0f;
-  return res;
-}
 
 }  // namespace aeb
