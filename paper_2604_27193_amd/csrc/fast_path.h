@@ -15,7 +15,7 @@ struct Job {
   double nkd;     // -kd
   double c;       // grade plus rolling resistance
   double alim;    // friction limit (negative)
-  double kt;      // dt / tau
+  double kt;      // dt / tau (explicit Euler) or 1 / tau (RK4)
   double gap;     // initial gap to the obstacle
   double dmax;    // bound on |dv/dt| over the whole rollout
   float pred;     // predicted number of steps

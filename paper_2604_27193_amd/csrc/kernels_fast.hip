@@ -127,7 +127,7 @@ __global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job
     J.nkd = -k.kd;
     J.c = k.c;
     J.alim = k.alim;
-    J.kt = s.dt / tau;
+    J.kt = s.integrator == AEB_RK4 ? 1.0 / tau : s.dt / tau;  // Euler: dt/tau; RK4: 1/tau
     J.gap = gap;
     // |acc| <= min(|a_cmd|, |alim|) + kd vmax^2 + |c|, with vmax the largest
     // speed the sample can reach (only a downhill pull can raise it)
@@ -231,8 +231,57 @@ struct Ld64 {
   double xl, vl, gmin;
 };
 
-template <int FORM, int K, bool LEAD>
+// ---------------------------------------------------------------------------
+// Classical RK4 (Sec. IV-D) in the same forms, no fused operations, the
+// command held over the step.  Stage derivative of the speed:
+//   (max(a, alim) - kd v v) - c, written (m + (-kd) (v v)) - c (the same bits);
+// the position's stages are the stage speeds.  Job.kt holds 1/tau here.
+// ---------------------------------------------------------------------------
+template <int FORM>
+__device__ inline double rk_dv(const Job& J, double v, double a) {
+  double m;
+  if (FORM == FORM_G)
+    m = fmax(a, J.alim);
+  else if (FORM == FORM_F)
+    m = a;
+  else if (FORM == FORM_C)
+    m = J.alim;
+  else
+    m = 0.0;  // dead time: a = 0 exactly and max(0, alim) = 0
+  return (m + J.nkd * (v * v)) - J.c;
+}
+
+template <int FORM>
+__device__ inline void rk4_step(St64& s, const Job& J, double dt, double h2, double h6,
+                                double cmd) {
+  constexpr bool ACT = FORM == FORM_G || FORM == FORM_F;  // the actuator is read
+  const double v1 = s.v, a1 = s.a;
+  const double k1v = rk_dv<FORM>(J, v1, a1);
+  const double k1a = ACT ? (cmd - a1) * J.kt : 0.0;
+  const double v2 = v1 + h2 * k1v, a2 = ACT ? a1 + h2 * k1a : a1;
+  const double k2v = rk_dv<FORM>(J, v2, a2);
+  const double k2a = ACT ? (cmd - a2) * J.kt : 0.0;
+  const double v3 = v1 + h2 * k2v, a3 = ACT ? a1 + h2 * k2a : a1;
+  const double k3v = rk_dv<FORM>(J, v3, a3);
+  const double k3a = ACT ? (cmd - a3) * J.kt : 0.0;
+  const double v4 = v1 + dt * k3v, a4 = ACT ? a1 + dt * k3a : a1;
+  const double k4v = rk_dv<FORM>(J, v4, a4);
+  s.x = s.x + h6 * (((v1 + 2.0 * v2) + 2.0 * v3) + v4);
+  s.v = v1 + h6 * (((k1v + 2.0 * k2v) + 2.0 * k3v) + k4v);
+  if (ACT) {
+    const double k4a = (cmd - a4) * J.kt;
+    s.a = a1 + h6 * (((k1a + 2.0 * k2a) + 2.0 * k3a) + k4a);
+  }
+}
+
+template <int FORM, int K, bool LEAD, int INTEG = AEB_EULER>
 __device__ inline void block64(St64& s, Ld64& l, const Job& J, double al, double dt, double cmd) {
+  if (INTEG == AEB_RK4) {
+    const double h2 = 0.5 * dt, h6 = dt / 6.0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) rk4_step<FORM>(s, J, dt, h2, h6, cmd);
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     const double q = s.v * s.v;
@@ -258,8 +307,12 @@ __device__ inline void block64(St64& s, Ld64& l, const Job& J, double al, double
   }
 }
 
-template <bool LEAD>
+template <bool LEAD, int INTEG = AEB_EULER>
 __device__ inline void step64(St64& s, Ld64& l, const Job& J, double al, double dt, double cmd) {
+  if (INTEG == AEB_RK4) {
+    rk4_step<FORM_G>(s, J, dt, 0.5 * dt, dt / 6.0, cmd);
+    return;
+  }
   const double q = s.v * s.v;
   const double acc = fma(J.nkd, q, fmax(s.a, J.alim)) - J.c;
   s.a = fma(J.kt, cmd - s.a, s.a);
@@ -370,7 +423,7 @@ struct Lane64 {
 
 // wnd: the smallest nd of the wavefront's lanes (the whole block is dead time
 // for every lane when k + B <= wnd)
-template <int OBS, int B>
+template <int OBS, int B, int INTEG>
 __device__ inline void run_block64(Lane64& L, const Job& J, double al, const LaneScn& c, int k,
                                    int wnd, int impact_exit) {
   constexpr bool LEAD = OBS == AEB_OBS_LEAD;
@@ -381,13 +434,13 @@ __device__ inline void run_block64(Lane64& L, const Job& J, double al, const Lan
     L.sk = k;
   }
   if (k + B <= wnd) {
-    block64<FORM_D, B, LEAD>(L.s, L.l, J, al, c.dt, cmd);
+    block64<FORM_D, B, LEAD, INTEG>(L.s, L.l, J, al, c.dt, cmd);
   } else if (__all(!L.active || L.clamped)) {
-    block64<FORM_C, B, LEAD>(L.s, L.l, J, al, c.dt, cmd);
+    block64<FORM_C, B, LEAD, INTEG>(L.s, L.l, J, al, c.dt, cmd);
   } else if (__all(!L.active || L.free_lane)) {
-    block64<FORM_F, B, LEAD>(L.s, L.l, J, al, c.dt, cmd);
+    block64<FORM_F, B, LEAD, INTEG>(L.s, L.l, J, al, c.dt, cmd);
   } else {
-    block64<FORM_G, B, LEAD>(L.s, L.l, J, al, c.dt, cmd);
+    block64<FORM_G, B, LEAD, INTEG>(L.s, L.l, J, al, c.dt, cmd);
     L.clamped = L.clamped || (L.limited && k + B > c.nd && L.s.a <= J.alim);
   }
   if (OBS == AEB_OBS_STATIONARY && L.active && !L.collided && L.s.x > J.gap) {
@@ -402,7 +455,7 @@ __device__ inline void run_block64(Lane64& L, const Job& J, double al, const Lan
   }
 }
 
-template <int OBS, int K, bool BATCH>
+template <int OBS, int K, bool BATCH, int INTEG = AEB_EULER>
 __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
                                                    const LeadJob* __restrict__ leads,
                                                    const uint32_t* __restrict__ perm, int64_t n,
@@ -444,6 +497,11 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
     // margin: with a lead vehicle the running minimum of the clearance, taken
     // when the lane ends (later blocks keep integrating an ended lane's state)
     double dist = 0.0, margin = J.gap;
+    // RK4's last step may move the position back (stage speeds below zero as
+    // the vehicle stops): the margin then comes from the largest position,
+    // tracked over the checked steps (blocks run only while every stage
+    // speed is positive, so inside them the position rises)
+    double xmax = 0.0;
     float vimp = 0.0f;
     int k = 0, wl = -1;
     // every lane has ended by its step nmax (the horizon test fires at k + 1 == nmax)
@@ -453,15 +511,18 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
       if (!__any(L.active)) break;
       if (!BATCH || k >= wl) wl = wave_lim<BATCH>(L.active, k, c.nd, c.nmax);
       if (k + K <= wl && !__any(L.active && L.s.v <= thr_k)) {
-        run_block64<OBS, K>(L, J, al, c, k, wnd, ctx.impact_exit);
+        run_block64<OBS, K, INTEG>(L, J, al, c, k, wnd, ctx.impact_exit);
+        if (INTEG == AEB_RK4 && L.active) xmax = fmax(xmax, L.s.x);
         k += K;
       } else if (k + KS <= wl && !__any(L.active && L.s.v <= thr_s)) {
-        run_block64<OBS, KS>(L, J, al, c, k, wnd, ctx.impact_exit);
+        run_block64<OBS, KS, INTEG>(L, J, al, c, k, wnd, ctx.impact_exit);
+        if (INTEG == AEB_RK4 && L.active) xmax = fmax(xmax, L.s.x);
         k += KS;
       } else {
         const double cmd = k >= c.nd ? c.a_cmd : 0.0;
         if (L.active) {
-          step64<LEAD>(L.s, L.l, J, al, c.dt, cmd);
+          step64<LEAD, INTEG>(L.s, L.l, J, al, c.dt, cmd);
+          if (INTEG == AEB_RK4) xmax = fmax(xmax, L.s.x);
           if (k >= c.nd) L.clamped = L.clamped || (L.limited && L.s.a <= J.alim);
           bool impact = false;
           if (LEAD) {
@@ -509,7 +570,7 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
         if (!__any(L.pend)) break;
         if (L.pend) {
           const double cmd = kr >= c.nd ? c.a_cmd : 0.0;
-          step64<LEAD>(r, rl, J, al, c.dt, cmd);
+          step64<LEAD, INTEG>(r, rl, J, al, c.dt, cmd);
           ++kr;
           bool impact;
           if (LEAD) {
@@ -526,6 +587,7 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
               end = AEB_END_IMPACT;
               steps = kr;
               dist = r.x;
+              xmax = r.x;
               margin = rl.gmin;
             }
           }
@@ -535,7 +597,7 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
     if (L.pend) vimp = __builtin_nanf("");  // unreachable; makes a broken replay visible
     if (valid) {
       if (!LEAD) {
-        const double mg = J.gap - dist;
+        const double mg = J.gap - (INTEG == AEB_RK4 ? xmax : dist);
         margin = mg < J.gap ? mg : J.gap;
       }
       int64_t i;
@@ -1100,8 +1162,9 @@ __global__ __launch_bounds__(256) void k_roll_fp32c_lead(const Job* __restrict__
 }  // namespace
 
 bool fast_path_applies(const aeb_scenario& s, int precision) {
+  if (precision == AEB_FP64)
+    return s.integrator == AEB_RK4 ? s.obstacle != AEB_OBS_LEAD : !s.nofma;
   if (s.integrator != AEB_EULER) return false;
-  if (precision == AEB_FP64) return !s.nofma;
   return precision == AEB_FP32C || precision == AEB_FP32C_FIXUP;
 }
 
@@ -1189,10 +1252,10 @@ void sort_keys(const Bufs& b, int64_t n, hipStream_t st) {
                      int64_t(2));
 }
 
-template <int OBS, int K, bool BATCH>
+template <int OBS, int K, bool BATCH, int INTEG = AEB_EULER>
 void go64(const Shape& sh, const Bufs& b, int64_t n, const Ctx& ctx, hipStream_t st) {
-  hipLaunchKernelGGL((k_roll_fp64<OBS, K, BATCH>), dim3(sh.grid), dim3(sh.block), 0, st, b.jobs,
-                     b.leads, b.perm, n, ctx, b.counter, sh.persistent);
+  hipLaunchKernelGGL((k_roll_fp64<OBS, K, BATCH, INTEG>), dim3(sh.grid), dim3(sh.block), 0, st,
+                     b.jobs, b.leads, b.perm, n, ctx, b.counter, sh.persistent);
 }
 
 template <int OBS, bool BATCH>
@@ -1225,6 +1288,17 @@ int integrate(const aeb_scenario& s0, int precision, const Bufs& b, int64_t n, c
   const int obs = s0.obstacle;
   const TuneCfg t = tune_get(precision == AEB_FP64 ? AEB_FP64 : AEB_FP32C, obs);
   const Shape sh = shape(t, n);
+  if (precision == AEB_FP64 && s0.integrator == AEB_RK4) {
+    // an RK4 step costs about eight Euler steps: short blocks keep the tail small
+    timing_begin(st);
+    if (obs == AEB_OBS_STATIONARY)
+      go64<AEB_OBS_STATIONARY, 16, BATCH, AEB_RK4>(sh, b, n, ctx, st);
+    else
+      go64<AEB_OBS_NONE, 16, BATCH, AEB_RK4>(sh, b, n, ctx, st);
+    timing_end(st);
+    AEB_HIP(hipGetLastError());
+    return AEB_OK;
+  }
   if (precision == AEB_FP64) {
     timing_begin(st);
     if (obs == AEB_OBS_STATIONARY)

@@ -73,8 +73,8 @@ def test_batch_reduce_matches_reference(B, orc):
         assert abs(st["mean_dist"] - ref["mean_dist"]) <= 1e-12 * ref["mean_dist"]
 
 
-def test_batch_fallback_paths(B, orc):
-    # RK4 and FP32 with a lead vehicle run scenario by scenario
+def test_batch_rk4_and_fp32_lead(B, orc):
+    # RK4 (FP64) and FP32 with a lead vehicle in one batched launch each
     rk = [W.paper_preset(700, seed=s, scenario_id=s) for s in (1, 2, 3)]
     for d, o in zip(rk, B.batch_rollout(rk)):
         check_fp64(to_np(o), orc.run(d))
@@ -165,3 +165,9 @@ def test_uneven_full_size_sampled(B, orc):
             assert int(o["status"][i].item()) == int(ref["status"][0])
             assert int(o["steps"][i].item()) == int(ref["steps"][0])
             assert abs(float(o["dist"][i].item()) - ref["dist"][0]) <= 1e-12 * abs(ref["dist"][0])
+
+
+def test_batch_unfused_runs_scenario_by_scenario(B, orc):
+    scns = [W.single(900, seed=s, scenario_id=s, nofma=True) for s in (4, 5)]
+    for d, o in zip(scns, B.batch_rollout(scns)):
+        check_fp64(to_np(o), orc.run(d))

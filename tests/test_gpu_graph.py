@@ -110,7 +110,7 @@ def test_batch_graph_replays_equal_eager(B):
 
 def test_graph_rejects(B):
     with pytest.raises(B.AebError) as e:
-        B.Graph(W.paper_preset(100))          # RK4 is not recorded
+        B.Graph(W.single(100, nofma=True))    # the unfused form is not recorded
     assert e.value.code == B.EINVAL
     with pytest.raises(B.AebError) as e:
         B.Graph(W.single(100), precision="fp32c_fixup")

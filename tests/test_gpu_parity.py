@@ -265,9 +265,11 @@ MU_AT_COMMAND = 6.0 / (9.81 - 6.0 * 0.55 / 2.7)   # friction limit equal to the 
 @pytest.mark.parametrize("case", ["no_dead_time", "dead_2K", "dead_beyond_horizon",
                                   "horizon_cut", "horizon_short", "dt2ms", "mu_at_command",
                                   "wide_gap", "wide_gap_exit", "downhill"])
-@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "rk4"])
 def test_block_path_edges(B, orc, case, prec):
     d = W.single(3000, seed=77)
+    if prec == "rk4":
+        d["integrator"] = "rk4"
     d.update({
         "no_dead_time": dict(dead_time=0.0),
         "dead_2K": dict(dead_time=0.064),
@@ -281,8 +283,8 @@ def test_block_path_edges(B, orc, case, prec):
         "downhill": dict(grade=("normal", -0.25, 0.05), mu=("uniform", 0.3, 0.5)),
     }[case])
     ref = orc.run(d)
-    got = to_np(B.rollout(d, precision=prec))
-    if prec == "fp64":
+    got = to_np(B.rollout(d, precision="fp64" if prec == "rk4" else prec))
+    if prec in ("fp64", "rk4"):
         check_fp64(got, ref)
     else:
         check_fp32c(got, ref)

@@ -112,7 +112,7 @@ def test_concurrent_clients(B):
 def test_refusals(B):
     with B.Server(64 << 20, max_slots=4, n_streams=1, max_tick_samples=1 << 14) as srv:
         with pytest.raises(B.AebError) as e:
-            srv.submit(W.paper_preset(100))           # RK4 is not on the batched path
+            srv.submit(W.single(100, nofma=True))     # the unfused form is not batched
         assert e.value.code == B.EINVAL
         with pytest.raises(B.AebError) as e:
             srv.submit(W.single(1 << 15))              # more than a launch holds

@@ -22,13 +22,16 @@ def B():
     return binding
 
 
-@pytest.mark.parametrize("prec,obs", [("fp64", "stationary"), ("fp64", "lead"),
-                                      ("fp64", "none"), ("fp32c", "stationary")])
-def test_results_do_not_depend_on_shape(B, prec, obs):
+@pytest.mark.parametrize("prec,obs,integ", [("fp64", "stationary", "euler"),
+                                            ("fp64", "lead", "euler"), ("fp64", "none", "euler"),
+                                            ("fp64", "none", "rk4"), ("fp64", "stationary", "rk4"),
+                                            ("fp32c", "stationary", "euler"),
+                                            ("fp32c", "lead", "euler")])
+def test_results_do_not_depend_on_shape(B, prec, obs, integ):
     if obs == "lead":
         d = W.sweep(n=20000)[70]
     else:
-        d = W.single(20000, seed=4, scenario_id=2, obstacle=obs)
+        d = W.single(20000, seed=4, scenario_id=2, obstacle=obs, integrator=integ)
     keep = B.tune_get(prec, obs)
     try:
         ref = to_np(B.rollout(d, precision=prec))
