@@ -34,6 +34,9 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # packed FP32; unpacked FP32 issues at the FP64 rate
 EULER_FLOPS_PER_STEP = 11        # 4 fma (2 each) + 3 (v*v, -c, cmd-a)
 FP32C_FLOPS_PER_STEP = 9         # 4 fma + v*v, compensated sums per block not counted
+RK4_FLOPS_PER_STEP = 57          # 4 stage speed/actuator derivatives (6 each), 3 stage
+                                 # updates of v and a (4 each), 3 weighted sums (5 each),
+                                 # the final update of x, v, a (2 each)
 RISK = (0.05, 0.01, 0.001)
 MARGIN_Q = (0.0, 0.01, 0.05, 0.5)
 GRID = (30.0, 130.0, 256)
@@ -132,6 +135,31 @@ def cpu_baseline(d, budget_samples):
     return {"value": n / el, "unit": "rollouts/s", "cores": threads, "kind": "oracle",
             "sample": f"samples 0..{n - 1} of the same scenario, {threads} threads, "
                       f"{el:.2f} s wall"}
+
+
+def rk4_leg(B, W, torch, n, steps=5):
+    """The paper's own integrator on its Sec. IV-B uncertainty model (classical
+    RK4, no fused operations, no obstacle), parameters drawn in-kernel: the
+    integration kernel's time from the library's events, FP64 flops per step
+    counted as in RK4_FLOPS_PER_STEP."""
+    import numpy as np
+    d = W.paper_preset(n)
+    out = B.alloc_outputs(n)
+    B.rollout(d, out=out)
+    torch.cuda.synchronize()
+    B.timing_enable(True)
+    ks = []
+    for _ in range(steps):
+        B.rollout(d, out=out)
+        ks.append(B.timing_last())
+    B.timing_enable(False)
+    nsteps = int(out["steps"].to(torch.int64).sum().item())
+    ms = float(np.mean(ks))
+    tflops = RK4_FLOPS_PER_STEP * nsteps / (ms * 1e-3) / 1e12
+    return {"workload": f"paper preset (Sec. IV-B), {n} samples, RK4 dt=1 ms, no obstacle",
+            "kernel_ms": ms, "rollouts_per_s": n / (ms * 1e-3), "steps_per_launch": nsteps,
+            "flops_per_step": RK4_FLOPS_PER_STEP, "achieved_tflops": tflops,
+            "frac_fp64_peak": tflops / FP64_VECTOR_PEAK_TFLOPS}
 
 
 def batch_leg(B, W, torch, reps=2):
@@ -309,6 +337,9 @@ def main():
     step_wall = wallg64 if use_graph else wall64
     value = args.steps * n / step_wall
 
+    log("bench: rk4 leg")
+    rk4 = rk4_leg(B, W, torch, n)
+
     batch = None
     if not args.no_batch:
         log("bench: batched launches")
@@ -379,6 +410,7 @@ def main():
             "collision_flags_equal_fp64_outside_band": flags_equal,
             "speedup_vs_fp64_kernel": kavg64 / kavg32,
         },
+        "rk4": rk4,
         "batch": batch,
         "serving": serving,
         "plain_method_host": {"sampling_s": t_sample, "h2d_s": t_h2d,
