@@ -298,11 +298,13 @@ def main():
     t_sample = time.perf_counter() - t0
     params = B.alloc_params(n, device=True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for c in B.COLUMNS:
-        params[c].copy_(host[c], non_blocking=True)
-    torch.cuda.synchronize()
-    t_h2d = time.perf_counter() - t0
+    t_h2d = float("inf")
+    for _ in range(3):  # the first copy also pays one-time driver costs
+        t0 = time.perf_counter()
+        for c in B.COLUMNS:
+            params[c].copy_(host[c], non_blocking=True)
+        torch.cuda.synchronize()
+        t_h2d = min(t_h2d, time.perf_counter() - t0)
     out = B.alloc_outputs(n)
 
     log("bench: fp64 timed loop")

@@ -279,8 +279,11 @@ __global__ __launch_bounds__(FB) void k_fin1(const Partial* part, int nb, long l
     p.vmax = static_cast<float>(wave_reduce(vmax, MaxOp()));
     if ((threadIdx.x & 63) == 0) wp[threadIdx.x >> 6] = p;
     __syncthreads();
-    Partial q = wp[0];
-    for (int w = 1; w < FB / 64; ++w) combine(q, wp[w]);
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < FB / 64; ++w) combine(wp[0], wp[w]);
+    }
+    __syncthreads();
+    const Partial& q = wp[0];
     ncol = q.ncol;
     nstop = q.nstop;
     nimp = q.nimp;
