@@ -281,8 +281,9 @@ int aeb_autotune(const aeb_scenario* calib, int precision, const char* cache_pat
  * (parameter columns as they are at replay time, or the in-kernel generator)
  * and gives the same results as the eager calls.  The graph owns its device
  * scratch (allocated at creation) and, for batches, pinned copies of the
- * scenario tables.  Only the block-structured Euler path is recorded (FP64 or
- * FP32C; no RK4, no nofma, no FP32 lead vehicle): AEB_EINVAL otherwise. */
+ * scenario tables.  Only the sorted block-structured path is recorded: FP64
+ * explicit Euler (fused form) or RK4, FP32C explicit Euler; AEB_EINVAL for
+ * the unfused Euler form (nofma) and the FP32C fix-up mode. */
 typedef struct aeb_graph aeb_graph;
 
 /* One scenario: params (device columns, or NULL for the in-kernel generator),
@@ -386,7 +387,7 @@ int aeb_server_create(const aeb_server_cfg* cfg, aeb_server** out);
 int aeb_server_destroy(aeb_server* srv);
 
 /* Queue one evaluation (non-blocking).  AEB_EINVAL: invalid scenario or one
- * the batched path cannot run (RK4, nofma, FP32C with a lead vehicle);
+ * the batched path cannot run (the unfused Euler form, RK4 in FP32C);
  * AEB_ENOMEM: its footprint exceeds the request part of the arena or its
  * sample count max_tick_samples; AEB_EAGAIN: the queue is full.  deadline_s:
  * latency budget used for miss accounting (e.g. 0.530). */

@@ -127,8 +127,8 @@ int aeb_graph_create(const aeb_scenario* scn, const aeb_params* params, int prec
   rc = check_common(precision, req, host_stats);
   if (rc != AEB_OK) return rc;
   if (!fast_path_applies(*scn, precision))
-    return fail(AEB_EINVAL, "graphs record the block-structured Euler path (no RK4, no nofma, "
-                            "no FP32 lead vehicle)");
+    return fail(AEB_EINVAL, "graphs record the block-structured path (not the unfused Euler "
+                            "form, not RK4 in FP32C)");
   if (out->n != scn->n_samples) return fail(AEB_EINVAL, "outputs length differs from n_samples");
   ParamSrc src{};
   if (params) {

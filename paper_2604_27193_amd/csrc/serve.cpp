@@ -121,14 +121,22 @@ class HipExecutor final : public serve::Executor {
     if (rc != AEB_OK) return rc;
     if (!fast_path_applies(s, cfg_.precision))
       return fail(AEB_EINVAL,
-                  "serving runs the batched explicit-Euler path (no RK4, no nofma, no FP32 "
-                  "lead vehicle)");
+                  "serving runs the batched block-structured path (not the unfused Euler "
+                  "form, not RK4 in FP32C)");
     return AEB_OK;
   }
 
   void bind_thread() override { (void)hipSetDevice(dev_); }
 
   int launch(int stream, const std::vector<serve::Request*>& tick) override {
+    const int rc = enqueue(stream, tick);
+    // on failure part of the tick may already be queued: let it drain before
+    // the scheduler hands the requests' memory to others
+    if (rc != AEB_OK) (void)hipStreamSynchronize(streams_[stream].st);
+    return rc;
+  }
+
+  int enqueue(int stream, const std::vector<serve::Request*>& tick) {
     StreamCtx& S = streams_[stream];
     const int n = static_cast<int>(tick.size());
     std::vector<OutCols> oc(n);

@@ -49,10 +49,12 @@ def eager_noise(B, torch):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "rk4"])
 def test_graph_replays_equal_eager(B, prec):
     import torch
     d = W.single(30000, seed=12, scenario_id=3)
+    if prec == "rk4":
+        d, prec = W.paper_preset(30000, seed=12, scenario_id=3), "fp64"
     ref_out = B.rollout(d, precision=prec)
     ref_st = B.reduce(ref_out, risk=RISK, margin_q=MQ, grid=GRID)
     ref = host(ref_out)

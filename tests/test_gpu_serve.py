@@ -123,3 +123,14 @@ def test_refusals(B):
     with pytest.raises(B.AebError) as e:
         B.Server(1 << 20, max_tick_samples=1 << 20)     # arena too small
     assert e.value.code == B.ENOMEM
+
+
+def test_rk4_requests_equal_alone(B):
+    scns = [W.paper_preset(n, seed=40 + j, scenario_id=j) for j, n in
+            enumerate((5000, 12000, 700, 20000))]
+    with B.Server(128 << 20, max_slots=8, n_streams=2, tick_us=1000,
+                  max_tick_samples=1 << 16, risk=RISK, margin_q=MQ, grid=GRID) as srv:
+        tickets = [srv.submit(d) for d in scns]
+        got = [srv.wait(t)[0] for t in tickets]
+    for d, st in zip(scns, got):
+        same(alone(B, d, "fp64"), st)
