@@ -125,16 +125,25 @@ def same_stats(a, b):
     return True
 
 
-def cpu_baseline(d, budget_samples):
+def cpu_baseline(d, budget_samples, single_samples=10_000):
+    """The oracle (plain C, FP64) on the host cores: all threads over the first
+    `budget_samples` samples (the value), and one thread over the first
+    `single_samples` (reported beside it)."""
     from oracle import oracle
     threads = oracle.host_threads()
     n = min(budget_samples, int(d["n_samples"]))
     t0 = time.perf_counter()
     oracle.run(d, first=0, count=n, threads=threads)
     el = time.perf_counter() - t0
+    m = min(single_samples, int(d["n_samples"]))
+    t0 = time.perf_counter()
+    oracle.run(d, first=0, count=m, threads=1)
+    el1 = time.perf_counter() - t0
     return {"value": n / el, "unit": "rollouts/s", "cores": threads, "kind": "oracle",
-            "sample": f"samples 0..{n - 1} of the same scenario, {threads} threads, "
-                      f"{el:.2f} s wall"}
+            "sample": f"samples 0..{n - 1} of the same scenario on {threads} threads "
+                      f"({el:.2f} s wall); single thread over samples 0..{m - 1}: "
+                      f"{m / el1:.0f} rollouts/s ({el1:.2f} s)",
+            "single_thread_rollouts_per_s": m / el1}
 
 
 def rk4_leg(B, W, torch, n, steps=5):
@@ -160,6 +169,28 @@ def rk4_leg(B, W, torch, n, steps=5):
             "kernel_ms": ms, "rollouts_per_s": n / (ms * 1e-3), "steps_per_launch": nsteps,
             "flops_per_step": RK4_FLOPS_PER_STEP, "achieved_tflops": tflops,
             "frac_fp64_peak": tflops / FP64_VECTOR_PEAK_TFLOPS}
+
+
+def n_sweep_leg(B, W, torch, sizes=(1_000, 10_000, 100_000, 1_048_576), reps=5):
+    """Rollout call (parameters drawn in-kernel) plus reduction at growing N:
+    below ~1e5 samples the launch sequence, not the integration, sets the time."""
+    import numpy as np
+    res = {}
+    for n in sizes:
+        d = W.single(n)
+        out = B.alloc_outputs(n)
+        B.rollout(d, out=out)
+        B.reduce(out, risk=RISK)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            B.rollout(d, out=out)
+            B.reduce(out, risk=RISK)
+            ts.append(time.perf_counter() - t0)
+        t = float(np.median(ts))
+        res[str(n)] = {"ms": t * 1e3, "rollouts_per_s": n / t}
+    return res
 
 
 def batch_leg(B, W, torch, reps=2):
@@ -218,23 +249,34 @@ def serving_leg(B, W, precision, rates, duration, arena_gib=4):
         for rate in rates:
             stream = W.serving_stream(rate, duration=duration)
             pending, done = {}, []
+            keep = {}  # a sampled subset, re-run alone afterwards
             t0 = time.perf_counter()
             k = 0
             while k < len(stream) or pending:
                 now = time.perf_counter() - t0
                 while k < len(stream) and stream[k][0] <= now:
                     _, d, dl = stream[k]
-                    pending[srv.submit(d, deadline=dl)] = int(d["n_samples"])
+                    t = srv.submit(d, deadline=dl)
+                    pending[t] = int(d["n_samples"])
+                    if k % 97 == 0:
+                        keep[t] = [d, None]
                     k += 1
                 for t in list(pending):
                     r = srv.poll(t)
                     if r is not None:
                         done.append((pending.pop(t), r[1]))
+                        if t in keep:
+                            keep[t][1] = r[0]
                 if k < len(stream):
                     time.sleep(max(0.0, min(2e-4, stream[k][0] - (time.perf_counter() - t0))))
                 else:
                     time.sleep(1e-4)
             wall = time.perf_counter() - t0
+            equal = True
+            for d, st in keep.values():
+                o = B.rollout(d, precision=precision)
+                equal = equal and same_stats(B.reduce(o, risk=RISK, margin_q=MARGIN_Q,
+                                                      grid=GRID), st)
             lat = np.array([tm["done"] - tm["arrive"] for _, tm in done])
             lat25 = np.array([tm["done"] - tm["arrive"] for n, tm in done if n == 25_000])
             samples = sum(n for n, _ in done)
@@ -246,6 +288,7 @@ def serving_leg(B, W, precision, rates, duration, arena_gib=4):
                 "max_ms": float(lat.max() * 1e3),
                 "deadline_miss_rate": float(np.mean([tm["missed"] for _, tm in done])),
                 "rollouts_per_s": samples / wall,
+                "alone_vs_mix_checked": len(keep), "alone_vs_mix_equal": equal,
             }
             log(f"bench: serving {precision} {rate} req/s: {res[str(rate)]}")
         info = srv.info()
@@ -260,7 +303,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1_048_576)
-    ap.add_argument("--cpu-samples", type=int, default=262_144)
+    ap.add_argument("--cpu-samples", type=int, default=1_048_576)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch leg")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
@@ -341,6 +384,8 @@ def main():
 
     log("bench: rk4 leg")
     rk4 = rk4_leg(B, W, torch, n)
+    log("bench: N sweep")
+    nsweep = n_sweep_leg(B, W, torch)
 
     batch = None
     if not args.no_batch:
@@ -352,7 +397,8 @@ def main():
         log("bench: serving streams")
         serving = {"precision": "fp32c", "deadline_ms": 530.0,
                    "duration_s": args.serve_seconds,
-                   "rates": serving_leg(B, W, "fp32c", (50, 200, 800), args.serve_seconds)}
+                   "rates": serving_leg(B, W, "fp32c", (50, 200, 800), args.serve_seconds),
+                   "fp64_at_800": serving_leg(B, W, "fp64", (800,), args.serve_seconds)}
 
     cpu = None
     if not args.no_cpu:
@@ -413,6 +459,7 @@ def main():
             "speedup_vs_fp64_kernel": kavg64 / kavg32,
         },
         "rk4": rk4,
+        "n_sweep_fp64_step": nsweep,
         "batch": batch,
         "serving": serving,
         "plain_method_host": {"sampling_s": t_sample, "h2d_s": t_h2d,
