@@ -171,6 +171,46 @@ def rk4_leg(B, W, torch, n, steps=5):
             "frac_fp64_peak": tflops / FP64_VECTOR_PEAK_TFLOPS}
 
 
+def paper_study_leg(B, W, torch):
+    """The paper's own workload (Sec. IV-B preset, RK4, no obstacle) on the GPU:
+    Table I's sample counts (mean and sd of the stopping distance beside the
+    printed rows), the Sec. VI-C headways at 350,000 samples, and the step size
+    against fidelity and speed (RK4 and explicit Euler, dt = 1 to 20 ms)."""
+    import numpy as np
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_results.json")))
+    risk = tuple(gold["headways"]["risk"])
+    rows = []
+    for row in gold["table_I"]["rows"]:
+        st = B.reduce(B.rollout(W.paper_preset(row["n"])), risk=risk)
+        rows.append({"n": row["n"], "mean": st["mean_dist"], "sd": st["sd_dist"],
+                     "paper_mean": row["mean"], "paper_sd": row["sd"]})
+    dt_rows = []
+    ref = None
+    for integ in ("rk4", "euler"):
+        for dt in (1e-3, 2e-3, 5e-3, 1e-2, 2e-2):
+            d = W.paper_preset(350_000, integrator=integ, dt=dt)
+            out = B.alloc_outputs(350_000)
+            B.rollout(d, out=out)
+            torch.cuda.synchronize()
+            B.timing_enable(True)
+            ks = []
+            for _ in range(3):
+                B.rollout(d, out=out)
+                ks.append(B.timing_last())
+            B.timing_enable(False)
+            st = B.reduce(out, risk=risk)
+            if ref is None:
+                ref = st
+            dt_rows.append({"integrator": integ, "dt_ms": dt * 1e3, "mean": st["mean_dist"],
+                            "sd": st["sd_dist"], "headways": st["headway"],
+                            "mean_minus_rk4_1ms": st["mean_dist"] - ref["mean_dist"],
+                            "kernel_ms": float(np.median(ks)),
+                            "rollouts_per_s": 350_000 / (float(np.median(ks)) * 1e-3)})
+    return {"workload": "paper preset (Sec. IV-B), RK4 dt = 1 ms unless stated, no obstacle",
+            "table_I": rows, "headways_350k": ref["headway"],
+            "paper_headways": gold["headways"]["h0"], "step_size": dt_rows}
+
+
 def n_sweep_leg(B, W, torch, sizes=(1_000, 10_000, 100_000, 1_048_576), reps=5):
     """Rollout call (parameters drawn in-kernel) plus reduction at growing N:
     below ~1e5 samples the launch sequence, not the integration, sets the time."""
@@ -386,6 +426,8 @@ def main():
     rk4 = rk4_leg(B, W, torch, n)
     log("bench: N sweep")
     nsweep = n_sweep_leg(B, W, torch)
+    log("bench: paper-preset study")
+    study = paper_study_leg(B, W, torch)
 
     batch = None
     if not args.no_batch:
@@ -460,6 +502,7 @@ def main():
         },
         "rk4": rk4,
         "n_sweep_fp64_step": nsweep,
+        "paper_preset_study": study,
         "batch": batch,
         "serving": serving,
         "plain_method_host": {"sampling_s": t_sample, "h2d_s": t_h2d,
