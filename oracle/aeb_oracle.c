@@ -17,6 +17,7 @@
  */
 #include "aeb_oracle.h"
 
+#include <limits.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -141,6 +142,47 @@ double orc_draw(const orc_dist* d, uint64_t seed, uint64_t scenario_id, uint64_t
   }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Perception trigger delay (see orc_scenario).  Frame j (captured at time    */
+/* j * frame_period) sees the object if j >= the occluded frame count and its */
+/* own uniform (slot DETECT, word j of the generator calls) is at least       */
+/* p_dropout.  The object is confirmed at the frame that completes `confirm`  */
+/* consecutive detections; frames are searched until the horizon.             */
+/* ------------------------------------------------------------------------ */
+
+static int perception_on(const orc_scenario* s) {
+  return !(s->latency.kind == ORC_D_CONST && s->latency.p0 == 0.0 && s->frame_period == 0.0);
+}
+
+double orc_trigger_delay(const orc_scenario* s, uint64_t i) {
+  const uint64_t seed = s->seed, sid = s->scenario_id;
+  double lat = orc_draw(&s->latency, seed, sid, i, ORC_SLOT_LATENCY);
+  if (!(lat > 0.0)) lat = 0.0;
+  if (s->frame_period == 0.0) return lat;
+  double occ = orc_draw(&s->occlusion, seed, sid, i, ORC_SLOT_OCCLUSION);
+  const long long hidden = occ > 0.0 ? (long long)floor(occ) : 0;
+  const long long frames = (long long)floor(s->horizon / s->frame_period) + 1;
+  int run = 0;
+  for (long long j = 0; j < frames; ++j) {
+    int seen = 0;
+    if (j >= hidden) {
+      double u[2];
+      orc_uniform_pair(seed, sid, i, ORC_SLOT_DETECT, (uint32_t)(j / 2), u);
+      seen = u[j % 2] >= s->p_dropout;
+    }
+    run = seen ? run + 1 : 0;
+    if (run == s->confirm) return (double)j * s->frame_period + lat;
+  }
+  return INFINITY;
+}
+
+/* first step with the brake command: the dead time plus the trigger delay */
+static long long command_step(const orc_scenario* s, const orc_sample* p) {
+  const double q = (s->dead_time + p->trigger) / s->dt;
+  if (!(q < 4.0e18)) return LLONG_MAX;
+  return llround(q);
+}
+
 void orc_sample_one(const orc_scenario* s, uint64_t i, orc_sample* p) {
   const uint64_t seed = s->seed, sid = s->scenario_id;
   p->v0 = orc_draw(&s->v0, seed, sid, i, ORC_SLOT_V0);
@@ -154,9 +196,10 @@ void orc_sample_one(const orc_scenario* s, uint64_t i, orc_sample* p) {
   p->tau = orc_draw(&s->tau, seed, sid, i, ORC_SLOT_TAU);
   p->gap = orc_draw(&s->gap, seed, sid, i, ORC_SLOT_GAP);
   p->lead_decel = orc_draw(&s->lead_decel, seed, sid, i, ORC_SLOT_LEAD);
+  p->trigger = perception_on(s) ? orc_trigger_delay(s, i) : 0.0;
 }
 
-int orc_sample_range(const orc_scenario* s, int64_t first, int64_t count, double* const cols[11]) {
+int orc_sample_range(const orc_scenario* s, int64_t first, int64_t count, double* const cols[12]) {
   if (first < 0 || count < 0) return ORC_EINVAL;
   for (int64_t k = 0; k < count; ++k) {
     orc_sample p;
@@ -172,6 +215,7 @@ int orc_sample_range(const orc_scenario* s, int64_t first, int64_t count, double
     cols[8][k] = p.tau;
     cols[9][k] = p.gap;
     cols[10][k] = p.lead_decel;
+    cols[11][k] = p.trigger;
   }
   return ORC_OK;
 }
@@ -229,6 +273,13 @@ int orc_validate(const orc_scenario* s) {
                             &s->crr, &s->tau, &s->gap, &s->lead_decel};
   for (int k = 0; k < 9; ++k)
     if (!dist_ok(all[k])) return ORC_EINVAL;
+  /* perception: finite distributions, a dropout probability in [0, 1), at
+   * most 1e6 frames over the horizon, 1 to 64 confirming detections */
+  if (!dist_ok(&s->latency) || !dist_ok(&s->occlusion)) return ORC_EINVAL;
+  if (!(s->frame_period >= 0.0) || !isfinite(s->frame_period)) return ORC_EINVAL;
+  if (s->frame_period > 0.0 && !(s->horizon / s->frame_period <= 1.0e6)) return ORC_EINVAL;
+  if (!(s->p_dropout >= 0.0 && s->p_dropout < 1.0)) return ORC_EINVAL;
+  if (s->confirm < 1 || s->confirm > 64) return ORC_EINVAL;
   /* the explicit actuator update needs dt/tau <= 1 for every sample */
   if (!(dist_min(&s->tau) > 0.0)) return ORC_EINVAL;
   if (s->integrator == ORC_EULER && dist_min(&s->tau) < s->dt) return ORC_EINVAL;
@@ -274,7 +325,7 @@ static void rollout_euler(const orc_scenario* s, const orc_sample* p, int clamp_
   derive(s, p, &k);
   const double dt = s->dt;
   const double kt = dt / p->tau;
-  const long long nd = llround(s->dead_time / dt);
+  const long long nd = command_step(s, p);
   const long long nmax = llround(s->horizon / dt);
   const int lead = s->obstacle == ORC_OBS_LEAD;
   const int nofma = s->nofma;
@@ -383,7 +434,7 @@ static void rollout_rk4(const orc_scenario* s, const orc_sample* p, orc_result* 
   const double h2 = 0.5 * dt;
   const double h6 = dt / 6.0;
   const double rt = 1.0 / p->tau;
-  const long long nd = llround(s->dead_time / dt);
+  const long long nd = command_step(s, p);
   const long long nmax = llround(s->horizon / dt);
   const double gap0 = p->gap;
 
@@ -458,7 +509,7 @@ int orc_run_range(const orc_scenario* s, int64_t first, int64_t count, double* d
   return ORC_OK;
 }
 
-int orc_rollout_given(const orc_scenario* s, const double* const cols[11], int64_t n,
+int orc_rollout_given(const orc_scenario* s, const double* const cols[12], int64_t n,
                       int clamp_state, double* dist, uint8_t* status, int32_t* steps,
                       double* margin, float* v_impact) {
   if (n < 0) return ORC_EINVAL;
@@ -476,6 +527,7 @@ int orc_rollout_given(const orc_scenario* s, const double* const cols[11], int64
     p.tau = cols[8][k];
     p.gap = cols[9][k];
     p.lead_decel = cols[10][k];
+    p.trigger = cols[11][k];
     orc_rollout_one(s, &p, clamp_state, &r);
     dist[k] = r.dist;
     status[k] = r.status;

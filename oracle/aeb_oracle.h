@@ -35,7 +35,7 @@ enum { ORC_OK = 0, ORC_EINVAL = -1 };
 enum {
   ORC_SLOT_V0 = 0, ORC_SLOT_MU = 1, ORC_SLOT_MASS = 2, ORC_SLOT_GRADE = 3,
   ORC_SLOT_CDA = 4, ORC_SLOT_CRR = 5, ORC_SLOT_TAU = 6, ORC_SLOT_GAP = 7,
-  ORC_SLOT_LEAD = 8
+  ORC_SLOT_LEAD = 8, ORC_SLOT_LATENCY = 9, ORC_SLOT_OCCLUSION = 10, ORC_SLOT_DETECT = 11
 };
 
 typedef struct {
@@ -55,11 +55,24 @@ typedef struct {
   int32_t nofma;        /* 1: Euler uses separate multiply and add (paper's literal rule) */
   double dt, horizon, dead_time, a_cmd, g, rho, h_cog, wheelbase;
   orc_dist v0, mu, mass, grade, cda, crr, tau, gap, lead_decel;
+  /* Perception (the sensing effects Section VIII lists as future work): the
+   * brake command starts after the dead time plus a per-sample trigger delay,
+   * the sensing latency plus the time until the object is confirmed.  Frames
+   * arrive every frame_period seconds; the first `occlusion` frames cannot
+   * see the object; a visible frame misses it with probability p_dropout;
+   * `confirm` consecutive detections confirm it.  frame_period = 0 leaves the
+   * latency alone.  latency = CONST 0 and frame_period = 0: no perception. */
+  orc_dist latency;    /* seconds, clamped at 0 */
+  orc_dist occlusion;  /* frames, rounded down, clamped at 0 */
+  double frame_period, p_dropout;
+  int32_t confirm;
+  int32_t pad2;
 } orc_scenario;
 
 /* One sample's realised parameter vector (xi^(i) of Section IV-A). */
 typedef struct {
   double v0, mu, mass, grade, sin_grade, cos_grade, cda, crr, tau, gap, lead_decel;
+  double trigger;  /* perception trigger delay (s); +inf: the object is never confirmed */
 } orc_sample;
 
 typedef struct {
@@ -109,9 +122,12 @@ double orc_draw(const orc_dist* d, uint64_t seed, uint64_t scenario_id, uint64_t
                 uint32_t slot);
 void orc_sample_one(const orc_scenario* s, uint64_t i, orc_sample* out);
 
+/* Perception trigger delay of sample i (seconds, +inf if never confirmed). */
+double orc_trigger_delay(const orc_scenario* s, uint64_t i);
+
 /* SoA parameter columns, in this order: v0 mu mass grade sin_grade cos_grade
- * cda crr tau gap lead_decel.  cols[c] points at `count` doubles. */
-int orc_sample_range(const orc_scenario* s, int64_t first, int64_t count, double* const cols[11]);
+ * cda crr tau gap lead_decel trigger.  cols[c] points at `count` doubles. */
+int orc_sample_range(const orc_scenario* s, int64_t first, int64_t count, double* const cols[12]);
 
 void orc_rollout_one(const orc_scenario* s, const orc_sample* p, int clamp_state, orc_result* r);
 
@@ -120,7 +136,7 @@ int orc_run_range(const orc_scenario* s, int64_t first, int64_t count, double* d
                   uint8_t* status, int32_t* steps, double* margin, float* v_impact);
 
 /* Roll out caller-given parameter columns (same order as orc_sample_range). */
-int orc_rollout_given(const orc_scenario* s, const double* const cols[11], int64_t n,
+int orc_rollout_given(const orc_scenario* s, const double* const cols[12], int64_t n,
                       int clamp_state, double* dist, uint8_t* status, int32_t* steps,
                       double* margin, float* v_impact);
 

@@ -15,9 +15,13 @@ import numpy as np
 from . import build as _build
 
 COLUMNS = ("v0", "mu", "mass", "grade", "sin_grade", "cos_grade", "cda", "crr", "tau",
-           "gap", "lead_decel")
+           "gap", "lead_decel", "trigger")
 DISTS = ("v0", "mu", "mass", "grade", "cda", "crr", "tau", "gap", "lead_decel")
 SLOTS = {name: k for k, name in enumerate(DISTS)}
+SLOTS.update({"latency": 9, "occlusion": 10, "detect": 11})
+# perception (absent from a scenario dict: no perception)
+PERCEPTION_DEFAULTS = {"latency": ("const", 0.0), "occlusion": ("const", 0.0),
+                       "frame_period": 0.0, "p_dropout": 0.0, "confirm": 1}
 INTEGRATORS = {"euler": 0, "rk4": 1}
 OBSTACLES = {"none": 0, "stationary": 1, "lead": 2}
 DIST_KINDS = {"const": 0, "uniform": 1, "normal": 2, "trunc_normal": 3}
@@ -37,7 +41,9 @@ class Scenario(C.Structure):
                  ("impact_exit", C.c_int32), ("nofma", C.c_int32)]
                 + [(f, C.c_double) for f in ("dt", "horizon", "dead_time", "a_cmd", "g", "rho",
                                              "h_cog", "wheelbase")]
-                + [(f, Dist) for f in DISTS])
+                + [(f, Dist) for f in DISTS]
+                + [("latency", Dist), ("occlusion", Dist), ("frame_period", C.c_double),
+                   ("p_dropout", C.c_double), ("confirm", C.c_int32), ("pad2", C.c_int32)])
 
 
 class ReduceReq(C.Structure):
@@ -108,6 +114,13 @@ def scenario(d):
         setattr(s, f, float(d[f]))
     for f in DISTS:
         setattr(s, f, _dist(d[f]))
+    per = dict(PERCEPTION_DEFAULTS)
+    per.update({k: d[k] for k in PERCEPTION_DEFAULTS if k in d})
+    s.latency = _dist(per["latency"])
+    s.occlusion = _dist(per["occlusion"])
+    s.frame_period = float(per["frame_period"])
+    s.p_dropout = float(per["p_dropout"])
+    s.confirm = int(per["confirm"])
     return s
 
 
@@ -137,11 +150,11 @@ def uniforms(seed, scenario_id, first, count, slot, attempt=0):
 
 
 def sample(d, first=0, count=None):
-    """Dict of the eleven parameter columns for samples [first, first+count)."""
+    """Dict of the twelve parameter columns for samples [first, first+count)."""
     if count is None:
         count = int(d["n_samples"]) - first
     cols = [np.empty(count, dtype=np.float64) for _ in COLUMNS]
-    arr = (C.POINTER(C.c_double) * 11)(*[_dptr(c) for c in cols])
+    arr = (C.POINTER(C.c_double) * 12)(*[_dptr(c) for c in cols])
     rc = lib().orc_sample_range(C.byref(scenario(d)), first, count, arr)
     if rc != OK:
         raise ValueError("orc_sample_range rejected its arguments")
@@ -191,8 +204,9 @@ def run(d, first=0, count=None, threads=1):
 def rollout_given(d, cols, clamp_state=False):
     """Roll out caller-given parameter columns (dict keyed by COLUMNS)."""
     n = len(cols["v0"])
-    arrs = [np.ascontiguousarray(cols[c], dtype=np.float64) for c in COLUMNS]
-    arr = (C.POINTER(C.c_double) * 11)(*[_dptr(a) for a in arrs])
+    arrs = [np.ascontiguousarray(cols[c] if c in cols else np.zeros(n), dtype=np.float64)
+            for c in COLUMNS]
+    arr = (C.POINTER(C.c_double) * 12)(*[_dptr(a) for a in arrs])
     o = _alloc_out(n)
     rc = lib().orc_rollout_given(C.byref(scenario(d)), arr, n, int(bool(clamp_state)),
                                  *_out_ptrs(o, 0, n))

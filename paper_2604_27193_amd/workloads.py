@@ -21,6 +21,8 @@ Workloads:
   * ``uneven_batch`` -- 1,000 scenarios with log-uniform sample counts, random
     horizons and steps, scenario means drawn from seed 7.
   * ``serving_stream`` -- Poisson arrivals of randomized single scenarios.
+  * ``perception`` -- ``single`` with a stochastic brake trigger from frame
+    sensing: occlusion, per-frame dropout, a confirmation run and latency.
 """
 import numpy as np
 
@@ -137,3 +139,21 @@ def serving_stream(rate, duration=60.0, seed=None, sizes=(25_000, 100_000, 1_000
         reqs.append((t, d, deadline))
         k += 1
     return reqs
+
+
+def perception(n=10_000, seed=42, scenario_id=0, **over):
+    """The stationary-obstacle scenario with a stochastic brake trigger.
+
+    Sensing runs at 20 Hz (frame period 50 ms); the obstacle is hidden for the
+    first U(0, 4) frames, each later frame misses it with probability 0.1, and
+    braking is requested after 3 consecutive detections plus a processing
+    latency ~ N(80 ms, 20 ms) truncated to [30, 120] ms (120 ms being the
+    perception allowance of the timing budget in Section VI-F;
+    perception effects are the extension named in Section VIII).
+    """
+    d = single(n, seed, scenario_id)
+    d.update({"latency": ("trunc_normal", 0.08, 0.02, 0.03, 0.12),
+              "occlusion": ("uniform", 0.0, 4.0), "frame_period": 0.05,
+              "p_dropout": 0.1, "confirm": 3})
+    d.update(over)
+    return d
