@@ -60,7 +60,8 @@ enum { AEB_END_STOP = 1, AEB_END_IMPACT = 2, AEB_END_HORIZON = 3, AEB_COLLIDED =
 /* counter slots of the random parameters, one generator stream each */
 enum {
   AEB_SLOT_V0 = 0, AEB_SLOT_MU = 1, AEB_SLOT_MASS = 2, AEB_SLOT_GRADE = 3, AEB_SLOT_CDA = 4,
-  AEB_SLOT_CRR = 5, AEB_SLOT_TAU = 6, AEB_SLOT_GAP = 7, AEB_SLOT_LEAD = 8
+  AEB_SLOT_CRR = 5, AEB_SLOT_TAU = 6, AEB_SLOT_GAP = 7, AEB_SLOT_LEAD = 8,
+  AEB_SLOT_LATENCY = 9, AEB_SLOT_OCCLUSION = 10, AEB_SLOT_DETECT = 11
 };
 
 /* Distribution of one uncertain parameter (eq. (11)-(15) use NORMAL).
@@ -87,10 +88,25 @@ typedef struct {
  *     AEB_EULER.
  *   dt, horizon: step and T_max; the rollout takes at most llround(horizon/dt)
  *     steps.  dead_time: the brake command is zero for the first
- *     llround(dead_time/dt) steps and a_cmd afterwards.
+ *     llround((dead_time + trigger)/dt) steps and a_cmd afterwards, trigger
+ *     being the sample's perception delay (0 without perception).
  *   g, rho, h_cog, wheelbase: eq. (4)-(5) constants.
  *   v0 .. lead_decel: distributions; cda is the product C_d A_f (m^2), grade is
- *     theta, tau the actuator time constant of eq. (6). */
+ *     theta, tau the actuator time constant of eq. (6).
+ *   Perception (sensing latency, dropout and occlusion, the perception effects
+ *   of Sec. VIII), giving each sample a brake-trigger delay:
+ *     latency: processing delay (s), values below 0 taken as 0.
+ *     frame_period: sensing period P (s); 0 = no frames, trigger = latency.
+ *     occlusion: frames during which the object is hidden: the first
+ *       floor(occlusion) frames (values below 0 taken as 0) cannot detect it.
+ *     p_dropout: probability in [0, 1) that a later frame misses the object;
+ *       frame j's decision uses the uniform of word j mod 2 of the generator
+ *       call (i, AEB_SLOT_DETECT | (j / 2) << 8, ...), detected if u >= p.
+ *     confirm: detections in a row (1..64) that confirm the object.
+ *     trigger = J P + latency with J the first frame that completes `confirm`
+ *     consecutive detections, searched over frames j with j P <= horizon;
+ *     +inf (no braking) if there is none.  latency CONST 0 and frame_period 0
+ *     switch perception off (trigger = 0) and draw nothing. */
 typedef struct {
   uint64_t seed;
   uint64_t scenario_id;
@@ -101,12 +117,19 @@ typedef struct {
   int32_t nofma;
   double dt, horizon, dead_time, a_cmd, g, rho, h_cog, wheelbase;
   aeb_dist v0, mu, mass, grade, cda, crr, tau, gap, lead_decel;
+  aeb_dist latency, occlusion;
+  double frame_period, p_dropout;
+  int32_t confirm;
+  int32_t reserved2;
 } aeb_scenario;
 
 /* Structure-of-arrays parameter columns, each `n` doubles (host or device,
- * as the called function states).  sin_grade/cos_grade hold sin/cos of grade. */
+ * as the called function states).  sin_grade/cos_grade hold sin/cos of grade;
+ * trigger the perception delay in seconds (+inf: never confirmed).  A NULL
+ * trigger column reads as zeros; a scenario with perception needs it. */
 typedef struct {
   double *v0, *mu, *mass, *grade, *sin_grade, *cos_grade, *cda, *crr, *tau, *gap, *lead_decel;
+  double* trigger;
   int64_t n;
 } aeb_params;
 
@@ -169,7 +192,9 @@ int aeb_version(void);
  * horizon/dt outside [1, 2^31-1]; negative dead_time; wheelbase <= 0; unknown
  * enums; non-finite distribution parameters, sd < 0, uniform p0 > p1,
  * truncation lo >= hi; a tau distribution that can reach 0 (or, for Euler,
- * values below dt); RK4 combined with a lead vehicle. */
+ * values below dt); RK4 combined with a lead vehicle; for perception:
+ * frame_period negative or not finite, more than 1e6 frames over the horizon,
+ * p_dropout outside [0, 1), confirm outside [1, 64]. */
 int aeb_validate(const aeb_scenario* scn);
 
 /* Raw generator output (Sec. IV-B "fixed seed"; Philox4x32-10 of Salmon et

@@ -14,10 +14,14 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libaeb.so")
+ABI_VERSION = 3     # the aeb_version() these structures match
 
 COLUMNS = ("v0", "mu", "mass", "grade", "sin_grade", "cos_grade", "cda", "crr", "tau", "gap",
-           "lead_decel")
+           "lead_decel", "trigger")
 DISTS = ("v0", "mu", "mass", "grade", "cda", "crr", "tau", "gap", "lead_decel")
+# perception fields and their values when a scenario dict leaves them out
+PERCEPTION_DEFAULTS = {"latency": ("const", 0.0), "occlusion": ("const", 0.0),
+                       "frame_period": 0.0, "p_dropout": 0.0, "confirm": 1}
 INTEGRATORS = {"euler": 0, "rk4": 1}
 OBSTACLES = {"none": 0, "stationary": 1, "lead": 2}
 DIST_KINDS = {"const": 0, "uniform": 1, "normal": 2, "trunc_normal": 3}
@@ -52,7 +56,9 @@ class Scenario(C.Structure):
                  ("impact_exit", C.c_int32), ("nofma", C.c_int32)]
                 + [(f, C.c_double) for f in ("dt", "horizon", "dead_time", "a_cmd", "g", "rho",
                                              "h_cog", "wheelbase")]
-                + [(f, Dist) for f in DISTS])
+                + [(f, Dist) for f in DISTS]
+                + [("latency", Dist), ("occlusion", Dist), ("frame_period", C.c_double),
+                   ("p_dropout", C.c_double), ("confirm", C.c_int32), ("reserved2", C.c_int32)])
 
 
 class Params(C.Structure):
@@ -109,6 +115,9 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
         L = C.CDLL(LIB_PATH)
+        if L.aeb_version() != ABI_VERSION:
+            raise ImportError(f"{LIB_PATH} has ABI version {L.aeb_version()}, the binding "
+                              f"needs {ABI_VERSION}; rebuild it with __graft_entry__.build()")
         P = C.POINTER
         L.aeb_last_error.restype = C.c_char_p
         L.aeb_validate.argtypes = [P(Scenario)]
@@ -174,6 +183,13 @@ def scenario(d):
         setattr(s, f, float(d[f]))
     for f in DISTS:
         setattr(s, f, _dist(d[f]))
+    per = dict(PERCEPTION_DEFAULTS)
+    per.update({k: d[k] for k in PERCEPTION_DEFAULTS if k in d})
+    s.latency = _dist(per["latency"])
+    s.occlusion = _dist(per["occlusion"])
+    s.frame_period = float(per["frame_period"])
+    s.p_dropout = float(per["p_dropout"])
+    s.confirm = int(per["confirm"])
     return s
 
 
@@ -208,7 +224,7 @@ def uniforms(seed, scenario_id, first, count, slot, attempt=0, device=True, stre
 
 
 def alloc_params(n, device=True, pinned=False):
-    """Dict of eleven float64 columns: cuda tensors, pinned host tensors or numpy arrays."""
+    """Dict of the twelve float64 columns: cuda tensors, pinned host tensors or numpy arrays."""
     if device or pinned:
         torch = _torch()
         if device:
@@ -224,9 +240,10 @@ def _ptr(a):
 
 
 def _params_struct(cols, n):
+    """Columns by name; a missing trigger column is passed as NULL (zero delay)."""
     p = Params()
     for c in COLUMNS:
-        setattr(p, c, _ptr(cols[c]))
+        setattr(p, c, _ptr(cols[c]) if c in cols or c != "trigger" else None)
     p.n = n
     return p
 

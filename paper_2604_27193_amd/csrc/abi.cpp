@@ -129,6 +129,14 @@ int validate(const aeb_scenario& s) {
   static const char* names[9] = {"v0", "mu", "mass", "grade", "cda", "crr", "tau", "gap", "lead_decel"};
   for (int k = 0; k < 9; ++k)
     if (!dist_ok(*all[k])) return fail(AEB_EINVAL, std::string("invalid distribution for ") + names[k]);
+  if (!dist_ok(s.latency)) return fail(AEB_EINVAL, "invalid distribution for latency");
+  if (!dist_ok(s.occlusion)) return fail(AEB_EINVAL, "invalid distribution for occlusion");
+  if (!(s.frame_period >= 0.0) || !std::isfinite(s.frame_period))
+    return fail(AEB_EINVAL, "frame_period must be >= 0 and finite");
+  if (s.frame_period > 0.0 && !(s.horizon / s.frame_period <= 1.0e6))
+    return fail(AEB_EINVAL, "more than 1e6 sensing frames over the horizon");
+  if (!(s.p_dropout >= 0.0 && s.p_dropout < 1.0)) return fail(AEB_EINVAL, "p_dropout out of [0, 1)");
+  if (s.confirm < 1 || s.confirm > 64) return fail(AEB_EINVAL, "confirm out of [1, 64]");
   double tmin = support_min(s.tau);
   if (!(tmin > 0.0)) return fail(AEB_EINVAL, "tau distribution can reach 0");
   if (s.integrator == AEB_EULER && tmin < s.dt)
@@ -215,7 +223,7 @@ extern "C" {
 
 const char* aeb_last_error(void) { return g_err.c_str(); }
 
-int aeb_version(void) { return 2; }
+int aeb_version(void) { return 3; }
 
 int aeb_timing_enable(int on) {
   g_timing.on = on != 0;
@@ -263,6 +271,8 @@ int aeb_sample_params(const aeb_scenario* scn, int64_t first, int64_t count, con
   if (rc != AEB_OK) return rc;
   if (first < 0 || count < 0 || first + count > (int64_t(1) << 32))
     return fail(AEB_EINVAL, "aeb_sample_params: sample range out of [0, 2^32)");
+  if (perception_on(*scn) && !out->trigger)
+    return fail(AEB_EINVAL, "aeb_sample_params: a scenario with perception needs the trigger column");
   if (count == 0) return AEB_OK;
   if (on_device) return launch_sample(*scn, first, count, *out, static_cast<hipStream_t>(stream));
   // the paper's plain method: draw on the host with host libm, all cores
@@ -282,6 +292,7 @@ int aeb_sample_params(const aeb_scenario* scn, int64_t first, int64_t count, con
       p.tau[k] = q.tau;
       p.gap[k] = q.gap;
       p.lead_decel[k] = q.lead_decel;
+      if (p.trigger) p.trigger[k] = q.trigger;
     }
   };
   int nt = host_threads();
@@ -310,8 +321,11 @@ int aeb_rollout(const aeb_scenario* scn, const aeb_params* params, int precision
   if (params) {
     if (!params_complete(params)) return fail(AEB_EINVAL, "aeb_rollout: incomplete parameter columns");
     if (params->n != scn->n_samples) return fail(AEB_EINVAL, "parameter length differs from n_samples");
+    if (perception_on(*scn) && !params->trigger)
+      return fail(AEB_EINVAL, "aeb_rollout: a scenario with perception needs the trigger column");
     src = ParamSrc{params->v0, params->mu,  params->mass, params->sin_grade, params->cos_grade,
-                   params->cda, params->crr, params->tau, params->gap, params->lead_decel};
+                   params->cda, params->crr, params->tau, params->gap, params->lead_decel,
+                   params->trigger};
   }
   OutCols oc{out->dist, out->status, out->steps, out->margin, out->v_impact};
   return launch_rollout(*scn, params ? &src : nullptr, precision, oc, scn->n_samples,

@@ -104,9 +104,53 @@ __host__ __device__ inline double draw(const aeb_dist& d, uint64_t seed, uint64_
   return val < d.lo ? d.lo : d.hi;
 }
 
+// ---------------------------------------------------------------------------
+// Perception (sensing latency, dropout and occlusion; Sec. VIII): the delay
+// from the start of the rollout to the brake request.  Frames come every
+// frame_period seconds; the first floor(occlusion) cannot see the object; a
+// later frame j detects it when its uniform (word j mod 2 of the call with
+// attempt j / 2 on the DETECT slot) is at least p_dropout; the request
+// follows the frame that completes `confirm` detections in a row, plus the
+// processing latency.  No such frame up to the horizon: +inf.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline bool perception_on(const aeb_scenario& s) {
+  return !(s.latency.kind == AEB_DIST_CONST && s.latency.p0 == 0.0 && s.frame_period == 0.0);
+}
+
+__host__ __device__ inline double trigger_delay(const aeb_scenario& s, uint64_t i) {
+  double lat = draw(s.latency, s.seed, s.scenario_id, i, AEB_SLOT_LATENCY);
+  if (!(lat > 0.0)) lat = 0.0;
+  if (s.frame_period == 0.0) return lat;
+  const double occ = draw(s.occlusion, s.seed, s.scenario_id, i, AEB_SLOT_OCCLUSION);
+  // frames j = 0 .. last with j * frame_period <= horizon (at most 1e6 + 1)
+  const int64_t last = static_cast<int64_t>(floor(s.horizon / s.frame_period));
+  int64_t j = 0;
+  if (occ > 0.0) j = occ <= static_cast<double>(last) ? static_cast<int64_t>(floor(occ)) : last + 1;
+  const int64_t first = j;
+  int run = 0;
+  U2 u{0.0, 0.0};
+  for (; j <= last; ++j) {
+    if ((j & 1) == 0 || j == first)
+      u = uniform2(s.seed, s.scenario_id, i, AEB_SLOT_DETECT, static_cast<uint32_t>(j >> 1));
+    const double uj = (j & 1) ? u.b : u.a;
+    run = uj >= s.p_dropout ? run + 1 : 0;
+    if (run == s.confirm) return static_cast<double>(j) * s.frame_period + lat;
+  }
+  return INFINITY;
+}
+
+// First step with the brake command for a sample with trigger delay `trig`:
+// llround((dead_time + trig) / dt), capped at nmax (a command at or beyond the
+// last step is never applied, so every value from nmax up acts the same).
+__host__ __device__ inline int64_t command_step(const aeb_scenario& s, double trig, int64_t nmax) {
+  const double q = round((s.dead_time + trig) / s.dt);
+  return q < static_cast<double>(nmax) ? static_cast<int64_t>(q) : nmax;
+}
+
 // One realised parameter vector.
 struct Sample {
   double v0, mu, mass, grade, sin_grade, cos_grade, cda, crr, tau, gap, lead_decel;
+  double trigger;  // perception delay (s), 0 without perception
 };
 
 __host__ __device__ inline Sample draw_sample(const aeb_scenario& s, uint64_t i) {
@@ -122,6 +166,7 @@ __host__ __device__ inline Sample draw_sample(const aeb_scenario& s, uint64_t i)
   p.tau = draw(s.tau, s.seed, s.scenario_id, i, AEB_SLOT_TAU);
   p.gap = draw(s.gap, s.seed, s.scenario_id, i, AEB_SLOT_GAP);
   p.lead_decel = draw(s.lead_decel, s.seed, s.scenario_id, i, AEB_SLOT_LEAD);
+  p.trigger = perception_on(s) ? trigger_delay(s, i) : 0.0;
   return p;
 }
 

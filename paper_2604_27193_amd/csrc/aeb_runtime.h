@@ -49,6 +49,7 @@ int64_t dead_steps(const aeb_scenario& s);
 // Kernel-side view of the parameter source: device columns or the generator.
 struct ParamSrc {
   const double *v0, *mu, *mass, *sin_g, *cos_g, *cda, *crr, *tau, *gap, *lead;
+  const double* trig;  // perception delay; null reads as 0
 };
 
 struct OutCols {

@@ -136,8 +136,11 @@ int aeb_graph_create(const aeb_scenario* scn, const aeb_params* params, int prec
         !params->cos_grade || !params->cda || !params->crr || !params->tau || !params->gap ||
         !params->lead_decel || params->n != scn->n_samples)
       return fail(AEB_EINVAL, "aeb_graph_create: incomplete parameter columns");
+    if (perception_on(*scn) && !params->trigger)
+      return fail(AEB_EINVAL, "aeb_graph_create: a scenario with perception needs the trigger column");
     src = ParamSrc{params->v0, params->mu,  params->mass, params->sin_grade, params->cos_grade,
-                   params->cda, params->crr, params->tau, params->gap, params->lead_decel};
+                   params->cda, params->crr, params->tau, params->gap, params->lead_decel,
+                   params->trigger};
   }
   aeb_graph* g = new (std::nothrow) aeb_graph;
   if (!g) return fail(AEB_ENOMEM, "host allocation failed");

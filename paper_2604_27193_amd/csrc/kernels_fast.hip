@@ -14,7 +14,9 @@
 //     together and long wavefronts start early.
 //  3. rollout: each lane integrates one sample.  Steps run in unchecked
 //     blocks of K steps whenever no lane can stop, reach the horizon or pass
-//     the dead-time switch inside the block (guaranteed by per-lane bounds);
+//     its command switch inside the block (guaranteed by per-lane bounds; the
+//     switch is the dead time, plus the sample's own perception delay when
+//     the scenario has one, and then the sort groups equal switch steps);
 //     otherwise single steps with every test.  Inside a block the step takes
 //     the cheapest form that gives bit-identical results in the current
 //     phase: dead time (a = 0), generic, never-limited (max(a, alim) = a) or
@@ -80,6 +82,7 @@ struct PrepArgs {
   const aeb_scenario* scns;  // batch: scenarios
   const ScnDev* tab;         // batch: per-scenario constants and offsets
   int n_scn;
+  int32_t* nds;              // per-sample command step (launches with perception), else null
 };
 
 template <bool DEVRNG, bool BATCH>
@@ -111,15 +114,23 @@ __global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job
     const aeb_scenario& s = BATCH ? a.scns[j] : a.s;
     const int nd = BATCH ? a.tab[j].nd : a.nd;
     const int nmax = BATCH ? a.tab[j].nmax : a.nmax;
-    double v0, mu, mass, sg, cg, cda, crr, tau, gap, lead;
+    double v0, mu, mass, sg, cg, cda, crr, tau, gap, lead, trig;
     if (DEVRNG) {
       Sample q = draw_sample(s, static_cast<uint64_t>(local));
       v0 = q.v0; mu = q.mu; mass = q.mass; sg = q.sin_grade; cg = q.cos_grade;
       cda = q.cda; crr = q.crr; tau = q.tau; gap = q.gap; lead = q.lead_decel;
+      trig = q.trigger;
     } else {
       v0 = a.src.v0[i]; mu = a.src.mu[i]; mass = a.src.mass[i]; sg = a.src.sin_g[i];
       cg = a.src.cos_g[i]; cda = a.src.cda[i]; crr = a.src.crr[i]; tau = a.src.tau[i];
       gap = a.src.gap[i]; lead = a.src.lead[i];
+      trig = a.src.trig ? a.src.trig[i] : 0.0;
+    }
+    // with perception every sample has its own command step
+    int ndl = nd;
+    if (a.nds) {
+      ndl = static_cast<int>(command_step(s, trig, nmax));
+      a.nds[i] = ndl;
     }
     const Consts k = derive(s, mu, mass, sg, cg, cda, crr);
     Job J;
@@ -140,7 +151,7 @@ __global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job
     const float t = predict_stop_time(static_cast<float>(v0), static_cast<float>(k.kd),
                                       static_cast<float>(k.c), static_cast<float>(k.alim),
                                       static_cast<float>(tau), static_cast<float>(s.a_cmd),
-                                      static_cast<float>(nd) * static_cast<float>(s.dt));
+                                      static_cast<float>(ndl) * static_cast<float>(s.dt));
     float steps = t / static_cast<float>(s.dt);
     if (!(steps < static_cast<float>(nmax))) steps = static_cast<float>(nmax);
     if (!(steps > 0.0f)) steps = 0.0f;
@@ -150,7 +161,11 @@ __global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job
     if (leads) leads[i].decel = lead;
     const uint32_t u = static_cast<uint32_t>(fminf(steps, a.cap) * (4096.0f / (a.cap + 1.0f)));
     const uint32_t ud = 4095u - (u > 4095u ? 4095u : u);  // longest first
-    const uint32_t key = ((ud >> 6) << 7) | (limited ? 0u : 64u) | (ud & 63u);
+    // within a coarse length bin: finer length, or with perception the command
+    // step in 8-step bins (so a wavefront's lanes switch the command together
+    // and its blocks are rarely cut at a lane's switch)
+    const uint32_t fine = a.nds ? (static_cast<uint32_t>(ndl) >> 3) & 63u : ud & 63u;
+    const uint32_t key = ((ud >> 6) << 7) | (limited ? 0u : 64u) | fine;
     keys[i] = key;
     atomicAdd(&hist[key], 1u);
   }
@@ -331,6 +346,7 @@ struct Ctx {
   int nd, nmax, impact_exit;
   OutCols out;
   const ScnDev* tab;
+  const int32_t* nds;  // per-sample command steps (perception), else null
 };
 
 struct LaneScn {
@@ -339,7 +355,7 @@ struct LaneScn {
 };
 
 template <bool BATCH>
-__device__ inline LaneScn lane_scn(const Ctx& c, const Job& J) {
+__device__ inline LaneScn lane_scn(const Ctx& c, const Job& J, bool valid, uint32_t g) {
   LaneScn r;
   if (BATCH) {
     const ScnDev& t = c.tab[J.scn];
@@ -353,6 +369,7 @@ __device__ inline LaneScn lane_scn(const Ctx& c, const Job& J) {
     r.nd = c.nd;
     r.nmax = c.nmax;
   }
+  if (c.nds && valid) r.nd = c.nds[g];
   return r;
 }
 
@@ -384,9 +401,9 @@ __device__ inline int wave_min(int x) {
   return __builtin_amdgcn_readfirstlane(x);
 }
 
-template <bool BATCH>
-__device__ inline int wave_lim(bool active, int k, int nd, int nmax) {
-  if (!BATCH) return lane_lim(k, nd, nmax);  // nd, nmax are uniform
+// varnd: nd or nmax differ between lanes (a batch, or per-sample command steps)
+__device__ inline int wave_lim(bool varnd, bool active, int k, int nd, int nmax) {
+  if (!varnd) return lane_lim(k, nd, nmax);  // nd, nmax are uniform
   return wave_min(active ? lane_lim(k, nd, nmax) : INT_MAX);
 }
 
@@ -476,8 +493,9 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
       J = Job{1.0, 0.0, 0.0, -1.0, 0.5, 1e30, 1.0, 0.0f, 0u};
     }
     const double al = (LEAD && valid) ? leads[g].decel : 0.0;
-    const LaneScn c = lane_scn<BATCH>(ctx, J);
-    const int wnd = BATCH ? wave_min(valid ? c.nd : INT_MAX) : c.nd;
+    const LaneScn c = lane_scn<BATCH>(ctx, J, valid, g);
+    const bool varnd = BATCH || ctx.nds;
+    const int wnd = varnd ? wave_min(valid ? c.nd : INT_MAX) : c.nd;
     // v above these cannot reach 0 within a block (|dv/dt| <= dmax)
     const double thr_k = static_cast<double>(K) * c.dt * J.dmax;
     const double thr_s = static_cast<double>(KS) * c.dt * J.dmax;
@@ -509,7 +527,7 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
       // the step index is the same in every lane: keep it (and the branches on it) scalar
       k = __builtin_amdgcn_readfirstlane(k);
       if (!__any(L.active)) break;
-      if (!BATCH || k >= wl) wl = wave_lim<BATCH>(L.active, k, c.nd, c.nmax);
+      if (!varnd || k >= wl) wl = wave_lim(varnd, L.active, k, c.nd, c.nmax);
       if (k + K <= wl && !__any(L.active && L.s.v <= thr_k)) {
         run_block64<OBS, K, INTEG>(L, J, al, c, k, wnd, ctx.impact_exit);
         if (INTEG == AEB_RK4 && L.active) xmax = fmax(xmax, L.s.x);
@@ -761,9 +779,10 @@ __global__ __launch_bounds__(256) void k_roll_fp32c(const Job* __restrict__ jobs
     } else {
       J = Job{1.0, 0.0, 0.0, -1.0, 0.5, 1e30, 1.0, 0.0f, 0u};
     }
-    const LaneScn sc = lane_scn<BATCH>(ctx, J);
+    const LaneScn sc = lane_scn<BATCH>(ctx, J, valid, g);
     const int nd = sc.nd, nmax = sc.nmax;
-    const int wnd = BATCH ? wave_min(valid ? nd : INT_MAX) : nd;
+    const bool varnd = BATCH || ctx.nds;
+    const int wnd = varnd ? wave_min(valid ? nd : INT_MAX) : nd;
     L32 c;  // (the speed read below is base + increment; the increment is 0 without compensation)
     c.dt = static_cast<float>(sc.dt);
     c.nkd = static_cast<float>(J.nkd);
@@ -799,7 +818,7 @@ __global__ __launch_bounds__(256) void k_roll_fp32c(const Job* __restrict__ jobs
       // the step index is the same in every lane: keep it (and the branches on it) scalar
       k = __builtin_amdgcn_readfirstlane(k);
       if (!__any(L.active)) break;
-      if (!BATCH || k >= wl) wl = wave_lim<BATCH>(L.active, k, nd, nmax);
+      if (!varnd || k >= wl) wl = wave_lim(varnd, L.active, k, nd, nmax);
       // the command switches on at step nd: e = a - cmd jumps by -a_cmd.  Blocks
       // never straddle nd, so every lane passes through k == nd at a loop top.
       if (k == nd) L.s.e += c.ejump;
@@ -1026,9 +1045,10 @@ __global__ __launch_bounds__(256) void k_roll_fp32c_lead(const Job* __restrict__
       J = Job{1.0, 0.0, 0.0, -1.0, 0.5, 1e30, 1.0, 0.0f, 0u};
     }
     const float al = valid ? static_cast<float>(leads[g].decel) : 0.0f;
-    const LaneScn sc = lane_scn<BATCH>(ctx, J);
+    const LaneScn sc = lane_scn<BATCH>(ctx, J, valid, g);
     const int nd = sc.nd, nmax = sc.nmax;
-    const int wnd = BATCH ? wave_min(valid ? nd : INT_MAX) : nd;
+    const bool varnd = BATCH || ctx.nds;
+    const int wnd = varnd ? wave_min(valid ? nd : INT_MAX) : nd;
     L32 c;
     c.dt = static_cast<float>(sc.dt);
     c.nkd = static_cast<float>(J.nkd);
@@ -1069,7 +1089,7 @@ __global__ __launch_bounds__(256) void k_roll_fp32c_lead(const Job* __restrict__
     for (;;) {
       k = __builtin_amdgcn_readfirstlane(k);
       if (!__any(L.active)) break;
-      if (!BATCH || k >= wl) wl = wave_lim<BATCH>(L.active, k, nd, nmax);
+      if (!varnd || k >= wl) wl = wave_lim(varnd, L.active, k, nd, nmax);
       if (k == nd) L.s.e += c.ejump;
       const float v_now = L.s.vb + L.s.vi;
       if (k % K == 0 && k + K <= wl && !__any(L.active && v_now <= c.thr)) {
@@ -1205,20 +1225,23 @@ struct Bufs {
   LeadJob* leads;
   uint32_t* keys;
   uint32_t* perm;
+  int32_t* nds;
   uint32_t* hist;
   unsigned long long* counter;
   ScnDev* tab;
   aeb_scenario* scns;
 };
 
-// scratch: jobs | leads | keys | perm | histogram | counter | scenario tables
+// scratch: jobs | leads | keys | perm | command steps | histogram | counter |
+// scenario tables
 size_t bufs_layout(int64_t n, int n_scn, bool lead, char* base, Bufs* b) {
   auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
   const size_t off_jobs = 0;
   const size_t off_leads = up(off_jobs + sizeof(Job) * n);
   const size_t off_keys = up(off_leads + (lead ? sizeof(LeadJob) * n : 0));
   const size_t off_perm = up(off_keys + sizeof(uint32_t) * n);
-  const size_t off_hist = up(off_perm + sizeof(uint32_t) * n);
+  const size_t off_nds = up(off_perm + sizeof(uint32_t) * n);
+  const size_t off_hist = up(off_nds + sizeof(int32_t) * n);
   const size_t off_cnt = up(off_hist + sizeof(uint32_t) * NBINS);
   const size_t off_tab = up(off_cnt + sizeof(unsigned long long));
   const size_t off_scn = up(off_tab + sizeof(ScnDev) * n_scn);
@@ -1228,6 +1251,7 @@ size_t bufs_layout(int64_t n, int n_scn, bool lead, char* base, Bufs* b) {
     b->leads = lead ? reinterpret_cast<LeadJob*>(base + off_leads) : nullptr;
     b->keys = reinterpret_cast<uint32_t*>(base + off_keys);
     b->perm = reinterpret_cast<uint32_t*>(base + off_perm);
+    b->nds = reinterpret_cast<int32_t*>(base + off_nds);
     b->hist = reinterpret_cast<uint32_t*>(base + off_hist);
     b->counter = reinterpret_cast<unsigned long long*>(base + off_cnt);
     b->tab = reinterpret_cast<ScnDev*>(base + off_tab);
@@ -1367,6 +1391,7 @@ int launch_rollout_fast_into(const aeb_scenario& s, const ParamSrc* src, int pre
   pa.nd = static_cast<int>(nd);
   pa.nmax = static_cast<int>(nmax);
   pa.cap = static_cast<float>(nmax);
+  pa.nds = perception_on(s) ? b.nds : nullptr;
   if (src)
     hipLaunchKernelGGL((k_prep<false, false>), dim3(pblk), dim3(PREP_BLOCK), 0, st, pa, b.jobs,
                        b.leads, b.keys, b.hist);
@@ -1382,6 +1407,7 @@ int launch_rollout_fast_into(const aeb_scenario& s, const ParamSrc* src, int pre
   ctx.impact_exit = s.impact_exit;
   ctx.out = out;
   ctx.tab = nullptr;
+  ctx.nds = pa.nds;
   return integrate<false>(s, precision, b, n, ctx, src, st);
 }
 
@@ -1433,12 +1459,16 @@ int launch_batch_fast_into(const aeb_scenario* scns, int n_scn, int precision,
   pa.scns = b.scns;
   pa.tab = b.tab;
   pa.n_scn = n_scn;
+  bool perc = false;
+  for (int j = 0; j < n_scn; ++j) perc = perc || perception_on(scns[j]);
+  pa.nds = perc ? b.nds : nullptr;
   hipLaunchKernelGGL((k_prep<true, true>), dim3(pblk), dim3(PREP_BLOCK / 2), 0, st, pa, b.jobs,
                      b.leads, b.keys, b.hist);
   sort_keys(b, total, st);
   Ctx ctx{};
   ctx.impact_exit = scns[0].impact_exit;
   ctx.tab = b.tab;
+  ctx.nds = pa.nds;
   return integrate<true>(scns[0], precision, b, total, ctx, nullptr, st);
 }
 

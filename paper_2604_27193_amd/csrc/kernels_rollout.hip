@@ -27,6 +27,7 @@ __device__ inline Lane load_lane(const aeb_scenario& s, const ParamSrc& src, int
     L.tau = q.tau;
     L.gap = q.gap;
     L.lead = q.lead_decel;
+    L.trig = q.trigger;
   } else {
     L.v0 = src.v0[i];
     mu = src.mu[i];
@@ -38,6 +39,7 @@ __device__ inline Lane load_lane(const aeb_scenario& s, const ParamSrc& src, int
     L.tau = src.tau[i];
     L.gap = src.gap[i];
     L.lead = src.lead[i];
+    L.trig = src.trig ? src.trig[i] : 0.0;
   }
   L.k = derive(s, mu, mass, sg, cg, cda, crr);
   return L;
@@ -57,6 +59,8 @@ __global__ __launch_bounds__(256) void k_rollout_fp64(aeb_scenario s, ParamSrc s
   int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   Lane L = load_lane<DEVRNG>(s, src, i);
+  // with perception the command step is the sample's own
+  if (perception_on(s)) nd = command_step(s, L.trig, nmax);
   Result r = (INTEG == AEB_EULER) ? euler_fp64<OBS, NOFMA>(L, s.dt, s.a_cmd, nd, nmax, s.impact_exit)
                                   : rk4_fp64<OBS>(L, s.dt, s.a_cmd, nd, nmax, s.impact_exit);
   store(out, i, r);
@@ -71,7 +75,8 @@ __global__ __launch_bounds__(256) void k_fixup_fp64(aeb_scenario s, ParamSrc src
   for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < cnt; j += gridDim.x * blockDim.x) {
     int64_t i = fix[1 + j];
     Lane L = load_lane<DEVRNG>(s, src, i);
-    Result r = euler_fp64<OBS, false>(L, s.dt, s.a_cmd, nd, nmax, s.impact_exit);
+    const int64_t ndl = perception_on(s) ? command_step(s, L.trig, nmax) : nd;
+    Result r = euler_fp64<OBS, false>(L, s.dt, s.a_cmd, ndl, nmax, s.impact_exit);
     store(out, i, r);
   }
 }

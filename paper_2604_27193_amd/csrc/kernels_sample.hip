@@ -33,6 +33,7 @@ __global__ __launch_bounds__(256) void k_sample(aeb_scenario s, int64_t first, i
   p.tau[k] = q.tau;
   p.gap[k] = q.gap;
   p.lead_decel[k] = q.lead_decel;
+  if (p.trigger) p.trigger[k] = q.trigger;
 }
 
 int launch_uniforms(uint64_t seed, uint64_t sid, int64_t first, int64_t count, uint32_t slot,

@@ -29,6 +29,7 @@ struct Lane {
   double v0, gap, lead;  // initial speed, initial gap, lead deceleration
   Consts k;
   double tau;
+  double trig;           // perception delay (s)
 };
 
 // ---------------------------------------------------------------------------

@@ -39,7 +39,7 @@ def test_exports_listed_in_binding(B):
 
 
 def test_version(B):
-    assert B.lib().aeb_version() >= 1
+    assert B.lib().aeb_version() == B.ABI_VERSION
 
 
 def test_validation_agrees_with_reference(B, orc):
@@ -61,7 +61,11 @@ def test_host_uniforms_bitwise(B, orc, seed, sid, slot, attempt):
 
 
 @pytest.mark.parametrize("d", [W.single(20_000), W.paper_preset(5000), W.sweep(n=3000)[37],
-                               W.uneven_batch(4)[1]])
+                               W.uneven_batch(4)[1], W.perception(20_000),
+                               W.perception(5000, occlusion=("normal", 1.0, 3.0), p_dropout=0.6,
+                                            confirm=4, latency=("normal", 0.0, 0.05)),
+                               W.perception(3000, frame_period=0.0),
+                               W.perception(3000, occlusion=("const", 1e30), horizon=1.0)])
 def test_host_sampler_bitwise(B, orc, d):
     n = min(int(d["n_samples"]), 20_000)
     got = B.sample_params(d, 0, n, device=False)
@@ -76,6 +80,23 @@ def test_host_sampler_subrange(B, orc):
     want = orc.sample(d, 4321, 777)
     for c in B.COLUMNS:
         assert np.array_equal(got[c], want[c]), c
+
+
+def test_perception_validation_agrees(B, orc):
+    from test_oracle_perception import BAD
+    for change in BAD:
+        d = W.perception(10)
+        d.update(change)
+        assert B.validate(d) == B.EINVAL == orc.validate(d), change
+    assert B.validate(W.perception(10)) == B.OK
+
+
+def test_perception_needs_trigger_column(B):
+    cols = {c: np.zeros(10) for c in B.COLUMNS if c != "trigger"}
+    with pytest.raises(B.AebError) as e:
+        B.sample_params(W.perception(10), 0, 10, device=False, out=cols)
+    assert e.value.code == B.EINVAL
+    B.sample_params(W.single(10), 0, 10, device=False, out=cols)   # no perception: optional
 
 
 def test_host_sampler_rejects_invalid(B):

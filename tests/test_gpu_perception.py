@@ -1,0 +1,183 @@
+"""GPU parity of the perception workload (a stochastic brake-trigger delay
+from sensing latency, occlusion, per-frame dropout and a confirmation run;
+the perception effects named in Sec. VIII) against the FP64 reference.
+
+Every sample now has its own command step, so the block-structured path runs
+wavefronts whose lanes switch the brake on at different steps; the bars are
+those of the rest of the rollout: FP64 exact for host-sampled inputs and
+within 1e-12 for in-kernel draws, FP32C within 1e-4 with flags exact outside
+the boundary band.
+"""
+import numpy as np
+import pytest
+
+from paper_2604_27193_amd import workloads as W
+from test_gpu_parity import check_fp32c, check_fp64, compare_stats, plain, rel_err, to_np, upload
+
+pytestmark = pytest.mark.gpu
+
+RISK = (0.05, 0.01, 0.001)
+MQ = (0.0, 0.01, 0.5)
+GRID = (30.0, 130.0, 64)
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2604_27193_amd import binding
+    binding.lib()
+    return binding
+
+
+def variants():
+    return {
+        "base": W.perception(4000, seed=21),
+        "latency_only": W.perception(3000, frame_period=0.0, latency=("uniform", 0.0, 0.3)),
+        "heavy_dropout": W.perception(3000, p_dropout=0.7, confirm=4, occlusion=("const", 0.0)),
+        "never_confirmed": W.perception(2000, occlusion=("uniform", 150.0, 250.0),
+                                        horizon=9.0),          # part of them never brakes
+        "impact_exit": W.perception(3000, impact_exit=True),
+        "none": W.perception(3000, obstacle="none"),
+        "rk4": W.perception(2000, integrator="rk4"),
+        "rk4_paper": dict(W.paper_preset(2000), latency=("trunc_normal", 0.08, 0.02, 0.03, 0.12),
+                          occlusion=("uniform", 0.0, 4.0), frame_period=0.05, p_dropout=0.1,
+                          confirm=3),
+        "nofma": W.perception(2000, nofma=True),
+        "lead": dict(W.sweep(n=2000)[70], latency=("uniform", 0.05, 0.15), frame_period=0.04,
+                     occlusion=("uniform", 0.0, 6.0), p_dropout=0.2, confirm=2),
+        "dt2ms": W.perception(3000, dt=2e-3),
+    }
+
+
+def test_device_trigger_column(B, orc):
+    for d in (W.perception(30_000), W.perception(20_000, latency=("uniform", 0.01, 0.2),
+                                                 p_dropout=0.5, confirm=5)):
+        got = B.sample_params(d, device=True)["trigger"].cpu().numpy()
+        want = orc.sample(d)["trigger"]
+        if d["latency"][0] == "uniform":          # uniform draws: bit-identical
+            assert np.array_equal(got, want)
+        else:
+            assert rel_err(got, want).max() <= 1e-14
+
+
+@pytest.mark.parametrize("name", list(variants()))
+def test_plain_fp64_exact(B, orc, name):
+    d = variants()[name]
+    check_fp64(to_np(plain(B, d)), orc.run(d), exact=True)
+
+
+@pytest.mark.parametrize("name", ["base", "heavy_dropout", "never_confirmed", "lead", "rk4"])
+def test_device_rng_fp64(B, orc, name):
+    d = variants()[name]
+    check_fp64(to_np(B.rollout(d)), orc.run(d))
+
+
+@pytest.mark.parametrize("n,seed", [(1, 3), (63, 4), (64, 5), (257, 6), (4097, 7)])
+def test_ragged_sizes(B, orc, n, seed):
+    d = W.perception(n, seed=seed)
+    check_fp64(to_np(plain(B, d)), orc.run(d), exact=True)
+    check_fp64(to_np(B.rollout(d)), orc.run(d))
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp32c_fixup"])
+@pytest.mark.parametrize("name", ["base", "heavy_dropout", "never_confirmed", "impact_exit",
+                                  "none", "lead", "dt2ms"])
+def test_fp32c(B, orc, name, prec):
+    d = variants()[name]
+    margin_abs = 2e-3 if name == "lead" else None
+    check_fp32c(to_np(B.rollout(d, precision=prec)), orc.run(d), fixup=prec == "fp32c_fixup",
+                margin_abs=margin_abs)
+
+
+def test_trigger_column_is_read(B, orc):
+    """The plain method takes the caller's trigger column as given."""
+    d = W.perception(3000)
+    host = B.sample_params(d, device=False)
+    host["trigger"] = host["trigger"] + 0.25
+    got = to_np(B.rollout(d, params=upload(host)))
+    ref = orc.rollout_given(d, host)
+    check_fp64(got, ref, exact=True)
+    missing = upload({k: v for k, v in host.items() if k != "trigger"})
+    with pytest.raises(B.AebError) as e:
+        B.rollout(d, params=missing)
+    assert e.value.code == B.EINVAL
+
+
+def test_full_size_sampled(B, orc):
+    """1,048,576 samples in the benchmark's launch shape; 1,000 sampled indices
+    against the reference, and properties over all of them."""
+    d = W.perception(1_048_576)
+    host = B.sample_params(d, device=False)
+    got = to_np(B.rollout(d, params=upload(host)))
+    rng = np.random.default_rng(77)
+    idx = np.unique(np.concatenate([rng.integers(0, d["n_samples"], 1000),
+                                    [0, 1, d["n_samples"] - 1]]))
+    for i in idx:
+        r = orc.run(d, first=int(i), count=1)
+        assert got["status"][i] == r["status"][0] and got["steps"][i] == r["steps"][0], i
+        assert got["dist"][i] == r["dist"][0], i
+    col = (got["status"] & B.COLLIDED) != 0
+    assert np.array_equal(col, got["dist"] > host["gap"])
+    # the delayed command adds steps: never fewer than the command step
+    nd = np.minimum(np.round((d["dead_time"] + host["trigger"]) / d["dt"]), 10_000)
+    assert np.all(got["steps"] >= nd)
+    dev = to_np(B.rollout(d))
+    assert np.array_equal(dev["status"], got["status"])
+    assert rel_err(dev["dist"], got["dist"]).max() <= 1e-12
+
+
+def test_batch_mixed_with_and_without_perception(B, orc):
+    scns = []
+    for j, d in enumerate(W.uneven_batch(6, max_samples=2500)):
+        if j % 2 == 0:
+            d = dict(d, latency=("uniform", 0.02, 0.12), frame_period=0.05,
+                     occlusion=("uniform", 0.0, 3.0), p_dropout=0.15, confirm=2)
+        scns.append(d)
+    for prec in ("fp64", "fp32c"):
+        outs = B.batch_rollout(scns, precision=prec)
+        for d, o in zip(scns, outs):
+            got = to_np(o)
+            if prec == "fp64":
+                check_fp64(got, orc.run(d))
+            else:
+                check_fp32c(got, orc.run(d))
+            alone = to_np(B.rollout(d, precision=prec))
+            for c in got:
+                assert np.array_equal(got[c], alone[c]), c
+
+
+def test_shapes_give_same_bits(B):
+    d = W.perception(20_000, seed=4, scenario_id=2)
+    for prec in ("fp64", "fp32c"):
+        keep = B.tune_get(prec, "stationary")
+        try:
+            ref = to_np(B.rollout(d, precision=prec))
+            for k, blk, w in ((16, 64, 0), (32, 128, 4), (64, 256, 8)):
+                B.tune_set(prec, "stationary", k, blk, w)
+                got = to_np(B.rollout(d, precision=prec))
+                for c in ref:
+                    assert np.array_equal(ref[c], got[c]), (prec, k, blk, w, c)
+        finally:
+            B.tune_set(prec, "stationary", *keep)
+
+
+def test_graph_and_serving(B, orc):
+    d = W.perception(20_000, seed=5, scenario_id=3)
+    ref = B.reduce(B.rollout(d), risk=RISK, margin_q=MQ, grid=GRID)
+    want = orc.reduce(orc.run(d), risk=RISK, margin_q=MQ, grid=GRID)
+    compare_stats(ref, want)
+    g = B.Graph(d, risk=RISK, margin_q=MQ, grid=GRID)
+    for _ in range(3):
+        g.launch()
+        st = g.finish()
+        for k in ("n_collide", "n_stop", "headway", "margin_q", "mean_dist", "sd_dist"):
+            assert st[k] == ref[k], k
+    g.close()
+    with B.Server(128 << 20, max_slots=8, n_streams=2, max_tick_samples=1 << 17,
+                  risk=RISK, margin_q=MQ, grid=GRID) as srv:
+        tickets = [srv.submit(d), srv.submit(W.single(5000, seed=9)), srv.submit(d)]
+        got = [srv.wait(t)[0] for t in tickets]
+    for st in (got[0], got[2]):
+        for k in ("n_collide", "n_stop", "headway", "margin_q", "mean_dist", "sd_dist"):
+            assert st[k] == ref[k], k
