@@ -160,8 +160,9 @@ double orc_trigger_delay(const orc_scenario* s, uint64_t i) {
   if (!(lat > 0.0)) lat = 0.0;
   if (s->frame_period == 0.0) return lat;
   double occ = orc_draw(&s->occlusion, seed, sid, i, ORC_SLOT_OCCLUSION);
-  const long long hidden = occ > 0.0 ? (long long)floor(occ) : 0;
   const long long frames = (long long)floor(s->horizon / s->frame_period) + 1;
+  long long hidden = 0;  /* occluded frames; more than all of them hides every frame */
+  if (occ > 0.0) hidden = occ < (double)frames ? (long long)floor(occ) : frames;
   int run = 0;
   for (long long j = 0; j < frames; ++j) {
     int seen = 0;

@@ -173,6 +173,9 @@ def test_trigger_beyond_horizon_coasts(orc):
     T = 2.0
     d = flat(8, horizon=T, occlusion=("const", 100.0), frame_period=0.05, confirm=1)
     assert np.all(np.isinf(orc.sample(d)["trigger"]))
+    # an occlusion far beyond the frame count hides every frame as well
+    huge = flat(4, horizon=T, occlusion=("const", 1e30), frame_period=0.05)
+    assert np.all(np.isinf(orc.sample(huge)["trigger"]))
     r = orc.run(d)
     assert np.all(r["status"] & 3 == orc.END_HORIZON)
     assert np.all(r["steps"] == 2000)
