@@ -211,6 +211,66 @@ def paper_study_leg(B, W, torch):
             "paper_headways": gold["headways"]["h0"], "step_size": dt_rows}
 
 
+def kernel_ms(B, torch, d, out, precision="fp64", reps=3):
+    """Median integration-kernel time of `reps` rollouts (library HIP events)."""
+    import numpy as np
+    B.rollout(d, out=out, precision=precision)
+    torch.cuda.synchronize()
+    B.timing_enable(True)
+    ks = []
+    for _ in range(reps):
+        B.rollout(d, out=out, precision=precision)
+        ks.append(B.timing_last())
+    B.timing_enable(False)
+    return float(np.median(ks))
+
+
+def perception_leg(B, W, torch, n):
+    """Perception effects (Sec. VIII): each sample's brake command waits for a
+    stochastic trigger (latency, occlusion, frame dropout, a confirmation run).
+    The throughput of the stationary-obstacle scenario with and without it
+    (parameters drawn in-kernel, FP64 and FP32C), and the paper preset's
+    collision-risk headways as the dropout grows."""
+    import numpy as np
+    res = {"workload": f"stationary obstacle, {n} samples, explicit Euler dt=1 ms; perception: "
+                       "20 Hz frames, occlusion U(0,4) frames, dropout 0.1, 3 detections in a "
+                       "row, latency N(80, 20) ms truncated to [30, 120] ms"}
+    out = B.alloc_outputs(n)
+    for prec in ("fp64", "fp32c"):
+        row = {}
+        for name, d in (("without", W.single(n)), ("with", W.perception(n))):
+            ms = kernel_ms(B, torch, d, out, prec)
+            steps = int(out["steps"].to(torch.int64).sum().item())
+            st = B.reduce(out, risk=RISK)
+            flops = (EULER_FLOPS_PER_STEP if prec == "fp64" else FP32C_FLOPS_PER_STEP) * steps
+            row[name] = {"kernel_ms": ms, "rollouts_per_s": n / (ms * 1e-3),
+                         "steps_per_launch": steps, "achieved_tflops": flops / (ms * 1e-3) / 1e12,
+                         "p_collision": st["p_collision"], "mean_dist": st["mean_dist"]}
+        row["with"]["frac_fp64_peak"] = (row["with"]["achieved_tflops"] / FP64_VECTOR_PEAK_TFLOPS
+                                         if prec == "fp64" else None)
+        row["step_rate_with_over_without"] = (
+            (row["with"]["steps_per_launch"] / row["with"]["kernel_ms"])
+            / (row["without"]["steps_per_launch"] / row["without"]["kernel_ms"]))
+        res[prec] = row
+    trig = B.sample_params(W.perception(n), device=True)["trigger"]
+    res["trigger_mean_s"] = float(trig.mean().item())
+    res["trigger_p99_s"] = float(torch.quantile(trig[:1 << 20].float(), 0.99).item())
+    risk = (0.05, 0.01, 0.001)
+    rows = []
+    for p in (None, 0.0, 0.1, 0.3):
+        d = W.paper_preset(350_000)
+        if p is not None:
+            d.update({"latency": ("trunc_normal", 0.08, 0.02, 0.03, 0.12),
+                      "occlusion": ("uniform", 0.0, 4.0), "frame_period": 0.05,
+                      "p_dropout": p, "confirm": 3})
+        st = B.reduce(B.rollout(d), risk=risk)
+        rows.append({"p_dropout": p, "mean": st["mean_dist"], "sd": st["sd_dist"],
+                     "headways": st["headway"]})
+    res["paper_preset_headways"] = {"risk": list(risk), "samples": 350_000,
+                                    "integrator": "rk4", "rows": rows}
+    return res
+
+
 def n_sweep_leg(B, W, torch, sizes=(1_000, 10_000, 100_000, 1_048_576), reps=5):
     """Rollout call (parameters drawn in-kernel) plus reduction at growing N:
     below ~1e5 samples the launch sequence, not the integration, sets the time."""
@@ -346,6 +406,10 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=1_048_576)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch leg")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline step loops (FP64, FP32C, graphs): no RK4, N-sweep, "
+                         "paper-study or perception legs (for profiler runs, whose per-kernel "
+                         "averages would otherwise mix launch sizes)")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="length of each serving stream (0: no serving leg)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
@@ -379,12 +443,14 @@ def main():
     t0 = time.perf_counter()
     host = B.sample_params(d, device=False, out=B.alloc_params(n, device=False, pinned=True))
     t_sample = time.perf_counter() - t0
-    params = B.alloc_params(n, device=True)
+    # without perception the trigger column stays on the host (passed as NULL)
+    cols = [c for c in B.COLUMNS if c != "trigger"]
+    params = {c: torch.empty(n, dtype=torch.float64, device="cuda") for c in cols}
     torch.cuda.synchronize()
     t_h2d = float("inf")
     for _ in range(3):  # the first copy also pays one-time driver costs
         t0 = time.perf_counter()
-        for c in B.COLUMNS:
+        for c in cols:
             params[c].copy_(host[c], non_blocking=True)
         torch.cuda.synchronize()
         t_h2d = min(t_h2d, time.perf_counter() - t0)
@@ -422,12 +488,16 @@ def main():
     step_wall = wallg64 if use_graph else wall64
     value = args.steps * n / step_wall
 
-    log("bench: rk4 leg")
-    rk4 = rk4_leg(B, W, torch, n)
-    log("bench: N sweep")
-    nsweep = n_sweep_leg(B, W, torch)
-    log("bench: paper-preset study")
-    study = paper_study_leg(B, W, torch)
+    rk4 = nsweep = study = perception = None
+    if not args.headline_only:
+        log("bench: rk4 leg")
+        rk4 = rk4_leg(B, W, torch, n)
+        log("bench: N sweep")
+        nsweep = n_sweep_leg(B, W, torch)
+        log("bench: paper-preset study")
+        study = paper_study_leg(B, W, torch)
+        log("bench: perception leg")
+        perception = perception_leg(B, W, torch, n)
 
     batch = None
     if not args.no_batch:
@@ -503,10 +573,11 @@ def main():
         "rk4": rk4,
         "n_sweep_fp64_step": nsweep,
         "paper_preset_study": study,
+        "perception": perception,
         "batch": batch,
         "serving": serving,
         "plain_method_host": {"sampling_s": t_sample, "h2d_s": t_h2d,
-                              "h2d_GBps": 11 * 8 * n / t_h2d / 1e9},
+                              "h2d_GBps": len(cols) * 8 * n / t_h2d / 1e9},
         "stats": {"p_collision": st64["p_collision"], "mean_dist": st64["mean_dist"],
                   "sd_dist": st64["sd_dist"], "headways": st64["headway"],
                   "p_collision_fp32c": st32["p_collision"],

@@ -161,10 +161,12 @@ __global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job
     if (leads) leads[i].decel = lead;
     const uint32_t u = static_cast<uint32_t>(fminf(steps, a.cap) * (4096.0f / (a.cap + 1.0f)));
     const uint32_t ud = 4095u - (u > 4095u ? 4095u : u);  // longest first
-    // within a coarse length bin: finer length, or with perception the command
-    // step in 8-step bins (so a wavefront's lanes switch the command together
-    // and its blocks are rarely cut at a lane's switch)
-    const uint32_t fine = a.nds ? (static_cast<uint32_t>(ndl) >> 3) & 63u : ud & 63u;
+    // within a coarse length bin: finer length; with perception 8 finer length
+    // levels, then the command step in 16-step bins, so a wavefront's lanes
+    // end close together and switch the command within a few steps of each
+    // other (each distinct switch step cuts the wavefront's blocks)
+    const uint32_t fine =
+        a.nds ? (((ud >> 3) & 7u) << 3) | ((static_cast<uint32_t>(ndl) >> 4) & 7u) : ud & 63u;
     const uint32_t key = ((ud >> 6) << 7) | (limited ? 0u : 64u) | fine;
     keys[i] = key;
     atomicAdd(&hist[key], 1u);
