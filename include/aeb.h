@@ -275,7 +275,7 @@ int aeb_reduce(const aeb_outputs* out, const aeb_reduce_req* req, aeb_stats* hos
  * The block-structured integration kernel (Sec. V's one-thread-per-sample
  * mapping, reorganised as described for aeb_rollout) has three launch
  * parameters per precision (AEB_FP64, AEB_FP32C) and obstacle kind: k, the
- * steps per unchecked block (16, 32 or 64), the workgroup
+ * steps per unchecked block (16, 32 or 64; AEB_FP64 also 128), the workgroup
  * size (64, 128, 256), and waves_per_simd (0: one workgroup per `block`
  * samples in one pass; 1..32: a persistent grid of that many wavefronts per
  * SIMD claiming 64-sample chunks).  Results do not depend on them.  The

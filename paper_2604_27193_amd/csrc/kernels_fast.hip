@@ -480,7 +480,10 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
                                                    const uint32_t* __restrict__ perm, int64_t n,
                                                    Ctx ctx, unsigned long long* counter,
                                                    int persistent) {
-  constexpr int KS = 4;  // short blocks close to the stop
+  // block ladder as a lane approaches its stop: K steps, then KM, then KS,
+  // then single checked steps (a level runs while no lane can stop inside it)
+  constexpr int KS = 4;
+  constexpr int KM = K >= 64 ? 16 : KS;
   constexpr bool LEAD = OBS == AEB_OBS_LEAD;
   for (int pass = 0;; ++pass) {
     const int64_t base = next_chunk(counter, persistent, pass, n);
@@ -500,6 +503,7 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
     const int wnd = varnd ? wave_min(valid ? c.nd : INT_MAX) : c.nd;
     // v above these cannot reach 0 within a block (|dv/dt| <= dmax)
     const double thr_k = static_cast<double>(K) * c.dt * J.dmax;
+    const double thr_m = static_cast<double>(KM) * c.dt * J.dmax;
     const double thr_s = static_cast<double>(KS) * c.dt * J.dmax;
     Lane64 L;
     L.s = St64{0.0, J.v0, 0.0};
@@ -534,6 +538,10 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
         run_block64<OBS, K, INTEG>(L, J, al, c, k, wnd, ctx.impact_exit);
         if (INTEG == AEB_RK4 && L.active) xmax = fmax(xmax, L.s.x);
         k += K;
+      } else if (KM > KS && k + KM <= wl && !__any(L.active && L.s.v <= thr_m)) {
+        run_block64<OBS, KM, INTEG>(L, J, al, c, k, wnd, ctx.impact_exit);
+        if (INTEG == AEB_RK4 && L.active) xmax = fmax(xmax, L.s.x);
+        k += KM;
       } else if (k + KS <= wl && !__any(L.active && L.s.v <= thr_s)) {
         run_block64<OBS, KS, INTEG>(L, J, al, c, k, wnd, ctx.impact_exit);
         if (INTEG == AEB_RK4 && L.active) xmax = fmax(xmax, L.s.x);
@@ -768,7 +776,9 @@ __global__ __launch_bounds__(256) void k_roll_fp32c(const Job* __restrict__ jobs
                                                     uint32_t* fix, unsigned long long* counter,
                                                     int persistent) {
   constexpr int KS = 4;
-  static_assert(FLUSH % K == 0 && K % KS == 0, "flush points must fall on block ends");
+  constexpr int KM = K >= 64 ? 16 : KS;  // middle level of the block ladder
+  static_assert(FLUSH % K == 0 && K % KM == 0 && KM % KS == 0,
+                "flush points must fall on block ends");
   for (int pass = 0;; ++pass) {
     const int64_t base = next_chunk(counter, persistent, pass, n);
     if (base >= n) break;
@@ -796,6 +806,7 @@ __global__ __launch_bounds__(256) void k_roll_fp32c(const Job* __restrict__ jobs
     c.ejump = static_cast<float>(-sc.a_cmd);
     c.thr = static_cast<float>(static_cast<double>(K) * sc.dt * J.dmax);
     c.gapf = static_cast<float>(J.gap);
+    const float thr_m = static_cast<float>(static_cast<double>(KM) * sc.dt * J.dmax);
     const float thr_s = static_cast<float>(static_cast<double>(KS) * sc.dt * J.dmax);
     const double band = band_abs + band_rel * fabs(J.gap);
     const bool split = J.pred > SPLIT_STEPS;  // per lane
@@ -829,6 +840,10 @@ __global__ __launch_bounds__(256) void k_roll_fp32c(const Job* __restrict__ jobs
       if (k % K == 0 && k + K <= wl && !__any(L.active && v_now <= c.thr)) {
         run_block32<OBS, K>(L, c, split, nd, k, wnd, impact_exit);
         k += K;
+      } else if (KM > KS && k % KM == 0 && k + KM <= wl &&
+                 !__any(L.active && v_now <= thr_m)) {
+        run_block32<OBS, KM>(L, c, split, nd, k, wnd, impact_exit);
+        k += KM;
       } else if (k % KS == 0 && k + KS <= wl && !__any(L.active && v_now <= thr_s)) {
         run_block32<OBS, KS>(L, c, split, nd, k, wnd, impact_exit);
         k += KS;
@@ -1033,7 +1048,9 @@ __global__ __launch_bounds__(256) void k_roll_fp32c_lead(const Job* __restrict__
                                                          unsigned long long* counter,
                                                          int persistent) {
   constexpr int KS = 4;
-  static_assert(FLUSH % K == 0 && K % KS == 0, "flush points must fall on block ends");
+  constexpr int KM = K >= 64 ? 16 : KS;  // middle level of the block ladder
+  static_assert(FLUSH % K == 0 && K % KM == 0 && KM % KS == 0,
+                "flush points must fall on block ends");
   for (int pass = 0;; ++pass) {
     const int64_t base = next_chunk(counter, persistent, pass, n);
     if (base >= n) break;
@@ -1062,6 +1079,7 @@ __global__ __launch_bounds__(256) void k_roll_fp32c_lead(const Job* __restrict__
     c.ejump = static_cast<float>(-sc.a_cmd);
     c.thr = static_cast<float>(static_cast<double>(K) * sc.dt * J.dmax);
     c.gapf = static_cast<float>(J.gap);
+    const float thr_m = static_cast<float>(static_cast<double>(KM) * sc.dt * J.dmax);
     const float thr_s = static_cast<float>(static_cast<double>(KS) * sc.dt * J.dmax);
     const double band = band_abs + band_rel * fabs(J.gap);
     Lane32L L;
@@ -1097,6 +1115,10 @@ __global__ __launch_bounds__(256) void k_roll_fp32c_lead(const Job* __restrict__
       if (k % K == 0 && k + K <= wl && !__any(L.active && v_now <= c.thr)) {
         run_block32l<K>(L, c, al, nd, k, wnd);
         k += K;
+      } else if (KM > KS && k % KM == 0 && k + KM <= wl &&
+                 !__any(L.active && v_now <= thr_m)) {
+        run_block32l<KM>(L, c, al, nd, k, wnd);
+        k += KM;
       } else if (k % KS == 0 && k + KS <= wl && !__any(L.active && v_now <= thr_s)) {
         run_block32l<KS>(L, c, al, nd, k, wnd);
         k += KS;
@@ -1290,6 +1312,8 @@ void go64k(int k, const Shape& sh, const Bufs& b, int64_t n, const Ctx& ctx, hip
     go64<OBS, 16, BATCH>(sh, b, n, ctx, st);
   else if (k == 64)
     go64<OBS, 64, BATCH>(sh, b, n, ctx, st);
+  else if (k == 128)
+    go64<OBS, 128, BATCH>(sh, b, n, ctx, st);
   else
     go64<OBS, 32, BATCH>(sh, b, n, ctx, st);
 }

@@ -23,13 +23,14 @@ namespace {
 
 std::mutex g_mu;
 std::once_flag g_env_once;
-// [precision 0 FP64, 1 FP32C][obstacle]
-// defaults measured on MI355X (1,048,576-sample stationary workload): FP64
-// 64-step blocks, 256 threads, 4 persistent wavefronts per SIMD; FP32C
-// 32-step blocks, 128 threads, one pass
+// [precision 0 FP64, 1 FP32C][obstacle none, stationary, lead]
+// defaults measured on MI355X (1,048,576-sample workloads, launch shapes
+// timed in one process, interleaved): FP64 256 threads and 4 persistent
+// wavefronts per SIMD, 64-step blocks with a stationary obstacle and 128-step
+// blocks otherwise; FP32C 64-step blocks, 256 threads, one pass
 TuneCfg g_tab[2][3] = {
-    {{64, 256, 4}, {64, 256, 4}, {64, 256, 4}},
-    {{32, 128, 0}, {32, 128, 0}, {32, 128, 0}},
+    {{128, 256, 4}, {64, 256, 4}, {128, 256, 4}},
+    {{64, 256, 0}, {64, 256, 0}, {64, 256, 0}},
 };
 
 int pidx(int precision) { return precision == AEB_FP64 ? 0 : 1; }
@@ -109,7 +110,8 @@ float g_ms[2][3] = {};
 }  // namespace
 
 bool tune_valid(int precision, const TuneCfg& t) {
-  const bool k_ok = t.k == 16 || t.k == 32 || t.k == 64;
+  // FP32C blocks must divide its 64-step flush period; FP64 also takes 128
+  const bool k_ok = t.k == 16 || t.k == 32 || t.k == 64 || (t.k == 128 && precision == AEB_FP64);
   const bool b_ok = t.block == 64 || t.block == 128 || t.block == 256;
   return k_ok && b_ok && t.waves_per_simd >= 0 && t.waves_per_simd <= 32;
 }
@@ -182,7 +184,7 @@ int aeb_autotune(const aeb_scenario* calib, int precision, const char* cache_pat
   (void)hipEventCreate(&e1);
   const TuneCfg keep = tune_get(precision, calib->obstacle);
   std::vector<TuneCfg> cands;
-  for (int k : {16, 32, 64})
+  for (int k : {16, 32, 64, 128})
     for (int b : {64, 128, 256})
       for (int w : {0, 4, 8}) {
         const TuneCfg t{k, b, w};

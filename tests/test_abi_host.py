@@ -115,6 +115,10 @@ def test_tune_table_validation(B, tmp_path):
             B.tune_set("fp64", "stationary", *bad)
     with pytest.raises(B.AebError):
         B.tune_set("fp32c", "none", 128, 256, 0)     # blocks must divide the FP32 flush period
+    keep_none = B.tune_get("fp64", "none")
+    B.tune_set("fp64", "none", 128, 64, 0)           # FP64 also takes 128-step blocks
+    assert B.tune_get("fp64", "none") == (128, 64, 0)
+    B.tune_set("fp64", "none", *keep_none)
     B.tune_set("fp64", "stationary", *keep)
 
 

@@ -10,7 +10,8 @@ from test_gpu_parity import to_np
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(16, 64, 0), (16, 256, 8), (32, 128, 4), (32, 256, 0), (64, 64, 4), (64, 256, 8)]
+SHAPES = [(16, 64, 0), (16, 256, 8), (32, 128, 4), (32, 256, 0), (64, 64, 4), (64, 256, 8),
+          (128, 256, 4), (128, 64, 0)]
 
 
 @pytest.fixture(scope="module")
@@ -36,6 +37,8 @@ def test_results_do_not_depend_on_shape(B, prec, obs, integ):
     try:
         ref = to_np(B.rollout(d, precision=prec))
         for k, blk, w in SHAPES:
+            if k == 128 and prec != "fp64":
+                continue                      # FP32C blocks divide its 64-step flush period
             B.tune_set(prec, obs, k, blk, w)
             got = to_np(B.rollout(d, precision=prec))
             for c in ref:
