@@ -176,8 +176,10 @@ __global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job
     if (hist[j]) atomicAdd(&ghist[j], hist[j]);
 }
 
-// exclusive scan of the key histogram into bucket offsets (one block)
-__global__ __launch_bounds__(1024) void k_scan(uint32_t* hist) {
+// exclusive scan of the key histogram into bucket offsets (one block); also
+// clears the integration kernel's chunk counter
+__global__ __launch_bounds__(1024) void k_scan(uint32_t* hist, unsigned long long* counter) {
+  if (threadIdx.x == 0) *counter = 0ull;
   __shared__ uint32_t part[1024];
   constexpr int PER = NBINS / 1024;
   uint32_t loc[PER];
@@ -1291,13 +1293,11 @@ int scratch_bufs(int64_t n, int n_scn, bool lead, hipStream_t st, Bufs& b) {
   return AEB_OK;
 }
 
-// sort the prepared keys into the permutation; zero the claim counter
+// sort the prepared keys into the permutation (the scan zeroes the claim counter)
 void sort_keys(const Bufs& b, int64_t n, hipStream_t st) {
   const unsigned pblk = static_cast<unsigned>((n + PREP_SAMPLES - 1) / PREP_SAMPLES);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, b.hist);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, b.hist, b.counter);
   hipLaunchKernelGGL(k_scatter, dim3(pblk), dim3(PREP_BLOCK), 0, st, b.keys, n, b.hist, b.perm);
-  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(b.counter),
-                     int64_t(2));
 }
 
 template <int OBS, int K, bool BATCH, int INTEG = AEB_EULER>

@@ -8,9 +8,10 @@
 // bits.  Order statistics are exact: a histogram over 4,096 value bins
 // spanning each array's finite range (plus one bin for the censored +inf
 // values) finds the bin holding a target's rank; the bin's elements are
-// collected and sorted in LDS (bitonic, by an order-preserving map of the
-// FP64 bit patterns).  A bin with more than 8,192 elements falls back to a
-// most-significant-digit radix select (8 passes of 8 bits).
+// collected and the rank selected among them in LDS (a radix select over an
+// order-preserving map of the FP64 bit patterns).  A bin with more than 8,192
+// elements falls back to a radix select over the whole array (8 passes of 8
+// bits).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -23,10 +24,15 @@ namespace aeb {
 namespace {
 
 constexpr int RB = 256;          // threads per reduction block
+constexpr int EB = 1024;         // threads per block of the element passes
+constexpr int CP = 4;            // elements per thread loaded together
 constexpr int MAX_T = AEB_MAX_RISK + AEB_MAX_MARGIN_Q;
 constexpr int NVB = 4096;        // value bins of the selection histograms (+1 overflow)
 constexpr int CAP = 8192;        // candidates a target's bin may hold for the LDS sort
 constexpr int FB = 1024;         // threads of the finalize / bin-search blocks
+// block histogram row: distance value bins | margin value bins | risk-grid ranks
+constexpr int HG = 2 * (NVB + 1);             // offset of the risk-grid part
+constexpr int HW = HG + AEB_MAX_GRID + 1;     // row width
 
 struct Partial {
   long long ncol, nstop, nimp, nhor, nbnd;
@@ -50,7 +56,6 @@ struct Sel {
   int bin[MAX_T];          // -1: answered without candidates
   unsigned rank_in_bin[MAX_T];
   unsigned bin_count[MAX_T];
-  unsigned ccount[MAX_T];  // candidates collected
   double vmin[2], scale[2];
 };
 
@@ -89,10 +94,10 @@ __device__ inline int value_bin(double v, double vmin, double scale) {
 // number of grid headways strictly below d, H0_j = lo + j * step (j < ng):
 // an arithmetic guess corrected with exact comparisons against the same
 // expression, so the count is exact
-__device__ inline int grid_rank(double d, double lo, double step, int ng) {
+__device__ inline int grid_rank(double d, double lo, double step, double inv_step, int ng) {
   if (!(d > lo)) return 0;
   if (!(d < INFINITY)) return ng;
-  double g = (d - lo) / step;
+  double g = (d - lo) * inv_step;
   int j = g < static_cast<double>(ng) ? static_cast<int>(g) : ng;
   // count = first j with H0_j >= d
   while (j > 0 && !(lo + static_cast<double>(j - 1) * step < d)) --j;
@@ -129,24 +134,70 @@ __device__ inline unsigned long long block_exscan(unsigned long long v, unsigned
   return r;
 }
 
-// Reduction of one value per lane over a wavefront by an xor butterfly: with
-// a commutative op every lane ends with the same bits, in a fixed order.
+// A 64-bit value moved between lanes by a data-parallel-primitives (DPP)
+// modifier; lanes without a source lane under the row and bank masks get `id`.
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ inline unsigned long long dpp64(unsigned long long v, unsigned long long id) {
+  const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_update_dpp(
+      static_cast<int>(static_cast<unsigned>(id)), static_cast<int>(static_cast<unsigned>(v)), CTRL,
+      ROW_MASK, BANK_MASK, false));
+  const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_update_dpp(
+      static_cast<int>(static_cast<unsigned>(id >> 32)), static_cast<int>(static_cast<unsigned>(v >> 32)),
+      CTRL, ROW_MASK, BANK_MASK, false));
+  return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
+
+__device__ inline unsigned long long bits64(double v) {
+  return static_cast<unsigned long long>(__double_as_longlong(v));
+}
+__device__ inline unsigned long long bits64(long long v) { return static_cast<unsigned long long>(v); }
+__device__ inline double from_bits(unsigned long long u, double) {
+  return __longlong_as_double(static_cast<long long>(u));
+}
+__device__ inline long long from_bits(unsigned long long u, long long) {
+  return static_cast<long long>(u);
+}
+
+template <int CTRL, int ROW_MASK, int BANK_MASK, typename T>
+__device__ inline T dpp(T v, T id) {
+  return from_bits(dpp64<CTRL, ROW_MASK, BANK_MASK>(bits64(v), bits64(id)), v);
+}
+
+// Reduction of one value per lane over a wavefront (every lane active): an
+// inclusive scan by DPP row shifts of 1, 2, 4, 8 lanes inside each row of 16,
+// then row broadcasts of lane 15 and lane 31, leaves the total in lane 63,
+// which is read back for every lane.  A fixed association order, so repeated
+// calls give the same bits; register moves only, no memory round trips.
 template <typename T, typename Op>
 __device__ inline T wave_reduce(T v, Op op) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o));
-  return v;
+  const T id = Op::template ident<T>();
+  v = op(v, dpp<0x111, 0xf, 0xf>(v, id));  // row_shr:1
+  v = op(v, dpp<0x112, 0xf, 0xf>(v, id));  // row_shr:2
+  v = op(v, dpp<0x114, 0xf, 0xf>(v, id));  // row_shr:4
+  v = op(v, dpp<0x118, 0xf, 0xf>(v, id));  // row_shr:8
+  v = op(v, dpp<0x142, 0xa, 0xf>(v, id));  // row_bcast:15 into rows 1 and 3
+  v = op(v, dpp<0x143, 0xc, 0xf>(v, id));  // row_bcast:31 into rows 2 and 3
+  const unsigned long long u = bits64(v);
+  const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(u)), 63));
+  const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(u >> 32)), 63));
+  return from_bits((static_cast<unsigned long long>(hi) << 32) | lo, v);
 }
 
 struct AddOp {
   template <typename T>
   __device__ T operator()(T a, T b) const { return a + b; }
+  template <typename T>
+  __device__ static T ident() { return T(0); }
 };
 struct MinOp {
   __device__ double operator()(double a, double b) const { return b < a ? b : a; }
+  template <typename T>
+  __device__ static T ident() { return INFINITY; }
 };
 struct MaxOp {
   __device__ double operator()(double a, double b) const { return b > a ? b : a; }
+  template <typename T>
+  __device__ static T ident() { return -INFINITY; }
 };
 
 __global__ void k_zero_u32(unsigned* p, long long n) {
@@ -169,27 +220,82 @@ __device__ inline void combine(Partial& a, const Partial& b) {
   a.vmax = b.vmax > a.vmax ? b.vmax : a.vmax;
 }
 
-__global__ __launch_bounds__(RB) void k_pass1(OutCols o, long long n, long long chunk, double glo,
-                                              double gstep, int ng, unsigned* ghist, Partial* part) {
-  __shared__ Partial wp[RB / 64];
-  __shared__ unsigned hist[AEB_MAX_GRID + 1];
-  for (int j = threadIdx.x; j <= ng; j += RB) hist[j] = 0;
-  __syncthreads();
+__device__ inline Partial identity_partial() {
+  Partial p;
+  p.ncol = p.nstop = p.nimp = p.nhor = p.nbnd = 0;
+  p.sum = p.msum = 0.0;
+  p.dmin = p.mmin = INFINITY;
+  p.dmax = p.mmax = -INFINITY;
+  p.vmax = 0.0f;
+  p.pad = 0.0f;
+  return p;
+}
+
+// every field reduced over the wavefront by the fixed butterfly
+__device__ inline Partial wave_combine(const Partial& a) {
+  Partial p;
+  p.ncol = wave_reduce(a.ncol, AddOp());
+  p.nstop = wave_reduce(a.nstop, AddOp());
+  p.nimp = wave_reduce(a.nimp, AddOp());
+  p.nhor = wave_reduce(a.nhor, AddOp());
+  p.nbnd = wave_reduce(a.nbnd, AddOp());
+  p.sum = wave_reduce(a.sum, AddOp());
+  p.dmin = wave_reduce(a.dmin, MinOp());
+  p.dmax = wave_reduce(a.dmax, MaxOp());
+  p.msum = wave_reduce(a.msum, AddOp());
+  p.mmin = wave_reduce(a.mmin, MinOp());
+  p.mmax = wave_reduce(a.mmax, MaxOp());
+  p.vmax = static_cast<float>(wave_reduce(static_cast<double>(a.vmax), MaxOp()));
+  p.pad = 0.0f;
+  return p;
+}
+
+// the block's wavefront partials (in LDS) combined by wavefront 0, lane w
+// holding wavefront w's partial; every lane of wavefront 0 gets the result
+template <int NW>
+__device__ inline Partial block_combine(const Partial* wp) {
+  const int l = threadIdx.x;
+  return wave_combine(l < NW ? wp[l] : identity_partial());
+}
+
+__global__ __launch_bounds__(EB) void k_pass1(OutCols o, long long n, long long chunk,
+                                              Partial* part) {
+  __shared__ Partial wp[EB / 64];
   const long long lo = static_cast<long long>(blockIdx.x) * chunk;
   const long long hi = lo + chunk < n ? lo + chunk : n;
   long long ncol = 0, nstop = 0, nimp = 0, nhor = 0, nbnd = 0;
   double sum = 0.0, dmin = INFINITY, dmax = -INFINITY, msum = 0.0, mmin = INFINITY,
          mmax = -INFINITY;
   float vmax = 0.0f;
-  for (long long i = lo + threadIdx.x; i < hi; i += RB) {
-    const uint8_t st = o.status[i];
+  // CP elements per thread are loaded before any is used (chunk = CP * EB)
+  for (long long i0 = lo; i0 < hi; i0 += static_cast<long long>(EB) * CP) {
+    uint8_t sv[CP];
+    double dv[CP], mv[CP];
+    float vv[CP];
+#pragma unroll
+    for (int p = 0; p < CP; ++p) {
+      const long long i = i0 + p * EB + threadIdx.x;
+      sv[p] = 0;
+      dv[p] = mv[p] = 0.0;
+      vv[p] = 0.0f;
+      if (i < hi) {
+        sv[p] = o.status[i];
+        dv[p] = o.dist[i];
+        mv[p] = o.margin[i];
+        vv[p] = o.vimp[i];
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < CP; ++p) {
+    if (i0 + p * EB + threadIdx.x >= hi) break;
+    const uint8_t st = sv[p];
     if (st & AEB_BOUNDARY) ++nbnd;
-    const double d = o.dist[i];
-    const double m = o.margin[i];
+    const double d = dv[p];
+    const double m = mv[p];
     const int end = st & 3;
     if (st & AEB_COLLIDED) {
       ++ncol;
-      const float vi = o.vimp[i];
+      const float vi = vv[p];
       vmax = vi > vmax ? vi : vmax;
     }
     if (end == AEB_END_STOP) {
@@ -205,115 +311,48 @@ __global__ __launch_bounds__(RB) void k_pass1(OutCols o, long long n, long long 
     msum += m;
     mmin = m < mmin ? m : mmin;
     mmax = m > mmax ? m : mmax;
-    if (ng >= 2) {
-      const double dc = end == AEB_END_STOP ? d : INFINITY;
-      atomicAdd(&hist[grid_rank(dc, glo, gstep, ng)], 1u);
     }
   }
   // wavefront partials, then the block's waves combined in index order
   Partial p;
-  p.ncol = wave_reduce(ncol, AddOp());
-  p.nstop = wave_reduce(nstop, AddOp());
-  p.nimp = wave_reduce(nimp, AddOp());
-  p.nhor = wave_reduce(nhor, AddOp());
-  p.nbnd = wave_reduce(nbnd, AddOp());
-  p.sum = wave_reduce(sum, AddOp());
-  p.dmin = wave_reduce(dmin, MinOp());
-  p.dmax = wave_reduce(dmax, MaxOp());
-  p.msum = wave_reduce(msum, AddOp());
-  p.mmin = wave_reduce(mmin, MinOp());
-  p.mmax = wave_reduce(mmax, MaxOp());
-  p.vmax = static_cast<float>(wave_reduce(static_cast<double>(vmax), MaxOp()));
+  p.ncol = ncol;
+  p.nstop = nstop;
+  p.nimp = nimp;
+  p.nhor = nhor;
+  p.nbnd = nbnd;
+  p.sum = sum;
+  p.dmin = dmin;
+  p.dmax = dmax;
+  p.msum = msum;
+  p.mmin = mmin;
+  p.mmax = mmax;
+  p.vmax = vmax;
   p.pad = 0.0f;
+  p = wave_combine(p);
   if ((threadIdx.x & 63) == 0) wp[threadIdx.x >> 6] = p;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    Partial q = wp[0];
-    for (int w = 1; w < RB / 64; ++w) combine(q, wp[w]);
-    part[blockIdx.x] = q;
-  }
-  if (ng >= 2) {
-    for (int j = threadIdx.x; j <= ng; j += RB)
-      if (hist[j]) atomicAdd(&ghist[j], hist[j]);
+  if (threadIdx.x < 64) {
+    const Partial q = block_combine<EB / 64>(wp);
+    if (threadIdx.x == 0) part[blockIdx.x] = q;
   }
 }
 
 // Combine the block partials in a fixed order (thread t takes partials
-// t, t+FB, ... in order, then a fixed tree), the risk curve by a block scan.
-__global__ __launch_bounds__(FB) void k_fin1(const Partial* part, int nb, long long n, int ng,
-                                             const unsigned* ghist, aeb_stats* st, Sel* sel) {
+// t, t+FB, ... in order, then a fixed tree).
+__global__ __launch_bounds__(FB) void k_fin1(const Partial* part, int nb, long long n,
+                                             aeb_stats* st, Sel* sel) {
   __shared__ Partial wp[FB / 64];
-  __shared__ unsigned long long shu[FB];
-  long long ncol = 0, nstop = 0, nimp = 0, nhor = 0, nbnd = 0;
-  double sum = 0.0, dmin = INFINITY, dmax = -INFINITY, msum = 0.0, mmin = INFINITY,
-         mmax = -INFINITY;
-  double vmax = 0.0;
-  for (int b = threadIdx.x; b < nb; b += FB) {
-    const Partial& p = part[b];
-    ncol += p.ncol;
-    nstop += p.nstop;
-    nimp += p.nimp;
-    nhor += p.nhor;
-    nbnd += p.nbnd;
-    sum += p.sum;
-    dmin = p.dmin < dmin ? p.dmin : dmin;
-    dmax = p.dmax > dmax ? p.dmax : dmax;
-    msum += p.msum;
-    mmin = p.mmin < mmin ? p.mmin : mmin;
-    mmax = p.mmax > mmax ? p.mmax : mmax;
-    vmax = p.vmax > vmax ? p.vmax : vmax;
-  }
-  {
-    Partial p;
-    p.ncol = wave_reduce(ncol, AddOp());
-    p.nstop = wave_reduce(nstop, AddOp());
-    p.nimp = wave_reduce(nimp, AddOp());
-    p.nhor = wave_reduce(nhor, AddOp());
-    p.nbnd = wave_reduce(nbnd, AddOp());
-    p.sum = wave_reduce(sum, AddOp());
-    p.dmin = wave_reduce(dmin, MinOp());
-    p.dmax = wave_reduce(dmax, MaxOp());
-    p.msum = wave_reduce(msum, AddOp());
-    p.mmin = wave_reduce(mmin, MinOp());
-    p.mmax = wave_reduce(mmax, MaxOp());
-    p.vmax = static_cast<float>(wave_reduce(vmax, MaxOp()));
-    if ((threadIdx.x & 63) == 0) wp[threadIdx.x >> 6] = p;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int w = 1; w < FB / 64; ++w) combine(wp[0], wp[w]);
-    }
-    __syncthreads();
-    const Partial& q = wp[0];
-    ncol = q.ncol;
-    nstop = q.nstop;
-    nimp = q.nimp;
-    nhor = q.nhor;
-    nbnd = q.nbnd;
-    sum = q.sum;
-    dmin = q.dmin;
-    dmax = q.dmax;
-    msum = q.msum;
-    mmin = q.mmin;
-    mmax = q.mmax;
-    vmax = q.vmax;
-  }
-  // risk curve: #{D > H0_j} = n - #{D with grid rank <= j}
-  constexpr int PER = (AEB_MAX_GRID + FB - 1) / FB;
-  unsigned long long loc = 0;
-  for (int q = 0; q < PER; ++q) {
-    const int j = threadIdx.x * PER + q;
-    if (j < ng) loc += ghist[j];
-  }
-  unsigned long long before = block_exscan<FB>(loc, shu);
-  for (int q = 0; q < PER; ++q) {
-    const int j = threadIdx.x * PER + q;
-    if (j < ng) {
-      before += ghist[j];
-      const long long above = n - static_cast<long long>(before);
-      st->risk_count[j] = above;
-      st->risk_p[j] = static_cast<double>(above) / static_cast<double>(n);
-    }
-  }
+  Partial p = identity_partial();
+  for (int b = threadIdx.x; b < nb; b += FB) combine(p, part[b]);
+  p = wave_combine(p);
+  if ((threadIdx.x & 63) == 0) wp[threadIdx.x >> 6] = p;
+  __syncthreads();
+  if (threadIdx.x >= 64) return;
+  const Partial q = block_combine<FB / 64>(wp);
+  const long long ncol = q.ncol, nstop = q.nstop, nimp = q.nimp, nhor = q.nhor, nbnd = q.nbnd;
+  const double sum = q.sum, dmin = q.dmin, dmax = q.dmax, msum = q.msum, mmin = q.mmin,
+               mmax = q.mmax;
+  const double vmax = q.vmax;
   if (threadIdx.x == 0) {
     st->n = n;
     st->n_collide = ncol;
@@ -337,14 +376,17 @@ __global__ __launch_bounds__(FB) void k_fin1(const Partial* part, int nb, long l
   }
 }
 
-// Sum of squared deviations for the sd, and block-private value histograms
-// (LDS, written out without atomics) of the arrays that have targets.
-__global__ __launch_bounds__(RB) void k_pass2(OutCols o, long long n, long long chunk,
+// Sum of squared deviations for the sd, and block-private histograms (LDS,
+// written out without atomics): value bins of the arrays that have targets,
+// and the number of risk-grid headways below each censored distance.
+__global__ __launch_bounds__(EB) void k_pass2(OutCols o, long long n, long long chunk,
                                               const aeb_stats* st, const Sel* sel, int need_d,
-                                              int need_m, unsigned* bhist, double* part) {
-  __shared__ double shd[RB / 64];
-  __shared__ unsigned h[2 * (NVB + 1)];
-  for (int j = threadIdx.x; j < 2 * (NVB + 1); j += RB) h[j] = 0;
+                                              int need_m, double glo, double gstep,
+                                              double ginv, int ng,
+                                              int hw, unsigned* bhist, double* part) {
+  __shared__ double shd[EB / 64];
+  __shared__ unsigned h[HW];
+  for (int j = threadIdx.x; j < hw; j += EB) h[j] = 0;
   __syncthreads();
   const double mean = st->mean_dist;
   const double vmin0 = sel->vmin[0], sc0 = sel->scale[0];
@@ -352,57 +394,100 @@ __global__ __launch_bounds__(RB) void k_pass2(OutCols o, long long n, long long 
   const long long lo = static_cast<long long>(blockIdx.x) * chunk;
   const long long hi = lo + chunk < n ? lo + chunk : n;
   double ss = 0.0;
-  for (long long i = lo + threadIdx.x; i < hi; i += RB) {
-    const bool stop = (o.status[i] & 3) == AEB_END_STOP;
-    const double d = o.dist[i];
-    if (stop) {
-      const double e = d - mean;
-      ss += e * e;
+  // CP elements per thread are loaded before any is used (chunk2 = CP * EB)
+  for (long long i0 = lo; i0 < hi; i0 += static_cast<long long>(EB) * CP) {
+    uint8_t sv[CP];
+    double dv[CP], mv[CP];
+#pragma unroll
+    for (int p = 0; p < CP; ++p) {
+      const long long i = i0 + p * EB + threadIdx.x;
+      sv[p] = 0;
+      dv[p] = mv[p] = 0.0;
+      if (i < hi) {
+        sv[p] = o.status[i];
+        dv[p] = o.dist[i];
+        mv[p] = o.margin[i];
+      }
     }
-    if (need_d) atomicAdd(&h[value_bin(stop ? d : INFINITY, vmin0, sc0)], 1u);
-    if (need_m) atomicAdd(&h[(NVB + 1) + value_bin(o.margin[i], vmin1, sc1)], 1u);
+#pragma unroll
+    for (int p = 0; p < CP; ++p) {
+      if (i0 + p * EB + threadIdx.x >= hi) break;
+      const bool stop = (sv[p] & 3) == AEB_END_STOP;
+      const double d = dv[p];
+      if (stop) {
+        const double e = d - mean;
+        ss += e * e;
+      }
+      if (need_d) atomicAdd(&h[value_bin(stop ? d : INFINITY, vmin0, sc0)], 1u);
+      if (need_m) atomicAdd(&h[(NVB + 1) + value_bin(mv[p], vmin1, sc1)], 1u);
+      if (ng >= 2) atomicAdd(&h[HG + grid_rank(stop ? d : INFINITY, glo, gstep, ginv, ng)], 1u);
+    }
   }
   ss = wave_reduce(ss, AddOp());
   if ((threadIdx.x & 63) == 0) shd[threadIdx.x >> 6] = ss;
   __syncthreads();
   if (threadIdx.x == 0) {
     double t = shd[0];
-    for (int w = 1; w < RB / 64; ++w) t += shd[w];
+    for (int w = 1; w < EB / 64; ++w) t += shd[w];
     part[blockIdx.x] = t;
   }
-  unsigned* out = bhist + static_cast<size_t>(blockIdx.x) * 2 * (NVB + 1);
-  for (int j = threadIdx.x; j < 2 * (NVB + 1); j += RB) out[j] = h[j];
+  unsigned* out = bhist + static_cast<size_t>(blockIdx.x) * hw;
+  for (int j = threadIdx.x; j < hw; j += EB) out[j] = h[j];
 }
 
 // Bin totals of the block-private histograms: a 2-D grid, each thread sums
 // BT_ROWS blocks' counts of one bin (adjacent threads, adjacent bins) and adds
 // them to the zeroed totals (integer adds: order-free).
 constexpr int BT_ROWS = 16;
-__global__ __launch_bounds__(256) void k_bin_totals(const unsigned* bhist, int nb, unsigned* btot) {
+__global__ __launch_bounds__(256) void k_bin_totals(const unsigned* bhist, int nb, int hw,
+                                                    unsigned* btot) {
   const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= 2 * (NVB + 1)) return;
+  if (j >= hw) return;
   const int b0 = blockIdx.y * BT_ROWS;
   const int b1 = b0 + BT_ROWS < nb ? b0 + BT_ROWS : nb;
   unsigned c = 0;
-  for (int b = b0; b < b1; ++b) c += bhist[static_cast<size_t>(b) * 2 * (NVB + 1) + j];
+  for (int b = b0; b < b1; ++b) c += bhist[static_cast<size_t>(b) * hw + j];
   if (c) atomicAdd(&btot[j], c);
 }
 
-// Block 0: the sd.  Block 1 + t: find the value bin holding target t's rank.
-__global__ __launch_bounds__(FB) void k_fin2(const double* part, int nb, aeb_stats* st, Sel* sel,
-                                             SelIn in, const unsigned* btot) {
+// Block 0: the sd and the risk curve.  Block 1 + t: find the value bin
+// holding target t's rank.
+__global__ __launch_bounds__(FB) void k_fin2(const double* part, int nb, long long n, int ng,
+                                             aeb_stats* st, Sel* sel, SelIn in,
+                                             const unsigned* btot, const unsigned* bhist, int hw,
+                                             unsigned* boff) {
   __shared__ double shd[FB];
   __shared__ unsigned long long shu[FB];
+  __shared__ int s_bin;
   if (blockIdx.x == 0) {
     double ss = 0.0;
     for (int b = threadIdx.x; b < nb; b += FB) ss += part[b];
     ss = block_reduce<FB>(ss, shd, AddOp());
     if (threadIdx.x == 0)
       st->sd_dist = st->n_stop > 1 ? sqrt(ss / static_cast<double>(st->n_stop - 1)) : NAN;
+    // risk curve: #{D > H0_j} = n - #{D with at most j headways below it}
+    const unsigned* gh = btot + HG;
+    constexpr int PER = (AEB_MAX_GRID + FB - 1) / FB;
+    unsigned long long loc = 0;
+    for (int q = 0; q < PER; ++q) {
+      const int j = threadIdx.x * PER + q;
+      if (j < ng) loc += gh[j];
+    }
+    unsigned long long before = block_exscan<FB>(loc, shu);
+    for (int q = 0; q < PER; ++q) {
+      const int j = threadIdx.x * PER + q;
+      if (j < ng) {
+        before += gh[j];
+        const long long above = n - static_cast<long long>(before);
+        st->risk_count[j] = above;
+        st->risk_p[j] = static_cast<double>(above) / static_cast<double>(n);
+      }
+    }
     return;
   }
   const int t = blockIdx.x - 1;
   if (t >= in.count) return;
+  if (threadIdx.x == 0) s_bin = -1;
   const unsigned* tot = btot + (in.kind[t] ? (NVB + 1) : 0);
   constexpr int PER = (NVB + 1 + FB - 1) / FB;
   unsigned cnt[PER];
@@ -429,23 +514,49 @@ __global__ __launch_bounds__(FB) void k_fin2(const double* part, int nb, aeb_sta
           atomicOr(&sel->fallback, 1);
         } else {
           sel->bin[t] = j;
+          s_bin = j;
         }
         break;
       }
       before += cnt[q];
     }
   }
+  __syncthreads();
+  // where each histogram block's elements of the bin go among the candidates:
+  // an exclusive scan of the block histograms' counts of that bin, so the
+  // collection needs no global atomics (it uses the histogram pass's blocks)
+  const int j = s_bin;
+  if (j < 0) return;
+  const int col = (in.kind[t] ? (NVB + 1) : 0) + j;
+  unsigned long long carry = 0;
+  for (int b0 = 0; b0 < nb; b0 += FB) {
+    const int b = b0 + static_cast<int>(threadIdx.x);
+    const unsigned long long c = b < nb ? bhist[static_cast<size_t>(b) * hw + col] : 0ull;
+    const unsigned long long ex = block_exscan<FB>(c, shu);
+    if (b < nb) boff[static_cast<size_t>(t) * nb + b] = static_cast<unsigned>(carry + ex);
+    if (threadIdx.x == FB - 1) shu[0] = ex + c;  // the tile's total
+    __syncthreads();
+    carry += shu[0];
+    __syncthreads();
+  }
 }
 
-// Collect the keys of every element in a target's bin.
-__global__ __launch_bounds__(RB) void k_collect(OutCols o, long long n, long long chunk, Sel* sel,
-                                                SelIn in, unsigned long long* cand) {
+// Collect the keys of every element in a target's bin: block b of the
+// histogram pass's decomposition writes its elements from the offset the bin
+// search computed for it, ranked inside the block by LDS counters.
+__global__ __launch_bounds__(EB) void k_collect(OutCols o, long long n, long long chunk, Sel* sel,
+                                                SelIn in, const unsigned* boff,
+                                                unsigned long long* cand) {
   __shared__ int tb[MAX_T], tk[MAX_T];
+  __shared__ unsigned lc[MAX_T], lbase[MAX_T];
   __shared__ double vmin[2], scale[2];
   const int T = in.count;
   if (static_cast<int>(threadIdx.x) < T) {
     tb[threadIdx.x] = sel->bin[threadIdx.x];
     tk[threadIdx.x] = in.kind[threadIdx.x];
+    lc[threadIdx.x] = 0u;
+    lbase[threadIdx.x] =
+        tb[threadIdx.x] >= 0 ? boff[static_cast<size_t>(threadIdx.x) * gridDim.x + blockIdx.x] : 0u;
   }
   if (threadIdx.x < 2) {
     vmin[threadIdx.x] = sel->vmin[threadIdx.x];
@@ -454,16 +565,40 @@ __global__ __launch_bounds__(RB) void k_collect(OutCols o, long long n, long lon
   __syncthreads();
   const long long lo = static_cast<long long>(blockIdx.x) * chunk;
   const long long hi = lo + chunk < n ? lo + chunk : n;
-  for (long long i = lo + threadIdx.x; i < hi; i += RB) {
-    const double dc = censored(o.dist, o.status, i);
-    const double m = o.margin[i];
-    const int bd = value_bin(dc, vmin[0], scale[0]);
-    const int bm = value_bin(m, vmin[1], scale[1]);
-    for (int t = 0; t < T; ++t) {
-      const int b = tk[t] ? bm : bd;
-      if (tb[t] >= 0 && b == tb[t]) {
-        const unsigned slot = atomicAdd(&sel->ccount[t], 1u);
-        if (slot < CAP) cand[t * CAP + slot] = ordered(tk[t] ? m : dc);
+  // each pass loads CP elements per thread before using any of them
+  for (long long i0 = lo; i0 < hi; i0 += static_cast<long long>(EB) * CP) {
+    uint8_t stt[CP];
+    double dv[CP], mv[CP];
+#pragma unroll
+    for (int p = 0; p < CP; ++p) {
+      const long long i = i0 + p * EB + threadIdx.x;
+      stt[p] = 0;
+      dv[p] = mv[p] = 0.0;
+      if (i < hi) {
+        stt[p] = o.status[i];
+        dv[p] = o.dist[i];
+        mv[p] = o.margin[i];
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < CP; ++p) {
+      const bool ok = i0 + p * EB + threadIdx.x < hi;
+      const double dc = (stt[p] & 3) == AEB_END_STOP ? dv[p] : INFINITY;
+      const double m = mv[p];
+      const int bd = value_bin(dc, vmin[0], scale[0]);
+      const int bm = value_bin(m, vmin[1], scale[1]);
+      // most wavefronts hold no element of any target's bin: one test first
+      bool any = false;
+#pragma unroll
+      for (int t = 0; t < MAX_T; ++t)
+        if (t < T) any = any || (tb[t] >= 0 && (tk[t] ? bm : bd) == tb[t]);
+      if (!(ok && any)) continue;
+      for (int t = 0; t < T; ++t) {
+        const int b = tk[t] ? bm : bd;
+        if (tb[t] >= 0 && b == tb[t]) {
+          const unsigned slot = lbase[t] + atomicAdd(&lc[t], 1u);
+          if (slot < CAP) cand[t * CAP + slot] = ordered(tk[t] ? m : dc);
+        }
       }
     }
   }
@@ -480,8 +615,11 @@ __global__ __launch_bounds__(RB) void k_pick(const Sel* sel, SelIn in,
   __shared__ unsigned long long s_prefix;
   __shared__ unsigned s_rank;
   const int t = blockIdx.x;
+  // the host reads the fallback flag through the statistics' reserved word
+  if (t == 0 && threadIdx.x == 0) st->reserved = sel->fallback;
   if (t >= in.count || sel->bin[t] < 0) return;
-  const unsigned m = sel->ccount[t] < CAP ? sel->ccount[t] : CAP;
+  // every element of the bin was collected (the bin holds at most CAP)
+  const unsigned m = sel->bin_count[t] < CAP ? sel->bin_count[t] : CAP;
   unsigned long long lo = ~0ull, hi = 0ull;
   for (unsigned j = threadIdx.x; j < m; j += RB) {
     const unsigned long long k = cand[t * CAP + j];
@@ -560,11 +698,6 @@ __global__ __launch_bounds__(RB) void k_pick(const Sel* sel, SelIn in,
   }
 }
 
-// the host reads the fallback flag through the statistics' reserved word
-__global__ void k_flag(const Sel* sel, aeb_stats* st) {
-  if (threadIdx.x == 0) st->reserved = sel->fallback;
-}
-
 // ---- fallback: most-significant-digit radix select, 8 passes of 8 bits ----
 __global__ __launch_bounds__(RB) void k_select_hist(OutCols o, long long n, long long chunk,
                                                     const SelState* ss, int pass, unsigned* ghist) {
@@ -627,33 +760,34 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 namespace {
 
-// Scratch layout of one reduction: stats, risk-grid histogram, selection
-// state and the selection bin totals first (zeroed by one launch), then the
-// block partials, the block selection histograms, the candidates and the
-// radix-select state.
+// Scratch layout of one reduction: stats, selection state and the bin totals
+// (selection bins and risk-grid ranks) first (zeroed by one launch), then the
+// block partials, the block histograms, the candidates and the radix-select
+// state.
 struct RLayout {
   long long chunk, chunk2;
   int nb, nb2, T;
-  size_t off_rh, off_sel, off_zero_end, off_var, off_bh, off_bt, off_cand, off_ss, off_sh, total;
+  size_t off_sel, off_zero_end, off_var, off_bh, off_bt, off_bo, off_cand, off_ss, off_sh, total;
 };
 
 RLayout layout(int64_t n, const aeb_reduce_req& req) {
   RLayout L;
-  // element passes take 1,024-element slices (enough blocks to fill the chip);
-  // the histogram pass 4,096 (fewer block histograms to merge)
-  L.chunk = 1024;
-  L.chunk2 = L.chunk * 4;
+  // element passes: 4,096 elements per block of 1,024 threads (measured faster
+  // than smaller blocks or slices: fewer partials, block histograms and
+  // per-block fixed costs)
+  L.chunk = EB * CP;
+  L.chunk2 = EB * CP;
   L.nb = static_cast<int>((n + L.chunk - 1) / L.chunk);
   L.nb2 = static_cast<int>((n + L.chunk2 - 1) / L.chunk2);
   L.T = req.n_risk + req.n_margin_q;
   const int tc = L.T > 0 ? L.T : 1;
-  L.off_rh = align256(sizeof(aeb_stats));
-  L.off_sel = align256(L.off_rh + sizeof(unsigned) * (AEB_MAX_GRID + 1));
+  L.off_sel = align256(sizeof(aeb_stats));
   L.off_bt = align256(L.off_sel + sizeof(Sel));
-  L.off_zero_end = align256(L.off_bt + sizeof(unsigned) * 2 * (NVB + 1));
+  L.off_zero_end = align256(L.off_bt + sizeof(unsigned) * HW);
   L.off_var = align256(L.off_zero_end + sizeof(Partial) * L.nb);
   L.off_bh = align256(L.off_var + sizeof(double) * (L.nb > L.nb2 ? L.nb : L.nb2));
-  L.off_cand = align256(L.off_bh + sizeof(unsigned) * 2 * (NVB + 1) * L.nb2);
+  L.off_bo = align256(L.off_bh + sizeof(unsigned) * HW * L.nb2);
+  L.off_cand = align256(L.off_bo + sizeof(unsigned) * tc * L.nb2);
   L.off_ss = align256(L.off_cand + sizeof(unsigned long long) * tc * CAP);
   L.off_sh = align256(L.off_ss + sizeof(SelState));
   L.total = align256(L.off_sh + sizeof(unsigned) * tc * 256);
@@ -671,12 +805,12 @@ int reduce_enqueue(const OutCols& out, int64_t n, const aeb_reduce_req& req, voi
   const int T = L.T;
   char* base = static_cast<char*>(scratch_base);
   aeb_stats* dstats = reinterpret_cast<aeb_stats*>(base);
-  unsigned* rhist = reinterpret_cast<unsigned*>(base + L.off_rh);
   Sel* sel = reinterpret_cast<Sel*>(base + L.off_sel);
   Partial* part = reinterpret_cast<Partial*>(base + L.off_zero_end);
   double* vpart = reinterpret_cast<double*>(base + L.off_var);
   unsigned* bhist = reinterpret_cast<unsigned*>(base + L.off_bh);
   unsigned* btot = reinterpret_cast<unsigned*>(base + L.off_bt);
+  unsigned* boff = reinterpret_cast<unsigned*>(base + L.off_bo);
   unsigned long long* cand = reinterpret_cast<unsigned long long*>(base + L.off_cand);
 
   // targets: ranks computed exactly as floor(level * N) in binary64
@@ -702,22 +836,26 @@ int reduce_enqueue(const OutCols& out, int64_t n, const aeb_reduce_req& req, voi
   hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<unsigned>((zero_words + 255) / 256)), dim3(256),
                      0, st, reinterpret_cast<unsigned*>(base), zero_words);
   const double gstep = ng >= 2 ? (req.grid_hi - req.grid_lo) / static_cast<double>(ng - 1) : 0.0;
-  hipLaunchKernelGGL(k_pass1, dim3(L.nb), dim3(RB), 0, st, out, static_cast<long long>(n), L.chunk,
-                     req.grid_lo, gstep, ng, rhist, part);
-  hipLaunchKernelGGL(k_fin1, dim3(1), dim3(FB), 0, st, part, L.nb, static_cast<long long>(n), ng,
-                     rhist, dstats, sel);
-  hipLaunchKernelGGL(k_pass2, dim3(L.nb2), dim3(RB), 0, st, out, static_cast<long long>(n),
-                     L.chunk2, dstats, sel, need_d ? 1 : 0, need_m ? 1 : 0, bhist, vpart);
-  if (T > 0)
-    hipLaunchKernelGGL(k_bin_totals,
-                       dim3((2 * (NVB + 1) + 255) / 256, (L.nb2 + BT_ROWS - 1) / BT_ROWS),
-                       dim3(256), 0, st, bhist, L.nb2, btot);
-  hipLaunchKernelGGL(k_fin2, dim3(1 + T), dim3(FB), 0, st, vpart, L.nb2, dstats, sel, in, btot);
+  hipLaunchKernelGGL(k_pass1, dim3(L.nb), dim3(EB), 0, st, out, static_cast<long long>(n), L.chunk,
+                     part);
+  hipLaunchKernelGGL(k_fin1, dim3(1), dim3(FB), 0, st, part, L.nb, static_cast<long long>(n),
+                     dstats, sel);
+  // block histograms: the value bins only when some target needs them
+  const int hw = ng >= 2 ? HG + ng + 1 : (T > 0 ? HG : 0);
+  hipLaunchKernelGGL(k_pass2, dim3(L.nb2), dim3(EB), 0, st, out, static_cast<long long>(n),
+                     L.chunk2, dstats, sel, need_d ? 1 : 0, need_m ? 1 : 0, req.grid_lo, gstep,
+                     ng >= 2 ? 1.0 / gstep : 0.0,
+                     ng, hw, bhist, vpart);
+  if (hw > 0)
+    hipLaunchKernelGGL(k_bin_totals, dim3((hw + 255) / 256, (L.nb2 + BT_ROWS - 1) / BT_ROWS),
+                       dim3(256), 0, st, bhist, L.nb2, hw, btot);
+  hipLaunchKernelGGL(k_fin2, dim3(1 + T), dim3(FB), 0, st, vpart, L.nb2,
+                     static_cast<long long>(n), ng, dstats, sel, in, btot, bhist, hw, boff);
   if (T > 0) {
-    hipLaunchKernelGGL(k_collect, dim3(L.nb), dim3(RB), 0, st, out, static_cast<long long>(n),
-                       L.chunk, sel, in, cand);
+    // the histogram pass's blocks: the offsets above are per block of it
+    hipLaunchKernelGGL(k_collect, dim3(L.nb2), dim3(EB), 0, st, out, static_cast<long long>(n),
+                       L.chunk2, sel, in, boff, cand);
     hipLaunchKernelGGL(k_pick, dim3(T), dim3(RB), 0, st, sel, in, cand, dstats);
-    hipLaunchKernelGGL(k_flag, dim3(1), dim3(64), 0, st, sel, dstats);
   }
   AEB_HIP(hipGetLastError());
   AEB_HIP(hipMemcpyAsync(host_out, dstats, sizeof(aeb_stats), hipMemcpyDeviceToHost, st));
@@ -749,9 +887,12 @@ int reduce_fallback(const OutCols& out, int64_t n, const aeb_reduce_req& req, vo
   AEB_HIP(hipMemcpyAsync(ss, &rs, sizeof(rs), hipMemcpyHostToDevice, st));
   hipLaunchKernelGGL(k_zero_u32, dim3((T * 256 + 255) / 256), dim3(256), 0, st, shist,
                      static_cast<long long>(T * 256));
+  // larger slices than the main passes: each block merges T x 256 counters
+  const long long fchunk = 16384;
+  const unsigned fnb = static_cast<unsigned>((n + fchunk - 1) / fchunk);
   for (int pass = 0; pass < 8; ++pass) {
-    hipLaunchKernelGGL(k_select_hist, dim3(L.nb), dim3(RB), 0, st, out, static_cast<long long>(n),
-                       L.chunk, ss, pass, shist);
+    hipLaunchKernelGGL(k_select_hist, dim3(fnb), dim3(RB), 0, st, out, static_cast<long long>(n),
+                       fchunk, ss, pass, shist);
     hipLaunchKernelGGL(k_select_step, dim3(1), dim3(64), 0, st, ss, pass, shist);
   }
   hipLaunchKernelGGL(k_select_out, dim3(1), dim3(64), 0, st, ss, req.n_risk, dstats);
