@@ -177,6 +177,58 @@ double orc_trigger_delay(const orc_scenario* s, uint64_t i) {
   return INFINITY;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Closed-loop controller (see orc_scenario).  A decision at tick m reads the */
+/* state after m * period steps: the measured gap and closing speed carry    */
+/* the cosine and sine Box-Muller normals of generator call                  */
+/* (index, CONTROL slot, attempt m) times their noise sds.                   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  long long period;     /* steps between decisions */
+  long long next_tick;  /* step of the next decision */
+  long long on1, on2;   /* steps from which the warning / full command applies */
+  uint32_t tick;        /* decisions taken */
+  int stage;
+} ctl_state;
+
+static int control_on(const orc_scenario* s) { return s->ctl_period > 0.0; }
+
+static void ctl_init(const orc_scenario* s, ctl_state* c) {
+  c->period = llround(s->ctl_period / s->dt);
+  c->next_tick = 0;
+  c->on1 = c->on2 = LLONG_MAX;
+  c->tick = 0;
+  c->stage = 0;
+}
+
+static void ctl_decide(const orc_scenario* s, const orc_sample* p, ctl_state* c, long long step,
+                       long long nd, double gap_true, double closing) {
+  double u[2];
+  orc_uniform_pair(s->seed, s->scenario_id, p->index, ORC_SLOT_CONTROL, c->tick, u);
+  const double r = sqrt(-2.0 * log(u[0]));
+  const double ang = TWO_PI * u[1];
+  const double g = gap_true + s->noise_gap * (r * cos(ang));
+  const double cl = closing + s->noise_v * (r * sin(ang));
+  const double ttc = cl > 0.0 ? g / cl : INFINITY;
+  const int want = ttc < s->ttc_brake ? 2 : (ttc < s->ttc_warn ? 1 : 0);
+  if (want > c->stage) {
+    if (want == 2)
+      c->on2 = step + nd;
+    else
+      c->on1 = step + nd;
+    c->stage = want;
+  }
+  c->tick += 1;
+  c->next_tick += c->period;
+}
+
+static double ctl_command(const orc_scenario* s, const ctl_state* c, long long step) {
+  if (step >= c->on2) return s->a_cmd;
+  if (step >= c->on1) return s->a_warn;
+  return 0.0;
+}
+
 /* first step with the brake command: the dead time plus the trigger delay */
 static long long command_step(const orc_scenario* s, const orc_sample* p) {
   const double q = (s->dead_time + p->trigger) / s->dt;
@@ -198,6 +250,7 @@ void orc_sample_one(const orc_scenario* s, uint64_t i, orc_sample* p) {
   p->gap = orc_draw(&s->gap, seed, sid, i, ORC_SLOT_GAP);
   p->lead_decel = orc_draw(&s->lead_decel, seed, sid, i, ORC_SLOT_LEAD);
   p->trigger = perception_on(s) ? orc_trigger_delay(s, i) : 0.0;
+  p->index = i;
 }
 
 int orc_sample_range(const orc_scenario* s, int64_t first, int64_t count, double* const cols[12]) {
@@ -281,6 +334,20 @@ int orc_validate(const orc_scenario* s) {
   if (s->frame_period > 0.0 && !(s->horizon / s->frame_period <= 1.0e6)) return ORC_EINVAL;
   if (!(s->p_dropout >= 0.0 && s->p_dropout < 1.0)) return ORC_EINVAL;
   if (s->confirm < 1 || s->confirm > 64) return ORC_EINVAL;
+  /* controller: a whole positive number of steps per tick, fewer than 2^24
+   * ticks over the horizon, an obstacle to measure, no perception trigger,
+   * thresholds >= 0 (+inf allowed), a_cmd <= a_warn <= 0, noise sds >= 0 */
+  if (!(s->ctl_period >= 0.0) || !isfinite(s->ctl_period)) return ORC_EINVAL;
+  if (s->ctl_period > 0.0) {
+    const long long per = llround(s->ctl_period / s->dt);
+    if (per < 1) return ORC_EINVAL;
+    if (!(s->horizon / s->dt / (double)per < 16777216.0)) return ORC_EINVAL;
+    if (s->obstacle == ORC_OBS_NONE || perception_on(s)) return ORC_EINVAL;
+    if (!(s->ttc_warn >= 0.0) || !(s->ttc_brake >= 0.0)) return ORC_EINVAL;
+    if (!isfinite(s->a_warn) || !(s->a_cmd <= s->a_warn && s->a_warn <= 0.0)) return ORC_EINVAL;
+    if (!(s->noise_gap >= 0.0) || !isfinite(s->noise_gap)) return ORC_EINVAL;
+    if (!(s->noise_v >= 0.0) || !isfinite(s->noise_v)) return ORC_EINVAL;
+  }
   /* the explicit actuator update needs dt/tau <= 1 for every sample */
   if (!(dist_min(&s->tau) > 0.0)) return ORC_EINVAL;
   if (s->integrator == ORC_EULER && dist_min(&s->tau) < s->dt) return ORC_EINVAL;
@@ -339,9 +406,18 @@ static void rollout_euler(const orc_scenario* s, const orc_sample* p, int clamp_
   int collided = 0, end = 0;
   float vimp = 0.0f;
   long long step = 0;
+  const int ctl = control_on(s);
+  ctl_state cs;
+  ctl_init(s, &cs);
 
   for (;;) {
-    double cmd = step >= nd ? s->a_cmd : 0.0;
+    double cmd;
+    if (ctl) {
+      if (step == cs.next_tick) ctl_decide(s, p, &cs, step, nd, (gap0 + xl) - x, v - vl);
+      cmd = ctl_command(s, &cs, step);
+    } else {
+      cmd = step >= nd ? s->a_cmd : 0.0;
+    }
     /* realised brake deceleration cannot exceed the friction limit */
     double abe = clamp_state ? a : max2(a, k.alim);
     double v2 = v * v;
@@ -444,9 +520,18 @@ static void rollout_rk4(const orc_scenario* s, const orc_sample* p, orc_result* 
   int collided = 0, end = 0;
   float vimp = 0.0f;
   long long step = 0;
+  const int ctl = control_on(s);
+  ctl_state cs;
+  ctl_init(s, &cs);
 
   for (;;) {
-    double cmd = step >= nd ? s->a_cmd : 0.0;
+    double cmd;
+    if (ctl) {
+      if (step == cs.next_tick) ctl_decide(s, p, &cs, step, nd, gap0 - y.x, y.v);
+      cmd = ctl_command(s, &cs, step);
+    } else {
+      cmd = step >= nd ? s->a_cmd : 0.0;
+    }
     orc_state k1 = rhs(&k, rt, cmd, y);
     orc_state k2 = rhs(&k, rt, cmd, axpy(y, h2, k1));
     orc_state k3 = rhs(&k, rt, cmd, axpy(y, h2, k2));
@@ -529,6 +614,7 @@ int orc_rollout_given(const orc_scenario* s, const double* const cols[12], int64
     p.gap = cols[9][k];
     p.lead_decel = cols[10][k];
     p.trigger = cols[11][k];
+    p.index = (uint64_t)k;
     orc_rollout_one(s, &p, clamp_state, &r);
     dist[k] = r.dist;
     status[k] = r.status;

@@ -35,7 +35,8 @@ enum { ORC_OK = 0, ORC_EINVAL = -1 };
 enum {
   ORC_SLOT_V0 = 0, ORC_SLOT_MU = 1, ORC_SLOT_MASS = 2, ORC_SLOT_GRADE = 3,
   ORC_SLOT_CDA = 4, ORC_SLOT_CRR = 5, ORC_SLOT_TAU = 6, ORC_SLOT_GAP = 7,
-  ORC_SLOT_LEAD = 8, ORC_SLOT_LATENCY = 9, ORC_SLOT_OCCLUSION = 10, ORC_SLOT_DETECT = 11
+  ORC_SLOT_LEAD = 8, ORC_SLOT_LATENCY = 9, ORC_SLOT_OCCLUSION = 10, ORC_SLOT_DETECT = 11,
+  ORC_SLOT_CONTROL = 12
 };
 
 typedef struct {
@@ -67,12 +68,22 @@ typedef struct {
   double frame_period, p_dropout;
   int32_t confirm;
   int32_t pad2;
+  /* Closed-loop controller (the controller assessment Section VIII names):
+   * every ctl_period seconds (a whole number of steps, llround(ctl_period /
+   * dt)) it measures the gap and the closing speed with additive normal
+   * noise (sd noise_gap, noise_v), forms TTC = gap / closing speed (+inf if
+   * the measured closing speed is not positive) and raises its stage, which
+   * never falls: TTC < ttc_warn -> stage 1 (command a_warn), TTC < ttc_brake
+   * -> stage 2 (command a_cmd); a new stage's command starts dead_time
+   * later.  ctl_period = 0: the open-loop command of dead_time. */
+  double ctl_period, ttc_warn, ttc_brake, a_warn, noise_gap, noise_v;
 } orc_scenario;
 
 /* One sample's realised parameter vector (xi^(i) of Section IV-A). */
 typedef struct {
   double v0, mu, mass, grade, sin_grade, cos_grade, cda, crr, tau, gap, lead_decel;
   double trigger;  /* perception trigger delay (s); +inf: the object is never confirmed */
+  uint64_t index;  /* the sample's index (keys the controller's measurement noise) */
 } orc_sample;
 
 typedef struct {

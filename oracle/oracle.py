@@ -18,10 +18,12 @@ COLUMNS = ("v0", "mu", "mass", "grade", "sin_grade", "cos_grade", "cda", "crr", 
            "gap", "lead_decel", "trigger")
 DISTS = ("v0", "mu", "mass", "grade", "cda", "crr", "tau", "gap", "lead_decel")
 SLOTS = {name: k for k, name in enumerate(DISTS)}
-SLOTS.update({"latency": 9, "occlusion": 10, "detect": 11})
+SLOTS.update({"latency": 9, "occlusion": 10, "detect": 11, "control": 12})
 # perception (absent from a scenario dict: no perception)
 PERCEPTION_DEFAULTS = {"latency": ("const", 0.0), "occlusion": ("const", 0.0),
                        "frame_period": 0.0, "p_dropout": 0.0, "confirm": 1}
+# closed-loop controller (absent: open loop)
+CONTROL_FIELDS = ("ctl_period", "ttc_warn", "ttc_brake", "a_warn", "noise_gap", "noise_v")
 INTEGRATORS = {"euler": 0, "rk4": 1}
 OBSTACLES = {"none": 0, "stationary": 1, "lead": 2}
 DIST_KINDS = {"const": 0, "uniform": 1, "normal": 2, "trunc_normal": 3}
@@ -43,7 +45,8 @@ class Scenario(C.Structure):
                                              "h_cog", "wheelbase")]
                 + [(f, Dist) for f in DISTS]
                 + [("latency", Dist), ("occlusion", Dist), ("frame_period", C.c_double),
-                   ("p_dropout", C.c_double), ("confirm", C.c_int32), ("pad2", C.c_int32)])
+                   ("p_dropout", C.c_double), ("confirm", C.c_int32), ("pad2", C.c_int32)]
+                + [(f, C.c_double) for f in CONTROL_FIELDS])
 
 
 class ReduceReq(C.Structure):
@@ -121,6 +124,8 @@ def scenario(d):
     s.frame_period = float(per["frame_period"])
     s.p_dropout = float(per["p_dropout"])
     s.confirm = int(per["confirm"])
+    for f in CONTROL_FIELDS:
+        setattr(s, f, float(d.get(f, 0.0)))
     return s
 
 

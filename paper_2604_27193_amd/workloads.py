@@ -23,6 +23,8 @@ Workloads:
   * ``serving_stream`` -- Poisson arrivals of randomized single scenarios.
   * ``perception`` -- ``single`` with a stochastic brake trigger from frame
     sensing: occlusion, per-frame dropout, a confirmation run and latency.
+  * ``closed_loop`` -- ``single`` with the obstacle farther ahead and a
+    two-stage TTC-threshold controller on noisy measurements.
 """
 import numpy as np
 
@@ -155,5 +157,21 @@ def perception(n=10_000, seed=42, scenario_id=0, **over):
     d.update({"latency": ("trunc_normal", 0.08, 0.02, 0.03, 0.12),
               "occlusion": ("uniform", 0.0, 4.0), "frame_period": 0.05,
               "p_dropout": 0.1, "confirm": 3})
+    d.update(over)
+    return d
+
+
+def closed_loop(n=10_000, seed=42, scenario_id=0, **over):
+    """The stationary-obstacle scenario under a TTC-threshold controller.
+
+    The obstacle is far ahead (gap ~ N(120 m, 10 m)); at 20 Hz the controller
+    measures gap and closing speed with noise (sd 0.5 m, 0.3 m/s), brakes
+    partially at -3 m/s^2 once the measured TTC drops below 3.0 s and fully
+    (a_cmd) below 2.0 s, each command after the 50 ms dead time; horizon 15 s.
+    """
+    d = single(n, seed, scenario_id)
+    d.update({"gap": ("normal", 120.0, 10.0), "horizon": 15.0, "ctl_period": 0.05,
+              "ttc_warn": 3.0, "ttc_brake": 2.0, "a_warn": -3.0, "noise_gap": 0.5,
+              "noise_v": 0.3})
     d.update(over)
     return d
