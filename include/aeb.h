@@ -61,7 +61,7 @@ enum { AEB_END_STOP = 1, AEB_END_IMPACT = 2, AEB_END_HORIZON = 3, AEB_COLLIDED =
 enum {
   AEB_SLOT_V0 = 0, AEB_SLOT_MU = 1, AEB_SLOT_MASS = 2, AEB_SLOT_GRADE = 3, AEB_SLOT_CDA = 4,
   AEB_SLOT_CRR = 5, AEB_SLOT_TAU = 6, AEB_SLOT_GAP = 7, AEB_SLOT_LEAD = 8,
-  AEB_SLOT_LATENCY = 9, AEB_SLOT_OCCLUSION = 10, AEB_SLOT_DETECT = 11
+  AEB_SLOT_LATENCY = 9, AEB_SLOT_OCCLUSION = 10, AEB_SLOT_DETECT = 11, AEB_SLOT_CONTROL = 12
 };
 
 /* Distribution of one uncertain parameter (eq. (11)-(15) use NORMAL).
@@ -106,7 +106,20 @@ typedef struct {
  *     trigger = J P + latency with J the first frame that completes `confirm`
  *     consecutive detections, searched over frames j with j P <= horizon;
  *     +inf (no braking) if there is none.  latency CONST 0 and frame_period 0
- *     switch perception off (trigger = 0) and draw nothing. */
+ *     switch perception off (trigger = 0) and draw nothing.
+ *   Closed-loop controller (the controller assessment of Sec. VIII), on when
+ *   ctl_period > 0; replaces the open-loop command, needs an obstacle and no
+ *   perception:
+ *     ctl_period: decision period, rounded to S = llround(ctl_period/dt) >= 1
+ *       steps; decision m reads the state after m S steps.
+ *     noise_gap, noise_v: sds of additive normal noise on the measured gap
+ *       (gap + x_lead - x) and closing speed (v - v_lead): the cosine and sine
+ *       Box-Muller normals of the call (i, AEB_SLOT_CONTROL | m << 8, ...).
+ *     TTC = measured gap / measured closing speed (+inf if the latter <= 0);
+ *     the controller's stage only rises: TTC < ttc_warn -> 1 (command a_warn,
+ *     a_cmd <= a_warn <= 0), TTC < ttc_brake -> 2 (command a_cmd).  The
+ *     command of a stage raised at decision step k applies from step
+ *     k + llround(dead_time/dt). */
 typedef struct {
   uint64_t seed;
   uint64_t scenario_id;
@@ -121,6 +134,7 @@ typedef struct {
   double frame_period, p_dropout;
   int32_t confirm;
   int32_t reserved2;
+  double ctl_period, ttc_warn, ttc_brake, a_warn, noise_gap, noise_v;
 } aeb_scenario;
 
 /* Structure-of-arrays parameter columns, each `n` doubles (host or device,
@@ -194,7 +208,11 @@ int aeb_version(void);
  * truncation lo >= hi; a tau distribution that can reach 0 (or, for Euler,
  * values below dt); RK4 combined with a lead vehicle; for perception:
  * frame_period negative or not finite, more than 1e6 frames over the horizon,
- * p_dropout outside [0, 1), confirm outside [1, 64]. */
+ * p_dropout outside [0, 1), confirm outside [1, 64]; for the controller:
+ * ctl_period negative, not finite or below half a step, 2^24 or more
+ * decisions over the horizon, no obstacle, perception on, a TTC threshold
+ * below 0 or NaN, a_warn outside [a_cmd, 0], noise sds negative or not
+ * finite. */
 int aeb_validate(const aeb_scenario* scn);
 
 /* Raw generator output (Sec. IV-B "fixed seed"; Philox4x32-10 of Salmon et
@@ -230,7 +248,9 @@ int aeb_sample_params(const aeb_scenario* scn, int64_t first, int64_t count, con
  *     distance and collision decision; samples whose distance or clearance is
  *     within 1 mm + 1e-5 gap of the obstacle get AEB_BOUNDARY in their status)
  *     or AEB_FP32C_FIXUP (as AEB_FP32C, then the flagged samples are
- *     recomputed in FP64, so every collision flag is exact).
+ *     recomputed in FP64, so every collision flag is exact).  A scenario with
+ *     the closed-loop controller takes AEB_FP64 only (one checked lane per
+ *     sample; AEB_EINVAL otherwise).
  *   out: device output columns with out->n == n_samples.
  * Asynchronous on `stream`.  May grow the scratch arena on first use. */
 int aeb_rollout(const aeb_scenario* scn, const aeb_params* params, int precision,
@@ -308,7 +328,8 @@ int aeb_autotune(const aeb_scenario* calib, int precision, const char* cache_pat
  * scratch (allocated at creation) and, for batches, pinned copies of the
  * scenario tables.  Only the sorted block-structured path is recorded: FP64
  * explicit Euler (fused form) or RK4, FP32C explicit Euler; AEB_EINVAL for
- * the unfused Euler form (nofma) and the FP32C fix-up mode. */
+ * the unfused Euler form (nofma), the closed-loop controller and the FP32C
+ * fix-up mode. */
 typedef struct aeb_graph aeb_graph;
 
 /* One scenario: params (device columns, or NULL for the in-kernel generator),
@@ -412,7 +433,8 @@ int aeb_server_create(const aeb_server_cfg* cfg, aeb_server** out);
 int aeb_server_destroy(aeb_server* srv);
 
 /* Queue one evaluation (non-blocking).  AEB_EINVAL: invalid scenario or one
- * the batched path cannot run (the unfused Euler form, RK4 in FP32C);
+ * the batched path cannot run (the unfused Euler form, RK4 in FP32C, the
+ * closed-loop controller);
  * AEB_ENOMEM: its footprint exceeds the request part of the arena or its
  * sample count max_tick_samples; AEB_EAGAIN: the queue is full.  deadline_s:
  * latency budget used for miss accounting (e.g. 0.530). */

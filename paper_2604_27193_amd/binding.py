@@ -14,7 +14,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libaeb.so")
-ABI_VERSION = 3     # the aeb_version() these structures match
+ABI_VERSION = 4     # the aeb_version() these structures match
 
 COLUMNS = ("v0", "mu", "mass", "grade", "sin_grade", "cos_grade", "cda", "crr", "tau", "gap",
            "lead_decel", "trigger")
@@ -22,6 +22,8 @@ DISTS = ("v0", "mu", "mass", "grade", "cda", "crr", "tau", "gap", "lead_decel")
 # perception fields and their values when a scenario dict leaves them out
 PERCEPTION_DEFAULTS = {"latency": ("const", 0.0), "occlusion": ("const", 0.0),
                        "frame_period": 0.0, "p_dropout": 0.0, "confirm": 1}
+# closed-loop controller fields (absent: 0, the open-loop command)
+CONTROL_FIELDS = ("ctl_period", "ttc_warn", "ttc_brake", "a_warn", "noise_gap", "noise_v")
 INTEGRATORS = {"euler": 0, "rk4": 1}
 OBSTACLES = {"none": 0, "stationary": 1, "lead": 2}
 DIST_KINDS = {"const": 0, "uniform": 1, "normal": 2, "trunc_normal": 3}
@@ -58,7 +60,8 @@ class Scenario(C.Structure):
                                              "h_cog", "wheelbase")]
                 + [(f, Dist) for f in DISTS]
                 + [("latency", Dist), ("occlusion", Dist), ("frame_period", C.c_double),
-                   ("p_dropout", C.c_double), ("confirm", C.c_int32), ("reserved2", C.c_int32)])
+                   ("p_dropout", C.c_double), ("confirm", C.c_int32), ("reserved2", C.c_int32)]
+                + [(f, C.c_double) for f in CONTROL_FIELDS])
 
 
 class Params(C.Structure):
@@ -190,6 +193,8 @@ def scenario(d):
     s.frame_period = float(per["frame_period"])
     s.p_dropout = float(per["p_dropout"])
     s.confirm = int(per["confirm"])
+    for f in CONTROL_FIELDS:
+        setattr(s, f, float(d.get(f, 0.0)))
     return s
 
 

@@ -137,6 +137,23 @@ int validate(const aeb_scenario& s) {
     return fail(AEB_EINVAL, "more than 1e6 sensing frames over the horizon");
   if (!(s.p_dropout >= 0.0 && s.p_dropout < 1.0)) return fail(AEB_EINVAL, "p_dropout out of [0, 1)");
   if (s.confirm < 1 || s.confirm > 64) return fail(AEB_EINVAL, "confirm out of [1, 64]");
+  if (!(s.ctl_period >= 0.0) || !std::isfinite(s.ctl_period))
+    return fail(AEB_EINVAL, "ctl_period must be >= 0 and finite");
+  if (s.ctl_period > 0.0) {
+    const long long per = std::llround(s.ctl_period / s.dt);
+    if (per < 1) return fail(AEB_EINVAL, "ctl_period shorter than half a step");
+    if (!(s.horizon / s.dt / static_cast<double>(per) < 16777216.0))
+      return fail(AEB_EINVAL, "2^24 or more controller decisions over the horizon");
+    if (s.obstacle == AEB_OBS_NONE) return fail(AEB_EINVAL, "the controller needs an obstacle");
+    if (perception_on(s)) return fail(AEB_EINVAL, "the controller and perception exclude each other");
+    if (!(s.ttc_warn >= 0.0) || !(s.ttc_brake >= 0.0))
+      return fail(AEB_EINVAL, "TTC thresholds must be >= 0");
+    if (!std::isfinite(s.a_warn) || !(s.a_cmd <= s.a_warn && s.a_warn <= 0.0))
+      return fail(AEB_EINVAL, "a_warn must lie in [a_cmd, 0]");
+    if (!(s.noise_gap >= 0.0) || !std::isfinite(s.noise_gap) || !(s.noise_v >= 0.0) ||
+        !std::isfinite(s.noise_v))
+      return fail(AEB_EINVAL, "measurement noise sds must be >= 0 and finite");
+  }
   double tmin = support_min(s.tau);
   if (!(tmin > 0.0)) return fail(AEB_EINVAL, "tau distribution can reach 0");
   if (s.integrator == AEB_EULER && tmin < s.dt)
@@ -223,7 +240,7 @@ extern "C" {
 
 const char* aeb_last_error(void) { return g_err.c_str(); }
 
-int aeb_version(void) { return 3; }
+int aeb_version(void) { return 4; }
 
 int aeb_timing_enable(int on) {
   g_timing.on = on != 0;

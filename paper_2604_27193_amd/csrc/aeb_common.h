@@ -139,6 +139,9 @@ __host__ __device__ inline double trigger_delay(const aeb_scenario& s, uint64_t 
   return INFINITY;
 }
 
+// The closed-loop controller replaces the open-loop command when on.
+__host__ __device__ inline bool control_on(const aeb_scenario& s) { return s.ctl_period > 0.0; }
+
 // First step with the brake command for a sample with trigger delay `trig`:
 // llround((dead_time + trig) / dt), capped at nmax (a command at or beyond the
 // last step is never applied, so every value from nmax up acts the same).

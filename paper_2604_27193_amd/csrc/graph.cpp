@@ -128,7 +128,7 @@ int aeb_graph_create(const aeb_scenario* scn, const aeb_params* params, int prec
   if (rc != AEB_OK) return rc;
   if (!fast_path_applies(*scn, precision))
     return fail(AEB_EINVAL, "graphs record the block-structured path (not the unfused Euler "
-                            "form, not RK4 in FP32C)");
+                            "form, not RK4 in FP32C, not the closed-loop controller)");
   if (out->n != scn->n_samples) return fail(AEB_EINVAL, "outputs length differs from n_samples");
   ParamSrc src{};
   if (params) {

@@ -1208,6 +1208,7 @@ __global__ __launch_bounds__(256) void k_roll_fp32c_lead(const Job* __restrict__
 }  // namespace
 
 bool fast_path_applies(const aeb_scenario& s, int precision) {
+  if (control_on(s)) return false;  // the controller runs in the checked kernel
   if (precision == AEB_FP64)
     return s.integrator == AEB_RK4 ? s.obstacle != AEB_OBS_LEAD : !s.nofma;
   if (s.integrator != AEB_EULER) return false;

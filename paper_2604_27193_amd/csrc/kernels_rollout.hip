@@ -42,6 +42,7 @@ __device__ inline Lane load_lane(const aeb_scenario& s, const ParamSrc& src, int
     L.trig = src.trig ? src.trig[i] : 0.0;
   }
   L.k = derive(s, mu, mass, sg, cg, cda, crr);
+  L.index = static_cast<uint64_t>(i);
   return L;
 }
 
@@ -53,17 +54,32 @@ __device__ inline void store(const OutCols& o, int64_t i, const Result& r) {
   o.vimp[i] = r.vimp;
 }
 
-template <int INTEG, int OBS, bool NOFMA, bool DEVRNG>
+template <int INTEG, int OBS, bool NOFMA, bool DEVRNG, bool CTL>
 __global__ __launch_bounds__(256) void k_rollout_fp64(aeb_scenario s, ParamSrc src, OutCols out,
-                                                      int64_t n, int64_t nd, int64_t nmax) {
+                                                      int64_t n, int64_t nd, int64_t nmax,
+                                                      CtlArgs ca) {
   int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   Lane L = load_lane<DEVRNG>(s, src, i);
   // with perception the command step is the sample's own
   if (perception_on(s)) nd = command_step(s, L.trig, nmax);
-  Result r = (INTEG == AEB_EULER) ? euler_fp64<OBS, NOFMA>(L, s.dt, s.a_cmd, nd, nmax, s.impact_exit)
-                                  : rk4_fp64<OBS>(L, s.dt, s.a_cmd, nd, nmax, s.impact_exit);
+  Result r = (INTEG == AEB_EULER)
+                 ? euler_fp64<OBS, NOFMA, CTL>(L, s.dt, s.a_cmd, nd, nmax, s.impact_exit, &ca)
+                 : rk4_fp64<OBS, CTL>(L, s.dt, s.a_cmd, nd, nmax, s.impact_exit, &ca);
   store(out, i, r);
+}
+
+static CtlArgs ctl_args(const aeb_scenario& s) {
+  CtlArgs a{};
+  if (control_on(s)) a.period = std::llround(s.ctl_period / s.dt);
+  a.ttc_warn = s.ttc_warn;
+  a.ttc_brake = s.ttc_brake;
+  a.a_warn = s.a_warn;
+  a.noise_gap = s.noise_gap;
+  a.noise_v = s.noise_v;
+  a.seed = s.seed;
+  a.sid = s.scenario_id;
+  return a;
 }
 
 // FP64 recomputation of the samples listed in fix[1 .. fix[0]]; clears the
@@ -84,17 +100,37 @@ __global__ __launch_bounds__(256) void k_fixup_fp64(aeb_scenario s, ParamSrc src
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
-template <int INTEG, int OBS, bool NOFMA>
+template <int INTEG, int OBS, bool NOFMA, bool CTL = false>
 static void go_fp64(const aeb_scenario& s, const ParamSrc* src, const OutCols& out, int64_t n,
                     int64_t nd, int64_t nmax, hipStream_t st) {
   dim3 grid(static_cast<unsigned>((n + 255) / 256)), block(256);
   ParamSrc p = src ? *src : ParamSrc{};
+  const CtlArgs ca = ctl_args(s);
   if (src)
-    hipLaunchKernelGGL((k_rollout_fp64<INTEG, OBS, NOFMA, false>), grid, block, 0, st, s, p, out, n,
-                       nd, nmax);
+    hipLaunchKernelGGL((k_rollout_fp64<INTEG, OBS, NOFMA, false, CTL>), grid, block, 0, st, s, p,
+                       out, n, nd, nmax, ca);
   else
-    hipLaunchKernelGGL((k_rollout_fp64<INTEG, OBS, NOFMA, true>), grid, block, 0, st, s, p, out, n,
-                       nd, nmax);
+    hipLaunchKernelGGL((k_rollout_fp64<INTEG, OBS, NOFMA, true, CTL>), grid, block, 0, st, s, p,
+                       out, n, nd, nmax, ca);
+}
+
+// the closed-loop controller: FP64, one checked lane per sample
+static int go_control(const aeb_scenario& s, const ParamSrc* src, int precision,
+                      const OutCols& out, int64_t n, int64_t nd, int64_t nmax, hipStream_t st) {
+  if (precision != AEB_FP64)
+    return fail(AEB_EINVAL, "the closed-loop controller runs in FP64 only");
+  timing_begin(st);
+  if (s.integrator == AEB_RK4)
+    go_fp64<AEB_RK4, AEB_OBS_STATIONARY, false, true>(s, src, out, n, nd, nmax, st);
+  else if (s.obstacle == AEB_OBS_LEAD)
+    s.nofma ? go_fp64<AEB_EULER, AEB_OBS_LEAD, true, true>(s, src, out, n, nd, nmax, st)
+            : go_fp64<AEB_EULER, AEB_OBS_LEAD, false, true>(s, src, out, n, nd, nmax, st);
+  else
+    s.nofma ? go_fp64<AEB_EULER, AEB_OBS_STATIONARY, true, true>(s, src, out, n, nd, nmax, st)
+            : go_fp64<AEB_EULER, AEB_OBS_STATIONARY, false, true>(s, src, out, n, nd, nmax, st);
+  timing_end(st);
+  AEB_HIP(hipGetLastError());
+  return AEB_OK;
 }
 
 template <int OBS>
@@ -137,6 +173,7 @@ int launch_batch(const aeb_scenario* scns, int n_scn, int precision, const OutCo
 int launch_rollout(const aeb_scenario& s, const ParamSrc* src, int precision, const OutCols& out,
                    int64_t n, hipStream_t st) {
   const int64_t nd = dead_steps(s), nmax = horizon_steps(s);
+  if (control_on(s)) return go_control(s, src, precision, out, n, nd, nmax, st);
   if (fast_path_applies(s, precision)) return launch_rollout_fast(s, src, precision, out, n, st);
   if (precision == AEB_FP32C || precision == AEB_FP32C_FIXUP) {
     // every Euler case takes the block-structured path

@@ -5,8 +5,9 @@
 //
 // FP64 forms: explicit Euler with four fused multiply-adds (or none when
 // NOFMA), RK4 without fused operations.  These checked per-step forms serve
-// RK4, the unfused Euler form and the FP64 recomputation of FP32 boundary
-// samples; the explicit-Euler throughput path is kernels_fast.hip.
+// RK4, the unfused Euler form, the closed-loop controller and the FP64
+// recomputation of FP32 boundary samples; the explicit-Euler throughput path
+// is kernels_fast.hip.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -30,7 +31,62 @@ struct Lane {
   Consts k;
   double tau;
   double trig;           // perception delay (s)
+  uint64_t index;        // the sample's index (keys the controller's noise)
 };
+
+// ---------------------------------------------------------------------------
+// Closed-loop controller (Sec. VIII's controller assessment).  Every `period`
+// steps it measures gap and closing speed with additive normal noise (the
+// cosine and sine Box-Muller normals of one generator call per decision),
+// forms TTC and raises its latched stage; a stage's command starts nd steps
+// after the decision.
+// ---------------------------------------------------------------------------
+struct CtlArgs {
+  int64_t period;
+  double ttc_warn, ttc_brake, a_warn, noise_gap, noise_v;
+  uint64_t seed, sid;
+};
+
+struct Ctl {
+  int64_t next_tick, on1, on2;  // next decision step; first steps of the two commands
+  uint32_t tick;                // decisions taken
+  int stage;
+};
+
+__device__ inline Ctl ctl_start() {
+  Ctl c;
+  c.next_tick = 0;
+  c.on1 = c.on2 = INT64_MAX;
+  c.tick = 0;
+  c.stage = 0;
+  return c;
+}
+
+__device__ inline void ctl_decide(const CtlArgs& A, Ctl& c, uint64_t index, int64_t step,
+                                  int64_t nd, double gap_true, double closing) {
+  const U2 u = uniform2(A.seed, A.sid, index, AEB_SLOT_CONTROL, c.tick);
+  const double r = sqrt(-2.0 * log(u.a));
+  const double ang = 6.283185307179586 * u.b;
+  const double g = gap_true + A.noise_gap * (r * cos(ang));
+  const double cl = closing + A.noise_v * (r * sin(ang));
+  const double ttc = cl > 0.0 ? g / cl : INFINITY;
+  const int want = ttc < A.ttc_brake ? 2 : (ttc < A.ttc_warn ? 1 : 0);
+  if (want > c.stage) {
+    if (want == 2)
+      c.on2 = step + nd;
+    else
+      c.on1 = step + nd;
+    c.stage = want;
+  }
+  c.tick += 1;
+  c.next_tick += A.period;
+}
+
+__device__ inline double ctl_command(const Ctl& c, int64_t step, double a_cmd, double a_warn) {
+  if (step >= c.on2) return a_cmd;
+  if (step >= c.on1) return a_warn;
+  return 0.0;
+}
 
 // ---------------------------------------------------------------------------
 // Explicit Euler, FP64.  Per step k (cmd = a_cmd once k >= nd, else 0):
@@ -38,9 +94,9 @@ struct Lane {
 //   x' = fma(dt, v, x); v' = fma(dt, acc, v); a' = fma(dt/tau, cmd - a, a)
 //   lead: xl' = fma(dt, vl, xl); vl' = max(fma(-dt, al, vl), 0)
 // ---------------------------------------------------------------------------
-template <int OBS, bool NOFMA>
+template <int OBS, bool NOFMA, bool CTL = false>
 __device__ inline Result euler_fp64(const Lane& L, double dt, double a_cmd, int64_t nd,
-                                    int64_t nmax, int impact_exit) {
+                                    int64_t nmax, int impact_exit, const CtlArgs* ca = nullptr) {
   const double kt = dt / L.tau;
   const double nkd = -L.k.kd, c = L.k.c, alim = L.k.alim;
   double x = 0.0, v = L.v0, a = 0.0;
@@ -51,8 +107,15 @@ __device__ inline Result euler_fp64(const Lane& L, double dt, double a_cmd, int6
   float vimp = 0.0f;
   int end = 0;
   int64_t step = 0;
+  Ctl cs = ctl_start();
   for (;;) {
-    const double cmd = step >= nd ? a_cmd : 0.0;
+    double cmd;
+    if (CTL) {
+      if (step == cs.next_tick) ctl_decide(*ca, cs, L.index, step, nd, (gap0 + xl) - x, v - vl);
+      cmd = ctl_command(cs, step, a_cmd, ca->a_warn);
+    } else {
+      cmd = step >= nd ? a_cmd : 0.0;
+    }
     const double abe = fmax(a, alim);
     const double v2 = v * v;
     double acc, xn, vn, an;
@@ -133,9 +196,9 @@ __device__ inline S3 rk_axpy(S3 y, double h, S3 d) {
   return o;
 }
 
-template <int OBS>
+template <int OBS, bool CTL = false>
 __device__ inline Result rk4_fp64(const Lane& L, double dt, double a_cmd, int64_t nd,
-                                  int64_t nmax, int impact_exit) {
+                                  int64_t nmax, int impact_exit, const CtlArgs* ca = nullptr) {
   const double h2 = 0.5 * dt, h6 = dt / 6.0, rt = 1.0 / L.tau;
   const double gap0 = L.gap;
   S3 y{0.0, L.v0, 0.0};
@@ -144,8 +207,15 @@ __device__ inline Result rk4_fp64(const Lane& L, double dt, double a_cmd, int64_
   float vimp = 0.0f;
   int end = 0;
   int64_t step = 0;
+  Ctl cs = ctl_start();
   for (;;) {
-    const double cmd = step >= nd ? a_cmd : 0.0;
+    double cmd;
+    if (CTL) {
+      if (step == cs.next_tick) ctl_decide(*ca, cs, L.index, step, nd, gap0 - y.x, y.v);
+      cmd = ctl_command(cs, step, a_cmd, ca->a_warn);
+    } else {
+      cmd = step >= nd ? a_cmd : 0.0;
+    }
     S3 k1 = rk_rhs(L.k, rt, cmd, y);
     S3 k2 = rk_rhs(L.k, rt, cmd, rk_axpy(y, h2, k1));
     S3 k3 = rk_rhs(L.k, rt, cmd, rk_axpy(y, h2, k2));

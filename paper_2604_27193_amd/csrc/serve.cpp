@@ -122,7 +122,7 @@ class HipExecutor final : public serve::Executor {
     if (!fast_path_applies(s, cfg_.precision))
       return fail(AEB_EINVAL,
                   "serving runs the batched block-structured path (not the unfused Euler "
-                  "form, not RK4 in FP32C)");
+                  "form, not RK4 in FP32C, not the closed-loop controller)");
     return AEB_OK;
   }
 

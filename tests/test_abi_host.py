@@ -91,6 +91,15 @@ def test_perception_validation_agrees(B, orc):
     assert B.validate(W.perception(10)) == B.OK
 
 
+def test_controller_validation_agrees(B, orc):
+    from test_oracle_control import BAD
+    for change in BAD:
+        d = W.closed_loop(10)
+        d.update(change)
+        assert B.validate(d) == B.EINVAL == orc.validate(d), change
+    assert B.validate(W.closed_loop(10)) == B.OK == orc.validate(W.closed_loop(10))
+
+
 def test_perception_needs_trigger_column(B):
     cols = {c: np.zeros(10) for c in B.COLUMNS if c != "trigger"}
     with pytest.raises(B.AebError) as e:
