@@ -271,6 +271,45 @@ def perception_leg(B, W, torch, n):
     return res
 
 
+def control_leg(B, W, torch, n):
+    """Closed-loop controller assessment (Sec. VIII): the TTC-threshold
+    controller on noisy measurements, run by the block-structured FP64 kernel.
+    Its throughput against the open-loop run of the same scenario, and
+    P(collision) over a grid of full-brake thresholds and noise levels."""
+    import numpy as np
+    out = B.alloc_outputs(n)
+    d = W.closed_loop(n)
+    ms = kernel_ms(B, torch, d, out, "fp64")
+    steps = int(out["steps"].to(torch.int64).sum().item())
+    st = B.reduce(out, risk=RISK)
+    # the same scenario open loop (braking from the start) on the block path
+    d_open = {k: v for k, v in d.items() if k not in B.CONTROL_FIELDS}
+    ms_open = kernel_ms(B, torch, d_open, out, "fp64")
+    steps_open = int(out["steps"].to(torch.int64).sum().item())
+    flops = EULER_FLOPS_PER_STEP * steps
+    res = {"workload": f"stationary obstacle at N(120 m, 10 m), {n} samples, explicit Euler "
+                       "dt=1 ms, T=15 s; 20 Hz controller, partial braking -3 m/s^2 below TTC "
+                       "3.0 s, full braking below 2.0 s, measurement noise 0.5 m / 0.3 m/s",
+           "kernel": "k_roll_fp64 with the controller (block-structured; blocks end at "
+                     "decisions and command switches)",
+           "kernel_ms": ms, "rollouts_per_s": n / (ms * 1e-3), "steps_per_launch": steps,
+           "achieved_tflops": flops / (ms * 1e-3) / 1e12,
+           "frac_fp64_peak": flops / (ms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+           "p_collision": st["p_collision"],
+           "open_loop_block_path": {"kernel_ms": ms_open, "steps_per_launch": steps_open,
+                                    "step_rate_closed_over_open":
+                                        (steps / ms) / (steps_open / ms_open)}}
+    rows = []
+    for tb in (1.6, 1.8, 2.0, 2.2, 2.4):
+        for sg, sv in ((0.0, 0.0), (0.5, 0.3), (2.0, 1.0)):
+            dd = W.closed_loop(200_000, ttc_brake=tb, noise_gap=sg, noise_v=sv)
+            s2 = B.reduce(B.rollout(dd), risk=RISK)
+            rows.append({"ttc_brake": tb, "noise_gap": sg, "noise_v": sv,
+                         "p_collision": s2["p_collision"], "mean_dist": s2["mean_dist"]})
+    res["threshold_grid"] = {"samples": 200_000, "ttc_warn": 3.0, "rows": rows}
+    return res
+
+
 def n_sweep_leg(B, W, torch, sizes=(1_000, 10_000, 100_000, 1_048_576), reps=5):
     """Rollout call (parameters drawn in-kernel) plus reduction at growing N:
     below ~1e5 samples the launch sequence, not the integration, sets the time."""
@@ -488,7 +527,7 @@ def main():
     step_wall = wallg64 if use_graph else wall64
     value = args.steps * n / step_wall
 
-    rk4 = nsweep = study = perception = None
+    rk4 = nsweep = study = perception = control = None
     if not args.headline_only:
         log("bench: rk4 leg")
         rk4 = rk4_leg(B, W, torch, n)
@@ -498,6 +537,8 @@ def main():
         study = paper_study_leg(B, W, torch)
         log("bench: perception leg")
         perception = perception_leg(B, W, torch, n)
+        log("bench: controller leg")
+        control = control_leg(B, W, torch, n)
 
     batch = None
     if not args.no_batch:
@@ -574,6 +615,7 @@ def main():
         "n_sweep_fp64_step": nsweep,
         "paper_preset_study": study,
         "perception": perception,
+        "control": control,
         "batch": batch,
         "serving": serving,
         "plain_method_host": {"sampling_s": t_sample, "h2d_s": t_h2d,

@@ -249,8 +249,9 @@ int aeb_sample_params(const aeb_scenario* scn, int64_t first, int64_t count, con
  *     within 1 mm + 1e-5 gap of the obstacle get AEB_BOUNDARY in their status)
  *     or AEB_FP32C_FIXUP (as AEB_FP32C, then the flagged samples are
  *     recomputed in FP64, so every collision flag is exact).  A scenario with
- *     the closed-loop controller takes AEB_FP64 only (one checked lane per
- *     sample; AEB_EINVAL otherwise).
+ *     the closed-loop controller takes AEB_FP64 only (AEB_EINVAL otherwise):
+ *     the block-structured path with blocks that end at every decision, or,
+ *     for the unfused Euler form, one checked lane per sample.
  *   out: device output columns with out->n == n_samples.
  * Asynchronous on `stream`.  May grow the scratch arena on first use. */
 int aeb_rollout(const aeb_scenario* scn, const aeb_params* params, int precision,
@@ -328,8 +329,8 @@ int aeb_autotune(const aeb_scenario* calib, int precision, const char* cache_pat
  * scratch (allocated at creation) and, for batches, pinned copies of the
  * scenario tables.  Only the sorted block-structured path is recorded: FP64
  * explicit Euler (fused form) or RK4, FP32C explicit Euler; AEB_EINVAL for
- * the unfused Euler form (nofma), the closed-loop controller and the FP32C
- * fix-up mode. */
+ * the unfused Euler form (nofma), the FP32C fix-up mode, and the closed-loop
+ * controller in FP32C or in batched graphs. */
 typedef struct aeb_graph aeb_graph;
 
 /* One scenario: params (device columns, or NULL for the in-kernel generator),

@@ -128,7 +128,7 @@ int aeb_graph_create(const aeb_scenario* scn, const aeb_params* params, int prec
   if (rc != AEB_OK) return rc;
   if (!fast_path_applies(*scn, precision))
     return fail(AEB_EINVAL, "graphs record the block-structured path (not the unfused Euler "
-                            "form, not RK4 in FP32C, not the closed-loop controller)");
+                            "form, not RK4 or the closed-loop controller in FP32C)");
   if (out->n != scn->n_samples) return fail(AEB_EINVAL, "outputs length differs from n_samples");
   ParamSrc src{};
   if (params) {
@@ -187,8 +187,9 @@ int aeb_graph_create_batch(const aeb_scenario* scns, int n_scn, int precision,
         scns[j].impact_exit != scns[0].impact_exit || scns[j].nofma != scns[0].nofma)
       return fail(AEB_EINVAL, "batched scenarios must share integrator, obstacle, impact_exit, nofma");
   }
-  if (!fast_path_applies(scns[0], precision))
-    return fail(AEB_EINVAL, "graphs record the block-structured Euler path");
+  if (!fast_path_applies(scns[0], precision) || control_on(scns[0]))
+    return fail(AEB_EINVAL, "batched graphs record the batched block-structured path (not the "
+                            "unfused Euler form, not RK4 in FP32C, not the closed-loop controller)");
   aeb_graph* g = new (std::nothrow) aeb_graph;
   if (!g) return fail(AEB_ENOMEM, "host allocation failed");
   for (int j = 0; j < n_scn; ++j) {

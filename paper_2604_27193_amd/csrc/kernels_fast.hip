@@ -83,6 +83,7 @@ struct PrepArgs {
   const ScnDev* tab;         // batch: per-scenario constants and offsets
   int n_scn;
   int32_t* nds;              // per-sample command step (launches with perception), else null
+  int ctl;                   // closed-loop controller (single scenario)
 };
 
 template <bool DEVRNG, bool BATCH>
@@ -148,10 +149,21 @@ __global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job
     J.dmax = (brake + fabs(k.kd) * vmax * vmax + fabs(k.c)) * 1.0001 + 1e-9;
     // classify and predict
     const bool limited = !(k.alim < s.a_cmd - 1e-6);
+    float td = static_cast<float>(ndl) * static_cast<float>(s.dt);
+    if (a.ctl) {
+      // approach until the full-brake threshold, for the sort only: a
+      // stationary obstacle reached at v0; a lead braking at `lead` from the
+      // ego's speed (closing speed lead t, gap closed by lead t^2 / 2)
+      const float T = static_cast<float>(s.ttc_brake), G = static_cast<float>(gap);
+      const float V = static_cast<float>(v0), A = static_cast<float>(lead);
+      if (s.obstacle == AEB_OBS_LEAD)
+        td += A > 0.0f ? sqrtf(T * T + 2.0f * G / A) - T : static_cast<float>(s.horizon);
+      else
+        td += V > 0.0f ? fmaxf(G / V - T, 0.0f) : 0.0f;
+    }
     const float t = predict_stop_time(static_cast<float>(v0), static_cast<float>(k.kd),
                                       static_cast<float>(k.c), static_cast<float>(k.alim),
-                                      static_cast<float>(tau), static_cast<float>(s.a_cmd),
-                                      static_cast<float>(ndl) * static_cast<float>(s.dt));
+                                      static_cast<float>(tau), static_cast<float>(s.a_cmd), td);
     float steps = t / static_cast<float>(s.dt);
     if (!(steps < static_cast<float>(nmax))) steps = static_cast<float>(nmax);
     if (!(steps > 0.0f)) steps = 0.0f;
@@ -351,6 +363,7 @@ struct Ctx {
   OutCols out;
   const ScnDev* tab;
   const int32_t* nds;  // per-sample command steps (perception), else null
+  CtlArgs ca;          // the closed-loop controller (kernels instantiated for it)
 };
 
 struct LaneScn {
@@ -439,16 +452,40 @@ struct Lane64 {
   St64 s, sv;  // state, and start state of the block where the obstacle was passed
   Ld64 l, lv;  // lead vehicle, and its state at that block start
   int sk;      // step index at that block start
+  int on1, on2, stage;  // controller: first steps of its two commands (INT_MAX: none), stage
   bool active, collided, pend, clamped, free_lane, limited;
 };
 
+// The lane's brake command at step kk (constant inside every block: blocks
+// end at every command switch), and the first step with any command.
+template <bool CTL>
+__device__ inline double lane_cmd(const Lane64& L, const LaneScn& c, double a_warn, int kk) {
+  if (!CTL) return kk >= c.nd ? c.a_cmd : 0.0;
+  return kk >= L.on2 ? c.a_cmd : (kk >= L.on1 ? a_warn : 0.0);
+}
+
+template <bool CTL>
+__device__ inline int first_cmd(const Lane64& L, const LaneScn& c) {
+  return CTL ? min(L.on1, L.on2) : c.nd;
+}
+
+// Controller block limit of a lane: its next command switch, and the last step.
+__device__ inline int ctl_lim(const Lane64& L, int k, int nmax) {
+  // the earlier of the switches still ahead (either may be unset, INT_MAX)
+  int sw = INT_MAX;
+  if (L.on1 > k) sw = L.on1;
+  if (L.on2 > k) sw = min(sw, L.on2);
+  return min(sw, nmax - 1);
+}
+
 // wnd: the smallest nd of the wavefront's lanes (the whole block is dead time
 // for every lane when k + B <= wnd)
-template <int OBS, int B, int INTEG>
+template <int OBS, int B, int INTEG, bool CTL>
 __device__ inline void run_block64(Lane64& L, const Job& J, double al, const LaneScn& c, int k,
-                                   int wnd, int impact_exit) {
+                                   int wnd, int impact_exit, double a_warn) {
   constexpr bool LEAD = OBS == AEB_OBS_LEAD;
-  const double cmd = k >= c.nd ? c.a_cmd : 0.0;
+  const double cmd = lane_cmd<CTL>(L, c, a_warn, k);
+  const int fcmd = first_cmd<CTL>(L, c);
   if (OBS != AEB_OBS_NONE && !L.collided) {
     L.sv = L.s;
     if (LEAD) L.lv = L.l;
@@ -462,7 +499,7 @@ __device__ inline void run_block64(Lane64& L, const Job& J, double al, const Lan
     block64<FORM_F, B, LEAD, INTEG>(L.s, L.l, J, al, c.dt, cmd);
   } else {
     block64<FORM_G, B, LEAD, INTEG>(L.s, L.l, J, al, c.dt, cmd);
-    L.clamped = L.clamped || (L.limited && k + B > c.nd && L.s.a <= J.alim);
+    L.clamped = L.clamped || (L.limited && k + B > fcmd && L.s.a <= J.alim);
   }
   if (OBS == AEB_OBS_STATIONARY && L.active && !L.collided && L.s.x > J.gap) {
     L.collided = true;
@@ -476,7 +513,7 @@ __device__ inline void run_block64(Lane64& L, const Job& J, double al, const Lan
   }
 }
 
-template <int OBS, int K, bool BATCH, int INTEG = AEB_EULER>
+template <int OBS, int K, bool BATCH, int INTEG = AEB_EULER, bool CTL = false>
 __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
                                                    const LeadJob* __restrict__ leads,
                                                    const uint32_t* __restrict__ perm, int64_t n,
@@ -486,6 +523,9 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
   // then single checked steps (a level runs while no lane can stop inside it)
   constexpr int KS = 4;
   constexpr int KM = K >= 64 ? 16 : KS;
+  // with the controller, decisions every few tens of steps leave short
+  // remainders: a 2-step level before the single steps
+  constexpr int K2 = CTL ? 2 : KS;
   constexpr bool LEAD = OBS == AEB_OBS_LEAD;
   for (int pass = 0;; ++pass) {
     const int64_t base = next_chunk(counter, persistent, pass, n);
@@ -502,12 +542,17 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
     const double al = (LEAD && valid) ? leads[g].decel : 0.0;
     const LaneScn c = lane_scn<BATCH>(ctx, J, valid, g);
     const bool varnd = BATCH || ctx.nds;
-    const int wnd = varnd ? wave_min(valid ? c.nd : INT_MAX) : c.nd;
+    // every lane is in its dead time for blocks ending at or before wnd (with
+    // the controller: until its first command, known once decided)
+    int wnd = CTL ? INT_MAX : (varnd ? wave_min(valid ? c.nd : INT_MAX) : c.nd);
     // v above these cannot reach 0 within a block (|dv/dt| <= dmax)
     const double thr_k = static_cast<double>(K) * c.dt * J.dmax;
     const double thr_m = static_cast<double>(KM) * c.dt * J.dmax;
     const double thr_s = static_cast<double>(KS) * c.dt * J.dmax;
+    const double thr_2 = static_cast<double>(K2) * c.dt * J.dmax;
     Lane64 L;
+    L.on1 = L.on2 = INT_MAX;
+    L.stage = 0;
     L.s = St64{0.0, J.v0, 0.0};
     L.l = Ld64{0.0, LEAD ? J.v0 : 0.0, J.gap};
     L.sv = L.s;
@@ -530,30 +575,70 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
     double xmax = 0.0;
     float vimp = 0.0f;
     int k = 0, wl = -1;
+    // controller: the next decision step and the decisions taken (uniform)
+    int ktick = 0;
+    uint32_t tick = 0;
     // every lane has ended by its step nmax (the horizon test fires at k + 1 == nmax)
     for (;;) {
       // the step index is the same in every lane: keep it (and the branches on it) scalar
       k = __builtin_amdgcn_readfirstlane(k);
       if (!__any(L.active)) break;
-      if (!varnd || k >= wl) wl = wave_lim(varnd, L.active, k, c.nd, c.nmax);
+      if (CTL) {
+        if (k == ktick) {
+          // decision on the state after k steps; a raised stage's command
+          // starts nd steps later.  Once every active lane is at the full
+          // stage no decision can change anything: decisions stop, and so do
+          // the block limits at decision steps.
+          if (!__any(L.active && L.stage < 2)) {
+            ktick = INT_MAX;
+          } else {
+            if (L.active && L.stage < 2) {
+              const double gt = LEAD ? (J.gap + L.l.xl) - L.s.x : (J.gap + 0.0) - L.s.x;
+              const double cl = LEAD ? L.s.v - L.l.vl : L.s.v - 0.0;
+              const int want = ctl_want(ctx.ca, g, tick, gt, cl);
+              if (want > L.stage) {
+                if (want == 2)
+                  L.on2 = k + c.nd;
+                else
+                  L.on1 = k + c.nd;
+                L.stage = want;
+              }
+            }
+            ++tick;
+            // past the last step no decision can act
+            const int64_t nk = static_cast<int64_t>(ktick) + ctx.ca.period;
+            ktick = nk < c.nmax ? static_cast<int>(nk) : INT_MAX;
+          }
+          wnd = wave_min(valid ? min(L.on1, L.on2) : INT_MAX);
+          wl = -1;
+        }
+        if (k >= wl) wl = min(ktick, wave_min(L.active ? ctl_lim(L, k, c.nmax) : INT_MAX));
+      } else if (!varnd || k >= wl) {
+        wl = wave_lim(varnd, L.active, k, c.nd, c.nmax);
+      }
       if (k + K <= wl && !__any(L.active && L.s.v <= thr_k)) {
-        run_block64<OBS, K, INTEG>(L, J, al, c, k, wnd, ctx.impact_exit);
+        run_block64<OBS, K, INTEG, CTL>(L, J, al, c, k, wnd, ctx.impact_exit, ctx.ca.a_warn);
         if (INTEG == AEB_RK4 && L.active) xmax = fmax(xmax, L.s.x);
         k += K;
       } else if (KM > KS && k + KM <= wl && !__any(L.active && L.s.v <= thr_m)) {
-        run_block64<OBS, KM, INTEG>(L, J, al, c, k, wnd, ctx.impact_exit);
+        run_block64<OBS, KM, INTEG, CTL>(L, J, al, c, k, wnd, ctx.impact_exit, ctx.ca.a_warn);
         if (INTEG == AEB_RK4 && L.active) xmax = fmax(xmax, L.s.x);
         k += KM;
       } else if (k + KS <= wl && !__any(L.active && L.s.v <= thr_s)) {
-        run_block64<OBS, KS, INTEG>(L, J, al, c, k, wnd, ctx.impact_exit);
+        run_block64<OBS, KS, INTEG, CTL>(L, J, al, c, k, wnd, ctx.impact_exit, ctx.ca.a_warn);
         if (INTEG == AEB_RK4 && L.active) xmax = fmax(xmax, L.s.x);
         k += KS;
+      } else if (K2 < KS && k + K2 <= wl && !__any(L.active && L.s.v <= thr_2)) {
+        run_block64<OBS, K2, INTEG, CTL>(L, J, al, c, k, wnd, ctx.impact_exit, ctx.ca.a_warn);
+        if (INTEG == AEB_RK4 && L.active) xmax = fmax(xmax, L.s.x);
+        k += K2;
       } else {
-        const double cmd = k >= c.nd ? c.a_cmd : 0.0;
+        const double cmd = lane_cmd<CTL>(L, c, ctx.ca.a_warn, k);
         if (L.active) {
           step64<LEAD, INTEG>(L.s, L.l, J, al, c.dt, cmd);
           if (INTEG == AEB_RK4) xmax = fmax(xmax, L.s.x);
-          if (k >= c.nd) L.clamped = L.clamped || (L.limited && L.s.a <= J.alim);
+          if (k >= first_cmd<CTL>(L, c))
+            L.clamped = L.clamped || (L.limited && L.s.a <= J.alim);
           bool impact = false;
           if (LEAD) {
             const double gk = (J.gap + L.l.xl) - L.s.x;
@@ -599,7 +684,7 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
       for (int it = 0; it <= K; ++it) {
         if (!__any(L.pend)) break;
         if (L.pend) {
-          const double cmd = kr >= c.nd ? c.a_cmd : 0.0;
+          const double cmd = lane_cmd<CTL>(L, c, ctx.ca.a_warn, kr);
           step64<LEAD, INTEG>(r, rl, J, al, c.dt, cmd);
           ++kr;
           bool impact;
@@ -1208,7 +1293,8 @@ __global__ __launch_bounds__(256) void k_roll_fp32c_lead(const Job* __restrict__
 }  // namespace
 
 bool fast_path_applies(const aeb_scenario& s, int precision) {
-  if (control_on(s)) return false;  // the controller runs in the checked kernel
+  // the controller: FP64 explicit Euler (fused form) or RK4 only
+  if (control_on(s)) return precision == AEB_FP64 && (s.integrator == AEB_RK4 || !s.nofma);
   if (precision == AEB_FP64)
     return s.integrator == AEB_RK4 ? s.obstacle != AEB_OBS_LEAD : !s.nofma;
   if (s.integrator != AEB_EULER) return false;
@@ -1301,10 +1387,10 @@ void sort_keys(const Bufs& b, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_scatter, dim3(pblk), dim3(PREP_BLOCK), 0, st, b.keys, n, b.hist, b.perm);
 }
 
-template <int OBS, int K, bool BATCH, int INTEG = AEB_EULER>
+template <int OBS, int K, bool BATCH, int INTEG = AEB_EULER, bool CTL = false>
 void go64(const Shape& sh, const Bufs& b, int64_t n, const Ctx& ctx, hipStream_t st) {
-  hipLaunchKernelGGL((k_roll_fp64<OBS, K, BATCH, INTEG>), dim3(sh.grid), dim3(sh.block), 0, st,
-                     b.jobs, b.leads, b.perm, n, ctx, b.counter, sh.persistent);
+  hipLaunchKernelGGL((k_roll_fp64<OBS, K, BATCH, INTEG, CTL>), dim3(sh.grid), dim3(sh.block), 0,
+                     st, b.jobs, b.leads, b.perm, n, ctx, b.counter, sh.persistent);
 }
 
 template <int OBS, bool BATCH>
@@ -1339,6 +1425,20 @@ int integrate(const aeb_scenario& s0, int precision, const Bufs& b, int64_t n, c
   const int obs = s0.obstacle;
   const TuneCfg t = tune_get(precision == AEB_FP64 ? AEB_FP64 : AEB_FP32C, obs);
   const Shape sh = shape(t, n);
+  if (!BATCH && control_on(s0)) {
+    // the controller decides every ctl_period: blocks stay within a decision
+    // period, so the 64-step level rarely runs; FP64 only
+    timing_begin(st);
+    if (s0.integrator == AEB_RK4)
+      go64<AEB_OBS_STATIONARY, 16, false, AEB_RK4, true>(sh, b, n, ctx, st);
+    else if (obs == AEB_OBS_LEAD)
+      go64<AEB_OBS_LEAD, 64, false, AEB_EULER, true>(sh, b, n, ctx, st);
+    else
+      go64<AEB_OBS_STATIONARY, 64, false, AEB_EULER, true>(sh, b, n, ctx, st);
+    timing_end(st);
+    AEB_HIP(hipGetLastError());
+    return AEB_OK;
+  }
   if (precision == AEB_FP64 && s0.integrator == AEB_RK4) {
     // an RK4 step costs about eight Euler steps: short blocks keep the tail small
     timing_begin(st);
@@ -1419,6 +1519,7 @@ int launch_rollout_fast_into(const aeb_scenario& s, const ParamSrc* src, int pre
   pa.nmax = static_cast<int>(nmax);
   pa.cap = static_cast<float>(nmax);
   pa.nds = perception_on(s) ? b.nds : nullptr;
+  pa.ctl = control_on(s) ? 1 : 0;
   if (src)
     hipLaunchKernelGGL((k_prep<false, false>), dim3(pblk), dim3(PREP_BLOCK), 0, st, pa, b.jobs,
                        b.leads, b.keys, b.hist);
@@ -1435,6 +1536,7 @@ int launch_rollout_fast_into(const aeb_scenario& s, const ParamSrc* src, int pre
   ctx.out = out;
   ctx.tab = nullptr;
   ctx.nds = pa.nds;
+  ctx.ca = ctl_args(s);
   return integrate<false>(s, precision, b, n, ctx, src, st);
 }
 

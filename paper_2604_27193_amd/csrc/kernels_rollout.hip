@@ -69,19 +69,6 @@ __global__ __launch_bounds__(256) void k_rollout_fp64(aeb_scenario s, ParamSrc s
   store(out, i, r);
 }
 
-static CtlArgs ctl_args(const aeb_scenario& s) {
-  CtlArgs a{};
-  if (control_on(s)) a.period = std::llround(s.ctl_period / s.dt);
-  a.ttc_warn = s.ttc_warn;
-  a.ttc_brake = s.ttc_brake;
-  a.a_warn = s.a_warn;
-  a.noise_gap = s.noise_gap;
-  a.noise_v = s.noise_v;
-  a.seed = s.seed;
-  a.sid = s.scenario_id;
-  return a;
-}
-
 // FP64 recomputation of the samples listed in fix[1 .. fix[0]]; clears the
 // boundary bit
 template <int OBS, bool DEVRNG>
@@ -114,7 +101,8 @@ static void go_fp64(const aeb_scenario& s, const ParamSrc* src, const OutCols& o
                        out, n, nd, nmax, ca);
 }
 
-// the closed-loop controller: FP64, one checked lane per sample
+// the closed-loop controller outside the block path (the unfused Euler form):
+// FP64, one checked lane per sample
 static int go_control(const aeb_scenario& s, const ParamSrc* src, int precision,
                       const OutCols& out, int64_t n, int64_t nd, int64_t nmax, hipStream_t st) {
   if (precision != AEB_FP64)
@@ -157,11 +145,12 @@ int launch_fixup(const aeb_scenario& s, const ParamSrc* src, const OutCols& out,
   return AEB_OK;
 }
 
-// Batches the block-structured path cannot take (RK4, the unfused Euler form)
-// run scenario by scenario.
+// Batches the batched block-structured launch cannot take (the unfused Euler
+// form, the closed-loop controller, the fix-up mode) run scenario by scenario.
 int launch_batch(const aeb_scenario* scns, int n_scn, int precision, const OutCols* outs,
                  hipStream_t st) {
-  if (fast_path_applies(scns[0], precision) && precision != AEB_FP32C_FIXUP)
+  if (fast_path_applies(scns[0], precision) && precision != AEB_FP32C_FIXUP &&
+      !control_on(scns[0]))
     return launch_batch_fast(scns, n_scn, precision, outs, st);
   for (int j = 0; j < n_scn; ++j) {
     const int rc = launch_rollout(scns[j], nullptr, precision, outs[j], scns[j].n_samples, st);
@@ -173,8 +162,8 @@ int launch_batch(const aeb_scenario* scns, int n_scn, int precision, const OutCo
 int launch_rollout(const aeb_scenario& s, const ParamSrc* src, int precision, const OutCols& out,
                    int64_t n, hipStream_t st) {
   const int64_t nd = dead_steps(s), nmax = horizon_steps(s);
-  if (control_on(s)) return go_control(s, src, precision, out, n, nd, nmax, st);
   if (fast_path_applies(s, precision)) return launch_rollout_fast(s, src, precision, out, n, st);
+  if (control_on(s)) return go_control(s, src, precision, out, n, nd, nmax, st);
   if (precision == AEB_FP32C || precision == AEB_FP32C_FIXUP) {
     // every Euler case takes the block-structured path
     return fail(AEB_EINVAL, "the FP32 compensated form is available for the Euler integrator");

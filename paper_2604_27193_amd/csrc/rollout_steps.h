@@ -47,6 +47,19 @@ struct CtlArgs {
   uint64_t seed, sid;
 };
 
+inline CtlArgs ctl_args(const aeb_scenario& s) {
+  CtlArgs a{};
+  if (control_on(s)) a.period = std::llround(s.ctl_period / s.dt);
+  a.ttc_warn = s.ttc_warn;
+  a.ttc_brake = s.ttc_brake;
+  a.a_warn = s.a_warn;
+  a.noise_gap = s.noise_gap;
+  a.noise_v = s.noise_v;
+  a.seed = s.seed;
+  a.sid = s.scenario_id;
+  return a;
+}
+
 struct Ctl {
   int64_t next_tick, on1, on2;  // next decision step; first steps of the two commands
   uint32_t tick;                // decisions taken
@@ -62,15 +75,21 @@ __device__ inline Ctl ctl_start() {
   return c;
 }
 
-__device__ inline void ctl_decide(const CtlArgs& A, Ctl& c, uint64_t index, int64_t step,
-                                  int64_t nd, double gap_true, double closing) {
-  const U2 u = uniform2(A.seed, A.sid, index, AEB_SLOT_CONTROL, c.tick);
+// the stage decision `tick` asks for, from the true gap and closing speed
+__device__ inline int ctl_want(const CtlArgs& A, uint64_t index, uint32_t tick, double gap_true,
+                               double closing) {
+  const U2 u = uniform2(A.seed, A.sid, index, AEB_SLOT_CONTROL, tick);
   const double r = sqrt(-2.0 * log(u.a));
   const double ang = 6.283185307179586 * u.b;
   const double g = gap_true + A.noise_gap * (r * cos(ang));
   const double cl = closing + A.noise_v * (r * sin(ang));
   const double ttc = cl > 0.0 ? g / cl : INFINITY;
-  const int want = ttc < A.ttc_brake ? 2 : (ttc < A.ttc_warn ? 1 : 0);
+  return ttc < A.ttc_brake ? 2 : (ttc < A.ttc_warn ? 1 : 0);
+}
+
+__device__ inline void ctl_decide(const CtlArgs& A, Ctl& c, uint64_t index, int64_t step,
+                                  int64_t nd, double gap_true, double closing) {
+  const int want = ctl_want(A, index, c.tick, gap_true, closing);
   if (want > c.stage) {
     if (want == 2)
       c.on2 = step + nd;

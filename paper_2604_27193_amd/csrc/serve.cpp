@@ -119,7 +119,7 @@ class HipExecutor final : public serve::Executor {
   int check(const aeb_scenario& s) const override {
     const int rc = validate(s);
     if (rc != AEB_OK) return rc;
-    if (!fast_path_applies(s, cfg_.precision))
+    if (!fast_path_applies(s, cfg_.precision) || control_on(s))
       return fail(AEB_EINVAL,
                   "serving runs the batched block-structured path (not the unfused Euler "
                   "form, not RK4 in FP32C, not the closed-loop controller)");

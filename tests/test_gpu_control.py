@@ -1,8 +1,9 @@
 """GPU parity of the closed-loop controller (TTC thresholds on noisy gap and
 closing-speed measurements, latched partial and full braking; the controller
 assessment named in Sec. VIII) against the FP64 reference.  The controller
-runs in the checked FP64 kernel: host-drawn inputs give the reference's bits,
-in-kernel draws agree to 1e-12."""
+runs in the block-structured FP64 kernel (blocks end at every decision and
+command switch; the unfused Euler form in the checked kernel): host-drawn
+inputs give the reference's bits, in-kernel draws agree to 1e-12."""
 import math
 
 import numpy as np
@@ -33,6 +34,9 @@ def variants():
         "impact_exit": W.closed_loop(3000, impact_exit=True),
         "noise_free": W.closed_loop(3000, noise_gap=0.0, noise_v=0.0),
         "one_stage": W.closed_loop(3000, ttc_warn=0.0),
+        # a command switch between decision steps, with no warning stage set
+        "dead_30ms_one_stage": W.closed_loop(3000, ttc_warn=0.0, dead_time=0.03),
+        "dead_30ms": W.closed_loop(3000, dead_time=0.03),
         "period_1ms": W.closed_loop(1500, ctl_period=0.001),
         "rk4": W.closed_loop(1500, integrator="rk4"),
         "nofma": W.closed_loop(2000, nofma=True),
@@ -107,5 +111,35 @@ def test_refusals(B):
             B.rollout(d, precision=prec)
         assert e.value.code == B.EINVAL
     with pytest.raises(B.AebError) as e:
-        B.Graph(d)
+        B.Graph([d, d], batch=True)
     assert e.value.code == B.EINVAL
+
+
+def test_graph_replays_equal_eager(B):
+    d = W.closed_loop(20000, seed=8)
+    ref = to_np(B.rollout(d))
+    g = B.Graph(d)
+    for _ in range(3):
+        g.out["dist"].fill_(-1.0)
+        g.launch()
+        g.finish()
+        got = to_np(g.out)
+        for k in ref:
+            assert np.array_equal(ref[k], got[k]), k
+    g.close()
+
+
+def test_launch_shapes_give_same_bits(B):
+    """Workgroup size and persistent grids of the tuning table do not change
+    a controller run's results."""
+    d = W.closed_loop(30000, seed=9)
+    keep = B.tune_get("fp64", "stationary")
+    try:
+        ref = to_np(B.rollout(d))
+        for k, blk, w in ((16, 64, 0), (64, 256, 0), (128, 128, 8)):
+            B.tune_set("fp64", "stationary", k, blk, w)
+            got = to_np(B.rollout(d))
+            for c in ref:
+                assert np.array_equal(ref[c], got[c]), (k, blk, w, c)
+    finally:
+        B.tune_set("fp64", "stationary", *keep)
