@@ -236,24 +236,39 @@ static long long command_step(const orc_scenario* s, const orc_sample* p) {
   return llround(q);
 }
 
-void orc_sample_one(const orc_scenario* s, uint64_t i, orc_sample* p) {
-  const uint64_t seed = s->seed, sid = s->scenario_id;
-  p->v0 = orc_draw(&s->v0, seed, sid, i, ORC_SLOT_V0);
-  p->mu = orc_draw(&s->mu, seed, sid, i, ORC_SLOT_MU);
-  p->mass = orc_draw(&s->mass, seed, sid, i, ORC_SLOT_MASS);
-  p->grade = orc_draw(&s->grade, seed, sid, i, ORC_SLOT_GRADE);
-  p->sin_grade = sin(p->grade);
-  p->cos_grade = cos(p->grade);
-  p->cda = orc_draw(&s->cda, seed, sid, i, ORC_SLOT_CDA);
-  p->crr = orc_draw(&s->crr, seed, sid, i, ORC_SLOT_CRR);
-  p->tau = orc_draw(&s->tau, seed, sid, i, ORC_SLOT_TAU);
-  p->gap = orc_draw(&s->gap, seed, sid, i, ORC_SLOT_GAP);
-  p->lead_decel = orc_draw(&s->lead_decel, seed, sid, i, ORC_SLOT_LEAD);
-  p->trigger = perception_on(s) ? orc_trigger_delay(s, i) : 0.0;
-  p->index = i;
+/* Parameter `slot`: drawn from its proposal when importance sampling covers
+ * it (then its log likelihood ratio log p(x) - log q(x) is added to *log_w),
+ * else from its own distribution. */
+static double draw_param(const orc_scenario* s, const orc_dist* d, uint64_t i, uint32_t slot,
+                         double* log_w) {
+  if (!((s->is_mask >> slot) & 1)) return orc_draw(d, s->seed, s->scenario_id, i, slot);
+  const orc_dist* q = &s->proposal[slot];
+  const double x = orc_draw(q, s->seed, s->scenario_id, i, slot);
+  const double zp = (x - d->p0) / d->p1;
+  const double zq = (x - q->p0) / q->p1;
+  *log_w += log(q->p1 / d->p1) + (0.5 * (zq * zq) - 0.5 * (zp * zp));
+  return x;
 }
 
-int orc_sample_range(const orc_scenario* s, int64_t first, int64_t count, double* const cols[12]) {
+void orc_sample_one(const orc_scenario* s, uint64_t i, orc_sample* p) {
+  double lw = 0.0;
+  p->v0 = draw_param(s, &s->v0, i, ORC_SLOT_V0, &lw);
+  p->mu = draw_param(s, &s->mu, i, ORC_SLOT_MU, &lw);
+  p->mass = draw_param(s, &s->mass, i, ORC_SLOT_MASS, &lw);
+  p->grade = draw_param(s, &s->grade, i, ORC_SLOT_GRADE, &lw);
+  p->sin_grade = sin(p->grade);
+  p->cos_grade = cos(p->grade);
+  p->cda = draw_param(s, &s->cda, i, ORC_SLOT_CDA, &lw);
+  p->crr = draw_param(s, &s->crr, i, ORC_SLOT_CRR, &lw);
+  p->tau = draw_param(s, &s->tau, i, ORC_SLOT_TAU, &lw);
+  p->gap = draw_param(s, &s->gap, i, ORC_SLOT_GAP, &lw);
+  p->lead_decel = draw_param(s, &s->lead_decel, i, ORC_SLOT_LEAD, &lw);
+  p->trigger = perception_on(s) ? orc_trigger_delay(s, i) : 0.0;
+  p->index = i;
+  p->log_w = lw;
+}
+
+int orc_sample_range(const orc_scenario* s, int64_t first, int64_t count, double* const cols[13]) {
   if (first < 0 || count < 0) return ORC_EINVAL;
   for (int64_t k = 0; k < count; ++k) {
     orc_sample p;
@@ -270,6 +285,7 @@ int orc_sample_range(const orc_scenario* s, int64_t first, int64_t count, double
     cols[9][k] = p.gap;
     cols[10][k] = p.lead_decel;
     cols[11][k] = p.trigger;
+    cols[12][k] = p.log_w;
   }
   return ORC_OK;
 }
@@ -347,6 +363,19 @@ int orc_validate(const orc_scenario* s) {
     if (!isfinite(s->a_warn) || !(s->a_cmd <= s->a_warn && s->a_warn <= 0.0)) return ORC_EINVAL;
     if (!(s->noise_gap >= 0.0) || !isfinite(s->noise_gap)) return ORC_EINVAL;
     if (!(s->noise_v >= 0.0) || !isfinite(s->noise_v)) return ORC_EINVAL;
+  }
+  /* importance sampling: normal parameters with normal proposals (not tau,
+   * which must stay positive), sds > 0 */
+  if (s->is_mask & ~0x1BF) return ORC_EINVAL;
+  {
+    const orc_dist* nom[9] = {&s->v0, &s->mu, &s->mass, &s->grade, &s->cda,
+                              &s->crr, &s->tau, &s->gap, &s->lead_decel};
+    for (int j = 0; j < 9; ++j) {
+      if (!((s->is_mask >> j) & 1)) continue;
+      const orc_dist* q = &s->proposal[j];
+      if (nom[j]->kind != ORC_D_NORMAL || q->kind != ORC_D_NORMAL) return ORC_EINVAL;
+      if (!(nom[j]->p1 > 0.0) || !(q->p1 > 0.0) || !dist_ok(q)) return ORC_EINVAL;
+    }
   }
   /* the explicit actuator update needs dt/tau <= 1 for every sample */
   if (!(dist_min(&s->tau) > 0.0)) return ORC_EINVAL;
@@ -595,7 +624,7 @@ int orc_run_range(const orc_scenario* s, int64_t first, int64_t count, double* d
   return ORC_OK;
 }
 
-int orc_rollout_given(const orc_scenario* s, const double* const cols[12], int64_t n,
+int orc_rollout_given(const orc_scenario* s, const double* const cols[13], int64_t n,
                       int clamp_state, double* dist, uint8_t* status, int32_t* steps,
                       double* margin, float* v_impact) {
   if (n < 0) return ORC_EINVAL;
@@ -615,6 +644,7 @@ int orc_rollout_given(const orc_scenario* s, const double* const cols[12], int64
     p.lead_decel = cols[10][k];
     p.trigger = cols[11][k];
     p.index = (uint64_t)k;
+    p.log_w = cols[12][k];
     orc_rollout_one(s, &p, clamp_state, &r);
     dist[k] = r.dist;
     status[k] = r.status;
@@ -634,6 +664,35 @@ int orc_rollout_given(const orc_scenario* s, const double* const cols[12], int64
 static int cmp_double(const void* pa, const void* pb) {
   double a = *(const double*)pa, b = *(const double*)pb;
   return (a > b) - (a < b);
+}
+
+int orc_weighted_risk(const double* dist, const uint8_t* status, const double* weight, int64_t n,
+                      double grid_lo, double grid_hi, int32_t n_grid, double* p, double* se,
+                      double* p_collision, double* p_collision_se) {
+  if (n < 2 || n_grid < 0 || n_grid == 1 || n_grid > ORC_MAX_GRID) return ORC_EINVAL;
+  const double nd = (double)n;
+  for (int32_t j = 0; j < n_grid; ++j) {
+    const double h = grid_lo + (double)j * ((grid_hi - grid_lo) / (double)(n_grid - 1));
+    double s1 = 0.0, s2 = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      const double d = (status[i] & 3) == ORC_END_STOP ? dist[i] : INFINITY;
+      if (d > h) {
+        s1 += weight[i];
+        s2 += weight[i] * weight[i];
+      }
+    }
+    p[j] = s1 / nd;
+    se[j] = sqrt(fmax(s2 / nd - p[j] * p[j], 0.0) / (nd - 1.0));
+  }
+  double c1 = 0.0, c2 = 0.0;
+  for (int64_t i = 0; i < n; ++i)
+    if (status[i] & ORC_COLLIDED) {
+      c1 += weight[i];
+      c2 += weight[i] * weight[i];
+    }
+  *p_collision = c1 / nd;
+  *p_collision_se = sqrt(fmax(c2 / nd - (*p_collision) * (*p_collision), 0.0) / (nd - 1.0));
+  return ORC_OK;
 }
 
 int orc_reduce(const double* dist, const uint8_t* status, const double* margin,

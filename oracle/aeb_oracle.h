@@ -77,6 +77,15 @@ typedef struct {
    * -> stage 2 (command a_cmd); a new stage's command starts dead_time
    * later.  ctl_period = 0: the open-loop command of dead_time. */
   double ctl_period, ttc_warn, ttc_brake, a_warn, noise_gap, noise_v;
+  /* Importance sampling (rare-event estimation, Section VIII): parameter j
+   * (slot order v0 .. lead_decel) with bit j of is_mask set is drawn from
+   * proposal[j] instead of its distribution; both must be NORMAL.  The
+   * sample's likelihood ratio p(xi) / q(xi) is the product over those
+   * parameters of (sd_q / sd_p) exp(z_q^2 / 2 - z_p^2 / 2), z the
+   * standardised value under each. */
+  int32_t is_mask;
+  int32_t pad3;
+  orc_dist proposal[9];
 } orc_scenario;
 
 /* One sample's realised parameter vector (xi^(i) of Section IV-A). */
@@ -84,6 +93,7 @@ typedef struct {
   double v0, mu, mass, grade, sin_grade, cos_grade, cda, crr, tau, gap, lead_decel;
   double trigger;  /* perception trigger delay (s); +inf: the object is never confirmed */
   uint64_t index;  /* the sample's index (keys the controller's measurement noise) */
+  double log_w;    /* log likelihood ratio of importance sampling (0 without) */
 } orc_sample;
 
 typedef struct {
@@ -137,8 +147,9 @@ void orc_sample_one(const orc_scenario* s, uint64_t i, orc_sample* out);
 double orc_trigger_delay(const orc_scenario* s, uint64_t i);
 
 /* SoA parameter columns, in this order: v0 mu mass grade sin_grade cos_grade
- * cda crr tau gap lead_decel trigger.  cols[c] points at `count` doubles. */
-int orc_sample_range(const orc_scenario* s, int64_t first, int64_t count, double* const cols[12]);
+ * cda crr tau gap lead_decel trigger log_weight.  cols[c] points at `count`
+ * doubles. */
+int orc_sample_range(const orc_scenario* s, int64_t first, int64_t count, double* const cols[13]);
 
 void orc_rollout_one(const orc_scenario* s, const orc_sample* p, int clamp_state, orc_result* r);
 
@@ -147,9 +158,18 @@ int orc_run_range(const orc_scenario* s, int64_t first, int64_t count, double* d
                   uint8_t* status, int32_t* steps, double* margin, float* v_impact);
 
 /* Roll out caller-given parameter columns (same order as orc_sample_range). */
-int orc_rollout_given(const orc_scenario* s, const double* const cols[12], int64_t n,
+int orc_rollout_given(const orc_scenario* s, const double* const cols[13], int64_t n,
                       int clamp_state, double* dist, uint8_t* status, int32_t* steps,
                       double* margin, float* v_impact);
+
+/* Importance-sampling estimates over the samples' weights w (likelihood
+ * ratios): for each headway H0_j of the grid, P(D > H0_j) = sum w 1[D > H0_j]
+ * / n with D censored to +inf unless the sample stopped, and its standard
+ * error sqrt((sum w^2 1[.] / n - P^2) / (n - 1)); the same for the collision
+ * flag.  Plain sums in index order. */
+int orc_weighted_risk(const double* dist, const uint8_t* status, const double* weight, int64_t n,
+                      double grid_lo, double grid_hi, int32_t n_grid, double* p, double* se,
+                      double* p_collision, double* p_collision_se);
 
 int orc_reduce(const double* dist, const uint8_t* status, const double* margin,
                const float* v_impact, int64_t n, const orc_reduce_req* req, orc_stats* out);

@@ -15,7 +15,7 @@ import numpy as np
 from . import build as _build
 
 COLUMNS = ("v0", "mu", "mass", "grade", "sin_grade", "cos_grade", "cda", "crr", "tau",
-           "gap", "lead_decel", "trigger")
+           "gap", "lead_decel", "trigger", "log_weight")
 DISTS = ("v0", "mu", "mass", "grade", "cda", "crr", "tau", "gap", "lead_decel")
 SLOTS = {name: k for k, name in enumerate(DISTS)}
 SLOTS.update({"latency": 9, "occlusion": 10, "detect": 11, "control": 12})
@@ -46,7 +46,8 @@ class Scenario(C.Structure):
                 + [(f, Dist) for f in DISTS]
                 + [("latency", Dist), ("occlusion", Dist), ("frame_period", C.c_double),
                    ("p_dropout", C.c_double), ("confirm", C.c_int32), ("pad2", C.c_int32)]
-                + [(f, C.c_double) for f in CONTROL_FIELDS])
+                + [(f, C.c_double) for f in CONTROL_FIELDS]
+                + [("is_mask", C.c_int32), ("pad3", C.c_int32), ("proposal", Dist * 9)])
 
 
 class ReduceReq(C.Structure):
@@ -86,6 +87,9 @@ def lib():
         L.orc_rollout_given.argtypes = [P(Scenario), P(P(C.c_double)), C.c_int64, C.c_int,
                                         P(C.c_double), P(C.c_uint8), P(C.c_int32),
                                         P(C.c_double), P(C.c_float)]
+        L.orc_weighted_risk.argtypes = [P(C.c_double), P(C.c_uint8), P(C.c_double), C.c_int64,
+                                         C.c_double, C.c_double, C.c_int32, P(C.c_double),
+                                         P(C.c_double), P(C.c_double), P(C.c_double)]
         L.orc_reduce.argtypes = [P(C.c_double), P(C.c_uint8), P(C.c_double), P(C.c_float),
                                  C.c_int64, P(ReduceReq), P(Stats)]
         _lib = L
@@ -126,6 +130,13 @@ def scenario(d):
     s.confirm = int(per["confirm"])
     for f in CONTROL_FIELDS:
         setattr(s, f, float(d.get(f, 0.0)))
+    # importance sampling: {"param": distribution} drawn instead of the nominal
+    mask = 0
+    for name, spec in d.get("proposal", {}).items():
+        j = SLOTS[name]
+        mask |= 1 << j
+        s.proposal[j] = _dist(spec)
+    s.is_mask = mask
     return s
 
 
@@ -159,7 +170,7 @@ def sample(d, first=0, count=None):
     if count is None:
         count = int(d["n_samples"]) - first
     cols = [np.empty(count, dtype=np.float64) for _ in COLUMNS]
-    arr = (C.POINTER(C.c_double) * 12)(*[_dptr(c) for c in cols])
+    arr = (C.POINTER(C.c_double) * 13)(*[_dptr(c) for c in cols])
     rc = lib().orc_sample_range(C.byref(scenario(d)), first, count, arr)
     if rc != OK:
         raise ValueError("orc_sample_range rejected its arguments")
@@ -211,13 +222,32 @@ def rollout_given(d, cols, clamp_state=False):
     n = len(cols["v0"])
     arrs = [np.ascontiguousarray(cols[c] if c in cols else np.zeros(n), dtype=np.float64)
             for c in COLUMNS]
-    arr = (C.POINTER(C.c_double) * 12)(*[_dptr(a) for a in arrs])
+    arr = (C.POINTER(C.c_double) * 13)(*[_dptr(a) for a in arrs])
     o = _alloc_out(n)
     rc = lib().orc_rollout_given(C.byref(scenario(d)), arr, n, int(bool(clamp_state)),
                                  *_out_ptrs(o, 0, n))
     if rc != OK:
         raise ValueError("orc_rollout_given failed")
     return o
+
+
+def weighted_risk(out, weight, grid):
+    """Importance-sampling estimates: P(D > H0_j) and its standard error on the
+    grid (lo, hi, n), and P(collision) with its standard error."""
+    n = len(out["dist"])
+    lo, hi, ng = float(grid[0]), float(grid[1]), int(grid[2])
+    p = np.empty(ng, np.float64)
+    se = np.empty(ng, np.float64)
+    pc, pcs = C.c_double(), C.c_double()
+    dist = np.ascontiguousarray(out["dist"], np.float64)
+    status = np.ascontiguousarray(out["status"], np.uint8)
+    w = np.ascontiguousarray(weight, np.float64)
+    rc = lib().orc_weighted_risk(_dptr(dist), status.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                 _dptr(w), n, lo, hi, ng, _dptr(p), _dptr(se), C.byref(pc),
+                                 C.byref(pcs))
+    if rc != OK:
+        raise ValueError("orc_weighted_risk rejected its arguments")
+    return {"p": p, "se": se, "p_collision": pc.value, "p_collision_se": pcs.value}
 
 
 def reduce(out, risk=(), margin_q=(), grid=None):

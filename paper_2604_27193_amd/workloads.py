@@ -25,6 +25,8 @@ Workloads:
     sensing: occlusion, per-frame dropout, a confirmation run and latency.
   * ``closed_loop`` -- ``single`` with the obstacle farther ahead and a
     two-stage TTC-threshold controller on noisy measurements.
+  * ``rare_event`` -- ``paper_preset`` with importance-sampling proposals for
+    v0 and mu shifted toward long stopping distances.
 """
 import numpy as np
 
@@ -173,5 +175,16 @@ def closed_loop(n=10_000, seed=42, scenario_id=0, **over):
     d.update({"gap": ("normal", 120.0, 10.0), "horizon": 15.0, "ctl_period": 0.05,
               "ttc_warn": 3.0, "ttc_brake": 2.0, "a_warn": -3.0, "noise_gap": 0.5,
               "noise_v": 0.3})
+    d.update(over)
+    return d
+
+
+def rare_event(n=100_000, seed=2026, scenario_id=0, v0_shift=6.0, mu_shift=-0.25, **over):
+    """The paper preset with importance sampling toward long stops: v0 drawn
+    from N(30 + v0_shift, 2) and mu from N(0.8 + mu_shift, 0.1) (the nominal
+    distributions of Sec. IV-B otherwise), each sample weighted by its
+    likelihood ratio, for collision-risk levels far below 1/N."""
+    d = paper_preset(n, seed, scenario_id)
+    d["proposal"] = {"v0": ("normal", 30.0 + v0_shift, 2.0), "mu": ("normal", 0.8 + mu_shift, 0.1)}
     d.update(over)
     return d
