@@ -119,7 +119,14 @@ typedef struct {
  *     the controller's stage only rises: TTC < ttc_warn -> 1 (command a_warn,
  *     a_cmd <= a_warn <= 0), TTC < ttc_brake -> 2 (command a_cmd).  The
  *     command of a stage raised at decision step k applies from step
- *     k + llround(dead_time/dt). */
+ *     k + llround(dead_time/dt).
+ *   Importance sampling (rare-event estimation, Sec. VIII): parameter j in
+ *   slot order (v0, mu, mass, grade, cda, crr, tau, gap, lead_decel) with bit
+ *   j of is_mask set is drawn from proposal[j] instead of its distribution
+ *   (both NORMAL with sd > 0; not tau).  The sample's log likelihood ratio
+ *   log p(xi) - log q(xi) is the sum over those parameters of
+ *   log(sd_q / sd_p) + (z_q^2 / 2 - z_p^2 / 2), z the standardised value
+ *   under each; its exponential is the sample's weight. */
 typedef struct {
   uint64_t seed;
   uint64_t scenario_id;
@@ -135,15 +142,21 @@ typedef struct {
   int32_t confirm;
   int32_t reserved2;
   double ctl_period, ttc_warn, ttc_brake, a_warn, noise_gap, noise_v;
+  int32_t is_mask;
+  int32_t reserved3;
+  aeb_dist proposal[9];
 } aeb_scenario;
 
 /* Structure-of-arrays parameter columns, each `n` doubles (host or device,
  * as the called function states).  sin_grade/cos_grade hold sin/cos of grade;
  * trigger the perception delay in seconds (+inf: never confirmed).  A NULL
- * trigger column reads as zeros; a scenario with perception needs it. */
+ * trigger column reads as zeros; a scenario with perception needs it.
+ * log_weight: the importance-sampling log likelihood ratio; NULL reads as
+ * zeros; a scenario with importance sampling needs it. */
 typedef struct {
   double *v0, *mu, *mass, *grade, *sin_grade, *cos_grade, *cda, *crr, *tau, *gap, *lead_decel;
   double* trigger;
+  double* log_weight;
   int64_t n;
 } aeb_params;
 
@@ -151,13 +164,17 @@ typedef struct {
  *   dist: position x at exit (the stopping distance D_stop when status is STOP);
  *   status: AEB_END_* | AEB_COLLIDED;  steps: integration steps taken;
  *   margin: min over steps of (gap + x_lead) - x;
- *   v_impact: ego minus lead speed at the first step with x > gap + x_lead, else 0. */
+ *   v_impact: ego minus lead speed at the first step with x > gap + x_lead, else 0;
+ *   weight: optional (NULL: not written); the sample's importance-sampling
+ *     weight exp(log likelihood ratio), 1 without importance sampling.  A
+ *     reduction over outputs with weights adds the weighted estimates. */
 typedef struct {
   double* dist;
   uint8_t* status;
   int32_t* steps;
   double* margin;
   float* v_impact;
+  double* weight;
   int64_t n;
 } aeb_outputs;
 
@@ -193,6 +210,18 @@ typedef struct {
   int32_t reserved;
   int64_t risk_count[AEB_MAX_GRID];
   double risk_p[AEB_MAX_GRID];
+  /* with weights (importance sampling): weighted = 1 and, with w the
+   * weights, P(collision) = sum w [collided] / N and on the grid
+   * P(D > H0_j) = sum w [D > H0_j] / N, each with its standard error
+   * sqrt((sum w^2 [.] / N - P^2) / (N - 1)); the sums are exact (128-bit
+   * fixed point scaled to the largest weight), so repeated calls give the
+   * same bits.  weighted = 0 without weights; -1 if a weight was not finite
+   * and >= 0 (the weighted fields are then NaN). */
+  int32_t weighted;
+  int32_t reserved2;
+  double p_collision_w, p_collision_se, weight_mean;
+  double risk_pw[AEB_MAX_GRID];
+  double risk_se[AEB_MAX_GRID];
 } aeb_stats;
 
 /* Message of the last failure on this thread ("" if none). */

@@ -14,10 +14,10 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libaeb.so")
-ABI_VERSION = 4     # the aeb_version() these structures match
+ABI_VERSION = 5     # the aeb_version() these structures match
 
 COLUMNS = ("v0", "mu", "mass", "grade", "sin_grade", "cos_grade", "cda", "crr", "tau", "gap",
-           "lead_decel", "trigger")
+           "lead_decel", "trigger", "log_weight")
 DISTS = ("v0", "mu", "mass", "grade", "cda", "crr", "tau", "gap", "lead_decel")
 # perception fields and their values when a scenario dict leaves them out
 PERCEPTION_DEFAULTS = {"latency": ("const", 0.0), "occlusion": ("const", 0.0),
@@ -61,7 +61,8 @@ class Scenario(C.Structure):
                 + [(f, Dist) for f in DISTS]
                 + [("latency", Dist), ("occlusion", Dist), ("frame_period", C.c_double),
                    ("p_dropout", C.c_double), ("confirm", C.c_int32), ("reserved2", C.c_int32)]
-                + [(f, C.c_double) for f in CONTROL_FIELDS])
+                + [(f, C.c_double) for f in CONTROL_FIELDS]
+                + [("is_mask", C.c_int32), ("reserved3", C.c_int32), ("proposal", Dist * 9)])
 
 
 class Params(C.Structure):
@@ -70,7 +71,8 @@ class Params(C.Structure):
 
 class Outputs(C.Structure):
     _fields_ = [("dist", C.c_void_p), ("status", C.c_void_p), ("steps", C.c_void_p),
-                ("margin", C.c_void_p), ("v_impact", C.c_void_p), ("n", C.c_int64)]
+                ("margin", C.c_void_p), ("v_impact", C.c_void_p), ("weight", C.c_void_p),
+                ("n", C.c_int64)]
 
 
 class ReduceReq(C.Structure):
@@ -87,7 +89,10 @@ class Stats(C.Structure):
                 ("headway", C.c_double * 16), ("margin_min", C.c_double),
                 ("margin_mean", C.c_double), ("margin_q", C.c_double * 4),
                 ("v_impact_max", C.c_float), ("reserved", C.c_int32),
-                ("risk_count", C.c_int64 * 1024), ("risk_p", C.c_double * 1024)]
+                ("risk_count", C.c_int64 * 1024), ("risk_p", C.c_double * 1024),
+                ("weighted", C.c_int32), ("reserved2", C.c_int32), ("p_collision_w", C.c_double),
+                ("p_collision_se", C.c_double), ("weight_mean", C.c_double),
+                ("risk_pw", C.c_double * 1024), ("risk_se", C.c_double * 1024)]
 
 
 _lib = None
@@ -195,6 +200,13 @@ def scenario(d):
     s.confirm = int(per["confirm"])
     for f in CONTROL_FIELDS:
         setattr(s, f, float(d.get(f, 0.0)))
+    # importance sampling: {"param": distribution} drawn instead of the nominal
+    mask = 0
+    for name, spec in d.get("proposal", {}).items():
+        j = DISTS.index(name)
+        mask |= 1 << j
+        s.proposal[j] = _dist(spec)
+    s.is_mask = mask
     return s
 
 
@@ -245,10 +257,11 @@ def _ptr(a):
 
 
 def _params_struct(cols, n):
-    """Columns by name; a missing trigger column is passed as NULL (zero delay)."""
+    """Columns by name; a missing trigger or log_weight column is passed as NULL
+    (read as zeros)."""
     p = Params()
     for c in COLUMNS:
-        setattr(p, c, _ptr(cols[c]) if c in cols or c != "trigger" else None)
+        setattr(p, c, _ptr(cols[c]) if c in cols or c not in ("trigger", "log_weight") else None)
     p.n = n
     return p
 
@@ -266,19 +279,24 @@ def sample_params(d, first=0, count=None, device=True, out=None, stream=None):
     return out
 
 
-def alloc_outputs(n):
+def alloc_outputs(n, weight=False):
+    """Device output columns; weight=True adds the importance-sampling weights."""
     torch = _torch()
-    return {"dist": torch.empty(n, dtype=torch.float64, device="cuda"),
-            "status": torch.empty(n, dtype=torch.uint8, device="cuda"),
-            "steps": torch.empty(n, dtype=torch.int32, device="cuda"),
-            "margin": torch.empty(n, dtype=torch.float64, device="cuda"),
-            "v_impact": torch.empty(n, dtype=torch.float32, device="cuda")}
+    out = {"dist": torch.empty(n, dtype=torch.float64, device="cuda"),
+           "status": torch.empty(n, dtype=torch.uint8, device="cuda"),
+           "steps": torch.empty(n, dtype=torch.int32, device="cuda"),
+           "margin": torch.empty(n, dtype=torch.float64, device="cuda"),
+           "v_impact": torch.empty(n, dtype=torch.float32, device="cuda")}
+    if weight:
+        out["weight"] = torch.empty(n, dtype=torch.float64, device="cuda")
+    return out
 
 
 def _outputs_struct(out):
     o = Outputs()
     for k in ("dist", "status", "steps", "margin", "v_impact"):
         setattr(o, k, out[k].data_ptr())
+    o.weight = out["weight"].data_ptr() if "weight" in out else None
     o.n = out["dist"].numel()
     return o
 
@@ -287,7 +305,7 @@ def rollout(d, params=None, precision="fp64", out=None, stream=None):
     """Roll out every sample of scenario `d` on the GPU; params=None draws in-kernel."""
     n = int(d["n_samples"])
     if out is None:
-        out = alloc_outputs(n)
+        out = alloc_outputs(n, weight=bool(d.get("proposal")))
     s = scenario(d)
     pp = C.byref(_params_struct(params, n)) if params is not None else None
     _check(lib().aeb_rollout(C.byref(s), pp, PRECISIONS[precision],
@@ -319,6 +337,10 @@ def stats_dict(st, n_risk, n_mq, n_grid):
         "v_impact_max": st.v_impact_max,
         "risk_count": np.array(st.risk_count[:n_grid], dtype=np.int64),
         "risk_p": np.array(st.risk_p[:n_grid], dtype=np.float64),
+        "weighted": st.weighted, "p_collision_w": st.p_collision_w,
+        "p_collision_se": st.p_collision_se, "weight_mean": st.weight_mean,
+        "risk_pw": np.array(st.risk_pw[:n_grid], dtype=np.float64),
+        "risk_se": np.array(st.risk_se[:n_grid], dtype=np.float64),
     }
 
 
@@ -346,7 +368,7 @@ def batch_rollout(scns, precision="fp64", outs=None, stream=None):
     """Roll out every sample of several scenarios in one launch; returns a list of outputs."""
     k = len(scns)
     if outs is None:
-        outs = [alloc_outputs(int(d["n_samples"])) for d in scns]
+        outs = [alloc_outputs(int(d["n_samples"]), weight=bool(d.get("proposal"))) for d in scns]
     sarr = (Scenario * k)(*[scenario(d) for d in scns])
     oarr = (Outputs * k)(*[_outputs_struct(o) for o in outs])
     _check(lib().aeb_batch_rollout(sarr, k, PRECISIONS[precision], oarr, _stream(stream)))
@@ -474,8 +496,9 @@ class Graph:
         scns = list(d) if batch else [d]
         k = len(scns)
         if out is None:
-            out = [alloc_outputs(int(x["n_samples"])) for x in scns] if batch else \
-                alloc_outputs(int(scns[0]["n_samples"]))
+            out = [alloc_outputs(int(x["n_samples"]), weight=bool(x.get("proposal")))
+                   for x in scns] if batch else \
+                alloc_outputs(int(scns[0]["n_samples"]), weight=bool(scns[0].get("proposal")))
         self.out = out
         outs = out if batch else [out]
         self.req = reduce_request(risk, margin_q, grid) if stats else None

@@ -154,6 +154,16 @@ int validate(const aeb_scenario& s) {
         !std::isfinite(s.noise_v))
       return fail(AEB_EINVAL, "measurement noise sds must be >= 0 and finite");
   }
+  if (s.is_mask & ~0x1BF)
+    return fail(AEB_EINVAL, "importance sampling covers normal parameters other than tau");
+  for (int j = 0; j < 9; ++j) {
+    if (!((s.is_mask >> j) & 1)) continue;
+    const aeb_dist& q = s.proposal[j];
+    if (all[j]->kind != AEB_DIST_NORMAL || q.kind != AEB_DIST_NORMAL || !(all[j]->p1 > 0.0) ||
+        !(q.p1 > 0.0) || !dist_ok(q))
+      return fail(AEB_EINVAL, std::string("importance sampling of ") + names[j] +
+                                  " needs normal distribution and proposal with sd > 0");
+  }
   double tmin = support_min(s.tau);
   if (!(tmin > 0.0)) return fail(AEB_EINVAL, "tau distribution can reach 0");
   if (s.integrator == AEB_EULER && tmin < s.dt)
@@ -240,7 +250,7 @@ extern "C" {
 
 const char* aeb_last_error(void) { return g_err.c_str(); }
 
-int aeb_version(void) { return 4; }
+int aeb_version(void) { return 5; }
 
 int aeb_timing_enable(int on) {
   g_timing.on = on != 0;
@@ -290,6 +300,9 @@ int aeb_sample_params(const aeb_scenario* scn, int64_t first, int64_t count, con
     return fail(AEB_EINVAL, "aeb_sample_params: sample range out of [0, 2^32)");
   if (perception_on(*scn) && !out->trigger)
     return fail(AEB_EINVAL, "aeb_sample_params: a scenario with perception needs the trigger column");
+  if (scn->is_mask && !out->log_weight)
+    return fail(AEB_EINVAL,
+                "aeb_sample_params: importance sampling needs the log_weight column");
   if (count == 0) return AEB_OK;
   if (on_device) return launch_sample(*scn, first, count, *out, static_cast<hipStream_t>(stream));
   // the paper's plain method: draw on the host with host libm, all cores
@@ -310,6 +323,7 @@ int aeb_sample_params(const aeb_scenario* scn, int64_t first, int64_t count, con
       p.gap[k] = q.gap;
       p.lead_decel[k] = q.lead_decel;
       if (p.trigger) p.trigger[k] = q.trigger;
+      if (p.log_weight) p.log_weight[k] = q.log_w;
     }
   };
   int nt = host_threads();
@@ -340,11 +354,13 @@ int aeb_rollout(const aeb_scenario* scn, const aeb_params* params, int precision
     if (params->n != scn->n_samples) return fail(AEB_EINVAL, "parameter length differs from n_samples");
     if (perception_on(*scn) && !params->trigger)
       return fail(AEB_EINVAL, "aeb_rollout: a scenario with perception needs the trigger column");
+    if (scn->is_mask && !params->log_weight)
+      return fail(AEB_EINVAL, "aeb_rollout: importance sampling needs the log_weight column");
     src = ParamSrc{params->v0, params->mu,  params->mass, params->sin_grade, params->cos_grade,
                    params->cda, params->crr, params->tau, params->gap, params->lead_decel,
-                   params->trigger};
+                   params->trigger, params->log_weight};
   }
-  OutCols oc{out->dist, out->status, out->steps, out->margin, out->v_impact};
+  OutCols oc{out->dist, out->status, out->steps, out->margin, out->v_impact, out->weight};
   return launch_rollout(*scn, params ? &src : nullptr, precision, oc, scn->n_samples,
                         static_cast<hipStream_t>(stream));
 }
@@ -365,7 +381,8 @@ int aeb_batch_rollout(const aeb_scenario* scns, int n_scn, int precision, const 
         scns[j].impact_exit != scns[0].impact_exit || scns[j].nofma != scns[0].nofma)
       return fail(AEB_EINVAL, "batched scenarios must share integrator, obstacle, impact_exit, nofma");
     total += scns[j].n_samples;
-    oc[j] = OutCols{outs[j].dist, outs[j].status, outs[j].steps, outs[j].margin, outs[j].v_impact};
+    oc[j] = OutCols{outs[j].dist, outs[j].status, outs[j].steps, outs[j].margin, outs[j].v_impact,
+                    outs[j].weight};
   }
   if (total > 0xffffffffLL) return fail(AEB_EINVAL, "a batch holds at most 2^32 - 1 samples");
   return launch_batch(scns, n_scn, precision, oc.data(), static_cast<hipStream_t>(stream));
@@ -386,7 +403,7 @@ int aeb_reduce(const aeb_outputs* out, const aeb_reduce_req* req, aeb_stats* hos
   if (out->n < 1 || out->n > 0x7fffffffLL) return fail(AEB_EINVAL, "aeb_reduce: n out of [1, 2^31-1]");
   const int rc = check_reduce_req(*req);
   if (rc != AEB_OK) return rc;
-  OutCols oc{out->dist, out->status, out->steps, out->margin, out->v_impact};
+  OutCols oc{out->dist, out->status, out->steps, out->margin, out->v_impact, out->weight};
   return launch_reduce(oc, out->n, *req, host_out, static_cast<hipStream_t>(stream));
 }
 

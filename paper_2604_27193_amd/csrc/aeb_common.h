@@ -154,22 +154,38 @@ __host__ __device__ inline int64_t command_step(const aeb_scenario& s, double tr
 struct Sample {
   double v0, mu, mass, grade, sin_grade, cos_grade, cda, crr, tau, gap, lead_decel;
   double trigger;  // perception delay (s), 0 without perception
+  double log_w;    // importance-sampling log likelihood ratio, 0 without
 };
+
+// Parameter `slot`: from its proposal when importance sampling covers it
+// (adding log p(x) - log q(x) to lw), else from its own distribution.
+__host__ __device__ inline double draw_param(const aeb_scenario& s, const aeb_dist& d, uint64_t i,
+                                             uint32_t slot, double& lw) {
+  if (!((s.is_mask >> slot) & 1)) return draw(d, s.seed, s.scenario_id, i, slot);
+  const aeb_dist& q = s.proposal[slot];
+  const double x = draw(q, s.seed, s.scenario_id, i, slot);
+  const double zp = (x - d.p0) / d.p1;
+  const double zq = (x - q.p0) / q.p1;
+  lw += log(q.p1 / d.p1) + (0.5 * (zq * zq) - 0.5 * (zp * zp));
+  return x;
+}
 
 __host__ __device__ inline Sample draw_sample(const aeb_scenario& s, uint64_t i) {
   Sample p;
-  p.v0 = draw(s.v0, s.seed, s.scenario_id, i, AEB_SLOT_V0);
-  p.mu = draw(s.mu, s.seed, s.scenario_id, i, AEB_SLOT_MU);
-  p.mass = draw(s.mass, s.seed, s.scenario_id, i, AEB_SLOT_MASS);
-  p.grade = draw(s.grade, s.seed, s.scenario_id, i, AEB_SLOT_GRADE);
+  double lw = 0.0;
+  p.v0 = draw_param(s, s.v0, i, AEB_SLOT_V0, lw);
+  p.mu = draw_param(s, s.mu, i, AEB_SLOT_MU, lw);
+  p.mass = draw_param(s, s.mass, i, AEB_SLOT_MASS, lw);
+  p.grade = draw_param(s, s.grade, i, AEB_SLOT_GRADE, lw);
   p.sin_grade = sin(p.grade);
   p.cos_grade = cos(p.grade);
-  p.cda = draw(s.cda, s.seed, s.scenario_id, i, AEB_SLOT_CDA);
-  p.crr = draw(s.crr, s.seed, s.scenario_id, i, AEB_SLOT_CRR);
-  p.tau = draw(s.tau, s.seed, s.scenario_id, i, AEB_SLOT_TAU);
-  p.gap = draw(s.gap, s.seed, s.scenario_id, i, AEB_SLOT_GAP);
-  p.lead_decel = draw(s.lead_decel, s.seed, s.scenario_id, i, AEB_SLOT_LEAD);
+  p.cda = draw_param(s, s.cda, i, AEB_SLOT_CDA, lw);
+  p.crr = draw_param(s, s.crr, i, AEB_SLOT_CRR, lw);
+  p.tau = draw_param(s, s.tau, i, AEB_SLOT_TAU, lw);
+  p.gap = draw_param(s, s.gap, i, AEB_SLOT_GAP, lw);
+  p.lead_decel = draw_param(s, s.lead_decel, i, AEB_SLOT_LEAD, lw);
   p.trigger = perception_on(s) ? trigger_delay(s, i) : 0.0;
+  p.log_w = lw;
   return p;
 }
 

@@ -50,6 +50,7 @@ int64_t dead_steps(const aeb_scenario& s);
 struct ParamSrc {
   const double *v0, *mu, *mass, *sin_g, *cos_g, *cda, *crr, *tau, *gap, *lead;
   const double* trig;  // perception delay; null reads as 0
+  const double* logw;  // importance-sampling log likelihood ratio; null reads as 0
 };
 
 struct OutCols {
@@ -58,6 +59,7 @@ struct OutCols {
   int32_t* steps;
   double* margin;
   float* vimp;
+  double* weight;  // optional importance-sampling weights (null: not written)
 };
 
 // launchers (kernels_*.hip); all asynchronous on `stream`

@@ -136,15 +136,18 @@ int aeb_graph_create(const aeb_scenario* scn, const aeb_params* params, int prec
         !params->cos_grade || !params->cda || !params->crr || !params->tau || !params->gap ||
         !params->lead_decel || params->n != scn->n_samples)
       return fail(AEB_EINVAL, "aeb_graph_create: incomplete parameter columns");
+    if (scn->is_mask && !params->log_weight)
+      return fail(AEB_EINVAL, "aeb_graph_create: importance sampling needs the log_weight column");
     if (perception_on(*scn) && !params->trigger)
       return fail(AEB_EINVAL, "aeb_graph_create: a scenario with perception needs the trigger column");
     src = ParamSrc{params->v0, params->mu,  params->mass, params->sin_grade, params->cos_grade,
                    params->cda, params->crr, params->tau, params->gap, params->lead_decel,
-                   params->trigger};
+                   params->trigger, params->log_weight};
   }
   aeb_graph* g = new (std::nothrow) aeb_graph;
   if (!g) return fail(AEB_ENOMEM, "host allocation failed");
-  g->outs.push_back(OutCols{out->dist, out->status, out->steps, out->margin, out->v_impact});
+  g->outs.push_back(OutCols{out->dist, out->status, out->steps, out->margin, out->v_impact,
+                                   out->weight});
   g->ns.push_back(scn->n_samples);
   g->reduce = req != nullptr;
   if (req) g->req = *req;
@@ -194,7 +197,8 @@ int aeb_graph_create_batch(const aeb_scenario* scns, int n_scn, int precision,
   if (!g) return fail(AEB_ENOMEM, "host allocation failed");
   for (int j = 0; j < n_scn; ++j) {
     g->outs.push_back(
-        OutCols{outs[j].dist, outs[j].status, outs[j].steps, outs[j].margin, outs[j].v_impact});
+        OutCols{outs[j].dist, outs[j].status, outs[j].steps, outs[j].margin, outs[j].v_impact,
+                    outs[j].weight});
     g->ns.push_back(scns[j].n_samples);
   }
   g->reduce = req != nullptr;

@@ -84,6 +84,7 @@ struct PrepArgs {
   int n_scn;
   int32_t* nds;              // per-sample command step (launches with perception), else null
   int ctl;                   // closed-loop controller (single scenario)
+  double* weight;            // single scenario: importance-sampling weights out (or null)
 };
 
 template <bool DEVRNG, bool BATCH>
@@ -115,18 +116,23 @@ __global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job
     const aeb_scenario& s = BATCH ? a.scns[j] : a.s;
     const int nd = BATCH ? a.tab[j].nd : a.nd;
     const int nmax = BATCH ? a.tab[j].nmax : a.nmax;
-    double v0, mu, mass, sg, cg, cda, crr, tau, gap, lead, trig;
+    double v0, mu, mass, sg, cg, cda, crr, tau, gap, lead, trig, lw;
     if (DEVRNG) {
       Sample q = draw_sample(s, static_cast<uint64_t>(local));
       v0 = q.v0; mu = q.mu; mass = q.mass; sg = q.sin_grade; cg = q.cos_grade;
       cda = q.cda; crr = q.crr; tau = q.tau; gap = q.gap; lead = q.lead_decel;
       trig = q.trigger;
+      lw = q.log_w;
     } else {
       v0 = a.src.v0[i]; mu = a.src.mu[i]; mass = a.src.mass[i]; sg = a.src.sin_g[i];
       cg = a.src.cos_g[i]; cda = a.src.cda[i]; crr = a.src.crr[i]; tau = a.src.tau[i];
       gap = a.src.gap[i]; lead = a.src.lead[i];
       trig = a.src.trig ? a.src.trig[i] : 0.0;
+      lw = a.src.logw ? a.src.logw[i] : 0.0;
     }
+    // the importance-sampling weight goes straight to the sample's output
+    double* wout = BATCH ? a.tab[j].out.weight : a.weight;
+    if (wout) wout[local] = exp(lw);
     // with perception every sample has its own command step
     int ndl = nd;
     if (a.nds) {
@@ -1520,6 +1526,7 @@ int launch_rollout_fast_into(const aeb_scenario& s, const ParamSrc* src, int pre
   pa.cap = static_cast<float>(nmax);
   pa.nds = perception_on(s) ? b.nds : nullptr;
   pa.ctl = control_on(s) ? 1 : 0;
+  pa.weight = out.weight;
   if (src)
     hipLaunchKernelGGL((k_prep<false, false>), dim3(pblk), dim3(PREP_BLOCK), 0, st, pa, b.jobs,
                        b.leads, b.keys, b.hist);

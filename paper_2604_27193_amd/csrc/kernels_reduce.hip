@@ -39,6 +39,8 @@ struct Partial {
   double sum, dmin, dmax, msum, mmin, mmax;
   float vmax;
   float pad;
+  double wmax;     // largest importance-sampling weight
+  long long wbad;  // weights that are not finite and >= 0
 };
 
 // Selection targets: per target the array (0 censored distance, 1 margin)
@@ -57,6 +59,7 @@ struct Sel {
   unsigned rank_in_bin[MAX_T];
   unsigned bin_count[MAX_T];
   double vmin[2], scale[2];
+  int wshift[2];  // fixed-point exponents of w and w^2 (importance-sampling sums)
 };
 
 // Radix-select state of the fallback path.
@@ -218,6 +221,8 @@ __device__ inline void combine(Partial& a, const Partial& b) {
   a.mmin = b.mmin < a.mmin ? b.mmin : a.mmin;
   a.mmax = b.mmax > a.mmax ? b.mmax : a.mmax;
   a.vmax = b.vmax > a.vmax ? b.vmax : a.vmax;
+  a.wmax = b.wmax > a.wmax ? b.wmax : a.wmax;
+  a.wbad += b.wbad;
 }
 
 __device__ inline Partial identity_partial() {
@@ -228,6 +233,8 @@ __device__ inline Partial identity_partial() {
   p.dmax = p.mmax = -INFINITY;
   p.vmax = 0.0f;
   p.pad = 0.0f;
+  p.wmax = 0.0;
+  p.wbad = 0;
   return p;
 }
 
@@ -247,6 +254,8 @@ __device__ inline Partial wave_combine(const Partial& a) {
   p.mmax = wave_reduce(a.mmax, MaxOp());
   p.vmax = static_cast<float>(wave_reduce(static_cast<double>(a.vmax), MaxOp()));
   p.pad = 0.0f;
+  p.wmax = wave_reduce(a.wmax, MaxOp());
+  p.wbad = wave_reduce(a.wbad, AddOp());
   return p;
 }
 
@@ -263,10 +272,19 @@ __global__ __launch_bounds__(EB) void k_pass1(OutCols o, long long n, long long 
   __shared__ Partial wp[EB / 64];
   const long long lo = static_cast<long long>(blockIdx.x) * chunk;
   const long long hi = lo + chunk < n ? lo + chunk : n;
-  long long ncol = 0, nstop = 0, nimp = 0, nhor = 0, nbnd = 0;
+  long long ncol = 0, nstop = 0, nimp = 0, nhor = 0, nbnd = 0, wbad = 0;
   double sum = 0.0, dmin = INFINITY, dmax = -INFINITY, msum = 0.0, mmin = INFINITY,
-         mmax = -INFINITY;
+         mmax = -INFINITY, wmax = 0.0;
   float vmax = 0.0f;
+  if (o.weight) {  // importance-sampling weights: their range and validity
+    for (long long i = lo + threadIdx.x; i < hi; i += EB) {
+      const double w = o.weight[i];
+      if (w >= 0.0 && w < INFINITY)
+        wmax = w > wmax ? w : wmax;
+      else
+        ++wbad;
+    }
+  }
   // CP elements per thread are loaded before any is used (chunk = CP * EB)
   for (long long i0 = lo; i0 < hi; i0 += static_cast<long long>(EB) * CP) {
     uint8_t sv[CP];
@@ -328,6 +346,8 @@ __global__ __launch_bounds__(EB) void k_pass1(OutCols o, long long n, long long 
   p.mmax = mmax;
   p.vmax = vmax;
   p.pad = 0.0f;
+  p.wmax = wmax;
+  p.wbad = wbad;
   p = wave_combine(p);
   if ((threadIdx.x & 63) == 0) wp[threadIdx.x >> 6] = p;
   __syncthreads();
@@ -340,7 +360,7 @@ __global__ __launch_bounds__(EB) void k_pass1(OutCols o, long long n, long long 
 // Combine the block partials in a fixed order (thread t takes partials
 // t, t+FB, ... in order, then a fixed tree).
 __global__ __launch_bounds__(FB) void k_fin1(const Partial* part, int nb, long long n,
-                                             aeb_stats* st, Sel* sel) {
+                                             int weighted, aeb_stats* st, Sel* sel) {
   __shared__ Partial wp[FB / 64];
   Partial p = identity_partial();
   for (int b = threadIdx.x; b < nb; b += FB) combine(p, part[b]);
@@ -373,6 +393,16 @@ __global__ __launch_bounds__(FB) void k_fin1(const Partial* part, int nb, long l
     sel->scale[0] = (nstop > 0 && dmax > dmin) ? static_cast<double>(NVB) / (dmax - dmin) : 0.0;
     sel->vmin[1] = mmin;
     sel->scale[1] = mmax > mmin ? static_cast<double>(NVB) / (mmax - mmin) : 0.0;
+    // fixed point of the weighted sums: value * 2^shift as a 128-bit integer,
+    // with n * max value * 2^shift < 2^126 (no sum can overflow)
+    int ln = 0;
+    while ((1ll << ln) < n) ++ln;
+    int e1 = 0, e2 = 0;
+    frexp(q.wmax, &e1);
+    frexp(q.wmax * q.wmax, &e2);
+    sel->wshift[0] = q.wmax > 0.0 ? 126 - ln - e1 : 0;
+    sel->wshift[1] = q.wmax > 0.0 ? 126 - ln - e2 : 0;
+    st->weighted = weighted ? (q.wbad > 0 ? -1 : 1) : 0;
   }
 }
 
@@ -433,6 +463,111 @@ __global__ __launch_bounds__(EB) void k_pass2(OutCols o, long long n, long long 
   }
   unsigned* out = bhist + static_cast<size_t>(blockIdx.x) * hw;
   for (int j = threadIdx.x; j < hw; j += EB) out[j] = h[j];
+}
+
+// ---- importance-sampling sums: exact 128-bit fixed point ----
+// A nonnegative value as the integer floor(value * 2^shift) in two words
+// (the scaling by a power of two and the split are exact in binary64).
+__device__ inline void to_fixed(double v, int shift, unsigned long long& hi,
+                                unsigned long long& lo) {
+  const double t = ldexp(v, shift);
+  const double h = floor(ldexp(t, -64));
+  hi = static_cast<unsigned long long>(h);
+  lo = static_cast<unsigned long long>(t - ldexp(h, 64));
+}
+
+// acc[0] low word, acc[1] high word; integer adds in any order give the
+// same total, so the sums do not depend on scheduling
+__device__ inline void add_fixed(unsigned long long* acc, unsigned long long hi,
+                                 unsigned long long lo) {
+  if (lo) {
+    const unsigned long long old = atomicAdd(&acc[0], lo);
+    if (old + lo < old) atomicAdd(&acc[1], 1ull);
+  }
+  if (hi) atomicAdd(&acc[1], hi);
+}
+
+__device__ inline double from_fixed(unsigned long long hi, unsigned long long lo, int shift) {
+  return ldexp(static_cast<double>(hi), 64 - shift) + ldexp(static_cast<double>(lo), -shift);
+}
+
+// Per block (the histogram pass's slices): for each risk-grid rank bin the
+// sums of w and w^2, then bins for the collided samples and for all samples;
+// four words per bin (w low, w high, w^2 low, w^2 high), merged into the
+// zeroed global accumulators.
+constexpr int WACC = (AEB_MAX_GRID + 3) * 4;
+__global__ __launch_bounds__(EB) void k_wpass(OutCols o, long long n, long long chunk, double glo,
+                                              double gstep, double ginv, int ng, const Sel* sel,
+                                              unsigned long long* gacc) {
+  __shared__ unsigned long long acc[WACC];
+  const int G = ng >= 2 ? ng + 1 : 0;  // rank bins 0..ng
+  const int nacc = (G + 2) * 4;
+  for (int j = threadIdx.x; j < nacc; j += EB) acc[j] = 0ull;
+  __syncthreads();
+  const int s1 = sel->wshift[0], s2 = sel->wshift[1];
+  const long long lo = static_cast<long long>(blockIdx.x) * chunk;
+  const long long hi = lo + chunk < n ? lo + chunk : n;
+  for (long long i = lo + threadIdx.x; i < hi; i += EB) {
+    const double w = o.weight[i];
+    if (!(w >= 0.0 && w < INFINITY)) continue;  // reported through the statistics' flag
+    const uint8_t st = o.status[i];
+    const double d = o.dist[i];
+    unsigned long long h1, l1, h2, l2;
+    to_fixed(w, s1, h1, l1);
+    to_fixed(w * w, s2, h2, l2);
+    if (G) {
+      const int b = grid_rank((st & 3) == AEB_END_STOP ? d : INFINITY, glo, gstep, ginv, ng);
+      add_fixed(&acc[4 * b], h1, l1);
+      add_fixed(&acc[4 * b + 2], h2, l2);
+    }
+    if (st & AEB_COLLIDED) {
+      add_fixed(&acc[4 * G], h1, l1);
+      add_fixed(&acc[4 * G + 2], h2, l2);
+    }
+    add_fixed(&acc[4 * (G + 1)], h1, l1);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < nacc / 2; j += EB) {
+    const unsigned long long l = acc[2 * j], h = acc[2 * j + 1];
+    if (l | h) add_fixed(&gacc[2 * j], h, l);
+  }
+}
+
+// The weighted estimates from the accumulated sums (one thread, in a fixed
+// order): suffix sums over the rank bins from the top give sum w [D > H0_j].
+__global__ void k_wfin(long long n, int ng, const Sel* sel, const unsigned long long* gacc,
+                       aeb_stats* st) {
+  if (threadIdx.x != 0) return;
+  const int G = ng >= 2 ? ng + 1 : 0;
+  const double nd = static_cast<double>(n);
+  const int s1 = sel->wshift[0], s2 = sel->wshift[1];
+  if (st->weighted != 1) {
+    st->p_collision_w = st->p_collision_se = st->weight_mean = NAN;
+    for (int j = 0; j < ng; ++j) st->risk_pw[j] = st->risk_se[j] = NAN;
+    return;
+  }
+  auto se_of = [&](double p, double m2) {
+    const double v = m2 / nd - p * p;
+    return n > 1 ? sqrt((v > 0.0 ? v : 0.0) / (nd - 1.0)) : NAN;
+  };
+  unsigned long long a_l = 0, a_h = 0, b_l = 0, b_h = 0;  // suffix sums of w and w^2
+  for (int b = G - 1; b >= 1; --b) {
+    const unsigned long long* c = gacc + 4 * b;
+    const unsigned long long al = a_l + c[0];
+    a_h += c[1] + (al < a_l ? 1ull : 0ull);
+    a_l = al;
+    const unsigned long long bl = b_l + c[2];
+    b_h += c[3] + (bl < b_l ? 1ull : 0ull);
+    b_l = bl;
+    const double p = from_fixed(a_h, a_l, s1) / nd;
+    st->risk_pw[b - 1] = p;
+    st->risk_se[b - 1] = se_of(p, from_fixed(b_h, b_l, s2));
+  }
+  const unsigned long long* c = gacc + 4 * G;
+  const double pc = from_fixed(c[1], c[0], s1) / nd;
+  st->p_collision_w = pc;
+  st->p_collision_se = se_of(pc, from_fixed(c[3], c[2], s2));
+  st->weight_mean = from_fixed(gacc[4 * (G + 1) + 1], gacc[4 * (G + 1)], s1) / nd;
 }
 
 // Bin totals of the block-private histograms: a 2-D grid, each thread sums
@@ -767,7 +902,8 @@ namespace {
 struct RLayout {
   long long chunk, chunk2;
   int nb, nb2, T;
-  size_t off_sel, off_zero_end, off_var, off_bh, off_bt, off_bo, off_cand, off_ss, off_sh, total;
+  size_t off_sel, off_zero_end, off_var, off_bh, off_bt, off_wa, off_bo, off_cand, off_ss, off_sh,
+      total;
 };
 
 RLayout layout(int64_t n, const aeb_reduce_req& req) {
@@ -783,7 +919,8 @@ RLayout layout(int64_t n, const aeb_reduce_req& req) {
   const int tc = L.T > 0 ? L.T : 1;
   L.off_sel = align256(sizeof(aeb_stats));
   L.off_bt = align256(L.off_sel + sizeof(Sel));
-  L.off_zero_end = align256(L.off_bt + sizeof(unsigned) * HW);
+  L.off_wa = align256(L.off_bt + sizeof(unsigned) * HW);
+  L.off_zero_end = align256(L.off_wa + sizeof(unsigned long long) * WACC);
   L.off_var = align256(L.off_zero_end + sizeof(Partial) * L.nb);
   L.off_bh = align256(L.off_var + sizeof(double) * (L.nb > L.nb2 ? L.nb : L.nb2));
   L.off_bo = align256(L.off_bh + sizeof(unsigned) * HW * L.nb2);
@@ -811,6 +948,7 @@ int reduce_enqueue(const OutCols& out, int64_t n, const aeb_reduce_req& req, voi
   unsigned* bhist = reinterpret_cast<unsigned*>(base + L.off_bh);
   unsigned* btot = reinterpret_cast<unsigned*>(base + L.off_bt);
   unsigned* boff = reinterpret_cast<unsigned*>(base + L.off_bo);
+  unsigned long long* wacc = reinterpret_cast<unsigned long long*>(base + L.off_wa);
   unsigned long long* cand = reinterpret_cast<unsigned long long*>(base + L.off_cand);
 
   // targets: ranks computed exactly as floor(level * N) in binary64
@@ -839,7 +977,7 @@ int reduce_enqueue(const OutCols& out, int64_t n, const aeb_reduce_req& req, voi
   hipLaunchKernelGGL(k_pass1, dim3(L.nb), dim3(EB), 0, st, out, static_cast<long long>(n), L.chunk,
                      part);
   hipLaunchKernelGGL(k_fin1, dim3(1), dim3(FB), 0, st, part, L.nb, static_cast<long long>(n),
-                     dstats, sel);
+                     out.weight ? 1 : 0, dstats, sel);
   // block histograms: the value bins only when some target needs them
   const int hw = ng >= 2 ? HG + ng + 1 : (T > 0 ? HG : 0);
   hipLaunchKernelGGL(k_pass2, dim3(L.nb2), dim3(EB), 0, st, out, static_cast<long long>(n),
@@ -851,6 +989,12 @@ int reduce_enqueue(const OutCols& out, int64_t n, const aeb_reduce_req& req, voi
                        dim3(256), 0, st, bhist, L.nb2, hw, btot);
   hipLaunchKernelGGL(k_fin2, dim3(1 + T), dim3(FB), 0, st, vpart, L.nb2,
                      static_cast<long long>(n), ng, dstats, sel, in, btot, bhist, hw, boff);
+  if (out.weight) {
+    hipLaunchKernelGGL(k_wpass, dim3(L.nb2), dim3(EB), 0, st, out, static_cast<long long>(n),
+                       L.chunk2, req.grid_lo, gstep, ng >= 2 ? 1.0 / gstep : 0.0, ng, sel, wacc);
+    hipLaunchKernelGGL(k_wfin, dim3(1), dim3(64), 0, st, static_cast<long long>(n), ng, sel, wacc,
+                       dstats);
+  }
   if (T > 0) {
     // the histogram pass's blocks: the offsets above are per block of it
     hipLaunchKernelGGL(k_collect, dim3(L.nb2), dim3(EB), 0, st, out, static_cast<long long>(n),

@@ -28,6 +28,7 @@ __device__ inline Lane load_lane(const aeb_scenario& s, const ParamSrc& src, int
     L.gap = q.gap;
     L.lead = q.lead_decel;
     L.trig = q.trigger;
+    L.log_w = q.log_w;
   } else {
     L.v0 = src.v0[i];
     mu = src.mu[i];
@@ -40,6 +41,7 @@ __device__ inline Lane load_lane(const aeb_scenario& s, const ParamSrc& src, int
     L.gap = src.gap[i];
     L.lead = src.lead[i];
     L.trig = src.trig ? src.trig[i] : 0.0;
+    L.log_w = src.logw ? src.logw[i] : 0.0;
   }
   L.k = derive(s, mu, mass, sg, cg, cda, crr);
   L.index = static_cast<uint64_t>(i);
@@ -67,6 +69,7 @@ __global__ __launch_bounds__(256) void k_rollout_fp64(aeb_scenario s, ParamSrc s
                  ? euler_fp64<OBS, NOFMA, CTL>(L, s.dt, s.a_cmd, nd, nmax, s.impact_exit, &ca)
                  : rk4_fp64<OBS, CTL>(L, s.dt, s.a_cmd, nd, nmax, s.impact_exit, &ca);
   store(out, i, r);
+  if (out.weight) out.weight[i] = exp(L.log_w);
 }
 
 // FP64 recomputation of the samples listed in fix[1 .. fix[0]]; clears the

@@ -34,6 +34,7 @@ __global__ __launch_bounds__(256) void k_sample(aeb_scenario s, int64_t first, i
   p.gap[k] = q.gap;
   p.lead_decel[k] = q.lead_decel;
   if (p.trigger) p.trigger[k] = q.trigger;
+  if (p.log_weight) p.log_weight[k] = q.log_w;
 }
 
 int launch_uniforms(uint64_t seed, uint64_t sid, int64_t first, int64_t count, uint32_t slot,

@@ -32,6 +32,7 @@ struct Lane {
   double tau;
   double trig;           // perception delay (s)
   uint64_t index;        // the sample's index (keys the controller's noise)
+  double log_w;          // importance-sampling log likelihood ratio
 };
 
 // ---------------------------------------------------------------------------

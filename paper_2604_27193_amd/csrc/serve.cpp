@@ -119,6 +119,8 @@ class HipExecutor final : public serve::Executor {
   int check(const aeb_scenario& s) const override {
     const int rc = validate(s);
     if (rc != AEB_OK) return rc;
+    if (s.is_mask)
+      return fail(AEB_EINVAL, "serving returns unweighted statistics: no importance sampling");
     if (!fast_path_applies(s, cfg_.precision) || control_on(s))
       return fail(AEB_EINVAL,
                   "serving runs the batched block-structured path (not the unfused Euler "

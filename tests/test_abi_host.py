@@ -65,7 +65,10 @@ def test_host_uniforms_bitwise(B, orc, seed, sid, slot, attempt):
                                W.perception(5000, occlusion=("normal", 1.0, 3.0), p_dropout=0.6,
                                             confirm=4, latency=("normal", 0.0, 0.05)),
                                W.perception(3000, frame_period=0.0),
-                               W.perception(3000, occlusion=("const", 1e30), horizon=1.0)])
+                               W.perception(3000, occlusion=("const", 1e30), horizon=1.0),
+                               W.rare_event(5000),
+                               dict(W.single(3000), proposal={"mass": ("normal", 1400.0, 90.0),
+                                                              "gap": ("normal", 55.0, 3.0)})])
 def test_host_sampler_bitwise(B, orc, d):
     n = min(int(d["n_samples"]), 20_000)
     got = B.sample_params(d, 0, n, device=False)
@@ -89,6 +92,15 @@ def test_perception_validation_agrees(B, orc):
         d.update(change)
         assert B.validate(d) == B.EINVAL == orc.validate(d), change
     assert B.validate(W.perception(10)) == B.OK
+
+
+def test_importance_validation_agrees(B, orc):
+    from test_oracle_importance import BAD
+    for change in BAD:
+        d = W.paper_preset(10)
+        d.update(change)
+        assert B.validate(d) == B.EINVAL == orc.validate(d), change
+    assert B.validate(W.rare_event(10)) == B.OK
 
 
 def test_controller_validation_agrees(B, orc):
