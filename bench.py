@@ -310,6 +310,45 @@ def control_leg(B, W, torch, n):
     return res
 
 
+def rare_event_leg(B, W, torch, n):
+    """Rare-event estimation (Sec. VIII): the paper preset's collision-risk
+    tail P(D > H0) out to ~1e-7, by plain sampling and by importance sampling
+    (v0 and mu drawn from shifted normals, weighted by their likelihood ratio)
+    at the same sample count; the standard errors give the variance reduction
+    and the equivalent plain-sampling cost."""
+    import numpy as np
+    grid = (110.0, 190.0, 9)
+    res = {"workload": f"paper preset (Sec. IV-B), {n} samples, RK4 dt=1 ms; proposals "
+                       "v0 ~ N(36, 2), mu ~ N(0.55, 0.1)",
+           "grid_m": list(np.linspace(*grid[:2], grid[2]))}
+    out = B.alloc_outputs(n)
+    d = W.paper_preset(n)
+    ms_plain = kernel_ms(B, torch, d, out, "fp64")
+    st = B.reduce(out, grid=grid)
+    p_plain = st["risk_p"]
+    se_plain = np.sqrt(p_plain * (1 - p_plain) / n)
+    dw = W.rare_event(n)
+    outw = B.alloc_outputs(n, weight=True)
+    ms_is = kernel_ms(B, torch, dw, outw, "fp64")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stw = B.reduce(outw, grid=grid)
+    red_ms = (time.perf_counter() - t0) * 1e3
+    rows = []
+    for j, h in enumerate(res["grid_m"]):
+        p, se = stw["risk_pw"][j], stw["risk_se"][j]
+        vr = (se_plain[j] / se) ** 2 if se > 0 and se_plain[j] > 0 else None
+        # plain samples needed for IS's relative error: p(1-p) / se^2
+        n_eq = p * (1 - p) / se ** 2 if se > 0 else None
+        rows.append({"H0": h, "p_plain": float(p_plain[j]), "se_plain": float(se_plain[j]),
+                     "p_is": float(p), "se_is": float(se), "variance_ratio": vr,
+                     "plain_samples_for_same_se": n_eq})
+    res.update({"kernel_ms_plain": ms_plain, "kernel_ms_is": ms_is,
+                "weighted_reduce_call_ms": red_ms, "weight_mean": stw["weight_mean"],
+                "rows": rows})
+    return res
+
+
 def n_sweep_leg(B, W, torch, sizes=(1_000, 10_000, 100_000, 1_048_576), reps=5):
     """Rollout call (parameters drawn in-kernel) plus reduction at growing N:
     below ~1e5 samples the launch sequence, not the integration, sets the time."""
@@ -527,7 +566,7 @@ def main():
     step_wall = wallg64 if use_graph else wall64
     value = args.steps * n / step_wall
 
-    rk4 = nsweep = study = perception = control = None
+    rk4 = nsweep = study = perception = control = rare = None
     if not args.headline_only:
         log("bench: rk4 leg")
         rk4 = rk4_leg(B, W, torch, n)
@@ -539,6 +578,8 @@ def main():
         perception = perception_leg(B, W, torch, n)
         log("bench: controller leg")
         control = control_leg(B, W, torch, n)
+        log("bench: rare-event leg")
+        rare = rare_event_leg(B, W, torch, n)
 
     batch = None
     if not args.no_batch:
@@ -616,6 +657,7 @@ def main():
         "paper_preset_study": study,
         "perception": perception,
         "control": control,
+        "rare_event": rare,
         "batch": batch,
         "serving": serving,
         "plain_method_host": {"sampling_s": t_sample, "h2d_s": t_h2d,
