@@ -426,7 +426,8 @@ __device__ inline int wave_min(int x) {
 
 // varnd: nd or nmax differ between lanes (a batch, or per-sample command steps)
 __device__ inline int wave_lim(bool varnd, bool active, int k, int nd, int nmax) {
-  if (!varnd) return lane_lim(k, nd, nmax);  // nd, nmax are uniform
+  // nd, nmax are uniform: say so, so that the tests on the limit are scalar
+  if (!varnd) return __builtin_amdgcn_readfirstlane(lane_lim(k, nd, nmax));
   return wave_min(active ? lane_lim(k, nd, nmax) : INT_MAX);
 }
 
@@ -457,7 +458,7 @@ __device__ inline int64_t next_chunk(unsigned long long* counter, int persistent
 struct Lane64 {
   St64 s, sv;  // state, and start state of the block where the obstacle was passed
   Ld64 l, lv;  // lead vehicle, and its state at that block start
-  int sk;      // step index at that block start
+  int sk, se;  // step index at that block start, and at its end
   int on1, on2, stage;  // controller: first steps of its two commands (INT_MAX: none), stage
   bool active, collided, pend, clamped, free_lane, limited;
 };
@@ -496,6 +497,7 @@ __device__ inline void run_block64(Lane64& L, const Job& J, double al, const Lan
     L.sv = L.s;
     if (LEAD) L.lv = L.l;
     L.sk = k;
+    L.se = k + B;
   }
   if (k + B <= wnd) {
     block64<FORM_D, B, LEAD, INTEG>(L.s, L.l, J, al, c.dt, cmd);
@@ -517,6 +519,46 @@ __device__ inline void run_block64(Lane64& L, const Job& J, double al, const Lan
     L.pend = true;
     L.active = false;
   }
+}
+
+// Consecutive K-step blocks in one steady form (every active lane friction-
+// limited for good, or every one never limited), for as long as no lane can
+// stop or reach the block limit wl inside the next block.  A lane's block
+// start state is kept only through its block; where the obstacle is passed
+// inside a block, that state becomes the lane's replay start.  Returns the
+// step index after the last block.
+template <int OBS, int K, int FORM, int INTEG>
+__device__ inline int run_steady(Lane64& L, const Job& J, double al, double dt, double cmd, int k,
+                                 int wl, double thr, int impact_exit, double& xmax) {
+  constexpr bool LEAD = OBS == AEB_OBS_LEAD;
+  do {
+    const St64 b = L.s;
+    const Ld64 bl = L.l;
+    // in 16-step pieces whose position is pinned in a register at the end of
+    // each: with no obstacle nothing inside the run reads the position, and
+    // the compiler would otherwise hold every step's speed for a position
+    // update sunk to the end of the run (hundreds of registers)
+#pragma unroll
+    for (int q = 0; q < K / 16; ++q) {
+      block64<FORM, 16, LEAD, INTEG>(L.s, L.l, J, al, dt, cmd);
+      asm volatile("" : "+v"(L.s.x));
+    }
+    if (INTEG == AEB_RK4 && L.active) xmax = fmax(xmax, L.s.x);
+    bool hit = false;
+    if (OBS == AEB_OBS_STATIONARY) hit = L.active && !L.collided && L.s.x > J.gap;
+    if (LEAD) hit = L.active && L.l.gmin < 0.0;  // the lead was reached inside the block
+    if (hit) {
+      L.sv = b;
+      if (LEAD) L.lv = bl;
+      L.sk = k;
+      L.se = k + K;
+      L.collided = true;
+      L.pend = true;
+      if (LEAD || impact_exit) L.active = false;
+    }
+    k += K;
+  } while (k + K <= wl && __any(L.active) && !__any(L.active && L.s.v <= thr));
+  return k;
 }
 
 template <int OBS, int K, bool BATCH, int INTEG = AEB_EULER, bool CTL = false>
@@ -550,7 +592,8 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
     const bool varnd = BATCH || ctx.nds;
     // every lane is in its dead time for blocks ending at or before wnd (with
     // the controller: until its first command, known once decided)
-    int wnd = CTL ? INT_MAX : (varnd ? wave_min(valid ? c.nd : INT_MAX) : c.nd);
+    int wnd = CTL ? INT_MAX
+                  : __builtin_amdgcn_readfirstlane(varnd ? wave_min(valid ? c.nd : INT_MAX) : c.nd);
     // v above these cannot reach 0 within a block (|dv/dt| <= dmax)
     const double thr_k = static_cast<double>(K) * c.dt * J.dmax;
     const double thr_m = static_cast<double>(KM) * c.dt * J.dmax;
@@ -563,7 +606,7 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
     L.l = Ld64{0.0, LEAD ? J.v0 : 0.0, J.gap};
     L.sv = L.s;
     L.lv = L.l;
-    L.sk = 0;
+    L.sk = L.se = 0;
     L.active = valid;
     L.collided = L.pend = L.clamped = false;
     // never limited: a >= a_cmd - (rounding) > alim, so max(a, alim) = a
@@ -623,9 +666,21 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
         wl = wave_lim(varnd, L.active, k, c.nd, c.nmax);
       }
       if (k + K <= wl && !__any(L.active && L.s.v <= thr_k)) {
-        run_block64<OBS, K, INTEG, CTL>(L, J, al, c, k, wnd, ctx.impact_exit, ctx.ca.a_warn);
-        if (INTEG == AEB_RK4 && L.active) xmax = fmax(xmax, L.s.x);
-        k += K;
+        // past every lane's dead time, in a form no later block changes:
+        // a run of blocks without the per-block bookkeeping
+        const bool past = k + K > wnd;
+        if (past && __all(!L.active || L.clamped)) {
+          k = run_steady<OBS, K, FORM_C, INTEG>(L, J, al, c.dt, 0.0, k, wl, thr_k,
+                                                ctx.impact_exit, xmax);
+        } else if (past && __all(!L.active || L.free_lane)) {
+          const double cmd = lane_cmd<CTL>(L, c, ctx.ca.a_warn, k);
+          k = run_steady<OBS, K, FORM_F, INTEG>(L, J, al, c.dt, cmd, k, wl, thr_k,
+                                                ctx.impact_exit, xmax);
+        } else {
+          run_block64<OBS, K, INTEG, CTL>(L, J, al, c, k, wnd, ctx.impact_exit, ctx.ca.a_warn);
+          if (INTEG == AEB_RK4 && L.active) xmax = fmax(xmax, L.s.x);
+          k += K;
+        }
       } else if (KM > KS && k + KM <= wl && !__any(L.active && L.s.v <= thr_m)) {
         run_block64<OBS, KM, INTEG, CTL>(L, J, al, c, k, wnd, ctx.impact_exit, ctx.ca.a_warn);
         if (INTEG == AEB_RK4 && L.active) xmax = fmax(xmax, L.s.x);
@@ -681,11 +736,39 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
         k += 1;
       }
     }
-    // replay the block in which each pending lane passed the obstacle
+    // replay the block in which each pending lane passed the obstacle.  Inside
+    // that block every speed stays positive, so the position rises (and with
+    // a lead vehicle the running minimum of the clearance can only fall): a
+    // chunk of RB steps that ends inside the block holds the crossing exactly
+    // when its end state shows it.  Chunks without the crossing are skipped
+    // whole; the one holding it then runs step by step.  The generic form is
+    // the canonical step, so both reproduce the block's states bit for bit.
     if (OBS != AEB_OBS_NONE && __any(L.pend)) {
       St64 r = L.sv;
       Ld64 rl = L.lv;
       int kr = L.sk;
+      constexpr int RB = 8;
+      if (K > RB) {
+        // the command is constant over a block
+        const double cmd = lane_cmd<CTL>(L, c, ctx.ca.a_warn, kr);
+        bool skip = L.pend;
+        for (int it = 0; it < K / RB; ++it) {
+          skip = skip && kr + RB <= L.se;
+          if (!__any(skip)) break;
+          if (skip) {
+            St64 t = r;
+            Ld64 tl = rl;
+            block64<FORM_G, RB, LEAD, INTEG>(t, tl, J, al, c.dt, cmd);
+            if (LEAD ? tl.gmin < 0.0 : t.x > J.gap) {
+              skip = false;
+            } else {
+              r = t;
+              rl = tl;
+              kr += RB;
+            }
+          }
+        }
+      }
       // the replay is bit-identical to the block, so the crossing recurs within it
       for (int it = 0; it <= K; ++it) {
         if (!__any(L.pend)) break;
@@ -887,7 +970,7 @@ __global__ __launch_bounds__(256) void k_roll_fp32c(const Job* __restrict__ jobs
     const LaneScn sc = lane_scn<BATCH>(ctx, J, valid, g);
     const int nd = sc.nd, nmax = sc.nmax;
     const bool varnd = BATCH || ctx.nds;
-    const int wnd = varnd ? wave_min(valid ? nd : INT_MAX) : nd;
+    const int wnd = __builtin_amdgcn_readfirstlane(varnd ? wave_min(valid ? nd : INT_MAX) : nd);
     L32 c;  // (the speed read below is base + increment; the increment is 0 without compensation)
     c.dt = static_cast<float>(sc.dt);
     c.nkd = static_cast<float>(J.nkd);
@@ -1160,7 +1243,7 @@ __global__ __launch_bounds__(256) void k_roll_fp32c_lead(const Job* __restrict__
     const LaneScn sc = lane_scn<BATCH>(ctx, J, valid, g);
     const int nd = sc.nd, nmax = sc.nmax;
     const bool varnd = BATCH || ctx.nds;
-    const int wnd = varnd ? wave_min(valid ? nd : INT_MAX) : nd;
+    const int wnd = __builtin_amdgcn_readfirstlane(varnd ? wave_min(valid ? nd : INT_MAX) : nd);
     L32 c;
     c.dt = static_cast<float>(sc.dt);
     c.nkd = static_cast<float>(J.nkd);
