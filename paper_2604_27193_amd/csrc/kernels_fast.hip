@@ -945,6 +945,33 @@ __device__ inline void run_block32(Lane32& L, const L32& c, bool split, int nd, 
   }
 }
 
+// Consecutive K-step blocks in one steady form and one speed representation
+// (as run_steady of the FP64 kernel), with the flush at every flush point.
+template <int OBS, int K, int FORM, bool SPLIT>
+__device__ inline int run_steady32(Lane32& L, const L32& c, float tk, int k, int wl,
+                                   int impact_exit) {
+  do {
+    const St32 b = L.s;
+#pragma unroll
+    for (int q = 0; q < K / 16; ++q) {
+      block32<FORM, 16, SPLIT>(L.s, c, tk);
+      asm volatile("" : "+v"(L.s.p));  // no position update sunk to the end of the run
+    }
+    if ((k + K) % FLUSH == 0) flush32(L.s, SPLIT);
+    if (OBS == AEB_OBS_STATIONARY && L.active && !L.crossed &&
+        (L.s.X.hi - L.s.X.lo) + L.s.p > c.gapf) {
+      L.sv = b;
+      L.sk = k;
+      L.sb = K;
+      L.crossed = true;
+      L.pend = true;
+      if (impact_exit) L.active = false;
+    }
+    k += K;
+  } while (k + K <= wl && __any(L.active) && !__any(L.active && speed32<SPLIT>(L.s) <= c.thr));
+  return k;
+}
+
 template <int OBS, int K, bool BATCH>
 __global__ __launch_bounds__(256) void k_roll_fp32c(const Job* __restrict__ jobs,
                                                     const uint32_t* __restrict__ perm, int64_t n,
@@ -1014,8 +1041,27 @@ __global__ __launch_bounds__(256) void k_roll_fp32c(const Job* __restrict__ jobs
       const float v_now = speed32<true>(L.s);
       // blocks start on multiples of their length, so flush points fall on block ends
       if (k % K == 0 && k + K <= wl && !__any(L.active && v_now <= c.thr)) {
-        run_block32<OBS, K>(L, c, split, nd, k, wnd, impact_exit);
-        k += K;
+        // past every lane's dead time, in a form no later block changes, one
+        // speed representation in the wavefront: a run of blocks.  Without an
+        // obstacle only (measured: with one, the run's saved block start costs
+        // a wavefront per SIMD and the run loses to the single blocks)
+        const bool past = OBS == AEB_OBS_NONE && k + K > wnd;
+        const bool all_split = __all(split), no_split = __all(!split);
+        const bool steady_c = past && __all(!L.active || L.clamped);
+        const bool steady_f = past && !steady_c && __all(!L.active || L.free_lane);
+        const float tk = k >= nd ? c.tb : c.td;
+        if (steady_c && no_split) {
+          k = run_steady32<OBS, K, FORM_C, false>(L, c, tk, k, wl, impact_exit);
+        } else if (steady_c && all_split) {
+          k = run_steady32<OBS, K, FORM_C, true>(L, c, tk, k, wl, impact_exit);
+        } else if (steady_f && no_split) {
+          k = run_steady32<OBS, K, FORM_F, false>(L, c, tk, k, wl, impact_exit);
+        } else if (steady_f && all_split) {
+          k = run_steady32<OBS, K, FORM_F, true>(L, c, tk, k, wl, impact_exit);
+        } else {
+          run_block32<OBS, K>(L, c, split, nd, k, wnd, impact_exit);
+          k += K;
+        }
       } else if (KM > KS && k % KM == 0 && k + KM <= wl &&
                  !__any(L.active && v_now <= thr_m)) {
         run_block32<OBS, KM>(L, c, split, nd, k, wnd, impact_exit);

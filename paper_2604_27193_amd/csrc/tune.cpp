@@ -26,10 +26,10 @@ std::once_flag g_env_once;
 // [precision 0 FP64, 1 FP32C][obstacle none, stationary, lead]
 // defaults measured on MI355X (1,048,576-sample workloads, launch shapes
 // timed in one process, interleaved): FP64 256 threads and 4 persistent
-// wavefronts per SIMD, 64-step blocks with a stationary obstacle and 128-step
-// blocks otherwise; FP32C 64-step blocks, 256 threads, one pass
+// wavefronts per SIMD, 128-step blocks with an obstacle and 64-step blocks
+// without; FP32C 64-step blocks, 256 threads, one pass
 TuneCfg g_tab[2][3] = {
-    {{128, 256, 4}, {64, 256, 4}, {128, 256, 4}},
+    {{64, 256, 4}, {128, 256, 4}, {128, 256, 4}},
     {{64, 256, 0}, {64, 256, 0}, {64, 256, 0}},
 };
 
