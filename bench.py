@@ -11,9 +11,12 @@ One step = aeb_rollout (all samples) + aeb_reduce (counts, P(collision),
 moments, headways at 5/1/0.1 % risk, a 256-point risk curve, margin
 quantiles), timed as eager calls and as a recorded HIP graph of the same
 kernels (each replay recomputes everything and its statistics are collected
-before the next).  `value` is the FP64 rollouts/s of the faster of the two
-(the graph only if its statistics equal the eager ones); the FP32
-compensated form is timed the same way and reported beside it.
+before the next), and as two recorded graphs on two streams with their own
+outputs and scratch, step k+1 launched before step k is collected so that
+its prep and sort overlap step k's integration tail and reduction.  `value`
+is the FP64 rollouts/s of the fastest of the three among those whose
+statistics equal the eager ones; the FP32 compensated form is timed as eager
+calls and as one graph and reported beside it.
 
 Also printed: the rollout kernel's roofline position (vector-ALU bound,
 algorithmic flops = 11 per Euler step x the steps actually taken, FP64 vector
@@ -108,6 +111,34 @@ def time_graph_steps(B, torch, d, params, precision, out, steps, warmup):
     wall = time.perf_counter() - t0
     g.close()
     return wall, stats
+
+
+def time_graph_steps_two_streams(B, torch, d, params, precision, outs, steps, warmup):
+    """The recorded step on two streams, each with its own graph, outputs and
+    scratch: step k+1 is launched before step k is collected, so its prep and
+    sort overlap step k's integration tail and reduction.  Every step is still
+    a whole pass; returns the wall time of `steps` of them and the statistics
+    of the last (all must equal)."""
+    gs = [B.Graph(d, params=params, precision=precision, out=o, risk=RISK, margin_q=MARGIN_Q,
+                  grid=GRID) for o in outs]
+    ss = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for k in range(max(warmup, 2)):
+        gs[k % 2].launch(ss[k % 2])
+        gs[k % 2].finish(ss[k % 2])
+    torch.cuda.synchronize()
+    every = []
+    t0 = time.perf_counter()
+    gs[0].launch(ss[0])
+    for k in range(1, steps):
+        gs[k % 2].launch(ss[k % 2])
+        every.append(gs[(k - 1) % 2].finish(ss[(k - 1) % 2]))
+    every.append(gs[(steps - 1) % 2].finish(ss[(steps - 1) % 2]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for g in gs:
+        g.close()
+    all_equal = all(same_stats(every[-1], x) for x in every)
+    return wall, every[-1], all_equal
 
 
 def same_stats(a, b):
@@ -555,15 +586,25 @@ def main():
     wallg32, stg32 = time_graph_steps(B, torch, d, params, "fp32c", out32, args.steps,
                                       args.warmup)
     graph_equal = same_stats(st64, stg64) and same_stats(st32, stg32)
+    log("bench: recorded graphs on two streams")
+    out2 = B.alloc_outputs(n)
+    wallp64, stp64, p_same = time_graph_steps_two_streams(B, torch, d, params, "fp64",
+                                                          (out, out2), args.steps, args.warmup)
+    pipe_equal = p_same and same_stats(st64, stp64)
 
     kavg64 = float(np.mean(k64)) * 1e-3
     kavg32 = float(np.mean(k32)) * 1e-3
     flops64 = EULER_FLOPS_PER_STEP * steps_total
     achieved = flops64 / kavg64 / 1e12
-    # the step as a production caller repeats it: the recorded graph when it is
-    # faster and gives the same statistics, else the eager calls
-    use_graph = graph_equal and wallg64 < wall64
-    step_wall = wallg64 if use_graph else wall64
+    # the step as a production caller repeats it: the fastest of the eager
+    # calls, the recorded graph and the recorded graphs on two streams, among
+    # those whose statistics equal the eager ones
+    paths = [("eager calls", wall64)]
+    if graph_equal:
+        paths.append(("recorded graph", wallg64))
+    if pipe_equal:
+        paths.append(("recorded graphs pipelined over two streams", wallp64))
+    step_path, step_wall = min(paths, key=lambda p: p[1])
     value = args.steps * n / step_wall
 
     rk4 = nsweep = study = perception = control = rare = None
@@ -617,7 +658,7 @@ def main():
                         "(host-drawn parameters resident in HBM), explicit Euler dt=1 ms "
                         "T=10 s; step = rollout + reduce",
             "n_samples": n, "integrator": "euler", "precision": "fp64",
-            "step_path": "recorded graph" if use_graph else "eager calls",
+            "step_path": step_path,
         },
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
@@ -634,6 +675,8 @@ def main():
             "eager_ms_per_step": wall64 / args.steps * 1e3,
             "graph_ms_per_step": wallg64 / args.steps * 1e3,
             "graph_stats_equal_eager": graph_equal,
+            "two_stream_graph_ms_per_step": wallp64 / args.steps * 1e3,
+            "two_stream_stats_equal_eager": pipe_equal,
             "kernel_ms": kavg64 * 1e3, "kernel_rollouts_per_s": n / kavg64,
             "rollout_call_ms": float(np.mean(c64)),
             "rollout_call_rollouts_per_s": n / (float(np.mean(c64)) * 1e-3),
