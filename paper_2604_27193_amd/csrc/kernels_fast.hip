@@ -418,10 +418,22 @@ __device__ inline int lane_lim(int k, int nd, int nmax) {
   return k < nd ? min(nd, nmax - 1) : nmax - 1;
 }
 
+// Minimum over the wavefront (every lane active), left in every lane: DPP row
+// shifts of 1, 2, 4, 8 lanes give each row's minimum in its lane 15, the row
+// broadcasts of lanes 15 and 31 carry it to lane 63.  Register moves, no LDS.
+template <int CTRL, int ROW_MASK>
+__device__ inline int dpp_min(int x) {
+  return min(x, __builtin_amdgcn_update_dpp(INT_MAX, x, CTRL, ROW_MASK, 0xf, false));
+}
+
 __device__ inline int wave_min(int x) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) x = min(x, __shfl_xor(x, o));
-  return __builtin_amdgcn_readfirstlane(x);
+  x = dpp_min<0x111, 0xf>(x);  // row_shr:1
+  x = dpp_min<0x112, 0xf>(x);  // row_shr:2
+  x = dpp_min<0x114, 0xf>(x);  // row_shr:4
+  x = dpp_min<0x118, 0xf>(x);  // row_shr:8
+  x = dpp_min<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+  x = dpp_min<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+  return __builtin_amdgcn_readlane(x, 63);
 }
 
 // varnd: nd or nmax differ between lanes (a batch, or per-sample command steps)

@@ -82,8 +82,10 @@ __device__ inline int ctl_want(const CtlArgs& A, uint64_t index, uint32_t tick, 
   const U2 u = uniform2(A.seed, A.sid, index, AEB_SLOT_CONTROL, tick);
   const double r = sqrt(-2.0 * log(u.a));
   const double ang = 6.283185307179586 * u.b;
-  const double g = gap_true + A.noise_gap * (r * cos(ang));
-  const double cl = closing + A.noise_v * (r * sin(ang));
+  double sn, cs;
+  sincos(ang, &sn, &cs);  // one argument reduction for both (the same bits as cos and sin)
+  const double g = gap_true + A.noise_gap * (r * cs);
+  const double cl = closing + A.noise_v * (r * sn);
   const double ttc = cl > 0.0 ? g / cl : INFINITY;
   return ttc < A.ttc_brake ? 2 : (ttc < A.ttc_warn ? 1 : 0);
 }
