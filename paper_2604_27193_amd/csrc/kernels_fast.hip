@@ -582,7 +582,7 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
   // block ladder as a lane approaches its stop: K steps, then KM, then KS,
   // then single checked steps (a level runs while no lane can stop inside it)
   constexpr int KS = 4;
-  constexpr int KM = K >= 64 ? 16 : KS;
+  constexpr int KM = K > 16 ? 16 : KS;
   // with the controller, decisions every few tens of steps leave short
   // remainders: a 2-step level before the single steps
   constexpr int K2 = CTL ? 2 : KS;
@@ -1574,14 +1574,15 @@ int integrate(const aeb_scenario& s0, int precision, const Bufs& b, int64_t n, c
   const Shape sh = shape(t, n);
   if (!BATCH && control_on(s0)) {
     // the controller decides every ctl_period: blocks stay within a decision
-    // period, so the 64-step level rarely runs; FP64 only
+    // period, so the top level is 48 steps (a 50-step period, 20 Hz at 1 ms,
+    // takes one 48-step and one 2-step block); FP64 only
     timing_begin(st);
     if (s0.integrator == AEB_RK4)
       go64<AEB_OBS_STATIONARY, 16, false, AEB_RK4, true>(sh, b, n, ctx, st);
     else if (obs == AEB_OBS_LEAD)
-      go64<AEB_OBS_LEAD, 64, false, AEB_EULER, true>(sh, b, n, ctx, st);
+      go64<AEB_OBS_LEAD, 48, false, AEB_EULER, true>(sh, b, n, ctx, st);
     else
-      go64<AEB_OBS_STATIONARY, 64, false, AEB_EULER, true>(sh, b, n, ctx, st);
+      go64<AEB_OBS_STATIONARY, 48, false, AEB_EULER, true>(sh, b, n, ctx, st);
     timing_end(st);
     AEB_HIP(hipGetLastError());
     return AEB_OK;
