@@ -555,6 +555,7 @@ __device__ inline int run_steady(Lane64& L, const Job& J, double al, double dt, 
       block64<FORM, 16, LEAD, INTEG>(L.s, L.l, J, al, dt, cmd);
       asm volatile("" : "+v"(L.s.x));
     }
+    if (K % 16 != 0) block64<FORM, K % 16, LEAD, INTEG>(L.s, L.l, J, al, dt, cmd);
     if (INTEG == AEB_RK4 && L.active) xmax = fmax(xmax, L.s.x);
     bool hit = false;
     if (OBS == AEB_OBS_STATIONARY) hit = L.active && !L.collided && L.s.x > J.gap;
@@ -1573,16 +1574,22 @@ int integrate(const aeb_scenario& s0, int precision, const Bufs& b, int64_t n, c
   const TuneCfg t = tune_get(precision == AEB_FP64 ? AEB_FP64 : AEB_FP32C, obs);
   const Shape sh = shape(t, n);
   if (!BATCH && control_on(s0)) {
-    // the controller decides every ctl_period: blocks stay within a decision
-    // period, so the top level is 48 steps (a 50-step period, 20 Hz at 1 ms,
-    // takes one 48-step and one 2-step block); FP64 only
+    // the controller decides every ctl_period and blocks stay within a
+    // decision period: the top level is a block size that divides the period
+    // where one is built (50 steps: 20 and 10 Hz at 1 ms; 40: 25 Hz), else 48
+    // (a 50-step period would take a 48-step and a 2-step block); FP64 only
+    const int64_t per = ctl_args(s0).period;
     timing_begin(st);
     if (s0.integrator == AEB_RK4)
       go64<AEB_OBS_STATIONARY, 16, false, AEB_RK4, true>(sh, b, n, ctx, st);
     else if (obs == AEB_OBS_LEAD)
-      go64<AEB_OBS_LEAD, 48, false, AEB_EULER, true>(sh, b, n, ctx, st);
+      per % 50 == 0   ? go64<AEB_OBS_LEAD, 50, false, AEB_EULER, true>(sh, b, n, ctx, st)
+      : per % 40 == 0 ? go64<AEB_OBS_LEAD, 40, false, AEB_EULER, true>(sh, b, n, ctx, st)
+                      : go64<AEB_OBS_LEAD, 48, false, AEB_EULER, true>(sh, b, n, ctx, st);
     else
-      go64<AEB_OBS_STATIONARY, 48, false, AEB_EULER, true>(sh, b, n, ctx, st);
+      per % 50 == 0   ? go64<AEB_OBS_STATIONARY, 50, false, AEB_EULER, true>(sh, b, n, ctx, st)
+      : per % 40 == 0 ? go64<AEB_OBS_STATIONARY, 40, false, AEB_EULER, true>(sh, b, n, ctx, st)
+                      : go64<AEB_OBS_STATIONARY, 48, false, AEB_EULER, true>(sh, b, n, ctx, st);
     timing_end(st);
     AEB_HIP(hipGetLastError());
     return AEB_OK;

@@ -38,6 +38,11 @@ def variants():
         "dead_30ms_one_stage": W.closed_loop(3000, ttc_warn=0.0, dead_time=0.03),
         "dead_30ms": W.closed_loop(3000, dead_time=0.03),
         "period_1ms": W.closed_loop(1500, ctl_period=0.001),
+        # the top block size follows the decision period: 40, 50 and 48 steps
+        "period_40ms": W.closed_loop(2000, ctl_period=0.04),
+        "period_100ms": W.closed_loop(2000, ctl_period=0.1),
+        "period_30ms": W.closed_loop(2000, ctl_period=0.03),
+        "lead_period_40ms": dict(W.sweep(n=2000)[60], horizon=15.0, **dict(CTL, ctl_period=0.04)),
         "rk4": W.closed_loop(1500, integrator="rk4"),
         "nofma": W.closed_loop(2000, nofma=True),
         "lead": dict(W.sweep(n=3000)[100], horizon=15.0, **CTL),
