@@ -40,12 +40,15 @@ namespace aeb {
 namespace {
 
 constexpr int NBINS = 8192;  // sort keys: 64 coarse x 2 classes x 64 fine
-constexpr int PREP_BLOCK = 1024;
-constexpr int PREP_PER = 4;       // samples per thread in scatter (and plain prep)
-constexpr int PREP_SAMPLES = PREP_BLOCK * PREP_PER;  // samples per prep/scatter block
-// drawing the parameters needs more registers: half the threads, twice the samples each
+// The sort's kernels (prep, scan, scatter) run in workgroups of one wavefront
+// per SIMD: beside a running integration kernel (four wavefronts per SIMD)
+// each CU has room for one such workgroup, so the next launch's preparation
+// overlaps the current integration when launches are pipelined on two streams.
+constexpr int PREP_BLOCK = 256;
+constexpr int PREP_SAMPLES = 4096;                     // samples per prep/scatter block
+constexpr int PREP_PER = PREP_SAMPLES / PREP_BLOCK;    // samples per thread
 template <bool DEVRNG>
-constexpr int prep_threads() { return DEVRNG ? PREP_BLOCK / 2 : PREP_BLOCK; }
+constexpr int prep_threads() { return PREP_BLOCK; }
 
 // Closed-form estimate of the stopping time (s): dead time at zero brake,
 // first-order ramp of the brake to the friction limit (or to the command),
@@ -196,10 +199,10 @@ __global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job
 
 // exclusive scan of the key histogram into bucket offsets (one block); also
 // clears the integration kernel's chunk counter
-__global__ __launch_bounds__(1024) void k_scan(uint32_t* hist, unsigned long long* counter) {
+__global__ __launch_bounds__(PREP_BLOCK) void k_scan(uint32_t* hist, unsigned long long* counter) {
   if (threadIdx.x == 0) *counter = 0ull;
-  __shared__ uint32_t part[1024];
-  constexpr int PER = NBINS / 1024;
+  __shared__ uint32_t part[PREP_BLOCK];
+  constexpr int PER = NBINS / PREP_BLOCK;
   uint32_t loc[PER];
   uint32_t sum = 0;
   for (int j = 0; j < PER; ++j) {
@@ -208,7 +211,7 @@ __global__ __launch_bounds__(1024) void k_scan(uint32_t* hist, unsigned long lon
   }
   part[threadIdx.x] = sum;
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
+  for (int off = 1; off < PREP_BLOCK; off <<= 1) {
     uint32_t v = threadIdx.x >= static_cast<unsigned>(off) ? part[threadIdx.x - off] : 0u;
     __syncthreads();
     part[threadIdx.x] += v;
@@ -1531,7 +1534,7 @@ int scratch_bufs(int64_t n, int n_scn, bool lead, hipStream_t st, Bufs& b) {
 // sort the prepared keys into the permutation (the scan zeroes the claim counter)
 void sort_keys(const Bufs& b, int64_t n, hipStream_t st) {
   const unsigned pblk = static_cast<unsigned>((n + PREP_SAMPLES - 1) / PREP_SAMPLES);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, b.hist, b.counter);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(PREP_BLOCK), 0, st, b.hist, b.counter);
   hipLaunchKernelGGL(k_scatter, dim3(pblk), dim3(PREP_BLOCK), 0, st, b.keys, n, b.hist, b.perm);
 }
 
@@ -1680,7 +1683,7 @@ int launch_rollout_fast_into(const aeb_scenario& s, const ParamSrc* src, int pre
     hipLaunchKernelGGL((k_prep<false, false>), dim3(pblk), dim3(PREP_BLOCK), 0, st, pa, b.jobs,
                        b.leads, b.keys, b.hist);
   else
-    hipLaunchKernelGGL((k_prep<true, false>), dim3(pblk), dim3(PREP_BLOCK / 2), 0, st, pa, b.jobs,
+    hipLaunchKernelGGL((k_prep<true, false>), dim3(pblk), dim3(PREP_BLOCK), 0, st, pa, b.jobs,
                        b.leads, b.keys, b.hist);
   sort_keys(b, n, st);
   Ctx ctx{};
@@ -1747,7 +1750,7 @@ int launch_batch_fast_into(const aeb_scenario* scns, int n_scn, int precision,
   bool perc = false;
   for (int j = 0; j < n_scn; ++j) perc = perc || perception_on(scns[j]);
   pa.nds = perc ? b.nds : nullptr;
-  hipLaunchKernelGGL((k_prep<true, true>), dim3(pblk), dim3(PREP_BLOCK / 2), 0, st, pa, b.jobs,
+  hipLaunchKernelGGL((k_prep<true, true>), dim3(pblk), dim3(PREP_BLOCK), 0, st, pa, b.jobs,
                      b.leads, b.keys, b.hist);
   sort_keys(b, total, st);
   Ctx ctx{};
