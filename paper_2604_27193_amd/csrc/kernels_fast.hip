@@ -1057,23 +1057,20 @@ __global__ __launch_bounds__(256) void k_roll_fp32c(const Job* __restrict__ jobs
       const float v_now = speed32<true>(L.s);
       // blocks start on multiples of their length, so flush points fall on block ends
       if (k % K == 0 && k + K <= wl && !__any(L.active && v_now <= c.thr)) {
-        // past every lane's dead time, in a form no later block changes, one
-        // speed representation in the wavefront: a run of blocks.  Without an
-        // obstacle only (measured: with one, the run's saved block start costs
-        // a wavefront per SIMD and the run loses to the single blocks)
+        // past every lane's dead time, in a form no later block changes, no
+        // lane with the compensated speed: a run of blocks.  Without an
+        // obstacle only (measured: with one the run loses to single blocks,
+        // and runs for compensated-speed lanes cost more registers than they
+        // save)
         const bool past = OBS == AEB_OBS_NONE && k + K > wnd;
-        const bool all_split = __all(split), no_split = __all(!split);
+        const bool no_split = __all(!split);
         const bool steady_c = past && __all(!L.active || L.clamped);
         const bool steady_f = past && !steady_c && __all(!L.active || L.free_lane);
         const float tk = k >= nd ? c.tb : c.td;
         if (steady_c && no_split) {
           k = run_steady32<OBS, K, FORM_C, false>(L, c, tk, k, wl, impact_exit);
-        } else if (steady_c && all_split) {
-          k = run_steady32<OBS, K, FORM_C, true>(L, c, tk, k, wl, impact_exit);
         } else if (steady_f && no_split) {
           k = run_steady32<OBS, K, FORM_F, false>(L, c, tk, k, wl, impact_exit);
-        } else if (steady_f && all_split) {
-          k = run_steady32<OBS, K, FORM_F, true>(L, c, tk, k, wl, impact_exit);
         } else {
           run_block32<OBS, K>(L, c, split, nd, k, wnd, impact_exit);
           k += K;
