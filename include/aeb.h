@@ -27,6 +27,10 @@
  *   - All functions act on the HIP device that is current on the calling thread.
  *   - The library keeps a per-device scratch arena for sorting and reduction
  *     partials; it grows on demand (hipMalloc) and lives until process exit.
+ *     Calls that use it (aeb_rollout, aeb_reduce, aeb_batch_rollout) share it
+ *     across streams: work of two such calls in flight at once on different
+ *     streams of one device races.  For concurrent launches use recorded
+ *     graphs (each owns its scratch) or the server (per-stream scratch).
  */
 #ifndef AEB_H
 #define AEB_H

@@ -117,3 +117,28 @@ def test_graph_rejects(B):
     with pytest.raises(B.AebError) as e:
         B.Graph(W.single(100), precision="fp32c_fixup")
     assert e.value.code == B.EINVAL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_two_graphs_pipelined_on_two_streams(B, prec):
+    """Two graphs of one scenario (own outputs and scratch each) replayed on
+    two streams with step k+1 launched before step k is collected, as the
+    benchmark's throughput loop runs them: every step's outputs and
+    statistics equal the eager call's."""
+    import torch
+    d = W.single(60000, seed=21, scenario_id=4)
+    ref_out = B.rollout(d, precision=prec)
+    ref_st = B.reduce(ref_out, risk=RISK, margin_q=MQ, grid=GRID)
+    ref = host(ref_out)
+    gs = [B.Graph(d, precision=prec, risk=RISK, margin_q=MQ, grid=GRID) for _ in range(2)]
+    ss = [torch.cuda.Stream(), torch.cuda.Stream()]
+    steps = 6
+    gs[0].launch(ss[0])
+    for k in range(1, steps + 1):
+        if k < steps:
+            gs[k % 2].launch(ss[k % 2])
+        j = (k - 1) % 2
+        same_stats(ref_st, gs[j].finish(ss[j]))
+        same_out(ref, host(gs[j].out))
+    for g in gs:
+        g.close()
