@@ -37,6 +37,9 @@ struct ScnDev {
 
 enum { FORM_G = 0, FORM_F = 1, FORM_C = 2, FORM_D = 3 };
 
+// horizon plus dead time, in steps, that the block path accepts
+constexpr int64_t BLOCK_STEP_MAX = 0x7fffffffLL - 4096;
+bool block_steps_ok(const aeb_scenario& s);
 bool fast_path_applies(const aeb_scenario& s, int precision);
 int launch_rollout_fast(const aeb_scenario& s, const ParamSrc* src, int precision,
                         const OutCols& out, int64_t n, hipStream_t st);

@@ -190,9 +190,11 @@ int aeb_graph_create_batch(const aeb_scenario* scns, int n_scn, int precision,
         scns[j].impact_exit != scns[0].impact_exit || scns[j].nofma != scns[0].nofma)
       return fail(AEB_EINVAL, "batched scenarios must share integrator, obstacle, impact_exit, nofma");
   }
-  if (!fast_path_applies(scns[0], precision) || control_on(scns[0]))
-    return fail(AEB_EINVAL, "batched graphs record the batched block-structured path (not the "
-                            "unfused Euler form, not RK4 in FP32C, not the closed-loop controller)");
+  for (int j = 0; j < n_scn; ++j)
+    if (!fast_path_applies(scns[j], precision) || control_on(scns[j]))
+      return fail(AEB_EINVAL, "batched graphs record the batched block-structured path (not the "
+                              "unfused Euler form, not RK4 in FP32C, not the closed-loop "
+                              "controller, at most 2^31 - 4096 steps)");
   aeb_graph* g = new (std::nothrow) aeb_graph;
   if (!g) return fail(AEB_ENOMEM, "host allocation failed");
   for (int j = 0; j < n_scn; ++j) {

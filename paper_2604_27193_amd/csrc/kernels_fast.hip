@@ -1440,7 +1440,15 @@ __global__ __launch_bounds__(256) void k_roll_fp32c_lead(const Job* __restrict__
 
 }  // namespace
 
+// The block path counts steps in int and tests k + (block length) and
+// k + (command delay): the horizon and the dead time together stay this far
+// below 2^31 (longer runs take the checked FP64 kernel, which counts in 64 bits).
+bool block_steps_ok(const aeb_scenario& s) {
+  return horizon_steps(s) + dead_steps(s) <= BLOCK_STEP_MAX;
+}
+
 bool fast_path_applies(const aeb_scenario& s, int precision) {
+  if (!block_steps_ok(s)) return false;
   // the controller: FP64 explicit Euler (fused form) or RK4 only
   if (control_on(s)) return precision == AEB_FP64 && (s.integrator == AEB_RK4 || !s.nofma);
   if (precision == AEB_FP64)
@@ -1660,7 +1668,8 @@ size_t rollout_scratch_bytes(const aeb_scenario& s, int64_t n) {
 int launch_rollout_fast_into(const aeb_scenario& s, const ParamSrc* src, int precision,
                              const OutCols& out, int64_t n, void* scratch_base, hipStream_t st) {
   const int64_t nd = dead_steps(s), nmax = horizon_steps(s);
-  if (nmax > 0x7fffffff || nd > 0x7fffffff) return fail(AEB_EINVAL, "step counts beyond 2^31");
+  if (!block_steps_ok(s))
+    return fail(AEB_EINVAL, "horizon plus dead time beyond 2^31 - 4096 steps on the block path");
   const bool lead = s.obstacle == AEB_OBS_LEAD;
   Bufs b;
   bufs_layout(n, 0, lead, static_cast<char*>(scratch_base), &b);
@@ -1712,7 +1721,8 @@ int fill_batch_table(const aeb_scenario* scns, int n_scn, const OutCols* outs, S
   int64_t total = 0, cap = 1;
   for (int j = 0; j < n_scn; ++j) {
     const int64_t nd = dead_steps(scns[j]), nmax = horizon_steps(scns[j]);
-    if (nmax > 0x7fffffff || nd > 0x7fffffff) return fail(AEB_EINVAL, "step counts beyond 2^31");
+    if (!block_steps_ok(scns[j]))
+      return fail(AEB_EINVAL, "horizon plus dead time beyond 2^31 - 4096 steps on the block path");
     tab[j].dt = scns[j].dt;
     tab[j].a_cmd = scns[j].a_cmd;
     tab[j].nd = static_cast<int>(nd);

@@ -152,9 +152,10 @@ int launch_fixup(const aeb_scenario& s, const ParamSrc* src, const OutCols& out,
 // form, the closed-loop controller, the fix-up mode) run scenario by scenario.
 int launch_batch(const aeb_scenario* scns, int n_scn, int precision, const OutCols* outs,
                  hipStream_t st) {
-  if (fast_path_applies(scns[0], precision) && precision != AEB_FP32C_FIXUP &&
-      !control_on(scns[0]))
-    return launch_batch_fast(scns, n_scn, precision, outs, st);
+  bool fast = precision != AEB_FP32C_FIXUP;
+  for (int j = 0; j < n_scn && fast; ++j)
+    fast = fast_path_applies(scns[j], precision) && !control_on(scns[j]);
+  if (fast) return launch_batch_fast(scns, n_scn, precision, outs, st);
   for (int j = 0; j < n_scn; ++j) {
     const int rc = launch_rollout(scns[j], nullptr, precision, outs[j], scns[j].n_samples, st);
     if (rc != AEB_OK) return rc;
@@ -168,8 +169,10 @@ int launch_rollout(const aeb_scenario& s, const ParamSrc* src, int precision, co
   if (fast_path_applies(s, precision)) return launch_rollout_fast(s, src, precision, out, n, st);
   if (control_on(s)) return go_control(s, src, precision, out, n, nd, nmax, st);
   if (precision == AEB_FP32C || precision == AEB_FP32C_FIXUP) {
-    // every Euler case takes the block-structured path
-    return fail(AEB_EINVAL, "the FP32 compensated form is available for the Euler integrator");
+    // every Euler case within the block path's step limit takes it
+    return fail(AEB_EINVAL,
+                "the FP32 compensated form needs the explicit Euler integrator and a horizon "
+                "plus dead time below 2^31 - 4096 steps");
   } else if (s.integrator == AEB_RK4) {
     timing_begin(st);
     if (s.obstacle == AEB_OBS_NONE)

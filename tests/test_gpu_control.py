@@ -118,6 +118,23 @@ def test_refusals(B):
     with pytest.raises(B.AebError) as e:
         B.Graph([d, d], batch=True)
     assert e.value.code == B.EINVAL
+    # the controller in any scenario of a batched graph, not only the first
+    with pytest.raises(B.AebError) as e:
+        B.Graph([W.single(100), d], batch=True)
+    assert e.value.code == B.EINVAL
+
+
+def test_mixed_batch_open_and_closed_loop(B, orc):
+    """A batch whose second scenario has the controller runs scenario by
+    scenario; each result equals the reference and the scenario alone."""
+    scns = [W.single(1200, seed=3, scenario_id=1), W.closed_loop(1200, seed=4, scenario_id=2)]
+    outs = B.batch_rollout(scns)
+    for d, o in zip(scns, outs):
+        got = to_np(o)
+        check_fp64(got, orc.run(d))
+        alone = to_np(B.rollout(d))
+        for c in got:
+            assert np.array_equal(got[c], alone[c]), c
 
 
 def test_graph_replays_equal_eager(B):

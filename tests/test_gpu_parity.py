@@ -340,3 +340,16 @@ def test_reduce_on_synthetic(B, orc, n, seed):
     got = B.reduce(upload(syn), risk=RISK, margin_q=MQ, grid=GRID)
     want = orc.reduce(syn, risk=RISK, margin_q=MQ, grid=GRID)
     compare_stats(got, want)
+
+
+def test_horizon_beyond_block_path_limit(B, orc):
+    """A horizon of 2,147,483,000 steps (within the 2^31 - 1 validation
+    bound, beyond the block path's 2^31 - 4096): FP64 takes the checked
+    kernel, which counts steps in 64 bits, and matches the reference (every
+    sample stops long before the horizon); FP32C and a recorded graph say no."""
+    d = W.single(1500, seed=8, horizon=2147483.0)
+    check_fp64(to_np(plain(B, d)), orc.run(d), exact=True)
+    with pytest.raises(B.AebError, match="2\\^31 - 4096"):
+        B.rollout(d, precision="fp32c")
+    with pytest.raises(B.AebError):
+        B.Graph(d)
