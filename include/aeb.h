@@ -284,7 +284,10 @@ int aeb_sample_params(const aeb_scenario* scn, int64_t first, int64_t count, con
  *     recomputed in FP64, so every collision flag is exact).  A scenario with
  *     the closed-loop controller takes AEB_FP64 only (AEB_EINVAL otherwise):
  *     the block-structured path with blocks that end at every decision, or,
- *     for the unfused Euler form, one checked lane per sample.
+ *     for the unfused Euler form, one checked lane per sample.  The
+ *     block-structured path counts steps in 32 bits: a horizon plus dead time
+ *     beyond 2^31 - 4096 steps takes the checked FP64 kernel (AEB_FP32C:
+ *     AEB_EINVAL).
  *   out: device output columns with out->n == n_samples.
  * Asynchronous on `stream`.  May grow the scratch arena on first use. */
 int aeb_rollout(const aeb_scenario* scn, const aeb_params* params, int precision,
@@ -362,8 +365,9 @@ int aeb_autotune(const aeb_scenario* calib, int precision, const char* cache_pat
  * scratch (allocated at creation) and, for batches, pinned copies of the
  * scenario tables.  Only the sorted block-structured path is recorded: FP64
  * explicit Euler (fused form) or RK4, FP32C explicit Euler; AEB_EINVAL for
- * the unfused Euler form (nofma), the FP32C fix-up mode, and the closed-loop
- * controller in FP32C or in batched graphs. */
+ * the unfused Euler form (nofma), the FP32C fix-up mode, the closed-loop
+ * controller in FP32C or in batched graphs (in any of their scenarios), and
+ * a horizon plus dead time beyond 2^31 - 4096 steps. */
 typedef struct aeb_graph aeb_graph;
 
 /* One scenario: params (device columns, or NULL for the in-kernel generator),

@@ -124,7 +124,8 @@ class HipExecutor final : public serve::Executor {
     if (!fast_path_applies(s, cfg_.precision) || control_on(s))
       return fail(AEB_EINVAL,
                   "serving runs the batched block-structured path (not the unfused Euler "
-                  "form, not RK4 in FP32C, not the closed-loop controller)");
+                  "form, not RK4 in FP32C, not the closed-loop controller, at most "
+                  "2^31 - 4096 steps)");
     return AEB_OK;
   }
 
