@@ -127,6 +127,25 @@ def test_full_size_sampled(B, orc):
     assert rel_err(dev["dist"], got["dist"]).max() <= 1e-12
 
 
+def test_fp32c_full_size_error_budget(B):
+    """1,048,576 samples with perception: the FP32 compensated distances stay
+    within 1e-4 of FP64 everywhere, flags agree outside the boundary band, the
+    band holds under 0.1 % of the samples, and the fix-up mode leaves every flag
+    equal to FP64."""
+    from test_gpu_parity import REL32, B_BOUNDARY
+    d = W.perception(1_048_576)
+    params = upload(B.sample_params(d, device=False))
+    g64 = to_np(B.rollout(d, params=params))
+    g32 = to_np(B.rollout(d, params=params, precision="fp32c"))
+    rel = rel_err(g32["dist"], g64["dist"])
+    assert rel.max() <= REL32, rel.max()
+    bnd = (g32["status"] & B_BOUNDARY) != 0
+    assert np.array_equal((g32["status"] & 7)[~bnd], (g64["status"] & 7)[~bnd])
+    assert bnd.sum() < 1e-3 * d["n_samples"]
+    fix = to_np(B.rollout(d, params=params, precision="fp32c_fixup"))
+    assert np.array_equal(fix["status"] & 7, g64["status"] & 7)
+
+
 def test_batch_mixed_with_and_without_perception(B, orc):
     scns = []
     for j, d in enumerate(W.uneven_batch(6, max_samples=2500)):
