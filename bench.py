@@ -690,6 +690,13 @@ def main():
             "kernel_rollouts_per_s": n / kavg32,
             "rollout_call_ms": float(np.mean(c32)),
             "achieved_tflops": FP32C_FLOPS_PER_STEP * steps32 / kavg32 / 1e12,
+            # the build disables packed FP32 instructions, so FP32 issues at the
+            # unpacked rate (the FP64 rate, 78.6 TFLOP/s), half the packed peak
+            "peak_tflops_unpacked_fp32": FP64_VECTOR_PEAK_TFLOPS,
+            "frac_unpacked_fp32_peak": FP32C_FLOPS_PER_STEP * steps32 / kavg32 / 1e12
+                                       / FP64_VECTOR_PEAK_TFLOPS,
+            "frac_packed_fp32_peak": FP32C_FLOPS_PER_STEP * steps32 / kavg32 / 1e12
+                                     / FP32_VECTOR_PEAK_TFLOPS,
             "max_rel_dist_err_vs_fp64": rel32,
             "boundary_samples": int(inband.sum()),
             "collision_flags_equal_fp64_outside_band": flags_equal,
