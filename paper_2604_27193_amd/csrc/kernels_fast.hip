@@ -314,8 +314,22 @@ __device__ inline void rk4_step(St64& s, const Job& J, double dt, double h2, dou
   }
 }
 
+// Kernel tag of explicit Euler in the unfused form (the paper's rule of no
+// fused operations): every a*b + c below a rounded product, then a rounded sum.
+constexpr int EULER_NOFMA = 2;
+
+// a*b + c: one fused multiply-add, or (unfused) a rounded product and a
+// rounded sum (the build contracts nothing implicitly).  The canonical step's
+// (abe - kd v v) and vl - dt al equal abe + (-kd)(v v) and vl + (-dt) al bit
+// for bit (negation is exact), so one form serves both.
+template <bool NF>
+__device__ inline double mad(double a, double b, double c) {
+  return NF ? a * b + c : fma(a, b, c);
+}
+
 template <int FORM, int K, bool LEAD, int INTEG = AEB_EULER>
 __device__ inline void block64(St64& s, Ld64& l, const Job& J, double al, double dt, double cmd) {
+  constexpr bool NF = INTEG == EULER_NOFMA;
   if (INTEG == AEB_RK4) {
     const double h2 = 0.5 * dt, h6 = dt / 6.0;
 #pragma unroll
@@ -327,40 +341,44 @@ __device__ inline void block64(St64& s, Ld64& l, const Job& J, double al, double
     const double q = s.v * s.v;
     double acc;
     if (FORM == FORM_G) {
-      acc = fma(J.nkd, q, fmax(s.a, J.alim)) - J.c;
-      s.a = fma(J.kt, cmd - s.a, s.a);
+      acc = mad<NF>(J.nkd, q, fmax(s.a, J.alim)) - J.c;
+      s.a = mad<NF>(J.kt, cmd - s.a, s.a);
     } else if (FORM == FORM_F) {
-      acc = fma(J.nkd, q, s.a) - J.c;
-      s.a = fma(J.kt, cmd - s.a, s.a);
+      acc = mad<NF>(J.nkd, q, s.a) - J.c;
+      s.a = mad<NF>(J.kt, cmd - s.a, s.a);
     } else if (FORM == FORM_C) {
-      acc = fma(J.nkd, q, J.alim) - J.c;
+      acc = mad<NF>(J.nkd, q, J.alim) - J.c;
     } else {  // FORM_D
-      acc = fma(J.nkd, q, 0.0) - J.c;
+      acc = mad<NF>(J.nkd, q, 0.0) - J.c;
     }
-    s.x = fma(dt, s.v, s.x);
-    s.v = fma(dt, acc, s.v);
+    s.x = mad<NF>(dt, s.v, s.x);
+    s.v = mad<NF>(dt, acc, s.v);
     if (LEAD) {
-      l.xl = fma(dt, l.vl, l.xl);
-      l.vl = fmax(fma(-dt, al, l.vl), 0.0);
+      l.xl = mad<NF>(dt, l.vl, l.xl);
+      l.vl = fmax(mad<NF>(-dt, al, l.vl), 0.0);
       l.gmin = fmin(l.gmin, (J.gap + l.xl) - s.x);
     }
+    // unfused: each step's position sum happens at its step (else the
+    // compiler defers the sums and holds every step's product in a register)
+    if (NF) asm volatile("" : "+v"(s.x));
   }
 }
 
 template <bool LEAD, int INTEG = AEB_EULER>
 __device__ inline void step64(St64& s, Ld64& l, const Job& J, double al, double dt, double cmd) {
+  constexpr bool NF = INTEG == EULER_NOFMA;
   if (INTEG == AEB_RK4) {
     rk4_step<FORM_G>(s, J, dt, 0.5 * dt, dt / 6.0, cmd);
     return;
   }
   const double q = s.v * s.v;
-  const double acc = fma(J.nkd, q, fmax(s.a, J.alim)) - J.c;
-  s.a = fma(J.kt, cmd - s.a, s.a);
-  s.x = fma(dt, s.v, s.x);
-  s.v = fma(dt, acc, s.v);
+  const double acc = mad<NF>(J.nkd, q, fmax(s.a, J.alim)) - J.c;
+  s.a = mad<NF>(J.kt, cmd - s.a, s.a);
+  s.x = mad<NF>(dt, s.v, s.x);
+  s.v = mad<NF>(dt, acc, s.v);
   if (LEAD) {
-    l.xl = fma(dt, l.vl, l.xl);
-    l.vl = fmax(fma(-dt, al, l.vl), 0.0);
+    l.xl = mad<NF>(dt, l.vl, l.xl);
+    l.vl = fmax(mad<NF>(-dt, al, l.vl), 0.0);
   }
 }
 
@@ -1451,8 +1469,9 @@ bool fast_path_applies(const aeb_scenario& s, int precision) {
   if (!block_steps_ok(s)) return false;
   // the controller: FP64 explicit Euler (fused form) or RK4 only
   if (control_on(s)) return precision == AEB_FP64 && (s.integrator == AEB_RK4 || !s.nofma);
-  if (precision == AEB_FP64)
-    return s.integrator == AEB_RK4 ? s.obstacle != AEB_OBS_LEAD : !s.nofma;
+  // (RK4 has no lead vehicle; the unfused Euler form with one would not fit
+  // the registers and takes the checked kernel)
+  if (precision == AEB_FP64) return s.obstacle != AEB_OBS_LEAD || !(s.integrator == AEB_RK4 || s.nofma);
   if (s.integrator != AEB_EULER) return false;
   return precision == AEB_FP32C || precision == AEB_FP32C_FIXUP;
 }
@@ -1609,6 +1628,18 @@ int integrate(const aeb_scenario& s0, int precision, const Bufs& b, int64_t n, c
       go64<AEB_OBS_STATIONARY, 16, BATCH, AEB_RK4>(sh, b, n, ctx, st);
     else
       go64<AEB_OBS_NONE, 16, BATCH, AEB_RK4>(sh, b, n, ctx, st);
+    timing_end(st);
+    AEB_HIP(hipGetLastError());
+    return AEB_OK;
+  }
+  if (precision == AEB_FP64 && s0.nofma) {
+    // the unfused form (no lead vehicle: fast_path_applies): 128-step blocks,
+    // the launch shape of the table
+    timing_begin(st);
+    if (obs == AEB_OBS_STATIONARY)
+      go64<AEB_OBS_STATIONARY, 128, BATCH, EULER_NOFMA>(sh, b, n, ctx, st);
+    else
+      go64<AEB_OBS_NONE, 128, BATCH, EULER_NOFMA>(sh, b, n, ctx, st);
     timing_end(st);
     AEB_HIP(hipGetLastError());
     return AEB_OK;

@@ -82,7 +82,8 @@ __global__ __launch_bounds__(256) void k_fixup_fp64(aeb_scenario s, ParamSrc src
     int64_t i = fix[1 + j];
     Lane L = load_lane<DEVRNG>(s, src, i);
     const int64_t ndl = perception_on(s) ? command_step(s, L.trig, nmax) : nd;
-    Result r = euler_fp64<OBS, false>(L, s.dt, s.a_cmd, ndl, nmax, s.impact_exit);
+    Result r = s.nofma ? euler_fp64<OBS, true>(L, s.dt, s.a_cmd, ndl, nmax, s.impact_exit)
+                       : euler_fp64<OBS, false>(L, s.dt, s.a_cmd, ndl, nmax, s.impact_exit);
     store(out, i, r);
   }
 }

@@ -168,7 +168,8 @@ int aeb_autotune(const aeb_scenario* calib, int precision, const char* cache_pat
   if (rc != AEB_OK) return rc;
   if (precision != AEB_FP64 && precision != AEB_FP32C)
     return fail(AEB_EINVAL, "aeb_autotune: precision must be AEB_FP64 or AEB_FP32C");
-  if (!fast_path_applies(*calib, precision) || control_on(*calib))
+  if (!fast_path_applies(*calib, precision) || control_on(*calib) ||
+      (precision == AEB_FP64 && calib->nofma))
     return fail(AEB_EINVAL, "aeb_autotune: the scenario does not take the tuned block-structured path");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t n = calib->n_samples;

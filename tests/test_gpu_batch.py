@@ -34,6 +34,19 @@ def test_batch_uneven_fp64(B, orc):
         check_fp64(to_np(o), orc.run(d))
 
 
+def test_batch_uneven_unfused(B, orc):
+    """The paper's rule of no fused operations in one batched launch: every
+    scenario equals the reference bit for bit and equals its launch alone."""
+    scns = [dict(d, nofma=True) for d in W.uneven_batch(12, max_samples=1500)]
+    outs = B.batch_rollout(scns)
+    for d, o in zip(scns, outs):
+        got = to_np(o)
+        check_fp64(got, orc.run(d))
+        alone = to_np(B.rollout(d))
+        for c in got:
+            assert np.array_equal(got[c], alone[c]), c
+
+
 def test_batch_uneven_fp32c(B, orc):
     scns = W.uneven_batch(24, max_samples=1200)
     outs = B.batch_rollout(scns, precision="fp32c")

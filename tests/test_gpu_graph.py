@@ -49,12 +49,14 @@ def eager_noise(B, torch):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32c", "rk4"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "rk4", "nofma"])
 def test_graph_replays_equal_eager(B, prec):
     import torch
     d = W.single(30000, seed=12, scenario_id=3)
     if prec == "rk4":
         d, prec = W.paper_preset(30000, seed=12, scenario_id=3), "fp64"
+    if prec == "nofma":
+        d, prec = W.single(30000, seed=12, scenario_id=3, nofma=True), "fp64"
     ref_out = B.rollout(d, precision=prec)
     ref_st = B.reduce(ref_out, risk=RISK, margin_q=MQ, grid=GRID)
     ref = host(ref_out)
@@ -111,8 +113,8 @@ def test_batch_graph_replays_equal_eager(B):
 
 
 def test_graph_rejects(B):
-    with pytest.raises(B.AebError) as e:
-        B.Graph(W.single(100, nofma=True))    # the unfused form is not recorded
+    with pytest.raises(B.AebError) as e:   # the unfused form with a lead vehicle is not recorded
+        B.Graph(dict(W.sweep(n=100)[3], nofma=True))
     assert e.value.code == B.EINVAL
     with pytest.raises(B.AebError) as e:
         B.Graph(W.single(100), precision="fp32c_fixup")
