@@ -202,6 +202,33 @@ def rk4_leg(B, W, torch, n, steps=5):
             "frac_fp64_peak": tflops / FP64_VECTOR_PEAK_TFLOPS}
 
 
+def unfused_leg(B, W, torch, n, steps=5):
+    """The headline scenario under the paper's rule of no fused operations
+    (Sec. V-D): every multiply-add a rounded product and a rounded sum, on the
+    same block-structured kernel; 11 flop per step as for the fused form, so
+    the ceiling is half the FMA peak."""
+    import numpy as np
+    d = W.single(n, nofma=True)
+    out = B.alloc_outputs(n)
+    B.rollout(d, out=out)
+    torch.cuda.synchronize()
+    B.timing_enable(True)
+    ks = []
+    for _ in range(steps):
+        B.rollout(d, out=out)
+        ks.append(B.timing_last())
+    B.timing_enable(False)
+    nsteps = int(out["steps"].to(torch.int64).sum().item())
+    ms = float(np.mean(ks))
+    tflops = EULER_FLOPS_PER_STEP * nsteps / (ms * 1e-3) / 1e12
+    return {"workload": f"stationary obstacle, {n} samples, explicit Euler without fused "
+                        "operations, parameters drawn in-kernel",
+            "kernel_ms": ms, "rollouts_per_s": n / (ms * 1e-3), "steps_per_launch": nsteps,
+            "flops_per_step": EULER_FLOPS_PER_STEP, "achieved_tflops": tflops,
+            "frac_fp64_peak": tflops / FP64_VECTOR_PEAK_TFLOPS,
+            "frac_unfused_ceiling": tflops / (FP64_VECTOR_PEAK_TFLOPS / 2)}
+
+
 def paper_study_leg(B, W, torch):
     """The paper's own workload (Sec. IV-B preset, RK4, no obstacle) on the GPU:
     Table I's sample counts (mean and sd of the stopping distance beside the
@@ -607,10 +634,12 @@ def main():
     step_path, step_wall = min(paths, key=lambda p: p[1])
     value = args.steps * n / step_wall
 
-    rk4 = nsweep = study = perception = control = rare = None
+    rk4 = unfused = nsweep = study = perception = control = rare = None
     if not args.headline_only:
         log("bench: rk4 leg")
         rk4 = rk4_leg(B, W, torch, n)
+        log("bench: unfused Euler leg")
+        unfused = unfused_leg(B, W, torch, n)
         log("bench: N sweep")
         nsweep = n_sweep_leg(B, W, torch)
         log("bench: paper-preset study")
@@ -703,6 +732,7 @@ def main():
             "speedup_vs_fp64_kernel": kavg64 / kavg32,
         },
         "rk4": rk4,
+        "unfused_euler": unfused,
         "n_sweep_fp64_step": nsweep,
         "paper_preset_study": study,
         "perception": perception,
