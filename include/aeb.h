@@ -285,8 +285,8 @@ int aeb_sample_params(const aeb_scenario* scn, int64_t first, int64_t count, con
  *     the closed-loop controller takes AEB_FP64 only (AEB_EINVAL otherwise):
  *     the block-structured path with blocks that end at every decision, or,
  *     for the unfused Euler form, one checked lane per sample.  Without the
- *     controller the unfused Euler form takes the block-structured path too,
- *     except with a lead vehicle (one checked lane per sample).  The
+ *     controller the unfused Euler form takes the block-structured path too.
+ *     The
  *     block-structured path counts steps in 32 bits: a horizon plus dead time
  *     beyond 2^31 - 4096 steps takes the checked FP64 kernel (AEB_FP32C:
  *     AEB_EINVAL).
@@ -367,8 +367,7 @@ int aeb_autotune(const aeb_scenario* calib, int precision, const char* cache_pat
  * scratch (allocated at creation) and, for batches, pinned copies of the
  * scenario tables.  Only the sorted block-structured path is recorded: FP64
  * explicit Euler (fused or unfused form) or RK4, FP32C explicit Euler;
- * AEB_EINVAL for the unfused Euler form with a lead vehicle (nofma), the
- * FP32C fix-up mode, the closed-loop
+ * AEB_EINVAL for the FP32C fix-up mode, the closed-loop
  * controller in FP32C or in batched graphs (in any of their scenarios), and
  * a horizon plus dead time beyond 2^31 - 4096 steps. */
 typedef struct aeb_graph aeb_graph;
@@ -474,8 +473,7 @@ int aeb_server_create(const aeb_server_cfg* cfg, aeb_server** out);
 int aeb_server_destroy(aeb_server* srv);
 
 /* Queue one evaluation (non-blocking).  AEB_EINVAL: invalid scenario or one
- * the batched path cannot run (the unfused Euler form with a lead vehicle,
- * RK4 in FP32C, the closed-loop controller);
+ * the batched path cannot run (RK4 in FP32C, the closed-loop controller);
  * AEB_ENOMEM: its footprint exceeds the request part of the arena or its
  * sample count max_tick_samples; AEB_EAGAIN: the queue is full.  deadline_s:
  * latency budget used for miss accounting (e.g. 0.530). */

@@ -39,6 +39,11 @@ namespace aeb {
 
 namespace {
 
+// The step and block helpers of the FP64 integration are always inlined: an
+// out-of-line call takes the lane state by reference, which puts it in
+// scratch memory (the compiler declined to inline the largest forms).
+#define HOT __device__ __attribute__((always_inline)) inline
+
 constexpr int NBINS = 8192;  // sort keys: 64 coarse x 2 classes x 64 fine
 // The sort's kernels (prep, scan, scatter) run in workgroups of one wavefront
 // per SIMD: beside a running integration kernel (four wavefronts per SIMD)
@@ -328,7 +333,7 @@ __device__ inline double mad(double a, double b, double c) {
 }
 
 template <int FORM, int K, bool LEAD, int INTEG = AEB_EULER>
-__device__ inline void block64(St64& s, Ld64& l, const Job& J, double al, double dt, double cmd) {
+HOT void block64(St64& s, Ld64& l, const Job& J, double al, double dt, double cmd) {
   constexpr bool NF = INTEG == EULER_NOFMA;
   if (INTEG == AEB_RK4) {
     const double h2 = 0.5 * dt, h6 = dt / 6.0;
@@ -361,11 +366,15 @@ __device__ inline void block64(St64& s, Ld64& l, const Job& J, double al, double
     // unfused: each step's position sum happens at its step (else the
     // compiler defers the sums and holds every step's product in a register)
     if (NF) asm volatile("" : "+v"(s.x));
+    if (NF && LEAD) {  // likewise the lead vehicle's state, and no step interleaved with the next
+      asm volatile("" : "+v"(l.xl), "+v"(l.vl), "+v"(l.gmin), "+v"(s.v));
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
 }
 
 template <bool LEAD, int INTEG = AEB_EULER>
-__device__ inline void step64(St64& s, Ld64& l, const Job& J, double al, double dt, double cmd) {
+HOT void step64(St64& s, Ld64& l, const Job& J, double al, double dt, double cmd) {
   constexpr bool NF = INTEG == EULER_NOFMA;
   if (INTEG == AEB_RK4) {
     rk4_step<FORM_G>(s, J, dt, 0.5 * dt, dt / 6.0, cmd);
@@ -521,8 +530,8 @@ __device__ inline int ctl_lim(const Lane64& L, int k, int nmax) {
 // wnd: the smallest nd of the wavefront's lanes (the whole block is dead time
 // for every lane when k + B <= wnd)
 template <int OBS, int B, int INTEG, bool CTL>
-__device__ inline void run_block64(Lane64& L, const Job& J, double al, const LaneScn& c, int k,
-                                   int wnd, int impact_exit, double a_warn) {
+HOT void run_block64(Lane64& L, const Job& J, double al, const LaneScn& c, int k, int wnd,
+                     int impact_exit, double a_warn) {
   constexpr bool LEAD = OBS == AEB_OBS_LEAD;
   const double cmd = lane_cmd<CTL>(L, c, a_warn, k);
   const int fcmd = first_cmd<CTL>(L, c);
@@ -561,8 +570,8 @@ __device__ inline void run_block64(Lane64& L, const Job& J, double al, const Lan
 // inside a block, that state becomes the lane's replay start.  Returns the
 // step index after the last block.
 template <int OBS, int K, int FORM, int INTEG>
-__device__ inline int run_steady(Lane64& L, const Job& J, double al, double dt, double cmd, int k,
-                                 int wl, double thr, int impact_exit, double& xmax) {
+HOT int run_steady(Lane64& L, const Job& J, double al, double dt, double cmd, int k, int wl,
+                   double thr, int impact_exit, double& xmax) {
   constexpr bool LEAD = OBS == AEB_OBS_LEAD;
   do {
     const St64 b = L.s;
@@ -1469,9 +1478,7 @@ bool fast_path_applies(const aeb_scenario& s, int precision) {
   if (!block_steps_ok(s)) return false;
   // the controller: FP64 explicit Euler (fused form) or RK4 only
   if (control_on(s)) return precision == AEB_FP64 && (s.integrator == AEB_RK4 || !s.nofma);
-  // (RK4 has no lead vehicle; the unfused Euler form with one would not fit
-  // the registers and takes the checked kernel)
-  if (precision == AEB_FP64) return s.obstacle != AEB_OBS_LEAD || !(s.integrator == AEB_RK4 || s.nofma);
+  if (precision == AEB_FP64) return s.obstacle != AEB_OBS_LEAD || s.integrator != AEB_RK4;
   if (s.integrator != AEB_EULER) return false;
   return precision == AEB_FP32C || precision == AEB_FP32C_FIXUP;
 }
@@ -1633,11 +1640,12 @@ int integrate(const aeb_scenario& s0, int precision, const Bufs& b, int64_t n, c
     return AEB_OK;
   }
   if (precision == AEB_FP64 && s0.nofma) {
-    // the unfused form (no lead vehicle: fast_path_applies): 128-step blocks,
-    // the launch shape of the table
+    // the unfused form: 128-step blocks, the launch shape of the table
     timing_begin(st);
     if (obs == AEB_OBS_STATIONARY)
       go64<AEB_OBS_STATIONARY, 128, BATCH, EULER_NOFMA>(sh, b, n, ctx, st);
+    else if (obs == AEB_OBS_LEAD)
+      go64<AEB_OBS_LEAD, 128, BATCH, EULER_NOFMA>(sh, b, n, ctx, st);
     else
       go64<AEB_OBS_NONE, 128, BATCH, EULER_NOFMA>(sh, b, n, ctx, st);
     timing_end(st);

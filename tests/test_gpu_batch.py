@@ -47,6 +47,19 @@ def test_batch_uneven_unfused(B, orc):
             assert np.array_equal(got[c], alone[c]), c
 
 
+def test_batch_lead_sweep_unfused(B, orc):
+    """Sixteen cells of the lead-vehicle sweep without fused operations in one
+    batched launch: each equals the reference and its launch alone."""
+    scns = [dict(d, nofma=True) for d in W.sweep(n=800)[::16]]
+    outs = B.batch_rollout(scns)
+    for d, o in zip(scns, outs):
+        got = to_np(o)
+        check_fp64(got, orc.run(d))
+        alone = to_np(B.rollout(d))
+        for c in got:
+            assert np.array_equal(got[c], alone[c]), c
+
+
 def test_batch_uneven_fp32c(B, orc):
     scns = W.uneven_batch(24, max_samples=1200)
     outs = B.batch_rollout(scns, precision="fp32c")

@@ -113,8 +113,8 @@ def test_batch_graph_replays_equal_eager(B):
 
 
 def test_graph_rejects(B):
-    with pytest.raises(B.AebError) as e:   # the unfused form with a lead vehicle is not recorded
-        B.Graph(dict(W.sweep(n=100)[3], nofma=True))
+    with pytest.raises(B.AebError) as e:   # the controller in a batched graph is not recorded
+        B.Graph([W.single(100), W.closed_loop(100)], batch=True)
     assert e.value.code == B.EINVAL
     with pytest.raises(B.AebError) as e:
         B.Graph(W.single(100), precision="fp32c_fixup")

@@ -353,3 +353,11 @@ def test_horizon_beyond_block_path_limit(B, orc):
         B.rollout(d, precision="fp32c")
     with pytest.raises(B.AebError):
         B.Graph(d)
+
+
+@pytest.mark.parametrize("k", [3, 70, 130, 255])
+def test_lead_unfused_exact(B, orc, k):
+    """The paper's rule of no fused operations with a decelerating lead vehicle
+    (the block-structured kernel, lead state pinned per step): bit for bit."""
+    d = dict(W.sweep(n=2500)[k], nofma=True)
+    check_fp64(to_np(plain(B, d)), orc.run(d), exact=True)

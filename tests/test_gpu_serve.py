@@ -112,8 +112,8 @@ def test_concurrent_clients(B):
 def test_refusals(B):
     with B.Server(64 << 20, max_slots=4, n_streams=1, max_tick_samples=1 << 14) as srv:
         with pytest.raises(B.AebError) as e:
-            # the unfused form with a lead vehicle is not batched
-            srv.submit(dict(W.sweep(n=100)[3], nofma=True))
+            # the closed-loop controller is not batched
+            srv.submit(W.closed_loop(100))
         assert e.value.code == B.EINVAL
         with pytest.raises(B.AebError) as e:
             srv.submit(W.single(1 << 15))              # more than a launch holds
