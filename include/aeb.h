@@ -283,10 +283,8 @@ int aeb_sample_params(const aeb_scenario* scn, int64_t first, int64_t count, con
  *     or AEB_FP32C_FIXUP (as AEB_FP32C, then the flagged samples are
  *     recomputed in FP64, so every collision flag is exact).  A scenario with
  *     the closed-loop controller takes AEB_FP64 only (AEB_EINVAL otherwise):
- *     the block-structured path with blocks that end at every decision, or,
- *     for the unfused Euler form, one checked lane per sample.  Without the
- *     controller the unfused Euler form takes the block-structured path too.
- *     The
+ *     the block-structured path with blocks that end at every decision (both
+ *     Euler forms and RK4).  The
  *     block-structured path counts steps in 32 bits: a horizon plus dead time
  *     beyond 2^31 - 4096 steps takes the checked FP64 kernel (AEB_FP32C:
  *     AEB_EINVAL).

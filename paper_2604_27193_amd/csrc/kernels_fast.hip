@@ -1476,8 +1476,8 @@ bool block_steps_ok(const aeb_scenario& s) {
 
 bool fast_path_applies(const aeb_scenario& s, int precision) {
   if (!block_steps_ok(s)) return false;
-  // the controller: FP64 explicit Euler (fused form) or RK4 only
-  if (control_on(s)) return precision == AEB_FP64 && (s.integrator == AEB_RK4 || !s.nofma);
+  // the controller: FP64 only (explicit Euler, fused or unfused, or RK4)
+  if (control_on(s)) return precision == AEB_FP64;
   if (precision == AEB_FP64) return s.obstacle != AEB_OBS_LEAD || s.integrator != AEB_RK4;
   if (s.integrator != AEB_EULER) return false;
   return precision == AEB_FP32C || precision == AEB_FP32C_FIXUP;
@@ -1616,6 +1616,10 @@ int integrate(const aeb_scenario& s0, int precision, const Bufs& b, int64_t n, c
     timing_begin(st);
     if (s0.integrator == AEB_RK4)
       go64<AEB_OBS_STATIONARY, 16, false, AEB_RK4, true>(sh, b, n, ctx, st);
+    else if (s0.nofma)  // the unfused form: 48-step blocks for every period
+      obs == AEB_OBS_LEAD
+          ? go64<AEB_OBS_LEAD, 48, false, EULER_NOFMA, true>(sh, b, n, ctx, st)
+          : go64<AEB_OBS_STATIONARY, 48, false, EULER_NOFMA, true>(sh, b, n, ctx, st);
     else if (obs == AEB_OBS_LEAD)
       per % 50 == 0   ? go64<AEB_OBS_LEAD, 50, false, AEB_EULER, true>(sh, b, n, ctx, st)
       : per % 40 == 0 ? go64<AEB_OBS_LEAD, 40, false, AEB_EULER, true>(sh, b, n, ctx, st)

@@ -105,8 +105,8 @@ static void go_fp64(const aeb_scenario& s, const ParamSrc* src, const OutCols& o
                        out, n, nd, nmax, ca);
 }
 
-// the closed-loop controller outside the block path (the unfused Euler form):
-// FP64, one checked lane per sample
+// the closed-loop controller outside the block path (horizons beyond its step
+// limit): FP64, one checked lane per sample
 static int go_control(const aeb_scenario& s, const ParamSrc* src, int precision,
                       const OutCols& out, int64_t n, int64_t nd, int64_t nmax, hipStream_t st) {
   if (precision != AEB_FP64)

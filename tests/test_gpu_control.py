@@ -2,8 +2,8 @@
 closing-speed measurements, latched partial and full braking; the controller
 assessment named in Sec. VIII) against the FP64 reference.  The controller
 runs in the block-structured FP64 kernel (blocks end at every decision and
-command switch; the unfused Euler form in the checked kernel): host-drawn
-inputs give the reference's bits, in-kernel draws agree to 1e-12."""
+command switch; both Euler forms and RK4): host-drawn inputs give the
+reference's bits, in-kernel draws agree to 1e-12."""
 import math
 
 import numpy as np
@@ -45,6 +45,7 @@ def variants():
         "lead_period_40ms": dict(W.sweep(n=2000)[60], horizon=15.0, **dict(CTL, ctl_period=0.04)),
         "rk4": W.closed_loop(1500, integrator="rk4"),
         "nofma": W.closed_loop(2000, nofma=True),
+        "lead_nofma": dict(W.sweep(n=2000)[100], horizon=15.0, nofma=True, **CTL),
         "lead": dict(W.sweep(n=3000)[100], horizon=15.0, **CTL),
         "dt2ms": W.closed_loop(3000, dt=2e-3),
     }
