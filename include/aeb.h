@@ -84,6 +84,9 @@ typedef struct {
  *   n_samples: N, 1 <= N <= 2^31 - 1.
  *   integrator: AEB_EULER (explicit Euler, four fused multiply-adds per step
  *     unless nofma) or AEB_RK4 (classical RK4, no fused operations).
+ *   nofma: 1 for the paper's rule of no fused operations in AEB_FP64 explicit
+ *     Euler (each multiply-add a rounded product and a rounded sum); the FP32
+ *     compensated forms have their own arithmetic and ignore it.
  *   obstacle: NONE (only the stopping distance), STATIONARY (obstacle at the
  *     sampled gap; the rollout runs to a stop with the collision flag latched,
  *     or ends at impact if impact_exit), LEAD (lead vehicle starting at the
