@@ -86,7 +86,8 @@ typedef struct {
  *     unless nofma) or AEB_RK4 (classical RK4, no fused operations).
  *   nofma: 1 for the paper's rule of no fused operations in AEB_FP64 explicit
  *     Euler (each multiply-add a rounded product and a rounded sum); the FP32
- *     compensated forms have their own arithmetic and ignore it.
+ *     compensated forms have their own arithmetic and ignore it (the fix-up
+ *     mode recomputes its flagged samples in the FP64 form it names).
  *   obstacle: NONE (only the stopping distance), STATIONARY (obstacle at the
  *     sampled gap; the rollout runs to a stop with the collision flag latched,
  *     or ends at impact if impact_exit), LEAD (lead vehicle starting at the
