@@ -237,6 +237,7 @@ def test_fp32c_lead(B, orc, k, prec):
 def test_fp32c_variants(B, orc, prec):
     for d in (W.single(2000, obstacle="none"), W.single(2000, impact_exit=True),
               W.single(1500, obstacle="none", dt=5e-4, horizon=15.0),
+              W.single(2000, seed=17, nofma=True),  # the fix-up recomputes in the unfused form
               W.paper_preset(2000, integrator="euler"), W.single(1500, dt=5e-4, horizon=15.0),
               *W.uneven_batch(3, max_samples=1000)):
         check_fp32c(to_np(B.rollout(d, precision=prec)), orc.run(d), fixup=prec == "fp32c_fixup")
