@@ -1616,10 +1616,14 @@ int integrate(const aeb_scenario& s0, int precision, const Bufs& b, int64_t n, c
     timing_begin(st);
     if (s0.integrator == AEB_RK4)
       go64<AEB_OBS_STATIONARY, 16, false, AEB_RK4, true>(sh, b, n, ctx, st);
-    else if (s0.nofma)  // the unfused form: 48-step blocks for every period
-      obs == AEB_OBS_LEAD
-          ? go64<AEB_OBS_LEAD, 48, false, EULER_NOFMA, true>(sh, b, n, ctx, st)
-          : go64<AEB_OBS_STATIONARY, 48, false, EULER_NOFMA, true>(sh, b, n, ctx, st);
+    else if (s0.nofma && obs == AEB_OBS_LEAD)  // the unfused form
+      per % 50 == 0   ? go64<AEB_OBS_LEAD, 50, false, EULER_NOFMA, true>(sh, b, n, ctx, st)
+      : per % 40 == 0 ? go64<AEB_OBS_LEAD, 40, false, EULER_NOFMA, true>(sh, b, n, ctx, st)
+                      : go64<AEB_OBS_LEAD, 48, false, EULER_NOFMA, true>(sh, b, n, ctx, st);
+    else if (s0.nofma)
+      per % 50 == 0   ? go64<AEB_OBS_STATIONARY, 50, false, EULER_NOFMA, true>(sh, b, n, ctx, st)
+      : per % 40 == 0 ? go64<AEB_OBS_STATIONARY, 40, false, EULER_NOFMA, true>(sh, b, n, ctx, st)
+                      : go64<AEB_OBS_STATIONARY, 48, false, EULER_NOFMA, true>(sh, b, n, ctx, st);
     else if (obs == AEB_OBS_LEAD)
       per % 50 == 0   ? go64<AEB_OBS_LEAD, 50, false, AEB_EULER, true>(sh, b, n, ctx, st)
       : per % 40 == 0 ? go64<AEB_OBS_LEAD, 40, false, AEB_EULER, true>(sh, b, n, ctx, st)

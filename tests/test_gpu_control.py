@@ -46,6 +46,8 @@ def variants():
         "rk4": W.closed_loop(1500, integrator="rk4"),
         "nofma": W.closed_loop(2000, nofma=True),
         "lead_nofma": dict(W.sweep(n=2000)[100], horizon=15.0, nofma=True, **CTL),
+        "period_40ms_nofma": W.closed_loop(1500, ctl_period=0.04, nofma=True),
+        "period_30ms_nofma": W.closed_loop(1500, ctl_period=0.03, nofma=True),
         "lead": dict(W.sweep(n=3000)[100], horizon=15.0, **CTL),
         "dt2ms": W.closed_loop(3000, dt=2e-3),
     }
