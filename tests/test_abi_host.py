@@ -60,6 +60,16 @@ def test_host_uniforms_bitwise(B, orc, seed, sid, slot, attempt):
     assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
 
 
+@pytest.mark.parametrize("row", range(3))
+def test_host_uniforms_known_answers(B, row):
+    # the library's own generator against the published Philox4x32-10 rows
+    from test_oracle_rng import kat_as_uniform_call, kat_rows, kat_uniforms
+    ctr, key, out = kat_rows()[row]
+    seed, sid, i, slot, attempt = kat_as_uniform_call(ctr, key)
+    got = B.uniforms(seed, sid, i, 1, slot, attempt, device=False).ravel()
+    assert list(got) == kat_uniforms(out)
+
+
 @pytest.mark.parametrize("d", [W.single(20_000), W.paper_preset(5000), W.sweep(n=3000)[37],
                                W.uneven_batch(4)[1], W.perception(20_000),
                                W.perception(5000, occlusion=("normal", 1.0, 3.0), p_dropout=0.6,

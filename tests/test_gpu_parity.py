@@ -74,6 +74,16 @@ def test_device_uniforms_bitwise(B, orc, seed, sid, slot, attempt, n):
     assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
 
 
+@pytest.mark.parametrize("row", range(3))
+def test_device_uniforms_known_answers(B, row):
+    # the kernel generator against the published Philox4x32-10 rows
+    from test_oracle_rng import kat_as_uniform_call, kat_rows, kat_uniforms
+    ctr, key, out = kat_rows()[row]
+    seed, sid, i, slot, attempt = kat_as_uniform_call(ctr, key)
+    got = B.uniforms(seed, sid, i, 1, slot, attempt, device=True).cpu().numpy().ravel()
+    assert list(got) == kat_uniforms(out)
+
+
 def test_device_sampler_matches_reference(B, orc):
     d = W.single(50_000)
     got = {k: v.cpu().numpy() for k, v in B.sample_params(d, device=True).items()}

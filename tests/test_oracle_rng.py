@@ -1,15 +1,65 @@
 """Pins for the reference's counter-based generator and distributions.
 
-The generator has no known-answer vectors available here, so it is pinned by
-an independent second implementation (``philox_ref``) agreeing bit for bit on
-10^6 calls, plus distributional checks of the uniforms and of every derived
+The generator is pinned to the published Philox4x32-10 known-answer vectors
+(``golden/philox4x32_10_kat.txt``, from the Random123 distribution), to an
+independent second implementation (``philox_ref``) agreeing bit for bit on
+10^6 calls, and by distributional checks of the uniforms and of every derived
 distribution (moments and Kolmogorov-Smirnov against scipy's exact CDFs).
 """
+import os
+
 import numpy as np
 import pytest
 from scipy import stats
 
 import philox_ref as PR
+
+KAT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "philox4x32_10_kat.txt")
+
+
+def kat_rows():
+    """(counter, key, output) word lists of the published known-answer rows."""
+    rows = []
+    for line in open(KAT):
+        line = line.split("#", 1)[0].split()
+        if not line:
+            continue
+        w = [int(x, 16) for x in line]
+        assert len(w) == 10
+        rows.append((w[0:4], w[4:6], w[6:10]))
+    assert len(rows) == 3
+    return rows
+
+
+@pytest.mark.parametrize("row", range(3))
+def test_philox_known_answers(orc, row):
+    ctr, key, want = kat_rows()[row]
+    assert orc.philox(ctr, key) == want
+    assert PR.philox_int(ctr, key) == want
+
+
+def kat_as_uniform_call(ctr, key):
+    """The known-answer row as the generator's uniform call: counter
+    (i, slot | attempt << 8, lo32(id), hi32(id)), key (lo32(seed), hi32(seed));
+    returns (seed, id, i, slot, attempt) and the two uniforms
+    ((w >> 12) + 1/2) 2^-52 of the output words w = o1:o0 and o3:o2."""
+    seed = key[0] | (key[1] << 32)
+    sid = ctr[2] | (ctr[3] << 32)
+    return (seed, sid, ctr[0], ctr[1] & 0xFF, ctr[1] >> 8)
+
+
+def kat_uniforms(out):
+    w0 = out[0] | (out[1] << 32)
+    w1 = out[2] | (out[3] << 32)
+    return [((w0 >> 12) + 0.5) * 2.0 ** -52, ((w1 >> 12) + 0.5) * 2.0 ** -52]
+
+
+@pytest.mark.parametrize("row", range(3))
+def test_uniform_call_known_answers(orc, row):
+    ctr, key, out = kat_rows()[row]
+    seed, sid, i, slot, attempt = kat_as_uniform_call(ctr, key)
+    got = orc.uniforms(seed, sid, i, 1, slot, attempt).ravel()
+    assert list(got) == kat_uniforms(out)
 
 
 def test_philox_single_calls_match_independent_implementation(orc):
