@@ -125,7 +125,9 @@ __host__ __device__ inline double trigger_delay(const aeb_scenario& s, uint64_t 
   // frames j = 0 .. last with j * frame_period <= horizon (at most 1e6 + 1)
   const int64_t last = static_cast<int64_t>(floor(s.horizon / s.frame_period));
   int64_t j = 0;
-  if (occ > 0.0) j = occ <= static_cast<double>(last) ? static_cast<int64_t>(floor(occ)) : last + 1;
+  // the first floor(occ) frames are hidden; beyond the frame count, all of them
+  if (occ > 0.0)
+    j = occ < static_cast<double>(last + 1) ? static_cast<int64_t>(floor(occ)) : last + 1;
   const int64_t first = j;
   int run = 0;
   U2 u{0.0, 0.0};

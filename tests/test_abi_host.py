@@ -76,6 +76,8 @@ def test_host_uniforms_known_answers(B, row):
                                             confirm=4, latency=("normal", 0.0, 0.05)),
                                W.perception(3000, frame_period=0.0),
                                W.perception(3000, occlusion=("const", 1e30), horizon=1.0),
+                               W.perception(2000, occlusion=("const", 33.5), frame_period=0.3,
+                                            confirm=1, p_dropout=0.0),
                                W.rare_event(5000),
                                dict(W.single(3000), proposal={"mass": ("normal", 1400.0, 90.0),
                                                               "gap": ("normal", 55.0, 3.0)})])

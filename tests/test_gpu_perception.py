@@ -47,6 +47,10 @@ def variants():
         "lead": dict(W.sweep(n=2000)[70], latency=("uniform", 0.05, 0.15), frame_period=0.04,
                      occlusion=("uniform", 0.0, 6.0), p_dropout=0.2, confirm=2),
         "dt2ms": W.perception(3000, dt=2e-3),
+        # occlusion between the last frame index and the frame count: the last
+        # frame (9.9 s) stays visible and the command starts inside the horizon
+        "occl_last": W.perception(2000, occlusion=("const", 33.5), frame_period=0.3, confirm=1,
+                                  p_dropout=0.0, latency=("const", 0.0)),
     }
 
 
@@ -67,7 +71,8 @@ def test_plain_fp64_exact(B, orc, name):
     check_fp64(to_np(plain(B, d)), orc.run(d), exact=True)
 
 
-@pytest.mark.parametrize("name", ["base", "heavy_dropout", "never_confirmed", "lead", "rk4"])
+@pytest.mark.parametrize("name", ["base", "heavy_dropout", "never_confirmed", "lead", "rk4",
+                                  "occl_last"])
 def test_device_rng_fp64(B, orc, name):
     d = variants()[name]
     check_fp64(to_np(B.rollout(d)), orc.run(d))

@@ -185,6 +185,22 @@ def test_trigger_beyond_horizon_coasts(orc):
     assert orc.sample(d)["trigger"][0] == pytest.approx(1.95, abs=1e-12)
 
 
+def test_occlusion_between_last_frames(orc):
+    """Only the first floor(occlusion) frames are hidden: an occlusion between
+    the last frame index and the frame count leaves the last frame visible."""
+    T, P = 10.0, 0.3                      # frames 0..33 (33 P = 9.9 s <= T)
+    for occ, want in ((33.0, 33 * P), (33.5, 33 * P), (33.999, 33 * P), (34.0, np.inf),
+                      (34.5, np.inf)):
+        d = flat(2, horizon=T, occlusion=("const", occ), frame_period=P, confirm=1)
+        t = orc.sample(d)["trigger"]
+        assert np.all(t == want), (occ, t)
+    # the command then starts inside the horizon: the rollout brakes at its end
+    d = flat(1, horizon=T, occlusion=("const", 33.5), frame_period=P, confirm=1,
+             dead_time=0.05)
+    r = orc.run(d)
+    assert r["steps"][0] == 10_000 and r["dist"][0] < 25.3 * T - 1e-6
+
+
 def test_trigger_equals_extra_dead_time(orc):
     """In the full model (drag, grade, weight transfer, obstacle) a trigger T
     acts as dead time: same outputs as no perception with dead_time + T."""
