@@ -25,12 +25,17 @@
  *     stream).  Device work is enqueued on it; functions documented as
  *     "asynchronous" return before the work completes.
  *   - All functions act on the HIP device that is current on the calling thread.
- *   - The library keeps a per-device scratch arena for sorting and reduction
- *     partials; it grows on demand (hipMalloc) and lives until process exit.
- *     Calls that use it (aeb_rollout, aeb_reduce, aeb_batch_rollout) share it
- *     across streams: work of two such calls in flight at once on different
- *     streams of one device races.  For concurrent launches use recorded
- *     graphs (each owns its scratch) or the server (per-stream scratch).
+ *   - The library keeps a per-device pool of scratch blocks for sorting and
+ *     reduction partials; it grows on demand (hipMalloc) and lives until
+ *     process exit.  A call that needs scratch (aeb_rollout, aeb_reduce,
+ *     aeb_batch_rollout, aeb_batch_reduce, aeb_autotune) holds its blocks
+ *     while it enqueues work and then fences them with an event on its
+ *     stream; another call reuses a block only once that work is done (or
+ *     after its stream waits for the event on the device), and a block is
+ *     freed to grow it only after its event has completed.  Calls on
+ *     different streams and threads may therefore be in flight at once.
+ *     These calls cannot be captured into a caller's graph (AEB_EINVAL on a
+ *     capturing stream): record graphs with aeb_graph_create*.
  */
 #ifndef AEB_H
 #define AEB_H
@@ -283,7 +288,8 @@ int aeb_sample_params(const aeb_scenario* scn, int64_t first, int64_t count, con
  *     same steps), AEB_FP32C (FP32 state with compensated distance and, for
  *     long rollouts, compensated speed; FP64 derived constants, final
  *     distance and collision decision; samples whose distance or clearance is
- *     within 1 mm + 1e-5 gap of the obstacle get AEB_BOUNDARY in their status)
+ *     within 1 mm + 1e-4 gap of the obstacle -- the form's relative distance
+ *     tolerance at the obstacle -- get AEB_BOUNDARY in their status)
  *     or AEB_FP32C_FIXUP (as AEB_FP32C, then the flagged samples are
  *     recomputed in FP64, so every collision flag is exact).  A scenario with
  *     the closed-loop controller takes AEB_FP64 only (AEB_EINVAL otherwise):
@@ -368,8 +374,9 @@ int aeb_autotune(const aeb_scenario* calib, int precision, const char* cache_pat
  * and gives the same results as the eager calls.  The graph owns its device
  * scratch (allocated at creation) and, for batches, pinned copies of the
  * scenario tables.  Only the sorted block-structured path is recorded: FP64
- * explicit Euler (fused or unfused form) or RK4, FP32C explicit Euler;
- * AEB_EINVAL for the FP32C fix-up mode, the closed-loop
+ * explicit Euler (fused or unfused form) or RK4, FP32C explicit Euler (for
+ * one scenario also with the FP64 fix-up of its flagged samples);
+ * AEB_EINVAL for the fix-up mode in batched graphs, the closed-loop
  * controller in FP32C or in batched graphs (in any of their scenarios), and
  * a horizon plus dead time beyond 2^31 - 4096 steps. */
 typedef struct aeb_graph aeb_graph;

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <string>
 #include <thread>
 #include <vector>
@@ -28,15 +29,30 @@ int fail(int code, const std::string& msg) {
 }
 
 // ---------------------------------------------------------------------------
-// scratch arena
+// scratch pool
+//
+// Device blocks per device, each with an event recorded on the stream of the
+// call that last used it.  A call takes blocks inside a ScratchScope: a block
+// no other call holds, preferring one last used on the same stream (stream
+// order protects it) or one whose event has completed; otherwise a new block,
+// or, once the pool holds POOL_SOFT blocks, a fitting block whose event the
+// call's stream waits for on the device.  A block is freed (to grow it) only
+// when no call holds it and after its event has completed, so no queued work
+// can touch freed memory.
 // ---------------------------------------------------------------------------
 namespace {
-struct Arena {
+struct Block {
   void* ptr = nullptr;
   size_t bytes = 0;
+  hipEvent_t ev = nullptr;     // recorded on `last` when the last holder released it
+  hipStream_t last = nullptr;
+  bool busy = false;           // held by a live scope
+  bool fenced = false;         // ev has been recorded
 };
-std::mutex g_arena_mu;
-Arena g_arena[64][2];
+constexpr int MAX_DEV = 64;
+constexpr size_t POOL_SOFT = 8;
+std::mutex g_pool_mu;
+std::vector<Block*> g_pool[MAX_DEV];
 
 struct Timing {
   bool on = false;
@@ -45,36 +61,125 @@ struct Timing {
   hipEvent_t start = nullptr, stop = nullptr;
 };
 thread_local Timing g_timing;
-}  // namespace
+thread_local ScratchScope* g_scope = nullptr;
 
-void* scratch_slot(int slot, size_t bytes, hipStream_t stream) {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || slot < 0 || slot > 1) {
-    set_error("scratch: no current HIP device");
-    return nullptr;
+bool block_idle(const Block* b, hipStream_t st) {
+  if (!b->fenced || b->last == st) return true;
+  return hipEventQuery(b->ev) == hipSuccess;
+}
+
+// Called with g_pool_mu held.  Returns a block of at least `bytes` for work on
+// `st`, marked busy, or nullptr with the error set.
+Block* acquire(int dev, size_t bytes, hipStream_t st) {
+  std::vector<Block*>& pool = g_pool[dev];
+  Block* pick = nullptr;
+  for (Block* b : pool)  // a fitting block that is idle for this stream, smallest first
+    if (!b->busy && b->bytes >= bytes && block_idle(b, st) && (!pick || b->bytes < pick->bytes))
+      pick = b;
+  bool wait = false;
+  if (!pick && pool.size() >= POOL_SOFT) {
+    for (Block* b : pool)  // a fitting block still in flight on another stream
+      if (!b->busy && b->bytes >= bytes && (!pick || b->bytes < pick->bytes)) pick = b;
+    wait = pick != nullptr;
   }
-  std::lock_guard<std::mutex> lock(g_arena_mu);
-  Arena& a = g_arena[dev][slot];
-  if (a.bytes >= bytes) return a.ptr;
-  // work queued on any stream may still use the old block
-  if (a.ptr) {
-    (void)stream;
-    if (hipDeviceSynchronize() != hipSuccess || hipFree(a.ptr) != hipSuccess) {
-      set_error("scratch: could not release the previous arena");
+  if (!pick) {
+    // grow: replace the smallest block nobody holds -- below POOL_SOFT blocks
+    // only one idle for this stream, beyond it any (after its last work) --
+    // or add one
+    Block* old = nullptr;
+    const bool full = pool.size() >= POOL_SOFT;
+    for (Block* b : pool)
+      if (!b->busy && (full || block_idle(b, st)) && (!old || b->bytes < old->bytes)) old = b;
+    size_t want = bytes < (size_t(1) << 20) ? (size_t(1) << 20) : bytes;
+    want = (want + 4095) & ~size_t(4095);
+    if (old) {
+      if ((old->fenced && hipEventSynchronize(old->ev) != hipSuccess) || hipFree(old->ptr) != hipSuccess) {
+        set_error("scratch: could not release a pool block");
+        return nullptr;
+      }
+      old->ptr = nullptr;
+      old->bytes = 0;
+      old->fenced = false;
+      pick = old;
+    } else {
+      pick = new (std::nothrow) Block;
+      if (!pick) {
+        set_error("scratch: host allocation failed");
+        return nullptr;
+      }
+      if (hipEventCreateWithFlags(&pick->ev, hipEventDisableTiming) != hipSuccess) {
+        delete pick;
+        set_error("scratch: hipEventCreate failed");
+        return nullptr;
+      }
+      pool.push_back(pick);
+    }
+    if (hipMalloc(&pick->ptr, want) != hipSuccess) {
+      pick->ptr = nullptr;
+      set_error("scratch: hipMalloc of " + std::to_string(want) + " bytes failed");
       return nullptr;
     }
-    a.ptr = nullptr;
-    a.bytes = 0;
+    pick->bytes = want;
   }
-  size_t want = bytes < (size_t(1) << 20) ? (size_t(1) << 20) : bytes;
-  want = (want + 4095) & ~size_t(4095);
-  if (hipMalloc(&a.ptr, want) != hipSuccess) {
-    a.ptr = nullptr;
-    set_error("scratch: hipMalloc of " + std::to_string(want) + " bytes failed");
+  if (wait && hipStreamWaitEvent(st, pick->ev, 0) != hipSuccess) {
+    set_error("scratch: hipStreamWaitEvent failed");
     return nullptr;
   }
-  a.bytes = want;
-  return a.ptr;
+  pick->busy = true;
+  return pick;
+}
+
+// Called with g_pool_mu held: fence the block's work on `st` and hand it back.
+void release(Block* b, hipStream_t st) {
+  if (hipEventRecord(b->ev, st) == hipSuccess) {
+    b->fenced = true;
+    b->last = st;
+  } else {
+    // no fence: make sure its work is done before anyone else takes it
+    (void)hipStreamSynchronize(st);
+    b->fenced = false;
+  }
+  b->busy = false;
+}
+}  // namespace
+
+ScratchScope::ScratchScope(hipStream_t st) : st_(st), outer_(g_scope) {
+  if (hipGetDevice(&dev_) != hipSuccess || dev_ < 0 || dev_ >= MAX_DEV) dev_ = -1;
+  g_scope = this;
+}
+
+ScratchScope::~ScratchScope() {
+  {
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    for (void* h : held_)
+      if (h) release(static_cast<Block*>(h), st_);
+  }
+  g_scope = outer_;
+}
+
+void* scratch_slot(int slot, size_t bytes, hipStream_t stream) {
+  ScratchScope* sc = g_scope;
+  if (!sc || sc->st_ != stream || sc->dev_ < 0 || slot < 0 || slot >= ScratchScope::SLOTS) {
+    set_error("scratch: no scratch scope for this call (internal error)");
+    return nullptr;
+  }
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone) {
+    set_error("scratch: the pool's blocks are fenced by events and cannot be captured; record "
+              "graphs with aeb_graph_create");
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_pool_mu);
+  Block* have = static_cast<Block*>(sc->held_[slot]);
+  if (have && have->bytes >= bytes) return have->ptr;
+  if (have) {
+    release(have, stream);
+    sc->held_[slot] = nullptr;
+  }
+  Block* b = acquire(sc->dev_, bytes, stream);
+  if (!b) return nullptr;
+  sc->held_[slot] = b;
+  return b->ptr;
 }
 
 // ---------------------------------------------------------------------------
@@ -361,6 +466,7 @@ int aeb_rollout(const aeb_scenario* scn, const aeb_params* params, int precision
                    params->trigger, params->log_weight};
   }
   OutCols oc{out->dist, out->status, out->steps, out->margin, out->v_impact, out->weight};
+  ScratchScope scope(static_cast<hipStream_t>(stream));
   return launch_rollout(*scn, params ? &src : nullptr, precision, oc, scn->n_samples,
                         static_cast<hipStream_t>(stream));
 }
@@ -385,6 +491,7 @@ int aeb_batch_rollout(const aeb_scenario* scns, int n_scn, int precision, const 
                     outs[j].weight};
   }
   if (total > 0xffffffffLL) return fail(AEB_EINVAL, "a batch holds at most 2^32 - 1 samples");
+  ScratchScope scope(static_cast<hipStream_t>(stream));
   return launch_batch(scns, n_scn, precision, oc.data(), static_cast<hipStream_t>(stream));
 }
 
@@ -404,6 +511,7 @@ int aeb_reduce(const aeb_outputs* out, const aeb_reduce_req* req, aeb_stats* hos
   const int rc = check_reduce_req(*req);
   if (rc != AEB_OK) return rc;
   OutCols oc{out->dist, out->status, out->steps, out->margin, out->v_impact, out->weight};
+  ScratchScope scope(static_cast<hipStream_t>(stream));
   return launch_reduce(oc, out->n, *req, host_out, static_cast<hipStream_t>(stream));
 }
 

@@ -25,13 +25,35 @@ int fail(int code, const std::string& msg);
       return ::aeb::fail(AEB_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-// Grow-only device scratch, per device and slot; never shrinks before exit.
-// Returns nullptr (with the error set) if the allocation fails.  Slot 0 holds
-// the rollout's job records and sort buffers and the reduction's partials;
-// slot 1 the FP32 fix-up list, which lives alongside slot 0.
+// Device scratch of one library call.  Each ABI entry point that enqueues
+// work on scratch opens a ScratchScope on its stream; scratch_slot() inside
+// it hands out blocks of a per-device pool that no other live scope holds.
+// When the scope ends, an event recorded on the stream fences each block, so
+// a later call on another stream reuses it only after that work (or waits
+// for it on the device), and a block is freed to grow it only after its
+// event has completed.  Calls on different streams or threads therefore
+// never share scratch that is in flight.  A call holds one block per slot
+// (slot 0: the rollout's job records, sort buffers and fix-up list, or the
+// reduction's partials).  Returns nullptr (with the error set) if the
+// allocation fails, outside a scope, or on a stream that is being captured
+// into a graph.
+class ScratchScope {
+ public:
+  static constexpr int SLOTS = 1;
+  explicit ScratchScope(hipStream_t st);
+  ~ScratchScope();
+  ScratchScope(const ScratchScope&) = delete;
+  ScratchScope& operator=(const ScratchScope&) = delete;
+
+ private:
+  friend void* scratch_slot(int slot, size_t bytes, hipStream_t stream);
+  hipStream_t st_;
+  int dev_ = -1;
+  ScratchScope* outer_;
+  void* held_[SLOTS] = {nullptr};
+};
 void* scratch_slot(int slot, size_t bytes, hipStream_t stream);
-inline void* scratch(size_t bytes, hipStream_t stream) { return scratch_slot(0, bytes, stream); }
-inline void* scratch_fix(size_t bytes, hipStream_t stream) { return scratch_slot(1, bytes, stream); }
+inline void* pool_block(size_t bytes, hipStream_t stream) { return scratch_slot(0, bytes, stream); }
 
 // events around the integration kernel (aeb_timing_enable)
 void timing_begin(hipStream_t stream);

@@ -97,9 +97,10 @@ size_t plan_reduces(aeb_graph* g, size_t base) {
   return off;
 }
 
-int check_common(int precision, const aeb_reduce_req* req, aeb_stats* host_stats) {
-  if (precision != AEB_FP64 && precision != AEB_FP32C)
-    return fail(AEB_EINVAL, "graphs take AEB_FP64 or AEB_FP32C");
+int check_common(int precision, const aeb_reduce_req* req, aeb_stats* host_stats, bool batch) {
+  if (precision != AEB_FP64 && precision != AEB_FP32C && (batch || precision != AEB_FP32C_FIXUP))
+    return fail(AEB_EINVAL, batch ? "batched graphs take AEB_FP64 or AEB_FP32C"
+                                  : "graphs take AEB_FP64, AEB_FP32C or AEB_FP32C_FIXUP");
   if (req) {
     const int rc = check_reduce_req(*req);
     if (rc != AEB_OK) return rc;
@@ -124,7 +125,7 @@ int aeb_graph_create(const aeb_scenario* scn, const aeb_params* params, int prec
   if (!scn || !outputs_ok(out)) return fail(AEB_EINVAL, "aeb_graph_create: null argument");
   int rc = validate(*scn);
   if (rc != AEB_OK) return rc;
-  rc = check_common(precision, req, host_stats);
+  rc = check_common(precision, req, host_stats, false);
   if (rc != AEB_OK) return rc;
   if (!fast_path_applies(*scn, precision))
     return fail(AEB_EINVAL, "graphs record the block-structured path (not the unfused Euler "
@@ -179,7 +180,7 @@ int aeb_graph_create_batch(const aeb_scenario* scns, int n_scn, int precision,
   if (!out_graph) return fail(AEB_EINVAL, "aeb_graph_create_batch: null output");
   *out_graph = nullptr;
   if (!scns || !outs || n_scn < 1) return fail(AEB_EINVAL, "aeb_graph_create_batch: empty batch");
-  int rc = check_common(precision, req, host_stats);
+  int rc = check_common(precision, req, host_stats, true);
   if (rc != AEB_OK) return rc;
   for (int j = 0; j < n_scn; ++j) {
     rc = validate(scns[j]);

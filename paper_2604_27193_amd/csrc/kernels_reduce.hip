@@ -1049,7 +1049,7 @@ int reduce_fallback(const OutCols& out, int64_t n, const aeb_reduce_req& req, vo
 
 int launch_reduce(const OutCols& out, int64_t n, const aeb_reduce_req& req, aeb_stats* host_out,
                   hipStream_t st) {
-  void* base = scratch(reduce_scratch_bytes(n, req), st);
+  void* base = pool_block(reduce_scratch_bytes(n, req), st);
   if (!base) return AEB_ENOMEM;
   int rc = reduce_enqueue(out, n, req, base, host_out, st);
   if (rc != AEB_OK) return rc;

@@ -168,8 +168,11 @@ int aeb_autotune(const aeb_scenario* calib, int precision, const char* cache_pat
   if (rc != AEB_OK) return rc;
   if (precision != AEB_FP64 && precision != AEB_FP32C)
     return fail(AEB_EINVAL, "aeb_autotune: precision must be AEB_FP64 or AEB_FP32C");
+  // the tuned table serves explicit Euler in the fused form; RK4, the unfused
+  // form and the controller run fixed block sizes, so their timings would
+  // overwrite the Euler entry with noise
   if (!fast_path_applies(*calib, precision) || control_on(*calib) ||
-      (precision == AEB_FP64 && calib->nofma))
+      calib->integrator != AEB_EULER || (precision == AEB_FP64 && calib->nofma))
     return fail(AEB_EINVAL, "aeb_autotune: the scenario does not take the tuned block-structured path");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t n = calib->n_samples;
@@ -199,7 +202,10 @@ int aeb_autotune(const aeb_scenario* calib, int precision, const char* cache_pat
     std::vector<float> ms;
     for (int r = 0; r < 4 && rc == AEB_OK; ++r) {
       if (hipEventRecord(e0, st) != hipSuccess) rc = fail(AEB_EDEVICE, "event record failed");
-      if (rc == AEB_OK) rc = launch_rollout_fast(*calib, nullptr, precision, out, n, st);
+      if (rc == AEB_OK) {
+        ScratchScope scope(st);
+        rc = launch_rollout_fast(*calib, nullptr, precision, out, n, st);
+      }
       if (rc == AEB_OK && hipEventRecord(e1, st) != hipSuccess)
         rc = fail(AEB_EDEVICE, "event record failed");
       if (rc == AEB_OK && hipEventSynchronize(e1) != hipSuccess)

@@ -49,7 +49,7 @@ def eager_noise(B, torch):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32c", "rk4", "nofma"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "rk4", "nofma", "fp32c_fixup"])
 def test_graph_replays_equal_eager(B, prec):
     import torch
     d = W.single(30000, seed=12, scenario_id=3)
@@ -116,8 +116,8 @@ def test_graph_rejects(B):
     with pytest.raises(B.AebError) as e:   # the controller in a batched graph is not recorded
         B.Graph([W.single(100), W.closed_loop(100)], batch=True)
     assert e.value.code == B.EINVAL
-    with pytest.raises(B.AebError) as e:
-        B.Graph(W.single(100), precision="fp32c_fixup")
+    with pytest.raises(B.AebError) as e:   # the fix-up is recorded for one scenario only
+        B.Graph([W.single(100), W.single(200)], precision="fp32c_fixup", batch=True)
     assert e.value.code == B.EINVAL
 
 
