@@ -2,7 +2,10 @@
 
 Compiles ``aeb_oracle.c`` into ``liborc.so`` next to this file with gcc,
 ``-O2 -ffp-contract=off -fno-fast-math`` so that no multiply-add is fused
-except where the source calls ``fma`` explicitly.
+except where the source calls ``fma`` explicitly, and ``-fno-builtin`` so
+that each libm call is the function the source names (gcc would otherwise
+merge sin and cos of one argument into one sincos call, whose last bit
+differs from sin's and cos's for some arguments).
 """
 import os
 import subprocess
@@ -12,7 +15,7 @@ SRC = os.path.join(HERE, "aeb_oracle.c")
 HDR = os.path.join(HERE, "aeb_oracle.h")
 LIB = os.path.join(HERE, "liborc.so")
 
-CFLAGS = ["-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+CFLAGS = ["-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fno-builtin", "-fPIC", "-shared",
           "-Wall", "-Wextra", "-Wno-unused-parameter"]
 
 

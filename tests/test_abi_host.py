@@ -89,6 +89,20 @@ def test_host_sampler_bitwise(B, orc, d):
         assert np.array_equal(got[c].view(np.uint64), want[c].view(np.uint64)), c
 
 
+@pytest.mark.parametrize("name", ["single", "paper_preset", "perception", "rare_event"])
+def test_host_sampler_bitwise_full_size(B, orc, name):
+    """Every sample of the sizes the GPU tests and the benchmark run: the
+    grade's sine and cosine from host libm's sin and cos on both sides (a
+    compiler that merged them into one sincos call once gave a different
+    last bit for a few samples in a million)."""
+    n = {"single": 1_048_576, "paper_preset": 350_000}.get(name, 200_000)
+    d = getattr(W, name)(n)
+    got = B.sample_params(d, device=False)
+    want = orc.sample(d)
+    for c in B.COLUMNS:
+        assert np.array_equal(got[c].view(np.uint64), want[c].view(np.uint64)), c
+
+
 def test_host_sampler_subrange(B, orc):
     d = W.single(10_000)
     got = B.sample_params(d, 4321, 777, device=False)
