@@ -303,6 +303,28 @@ int aeb_sample_params(const aeb_scenario* scn, int64_t first, int64_t count, con
 int aeb_rollout(const aeb_scenario* scn, const aeb_params* params, int precision,
                 const aeb_outputs* out, void* stream);
 
+/* For callers that cannot allocate device memory while they run (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * aeb_rollout with the same arguments, results and errors, whose scratch is a
+ * fixed library-owned device array of AEB_NOALLOC_SCRATCH_BYTES per device
+ * instead of the growable pool.  The array holds the sorted path's per-sample
+ * job records, sort keys and permutation, command steps and FP32 fix-up list
+ * (80 bytes per sample, 88 with a lead vehicle, plus 33 KB): 32 MiB covers
+ * about 381,000 samples with a lead vehicle and 419,000 without.  A scenario
+ * that needs more returns AEB_ENOMEM (use aeb_rollout); nothing is enqueued
+ * then.  The call makes no hipMalloc/hipFree or other allocation and no
+ * synchronisation, so it can be captured into a caller's graph.  Each device
+ * holds its array from the library's first use of it until the process ends;
+ * every call on one device uses that device's array and overwrites it, so
+ * calls whose work overlaps on one device (two streams, two threads, or a
+ * call made before an earlier one's kernels have run) race and give wrong
+ * results: order them on one stream or synchronise between them.  The array
+ * keeps the last call's contents; the kernels clear what must start at zero.
+ * Asynchronous on `stream`. */
+#define AEB_NOALLOC_SCRATCH_BYTES (32LL << 20)
+int aeb_rollout_noalloc(const aeb_scenario* scn, const aeb_params* params, int precision,
+                        const aeb_outputs* out, void* stream);
+
 /* Batched rollout: all samples of n_scn scenarios in one sorted launch of the
  * persistent kernel (one lane per sample, wavefronts claiming chunks of the
  * length-sorted permutation), each sample's parameters drawn in-kernel from

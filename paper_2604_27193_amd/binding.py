@@ -15,6 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libaeb.so")
 ABI_VERSION = 5     # the aeb_version() these structures match
+NOALLOC_SCRATCH_BYTES = 32 << 20  # AEB_NOALLOC_SCRATCH_BYTES of aeb.h
 
 COLUMNS = ("v0", "mu", "mass", "grade", "sin_grade", "cos_grade", "cda", "crr", "tau", "gap",
            "lead_decel", "trigger", "log_weight")
@@ -33,7 +34,8 @@ OK, EINVAL, ENOMEM, EAGAIN, EDEVICE, ENOTFOUND = 0, -1, -2, -3, -4, -5
 END_STOP, END_IMPACT, END_HORIZON, COLLIDED, BOUNDARY = 1, 2, 3, 4, 8
 
 EXPORTS = ("aeb_last_error", "aeb_version", "aeb_validate", "aeb_uniforms", "aeb_sample_params",
-           "aeb_rollout", "aeb_reduce", "aeb_batch_rollout", "aeb_batch_reduce",
+           "aeb_rollout", "aeb_rollout_noalloc", "aeb_reduce", "aeb_batch_rollout",
+           "aeb_batch_reduce",
            "aeb_timing_enable", "aeb_timing_last", "aeb_server_fixed_bytes",
            "aeb_serve_footprint", "aeb_server_create", "aeb_server_destroy", "aeb_serve_submit",
            "aeb_serve_poll", "aeb_server_info_get", "aeb_graph_create", "aeb_graph_create_batch",
@@ -134,6 +136,8 @@ def lib():
         L.aeb_sample_params.argtypes = [P(Scenario), C.c_int64, C.c_int64, P(Params), C.c_int,
                                         C.c_void_p]
         L.aeb_rollout.argtypes = [P(Scenario), P(Params), C.c_int, P(Outputs), C.c_void_p]
+        L.aeb_rollout_noalloc.argtypes = [P(Scenario), P(Params), C.c_int, P(Outputs),
+                                          C.c_void_p]
         L.aeb_reduce.argtypes = [P(Outputs), P(ReduceReq), P(Stats), C.c_void_p]
         L.aeb_batch_rollout.argtypes = [P(Scenario), C.c_int, C.c_int, P(Outputs), C.c_void_p]
         L.aeb_batch_reduce.argtypes = [P(Outputs), C.c_int, P(ReduceReq), P(Stats), C.c_void_p]
@@ -310,6 +314,20 @@ def rollout(d, params=None, precision="fp64", out=None, stream=None):
     pp = C.byref(_params_struct(params, n)) if params is not None else None
     _check(lib().aeb_rollout(C.byref(s), pp, PRECISIONS[precision],
                              C.byref(_outputs_struct(out)), _stream(stream)))
+    return out
+
+
+def rollout_noalloc(d, params=None, precision="fp64", out=None, stream=None):
+    """rollout() through aeb_rollout_noalloc: the library's fixed per-device
+    scratch array instead of its growable pool (`out` must be preallocated
+    by callers that cannot allocate)."""
+    n = int(d["n_samples"])
+    if out is None:
+        out = alloc_outputs(n, weight=bool(d.get("proposal")))
+    s = scenario(d)
+    pp = C.byref(_params_struct(params, n)) if params is not None else None
+    _check(lib().aeb_rollout_noalloc(C.byref(s), pp, PRECISIONS[precision],
+                                     C.byref(_outputs_struct(out)), _stream(stream)))
     return out
 
 

@@ -333,6 +333,29 @@ using namespace aeb;
 
 namespace aeb {
 
+int rollout_args(const aeb_scenario* scn, const aeb_params* params, int precision,
+                 const aeb_outputs* out, ParamSrc* src) {
+  if (!scn || !outputs_complete(out)) return fail(AEB_EINVAL, "aeb_rollout: null argument");
+  int rc = validate(*scn);
+  if (rc != AEB_OK) return rc;
+  if (precision != AEB_FP64 && precision != AEB_FP32C && precision != AEB_FP32C_FIXUP)
+    return fail(AEB_EINVAL, "unknown precision");
+  if (out->n != scn->n_samples) return fail(AEB_EINVAL, "outputs length differs from n_samples");
+  *src = ParamSrc{};
+  if (params) {
+    if (!params_complete(params)) return fail(AEB_EINVAL, "aeb_rollout: incomplete parameter columns");
+    if (params->n != scn->n_samples) return fail(AEB_EINVAL, "parameter length differs from n_samples");
+    if (perception_on(*scn) && !params->trigger)
+      return fail(AEB_EINVAL, "aeb_rollout: a scenario with perception needs the trigger column");
+    if (scn->is_mask && !params->log_weight)
+      return fail(AEB_EINVAL, "aeb_rollout: importance sampling needs the log_weight column");
+    *src = ParamSrc{params->v0, params->mu,  params->mass, params->sin_grade, params->cos_grade,
+                    params->cda, params->crr, params->tau, params->gap, params->lead_decel,
+                    params->trigger, params->log_weight};
+  }
+  return AEB_OK;
+}
+
 int check_reduce_req(const aeb_reduce_req& req) {
   if (req.n_risk < 0 || req.n_risk > AEB_MAX_RISK || req.n_margin_q < 0 ||
       req.n_margin_q > AEB_MAX_MARGIN_Q || req.n_grid < 0 || req.n_grid > AEB_MAX_GRID ||
@@ -447,24 +470,9 @@ int aeb_sample_params(const aeb_scenario* scn, int64_t first, int64_t count, con
 
 int aeb_rollout(const aeb_scenario* scn, const aeb_params* params, int precision,
                 const aeb_outputs* out, void* stream) {
-  if (!scn || !outputs_complete(out)) return fail(AEB_EINVAL, "aeb_rollout: null argument");
-  int rc = validate(*scn);
-  if (rc != AEB_OK) return rc;
-  if (precision != AEB_FP64 && precision != AEB_FP32C && precision != AEB_FP32C_FIXUP)
-    return fail(AEB_EINVAL, "unknown precision");
-  if (out->n != scn->n_samples) return fail(AEB_EINVAL, "outputs length differs from n_samples");
   ParamSrc src{};
-  if (params) {
-    if (!params_complete(params)) return fail(AEB_EINVAL, "aeb_rollout: incomplete parameter columns");
-    if (params->n != scn->n_samples) return fail(AEB_EINVAL, "parameter length differs from n_samples");
-    if (perception_on(*scn) && !params->trigger)
-      return fail(AEB_EINVAL, "aeb_rollout: a scenario with perception needs the trigger column");
-    if (scn->is_mask && !params->log_weight)
-      return fail(AEB_EINVAL, "aeb_rollout: importance sampling needs the log_weight column");
-    src = ParamSrc{params->v0, params->mu,  params->mass, params->sin_grade, params->cos_grade,
-                   params->cda, params->crr, params->tau, params->gap, params->lead_decel,
-                   params->trigger, params->log_weight};
-  }
+  const int rc = rollout_args(scn, params, precision, out, &src);
+  if (rc != AEB_OK) return rc;
   OutCols oc{out->dist, out->status, out->steps, out->margin, out->v_impact, out->weight};
   ScratchScope scope(static_cast<hipStream_t>(stream));
   return launch_rollout(*scn, params ? &src : nullptr, precision, oc, scn->n_samples,

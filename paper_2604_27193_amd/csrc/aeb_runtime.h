@@ -110,4 +110,9 @@ int reduce_fallback(const OutCols& out, int64_t n, const aeb_reduce_req& req, vo
                     aeb_stats* host_out, hipStream_t stream);
 int check_reduce_req(const aeb_reduce_req& req);
 
+// Argument checks of aeb_rollout (scenario, precision, column lengths) and the
+// kernel view of the parameter columns (all null for the in-kernel generator).
+int rollout_args(const aeb_scenario* scn, const aeb_params* params, int precision,
+                 const aeb_outputs* out, ParamSrc* src);
+
 }  // namespace aeb
