@@ -49,21 +49,39 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def measured_traffic():
-    """HBM bytes per launch of the integration kernel from the committed
-    counter summary, or None if the kernel source changed since."""
+def profile_field(name, key, cast=float):
+    """A figure from the machine-readable block of a committed rocprofv3
+    summary under profiles/, or None if the kernel source it was taken on has
+    changed since (its sha1 differs) or the summary is missing."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "rollout_fp64_1M_hbm_traffic.md")
+    path = os.path.join(ROOT, "profiles", name)
     try:
         txt = open(path).read()
         src = re.search(r"kernel_source: (\S+)", txt).group(1)
         sha = re.search(r"source_sha1: ([0-9a-f]+)", txt).group(1)
-        traffic = int(re.search(r"traffic_bytes_per_launch: (\d+)", txt).group(1))
+        val = cast(re.search(key + r": ([0-9.eE+-]+)", txt).group(1))
         now = hashlib.sha1(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
-    except (OSError, AttributeError):
+    except (OSError, AttributeError, ValueError):
         return None
-    return traffic if now == sha else None
+    return val if now == sha else None
+
+
+def measured_traffic():
+    """HBM bytes per launch of the integration kernel from the committed
+    counter summary, or None if the kernel source changed since."""
+    return profile_field("rollout_fp64_1M_hbm_traffic.md", "traffic_bytes_per_launch", int)
+
+
+def cpu_model():
+    """The host CPU's model name (as lscpu reports it)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def time_steps(B, torch, d, params, precision, out, steps, warmup):
@@ -171,6 +189,7 @@ def cpu_baseline(d, budget_samples, single_samples=10_000):
     oracle.run(d, first=0, count=m, threads=1)
     el1 = time.perf_counter() - t0
     return {"value": n / el, "unit": "rollouts/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus_visible": os.cpu_count(),
             "sample": f"samples 0..{n - 1} of the same scenario on {threads} threads "
                       f"({el:.2f} s wall); single thread over samples 0..{m - 1}: "
                       f"{m / el1:.0f} rollouts/s ({el1:.2f} s)",
@@ -533,6 +552,92 @@ def serving_leg(B, W, precision, rates, duration, arena_gib=4):
     return res
 
 
+def plain_end_to_end(B, torch, d, n, cols, reps=3):
+    """The paper's plain method as one figure (Sec. IV-C, V-B): parameters
+    drawn on the host cores into pinned memory, copied to HBM, the rollout,
+    the reduction and its statistics back on the host, timed from the start
+    of the sampling to the statistics in host memory; median of `reps`."""
+    import numpy as np
+    host = B.alloc_params(n, device=False, pinned=True)
+    params = {c: torch.empty(n, dtype=torch.float64, device="cuda") for c in cols}
+    out = B.alloc_outputs(n)
+    rows = []
+    for r in range(reps + 1):  # the first pass pays one-time costs
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.sample_params(d, device=False, out=host)
+        t1 = time.perf_counter()
+        for c in cols:
+            params[c].copy_(host[c], non_blocking=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        B.rollout(d, params=params, out=out)
+        B.reduce(out, risk=RISK, margin_q=MARGIN_Q, grid=GRID)
+        t3 = time.perf_counter()
+        if r:
+            rows.append((t3 - t0, t1 - t0, t2 - t1, t3 - t2))
+    tot, samp, h2d, dev = (float(np.median([x[j] for x in rows])) for j in range(4))
+    return {"what": "host sampling + H2D copy + rollout + reduction + statistics D2H, one pass",
+            "ms": tot * 1e3, "rollouts_per_s": n / tot, "host_sampling_ms": samp * 1e3,
+            "h2d_ms": h2d * 1e3, "rollout_and_reduce_ms": dev * 1e3,
+            "host_sampling_threads": os.cpu_count()}
+
+
+def saturated_leg(B, W, torch, seconds, depth=64):
+    """The serving mix (25k/100k/1M samples at 70/25/5 %) submitted back to
+    back so that `depth` requests are always waiting or running, for
+    `seconds`, once in FP32C and once in FP64: the rollouts/s each served
+    form delivers when the device never idles, its latency under that load,
+    and the FP32C statistics against the FP64 ones of the same requests."""
+    import numpy as np
+    reqs = [(d, dl) for _, d, dl in W.serving_stream(800, duration=120.0, seed=4242)]
+    res = {"workload": "serving mix, requests back to back, %d in flight" % depth,
+           "seconds": seconds}
+    stats = {}
+    for prec in ("fp32c", "fp64"):
+        with B.Server(4 << 30, precision=prec, max_slots=256, n_streams=3, tick_us=200,
+                      max_tick_samples=1 << 22, risk=RISK, margin_q=MARGIN_Q, grid=GRID) as srv:
+            srv.wait(srv.submit(W.single(25_000, seed=1, scenario_id=1)))
+            pending, done, k = {}, {}, 0
+            t0 = time.perf_counter()
+            t_end = t0 + seconds
+            while time.perf_counter() < t_end:
+                while len(pending) < depth and k < len(reqs):
+                    pending[srv.submit(reqs[k][0], deadline=reqs[k][1])] = k
+                    k += 1
+                for t in list(pending):
+                    r = srv.poll(t)
+                    if r is not None:
+                        done[pending.pop(t)] = r
+                time.sleep(5e-5)
+            # requests completed inside the window count; the rest drain unmeasured
+            t_stop = time.perf_counter()
+            in_window = {j: r for j, r in done.items()}
+            while pending:
+                for t in list(pending):
+                    r = srv.poll(t)
+                    if r is not None:
+                        done[pending.pop(t)] = r
+                time.sleep(1e-4)
+        samples = sum(int(reqs[j][0]["n_samples"]) for j in in_window)
+        lat = np.array([tm["done"] - tm["arrive"] for _, tm in in_window.values()])
+        res[prec] = {"requests": len(in_window), "rollouts_per_s": samples / (t_stop - t0),
+                     "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                     "p99_ms": float(np.percentile(lat, 99) * 1e3)}
+        stats[prec] = {j: st for j, (st, _) in done.items()}
+        log(f"bench: saturated {prec}: {res[prec]}")
+    common = sorted(set(stats["fp32c"]) & set(stats["fp64"]))
+    dp = [abs(stats["fp32c"][j]["p_collision"] - stats["fp64"][j]["p_collision"]) for j in common]
+    dh = [abs(stats["fp32c"][j]["headway"][0] - stats["fp64"][j]["headway"][0])
+          / stats["fp64"][j]["headway"][0] for j in common]
+    nb = [stats["fp32c"][j]["n_boundary"] / stats["fp32c"][j]["n"] for j in common]
+    res["fp32c_over_fp64"] = res["fp32c"]["rollouts_per_s"] / res["fp64"]["rollouts_per_s"]
+    res["accuracy_fp32c_vs_fp64"] = {
+        "requests_compared": len(common), "max_abs_diff_p_collision": float(max(dp)),
+        "max_rel_diff_headway_5pct": float(max(dh)), "max_boundary_fraction": float(max(nb))}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -543,11 +648,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch leg")
     ap.add_argument("--headline-only", action="store_true",
-                    help="only the headline step loops (FP64, FP32C, graphs): no RK4, N-sweep, "
-                         "paper-study or perception legs (for profiler runs, whose per-kernel "
-                         "averages would otherwise mix launch sizes)")
-    ap.add_argument("--serve-seconds", type=float, default=5.0,
-                    help="length of each serving stream (0: no serving leg)")
+                    help="only the eager FP64 step loop on one stream (for profiler runs: "
+                         "every integration-kernel launch is then one of the timed steps)")
+    ap.add_argument("--fp32c-only", action="store_true",
+                    help="only the eager FP32C step loop (for counter runs of that kernel)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of each Poisson serving stream (0: no serving leg)")
+    ap.add_argument("--saturate-seconds", type=float, default=10.0,
+                    help="length of each saturated serving run, FP32C and FP64 (0: none)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic for scaling hardware byte counters)")
@@ -592,9 +700,55 @@ def main():
         t_h2d = min(t_h2d, time.perf_counter() - t0)
     out = B.alloc_outputs(n)
 
+    if args.fp32c_only:
+        out32 = B.alloc_outputs(n)
+        wall32, k32, c32, st32 = time_steps(B, torch, d, params, "fp32c", out32, args.steps,
+                                            args.warmup)
+        print(json.dumps({"fp32c_kernel_ms": float(np.mean(k32)), "steps": args.steps}),
+              flush=True)
+        return
     log("bench: fp64 timed loop")
     wall64, k64, c64, st64 = time_steps(B, torch, d, params, "fp64", out, args.steps, args.warmup)
     steps_total = int(out["steps"].to(torch.int64).sum().item())
+    kavg64 = float(np.mean(k64)) * 1e-3
+    flops64 = EULER_FLOPS_PER_STEP * steps_total
+    achieved = flops64 / kavg64 / 1e12
+    prof_us = profile_field("rollout_fp64_1M_kernel_stats.md", "k_roll_fp64_avg_us")
+    issued = profile_field("rollout_valu_counters_1M.md", "issued_fp64_flop_per_step")
+    roofline = {
+        "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+        "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+        "traffic": measured_traffic() if n == 1_048_576 else None,
+        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+        "algorithmic_bytes_per_launch": 93 * n,
+        "kernel": "k_roll_fp64 (block-structured explicit Euler, FP64)",
+        "kernel_ms": kavg64 * 1e3, "kernel_ms_source": "HIP events on the launch stream",
+        "flops_per_launch": flops64, "steps_per_launch": steps_total,
+        "flops_per_step": EULER_FLOPS_PER_STEP,
+        # the committed rocprofv3 kernel-trace summary of the --headline-only
+        # loop (same kernel source), and the FP64 flops the VALU counters saw
+        # issued per step (the clamped and dead-time forms skip the actuator
+        # update, which cannot change the result)
+        "profile_kernel_ms": prof_us * 1e-3 if (prof_us and n == 1_048_576) else None,
+        "frac_from_profile": (flops64 / (prof_us * 1e-6) / 1e12 / FP64_VECTOR_PEAK_TFLOPS
+                              if (prof_us and n == 1_048_576) else None),
+        "issued_flops_per_step": issued,
+        "issued_frac": (issued * steps_total / kavg64 / 1e12 / FP64_VECTOR_PEAK_TFLOPS
+                        if issued else None),
+    }
+    if args.headline_only:
+        res = {"metric": METRIC, "value": args.steps * n / wall64, "unit": "rollouts/s",
+               "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+               "ms_per_step": wall64 / args.steps * 1e3, "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+               "config": {"workload": f"single stationary-obstacle scenario, {n} samples, "
+                                      "eager FP64 loop only (profiling run)",
+                          "n_samples": n},
+               "roofline": roofline, "cpu_baseline": None}
+        print(json.dumps(res), flush=True)
+        return
+    log("bench: plain method end to end")
+    e2e = plain_end_to_end(B, torch, d, n, cols)
     log("bench: fp32c timed loop")
     out32 = B.alloc_outputs(n)
     wall32, k32, c32, st32 = time_steps(B, torch, d, params, "fp32c", out32, args.steps,
@@ -619,10 +773,7 @@ def main():
                                                           (out, out2), args.steps, args.warmup)
     pipe_equal = p_same and same_stats(st64, stp64)
 
-    kavg64 = float(np.mean(k64)) * 1e-3
     kavg32 = float(np.mean(k32)) * 1e-3
-    flops64 = EULER_FLOPS_PER_STEP * steps_total
-    achieved = flops64 / kavg64 / 1e12
     # the step as a production caller repeats it: the fastest of the eager
     # calls, the recorded graph and the recorded graphs on two streams, among
     # those whose statistics equal the eager ones
@@ -634,22 +785,20 @@ def main():
     step_path, step_wall = min(paths, key=lambda p: p[1])
     value = args.steps * n / step_wall
 
-    rk4 = unfused = nsweep = study = perception = control = rare = None
-    if not args.headline_only:
-        log("bench: rk4 leg")
-        rk4 = rk4_leg(B, W, torch, n)
-        log("bench: unfused Euler leg")
-        unfused = unfused_leg(B, W, torch, n)
-        log("bench: N sweep")
-        nsweep = n_sweep_leg(B, W, torch)
-        log("bench: paper-preset study")
-        study = paper_study_leg(B, W, torch)
-        log("bench: perception leg")
-        perception = perception_leg(B, W, torch, n)
-        log("bench: controller leg")
-        control = control_leg(B, W, torch, n)
-        log("bench: rare-event leg")
-        rare = rare_event_leg(B, W, torch, n)
+    log("bench: rk4 leg")
+    rk4 = rk4_leg(B, W, torch, n)
+    log("bench: unfused Euler leg")
+    unfused = unfused_leg(B, W, torch, n)
+    log("bench: N sweep")
+    nsweep = n_sweep_leg(B, W, torch)
+    log("bench: paper-preset study")
+    study = paper_study_leg(B, W, torch)
+    log("bench: perception leg")
+    perception = perception_leg(B, W, torch, n)
+    log("bench: controller leg")
+    control = control_leg(B, W, torch, n)
+    log("bench: rare-event leg")
+    rare = rare_event_leg(B, W, torch, n)
 
     batch = None
     if not args.no_batch:
@@ -657,12 +806,15 @@ def main():
         batch = batch_leg(B, W, torch)
 
     serving = None
-    if args.serve_seconds > 0:
-        log("bench: serving streams")
+    if args.serve_seconds > 0 or args.saturate_seconds > 0:
         serving = {"precision": "fp32c", "deadline_ms": 530.0,
-                   "duration_s": args.serve_seconds,
-                   "rates": serving_leg(B, W, "fp32c", (50, 200, 800), args.serve_seconds),
-                   "fp64_at_800": serving_leg(B, W, "fp64", (800,), args.serve_seconds)}
+                   "duration_s": args.serve_seconds}
+        if args.serve_seconds > 0:
+            log("bench: serving streams")
+            serving["rates"] = serving_leg(B, W, "fp32c", (50, 200, 800), args.serve_seconds)
+        if args.saturate_seconds > 0:
+            log("bench: saturated serving")
+            serving["saturated"] = saturated_leg(B, W, torch, args.saturate_seconds)
 
     cpu = None
     if not args.no_cpu:
@@ -689,16 +841,7 @@ def main():
             "n_samples": n, "integrator": "euler", "precision": "fp64",
             "step_path": step_path,
         },
-        "roofline": {
-            "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-            "traffic": measured_traffic() if n == 1_048_576 else None,
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-            "algorithmic_bytes_per_launch": 93 * n,
-            "kernel": "k_roll_fp64 (block-structured explicit Euler, FP64)",
-            "kernel_ms": kavg64 * 1e3, "flops_per_launch": flops64,
-            "steps_per_launch": steps_total, "flops_per_step": EULER_FLOPS_PER_STEP,
-        },
+        "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64": {
             "eager_ms_per_step": wall64 / args.steps * 1e3,
@@ -742,6 +885,7 @@ def main():
         "serving": serving,
         "plain_method_host": {"sampling_s": t_sample, "h2d_s": t_h2d,
                               "h2d_GBps": len(cols) * 8 * n / t_h2d / 1e9},
+        "plain_method_end_to_end": e2e,
         "stats": {"p_collision": st64["p_collision"], "mean_dist": st64["mean_dist"],
                   "sd_dist": st64["sd_dist"], "headways": st64["headway"],
                   "p_collision_fp32c": st32["p_collision"],
