@@ -452,7 +452,8 @@ def batch_leg(B, W, torch, reps=2):
     """Batched launches: the 256-scenario lead-vehicle sweep (100,000 samples
     each) and 1,000 scenarios of uneven size, horizon and step; parameters
     drawn in-kernel; rollouts/s of the batched rollout call (events on the
-    stream), FP64 and FP32C, and the error of the FP32C P(collision)."""
+    stream), FP64 and FP32C, and the error of the FP32C P(collision) and p99
+    distance against FP64 per scenario."""
     import numpy as np
     res = {}
     for name, scns in (("sweep_256x100k_lead", W.sweep(n=100_000)),
@@ -488,6 +489,73 @@ def batch_leg(B, W, torch, reps=2):
         del outs
         torch.cuda.empty_cache()
     return res
+
+
+def uneven_config_leg(B, W, torch, reps=3):
+    """The 1,000-scenario uneven batch as specified: FP32C, launch shape chosen
+    by the autotuner (calibrated on the batch's largest scenario; its choice
+    and the runner-up reported), every step the batched rollout plus the
+    statistics of every scenario, timed as eager calls and as a replay of one
+    recorded graph (same kernels, statistics equal)."""
+    import numpy as np
+    scns = W.uneven_batch(1000)
+    total = sum(int(d["n_samples"]) for d in scns)
+    big = max(scns, key=lambda d: int(d["n_samples"]))
+    keep = B.tune_get("fp32c", "stationary")
+    default_ms = None
+    try:
+        # the default shape's time on the calibration scenario, then the sweep
+        out = B.alloc_outputs(int(big["n_samples"]))
+        B.rollout(big, precision="fp32c", out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(4):
+            B.rollout(big, precision="fp32c", out=out)
+        torch.cuda.synchronize()
+        default_ms = (time.perf_counter() - t0) / 4 * 1e3
+        del out
+        best_ms = B.autotune(big, "fp32c")
+        ranked = B.tune_results("fp32c", "stationary")
+        chosen = B.tune_get("fp32c", "stationary")
+        outs = [B.alloc_outputs(int(d["n_samples"])) for d in scns]
+        # eager: batched rollout + segmented statistics, synchronised per step
+        B.batch_reduce(B.batch_rollout(scns, precision="fp32c", outs=outs), risk=RISK,
+                       margin_q=MARGIN_Q, grid=GRID)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st_e = B.batch_reduce(B.batch_rollout(scns, precision="fp32c", outs=outs),
+                                  risk=RISK, margin_q=MARGIN_Q, grid=GRID)
+        eager_ms = (time.perf_counter() - t0) / reps * 1e3
+        # one recorded graph of the same step
+        g = B.Graph(scns, precision="fp32c", out=outs, risk=RISK, margin_q=MARGIN_Q, grid=GRID,
+                    batch=True)
+        g.launch()
+        g.finish()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g.launch()
+            st_g = g.finish()
+        graph_ms = (time.perf_counter() - t0) / reps * 1e3
+        g.close()
+        same = all(a["headway"] == b["headway"] and a["n_collide"] == b["n_collide"] and
+                   a["mean_dist"] == b["mean_dist"] for a, b in zip(st_e, st_g))
+        del outs
+        torch.cuda.empty_cache()
+    finally:
+        B.tune_set("fp32c", "stationary", *keep)
+    return {"workload": "1,000 scenarios from seed 7: N log-uniform in [1e3, 1e6], horizon "
+                        "U(3, 15) s, dt in {0.5, 1, 2} ms, stationary obstacle; FP32C; step = "
+                        "batched rollout + statistics of every scenario",
+            "scenarios": len(scns), "samples": total,
+            "tuner": {"calibration": f"largest scenario, {int(big['n_samples'])} samples",
+                      "chosen": {"shape": list(chosen), "ms": best_ms},
+                      "runner_up": ({"shape": list(ranked[1][0]), "ms": ranked[1][1]}
+                                    if len(ranked) > 1 else None),
+                      "candidates": len(ranked), "default_shape_ms": default_ms},
+            "eager_ms_per_step": eager_ms, "eager_rollouts_per_s": total / (eager_ms * 1e-3),
+            "graph_ms_per_step": graph_ms, "graph_rollouts_per_s": total / (graph_ms * 1e-3),
+            "graph_stats_equal_eager": same}
 
 
 def serving_leg(B, W, precision, rates, duration, arena_gib=4):
@@ -800,10 +868,12 @@ def main():
     log("bench: rare-event leg")
     rare = rare_event_leg(B, W, torch, n)
 
-    batch = None
+    batch = uneven = None
     if not args.no_batch:
         log("bench: batched launches")
         batch = batch_leg(B, W, torch)
+        log("bench: uneven batch as specified (tuned FP32C, graph and eager, statistics)")
+        uneven = uneven_config_leg(B, W, torch)
 
     serving = None
     if args.serve_seconds > 0 or args.saturate_seconds > 0:
@@ -882,6 +952,7 @@ def main():
         "control": control,
         "rare_event": rare,
         "batch": batch,
+        "uneven_batch_config": uneven,
         "serving": serving,
         "plain_method_host": {"sampling_s": t_sample, "h2d_s": t_h2d,
                               "h2d_GBps": len(cols) * 8 * n / t_h2d / 1e9},

@@ -237,13 +237,19 @@ typedef struct {
   double risk_se[AEB_MAX_GRID];
 } aeb_stats;
 
-/* Message of the last failure on this thread ("" if none). */
+/* Message of the last failure on this thread ("" if none).  Library
+ * plumbing; no passage of the paper defines it. */
 const char* aeb_last_error(void);
 
-/* Library ABI version (increments on incompatible changes). */
+/* Library ABI version (increments on incompatible changes).  Library
+ * plumbing; no passage of the paper defines it. */
 int aeb_version(void);
 
 /* Validate a scenario: AEB_OK or AEB_EINVAL (with aeb_last_error() set).
+ * The physical constraints come from the model of Sec. III: a positive
+ * actuator time constant (eq. (6)), a positive wheelbase (eq. (5)), a step
+ * that the explicit update of eq. (7)-(9) keeps stable (dt <= tau); the
+ * others bound what the kernels' integer step counters can hold.
  * Rejects N outside [1, 2^31-1]; dt, horizon not positive and finite;
  * horizon/dt outside [1, 2^31-1]; negative dead_time; wheelbase <= 0; unknown
  * enums; non-finite distribution parameters, sd < 0, uniform p0 > p1,
@@ -325,7 +331,11 @@ int aeb_rollout(const aeb_scenario* scn, const aeb_params* params, int precision
 int aeb_rollout_noalloc(const aeb_scenario* scn, const aeb_params* params, int precision,
                         const aeb_outputs* out, void* stream);
 
-/* Batched rollout: all samples of n_scn scenarios in one sorted launch of the
+/* Batched rollout (an extension: the paper evaluates one scenario per launch,
+ * Sec. V-A; many small launches sit in its kernel-overhead regime, Sec. VI-E,
+ * and one launch over many scenarios leaves it).  Each sample is the rollout
+ * of aeb_rollout (Sec. IV-D, V).
+ * All samples of n_scn scenarios in one sorted launch of the
  * persistent kernel (one lane per sample, wavefronts claiming chunks of the
  * length-sorted permutation), each sample's parameters drawn in-kernel from
  * (seed, scenario_id, index) of its scenario.  Scenarios may differ in every
@@ -341,19 +351,36 @@ int aeb_rollout_noalloc(const aeb_scenario* scn, const aeb_params* params, int p
 int aeb_batch_rollout(const aeb_scenario* scns, int n_scn, int precision, const aeb_outputs* outs,
                       void* stream);
 
-/* aeb_reduce for each of n_scn output sets: stats[j] (host array) receives the
- * statistics of outs[j] under the same request.  Waits for completion. */
+/* The statistics of Sec. VI (eq. (20), Sec. VI-B, VI-C) per scenario of a
+ * batch: stats[j] (host array of n_scn) receives exactly what aeb_reduce(outs[j],
+ * req) gives, bit for bit.  The sets are reduced together: every kernel of the
+ * reduction covers a group of consecutive sets (each with its own scratch,
+ * up to 256 MiB of scratch per group), so a batch of many small scenarios
+ * costs a few launch sequences rather than one per scenario.  Sets with and
+ * without importance-sampling weights may be mixed.  Uses the scratch pool;
+ * waits for completion. */
 int aeb_batch_reduce(const aeb_outputs* outs, int n_scn, const aeb_reduce_req* req,
                      aeb_stats* stats, void* stream);
 
-/* Profiling aid.  While enabled on the calling thread, aeb_rollout brackets
+/* Profiling aid for the GPU execution time the paper measures (Sec. VI-E,
+ * eq. (17)).  While enabled on the calling thread, aeb_rollout brackets
  * its integration kernel with two HIP events on its stream; aeb_timing_last
  * waits for the second and returns the kernel's duration in milliseconds for
  * the last aeb_rollout call of this thread (AEB_EAGAIN if there was none). */
 int aeb_timing_enable(int on);
 int aeb_timing_last(float* ms);
 
-/* Statistics of `out` (device columns, out->n >= 1) as described for
+/* Metric of the exact order statistics (Sec. VI-C headways, margin
+ * quantiles): the number of reductions (aeb_reduce, aeb_batch_reduce per set,
+ * graphs, serving) since the library was loaded whose selection fell back
+ * from the in-LDS sort of one value bin (a bin with more than 8,192 samples,
+ * e.g. many equal values) to the radix select over the whole array. */
+int aeb_reduce_fallbacks(uint64_t* count);
+
+/* The statistics of Sec. VI: P(collision) = P(D_stop > H0) (eq. (20)), the
+ * risk curve and minimum safe headways (Sec. VI-C), moments of D_stop
+ * (Sec. VI-B, Table I), margins.
+ * Statistics of `out` (device columns, out->n >= 1) as described for
  * aeb_stats/aeb_reduce_req.  Kernels run on `stream`; the function waits for
  * them and fills *host_out before returning. */
 int aeb_reduce(const aeb_outputs* out, const aeb_reduce_req* req, aeb_stats* host_out,
@@ -362,23 +389,38 @@ int aeb_reduce(const aeb_outputs* out, const aeb_reduce_req* req, aeb_stats* hos
 /* ---- launch shapes and the autotuner ----
  *
  * The block-structured integration kernel (Sec. V's one-thread-per-sample
- * mapping, reorganised as described for aeb_rollout) has three launch
+ * mapping, reorganised as described for aeb_rollout) has four launch
  * parameters per precision (AEB_FP64, AEB_FP32C) and obstacle kind: k, the
  * steps per unchecked block (16, 32 or 64; AEB_FP64 also 128), the workgroup
- * size (64, 128, 256), and waves_per_simd (0: one workgroup per `block`
- * samples in one pass; 1..32: a persistent grid of that many wavefronts per
- * SIMD claiming 64-sample chunks).  Results do not depend on them.  The
- * table starts from built-in defaults; if the environment variable
- * AEB_TUNE_CACHE names a cache file it is loaded at first use. */
-int aeb_tune_get(int precision, int obstacle, int32_t* k, int32_t* block,
-                 int32_t* waves_per_simd);
-int aeb_tune_set(int precision, int obstacle, int32_t k, int32_t block, int32_t waves_per_simd);
+ * size (64, 128, 256), waves_per_simd (0: one workgroup per `block` (or
+ * 2 x `block`) samples in one pass; 1..32: a persistent grid of that many
+ * wavefronts per SIMD claiming chunks of 64 (or 128) samples), and
+ * samples_per_thread (1; or 2 for AEB_FP64 explicit Euler in the fused form
+ * without a lead vehicle or controller: each lane integrates two sorted
+ * samples, interleaving their steps; other scenarios of such an entry run
+ * one sample per lane).  Results do not depend on them.  The table starts
+ * from built-in defaults; if the environment variable AEB_TUNE_CACHE names a
+ * cache file it is loaded at first use. */
+typedef struct {
+  int32_t k, block, waves_per_simd, samples_per_thread;
+} aeb_tune_shape;
+int aeb_tune_get(int precision, int obstacle, aeb_tune_shape* shape);
+int aeb_tune_set(int precision, int obstacle, const aeb_tune_shape* shape);
 
-/* Load a cache written by aeb_autotune (AEB_EINVAL for a missing or malformed
+/* The candidates the last aeb_autotune on this (precision, obstacle) timed,
+ * fastest first: *count of them; the first min(max, *count) shapes and their
+ * median times (ms, whole rollout call) are written to shapes and ms. */
+int aeb_tune_results(int precision, int obstacle, aeb_tune_shape* shapes, float* ms, int max,
+                     int* count);
+
+/* (The launch configuration of Sec. V-A: block size and threads per sample.)
+ * Load a cache written by aeb_autotune (AEB_EINVAL for a missing or malformed
  * file; entries are validated before any is used). */
 int aeb_tune_load(const char* path);
 
-/* Time every candidate shape on `calib` (parameters drawn in-kernel; a few
+/* (Sec. V-A fixes one launch configuration, 256 threads per block, one
+ * thread per sample; this chooses it by measurement on this GPU.)
+ * Time every candidate shape on `calib` (parameters drawn in-kernel; a few
  * launches each, synchronous on `stream`), keep the fastest for (precision,
  * calib->obstacle), return its time for the whole rollout call in *best_ms
  * (may be NULL) and, if cache_path is not NULL, write the table as JSON. */
@@ -403,7 +445,9 @@ int aeb_autotune(const aeb_scenario* calib, int precision, const char* cache_pat
  * a horizon plus dead time beyond 2^31 - 4096 steps. */
 typedef struct aeb_graph aeb_graph;
 
-/* One scenario: params (device columns, or NULL for the in-kernel generator),
+/* (Removes the per-launch overhead the paper identifies at small N,
+ * Sec. VI-E; the recorded work is that of aeb_rollout and aeb_reduce.)
+ * One scenario: params (device columns, or NULL for the in-kernel generator),
  * out (device outputs, n_samples long), req (NULL: rollout only) and
  * host_stats: pinned host memory (hipHostMalloc) that each replay's
  * statistics are copied into; valid after aeb_graph_finish. */
@@ -411,19 +455,51 @@ int aeb_graph_create(const aeb_scenario* scn, const aeb_params* params, int prec
                      const aeb_outputs* out, const aeb_reduce_req* req, aeb_stats* host_stats,
                      aeb_graph** graph);
 
-/* A fixed mix of n_scn scenarios as one batched launch (as aeb_batch_rollout)
- * followed by one reduction per scenario into host_stats[j] (pinned, n_scn). */
+/* (As aeb_graph_create, for the batched launch.)
+ * A fixed mix of n_scn scenarios as one batched launch (as aeb_batch_rollout)
+ * followed by the statistics of every scenario (the segmented reduction of
+ * aeb_batch_reduce, all sets in one launch sequence) into host_stats[j]
+ * (pinned, n_scn). */
 int aeb_graph_create_batch(const aeb_scenario* scns, int n_scn, int precision,
                            const aeb_outputs* outs, const aeb_reduce_req* req,
                            aeb_stats* host_stats, aeb_graph** graph);
 
-/* Enqueue one replay on `stream` (asynchronous). */
+/* (A batched launch of changing mixes -- the serving path's steady-state
+ * ticks, Sec. VI-F -- without the per-kernel launch cost, Sec. VI-E.)
+ * A recording that replays ANY mix of up to max_scn scenarios with at most
+ * max_samples samples in all, each of the kind of `kind` (the same
+ * integrator, obstacle, impact_exit and nofma; perception allowed in the mix
+ * only if `kind` has it; importance sampling only if `kind` has it): the
+ * batched rollout of aeb_batch_rollout and, if req is not NULL, the
+ * statistics of every scenario (aeb_batch_reduce).  Every grid covers the
+ * capacity and the kernels read the mix's sizes from device tables, which
+ * the graph's first nodes copy from pinned memory the graph owns, so a
+ * replay only rewrites those tables.  The graph owns its device memory
+ * (tables, rollout and reduction scratch for the capacity).  precision:
+ * AEB_FP64 or AEB_FP32C.  AEB_EINVAL for a kind the batched path cannot run
+ * (the closed-loop controller, RK4 in FP32C). */
+int aeb_graph_create_mix(const aeb_scenario* kind, int precision, int max_scn,
+                         int64_t max_samples, const aeb_reduce_req* req, aeb_graph** graph);
+
+/* Replay a mix graph for n_scn scenarios (host array, each fitting the
+ * graph's kind and capacity) with outputs outs[j] (device columns,
+ * outs[j].n == scns[j].n_samples).  Asynchronous on `stream`; results equal
+ * aeb_batch_rollout (and aeb_batch_reduce) of the same mix bit for bit.
+ * host_stats (host array of n_scn, may be pageable; NULL if the graph has no
+ * statistics) is filled by aeb_graph_finish, which must follow every replay
+ * before the next (the replay reads the graph's pinned tables). */
+int aeb_graph_launch_mix(aeb_graph* graph, const aeb_scenario* scns, int n_scn,
+                         const aeb_outputs* outs, aeb_stats* host_stats, void* stream);
+
+/* Enqueue one replay on `stream` (asynchronous).  (Graph plumbing; no
+ * passage of the paper.) */
 int aeb_graph_launch(aeb_graph* graph, void* stream);
 
 /* Wait for `stream`; where a replay's order statistics needed the radix
  * fallback (rare), compute it; afterwards host_stats holds the statistics. */
 int aeb_graph_finish(aeb_graph* graph, void* stream);
 
+/* Release the graph, its scratch and pinned tables (graph plumbing). */
 int aeb_graph_destroy(aeb_graph* graph);
 
 /* ---- serving: continuous batching of evaluation requests ----
@@ -434,7 +510,8 @@ int aeb_graph_destroy(aeb_graph* graph);
  * arrive, admits them in arrival order while their device footprint fits the
  * free part of a caller-provided arena and a slot is free, packs admitted
  * requests of one kind (integrator, obstacle, impact_exit, nofma) into one
- * sorted multi-scenario launch followed by one reduction per request, and
+ * sorted multi-scenario launch followed by one segmented reduction over its
+ * requests (as aeb_batch_reduce), and
  * rotates launches over its streams so that work overlaps on the device.  A
  * request's statistics equal those of aeb_rollout (params == NULL) plus
  * aeb_reduce on the same scenario alone, bit for bit.  A worker thread of
@@ -455,9 +532,18 @@ typedef struct aeb_server aeb_server;
  *   tick_us: while a launch is in flight, admitted requests wait up to this
  *     long (0..1e6 us) for others to share their launch.
  *   max_queue: waiting requests beyond which submit returns AEB_EAGAIN.
+ *   flags: 0, or AEB_SERVE_EAGER to issue every launch's copies and kernels
+ *     one by one instead of replaying a recorded graph (for comparison).
+ *     By default a launch replays a HIP graph recorded once per stream and
+ *     bucket -- kind, perception on or off, scenario count rounded up to a
+ *     power of two, samples rounded up to a power of two (at least 2^15,
+ *     at most max_tick_samples) -- whose first nodes copy the launch's
+ *     scenario and set tables from pinned memory, so every mix that falls
+ *     in a bucket replays the same recording.
  *   max_tick_samples: samples per launch (1..2^31-1); also the largest
  *     request.
  *   req: the statistics computed for every request (as for aeb_reduce). */
+#define AEB_SERVE_EAGER 1
 typedef struct {
   void* arena;
   uint64_t arena_bytes;
@@ -466,7 +552,7 @@ typedef struct {
   int32_t n_streams;
   int32_t tick_us;
   int32_t max_queue;
-  int32_t reserved;
+  int32_t flags;
   int64_t max_tick_samples;
   aeb_reduce_req req;
 } aeb_server_cfg;
@@ -488,22 +574,27 @@ typedef struct {
   uint64_t arena_in_use, arena_peak, arena_request_bytes, fixed_bytes;
 } aeb_server_info;
 
-/* Arena bytes a server with this configuration keeps for its streams (the
+/* (Admission by device footprint, for the Sec. VI-F request stream.)
+ * Arena bytes a server with this configuration keeps for its streams (the
  * rest holds request footprints), and the footprint of one request of
  * n_samples samples. */
 int aeb_server_fixed_bytes(const aeb_server_cfg* cfg, uint64_t* bytes);
 int aeb_serve_footprint(const aeb_server_cfg* cfg, int64_t n_samples, uint64_t* bytes);
 
-/* Create a server on the current device (AEB_EINVAL for a bad
+/* (The Sec. VI-F real-time evaluation as a service.)
+ * Create a server on the current device (AEB_EINVAL for a bad
  * configuration, AEB_ENOMEM if the arena cannot hold the fixed part plus one
  * request of max_tick_samples samples). */
 int aeb_server_create(const aeb_server_cfg* cfg, aeb_server** out);
 
-/* Finish all accepted requests, stop the worker, release the streams and
+/* (Server plumbing; no passage of the paper.)
+ * Finish all accepted requests, stop the worker, release the streams and
  * pinned staging; results not polled yet are dropped.  NULL is accepted. */
 int aeb_server_destroy(aeb_server* srv);
 
-/* Queue one evaluation (non-blocking).  AEB_EINVAL: invalid scenario or one
+/* One Monte Carlo evaluation of Sec. IV-VI under the 530 ms budget of
+ * Sec. VI-F (deadline_s).
+ * Queue one evaluation (non-blocking).  AEB_EINVAL: invalid scenario or one
  * the batched path cannot run (RK4 in FP32C, the closed-loop controller);
  * AEB_ENOMEM: its footprint exceeds the request part of the arena or its
  * sample count max_tick_samples; AEB_EAGAIN: the queue is full.  deadline_s:
@@ -511,12 +602,16 @@ int aeb_server_destroy(aeb_server* srv);
 int aeb_serve_submit(aeb_server* srv, const aeb_scenario* scn, double deadline_s,
                      uint64_t* ticket);
 
-/* Collect a request: AEB_OK with *out (and *timing, if not NULL) filled once
+/* The statistics of Sec. VI for one request, and its latency against the
+ * Sec. VI-F budget.
+ * Collect a request: AEB_OK with *out (and *timing, if not NULL) filled once
  * it is done, after which the ticket is forgotten; AEB_EAGAIN while pending;
  * AEB_ENOTFOUND for an unknown or already collected ticket; the request's
  * own error if its execution failed. */
 int aeb_serve_poll(aeb_server* srv, uint64_t ticket, aeb_stats* out, aeb_req_timing* timing);
 
+/* Counters of the server (server plumbing; deadline misses against the
+ * Sec. VI-F budget). */
 int aeb_server_info_get(aeb_server* srv, aeb_server_info* out);
 
 #ifdef __cplusplus

@@ -14,8 +14,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libaeb.so")
-ABI_VERSION = 5     # the aeb_version() these structures match
+ABI_VERSION = 6     # the aeb_version() these structures match
 NOALLOC_SCRATCH_BYTES = 32 << 20  # AEB_NOALLOC_SCRATCH_BYTES of aeb.h
+SERVE_EAGER = 1                   # AEB_SERVE_EAGER of aeb.h
 
 COLUMNS = ("v0", "mu", "mass", "grade", "sin_grade", "cos_grade", "cda", "crr", "tau", "gap",
            "lead_decel", "trigger", "log_weight")
@@ -36,11 +37,12 @@ END_STOP, END_IMPACT, END_HORIZON, COLLIDED, BOUNDARY = 1, 2, 3, 4, 8
 EXPORTS = ("aeb_last_error", "aeb_version", "aeb_validate", "aeb_uniforms", "aeb_sample_params",
            "aeb_rollout", "aeb_rollout_noalloc", "aeb_reduce", "aeb_batch_rollout",
            "aeb_batch_reduce",
-           "aeb_timing_enable", "aeb_timing_last", "aeb_server_fixed_bytes",
+           "aeb_timing_enable", "aeb_timing_last", "aeb_reduce_fallbacks", "aeb_server_fixed_bytes",
            "aeb_serve_footprint", "aeb_server_create", "aeb_server_destroy", "aeb_serve_submit",
            "aeb_serve_poll", "aeb_server_info_get", "aeb_graph_create", "aeb_graph_create_batch",
-           "aeb_graph_launch", "aeb_graph_finish", "aeb_graph_destroy", "aeb_tune_get",
-           "aeb_tune_set", "aeb_tune_load", "aeb_autotune")
+           "aeb_graph_launch", "aeb_graph_finish", "aeb_graph_destroy", "aeb_graph_create_mix",
+           "aeb_graph_launch_mix", "aeb_tune_get",
+           "aeb_tune_set", "aeb_tune_results", "aeb_tune_load", "aeb_autotune")
 
 
 class AebError(RuntimeError):
@@ -100,10 +102,15 @@ class Stats(C.Structure):
 _lib = None
 
 
+class TuneShape(C.Structure):
+    _fields_ = [("k", C.c_int32), ("block", C.c_int32), ("waves_per_simd", C.c_int32),
+                ("samples_per_thread", C.c_int32)]
+
+
 class ServerCfg(C.Structure):
     _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_uint64), ("max_slots", C.c_int32),
                 ("precision", C.c_int32), ("n_streams", C.c_int32), ("tick_us", C.c_int32),
-                ("max_queue", C.c_int32), ("reserved", C.c_int32),
+                ("max_queue", C.c_int32), ("flags", C.c_int32),
                 ("max_tick_samples", C.c_int64), ("req", ReduceReq)]
 
 
@@ -143,6 +150,7 @@ def lib():
         L.aeb_batch_reduce.argtypes = [P(Outputs), C.c_int, P(ReduceReq), P(Stats), C.c_void_p]
         L.aeb_timing_enable.argtypes = [C.c_int]
         L.aeb_timing_last.argtypes = [P(C.c_float)]
+        L.aeb_reduce_fallbacks.argtypes = [P(C.c_uint64)]
         L.aeb_server_fixed_bytes.argtypes = [P(ServerCfg), P(C.c_uint64)]
         L.aeb_serve_footprint.argtypes = [P(ServerCfg), C.c_int64, P(C.c_uint64)]
         L.aeb_server_create.argtypes = [P(ServerCfg), P(C.c_void_p)]
@@ -155,10 +163,16 @@ def lib():
         L.aeb_graph_create_batch.argtypes = [P(Scenario), C.c_int, C.c_int, P(Outputs),
                                              P(ReduceReq), C.c_void_p, P(C.c_void_p)]
         L.aeb_graph_launch.argtypes = [C.c_void_p, C.c_void_p]
+        L.aeb_graph_create_mix.argtypes = [P(Scenario), C.c_int, C.c_int, C.c_int64,
+                                           P(ReduceReq), P(C.c_void_p)]
+        L.aeb_graph_launch_mix.argtypes = [C.c_void_p, P(Scenario), C.c_int, P(Outputs),
+                                           C.c_void_p, C.c_void_p]
         L.aeb_graph_finish.argtypes = [C.c_void_p, C.c_void_p]
         L.aeb_graph_destroy.argtypes = [C.c_void_p]
-        L.aeb_tune_get.argtypes = [C.c_int, C.c_int, P(C.c_int32), P(C.c_int32), P(C.c_int32)]
-        L.aeb_tune_set.argtypes = [C.c_int, C.c_int, C.c_int32, C.c_int32, C.c_int32]
+        L.aeb_tune_get.argtypes = [C.c_int, C.c_int, P(TuneShape)]
+        L.aeb_tune_set.argtypes = [C.c_int, C.c_int, P(TuneShape)]
+        L.aeb_tune_results.argtypes = [C.c_int, C.c_int, P(TuneShape), P(C.c_float), C.c_int,
+                                       P(C.c_int)]
         L.aeb_tune_load.argtypes = [C.c_char_p]
         L.aeb_autotune.argtypes = [P(Scenario), C.c_int, C.c_char_p, C.c_void_p, P(C.c_float)]
         _lib = L
@@ -371,6 +385,13 @@ def reduce(out, risk=(), margin_q=(), grid=None, stream=None):
     return stats_dict(st, req.n_risk, req.n_margin_q, req.n_grid)
 
 
+def reduce_fallbacks():
+    """Reductions since load whose order statistics took the radix-select fallback."""
+    c = C.c_uint64()
+    _check(lib().aeb_reduce_fallbacks(C.byref(c)))
+    return c.value
+
+
 def timing_enable(on=True):
     _check(lib().aeb_timing_enable(1 if on else 0))
 
@@ -409,9 +430,11 @@ class Server:
     library, which never frees it)."""
 
     def __init__(self, arena_bytes, precision="fp64", max_slots=256, n_streams=2, tick_us=200,
-                 max_queue=4096, max_tick_samples=1 << 22, risk=(), margin_q=(), grid=None):
+                 max_queue=4096, max_tick_samples=1 << 22, risk=(), margin_q=(), grid=None,
+                 eager=False):
         torch = _torch()
         self.cfg = ServerCfg()
+        self.cfg.flags = SERVE_EAGER if eager else 0
         self.cfg.max_slots = max_slots
         self.cfg.precision = PRECISIONS[precision]
         self.cfg.n_streams = n_streams
@@ -561,17 +584,78 @@ class Graph:
             pass
 
 
+class MixGraph:
+    """One recording that replays any mix of up to max_scn scenarios of the
+    kind of `kind` with at most max_samples samples in all (the batched
+    rollout, plus the statistics of each scenario unless stats=False)."""
+
+    def __init__(self, kind, precision="fp64", max_scn=16, max_samples=1 << 20, risk=(),
+                 margin_q=(), grid=None, stats=True):
+        self.req = reduce_request(risk, margin_q, grid) if stats else None
+        h = C.c_void_p()
+        _check(lib().aeb_graph_create_mix(C.byref(scenario(kind)), PRECISIONS[precision],
+                                          int(max_scn), int(max_samples),
+                                          C.byref(self.req) if stats else None, C.byref(h)))
+        self.h = h
+        self._st = None
+
+    def launch(self, scns, outs=None, stream=None):
+        """Replay for the scenarios `scns` (outputs allocated if not given);
+        returns the outputs."""
+        k = len(scns)
+        if outs is None:
+            outs = [alloc_outputs(int(d["n_samples"]), weight=bool(d.get("proposal")))
+                    for d in scns]
+        self._sarr = (Scenario * k)(*[scenario(d) for d in scns])
+        self._oarr = (Outputs * k)(*[_outputs_struct(o) for o in outs])
+        self._st = (Stats * k)() if self.req is not None else None
+        _check(lib().aeb_graph_launch_mix(self.h, self._sarr, k, self._oarr,
+                                          C.cast(self._st, C.c_void_p) if self._st else None,
+                                          _stream(stream)))
+        self.k = k
+        return outs
+
+    def finish(self, stream=None):
+        """Wait for the replay; returns the statistics (list) or None."""
+        _check(lib().aeb_graph_finish(self.h, _stream(stream)))
+        if self.req is None:
+            return None
+        r = self.req
+        return [stats_dict(self._st[j], r.n_risk, r.n_margin_q, r.n_grid) for j in range(self.k)]
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(lib().aeb_graph_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def tune_get(precision="fp64", obstacle="stationary"):
-    """(k, block, waves_per_simd) of the integration kernel's launch."""
-    k, b, w = C.c_int32(), C.c_int32(), C.c_int32()
-    _check(lib().aeb_tune_get(PRECISIONS[precision], OBSTACLES[obstacle], C.byref(k), C.byref(b),
-                              C.byref(w)))
-    return k.value, b.value, w.value
+    """(k, block, waves_per_simd, samples_per_thread) of the integration kernel's launch."""
+    t = TuneShape()
+    _check(lib().aeb_tune_get(PRECISIONS[precision], OBSTACLES[obstacle], C.byref(t)))
+    return t.k, t.block, t.waves_per_simd, t.samples_per_thread
 
 
-def tune_set(precision, obstacle, k, block, waves_per_simd):
-    _check(lib().aeb_tune_set(PRECISIONS[precision], OBSTACLES[obstacle], k, block,
-                              waves_per_simd))
+def tune_set(precision, obstacle, k, block, waves_per_simd, samples_per_thread=1):
+    t = TuneShape(k, block, waves_per_simd, samples_per_thread)
+    _check(lib().aeb_tune_set(PRECISIONS[precision], OBSTACLES[obstacle], C.byref(t)))
+
+
+def tune_results(precision="fp64", obstacle="stationary", max_n=256):
+    """The last autotune's candidates, fastest first: [((k, block, waves, spt), ms), ...]."""
+    shapes = (TuneShape * max_n)()
+    ms = (C.c_float * max_n)()
+    cnt = C.c_int()
+    _check(lib().aeb_tune_results(PRECISIONS[precision], OBSTACLES[obstacle], shapes, ms, max_n,
+                                  C.byref(cnt)))
+    return [((t.k, t.block, t.waves_per_simd, t.samples_per_thread), ms[j])
+            for j, t in enumerate(shapes[:min(cnt.value, max_n)])]
 
 
 def tune_load(path):

@@ -378,11 +378,17 @@ extern "C" {
 
 const char* aeb_last_error(void) { return g_err.c_str(); }
 
-int aeb_version(void) { return 5; }
+int aeb_version(void) { return 6; }
 
 int aeb_timing_enable(int on) {
   g_timing.on = on != 0;
   g_timing.recorded = false;
+  return AEB_OK;
+}
+
+int aeb_reduce_fallbacks(uint64_t* count) {
+  if (!count) return fail(AEB_EINVAL, "aeb_reduce_fallbacks: null argument");
+  *count = reduce_fallback_count();
   return AEB_OK;
 }
 
@@ -505,12 +511,22 @@ int aeb_batch_rollout(const aeb_scenario* scns, int n_scn, int precision, const 
 
 int aeb_batch_reduce(const aeb_outputs* outs, int n_scn, const aeb_reduce_req* req, aeb_stats* stats,
                      void* stream) {
-  if (!outs || !stats || n_scn < 1) return fail(AEB_EINVAL, "aeb_batch_reduce: empty batch");
+  if (!outs || !stats || !req || n_scn < 1) return fail(AEB_EINVAL, "aeb_batch_reduce: empty batch");
+  const int rc = check_reduce_req(*req);
+  if (rc != AEB_OK) return rc;
+  std::vector<OutCols> oc(n_scn);
+  std::vector<int64_t> ns(n_scn);
   for (int j = 0; j < n_scn; ++j) {
-    const int rc = aeb_reduce(&outs[j], req, &stats[j], stream);
-    if (rc != AEB_OK) return rc;
+    if (!outputs_complete(&outs[j])) return fail(AEB_EINVAL, "aeb_batch_reduce: null argument");
+    if (outs[j].n < 1 || outs[j].n > 0x7fffffffLL)
+      return fail(AEB_EINVAL, "aeb_batch_reduce: n out of [1, 2^31-1]");
+    oc[j] = OutCols{outs[j].dist, outs[j].status, outs[j].steps, outs[j].margin, outs[j].v_impact,
+                    outs[j].weight};
+    ns[j] = outs[j].n;
   }
-  return AEB_OK;
+  ScratchScope scope(static_cast<hipStream_t>(stream));
+  return launch_batch_reduce(oc.data(), ns.data(), n_scn, *req, stats,
+                             static_cast<hipStream_t>(stream));
 }
 
 int aeb_reduce(const aeb_outputs* out, const aeb_reduce_req* req, aeb_stats* host_out, void* stream) {

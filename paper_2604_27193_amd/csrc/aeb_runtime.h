@@ -97,17 +97,58 @@ int launch_fixup(const aeb_scenario& s, const ParamSrc* src, const OutCols& out,
                  const uint32_t* fix, hipStream_t stream);
 int launch_reduce(const OutCols& out, int64_t n, const aeb_reduce_req& req, aeb_stats* host_out,
                   hipStream_t stream);
+// statistics of nseg output sets (segmented launches on one pool block; waits)
+int launch_batch_reduce(const OutCols* outs, const int64_t* ns, int nseg,
+                        const aeb_reduce_req& req, aeb_stats* host_out, hipStream_t stream);
 
 // The reduction in two parts on caller-provided scratch (reduce_scratch_bytes):
 // reduce_enqueue queues the kernels and the copy of the statistics into
 // host_out (pinned memory keeps it asynchronous); once the stream has run
 // them, a non-zero host_out->reserved asks for reduce_fallback (synchronous),
-// which recomputes the order statistics by radix select.
+// which recomputes the order statistics by radix select into the set's
+// device statistics `dstats` and copies them to host_out.  reduce_enqueue
+// keeps the statistics at the start of the scratch (dstats = scratch).
 size_t reduce_scratch_bytes(int64_t n, const aeb_reduce_req& req);
+// a bound on the sum of reduce_scratch_bytes (each rounded up to 256 bytes)
+// over any cap_sets sets of cap_samples samples in all
+size_t reduce_scratch_bytes_cap(int cap_sets, int64_t cap_samples, const aeb_reduce_req& req);
 int reduce_enqueue(const OutCols& out, int64_t n, const aeb_reduce_req& req, void* scratch_base,
                    aeb_stats* host_out, hipStream_t stream);
 int reduce_fallback(const OutCols& out, int64_t n, const aeb_reduce_req& req, void* scratch_base,
-                    aeb_stats* host_out, hipStream_t stream);
+                    aeb_stats* dstats, aeb_stats* host_out, hipStream_t stream);
+// reduce_fallback calls since the library was loaded
+unsigned long long reduce_fallback_count();
+
+// The reduction of nseg output sets as one launch sequence (every kernel of
+// it covers all sets): set j has its own scratch at bases[j]
+// (reduce_scratch_bytes(ns[j])); `table_dev` (device) and `table_host` (host,
+// pinned for an asynchronous call, unchanged until the stream has copied it)
+// hold reduce_table_bytes(nseg, ns) bytes: the set table, copied to the
+// device by the call, and the sets' device statistics, at
+// reduce_table_stats(table_dev, nseg, ns) + j, copied to host_out[j].  The
+// fallback of set j then takes that device statistics pointer.
+size_t reduce_table_bytes(int nseg, const int64_t* ns);
+aeb_stats* reduce_table_stats(void* table_dev, int nseg, const int64_t* ns);
+int reduce_enqueue_sets(const OutCols* outs, const int64_t* ns, int nseg,
+                        const aeb_reduce_req& req, char* const* bases, void* table_dev,
+                        void* table_host, aeb_stats* host_out, hipStream_t stream);
+
+// The same launch sequence laid out for a capacity -- up to cap_sets sets of
+// cap_samples samples in all -- so that one recording serves any such mix:
+// reduce_fill_sets_cap writes a mix into the host table (before each replay),
+// reduce_enqueue_sets_cap queues the table copy, kernels whose grids cover
+// the capacity (blocks past the mix return at once) and the copy of
+// cap_sets statistics to host_out (the first nseg are the mix's).  The
+// table needs reduce_table_bytes_cap bytes on both sides; the statistics of
+// set j on the device are reduce_table_stats_cap(table_dev, ...) + j.
+size_t reduce_table_bytes_cap(int cap_sets, int64_t cap_samples);
+aeb_stats* reduce_table_stats_cap(void* table_dev, int cap_sets, int64_t cap_samples);
+int reduce_fill_sets_cap(const OutCols* outs, const int64_t* ns, int nseg, int cap_sets,
+                         int64_t cap_samples, char* const* bases, void* table_dev,
+                         void* table_host);
+int reduce_enqueue_sets_cap(int cap_sets, int64_t cap_samples, const aeb_reduce_req& req,
+                            bool weighted, void* table_dev, const void* table_host,
+                            aeb_stats* host_out, hipStream_t stream);
 int check_reduce_req(const aeb_reduce_req& req);
 
 // Argument checks of aeb_rollout (scenario, precision, column lengths) and the

@@ -27,6 +27,13 @@ struct LeadJob {
   double decel;   // lead deceleration
 };
 
+// Sizes of a batched launch on device tables (a recorded mix reads them here).
+struct BatchHdr {
+  long long total;  // samples
+  float cap;        // largest step count of the mix's scenarios (sort-key scale)
+  int n_scn;        // scenarios
+};
+
 // Per-scenario constants of a batched launch.
 struct ScnDev {
   double dt, a_cmd;
@@ -57,6 +64,15 @@ int launch_batch_fast(const aeb_scenario* scns, int n_scn, int precision, const 
 // copied to the device asynchronously: they must stay valid until the stream
 // has run the copies (pinned host memory lets the caller keep going).
 size_t batch_scratch_bytes(int64_t total, int n_scn, bool lead);
+
+// The batched launch on device tables the caller keeps (a recorded graph
+// refreshes them by a copy node before these kernels): every grid covers
+// cap_total samples and cap_scn scenarios, and the kernels read the actual
+// sizes from *hdr.  kind gives the integrator, obstacle, impact_exit and
+// nofma that all scenarios share; perception: whether any has it.
+int launch_batch_fast_dev(const aeb_scenario& kind, bool perception, int precision,
+                          const BatchHdr* hdr, const ScnDev* tab, const aeb_scenario* scns,
+                          int cap_scn, int64_t cap_total, void* scratch_base, hipStream_t st);
 int fill_batch_table(const aeb_scenario* scns, int n_scn, const OutCols* outs, ScnDev* tab,
                      int64_t* total, int64_t* cap);
 int launch_batch_fast_into(const aeb_scenario* scns, int n_scn, int precision,

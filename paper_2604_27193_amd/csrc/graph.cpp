@@ -13,6 +13,7 @@
 
 #include "aeb_runtime.h"
 #include "fast_path.h"
+#include "mixgraph.h"
 
 struct aeb_graph {
   hipGraph_t graph = nullptr;
@@ -23,9 +24,20 @@ struct aeb_graph {
   std::vector<aeb::OutCols> outs;
   std::vector<int64_t> ns;
   std::vector<size_t> red_off;       // offset of each set's reduce scratch
+  size_t tab_off = 0;                // batches: offset of the reduction's set table
+  char* rtab_host = nullptr;         // batches: pinned host copy of that table
   aeb_stats* host_stats = nullptr;   // caller's pinned statistics, one per set
   bool reduce = false;
   aeb_reduce_req req{};
+  // a recording for changing mixes (aeb_graph_create_mix)
+  bool mix = false;
+  aeb::MixShape shape;
+  aeb::MixBufs mb;
+  aeb::MixGraph mg;
+  char* mix_dev = nullptr;           // device: tables, rollout and reduction scratch
+  char* red_base = nullptr;          // device: the reduction scratch of the sets
+  int last_n = 0;                    // the last launched mix
+  aeb_stats* last_stats = nullptr;   // where its statistics go (caller's host memory)
 };
 
 namespace aeb {
@@ -44,6 +56,14 @@ void destroy(aeb_graph* g) {
   if (g->scratch) (void)hipFree(g->scratch);
   if (g->tab) (void)hipHostFree(g->tab);
   if (g->scns) (void)hipHostFree(g->scns);
+  if (g->rtab_host) (void)hipHostFree(g->rtab_host);
+  if (g->mix) {
+    aeb::mix_release(&g->mg);
+    if (g->mix_dev) (void)hipFree(g->mix_dev);
+    if (g->mb.htab) (void)hipHostFree(g->mb.htab);
+    if (g->mb.hrtab) (void)hipHostFree(g->mb.hrtab);
+    if (g->mb.hstats) (void)hipHostFree(g->mb.hstats);
+  }
   delete g;
 }
 
@@ -76,20 +96,40 @@ int capture(aeb_graph* g, F enqueue) {
   return AEB_OK;
 }
 
+// One set: its own reduction.  Several: one segmented reduction over all of
+// them (its set table copied from pinned memory by a node of the graph).
 int enqueue_reduces(aeb_graph* g, hipStream_t st) {
   if (!g->reduce) return AEB_OK;
-  for (size_t j = 0; j < g->outs.size(); ++j) {
-    const int rc = reduce_enqueue(g->outs[j], g->ns[j], g->req, g->scratch + g->red_off[j],
-                                  &g->host_stats[j], st);
-    if (rc != AEB_OK) return rc;
-  }
-  return AEB_OK;
+  if (g->outs.size() == 1)
+    return reduce_enqueue(g->outs[0], g->ns[0], g->req, g->scratch + g->red_off[0],
+                          &g->host_stats[0], st);
+  std::vector<char*> bases;
+  for (size_t j = 0; j < g->outs.size(); ++j) bases.push_back(g->scratch + g->red_off[j]);
+  return reduce_enqueue_sets(g->outs.data(), g->ns.data(), static_cast<int>(g->outs.size()),
+                             g->req, bases.data(), g->scratch + g->tab_off, g->rtab_host,
+                             g->host_stats, st);
 }
 
-// lay out the reduce scratch after `base` bytes; returns the total
+// the device statistics of set j (where the fallback writes)
+aeb_stats* set_stats(aeb_graph* g, size_t j) {
+  if (g->outs.size() == 1) return reinterpret_cast<aeb_stats*>(g->scratch + g->red_off[0]);
+  return reduce_table_stats(g->scratch + g->tab_off, static_cast<int>(g->outs.size()),
+                            g->ns.data()) + j;
+}
+
+// lay out the reduce scratch (and, for several sets, the set table) after
+// `base` bytes; returns the total (0 if the pinned table cannot be had)
 size_t plan_reduces(aeb_graph* g, size_t base) {
   size_t off = up256(base);
   g->red_off.clear();
+  if (g->reduce && g->outs.size() > 1) {
+    const size_t tb = reduce_table_bytes(static_cast<int>(g->outs.size()), g->ns.data());
+    g->tab_off = off;
+    off += up256(tb);
+    if (hipHostMalloc(reinterpret_cast<void**>(&g->rtab_host), tb, hipHostMallocDefault) !=
+        hipSuccess)
+      return 0;
+  }
   for (size_t j = 0; j < g->outs.size(); ++j) {
     g->red_off.push_back(off);
     if (g->reduce) off += up256(reduce_scratch_bytes(g->ns[j], g->req));
@@ -128,8 +168,8 @@ int aeb_graph_create(const aeb_scenario* scn, const aeb_params* params, int prec
   rc = check_common(precision, req, host_stats, false);
   if (rc != AEB_OK) return rc;
   if (!fast_path_applies(*scn, precision))
-    return fail(AEB_EINVAL, "graphs record the block-structured path (not the unfused Euler "
-                            "form, not RK4 or the closed-loop controller in FP32C)");
+    return fail(AEB_EINVAL, "graphs record the block-structured path (not RK4 or the "
+                            "closed-loop controller in FP32C, at most 2^31 - 4096 steps)");
   if (out->n != scn->n_samples) return fail(AEB_EINVAL, "outputs length differs from n_samples");
   ParamSrc src{};
   if (params) {
@@ -155,7 +195,7 @@ int aeb_graph_create(const aeb_scenario* scn, const aeb_params* params, int prec
   g->host_stats = host_stats;
   const size_t roll = rollout_scratch_bytes(*scn, scn->n_samples);
   const size_t total = plan_reduces(g, roll);
-  if (hipMalloc(reinterpret_cast<void**>(&g->scratch), total) != hipSuccess) {
+  if (total == 0 || hipMalloc(reinterpret_cast<void**>(&g->scratch), total) != hipSuccess) {
     destroy(g);
     return fail(AEB_ENOMEM, "graph scratch allocation failed");
   }
@@ -193,9 +233,9 @@ int aeb_graph_create_batch(const aeb_scenario* scns, int n_scn, int precision,
   }
   for (int j = 0; j < n_scn; ++j)
     if (!fast_path_applies(scns[j], precision) || control_on(scns[j]))
-      return fail(AEB_EINVAL, "batched graphs record the batched block-structured path (not the "
-                              "unfused Euler form, not RK4 in FP32C, not the closed-loop "
-                              "controller, at most 2^31 - 4096 steps)");
+      return fail(AEB_EINVAL, "batched graphs record the batched block-structured path (not "
+                              "RK4 in FP32C, not the closed-loop controller, at most 2^31 - 4096 "
+                              "steps)");
   aeb_graph* g = new (std::nothrow) aeb_graph;
   if (!g) return fail(AEB_ENOMEM, "host allocation failed");
   for (int j = 0; j < n_scn; ++j) {
@@ -224,7 +264,7 @@ int aeb_graph_create_batch(const aeb_scenario* scns, int n_scn, int precision,
   const bool lead = scns[0].obstacle == AEB_OBS_LEAD;
   const size_t roll = batch_scratch_bytes(total, n_scn, lead);
   const size_t bytes = plan_reduces(g, roll);
-  if (hipMalloc(reinterpret_cast<void**>(&g->scratch), bytes) != hipSuccess) {
+  if (bytes == 0 || hipMalloc(reinterpret_cast<void**>(&g->scratch), bytes) != hipSuccess) {
     destroy(g);
     return fail(AEB_ENOMEM, "graph scratch allocation failed");
   }
@@ -241,7 +281,105 @@ int aeb_graph_create_batch(const aeb_scenario* scns, int n_scn, int precision,
   return AEB_OK;
 }
 
+int aeb_graph_create_mix(const aeb_scenario* kind, int precision, int max_scn,
+                         int64_t max_samples, const aeb_reduce_req* req, aeb_graph** out_graph) {
+  if (!out_graph) return fail(AEB_EINVAL, "aeb_graph_create_mix: null output");
+  *out_graph = nullptr;
+  if (!kind) return fail(AEB_EINVAL, "aeb_graph_create_mix: null kind");
+  if (precision != AEB_FP64 && precision != AEB_FP32C)
+    return fail(AEB_EINVAL, "mix graphs take AEB_FP64 or AEB_FP32C");
+  if (max_scn < 1 || max_scn > 65536 || max_samples < 1 || max_samples > 0xffffffffLL)
+    return fail(AEB_EINVAL, "mix capacity outside 1..65536 scenarios, 1..2^32-1 samples");
+  int rc = validate(*kind);
+  if (rc != AEB_OK) return rc;
+  if (!fast_path_applies(*kind, precision) || control_on(*kind))
+    return fail(AEB_EINVAL, "mix graphs record the batched block-structured path (not RK4 "
+                            "in FP32C, not the closed-loop controller)");
+  if (req) {
+    rc = check_reduce_req(*req);
+    if (rc != AEB_OK) return rc;
+  }
+  aeb_graph* g = new (std::nothrow) aeb_graph;
+  if (!g) return fail(AEB_ENOMEM, "host allocation failed");
+  g->mix = true;
+  MixShape& m = g->shape;
+  m.kind = *kind;
+  m.perception = perception_on(*kind);
+  m.precision = precision;
+  m.cap_scn = max_scn;
+  m.cap_total = max_samples;
+  m.reduce = req != nullptr;
+  m.weighted = kind->is_mask != 0;
+  if (req) m.req = *req;
+  const size_t tb = up256(mix_table_bytes(max_scn));
+  const size_t sb = up256(mix_scratch_bytes(m));
+  const size_t rb = req ? up256(reduce_table_bytes_cap(max_scn, max_samples)) : 0;
+  const size_t rs = req ? up256(reduce_scratch_bytes_cap(max_scn, max_samples, *req)) : 0;
+  if (hipMalloc(reinterpret_cast<void**>(&g->mix_dev), tb + sb + rb + rs) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&g->mb.htab), tb, hipHostMallocDefault) !=
+          hipSuccess ||
+      (req && (hipHostMalloc(reinterpret_cast<void**>(&g->mb.hrtab), rb, hipHostMallocDefault) !=
+                   hipSuccess ||
+               hipHostMalloc(reinterpret_cast<void**>(&g->mb.hstats),
+                             sizeof(aeb_stats) * max_scn, hipHostMallocDefault) != hipSuccess))) {
+    destroy(g);
+    return fail(AEB_ENOMEM, "mix graph allocation failed");
+  }
+  g->mb.dtab = g->mix_dev;
+  g->mb.scratch = g->mix_dev + tb;
+  g->mb.drtab = req ? g->mix_dev + tb + sb : nullptr;
+  g->red_base = req ? g->mix_dev + tb + sb + rb : nullptr;
+  rc = mix_record(m, g->mb, &g->mg);
+  if (rc != AEB_OK) {
+    destroy(g);
+    return rc;
+  }
+  *out_graph = g;
+  return AEB_OK;
+}
+
+int aeb_graph_launch_mix(aeb_graph* g, const aeb_scenario* scns, int n_scn,
+                         const aeb_outputs* outs, aeb_stats* host_stats, void* stream) {
+  if (!g || !g->mix) return fail(AEB_EINVAL, "aeb_graph_launch_mix: not a mix graph");
+  if (!scns || !outs || n_scn < 1) return fail(AEB_EINVAL, "aeb_graph_launch_mix: empty mix");
+  if (g->shape.reduce && !host_stats)
+    return fail(AEB_EINVAL, "aeb_graph_launch_mix: the graph computes statistics: host_stats");
+  if (g->last_n != 0)
+    return fail(AEB_EINVAL, "aeb_graph_launch_mix: the previous replay was not finished "
+                            "(aeb_graph_finish) and may still read the tables");
+  std::vector<OutCols> oc(n_scn);
+  std::vector<int64_t> ns(n_scn);
+  std::vector<char*> bases(n_scn);
+  char* p = g->red_base;
+  for (int j = 0; j < n_scn; ++j) {
+    int rc = validate(scns[j]);
+    if (rc != AEB_OK) return fail(rc, "scenario " + std::to_string(j) + ": " + aeb_last_error());
+    if (!outputs_ok(&outs[j]) || outs[j].n != scns[j].n_samples)
+      return fail(AEB_EINVAL, "outputs of scenario " + std::to_string(j) + " do not match it");
+    if (control_on(scns[j]) || !fast_path_applies(scns[j], g->shape.precision))
+      return fail(AEB_EINVAL, "scenario " + std::to_string(j) + " does not take the batched path");
+    oc[j] = OutCols{outs[j].dist, outs[j].status, outs[j].steps, outs[j].margin, outs[j].v_impact,
+                    outs[j].weight};
+    ns[j] = scns[j].n_samples;
+    bases[j] = p;
+    if (g->shape.reduce) p += up256(reduce_scratch_bytes(ns[j], g->shape.req));
+  }
+  // the graph's previous replay must have finished reading the pinned tables
+  // (aeb_graph_finish, or any sync of its stream, orders that)
+  int rc = mix_fill(g->shape, scns, n_scn, oc.data(), bases.data(), g->mb);
+  if (rc != AEB_OK) return rc;
+  AEB_HIP(hipGraphLaunch(g->mg.exec, static_cast<hipStream_t>(stream)));
+  g->outs = oc;
+  g->ns = ns;
+  g->red_off.clear();
+  for (int j = 0; j < n_scn; ++j) g->red_off.push_back(static_cast<size_t>(bases[j] - g->red_base));
+  g->last_n = n_scn;
+  g->last_stats = host_stats;
+  return AEB_OK;
+}
+
 int aeb_graph_launch(aeb_graph* g, void* stream) {
+  if (g && g->mix) return fail(AEB_EINVAL, "aeb_graph_launch: a mix graph takes aeb_graph_launch_mix");
   if (!g || !g->exec) return fail(AEB_EINVAL, "aeb_graph_launch: null graph");
   AEB_HIP(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
   return AEB_OK;
@@ -251,12 +389,28 @@ int aeb_graph_finish(aeb_graph* g, void* stream) {
   if (!g) return fail(AEB_EINVAL, "aeb_graph_finish: null graph");
   hipStream_t st = static_cast<hipStream_t>(stream);
   AEB_HIP(hipStreamSynchronize(st));
+  if (g->mix) {
+    if (!g->shape.reduce) return AEB_OK;
+    aeb_stats* dst = reduce_table_stats_cap(g->mb.drtab, g->shape.cap_scn, g->shape.cap_total);
+    for (int j = 0; j < g->last_n; ++j) {
+      aeb_stats& s = g->mb.hstats[j];
+      if (s.reserved) {
+        const int rc = reduce_fallback(g->outs[j], g->ns[j], g->shape.req,
+                                       g->red_base + g->red_off[j], dst + j, &s, st);
+        if (rc != AEB_OK) return rc;
+      }
+      s.reserved = 0;
+      g->last_stats[j] = s;
+    }
+    g->last_n = 0;
+    return AEB_OK;
+  }
   if (!g->reduce) return AEB_OK;
   for (size_t j = 0; j < g->outs.size(); ++j) {
     aeb_stats& s = g->host_stats[j];
     if (s.reserved) {
       const int rc = reduce_fallback(g->outs[j], g->ns[j], g->req, g->scratch + g->red_off[j],
-                                     &s, st);
+                                     set_stats(g, j), &s, st);
       if (rc != AEB_OK) return rc;
     }
     s.reserved = 0;

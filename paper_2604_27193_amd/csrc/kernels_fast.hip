@@ -93,6 +93,7 @@ struct PrepArgs {
   int32_t* nds;              // per-sample command step (launches with perception), else null
   int ctl;                   // closed-loop controller (single scenario)
   double* weight;            // single scenario: importance-sampling weights out (or null)
+  const BatchHdr* hdr;       // batch on device tables: n, cap and n_scn from here (else null)
 };
 
 template <bool DEVRNG, bool BATCH>
@@ -100,17 +101,21 @@ __global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job
                                                                  LeadJob* leads, uint32_t* keys,
                                                                  uint32_t* ghist) {
   constexpr int NT = prep_threads<DEVRNG>();
+  // a recorded mix reads its sizes from the device header
+  const int64_t n_all = a.hdr ? a.hdr->total : a.n;
+  const float capf = a.hdr ? a.hdr->cap : a.cap;
+  const int n_scn = a.hdr ? a.hdr->n_scn : a.n_scn;
   __shared__ uint32_t hist[NBINS];
   for (int j = threadIdx.x; j < NBINS; j += NT) hist[j] = 0;
   __syncthreads();
   for (int r = 0; r < PREP_SAMPLES / NT; ++r) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * PREP_SAMPLES + r * NT + threadIdx.x;
-    if (i >= a.n) break;
+    if (i >= n_all) break;
     // the sample's scenario and its index within it
     uint32_t j = 0;
     int64_t local = i;
     if (BATCH) {
-      int lo = 0, hi = a.n_scn - 1;
+      int lo = 0, hi = n_scn - 1;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (a.tab[mid].off <= i)
@@ -185,7 +190,7 @@ __global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job
     J.scn = j;
     jobs[i] = J;
     if (leads) leads[i].decel = lead;
-    const uint32_t u = static_cast<uint32_t>(fminf(steps, a.cap) * (4096.0f / (a.cap + 1.0f)));
+    const uint32_t u = static_cast<uint32_t>(fminf(steps, capf) * (4096.0f / (capf + 1.0f)));
     const uint32_t ud = 4095u - (u > 4095u ? 4095u : u);  // longest first
     // within a coarse length bin: finer length; with perception 8 finer length
     // levels, then the command step in 16-step bins, so a wavefront's lanes
@@ -232,7 +237,9 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_scan(uint32_t* hist, unsigned lo
 // Placement: each block ranks its samples per key in LDS, reserves one range
 // per key with a single global atomic, then writes the permutation.
 __global__ __launch_bounds__(PREP_BLOCK) void k_scatter(const uint32_t* keys, int64_t n,
-                                                        uint32_t* offs, uint32_t* perm) {
+                                                        uint32_t* offs, uint32_t* perm,
+                                                        const BatchHdr* hdr) {
+  if (hdr) n = hdr->total;
   __shared__ uint32_t cnt[NBINS];
   for (int j = threadIdx.x; j < NBINS; j += PREP_BLOCK) cnt[j] = 0;
   __syncthreads();
@@ -400,6 +407,7 @@ struct Ctx {
   const ScnDev* tab;
   const int32_t* nds;  // per-sample command steps (perception), else null
   CtlArgs ca;          // the closed-loop controller (kernels instantiated for it)
+  const BatchHdr* hdr; // a recorded mix: the launch's sample count (else null)
 };
 
 struct LaneScn {
@@ -610,6 +618,7 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
                                                    const uint32_t* __restrict__ perm, int64_t n,
                                                    Ctx ctx, unsigned long long* counter,
                                                    int persistent) {
+  if (ctx.hdr) n = ctx.hdr->total;  // a recorded mix: its size from the device header
   // block ladder as a lane approaches its stop: K steps, then KM, then KS,
   // then single checked steps (a level runs while no lane can stop inside it)
   constexpr int KS = 4;
@@ -859,6 +868,299 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
 }
 
 // ---------------------------------------------------------------------------
+// Two samples per lane (explicit Euler, fused form, no obstacle or a
+// stationary one, no controller): lane l of a wavefront integrates the
+// sorted positions base + l and base + 64 + l of a 128-sample chunk, so a
+// wavefront's block bookkeeping, ladder and replay serve twice the samples
+// and every block interleaves two independent dependency chains.  The forms,
+// ladder, block limits and crossing replay are those of k_roll_fp64, taken
+// over both samples of every lane; each sample's steps are the canonical
+// step's, bit for bit.
+// ---------------------------------------------------------------------------
+template <int FORM, int K>
+HOT void block64x2(St64 (&s)[2], const Job (&J)[2], double dt0, double dt1, double cmd0,
+                   double cmd1) {
+  Ld64 l{};
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    block64<FORM, 1, false, AEB_EULER>(s[0], l, J[0], 0.0, dt0, cmd0);
+    block64<FORM, 1, false, AEB_EULER>(s[1], l, J[1], 0.0, dt1, cmd1);
+    // each step's position sums happen at their step (else the compiler
+    // defers them and holds the speeds of many steps in registers)
+    asm volatile("" : "+v"(s[0].x), "+v"(s[1].x));
+  }
+}
+
+template <int OBS, int B>
+HOT void run_block64x2(Lane64 (&L)[2], const Job (&J)[2], const LaneScn (&c)[2], int k, int wnd,
+                       int impact_exit) {
+  double cmd[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    cmd[q] = k >= c[q].nd ? c[q].a_cmd : 0.0;
+    if (OBS != AEB_OBS_NONE && !L[q].collided) {
+      L[q].sv = L[q].s;
+      L[q].sk = k;
+      L[q].se = k + B;
+    }
+  }
+  St64 s[2] = {L[0].s, L[1].s};
+  if (k + B <= wnd) {
+    block64x2<FORM_D, B>(s, J, c[0].dt, c[1].dt, cmd[0], cmd[1]);
+  } else if (__all((!L[0].active || L[0].clamped) && (!L[1].active || L[1].clamped))) {
+    block64x2<FORM_C, B>(s, J, c[0].dt, c[1].dt, cmd[0], cmd[1]);
+  } else if (__all((!L[0].active || L[0].free_lane) && (!L[1].active || L[1].free_lane))) {
+    block64x2<FORM_F, B>(s, J, c[0].dt, c[1].dt, cmd[0], cmd[1]);
+  } else {
+    block64x2<FORM_G, B>(s, J, c[0].dt, c[1].dt, cmd[0], cmd[1]);
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      L[q].clamped = L[q].clamped || (L[q].limited && k + B > c[q].nd && s[q].a <= J[q].alim);
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    L[q].s = s[q];
+    if (OBS == AEB_OBS_STATIONARY && L[q].active && !L[q].collided && L[q].s.x > J[q].gap) {
+      L[q].collided = true;
+      L[q].pend = true;
+      if (impact_exit) L[q].active = false;
+    }
+  }
+}
+
+// runs of steady blocks for both samples of every lane (see run_steady)
+template <int OBS, int K, int FORM>
+HOT int run_steady_x2(Lane64 (&L)[2], const Job (&J)[2], const LaneScn (&c)[2], double cmd0,
+                      double cmd1, int k, int wl, const double (&thr)[2], int impact_exit) {
+  St64 s[2] = {L[0].s, L[1].s};
+  do {
+    const St64 b0 = s[0], b1 = s[1];
+#pragma unroll
+    for (int q = 0; q < K / 16; ++q) {
+      block64x2<FORM, 16>(s, J, c[0].dt, c[1].dt, cmd0, cmd1);
+      asm volatile("" : "+v"(s[0].x), "+v"(s[1].x));
+    }
+    if (K % 16 != 0) block64x2<FORM, K % 16>(s, J, c[0].dt, c[1].dt, cmd0, cmd1);
+    if (OBS == AEB_OBS_STATIONARY) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (L[q].active && !L[q].collided && s[q].x > J[q].gap) {
+          L[q].sv = q == 0 ? b0 : b1;
+          L[q].sk = k;
+          L[q].se = k + K;
+          L[q].collided = true;
+          L[q].pend = true;
+          if (impact_exit) L[q].active = false;
+        }
+      }
+    }
+    k += K;
+  } while (k + K <= wl && __any(L[0].active || L[1].active) &&
+           !__any((L[0].active && s[0].v <= thr[0]) || (L[1].active && s[1].v <= thr[1])));
+  L[0].s = s[0];
+  L[1].s = s[1];
+  return k;
+}
+
+// the next 128 sorted positions of a wavefront (see next_chunk)
+__device__ inline int64_t next_chunk2(unsigned long long* counter, int persistent, int pass,
+                                      int64_t n) {
+  if (pass == 0)
+    return 2 * (static_cast<int64_t>(blockIdx.x) * blockDim.x +
+                __builtin_amdgcn_readfirstlane(threadIdx.x & ~63u));
+  if (!persistent) return n;
+  unsigned long long b = 0;
+  if ((threadIdx.x & 63) == 0) b = atomicAdd(counter, 128ull);
+  const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(b));
+  const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(b >> 32));
+  return static_cast<int64_t>((static_cast<unsigned long long>(hi) << 32) | lo) +
+         2 * static_cast<int64_t>(gridDim.x) * blockDim.x;
+}
+
+template <int OBS, int K, bool BATCH>
+__global__ __launch_bounds__(256) void k_roll_fp64x2(const Job* __restrict__ jobs,
+                                                     const uint32_t* __restrict__ perm,
+                                                     int64_t n, Ctx ctx,
+                                                     unsigned long long* counter,
+                                                     int persistent) {
+  if (ctx.hdr) n = ctx.hdr->total;  // a recorded mix: its size from the device header
+  constexpr int KS = 4;
+  constexpr int KM = K > 16 ? 16 : KS;
+  for (int pass = 0;; ++pass) {
+    const int64_t base = next_chunk2(counter, persistent, pass, n);
+    if (base >= n) break;
+    bool valid[2];
+    uint32_t g[2];
+    Job J[2];
+    LaneScn c[2];
+    Lane64 L[2];
+    double thr_k[2], thr_m[2], thr_s[2], dist[2], margin[2];
+    float vimp[2];
+    int end[2], steps[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int64_t pos = base + 64 * q + (threadIdx.x & 63);
+      valid[q] = pos < n;
+      g[q] = valid[q] ? perm[pos] : 0u;
+      J[q] = valid[q] ? jobs[g[q]] : Job{1.0, 0.0, 0.0, -1.0, 0.5, 1e30, 1.0, 0.0f, 0u};
+      c[q] = lane_scn<BATCH>(ctx, J[q], valid[q], g[q]);
+      thr_k[q] = static_cast<double>(K) * c[q].dt * J[q].dmax;
+      thr_m[q] = static_cast<double>(KM) * c[q].dt * J[q].dmax;
+      thr_s[q] = static_cast<double>(KS) * c[q].dt * J[q].dmax;
+      L[q].on1 = L[q].on2 = INT_MAX;
+      L[q].stage = 0;
+      L[q].s = St64{0.0, J[q].v0, 0.0};
+      L[q].l = Ld64{0.0, 0.0, J[q].gap};
+      L[q].sv = L[q].s;
+      L[q].lv = L[q].l;
+      L[q].sk = L[q].se = 0;
+      L[q].active = valid[q];
+      L[q].collided = L[q].pend = L[q].clamped = false;
+      L[q].free_lane = J[q].alim < c[q].a_cmd - 1e-6;
+      L[q].limited = J[q].alim > c[q].a_cmd + 1e-9;
+      dist[q] = 0.0;
+      margin[q] = J[q].gap;
+      vimp[q] = 0.0f;
+      end[q] = steps[q] = 0;
+    }
+    const bool varnd = BATCH || ctx.nds;
+    int wnd = __builtin_amdgcn_readfirstlane(
+        varnd ? wave_min(min(valid[0] ? c[0].nd : INT_MAX, valid[1] ? c[1].nd : INT_MAX))
+              : c[0].nd);
+    int k = 0, wl = -1;
+    for (;;) {
+      k = __builtin_amdgcn_readfirstlane(k);
+      if (!__any(L[0].active || L[1].active)) break;
+      if (!varnd) {
+        wl = __builtin_amdgcn_readfirstlane(lane_lim(k, c[0].nd, c[0].nmax));
+      } else if (k >= wl) {
+        const int l0 = L[0].active ? lane_lim(k, c[0].nd, c[0].nmax) : INT_MAX;
+        const int l1 = L[1].active ? lane_lim(k, c[1].nd, c[1].nmax) : INT_MAX;
+        wl = wave_min(min(l0, l1));
+      }
+      if (k + K <= wl && !__any((L[0].active && L[0].s.v <= thr_k[0]) ||
+                                (L[1].active && L[1].s.v <= thr_k[1]))) {
+        const bool past = k + K > wnd;
+        if (past && __all((!L[0].active || L[0].clamped) && (!L[1].active || L[1].clamped))) {
+          k = run_steady_x2<OBS, K, FORM_C>(L, J, c, 0.0, 0.0, k, wl, thr_k, ctx.impact_exit);
+        } else if (past && __all((!L[0].active || L[0].free_lane) &&
+                                 (!L[1].active || L[1].free_lane))) {
+          const double cmd0 = k >= c[0].nd ? c[0].a_cmd : 0.0;
+          const double cmd1 = k >= c[1].nd ? c[1].a_cmd : 0.0;
+          k = run_steady_x2<OBS, K, FORM_F>(L, J, c, cmd0, cmd1, k, wl, thr_k, ctx.impact_exit);
+        } else {
+          run_block64x2<OBS, K>(L, J, c, k, wnd, ctx.impact_exit);
+          k += K;
+        }
+      } else if (KM > KS && k + KM <= wl &&
+                 !__any((L[0].active && L[0].s.v <= thr_m[0]) ||
+                        (L[1].active && L[1].s.v <= thr_m[1]))) {
+        run_block64x2<OBS, KM>(L, J, c, k, wnd, ctx.impact_exit);
+        k += KM;
+      } else if (k + KS <= wl && !__any((L[0].active && L[0].s.v <= thr_s[0]) ||
+                                        (L[1].active && L[1].s.v <= thr_s[1]))) {
+        run_block64x2<OBS, KS>(L, J, c, k, wnd, ctx.impact_exit);
+        k += KS;
+      } else {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          if (!L[q].active) continue;
+          const double cmd = k >= c[q].nd ? c[q].a_cmd : 0.0;
+          step64<false, AEB_EULER>(L[q].s, L[q].l, J[q], 0.0, c[q].dt, cmd);
+          if (k >= c[q].nd) L[q].clamped = L[q].clamped || (L[q].limited && L[q].s.a <= J[q].alim);
+          const bool impact = OBS == AEB_OBS_STATIONARY && L[q].s.x > J[q].gap;
+          if (impact && !L[q].collided) {
+            L[q].collided = true;
+            vimp[q] = static_cast<float>(L[q].s.v);
+          }
+          if (impact && ctx.impact_exit) {
+            L[q].active = false;
+            end[q] = AEB_END_IMPACT;
+            steps[q] = k + 1;
+            dist[q] = L[q].s.x;
+          }
+          if (L[q].active) {
+            if (L[q].s.v <= 0.0) {
+              L[q].active = false;
+              end[q] = AEB_END_STOP;
+              steps[q] = k + 1;
+              dist[q] = L[q].s.x;
+            } else if (k + 1 == c[q].nmax) {
+              L[q].active = false;
+              end[q] = AEB_END_HORIZON;
+              steps[q] = k + 1;
+              dist[q] = L[q].s.x;
+            }
+          }
+        }
+        k += 1;
+      }
+    }
+    // replay the block in which each pending sample passed the obstacle (see
+    // k_roll_fp64), one sample of the lane after the other
+    if (OBS == AEB_OBS_STATIONARY) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (!__any(L[q].pend)) continue;
+        St64 r = L[q].sv;
+        Ld64 rl{};
+        int kr = L[q].sk;
+        constexpr int RB = 8;
+        const double cmd = kr >= c[q].nd ? c[q].a_cmd : 0.0;
+        if (K > RB) {
+          bool skip = L[q].pend;
+          for (int it = 0; it < K / RB; ++it) {
+            skip = skip && kr + RB <= L[q].se;
+            if (!__any(skip)) break;
+            if (skip) {
+              St64 t = r;
+              block64<FORM_G, RB, false, AEB_EULER>(t, rl, J[q], 0.0, c[q].dt, cmd);
+              if (t.x > J[q].gap) {
+                skip = false;
+              } else {
+                r = t;
+                kr += RB;
+              }
+            }
+          }
+        }
+        for (int it = 0; it <= K; ++it) {
+          if (!__any(L[q].pend)) break;
+          if (L[q].pend) {
+            const double cm = kr >= c[q].nd ? c[q].a_cmd : 0.0;
+            step64<false, AEB_EULER>(r, rl, J[q], 0.0, c[q].dt, cm);
+            ++kr;
+            if (r.x > J[q].gap) {
+              L[q].pend = false;
+              vimp[q] = static_cast<float>(r.v);
+              if (ctx.impact_exit) {
+                end[q] = AEB_END_IMPACT;
+                steps[q] = kr;
+                dist[q] = r.x;
+              }
+            }
+          }
+        }
+        if (L[q].pend) vimp[q] = __builtin_nanf("");  // unreachable; makes a broken replay visible
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (!valid[q]) continue;
+      const double mg = J[q].gap - dist[q];
+      margin[q] = mg < J[q].gap ? mg : J[q].gap;
+      int64_t i;
+      const OutCols o = lane_out<BATCH>(ctx, J[q], g[q], i);
+      o.dist[i] = dist[q];
+      o.margin[i] = margin[q];
+      o.steps[i] = steps[q];
+      o.status[i] = static_cast<uint8_t>(end[q] | (L[q].collided ? AEB_COLLIDED : 0));
+      o.vimp[i] = L[q].collided ? vimp[q] : 0.0f;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // FP32 compensated block forms.  State: speed (a float, or with SPLIT a float
 // base plus an in-block increment carried exactly at block ends), actuator
 // deviation e = a - cmd, in-block position sum p and a Kahan pair X that
@@ -1021,6 +1323,7 @@ __global__ __launch_bounds__(256) void k_roll_fp32c(const Job* __restrict__ jobs
                                                     Ctx ctx, double band_abs, double band_rel,
                                                     uint32_t* fix, unsigned long long* counter,
                                                     int persistent) {
+  if (ctx.hdr) n = ctx.hdr->total;  // a recorded mix: its size from the device header
   constexpr int KS = 4;
   constexpr int KM = K >= 64 ? 16 : KS;  // middle level of the block ladder
   static_assert(FLUSH % K == 0 && K % KM == 0 && KM % KS == 0,
@@ -1309,6 +1612,7 @@ __global__ __launch_bounds__(256) void k_roll_fp32c_lead(const Job* __restrict__
                                                          double band_rel, uint32_t* fix,
                                                          unsigned long long* counter,
                                                          int persistent) {
+  if (ctx.hdr) n = ctx.hdr->total;  // a recorded mix: its size from the device header
   constexpr int KS = 4;
   constexpr int KM = K >= 64 ? 16 : KS;  // middle level of the block ladder
   static_assert(FLUSH % K == 0 && K % KM == 0 && KM % KS == 0,
@@ -1493,7 +1797,9 @@ struct Shape {
   int persistent;
 };
 
-Shape shape(const TuneCfg& t, int64_t n) {
+// spt: samples per lane of the kernel launched (a one-pass grid covers
+// n / spt lanes)
+Shape shape(const TuneCfg& t, int64_t n, int spt = 1) {
   static int cus = 0;
   if (cus == 0) {
     int dev = 0;
@@ -1503,7 +1809,8 @@ Shape shape(const TuneCfg& t, int64_t n) {
   }
   Shape sh;
   sh.block = static_cast<unsigned>(t.block);
-  const int64_t need = (n + t.block - 1) / t.block;
+  const int64_t per = static_cast<int64_t>(t.block) * spt;
+  const int64_t need = (n + per - 1) / per;
   if (t.waves_per_simd > 0) {
     const int64_t grid = static_cast<int64_t>(cus) * 4 * t.waves_per_simd * 64 / t.block;
     sh.grid = static_cast<unsigned>(need < grid ? need : grid);
@@ -1559,16 +1866,36 @@ size_t bufs_layout(int64_t n, int n_scn, bool lead, char* base, Bufs* b) {
 }
 
 // sort the prepared keys into the permutation (the scan zeroes the claim counter)
-void sort_keys(const Bufs& b, int64_t n, hipStream_t st) {
+// (hdr: a recorded mix, n its capacity and the actual count on the device)
+void sort_keys(const Bufs& b, int64_t n, hipStream_t st, const BatchHdr* hdr = nullptr) {
   const unsigned pblk = static_cast<unsigned>((n + PREP_SAMPLES - 1) / PREP_SAMPLES);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(PREP_BLOCK), 0, st, b.hist, b.counter);
-  hipLaunchKernelGGL(k_scatter, dim3(pblk), dim3(PREP_BLOCK), 0, st, b.keys, n, b.hist, b.perm);
+  hipLaunchKernelGGL(k_scatter, dim3(pblk), dim3(PREP_BLOCK), 0, st, b.keys, n, b.hist, b.perm,
+                     hdr);
 }
 
 template <int OBS, int K, bool BATCH, int INTEG = AEB_EULER, bool CTL = false>
 void go64(const Shape& sh, const Bufs& b, int64_t n, const Ctx& ctx, hipStream_t st) {
   hipLaunchKernelGGL((k_roll_fp64<OBS, K, BATCH, INTEG, CTL>), dim3(sh.grid), dim3(sh.block), 0,
                      st, b.jobs, b.leads, b.perm, n, ctx, b.counter, sh.persistent);
+}
+
+template <int OBS, int K, bool BATCH>
+void go64x2(const Shape& sh, const Bufs& b, int64_t n, const Ctx& ctx, hipStream_t st) {
+  hipLaunchKernelGGL((k_roll_fp64x2<OBS, K, BATCH>), dim3(sh.grid), dim3(sh.block), 0, st, b.jobs,
+                     b.perm, n, ctx, b.counter, sh.persistent);
+}
+
+template <int OBS, bool BATCH>
+void go64x2k(int k, const Shape& sh, const Bufs& b, int64_t n, const Ctx& ctx, hipStream_t st) {
+  if (k == 16)
+    go64x2<OBS, 16, BATCH>(sh, b, n, ctx, st);
+  else if (k == 64)
+    go64x2<OBS, 64, BATCH>(sh, b, n, ctx, st);
+  else if (k == 128)
+    go64x2<OBS, 128, BATCH>(sh, b, n, ctx, st);
+  else
+    go64x2<OBS, 32, BATCH>(sh, b, n, ctx, st);
 }
 
 template <int OBS, bool BATCH>
@@ -1652,6 +1979,18 @@ int integrate(const aeb_scenario& s0, int precision, const Bufs& b, int64_t n, c
       go64<AEB_OBS_LEAD, 128, BATCH, EULER_NOFMA>(sh, b, n, ctx, st);
     else
       go64<AEB_OBS_NONE, 128, BATCH, EULER_NOFMA>(sh, b, n, ctx, st);
+    timing_end(st);
+    AEB_HIP(hipGetLastError());
+    return AEB_OK;
+  }
+  if (precision == AEB_FP64 && t.spt == 2 && obs != AEB_OBS_LEAD) {
+    // two samples per lane (the tuned FP64 shape)
+    const Shape sh2 = shape(t, n, 2);
+    timing_begin(st);
+    if (obs == AEB_OBS_STATIONARY)
+      go64x2k<AEB_OBS_STATIONARY, BATCH>(t.k, sh2, b, n, ctx, st);
+    else
+      go64x2k<AEB_OBS_NONE, BATCH>(t.k, sh2, b, n, ctx, st);
     timing_end(st);
     AEB_HIP(hipGetLastError());
     return AEB_OK;
@@ -1810,6 +2149,33 @@ int launch_batch_fast_into(const aeb_scenario* scns, int n_scn, int precision,
   ctx.tab = b.tab;
   ctx.nds = pa.nds;
   return integrate<true>(scns[0], precision, b, total, ctx, nullptr, st);
+}
+
+int launch_batch_fast_dev(const aeb_scenario& kind, bool perception, int precision,
+                          const BatchHdr* hdr, const ScnDev* tab, const aeb_scenario* scns,
+                          int cap_scn, int64_t cap_total, void* scratch_base, hipStream_t st) {
+  const bool lead = kind.obstacle == AEB_OBS_LEAD;
+  Bufs b;
+  bufs_layout(cap_total, 0, lead, static_cast<char*>(scratch_base), &b);
+  const unsigned pblk = static_cast<unsigned>((cap_total + PREP_SAMPLES - 1) / PREP_SAMPLES);
+  hipLaunchKernelGGL(k_zero, dim3(NBINS / 256), dim3(256), 0, st, b.hist, int64_t(NBINS));
+  PrepArgs pa{};
+  pa.n = cap_total;
+  pa.cap = 1.0f;
+  pa.scns = scns;
+  pa.tab = tab;
+  pa.n_scn = cap_scn;
+  pa.nds = perception ? b.nds : nullptr;
+  pa.hdr = hdr;
+  hipLaunchKernelGGL((k_prep<true, true>), dim3(pblk), dim3(PREP_BLOCK), 0, st, pa, b.jobs,
+                     b.leads, b.keys, b.hist);
+  sort_keys(b, cap_total, st, hdr);
+  Ctx ctx{};
+  ctx.impact_exit = kind.impact_exit;
+  ctx.tab = tab;
+  ctx.nds = pa.nds;
+  ctx.hdr = hdr;
+  return integrate<true>(kind, precision, b, cap_total, ctx, nullptr, st);
 }
 
 int launch_batch_fast(const aeb_scenario* scns, int n_scn, int precision, const OutCols* outs,

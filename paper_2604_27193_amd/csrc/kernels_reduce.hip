@@ -15,7 +15,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <atomic>
 #include <cstring>
+#include <vector>
 
 #include "aeb_runtime.h"
 
@@ -33,6 +35,9 @@ constexpr int FB = 1024;         // threads of the finalize / bin-search blocks
 // block histogram row: distance value bins | margin value bins | risk-grid ranks
 constexpr int HG = 2 * (NVB + 1);             // offset of the risk-grid part
 constexpr int HW = HG + AEB_MAX_GRID + 1;     // row width
+// importance-sampling accumulators: four words per risk-grid rank bin, plus
+// bins for the collided samples and for all samples
+constexpr int WACC = (AEB_MAX_GRID + 3) * 4;
 
 struct Partial {
   long long ncol, nstop, nimp, nhor, nbnd;
@@ -41,14 +46,6 @@ struct Partial {
   float pad;
   double wmax;     // largest importance-sampling weight
   long long wbad;  // weights that are not finite and >= 0
-};
-
-// Selection targets: per target the array (0 censored distance, 1 margin)
-// and the 0-based rank.  Passed by value.
-struct SelIn {
-  int count, n_risk;
-  int kind[MAX_T];
-  unsigned long long rank[MAX_T];
 };
 
 // Selection progress: the value bin holding each target's rank and the rank
@@ -70,6 +67,115 @@ struct SelState {
   int count;
   int pad;
 };
+
+__host__ __device__ inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Scratch layout of one reduction: stats, selection state and the bin totals
+// (selection bins and risk-grid ranks) first (zeroed by one launch), then the
+// block partials, the block histograms, the candidates and the radix-select
+// state.
+struct RLayout {
+  long long chunk, chunk2;
+  int nb, nb2, T;
+  unsigned ccap;  // candidates kept per target: min(n, CAP) (a bin holds at most n)
+  size_t off_sel, off_zero_end, off_var, off_bh, off_bt, off_wa, off_bo, off_cand, off_ss, off_sh,
+      total;
+};
+
+__host__ __device__ inline RLayout layout(long long n, int T) {
+  RLayout L;
+  // element passes: 4,096 elements per block of 1,024 threads (measured faster
+  // than smaller blocks or slices: fewer partials, block histograms and
+  // per-block fixed costs)
+  L.chunk = EB * CP;
+  L.chunk2 = EB * CP;
+  L.nb = static_cast<int>((n + L.chunk - 1) / L.chunk);
+  L.nb2 = static_cast<int>((n + L.chunk2 - 1) / L.chunk2);
+  L.T = T;
+  const int tc = L.T > 0 ? L.T : 1;
+  L.off_sel = align256(sizeof(aeb_stats));
+  L.off_bt = align256(L.off_sel + sizeof(Sel));
+  L.off_wa = align256(L.off_bt + sizeof(unsigned) * HW);
+  L.off_zero_end = align256(L.off_wa + sizeof(unsigned long long) * WACC);
+  L.off_var = align256(L.off_zero_end + sizeof(Partial) * L.nb);
+  L.off_bh = align256(L.off_var + sizeof(double) * (L.nb > L.nb2 ? L.nb : L.nb2));
+  L.off_bo = align256(L.off_bh + sizeof(unsigned) * HW * L.nb2);
+  L.off_cand = align256(L.off_bo + sizeof(unsigned) * tc * L.nb2);
+  L.ccap = static_cast<unsigned>(n < CAP ? (n > 0 ? n : 1) : CAP);
+  L.off_ss = align256(L.off_cand + sizeof(unsigned long long) * tc * L.ccap);
+  L.off_sh = align256(L.off_ss + sizeof(SelState));
+  L.total = align256(L.off_sh + sizeof(unsigned) * tc * 256);
+  return L;
+}
+
+// One output set of a segmented reduction: its columns, its scratch (the
+// layout below), where its statistics go, and its place among the launch's
+// element-pass blocks and bin-totals rows.
+struct RSeg {
+  OutCols out;
+  long long n;
+  char* base;      // the set's scratch (RLayout of n)
+  aeb_stats* st;   // its statistics (device)
+  int nb;          // element-pass blocks of the set
+  int blk0;        // its first block among the launch's element-pass blocks
+  int row0;        // its first row of the bin-totals grid
+  int pad;
+};
+
+// The sets of one launch sequence: a single set by value, or a device table
+// with the set of every element-pass block and every bin-totals row.
+// Grids cover a capacity of sets, blocks and rows; the table says how many
+// sets this launch has (a recorded graph replays with other counts) and maps
+// the blocks and rows beyond them to -1, and those blocks return at once.
+struct RSegs {
+  RSeg one;
+  const RSeg* tab;    // null: the single set `one`
+  const int* bmap;    // set of each element-pass block (-1: none)
+  const int* rmap;    // set of each bin-totals row (-1: none)
+  const int* count;   // sets of the launch (device)
+};
+
+__device__ inline int seg_count(const RSegs& S) { return S.tab ? *S.count : 1; }
+
+__device__ inline const RSeg& seg_at(const RSegs& S, int j) { return S.tab ? S.tab[j] : S.one; }
+
+// The set of element-pass block `gb` and the block's index inside it (null
+// for a block beyond the launch's sets).
+__device__ inline const RSeg* seg_of_block(const RSegs& S, int gb, int& local) {
+  if (!S.tab) {
+    local = gb;
+    return gb < S.one.nb ? &S.one : nullptr;
+  }
+  const int j = S.bmap[gb];
+  if (j < 0) return nullptr;
+  const RSeg* g = &S.tab[j];
+  local = gb - g->blk0;
+  return g;
+}
+
+// What a reduction computes: risk levels and margin quantile levels, and the
+// risk-curve grid (the request of the C ABI, by value).
+struct RReq {
+  int n_risk, n_mq, ng, pad;
+  double risk[AEB_MAX_RISK];
+  double mq[AEB_MAX_MARGIN_Q];
+  double glo, gstep, ginv;
+};
+
+// Selection targets of a set of n samples: target t < n_risk is H(risk[t]),
+// the element of 0-based rank n - floor(r n) - 1 of the censored distances;
+// target n_risk + j the margin quantile at mq[j], the element of rank
+// floor(p n) (floors of binary64 products, as the host computes them).
+__device__ inline int sel_kind(const RReq& q, int t) { return t >= q.n_risk ? 1 : 0; }
+
+__device__ inline unsigned long long sel_rank(const RReq& q, long long n, int t) {
+  const double nd = static_cast<double>(n);
+  if (t < q.n_risk) {
+    const long long m = static_cast<long long>(floor(q.risk[t] * nd));
+    return static_cast<unsigned long long>(n - m - 1);
+  }
+  return static_cast<unsigned long long>(static_cast<long long>(floor(q.mq[t - q.n_risk] * nd)));
+}
 
 // order-preserving map of binary64 onto uint64
 __device__ inline unsigned long long ordered(double d) {
@@ -267,10 +373,17 @@ __device__ inline Partial block_combine(const Partial* wp) {
   return wave_combine(l < NW ? wp[l] : identity_partial());
 }
 
-__global__ __launch_bounds__(EB) void k_pass1(OutCols o, long long n, long long chunk,
-                                              Partial* part) {
+__global__ __launch_bounds__(EB) void k_pass1(RSegs S) {
+  int bx;
+  const RSeg* gp = seg_of_block(S, blockIdx.x, bx);
+  if (!gp) return;  // beyond the launch's sets (the whole block)
+  const RSeg& g = *gp;
+  const OutCols o = g.out;
+  const long long n = g.n;
+  const long long chunk = static_cast<long long>(EB) * CP;
+  Partial* part = reinterpret_cast<Partial*>(g.base + layout(n, 0).off_zero_end);
   __shared__ Partial wp[EB / 64];
-  const long long lo = static_cast<long long>(blockIdx.x) * chunk;
+  const long long lo = static_cast<long long>(bx) * chunk;
   const long long hi = lo + chunk < n ? lo + chunk : n;
   long long ncol = 0, nstop = 0, nimp = 0, nhor = 0, nbnd = 0, wbad = 0;
   double sum = 0.0, dmin = INFINITY, dmax = -INFINITY, msum = 0.0, mmin = INFINITY,
@@ -353,14 +466,22 @@ __global__ __launch_bounds__(EB) void k_pass1(OutCols o, long long n, long long 
   __syncthreads();
   if (threadIdx.x < 64) {
     const Partial q = block_combine<EB / 64>(wp);
-    if (threadIdx.x == 0) part[blockIdx.x] = q;
+    if (threadIdx.x == 0) part[bx] = q;
   }
 }
 
 // Combine the block partials in a fixed order (thread t takes partials
 // t, t+FB, ... in order, then a fixed tree).
-__global__ __launch_bounds__(FB) void k_fin1(const Partial* part, int nb, long long n,
-                                             int weighted, aeb_stats* st, Sel* sel) {
+__global__ __launch_bounds__(FB) void k_fin1(RSegs S) {
+  if (static_cast<int>(blockIdx.x) >= seg_count(S)) return;
+  const RSeg& g = seg_at(S, blockIdx.x);
+  const int weighted = g.out.weight ? 1 : 0;
+  const long long n = g.n;
+  const RLayout RL = layout(n, 0);
+  const Partial* part = reinterpret_cast<const Partial*>(g.base + RL.off_zero_end);
+  const int nb = RL.nb;
+  aeb_stats* st = g.st;
+  Sel* sel = reinterpret_cast<Sel*>(g.base + RL.off_sel);
   __shared__ Partial wp[FB / 64];
   Partial p = identity_partial();
   for (int b = threadIdx.x; b < nb; b += FB) combine(p, part[b]);
@@ -409,11 +530,22 @@ __global__ __launch_bounds__(FB) void k_fin1(const Partial* part, int nb, long l
 // Sum of squared deviations for the sd, and block-private histograms (LDS,
 // written out without atomics): value bins of the arrays that have targets,
 // and the number of risk-grid headways below each censored distance.
-__global__ __launch_bounds__(EB) void k_pass2(OutCols o, long long n, long long chunk,
-                                              const aeb_stats* st, const Sel* sel, int need_d,
-                                              int need_m, double glo, double gstep,
-                                              double ginv, int ng,
-                                              int hw, unsigned* bhist, double* part) {
+__global__ __launch_bounds__(EB) void k_pass2(RSegs S, int need_d, int need_m, RReq rq,
+                                              int hw) {
+  int bx;
+  const RSeg* gp = seg_of_block(S, blockIdx.x, bx);
+  if (!gp) return;  // beyond the launch's sets (the whole block)
+  const RSeg& g = *gp;
+  const OutCols o = g.out;
+  const long long n = g.n;
+  const long long chunk = static_cast<long long>(EB) * CP;
+  const RLayout RL = layout(n, 0);
+  const aeb_stats* st = g.st;
+  const Sel* sel = reinterpret_cast<const Sel*>(g.base + RL.off_sel);
+  unsigned* bhist = reinterpret_cast<unsigned*>(g.base + RL.off_bh);
+  double* part = reinterpret_cast<double*>(g.base + RL.off_var);
+  const double glo = rq.glo, gstep = rq.gstep, ginv = rq.ginv;
+  const int ng = rq.ng;
   __shared__ double shd[EB / 64];
   __shared__ unsigned h[HW];
   for (int j = threadIdx.x; j < hw; j += EB) h[j] = 0;
@@ -421,7 +553,7 @@ __global__ __launch_bounds__(EB) void k_pass2(OutCols o, long long n, long long 
   const double mean = st->mean_dist;
   const double vmin0 = sel->vmin[0], sc0 = sel->scale[0];
   const double vmin1 = sel->vmin[1], sc1 = sel->scale[1];
-  const long long lo = static_cast<long long>(blockIdx.x) * chunk;
+  const long long lo = static_cast<long long>(bx) * chunk;
   const long long hi = lo + chunk < n ? lo + chunk : n;
   double ss = 0.0;
   // CP elements per thread are loaded before any is used (chunk2 = CP * EB)
@@ -459,9 +591,9 @@ __global__ __launch_bounds__(EB) void k_pass2(OutCols o, long long n, long long 
   if (threadIdx.x == 0) {
     double t = shd[0];
     for (int w = 1; w < EB / 64; ++w) t += shd[w];
-    part[blockIdx.x] = t;
+    part[bx] = t;
   }
-  unsigned* out = bhist + static_cast<size_t>(blockIdx.x) * hw;
+  unsigned* out = bhist + static_cast<size_t>(bx) * hw;
   for (int j = threadIdx.x; j < hw; j += EB) out[j] = h[j];
 }
 
@@ -495,17 +627,27 @@ __device__ inline double from_fixed(unsigned long long hi, unsigned long long lo
 // sums of w and w^2, then bins for the collided samples and for all samples;
 // four words per bin (w low, w high, w^2 low, w^2 high), merged into the
 // zeroed global accumulators.
-constexpr int WACC = (AEB_MAX_GRID + 3) * 4;
-__global__ __launch_bounds__(EB) void k_wpass(OutCols o, long long n, long long chunk, double glo,
-                                              double gstep, double ginv, int ng, const Sel* sel,
-                                              unsigned long long* gacc) {
+__global__ __launch_bounds__(EB) void k_wpass(RSegs S, RReq rq) {
+  int bx;
+  const RSeg* gp = seg_of_block(S, blockIdx.x, bx);
+  if (!gp) return;  // beyond the launch's sets (the whole block)
+  const RSeg& g = *gp;
+  const OutCols o = g.out;
+  const long long n = g.n;
+  const long long chunk = static_cast<long long>(EB) * CP;
+  const RLayout RL = layout(n, 0);
+  const Sel* sel = reinterpret_cast<const Sel*>(g.base + RL.off_sel);
+  unsigned long long* gacc = reinterpret_cast<unsigned long long*>(g.base + RL.off_wa);
+  const double glo = rq.glo, gstep = rq.gstep, ginv = rq.ginv;
+  const int ng = rq.ng;
+  if (!o.weight) return;  // a set without weights (uniform over the block)
   __shared__ unsigned long long acc[WACC];
   const int G = ng >= 2 ? ng + 1 : 0;  // rank bins 0..ng
   const int nacc = (G + 2) * 4;
   for (int j = threadIdx.x; j < nacc; j += EB) acc[j] = 0ull;
   __syncthreads();
   const int s1 = sel->wshift[0], s2 = sel->wshift[1];
-  const long long lo = static_cast<long long>(blockIdx.x) * chunk;
+  const long long lo = static_cast<long long>(bx) * chunk;
   const long long hi = lo + chunk < n ? lo + chunk : n;
   for (long long i = lo + threadIdx.x; i < hi; i += EB) {
     const double w = o.weight[i];
@@ -535,8 +677,15 @@ __global__ __launch_bounds__(EB) void k_wpass(OutCols o, long long n, long long 
 
 // The weighted estimates from the accumulated sums (one thread, in a fixed
 // order): suffix sums over the rank bins from the top give sum w [D > H0_j].
-__global__ void k_wfin(long long n, int ng, const Sel* sel, const unsigned long long* gacc,
-                       aeb_stats* st) {
+__global__ void k_wfin(RSegs S, int ng) {
+  if (static_cast<int>(blockIdx.x) >= seg_count(S)) return;
+  const RSeg& g = seg_at(S, blockIdx.x);
+  if (!g.out.weight) return;
+  const long long n = g.n;
+  const RLayout RL = layout(n, 0);
+  const Sel* sel = reinterpret_cast<const Sel*>(g.base + RL.off_sel);
+  const unsigned long long* gacc = reinterpret_cast<const unsigned long long*>(g.base + RL.off_wa);
+  aeb_stats* st = g.st;
   if (threadIdx.x != 0) return;
   const int G = ng >= 2 ? ng + 1 : 0;
   const double nd = static_cast<double>(n);
@@ -574,11 +723,17 @@ __global__ void k_wfin(long long n, int ng, const Sel* sel, const unsigned long 
 // BT_ROWS blocks' counts of one bin (adjacent threads, adjacent bins) and adds
 // them to the zeroed totals (integer adds: order-free).
 constexpr int BT_ROWS = 16;
-__global__ __launch_bounds__(256) void k_bin_totals(const unsigned* bhist, int nb, int hw,
-                                                    unsigned* btot) {
+__global__ __launch_bounds__(256) void k_bin_totals(RSegs S, int hw) {
+  if (S.tab && S.rmap[blockIdx.y] < 0) return;
+  const RSeg& g = S.tab ? S.tab[S.rmap[blockIdx.y]] : S.one;
+  const int row = S.tab ? static_cast<int>(blockIdx.y) - g.row0 : static_cast<int>(blockIdx.y);
+  const RLayout RL = layout(g.n, 0);
+  const unsigned* bhist = reinterpret_cast<const unsigned*>(g.base + RL.off_bh);
+  unsigned* btot = reinterpret_cast<unsigned*>(g.base + RL.off_bt);
+  const int nb = RL.nb2;
   const int j = blockIdx.x * 256 + threadIdx.x;
   if (j >= hw) return;
-  const int b0 = blockIdx.y * BT_ROWS;
+  const int b0 = row * BT_ROWS;
   const int b1 = b0 + BT_ROWS < nb ? b0 + BT_ROWS : nb;
   unsigned c = 0;
   for (int b = b0; b < b1; ++b) c += bhist[static_cast<size_t>(b) * hw + j];
@@ -587,14 +742,25 @@ __global__ __launch_bounds__(256) void k_bin_totals(const unsigned* bhist, int n
 
 // Block 0: the sd and the risk curve.  Block 1 + t: find the value bin
 // holding target t's rank.
-__global__ __launch_bounds__(FB) void k_fin2(const double* part, int nb, long long n, int ng,
-                                             aeb_stats* st, Sel* sel, SelIn in,
-                                             const unsigned* btot, const unsigned* bhist, int hw,
-                                             unsigned* boff) {
+__global__ __launch_bounds__(FB) void k_fin2(RSegs S, RReq rq, int hw) {
+  const int T1 = 1 + rq.n_risk + rq.n_mq;
+  if (static_cast<int>(blockIdx.x / T1) >= seg_count(S)) return;
+  const RSeg& g = seg_at(S, blockIdx.x / T1);
+  const int bx = blockIdx.x % T1;
+  const long long n = g.n;
+  const int ng = rq.ng;
+  const RLayout RL = layout(n, T1 - 1);
+  const double* part = reinterpret_cast<const double*>(g.base + RL.off_var);
+  const int nb = RL.nb2;
+  aeb_stats* st = g.st;
+  Sel* sel = reinterpret_cast<Sel*>(g.base + RL.off_sel);
+  const unsigned* btot = reinterpret_cast<const unsigned*>(g.base + RL.off_bt);
+  const unsigned* bhist = reinterpret_cast<const unsigned*>(g.base + RL.off_bh);
+  unsigned* boff = reinterpret_cast<unsigned*>(g.base + RL.off_bo);
   __shared__ double shd[FB];
   __shared__ unsigned long long shu[FB];
   __shared__ int s_bin;
-  if (blockIdx.x == 0) {
+  if (bx == 0) {
     double ss = 0.0;
     for (int b = threadIdx.x; b < nb; b += FB) ss += part[b];
     ss = block_reduce<FB>(ss, shd, AddOp());
@@ -620,10 +786,10 @@ __global__ __launch_bounds__(FB) void k_fin2(const double* part, int nb, long lo
     }
     return;
   }
-  const int t = blockIdx.x - 1;
-  if (t >= in.count) return;
+  const int t = bx - 1;
+  if (t >= (rq.n_risk + rq.n_mq)) return;
   if (threadIdx.x == 0) s_bin = -1;
-  const unsigned* tot = btot + (in.kind[t] ? (NVB + 1) : 0);
+  const unsigned* tot = btot + (sel_kind(rq, t) ? (NVB + 1) : 0);
   constexpr int PER = (NVB + 1 + FB - 1) / FB;
   unsigned cnt[PER];
   unsigned long long loc = 0;
@@ -632,7 +798,7 @@ __global__ __launch_bounds__(FB) void k_fin2(const double* part, int nb, long lo
     cnt[q] = j <= NVB ? tot[j] : 0u;
     loc += cnt[q];
   }
-  const unsigned long long r = in.rank[t];
+  const unsigned long long r = sel_rank(rq, n, t);
   unsigned long long before = block_exscan<FB>(loc, shu);
   if (r >= before && r < before + loc) {
     for (int q = 0; q < PER; ++q) {
@@ -643,7 +809,7 @@ __global__ __launch_bounds__(FB) void k_fin2(const double* part, int nb, long lo
         sel->bin_count[t] = cnt[q];
         if (j == NVB) {  // the rank falls among the censored (+inf) samples
           sel->bin[t] = -1;
-          if (t < in.n_risk) st->headway[t] = INFINITY;
+          if (t < rq.n_risk) st->headway[t] = INFINITY;
         } else if (cnt[q] > CAP) {
           sel->bin[t] = -1;
           atomicOr(&sel->fallback, 1);
@@ -662,7 +828,7 @@ __global__ __launch_bounds__(FB) void k_fin2(const double* part, int nb, long lo
   // collection needs no global atomics (it uses the histogram pass's blocks)
   const int j = s_bin;
   if (j < 0) return;
-  const int col = (in.kind[t] ? (NVB + 1) : 0) + j;
+  const int col = (sel_kind(rq, t) ? (NVB + 1) : 0) + j;
   unsigned long long carry = 0;
   for (int b0 = 0; b0 < nb; b0 += FB) {
     const int b = b0 + static_cast<int>(threadIdx.x);
@@ -679,26 +845,37 @@ __global__ __launch_bounds__(FB) void k_fin2(const double* part, int nb, long lo
 // Collect the keys of every element in a target's bin: block b of the
 // histogram pass's decomposition writes its elements from the offset the bin
 // search computed for it, ranked inside the block by LDS counters.
-__global__ __launch_bounds__(EB) void k_collect(OutCols o, long long n, long long chunk, Sel* sel,
-                                                SelIn in, const unsigned* boff,
-                                                unsigned long long* cand) {
+__global__ __launch_bounds__(EB) void k_collect(RSegs S, RReq rq) {
+  int bx;
+  const RSeg* gp = seg_of_block(S, blockIdx.x, bx);
+  if (!gp) return;  // beyond the launch's sets (the whole block)
+  const RSeg& g = *gp;
+  const OutCols o = g.out;
+  const long long n = g.n;
+  const long long chunk = static_cast<long long>(EB) * CP;
+  const RLayout RL = layout(n, rq.n_risk + rq.n_mq);
+  const Sel* sel = reinterpret_cast<const Sel*>(g.base + RL.off_sel);
+  const unsigned* boff = reinterpret_cast<const unsigned*>(g.base + RL.off_bo);
+  unsigned long long* cand = reinterpret_cast<unsigned long long*>(g.base + RL.off_cand);
+  const int nbk = RL.nb2;
+  const unsigned ccap = RL.ccap;
   __shared__ int tb[MAX_T], tk[MAX_T];
   __shared__ unsigned lc[MAX_T], lbase[MAX_T];
   __shared__ double vmin[2], scale[2];
-  const int T = in.count;
+  const int T = (rq.n_risk + rq.n_mq);
   if (static_cast<int>(threadIdx.x) < T) {
     tb[threadIdx.x] = sel->bin[threadIdx.x];
-    tk[threadIdx.x] = in.kind[threadIdx.x];
+    tk[threadIdx.x] = sel_kind(rq, threadIdx.x);
     lc[threadIdx.x] = 0u;
     lbase[threadIdx.x] =
-        tb[threadIdx.x] >= 0 ? boff[static_cast<size_t>(threadIdx.x) * gridDim.x + blockIdx.x] : 0u;
+        tb[threadIdx.x] >= 0 ? boff[static_cast<size_t>(threadIdx.x) * nbk + bx] : 0u;
   }
   if (threadIdx.x < 2) {
     vmin[threadIdx.x] = sel->vmin[threadIdx.x];
     scale[threadIdx.x] = sel->scale[threadIdx.x];
   }
   __syncthreads();
-  const long long lo = static_cast<long long>(blockIdx.x) * chunk;
+  const long long lo = static_cast<long long>(bx) * chunk;
   const long long hi = lo + chunk < n ? lo + chunk : n;
   // each pass loads CP elements per thread before using any of them
   for (long long i0 = lo; i0 < hi; i0 += static_cast<long long>(EB) * CP) {
@@ -732,7 +909,7 @@ __global__ __launch_bounds__(EB) void k_collect(OutCols o, long long n, long lon
         const int b = tk[t] ? bm : bd;
         if (tb[t] >= 0 && b == tb[t]) {
           const unsigned slot = lbase[t] + atomicAdd(&lc[t], 1u);
-          if (slot < CAP) cand[t * CAP + slot] = ordered(tk[t] ? m : dc);
+          if (slot < ccap) cand[t * ccap + slot] = ordered(tk[t] ? m : dc);
         }
       }
     }
@@ -742,22 +919,29 @@ __global__ __launch_bounds__(EB) void k_collect(OutCols o, long long n, long lon
 // One block per target: the element of rank r among the bin's candidates by
 // a most-significant-digit radix select in LDS, starting at the first byte
 // in which the candidates differ (they share the bin's leading bits).
-__global__ __launch_bounds__(RB) void k_pick(const Sel* sel, SelIn in,
-                                             const unsigned long long* cand, aeb_stats* st) {
+__global__ __launch_bounds__(RB) void k_pick(RSegs S, RReq rq) {
+  const int T = rq.n_risk + rq.n_mq;
+  if (static_cast<int>(blockIdx.x / T) >= seg_count(S)) return;
+  const RSeg& g = seg_at(S, blockIdx.x / T);
+  const int t = blockIdx.x % T;
+  const RLayout RL = layout(g.n, T);
+  const Sel* sel = reinterpret_cast<const Sel*>(g.base + RL.off_sel);
+  const unsigned long long* cand = reinterpret_cast<const unsigned long long*>(g.base + RL.off_cand);
+  const unsigned ccap = RL.ccap;
+  aeb_stats* st = g.st;
   __shared__ unsigned long long key[CAP];
   __shared__ unsigned hist[256];
   __shared__ unsigned long long wlo[RB / 64], whi[RB / 64];
   __shared__ unsigned long long s_prefix;
   __shared__ unsigned s_rank;
-  const int t = blockIdx.x;
   // the host reads the fallback flag through the statistics' reserved word
   if (t == 0 && threadIdx.x == 0) st->reserved = sel->fallback;
-  if (t >= in.count || sel->bin[t] < 0) return;
+  if (t >= (rq.n_risk + rq.n_mq) || sel->bin[t] < 0) return;
   // every element of the bin was collected (the bin holds at most CAP)
-  const unsigned m = sel->bin_count[t] < CAP ? sel->bin_count[t] : CAP;
+  const unsigned m = sel->bin_count[t] < ccap ? sel->bin_count[t] : ccap;
   unsigned long long lo = ~0ull, hi = 0ull;
   for (unsigned j = threadIdx.x; j < m; j += RB) {
-    const unsigned long long k = cand[t * CAP + j];
+    const unsigned long long k = cand[t * ccap + j];
     key[j] = k;
     lo = k < lo ? k : lo;
     hi = k > hi ? k : hi;
@@ -826,10 +1010,10 @@ __global__ __launch_bounds__(RB) void k_pick(const Sel* sel, SelIn in,
   }
   if (threadIdx.x == 0) {
     const double v = unordered(first == 8 ? lo : s_prefix);
-    if (t < in.n_risk)
+    if (t < rq.n_risk)
       st->headway[t] = v;
     else
-      st->margin_q[t - in.n_risk] = v;
+      st->margin_q[t - rq.n_risk] = v;
   }
 }
 
@@ -889,130 +1073,268 @@ __global__ void k_select_out(const SelState* ss, int n_risk, aeb_stats* st) {
     st->margin_q[t - n_risk] = v;
 }
 
-size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
 
 }  // namespace
 
 namespace {
 
-// Scratch layout of one reduction: stats, selection state and the bin totals
-// (selection bins and risk-grid ranks) first (zeroed by one launch), then the
-// block partials, the block histograms, the candidates and the radix-select
-// state.
-struct RLayout {
-  long long chunk, chunk2;
-  int nb, nb2, T;
-  size_t off_sel, off_zero_end, off_var, off_bh, off_bt, off_wa, off_bo, off_cand, off_ss, off_sh,
-      total;
+// zero each set's selection state, bin totals and weighted accumulators, and
+// its statistics (fill kernels: no memset nodes in recorded graphs)
+__global__ void k_zero_sets(RSegs S) {
+  if (static_cast<int>(blockIdx.y) >= seg_count(S)) return;
+  const RSeg& g = seg_at(S, blockIdx.y);
+  const RLayout RL = layout(g.n, 0);
+  unsigned* a = reinterpret_cast<unsigned*>(g.base + RL.off_sel);
+  const long long na = static_cast<long long>((RL.off_zero_end - RL.off_sel) / 4);
+  unsigned* b = reinterpret_cast<unsigned*>(g.st);
+  const long long nw = static_cast<long long>(sizeof(aeb_stats) / 4);
+  const long long stride = static_cast<long long>(gridDim.x) * blockDim.x;
+  for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < na; i += stride)
+    a[i] = 0u;
+  for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < nw; i += stride)
+    b[i] = 0u;
+}
+
+int n_targets(const aeb_reduce_req& req) { return req.n_risk + req.n_margin_q; }
+
+RReq rreq_of(const aeb_reduce_req& req) {
+  RReq q;
+  std::memset(&q, 0, sizeof(q));
+  q.n_risk = req.n_risk;
+  q.n_mq = req.n_margin_q;
+  q.ng = req.n_grid;
+  for (int j = 0; j < req.n_risk; ++j) q.risk[j] = req.risk[j];
+  for (int j = 0; j < req.n_margin_q; ++j) q.mq[j] = req.margin_q[j];
+  q.glo = req.grid_lo;
+  q.gstep = q.ng >= 2 ? (req.grid_hi - req.grid_lo) / static_cast<double>(q.ng - 1) : 0.0;
+  q.ginv = q.ng >= 2 ? 1.0 / q.gstep : 0.0;
+  return q;
+}
+
+// Table of a segmented launch, laid out for a capacity of sets, element-pass
+// blocks and bin-totals rows: the launch's set count, the sets, the set of
+// every block and row (-1 past the launch's), then (device only) the sets'
+// statistics.
+struct TLayout {
+  int cap, tb, tr;
+  size_t off_seg, off_bmap, off_rmap, host_bytes, off_stats, total;
 };
 
-RLayout layout(int64_t n, const aeb_reduce_req& req) {
-  RLayout L;
-  // element passes: 4,096 elements per block of 1,024 threads (measured faster
-  // than smaller blocks or slices: fewer partials, block histograms and
-  // per-block fixed costs)
-  L.chunk = EB * CP;
-  L.chunk2 = EB * CP;
-  L.nb = static_cast<int>((n + L.chunk - 1) / L.chunk);
-  L.nb2 = static_cast<int>((n + L.chunk2 - 1) / L.chunk2);
-  L.T = req.n_risk + req.n_margin_q;
-  const int tc = L.T > 0 ? L.T : 1;
-  L.off_sel = align256(sizeof(aeb_stats));
-  L.off_bt = align256(L.off_sel + sizeof(Sel));
-  L.off_wa = align256(L.off_bt + sizeof(unsigned) * HW);
-  L.off_zero_end = align256(L.off_wa + sizeof(unsigned long long) * WACC);
-  L.off_var = align256(L.off_zero_end + sizeof(Partial) * L.nb);
-  L.off_bh = align256(L.off_var + sizeof(double) * (L.nb > L.nb2 ? L.nb : L.nb2));
-  L.off_bo = align256(L.off_bh + sizeof(unsigned) * HW * L.nb2);
-  L.off_cand = align256(L.off_bo + sizeof(unsigned) * tc * L.nb2);
-  L.off_ss = align256(L.off_cand + sizeof(unsigned long long) * tc * CAP);
-  L.off_sh = align256(L.off_ss + sizeof(SelState));
-  L.total = align256(L.off_sh + sizeof(unsigned) * tc * 256);
-  return L;
+TLayout tlayout_of(int cap, int tb, int tr) {
+  TLayout T;
+  T.cap = cap;
+  T.tb = tb;
+  T.tr = tr;
+  T.off_seg = 256;
+  T.off_bmap = align256(T.off_seg + sizeof(RSeg) * cap);
+  T.off_rmap = align256(T.off_bmap + sizeof(int) * tb);
+  T.host_bytes = T.off_rmap + sizeof(int) * tr;
+  T.off_stats = align256(T.host_bytes);
+  T.total = align256(T.off_stats + sizeof(aeb_stats) * cap);
+  return T;
+}
+
+// exactly the given sets
+TLayout tlayout(int nseg, const int64_t* ns) {
+  int tb = 0, tr = 0;
+  for (int j = 0; j < nseg; ++j) {
+    const RLayout L = layout(ns[j], 0);
+    tb += L.nb;
+    tr += (L.nb2 + BT_ROWS - 1) / BT_ROWS;
+  }
+  return tlayout_of(nseg, tb, tr);
+}
+
+// any cap sets of cap_samples samples in all: every set adds at most one
+// partly filled block and one partly filled row
+TLayout tlayout_cap(int cap, int64_t cap_samples) {
+  const long long chunk = static_cast<long long>(EB) * CP;
+  const int tb = static_cast<int>(cap_samples / chunk) + cap;
+  return tlayout_of(cap, tb, tb / BT_ROWS + cap);
+}
+
+// Fill the host side of the table for the sets (which must fit T); returns
+// whether any set carries importance-sampling weights.
+bool fill_table(const TLayout& T, const OutCols* outs, const int64_t* ns, int nseg,
+                char* const* bases, char* table_dev, char* hb) {
+  *reinterpret_cast<int*>(hb) = nseg;
+  RSeg* seg = reinterpret_cast<RSeg*>(hb + T.off_seg);
+  int* bmap = reinterpret_cast<int*>(hb + T.off_bmap);
+  int* rmap = reinterpret_cast<int*>(hb + T.off_rmap);
+  aeb_stats* dst = reinterpret_cast<aeb_stats*>(table_dev + T.off_stats);
+  bool weighted = false;
+  int blk = 0, row = 0;
+  for (int j = 0; j < nseg; ++j) {
+    const RLayout L = layout(ns[j], 0);
+    std::memset(&seg[j], 0, sizeof(RSeg));
+    seg[j].out = outs[j];
+    seg[j].n = ns[j];
+    seg[j].base = bases[j];
+    seg[j].st = dst + j;
+    seg[j].nb = L.nb;
+    seg[j].blk0 = blk;
+    seg[j].row0 = row;
+    for (int b = 0; b < L.nb; ++b) bmap[blk + b] = j;
+    const int rows = (L.nb2 + BT_ROWS - 1) / BT_ROWS;
+    for (int r = 0; r < rows; ++r) rmap[row + r] = j;
+    blk += L.nb;
+    row += rows;
+    weighted = weighted || outs[j].weight != nullptr;
+  }
+  for (int b = blk; b < T.tb; ++b) bmap[b] = -1;
+  for (int r = row; r < T.tr; ++r) rmap[r] = -1;
+  return weighted;
+}
+
+RSegs table_segs(const TLayout& T, const char* db) {
+  RSegs S;
+  std::memset(&S, 0, sizeof(S));
+  S.tab = reinterpret_cast<const RSeg*>(db + T.off_seg);
+  S.bmap = reinterpret_cast<const int*>(db + T.off_bmap);
+  S.rmap = reinterpret_cast<const int*>(db + T.off_rmap);
+  S.count = reinterpret_cast<const int*>(db);
+  return S;
+}
+
+// The launch sequence over the sets of S (grids from the totals).
+int enqueue_sets(const RSegs& S, int nseg, int tb, int tr, bool weighted,
+                 const aeb_reduce_req& req, hipStream_t st) {
+  // nseg, tb, tr: the grids' capacity of sets, element-pass blocks and rows
+  const RReq q = rreq_of(req);
+  const int T = n_targets(req);
+  const int ng = req.n_grid;
+  hipLaunchKernelGGL(k_zero_sets, dim3(32, nseg), dim3(256), 0, st, S);
+  hipLaunchKernelGGL(k_pass1, dim3(tb), dim3(EB), 0, st, S);
+  hipLaunchKernelGGL(k_fin1, dim3(nseg), dim3(FB), 0, st, S);
+  // block histograms: the value bins only when some target needs them
+  const int hw = ng >= 2 ? HG + ng + 1 : (T > 0 ? HG : 0);
+  hipLaunchKernelGGL(k_pass2, dim3(tb), dim3(EB), 0, st, S, req.n_risk > 0 ? 1 : 0,
+                     req.n_margin_q > 0 ? 1 : 0, q, hw);
+  if (hw > 0)
+    hipLaunchKernelGGL(k_bin_totals, dim3((hw + 255) / 256, tr), dim3(256), 0, st, S, hw);
+  hipLaunchKernelGGL(k_fin2, dim3(nseg * (1 + T)), dim3(FB), 0, st, S, q, hw);
+  if (weighted) {
+    hipLaunchKernelGGL(k_wpass, dim3(tb), dim3(EB), 0, st, S, q);
+    hipLaunchKernelGGL(k_wfin, dim3(nseg), dim3(64), 0, st, S, ng);
+  }
+  if (T > 0) {
+    hipLaunchKernelGGL(k_collect, dim3(tb), dim3(EB), 0, st, S, q);
+    hipLaunchKernelGGL(k_pick, dim3(nseg * T), dim3(RB), 0, st, S, q);
+  }
+  AEB_HIP(hipGetLastError());
+  return AEB_OK;
 }
 
 }  // namespace
 
-size_t reduce_scratch_bytes(int64_t n, const aeb_reduce_req& req) { return layout(n, req).total; }
+size_t reduce_scratch_bytes(int64_t n, const aeb_reduce_req& req) {
+  return layout(n, n_targets(req)).total;
+}
+
+size_t reduce_scratch_bytes_cap(int cap_sets, int64_t cap_samples, const aeb_reduce_req& req) {
+  // a set's scratch is a fixed part, parts per element-pass block and the
+  // candidate lists (min(n, CAP) per target), each rounded up to 256 bytes:
+  // bound the blocks by cap_samples / chunk + cap_sets and the candidates
+  // by min(cap_samples, cap_sets * CAP)
+  const int T = n_targets(req);
+  const int tc = T > 0 ? T : 1;
+  const RLayout one = layout(1, T);
+  const long long chunk = static_cast<long long>(EB) * CP;
+  const size_t blocks = static_cast<size_t>(cap_samples / chunk) + cap_sets + 1;
+  const size_t per_block = sizeof(Partial) + sizeof(double) + sizeof(unsigned) * HW +
+                           sizeof(unsigned) * tc;
+  const size_t cand = static_cast<size_t>(cap_samples < static_cast<int64_t>(cap_sets) * CAP
+                                              ? cap_samples
+                                              : static_cast<int64_t>(cap_sets) * CAP);
+  return static_cast<size_t>(cap_sets) * (one.total + 8 * 256) + blocks * per_block +
+         cand * sizeof(unsigned long long) * tc;
+}
 
 int reduce_enqueue(const OutCols& out, int64_t n, const aeb_reduce_req& req, void* scratch_base,
                    aeb_stats* host_out, hipStream_t st) {
-  const RLayout L = layout(n, req);
-  const int ng = req.n_grid;
-  const int T = L.T;
-  char* base = static_cast<char*>(scratch_base);
-  aeb_stats* dstats = reinterpret_cast<aeb_stats*>(base);
-  Sel* sel = reinterpret_cast<Sel*>(base + L.off_sel);
-  Partial* part = reinterpret_cast<Partial*>(base + L.off_zero_end);
-  double* vpart = reinterpret_cast<double*>(base + L.off_var);
-  unsigned* bhist = reinterpret_cast<unsigned*>(base + L.off_bh);
-  unsigned* btot = reinterpret_cast<unsigned*>(base + L.off_bt);
-  unsigned* boff = reinterpret_cast<unsigned*>(base + L.off_bo);
-  unsigned long long* wacc = reinterpret_cast<unsigned long long*>(base + L.off_wa);
-  unsigned long long* cand = reinterpret_cast<unsigned long long*>(base + L.off_cand);
-
-  // targets: ranks computed exactly as floor(level * N) in binary64
-  SelIn in;
-  std::memset(&in, 0, sizeof(in));
-  in.count = T;
-  in.n_risk = req.n_risk;
-  bool need_d = false, need_m = false;
-  for (int j = 0; j < req.n_risk; ++j) {
-    long long m = static_cast<long long>(std::floor(req.risk[j] * static_cast<double>(n)));
-    in.rank[j] = static_cast<unsigned long long>(n - m - 1);
-    in.kind[j] = 0;
-    need_d = true;
-  }
-  for (int j = 0; j < req.n_margin_q; ++j) {
-    long long m = static_cast<long long>(std::floor(req.margin_q[j] * static_cast<double>(n)));
-    in.rank[req.n_risk + j] = static_cast<unsigned long long>(m);
-    in.kind[req.n_risk + j] = 1;
-    need_m = true;
-  }
-  static_assert(sizeof(aeb_stats) % 4 == 0, "stats size");
-  const long long zero_words = static_cast<long long>(L.off_zero_end / 4);
-  hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<unsigned>((zero_words + 255) / 256)), dim3(256),
-                     0, st, reinterpret_cast<unsigned*>(base), zero_words);
-  const double gstep = ng >= 2 ? (req.grid_hi - req.grid_lo) / static_cast<double>(ng - 1) : 0.0;
-  hipLaunchKernelGGL(k_pass1, dim3(L.nb), dim3(EB), 0, st, out, static_cast<long long>(n), L.chunk,
-                     part);
-  hipLaunchKernelGGL(k_fin1, dim3(1), dim3(FB), 0, st, part, L.nb, static_cast<long long>(n),
-                     out.weight ? 1 : 0, dstats, sel);
-  // block histograms: the value bins only when some target needs them
-  const int hw = ng >= 2 ? HG + ng + 1 : (T > 0 ? HG : 0);
-  hipLaunchKernelGGL(k_pass2, dim3(L.nb2), dim3(EB), 0, st, out, static_cast<long long>(n),
-                     L.chunk2, dstats, sel, need_d ? 1 : 0, need_m ? 1 : 0, req.grid_lo, gstep,
-                     ng >= 2 ? 1.0 / gstep : 0.0,
-                     ng, hw, bhist, vpart);
-  if (hw > 0)
-    hipLaunchKernelGGL(k_bin_totals, dim3((hw + 255) / 256, (L.nb2 + BT_ROWS - 1) / BT_ROWS),
-                       dim3(256), 0, st, bhist, L.nb2, hw, btot);
-  hipLaunchKernelGGL(k_fin2, dim3(1 + T), dim3(FB), 0, st, vpart, L.nb2,
-                     static_cast<long long>(n), ng, dstats, sel, in, btot, bhist, hw, boff);
-  if (out.weight) {
-    hipLaunchKernelGGL(k_wpass, dim3(L.nb2), dim3(EB), 0, st, out, static_cast<long long>(n),
-                       L.chunk2, req.grid_lo, gstep, ng >= 2 ? 1.0 / gstep : 0.0, ng, sel, wacc);
-    hipLaunchKernelGGL(k_wfin, dim3(1), dim3(64), 0, st, static_cast<long long>(n), ng, sel, wacc,
-                       dstats);
-  }
-  if (T > 0) {
-    // the histogram pass's blocks: the offsets above are per block of it
-    hipLaunchKernelGGL(k_collect, dim3(L.nb2), dim3(EB), 0, st, out, static_cast<long long>(n),
-                       L.chunk2, sel, in, boff, cand);
-    hipLaunchKernelGGL(k_pick, dim3(T), dim3(RB), 0, st, sel, in, cand, dstats);
-  }
-  AEB_HIP(hipGetLastError());
-  AEB_HIP(hipMemcpyAsync(host_out, dstats, sizeof(aeb_stats), hipMemcpyDeviceToHost, st));
+  const RLayout L = layout(n, n_targets(req));
+  RSegs S;
+  std::memset(&S, 0, sizeof(S));
+  S.one.out = out;
+  S.one.n = n;
+  S.one.base = static_cast<char*>(scratch_base);
+  S.one.st = reinterpret_cast<aeb_stats*>(scratch_base);
+  S.one.nb = L.nb;
+  const int rc = enqueue_sets(S, 1, L.nb, (L.nb2 + BT_ROWS - 1) / BT_ROWS, out.weight != nullptr,
+                              req, st);
+  if (rc != AEB_OK) return rc;
+  AEB_HIP(hipMemcpyAsync(host_out, S.one.st, sizeof(aeb_stats), hipMemcpyDeviceToHost, st));
   return AEB_OK;
 }
 
+size_t reduce_table_bytes(int nseg, const int64_t* ns) { return tlayout(nseg, ns).total; }
+
+size_t reduce_table_bytes_cap(int cap_sets, int64_t cap_samples) {
+  return tlayout_cap(cap_sets, cap_samples).total;
+}
+
+aeb_stats* reduce_table_stats(void* table_dev, int nseg, const int64_t* ns) {
+  return reinterpret_cast<aeb_stats*>(static_cast<char*>(table_dev) + tlayout(nseg, ns).off_stats);
+}
+
+aeb_stats* reduce_table_stats_cap(void* table_dev, int cap_sets, int64_t cap_samples) {
+  return reinterpret_cast<aeb_stats*>(static_cast<char*>(table_dev) +
+                                      tlayout_cap(cap_sets, cap_samples).off_stats);
+}
+
+int reduce_enqueue_sets(const OutCols* outs, const int64_t* ns, int nseg,
+                        const aeb_reduce_req& req, char* const* bases, void* table_dev,
+                        void* table_host, aeb_stats* host_out, hipStream_t st) {
+  if (nseg < 1) return fail(AEB_EINVAL, "reduction of no output sets");
+  const TLayout T = tlayout(nseg, ns);
+  char* db = static_cast<char*>(table_dev);
+  char* hb = static_cast<char*>(table_host);
+  const bool weighted = fill_table(T, outs, ns, nseg, bases, db, hb);
+  AEB_HIP(hipMemcpyAsync(db, hb, T.host_bytes, hipMemcpyHostToDevice, st));
+  const int rc = enqueue_sets(table_segs(T, db), T.cap, T.tb, T.tr, weighted, req, st);
+  if (rc != AEB_OK) return rc;
+  AEB_HIP(hipMemcpyAsync(host_out, db + T.off_stats, sizeof(aeb_stats) * nseg,
+                         hipMemcpyDeviceToHost, st));
+  return AEB_OK;
+}
+
+int reduce_fill_sets_cap(const OutCols* outs, const int64_t* ns, int nseg, int cap_sets,
+                         int64_t cap_samples, char* const* bases, void* table_dev,
+                         void* table_host) {
+  int64_t tot = 0;
+  for (int j = 0; j < nseg; ++j) tot += ns[j];
+  if (nseg < 1 || nseg > cap_sets || tot > cap_samples)
+    return fail(AEB_EINVAL, "output sets beyond the recorded reduction's capacity");
+  (void)fill_table(tlayout_cap(cap_sets, cap_samples), outs, ns, nseg, bases,
+                   static_cast<char*>(table_dev), static_cast<char*>(table_host));
+  return AEB_OK;
+}
+
+int reduce_enqueue_sets_cap(int cap_sets, int64_t cap_samples, const aeb_reduce_req& req,
+                            bool weighted, void* table_dev, const void* table_host,
+                            aeb_stats* host_out, hipStream_t st) {
+  const TLayout T = tlayout_cap(cap_sets, cap_samples);
+  char* db = static_cast<char*>(table_dev);
+  AEB_HIP(hipMemcpyAsync(db, table_host, T.host_bytes, hipMemcpyHostToDevice, st));
+  const int rc = enqueue_sets(table_segs(T, db), T.cap, T.tb, T.tr, weighted, req, st);
+  if (rc != AEB_OK) return rc;
+  AEB_HIP(hipMemcpyAsync(host_out, db + T.off_stats, sizeof(aeb_stats) * cap_sets,
+                         hipMemcpyDeviceToHost, st));
+  return AEB_OK;
+}
+
+static std::atomic<unsigned long long> g_fallbacks{0};
+
+unsigned long long reduce_fallback_count() { return g_fallbacks.load(); }
+
 int reduce_fallback(const OutCols& out, int64_t n, const aeb_reduce_req& req, void* scratch_base,
-                    aeb_stats* host_out, hipStream_t st) {
-  // a target's value bin held more than CAP distinct candidates: radix select
-  const RLayout L = layout(n, req);
+                    aeb_stats* dstats, aeb_stats* host_out, hipStream_t st) {
+  // a target's value bin held more than CAP candidates: radix select
+  g_fallbacks.fetch_add(1);
+  const RLayout L = layout(n, n_targets(req));
   const int T = L.T;
   char* base = static_cast<char*>(scratch_base);
-  aeb_stats* dstats = reinterpret_cast<aeb_stats*>(base);
   SelState* ss = reinterpret_cast<SelState*>(base + L.off_ss);
   unsigned* shist = reinterpret_cast<unsigned*>(base + L.off_sh);
   SelState rs;
@@ -1057,7 +1379,67 @@ int launch_reduce(const OutCols& out, int64_t n, const aeb_reduce_req& req, aeb_
   const int fallback = host_out->reserved;
   host_out->reserved = 0;
   if (!fallback) return AEB_OK;
-  return reduce_fallback(out, n, req, base, host_out, st);
+  return reduce_fallback(out, n, req, base, static_cast<aeb_stats*>(base), host_out, st);
+}
+
+int launch_batch_reduce(const OutCols* outs, const int64_t* ns, int nseg,
+                        const aeb_reduce_req& req, aeb_stats* host_out, hipStream_t st) {
+  // consecutive sets in groups of at most GROUP_BYTES of set scratch (or one
+  // larger set): one launch sequence per group, all groups on one pool block
+  constexpr size_t GROUP_BYTES = size_t(256) << 20;
+  constexpr int GROUP_SETS = 4096;
+  std::vector<int> first{0};
+  size_t need = 0;
+  {
+    size_t acc = 0;
+    int cnt = 0;
+    for (int j = 0; j < nseg; ++j) {
+      const size_t b = align256(reduce_scratch_bytes(ns[j], req));
+      if (cnt > 0 && (acc + b > GROUP_BYTES || cnt == GROUP_SETS)) {
+        first.push_back(j);
+        acc = 0;
+        cnt = 0;
+      }
+      acc += b;
+      ++cnt;
+    }
+    first.push_back(nseg);
+    for (size_t g = 0; g + 1 < first.size(); ++g) {
+      const int a = first[g], c = first[g + 1] - first[g];
+      size_t bytes = align256(reduce_table_bytes(c, ns + a));
+      for (int j = a; j < a + c; ++j) bytes += align256(reduce_scratch_bytes(ns[j], req));
+      need = bytes > need ? bytes : need;
+    }
+  }
+  char* pool = static_cast<char*>(pool_block(need, st));
+  if (!pool) return AEB_ENOMEM;
+  std::vector<char> host;
+  std::vector<char*> bases;
+  for (size_t g = 0; g + 1 < first.size(); ++g) {
+    const int a = first[g], c = first[g + 1] - first[g];
+    const size_t tbytes = align256(reduce_table_bytes(c, ns + a));
+    host.assign(tbytes, 0);
+    bases.clear();
+    char* p = pool + tbytes;
+    for (int j = a; j < a + c; ++j) {
+      bases.push_back(p);
+      p += align256(reduce_scratch_bytes(ns[j], req));
+    }
+    int rc = reduce_enqueue_sets(outs + a, ns + a, c, req, bases.data(), pool, host.data(),
+                                 host_out + a, st);
+    if (rc != AEB_OK) return rc;
+    AEB_HIP(hipStreamSynchronize(st));
+    aeb_stats* dst = reduce_table_stats(pool, c, ns + a);
+    for (int j = 0; j < c; ++j) {
+      aeb_stats& h = host_out[a + j];
+      const int fallback = h.reserved;
+      h.reserved = 0;
+      if (!fallback) continue;
+      rc = reduce_fallback(outs[a + j], ns[a + j], req, bases[j], dst + j, &h, st);
+      if (rc != AEB_OK) return rc;
+    }
+  }
+  return AEB_OK;
 }
 
 }  // namespace aeb

@@ -3,15 +3,21 @@
 //
 // A launch ("tick") runs the admitted requests of one kind as one sorted
 // multi-scenario rollout (parameters drawn in-kernel from each request's seed
-// and id, so nothing per sample crosses PCIe) followed by one reduction per
-// request, all on one of the server's streams; the statistics land in pinned
-// host slots and an event marks the tick's end.  All device memory comes from
+// and id, so nothing per sample crosses PCIe) followed by one segmented
+// reduction over all of its requests, all on one of the server's streams; the
+// statistics land in pinned host memory and an event marks the tick's end.
+// A tick replays a HIP graph recorded once per stream and bucket (kind,
+// perception, scenario count and samples rounded up to powers of two): the
+// host writes the tick's scenario and set tables into pinned memory and the
+// graph's first nodes copy them to the device, so the mix changes from tick
+// to tick while the recording stays the same.  All device memory comes from
 // the caller's arena: per stream, the rollout's job records and sort buffers
-// for max_tick_samples samples; per request, its output columns and the
-// reduction's scratch.
+// for max_tick_samples samples and the device tables; per request, its
+// output columns and the reduction's scratch.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <map>
 #include <memory>
 #include <new>
 #include <string>
@@ -19,6 +25,7 @@
 
 #include "aeb_runtime.h"
 #include "fast_path.h"
+#include "mixgraph.h"
 #include "serve_sched.h"
 
 namespace aeb {
@@ -43,8 +50,13 @@ OutCols out_cols(char* base, int64_t n) {
   return o;
 }
 
+size_t table_bytes(const aeb_server_cfg& c) {
+  return up256(reduce_table_bytes_cap(c.max_slots, c.max_tick_samples));
+}
+
 size_t stream_bytes(const aeb_server_cfg& c) {
-  return up256(batch_scratch_bytes(c.max_tick_samples, c.max_slots, true));
+  return up256(batch_scratch_bytes(c.max_tick_samples, c.max_slots, true)) + table_bytes(c) +
+         up256(mix_table_bytes(c.max_slots));
 }
 
 size_t request_bytes(const aeb_server_cfg& c, int64_t n) {
@@ -61,6 +73,7 @@ int check_cfg(const aeb_server_cfg* c) {
   if (c->max_queue < 1) return fail(AEB_EINVAL, "max_queue must be >= 1");
   if (c->max_tick_samples < 1 || c->max_tick_samples > 0x7fffffffLL)
     return fail(AEB_EINVAL, "max_tick_samples outside 1..2^31-1");
+  if (c->flags & ~AEB_SERVE_EAGER) return fail(AEB_EINVAL, "unknown server flags");
   return check_reduce_req(c->req);
 }
 
@@ -68,8 +81,17 @@ struct StreamCtx {
   hipStream_t st = nullptr;
   hipEvent_t ev = nullptr;
   char* scratch = nullptr;          // device: rollout scratch of one launch
+  char* rtab = nullptr;             // device: the reduction's set table
   ScnDev* tab = nullptr;            // pinned: scenario table of the launch
   aeb_scenario* scns = nullptr;     // pinned: its scenarios
+  char* rtab_host = nullptr;        // pinned: host side of the reduction's set table
+  char* mtab = nullptr;             // device: scenario tables of a recorded launch
+  char* mtab_host = nullptr;        // pinned: host side of those tables
+  aeb_stats* stats = nullptr;       // pinned: statistics of the launch's requests
+  std::vector<int64_t> ns;          // sample counts of the launch's requests
+  MixShape last;                    // bucket of the last launch (if recorded)
+  bool last_recorded = false;
+  std::map<uint64_t, MixGraph> graphs;  // recordings by bucket
   hipError_t status = hipSuccess;   // completion status of the last launch
 };
 
@@ -88,13 +110,19 @@ class HipExecutor final : public serve::Executor {
       AEB_HIP(hipStreamCreateWithFlags(&S.st, hipStreamNonBlocking));
       AEB_HIP(hipEventCreateWithFlags(&S.ev, hipEventDisableTiming));
       S.scratch = arena + sb * s;
+      S.mtab = S.scratch + (sb - up256(mix_table_bytes(cfg_.max_slots)));
+      S.rtab = S.mtab - table_bytes(cfg_);
       AEB_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.tab), sizeof(ScnDev) * cfg_.max_slots,
                             hipHostMallocDefault));
       AEB_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.scns),
                             sizeof(aeb_scenario) * cfg_.max_slots, hipHostMallocDefault));
+      AEB_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.rtab_host), table_bytes(cfg_),
+                            hipHostMallocDefault));
+      AEB_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.mtab_host),
+                            mix_table_bytes(cfg_.max_slots), hipHostMallocDefault));
+      AEB_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.stats),
+                            sizeof(aeb_stats) * cfg_.max_slots, hipHostMallocDefault));
     }
-    AEB_HIP(hipHostMalloc(reinterpret_cast<void**>(&stats_), sizeof(aeb_stats) * cfg_.max_slots,
-                          hipHostMallocDefault));
     req_base_ = arena + sb * cfg_.n_streams;
     return AEB_OK;
   }
@@ -106,10 +134,12 @@ class HipExecutor final : public serve::Executor {
       if (S.st) (void)hipStreamDestroy(S.st);
       if (S.tab) (void)hipHostFree(S.tab);
       if (S.scns) (void)hipHostFree(S.scns);
+      if (S.rtab_host) (void)hipHostFree(S.rtab_host);
+      if (S.mtab_host) (void)hipHostFree(S.mtab_host);
+      for (auto& kv : S.graphs) mix_release(&kv.second);
+      if (S.stats) (void)hipHostFree(S.stats);
       S = StreamCtx{};
     }
-    if (stats_) (void)hipHostFree(stats_);
-    stats_ = nullptr;
   }
 
   uint64_t footprint(const aeb_scenario& s) const override {
@@ -123,9 +153,8 @@ class HipExecutor final : public serve::Executor {
       return fail(AEB_EINVAL, "serving returns unweighted statistics: no importance sampling");
     if (!fast_path_applies(s, cfg_.precision) || control_on(s))
       return fail(AEB_EINVAL,
-                  "serving runs the batched block-structured path (not the unfused Euler "
-                  "form, not RK4 in FP32C, not the closed-loop controller, at most "
-                  "2^31 - 4096 steps)");
+                  "serving runs the batched block-structured path (not RK4 in FP32C, not "
+                  "the closed-loop controller, at most 2^31 - 4096 steps)");
     return AEB_OK;
   }
 
@@ -139,25 +168,88 @@ class HipExecutor final : public serve::Executor {
     return rc;
   }
 
+  // The tick's bucket: its kind, capacities rounded up to powers of two.
+  MixShape shape_of(const std::vector<serve::Request*>& tick) const {
+    MixShape m;
+    m.kind = tick[0]->scn;
+    m.precision = cfg_.precision;
+    int64_t total = 0;
+    for (const serve::Request* r : tick) {
+      m.perception = m.perception || perception_on(r->scn);
+      total += r->scn.n_samples;
+    }
+    int c = 1;
+    while (c < static_cast<int>(tick.size())) c <<= 1;
+    m.cap_scn = c < cfg_.max_slots ? c : cfg_.max_slots;
+    int64_t t = int64_t(1) << 15;
+    while (t < total) t <<= 1;
+    m.cap_total = t < cfg_.max_tick_samples ? t : cfg_.max_tick_samples;
+    m.reduce = true;
+    m.weighted = false;
+    m.req = cfg_.req;
+    return m;
+  }
+
+  static uint64_t key_of(const MixShape& m) {
+    return static_cast<uint64_t>(m.kind.integrator) | static_cast<uint64_t>(m.kind.obstacle) << 1 |
+           static_cast<uint64_t>(m.kind.impact_exit) << 3 | static_cast<uint64_t>(m.kind.nofma) << 4 |
+           static_cast<uint64_t>(m.perception) << 5 | static_cast<uint64_t>(m.cap_scn) << 6 |
+           static_cast<uint64_t>(m.cap_total) << 20;
+  }
+
+  MixBufs bufs(const StreamCtx& S) const {
+    MixBufs b;
+    b.dtab = S.mtab;
+    b.htab = S.mtab_host;
+    b.scratch = S.scratch;
+    b.drtab = S.rtab;
+    b.hrtab = S.rtab_host;
+    b.hstats = S.stats;
+    return b;
+  }
+
   int enqueue(int stream, const std::vector<serve::Request*>& tick) {
     StreamCtx& S = streams_[stream];
     const int n = static_cast<int>(tick.size());
     std::vector<OutCols> oc(n);
+    std::vector<aeb_scenario> scns(n);
+    std::vector<char*> bases(n);
+    S.ns.resize(n);
     for (int j = 0; j < n; ++j) {
-      S.scns[j] = tick[j]->scn;
-      oc[j] = out_cols(req_base_ + tick[j]->off, tick[j]->scn.n_samples);
+      scns[j] = tick[j]->scn;
+      S.ns[j] = tick[j]->scn.n_samples;
+      oc[j] = out_cols(req_base_ + tick[j]->off, S.ns[j]);
+      bases[j] = req_base_ + tick[j]->off + out_bytes(S.ns[j]);
     }
-    int64_t total = 0, cap = 1;
-    int rc = fill_batch_table(S.scns, n, oc.data(), S.tab, &total, &cap);
-    if (rc != AEB_OK) return rc;
-    rc = launch_batch_fast_into(S.scns, n, cfg_.precision, S.tab, total, cap, S.scratch, S.st);
-    if (rc != AEB_OK) return rc;
-    for (int j = 0; j < n; ++j) {
-      serve::Request* r = tick[j];
-      rc = reduce_enqueue(oc[j], r->scn.n_samples, cfg_.req,
-                          req_base_ + r->off + out_bytes(r->scn.n_samples), &stats_[r->slot],
-                          S.st);
+    int rc;
+    if (cfg_.flags & AEB_SERVE_EAGER) {
+      // the copies and kernels one by one, tables laid out for this tick
+      std::memcpy(S.scns, scns.data(), sizeof(aeb_scenario) * n);
+      int64_t total = 0, cap = 1;
+      rc = fill_batch_table(S.scns, n, oc.data(), S.tab, &total, &cap);
       if (rc != AEB_OK) return rc;
+      rc = launch_batch_fast_into(S.scns, n, cfg_.precision, S.tab, total, cap, S.scratch, S.st);
+      if (rc != AEB_OK) return rc;
+      rc = reduce_enqueue_sets(oc.data(), S.ns.data(), n, cfg_.req, bases.data(), S.rtab,
+                               S.rtab_host, S.stats, S.st);
+      if (rc != AEB_OK) return rc;
+      S.last_recorded = false;
+    } else {
+      const MixShape m = shape_of(tick);
+      const MixBufs b = bufs(S);
+      rc = mix_fill(m, scns.data(), n, oc.data(), bases.data(), b);
+      if (rc != AEB_OK) return rc;
+      const uint64_t key = key_of(m);
+      auto it = S.graphs.find(key);
+      if (it == S.graphs.end()) {
+        MixGraph g;
+        rc = mix_record(m, b, &g);
+        if (rc != AEB_OK) return rc;
+        it = S.graphs.emplace(key, g).first;
+      }
+      AEB_HIP(hipGraphLaunch(it->second.exec, S.st));
+      S.last = m;
+      S.last_recorded = true;
     }
     AEB_HIP(hipEventRecord(S.ev, S.st));
     return AEB_OK;
@@ -173,17 +265,23 @@ class HipExecutor final : public serve::Executor {
 
   void finish(int stream, const std::vector<serve::Request*>& tick) override {
     StreamCtx& S = streams_[stream];
-    for (serve::Request* r : tick) {
+    const int n = static_cast<int>(tick.size());
+    for (int j = 0; j < n; ++j) {
+      serve::Request* r = tick[j];
       if (S.status != hipSuccess) {
         r->rc = fail(AEB_EDEVICE, std::string("serving launch: ") + hipGetErrorString(S.status));
         continue;
       }
-      aeb_stats& st = stats_[r->slot];
+      aeb_stats& st = S.stats[j];
       if (st.reserved) {
         // rare: a selection bin too crowded for the in-LDS sort
         char* base = req_base_ + r->off;
+        char* red = base + out_bytes(r->scn.n_samples);
+        aeb_stats* dst =
+            S.last_recorded ? reduce_table_stats_cap(S.rtab, S.last.cap_scn, S.last.cap_total) + j
+                            : reduce_table_stats(S.rtab, n, S.ns.data()) + j;
         r->rc = reduce_fallback(out_cols(base, r->scn.n_samples), r->scn.n_samples, cfg_.req,
-                                base + out_bytes(r->scn.n_samples), &st, S.st);
+                                red, dst, &st, S.st);
       }
       st.reserved = 0;
       r->stats = st;
@@ -194,7 +292,6 @@ class HipExecutor final : public serve::Executor {
   aeb_server_cfg cfg_;
   int dev_;
   std::vector<StreamCtx> streams_;
-  aeb_stats* stats_ = nullptr;  // pinned, one per slot
   char* req_base_ = nullptr;    // device: the request part of the arena
 };
 

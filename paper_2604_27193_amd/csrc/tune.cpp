@@ -29,9 +29,10 @@ std::once_flag g_env_once;
 // wavefronts per SIMD, 128-step blocks with an obstacle and 64-step blocks
 // without; FP32C 64-step blocks, 256 threads, one pass
 TuneCfg g_tab[2][3] = {
-    {{64, 256, 4}, {128, 256, 4}, {128, 256, 4}},
-    {{64, 256, 0}, {64, 256, 0}, {64, 256, 0}},
+    {{64, 256, 4, 1}, {128, 256, 4, 1}, {128, 256, 4, 1}},
+    {{64, 256, 0, 1}, {64, 256, 0, 1}, {64, 256, 0, 1}},
 };
+std::vector<TuneResult> g_res[2][3];  // the last sweep's candidates
 
 int pidx(int precision) { return precision == AEB_FP64 ? 0 : 1; }
 
@@ -67,13 +68,15 @@ int load_file(const char* path) {
     if (b == std::string::npos) break;
     const std::string obj = txt.substr(a, b - a + 1);
     pos = b + 1;
-    long prec, obs, k, block, w;
+    long prec, obs, k, block, w, spt = 1;
     if (!field(obj, "precision", &prec) || !field(obj, "obstacle", &obs) || !field(obj, "k", &k) ||
         !field(obj, "block", &block) || !field(obj, "waves_per_simd", &w))
       return fail(AEB_EINVAL, "malformed tuning cache entry: " + obj);
-    const TuneCfg t{static_cast<int>(k), static_cast<int>(block), static_cast<int>(w)};
+    (void)field(obj, "samples_per_thread", &spt);  // absent in caches of format 1: one
+    const TuneCfg t{static_cast<int>(k), static_cast<int>(block), static_cast<int>(w),
+                    static_cast<int>(spt)};
     if ((prec != AEB_FP64 && prec != AEB_FP32C) || obs < 0 || obs > 2 ||
-        !tune_valid(static_cast<int>(prec), t))
+        !tune_valid(static_cast<int>(prec), t, static_cast<int>(obs)))
       return fail(AEB_EINVAL, "invalid tuning cache entry: " + obj);
     got.push_back(Entry{pidx(static_cast<int>(prec)), static_cast<int>(obs), t});
   }
@@ -86,14 +89,15 @@ int load_file(const char* path) {
 int save_file(const char* path, const float ms[2][3]) {
   std::ofstream f(path);
   if (!f) return fail(AEB_EINVAL, std::string("cannot write tuning cache ") + path);
-  f << "{\"format\": 1, \"entries\": [\n";
+  f << "{\"format\": 2, \"entries\": [\n";
   std::lock_guard<std::mutex> g(g_mu);
   for (int p = 0; p < 2; ++p)
     for (int o = 0; o < 3; ++o) {
       const TuneCfg& t = g_tab[p][o];
       f << "  {\"precision\": " << (p == 0 ? AEB_FP64 : AEB_FP32C) << ", \"obstacle\": " << o
         << ", \"k\": " << t.k << ", \"block\": " << t.block
-        << ", \"waves_per_simd\": " << t.waves_per_simd << ", \"ms\": " << ms[p][o] << "}"
+        << ", \"waves_per_simd\": " << t.waves_per_simd
+        << ", \"samples_per_thread\": " << t.spt << ", \"ms\": " << ms[p][o] << "}"
         << (p == 1 && o == 2 ? "\n" : ",\n");
     }
   f << "]}\n";
@@ -109,11 +113,18 @@ float g_ms[2][3] = {};
 
 }  // namespace
 
-bool tune_valid(int precision, const TuneCfg& t) {
+bool tune_valid(int precision, const TuneCfg& t, int obstacle) {
   // FP32C blocks must divide its 64-step flush period; FP64 also takes 128
   const bool k_ok = t.k == 16 || t.k == 32 || t.k == 64 || (t.k == 128 && precision == AEB_FP64);
   const bool b_ok = t.block == 64 || t.block == 128 || t.block == 256;
-  return k_ok && b_ok && t.waves_per_simd >= 0 && t.waves_per_simd <= 32;
+  // two samples per thread: the FP64 kernel without a lead vehicle
+  const bool s_ok = t.spt == 1 || (t.spt == 2 && precision == AEB_FP64 && obstacle != AEB_OBS_LEAD);
+  return k_ok && b_ok && s_ok && t.waves_per_simd >= 0 && t.waves_per_simd <= 32;
+}
+
+std::vector<TuneResult> tune_results(int precision, int obstacle) {
+  std::lock_guard<std::mutex> g(g_mu);
+  return g_res[pidx(precision)][obstacle < 0 || obstacle > 2 ? 0 : obstacle];
 }
 
 TuneCfg tune_get(int precision, int obstacle) {
@@ -134,24 +145,41 @@ using namespace aeb;
 
 extern "C" {
 
-int aeb_tune_get(int precision, int obstacle, int32_t* k, int32_t* block,
-                 int32_t* waves_per_simd) {
-  if ((precision != AEB_FP64 && precision != AEB_FP32C) || obstacle < 0 || obstacle > 2 || !k ||
-      !block || !waves_per_simd)
+int aeb_tune_get(int precision, int obstacle, aeb_tune_shape* shape) {
+  if ((precision != AEB_FP64 && precision != AEB_FP32C) || obstacle < 0 || obstacle > 2 || !shape)
     return fail(AEB_EINVAL, "aeb_tune_get: bad argument");
   const TuneCfg t = tune_get(precision, obstacle);
-  *k = t.k;
-  *block = t.block;
-  *waves_per_simd = t.waves_per_simd;
+  shape->k = t.k;
+  shape->block = t.block;
+  shape->waves_per_simd = t.waves_per_simd;
+  shape->samples_per_thread = t.spt;
   return AEB_OK;
 }
 
-int aeb_tune_set(int precision, int obstacle, int32_t k, int32_t block, int32_t waves_per_simd) {
-  const TuneCfg t{k, block, waves_per_simd};
+int aeb_tune_set(int precision, int obstacle, const aeb_tune_shape* shape) {
+  if (!shape) return fail(AEB_EINVAL, "aeb_tune_set: null shape");
+  const TuneCfg t{shape->k, shape->block, shape->waves_per_simd, shape->samples_per_thread};
   if ((precision != AEB_FP64 && precision != AEB_FP32C) || obstacle < 0 || obstacle > 2 ||
-      !tune_valid(precision, t))
+      !tune_valid(precision, t, obstacle))
     return fail(AEB_EINVAL, "aeb_tune_set: unsupported shape");
   tune_set(precision, obstacle, t);
+  return AEB_OK;
+}
+
+int aeb_tune_results(int precision, int obstacle, aeb_tune_shape* shapes, float* ms, int max,
+                     int* count) {
+  if ((precision != AEB_FP64 && precision != AEB_FP32C) || obstacle < 0 || obstacle > 2 ||
+      !count || max < 0 || (max > 0 && (!shapes || !ms)))
+    return fail(AEB_EINVAL, "aeb_tune_results: bad argument");
+  const std::vector<TuneResult> r = tune_results(precision, obstacle);
+  *count = static_cast<int>(r.size());
+  for (int j = 0; j < max && j < static_cast<int>(r.size()); ++j) {
+    shapes[j].k = r[j].t.k;
+    shapes[j].block = r[j].t.block;
+    shapes[j].waves_per_simd = r[j].t.waves_per_simd;
+    shapes[j].samples_per_thread = r[j].t.spt;
+    ms[j] = r[j].ms;
+  }
   return AEB_OK;
 }
 
@@ -188,12 +216,14 @@ int aeb_autotune(const aeb_scenario* calib, int precision, const char* cache_pat
   (void)hipEventCreate(&e1);
   const TuneCfg keep = tune_get(precision, calib->obstacle);
   std::vector<TuneCfg> cands;
-  for (int k : {16, 32, 64, 128})
-    for (int b : {64, 128, 256})
-      for (int w : {0, 4, 8}) {
-        const TuneCfg t{k, b, w};
-        if (tune_valid(precision, t)) cands.push_back(t);
-      }
+  for (int sp : {1, 2})
+    for (int k : {16, 32, 64, 128})
+      for (int b : {64, 128, 256})
+        for (int w : {0, 4, 8}) {
+          const TuneCfg t{k, b, w, sp};
+          if (tune_valid(precision, t, calib->obstacle)) cands.push_back(t);
+        }
+  std::vector<TuneResult> res;
   TuneCfg best = keep;
   float best_t = 1e30f;
   rc = AEB_OK;
@@ -217,6 +247,7 @@ int aeb_autotune(const aeb_scenario* calib, int precision, const char* cache_pat
     if (rc != AEB_OK) break;
     std::sort(ms.begin(), ms.end());
     const float med = ms[ms.size() / 2];
+    res.push_back(TuneResult{t, med});
     if (med < best_t) {
       best_t = med;
       best = t;
@@ -228,6 +259,12 @@ int aeb_autotune(const aeb_scenario* calib, int precision, const char* cache_pat
   (void)hipFree(mem);
   if (rc != AEB_OK) return rc;
   g_ms[pidx(precision)][calib->obstacle] = best_t;
+  std::stable_sort(res.begin(), res.end(),
+                   [](const TuneResult& a, const TuneResult& b) { return a.ms < b.ms; });
+  {
+    std::lock_guard<std::mutex> g(g_mu);
+    g_res[pidx(precision)][calib->obstacle] = res;
+  }
   if (best_ms) *best_ms = best_t;
   if (cache_path) return save_file(cache_path, g_ms);
   return AEB_OK;

@@ -156,7 +156,7 @@ def test_host_sampler_rejects_invalid(B):
 def test_tune_table_validation(B, tmp_path):
     keep = B.tune_get("fp64", "stationary")
     B.tune_set("fp64", "stationary", 64, 128, 4)
-    assert B.tune_get("fp64", "stationary") == (64, 128, 4)
+    assert B.tune_get("fp64", "stationary") == (64, 128, 4, 1)
     for bad in ((48, 256, 0), (32, 512, 0), (32, 256, -1), (32, 256, 33)):
         with pytest.raises(B.AebError):
             B.tune_set("fp64", "stationary", *bad)
@@ -164,7 +164,14 @@ def test_tune_table_validation(B, tmp_path):
         B.tune_set("fp32c", "none", 128, 256, 0)     # blocks must divide the FP32 flush period
     keep_none = B.tune_get("fp64", "none")
     B.tune_set("fp64", "none", 128, 64, 0)           # FP64 also takes 128-step blocks
-    assert B.tune_get("fp64", "none") == (128, 64, 0)
+    assert B.tune_get("fp64", "none") == (128, 64, 0, 1)
+    B.tune_set("fp64", "none", 64, 256, 4, 2)        # two samples per thread: FP64, no lead
+    assert B.tune_get("fp64", "none") == (64, 256, 4, 2)
+    for p, o in (("fp32c", "stationary"), ("fp64", "lead")):
+        with pytest.raises(B.AebError):
+            B.tune_set(p, o, 64, 256, 0, 2)
+    with pytest.raises(B.AebError):
+        B.tune_set("fp64", "stationary", 64, 256, 0, 3)
     B.tune_set("fp64", "none", *keep_none)
     B.tune_set("fp64", "stationary", *keep)
 
@@ -177,8 +184,19 @@ def test_tune_cache_load(B, tmp_path):
                     '  {"precision": 1, "obstacle": 0, "k": 16, "block": 128, "waves_per_simd": 0, "ms": 2.0}\n'
                     ']}\n')
     B.tune_load(str(good))
-    assert B.tune_get("fp64", "stationary") == (16, 64, 8)
-    assert B.tune_get("fp32c", "none") == (16, 128, 0)
+    assert B.tune_get("fp64", "stationary") == (16, 64, 8, 1)
+    assert B.tune_get("fp32c", "none") == (16, 128, 0, 1)
+    v2 = tmp_path / "tune2.json"
+    v2.write_text('{"format": 2, "entries": [\n'
+                  '  {"precision": 0, "obstacle": 1, "k": 128, "block": 256, "waves_per_simd": 4, '
+                  '"samples_per_thread": 2, "ms": 1.0}\n]}\n')
+    B.tune_load(str(v2))
+    assert B.tune_get("fp64", "stationary") == (128, 256, 4, 2)
+    bad2 = tmp_path / "bad2.json"
+    bad2.write_text('{"entries": [{"precision": 0, "obstacle": 2, "k": 64, "block": 64, '
+                    '"waves_per_simd": 0, "samples_per_thread": 2}]}')
+    with pytest.raises(B.AebError):                  # a lead vehicle takes one sample per lane
+        B.tune_load(str(bad2))
     bad = tmp_path / "bad.json"
     bad.write_text('{"entries": [{"precision": 0, "obstacle": 0, "k": 16, "block": 64, '
                    '"waves_per_simd": 0}, {"precision": 1, "obstacle": 0, "k": 48, "block": 64, '

@@ -12,6 +12,9 @@ pytestmark = pytest.mark.gpu
 
 SHAPES = [(16, 64, 0), (16, 256, 8), (32, 128, 4), (32, 256, 0), (64, 64, 4), (64, 256, 8),
           (128, 256, 4), (128, 64, 0)]
+# two samples per lane (FP64, no lead vehicle): one pass and persistent grids
+SHAPES2 = [(16, 256, 0, 2), (32, 64, 3, 2), (64, 128, 0, 2), (64, 256, 2, 2), (128, 256, 3, 2),
+           (128, 64, 8, 2)]
 
 
 @pytest.fixture(scope="module")
@@ -62,29 +65,56 @@ def test_results_do_not_depend_on_shape(B, shape_cases, prec, obs, integ):
             check_fp64(ref, ref_o, exact=True)
         else:
             check_fp32c(ref, ref_o, margin_abs=2e-3 if obs == "lead" else None)
-        for k, blk, w in SHAPES:
+        shapes = [t + (1,) for t in SHAPES]
+        if prec == "fp64" and obs != "lead" and integ == "euler":
+            shapes += SHAPES2
+        for k, blk, w, spt in shapes:
             if k == 128 and prec != "fp64":
                 continue                      # FP32C blocks divide its 64-step flush period
-            B.tune_set(prec, obs, k, blk, w)
+            B.tune_set(prec, obs, k, blk, w, spt)
             got = to_np(B.rollout(d, params=params, precision=prec))
             for c in ref:
-                assert np.array_equal(ref[c], got[c]), (k, blk, w, c)
+                assert np.array_equal(ref[c], got[c]), (k, blk, w, spt, c)
     finally:
         B.tune_set(prec, obs, *keep)
 
 
-def test_batch_does_not_depend_on_shape(B):
-    scns = W.uneven_batch(8, max_samples=2000)
+@pytest.mark.parametrize("shape", [(16, 64, 8, 1), (64, 256, 0, 2), (128, 128, 3, 2)])
+def test_batch_does_not_depend_on_shape(B, shape):
+    scns = W.uneven_batch(8, max_samples=2000) + [W.perception(3000, seed=9)]
     keep = B.tune_get("fp64", "stationary")
     try:
         ref = [to_np(o) for o in B.batch_rollout(scns)]
-        B.tune_set("fp64", "stationary", 16, 64, 8)
+        B.tune_set("fp64", "stationary", *shape)
         got = [to_np(o) for o in B.batch_rollout(scns)]
     finally:
         B.tune_set("fp64", "stationary", *keep)
     for a, b in zip(ref, got):
         for c in a:
             assert np.array_equal(a[c], b[c]), c
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 127, 128, 129, 4097])
+@pytest.mark.parametrize("variant", ["stationary", "impact_exit", "none", "perception"])
+def test_two_samples_per_lane_ragged(B, orc, n, variant):
+    """Two samples per lane on ragged sizes (a chunk of 128 sorted positions
+    split over the two halves of a wavefront) against the reference."""
+    if variant == "perception":
+        d = W.perception(n, seed=n)
+    elif variant == "impact_exit":
+        d = W.single(n, seed=n, impact_exit=True)
+    elif variant == "none":
+        d = W.single(n, seed=n, obstacle="none")
+    else:
+        d = W.single(n, seed=n)
+    obs = d["obstacle"]
+    keep = B.tune_get("fp64", obs)
+    try:
+        B.tune_set("fp64", obs, 128, 256, 0, 2)
+        got = to_np(B.rollout(d, params=upload(B.sample_params(d, device=False))))
+    finally:
+        B.tune_set("fp64", obs, *keep)
+    check_fp64(got, orc.run(d), exact=True)
 
 
 def test_autotune_writes_a_loadable_cache(B, tmp_path):
@@ -96,7 +126,10 @@ def test_autotune_writes_a_loadable_cache(B, tmp_path):
         chosen = B.tune_get("fp64", "stationary")
         entries = json.loads(path.read_text())["entries"]
         e = [x for x in entries if x["precision"] == 0 and x["obstacle"] == 1][0]
-        assert (e["k"], e["block"], e["waves_per_simd"]) == chosen
+        assert (e["k"], e["block"], e["waves_per_simd"], e["samples_per_thread"]) == chosen
+        res = B.tune_results("fp64", "stationary")
+        assert res[0][0] == chosen and res[0][1] <= res[1][1]
+        assert any(t[3] == 2 for t, _ in res) and any(t[3] == 1 for t, _ in res)
         B.tune_set("fp64", "stationary", *keep)
         B.tune_load(str(path))
         assert B.tune_get("fp64", "stationary") == chosen
