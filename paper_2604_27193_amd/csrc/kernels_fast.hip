@@ -50,8 +50,19 @@ constexpr int NBINS = 8192;  // sort keys: 64 coarse x 2 classes x 64 fine
 // each CU has room for one such workgroup, so the next launch's preparation
 // overlaps the current integration when launches are pipelined on two streams.
 constexpr int PREP_BLOCK = 256;
-constexpr int PREP_SAMPLES = 4096;                     // samples per prep/scatter block
-constexpr int PREP_PER = PREP_SAMPLES / PREP_BLOCK;    // samples per thread
+constexpr int PREP_SAMPLES = 4096;                     // samples per scatter block
+constexpr int PREP_PER = PREP_SAMPLES / PREP_BLOCK;    // samples per scatter thread
+// Samples per thread of the prep kernel: enough workgroups (about 512) to
+// spread the per-sample draws over the chip for small launches, at most 16
+// (a 4,096-sample block) for large ones.
+inline int prep_per(int64_t n) {
+  const int64_t p = (n + PREP_BLOCK * 512 - 1) / (PREP_BLOCK * 512);
+  return static_cast<int>(p < 1 ? 1 : (p > PREP_PER ? PREP_PER : p));
+}
+inline unsigned prep_grid(int64_t n) {
+  const int64_t per = static_cast<int64_t>(PREP_BLOCK) * prep_per(n);
+  return static_cast<unsigned>((n + per - 1) / per);
+}
 template <bool DEVRNG>
 constexpr int prep_threads() { return PREP_BLOCK; }
 
@@ -94,6 +105,7 @@ struct PrepArgs {
   int ctl;                   // closed-loop controller (single scenario)
   double* weight;            // single scenario: importance-sampling weights out (or null)
   const BatchHdr* hdr;       // batch on device tables: n, cap and n_scn from here (else null)
+  int per;                   // samples per thread (prep_per of the launch size)
 };
 
 template <bool DEVRNG, bool BATCH>
@@ -108,8 +120,8 @@ __global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job
   __shared__ uint32_t hist[NBINS];
   for (int j = threadIdx.x; j < NBINS; j += NT) hist[j] = 0;
   __syncthreads();
-  for (int r = 0; r < PREP_SAMPLES / NT; ++r) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * PREP_SAMPLES + r * NT + threadIdx.x;
+  for (int r = 0; r < a.per; ++r) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * (NT * a.per) + r * NT + threadIdx.x;
     if (i >= n_all) break;
     // the sample's scenario and its index within it
     uint32_t j = 0;
@@ -696,7 +708,10 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
             if (L.active && L.stage < 2) {
               const double gt = LEAD ? (J.gap + L.l.xl) - L.s.x : (J.gap + 0.0) - L.s.x;
               const double cl = LEAD ? L.s.v - L.l.vl : L.s.v - 0.0;
-              const int want = ctl_want(ctx.ca, g, tick, gt, cl);
+              // the noise is drawn (a Philox call, log, sqrt, sincos) only
+              // where it can change the decision
+              int want = ctl_screen(ctx.ca, L.stage, gt, cl);
+              if (want < 0) want = ctl_want(ctx.ca, g, tick, gt, cl);
               if (want > L.stage) {
                 if (want == 2)
                   L.on2 = k + c.nd;
@@ -2057,12 +2072,13 @@ int launch_rollout_fast_into(const aeb_scenario& s, const ParamSrc* src, int pre
   const bool lead = s.obstacle == AEB_OBS_LEAD;
   Bufs b;
   bufs_layout(n, 0, lead, static_cast<char*>(scratch_base), &b);
-  const unsigned pblk = static_cast<unsigned>((n + PREP_SAMPLES - 1) / PREP_SAMPLES);
+  const unsigned pblk = prep_grid(n);
   hipLaunchKernelGGL(k_zero, dim3(NBINS / 256), dim3(256), 0, st, b.hist, int64_t(NBINS));
   PrepArgs pa{};
   pa.s = s;
   pa.src = src ? *src : ParamSrc{};
   pa.n = n;
+  pa.per = prep_per(n);
   pa.nd = static_cast<int>(nd);
   pa.nmax = static_cast<int>(nmax);
   pa.cap = static_cast<float>(nmax);
@@ -2130,10 +2146,11 @@ int launch_batch_fast_into(const aeb_scenario* scns, int n_scn, int precision,
   bufs_layout(total, n_scn, lead, static_cast<char*>(scratch_base), &b);
   AEB_HIP(hipMemcpyAsync(b.tab, tab, sizeof(ScnDev) * n_scn, hipMemcpyHostToDevice, st));
   AEB_HIP(hipMemcpyAsync(b.scns, scns, sizeof(aeb_scenario) * n_scn, hipMemcpyHostToDevice, st));
-  const unsigned pblk = static_cast<unsigned>((total + PREP_SAMPLES - 1) / PREP_SAMPLES);
+  const unsigned pblk = prep_grid(total);
   hipLaunchKernelGGL(k_zero, dim3(NBINS / 256), dim3(256), 0, st, b.hist, int64_t(NBINS));
   PrepArgs pa{};
   pa.n = total;
+  pa.per = prep_per(total);
   pa.cap = static_cast<float>(cap);
   pa.scns = b.scns;
   pa.tab = b.tab;
@@ -2157,10 +2174,11 @@ int launch_batch_fast_dev(const aeb_scenario& kind, bool perception, int precisi
   const bool lead = kind.obstacle == AEB_OBS_LEAD;
   Bufs b;
   bufs_layout(cap_total, 0, lead, static_cast<char*>(scratch_base), &b);
-  const unsigned pblk = static_cast<unsigned>((cap_total + PREP_SAMPLES - 1) / PREP_SAMPLES);
+  const unsigned pblk = prep_grid(cap_total);
   hipLaunchKernelGGL(k_zero, dim3(NBINS / 256), dim3(256), 0, st, b.hist, int64_t(NBINS));
   PrepArgs pa{};
   pa.n = cap_total;
+  pa.per = prep_per(cap_total);
   pa.cap = 1.0f;
   pa.scns = scns;
   pa.tab = tab;

@@ -90,6 +90,32 @@ __device__ inline int ctl_want(const CtlArgs& A, uint64_t index, uint32_t tick, 
   return ttc < A.ttc_brake ? 2 : (ttc < A.ttc_warn ? 1 : 0);
 }
 
+// The decision's outcome when the measurement noise cannot change it, else
+// -1.  The Box-Muller radius is below 8.572 (the smallest uniform is 2^-53),
+// so the measured gap and closing speed lie within R = 8.6 noise sds of the
+// true ones; a lane whose measured TTC is above the next threshold for every
+// noise in that box (or below the full-brake threshold for every noise)
+// decides without drawing it.  Margins of 1e-9 cover the rounding of the
+// exact evaluation, so the outcome equals ctl_want's.
+__device__ inline int ctl_screen(const CtlArgs& A, int stage, double gap_true, double closing) {
+  constexpr double R = 8.6;
+  const double eg = A.noise_gap * R, ev = A.noise_v * R;
+  const double g_lo = gap_true - eg, g_hi = gap_true + eg;
+  const double c_lo = closing - ev, c_hi = closing + ev;
+  // every measured TTC at or above t (an infinite TTC included)
+  auto above = [&](double t) {
+    if (c_hi <= 0.0) return true;
+    const double b = t * c_hi;
+    return g_lo > 0.0 && g_lo >= b + 1e-9 * (fabs(b) + 1.0);
+  };
+  const double t_next = stage == 0 ? fmax(A.ttc_warn, A.ttc_brake) : A.ttc_brake;
+  if (above(t_next)) return stage;  // nothing changes: want <= stage
+  // every measured TTC below the full-brake threshold
+  const double b = A.ttc_brake * c_lo;
+  if (c_lo > 0.0 && g_hi <= b - 1e-9 * (fabs(b) + 1.0)) return 2;
+  return -1;
+}
+
 __device__ inline void ctl_decide(const CtlArgs& A, Ctl& c, uint64_t index, int64_t step,
                                   int64_t nd, double gap_true, double closing) {
   const int want = ctl_want(A, index, c.tick, gap_true, closing);
