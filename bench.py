@@ -719,6 +719,9 @@ def main():
                          "every integration-kernel launch is then one of the timed steps)")
     ap.add_argument("--fp32c-only", action="store_true",
                     help="only the eager FP32C step loop (for counter runs of that kernel)")
+    ap.add_argument("--control-only", choices=("closed", "open"), default=None,
+                    help="only the eager FP64 loop of the closed-loop controller scenario, "
+                         "or of the same scenario open loop (for counter runs of that kernel)")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of each Poisson serving stream (0: no serving leg)")
     ap.add_argument("--saturate-seconds", type=float, default=10.0,
@@ -746,6 +749,16 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.control_only:
+        d = W.closed_loop(args.n)
+        if args.control_only == "open":
+            d = {k: v for k, v in d.items() if k not in B.CONTROL_FIELDS}
+        outc = B.alloc_outputs(args.n)
+        wall, kc, cc, stc = time_steps(B, torch, d, None, "fp64", outc, args.steps, args.warmup)
+        steps_c = int(outc["steps"].to(torch.int64).sum().item())
+        print(json.dumps({"control": args.control_only, "kernel_ms": float(np.mean(kc)),
+                          "steps_per_launch": steps_c, "steps": args.steps}), flush=True)
+        return
     d = W.single(args.n)
     n = int(d["n_samples"])
 

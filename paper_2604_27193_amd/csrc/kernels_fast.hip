@@ -210,7 +210,21 @@ __global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job
     // other (each distinct switch step cuts the wavefront's blocks)
     const uint32_t fine =
         a.nds ? (((ud >> 3) & 7u) << 3) | ((static_cast<uint32_t>(ndl) >> 4) & 7u) : ud & 63u;
-    const uint32_t key = ((ud >> 6) << 7) | (limited ? 0u : 64u) | fine;
+    uint32_t key = ((ud >> 6) << 7) | (limited ? 0u : 64u) | fine;
+    if (a.ctl) {
+      // with the controller, lanes are grouped first by when they reach the
+      // TTC thresholds (the approach time, 256 bins over the horizon, latest
+      // first), where the measurement noise can decide and every lane of
+      // the wavefront pays for a draw; then the limited class; then the
+      // braking time after the approach (16 bins, longest first), so the
+      // lanes also end close together
+      const float per = (capf + 1.0f) * (1.0f / 256.0f);
+      const float tds = td / static_cast<float>(s.dt);
+      const float ua = fminf(fmaxf(tds, 0.0f) / per, 255.0f);
+      const float ub = fminf(fmaxf(steps - tds, 0.0f) / (2.0f * per), 15.0f);
+      key = ((255u - static_cast<uint32_t>(ua)) << 5) | (limited ? 0u : 16u) |
+            (15u - static_cast<uint32_t>(ub));
+    }
     keys[i] = key;
     atomicAdd(&hist[key], 1u);
   }
