@@ -137,20 +137,23 @@ struct RSegs {
 
 __device__ inline int seg_count(const RSegs& S) { return S.tab ? *S.count : 1; }
 
-__device__ inline const RSeg& seg_at(const RSegs& S, int j) { return S.tab ? S.tab[j] : S.one; }
+// The set by value: a pointer or reference that may point at the kernel
+// argument `one` makes the compiler copy the argument to per-lane scratch.
+__device__ inline RSeg seg_at(const RSegs& S, int j) { return S.tab ? S.tab[j] : S.one; }
 
-// The set of element-pass block `gb` and the block's index inside it (null
-// for a block beyond the launch's sets).
-__device__ inline const RSeg* seg_of_block(const RSegs& S, int gb, int& local) {
+// The set of element-pass block `gb` and the block's index inside it; false
+// for a block beyond the launch's sets.
+__device__ inline bool seg_of_block(const RSegs& S, int gb, int& local, RSeg& g) {
   if (!S.tab) {
     local = gb;
-    return gb < S.one.nb ? &S.one : nullptr;
+    g = S.one;
+    return gb < S.one.nb;
   }
   const int j = S.bmap[gb];
-  if (j < 0) return nullptr;
-  const RSeg* g = &S.tab[j];
-  local = gb - g->blk0;
-  return g;
+  if (j < 0) return false;
+  g = S.tab[j];
+  local = gb - g.blk0;
+  return true;
 }
 
 // What a reduction computes: risk levels and margin quantile levels, and the
@@ -375,9 +378,8 @@ __device__ inline Partial block_combine(const Partial* wp) {
 
 __global__ __launch_bounds__(EB) void k_pass1(RSegs S) {
   int bx;
-  const RSeg* gp = seg_of_block(S, blockIdx.x, bx);
-  if (!gp) return;  // beyond the launch's sets (the whole block)
-  const RSeg& g = *gp;
+  RSeg g;
+  if (!seg_of_block(S, blockIdx.x, bx, g)) return;  // beyond the launch's sets (the whole block)
   const OutCols o = g.out;
   const long long n = g.n;
   const long long chunk = static_cast<long long>(EB) * CP;
@@ -474,7 +476,7 @@ __global__ __launch_bounds__(EB) void k_pass1(RSegs S) {
 // t, t+FB, ... in order, then a fixed tree).
 __global__ __launch_bounds__(FB) void k_fin1(RSegs S) {
   if (static_cast<int>(blockIdx.x) >= seg_count(S)) return;
-  const RSeg& g = seg_at(S, blockIdx.x);
+  const RSeg g = seg_at(S, blockIdx.x);
   const int weighted = g.out.weight ? 1 : 0;
   const long long n = g.n;
   const RLayout RL = layout(n, 0);
@@ -533,9 +535,8 @@ __global__ __launch_bounds__(FB) void k_fin1(RSegs S) {
 __global__ __launch_bounds__(EB) void k_pass2(RSegs S, int need_d, int need_m, RReq rq,
                                               int hw) {
   int bx;
-  const RSeg* gp = seg_of_block(S, blockIdx.x, bx);
-  if (!gp) return;  // beyond the launch's sets (the whole block)
-  const RSeg& g = *gp;
+  RSeg g;
+  if (!seg_of_block(S, blockIdx.x, bx, g)) return;  // beyond the launch's sets (the whole block)
   const OutCols o = g.out;
   const long long n = g.n;
   const long long chunk = static_cast<long long>(EB) * CP;
@@ -629,9 +630,8 @@ __device__ inline double from_fixed(unsigned long long hi, unsigned long long lo
 // zeroed global accumulators.
 __global__ __launch_bounds__(EB) void k_wpass(RSegs S, RReq rq) {
   int bx;
-  const RSeg* gp = seg_of_block(S, blockIdx.x, bx);
-  if (!gp) return;  // beyond the launch's sets (the whole block)
-  const RSeg& g = *gp;
+  RSeg g;
+  if (!seg_of_block(S, blockIdx.x, bx, g)) return;  // beyond the launch's sets (the whole block)
   const OutCols o = g.out;
   const long long n = g.n;
   const long long chunk = static_cast<long long>(EB) * CP;
@@ -679,7 +679,7 @@ __global__ __launch_bounds__(EB) void k_wpass(RSegs S, RReq rq) {
 // order): suffix sums over the rank bins from the top give sum w [D > H0_j].
 __global__ void k_wfin(RSegs S, int ng) {
   if (static_cast<int>(blockIdx.x) >= seg_count(S)) return;
-  const RSeg& g = seg_at(S, blockIdx.x);
+  const RSeg g = seg_at(S, blockIdx.x);
   if (!g.out.weight) return;
   const long long n = g.n;
   const RLayout RL = layout(n, 0);
@@ -745,7 +745,7 @@ __global__ __launch_bounds__(256) void k_bin_totals(RSegs S, int hw) {
 __global__ __launch_bounds__(FB) void k_fin2(RSegs S, RReq rq, int hw) {
   const int T1 = 1 + rq.n_risk + rq.n_mq;
   if (static_cast<int>(blockIdx.x / T1) >= seg_count(S)) return;
-  const RSeg& g = seg_at(S, blockIdx.x / T1);
+  const RSeg g = seg_at(S, blockIdx.x / T1);
   const int bx = blockIdx.x % T1;
   const long long n = g.n;
   const int ng = rq.ng;
@@ -847,9 +847,8 @@ __global__ __launch_bounds__(FB) void k_fin2(RSegs S, RReq rq, int hw) {
 // search computed for it, ranked inside the block by LDS counters.
 __global__ __launch_bounds__(EB) void k_collect(RSegs S, RReq rq) {
   int bx;
-  const RSeg* gp = seg_of_block(S, blockIdx.x, bx);
-  if (!gp) return;  // beyond the launch's sets (the whole block)
-  const RSeg& g = *gp;
+  RSeg g;
+  if (!seg_of_block(S, blockIdx.x, bx, g)) return;  // beyond the launch's sets (the whole block)
   const OutCols o = g.out;
   const long long n = g.n;
   const long long chunk = static_cast<long long>(EB) * CP;
@@ -922,7 +921,7 @@ __global__ __launch_bounds__(EB) void k_collect(RSegs S, RReq rq) {
 __global__ __launch_bounds__(RB) void k_pick(RSegs S, RReq rq) {
   const int T = rq.n_risk + rq.n_mq;
   if (static_cast<int>(blockIdx.x / T) >= seg_count(S)) return;
-  const RSeg& g = seg_at(S, blockIdx.x / T);
+  const RSeg g = seg_at(S, blockIdx.x / T);
   const int t = blockIdx.x % T;
   const RLayout RL = layout(g.n, T);
   const Sel* sel = reinterpret_cast<const Sel*>(g.base + RL.off_sel);
@@ -1083,7 +1082,7 @@ namespace {
 // its statistics (fill kernels: no memset nodes in recorded graphs)
 __global__ void k_zero_sets(RSegs S) {
   if (static_cast<int>(blockIdx.y) >= seg_count(S)) return;
-  const RSeg& g = seg_at(S, blockIdx.y);
+  const RSeg g = seg_at(S, blockIdx.y);
   const RLayout RL = layout(g.n, 0);
   unsigned* a = reinterpret_cast<unsigned*>(g.base + RL.off_sel);
   const long long na = static_cast<long long>((RL.off_zero_end - RL.off_sel) / 4);
