@@ -370,6 +370,21 @@ int aeb_batch_reduce(const aeb_outputs* outs, int n_scn, const aeb_reduce_req* r
 int aeb_timing_enable(int on);
 int aeb_timing_last(float* ms);
 
+/* Self-check of the closed-loop controller's decision screen (Sec. VIII's
+ * controller: measured TTC from noisy gap and closing speed).  Where the
+ * noise can change a decision, the rollout kernels first estimate it with
+ * the GPU's single-precision log2, sqrt, sin and cos instructions inside an
+ * error box and take the exact double-precision evaluation only where the
+ * box straddles a threshold, so decisions equal the exact ones provided the
+ * instructions stay within the box's bounds.  This call measures their
+ * largest errors on the device over every input that can reach them (about
+ * 2.5e9 evaluations, a few milliseconds) and writes measured[0..3] (log2
+ * relative to max(1, |log2 a|), sqrt relative, sin and cos of 2 pi b
+ * absolute) and the bounds the screen assumes, bounds[0..3].  Every
+ * measured value must not exceed its bound.  Allocates 32 bytes of device
+ * memory; synchronises `stream`. */
+int aeb_ctl_approx_check(double* measured, double* bounds, void* stream);
+
 /* Metric of the exact order statistics (Sec. VI-C headways, margin
  * quantiles): the number of reductions (aeb_reduce, aeb_batch_reduce per set,
  * graphs, serving) since the library was loaded whose selection fell back

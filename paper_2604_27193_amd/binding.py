@@ -14,7 +14,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libaeb.so")
-ABI_VERSION = 6     # the aeb_version() these structures match
+ABI_VERSION = 7     # the aeb_version() these structures match
 NOALLOC_SCRATCH_BYTES = 32 << 20  # AEB_NOALLOC_SCRATCH_BYTES of aeb.h
 SERVE_EAGER = 1                   # AEB_SERVE_EAGER of aeb.h
 
@@ -37,7 +37,8 @@ END_STOP, END_IMPACT, END_HORIZON, COLLIDED, BOUNDARY = 1, 2, 3, 4, 8
 EXPORTS = ("aeb_last_error", "aeb_version", "aeb_validate", "aeb_uniforms", "aeb_sample_params",
            "aeb_rollout", "aeb_rollout_noalloc", "aeb_reduce", "aeb_batch_rollout",
            "aeb_batch_reduce",
-           "aeb_timing_enable", "aeb_timing_last", "aeb_reduce_fallbacks", "aeb_server_fixed_bytes",
+           "aeb_timing_enable", "aeb_timing_last", "aeb_reduce_fallbacks", "aeb_ctl_approx_check",
+           "aeb_server_fixed_bytes",
            "aeb_serve_footprint", "aeb_server_create", "aeb_server_destroy", "aeb_serve_submit",
            "aeb_serve_poll", "aeb_server_info_get", "aeb_graph_create", "aeb_graph_create_batch",
            "aeb_graph_launch", "aeb_graph_finish", "aeb_graph_destroy", "aeb_graph_create_mix",
@@ -151,6 +152,7 @@ def lib():
         L.aeb_timing_enable.argtypes = [C.c_int]
         L.aeb_timing_last.argtypes = [P(C.c_float)]
         L.aeb_reduce_fallbacks.argtypes = [P(C.c_uint64)]
+        L.aeb_ctl_approx_check.argtypes = [P(C.c_double), P(C.c_double), C.c_void_p]
         L.aeb_server_fixed_bytes.argtypes = [P(ServerCfg), P(C.c_uint64)]
         L.aeb_serve_footprint.argtypes = [P(ServerCfg), C.c_int64, P(C.c_uint64)]
         L.aeb_server_create.argtypes = [P(ServerCfg), P(C.c_void_p)]
@@ -390,6 +392,16 @@ def reduce_fallbacks():
     c = C.c_uint64()
     _check(lib().aeb_reduce_fallbacks(C.byref(c)))
     return c.value
+
+
+def ctl_approx_check(stream=None):
+    """Largest errors of the controller screen's single-precision log2, sqrt,
+    sin and cos over all their inputs, measured on the device, and the bounds
+    the screen assumes: two 4-tuples (measured, bounds)."""
+    m = (C.c_double * 4)()
+    b = (C.c_double * 4)()
+    _check(lib().aeb_ctl_approx_check(m, b, _stream(stream)))
+    return tuple(m), tuple(b)
 
 
 def timing_enable(on=True):

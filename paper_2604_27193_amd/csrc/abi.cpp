@@ -378,7 +378,7 @@ extern "C" {
 
 const char* aeb_last_error(void) { return g_err.c_str(); }
 
-int aeb_version(void) { return 6; }
+int aeb_version(void) { return 7; }
 
 int aeb_timing_enable(int on) {
   g_timing.on = on != 0;
@@ -390,6 +390,11 @@ int aeb_reduce_fallbacks(uint64_t* count) {
   if (!count) return fail(AEB_EINVAL, "aeb_reduce_fallbacks: null argument");
   *count = reduce_fallback_count();
   return AEB_OK;
+}
+
+int aeb_ctl_approx_check(double* measured, double* bounds, void* stream) {
+  if (!measured || !bounds) return fail(AEB_EINVAL, "aeb_ctl_approx_check: null argument");
+  return launch_approx_check(measured, bounds, static_cast<hipStream_t>(stream));
 }
 
 int aeb_timing_last(float* ms) {

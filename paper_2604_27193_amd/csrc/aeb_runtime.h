@@ -85,6 +85,11 @@ struct OutCols {
 };
 
 // launchers (kernels_*.hip); all asynchronous on `stream`
+// Largest errors of the controller screen's single-precision approximations
+// over their whole input ranges (measured[4]) and the bounds the screen
+// assumes for them (bounds[4]): log2, sqrt, sin, cos.  Synchronises `st`.
+int launch_approx_check(double* measured, double* bounds, hipStream_t st);
+
 int launch_uniforms(uint64_t seed, uint64_t sid, int64_t first, int64_t count, uint32_t slot,
                     uint32_t attempt, double* out, hipStream_t stream);
 int launch_sample(const aeb_scenario& s, int64_t first, int64_t count, const aeb_params& out,

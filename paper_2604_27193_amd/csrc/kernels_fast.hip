@@ -91,6 +91,54 @@ __device__ inline float predict_stop_time(float v0, float kd, float c, float ali
   return td + (v1 + amag * tau) / den;
 }
 
+// Predicted stop time under the closed-loop controller with a stationary
+// obstacle, for the sort only (noise left out): constant speed until the
+// first decision with TTC below ttc_warn, then the partial command (after
+// the dead time and, roughly, the actuator lag) until the first decision with
+// TTC below ttc_brake, then the full command as in predict_stop_time.
+// Decisions fall on the controller's tick grid (period per); *t_full gets
+// the predicted time of the full-braking decision.
+__device__ inline float predict_ctl_stop_time(float v0, float gap, float tw, float tb, float aw,
+                                              float per, float dead, float kd, float c,
+                                              float alim, float tau, float acmd,
+                                              float* t_full) {
+  *t_full = 0.0f;
+  if (!(v0 > 0.0f)) return dead;
+  auto tick = [&](float t) { return ceilf(fmaxf(t, 0.0f) / per) * per; };
+  float t_b, v_b;
+  if (!(tw > tb)) {
+    // no partial stage: full braking from the first decision below ttc_brake
+    t_b = tick(gap / v0 - tb);
+    v_b = v0;
+  } else {
+    const float t_w = tick(gap / v0 - tw);
+    const float delay = dead + tau;
+    const float g0 = gap - v0 * (t_w + delay);  // gap when the partial braking bites
+    if (g0 <= tb * v0) {
+      t_b = tick(gap / v0 - tb);
+      v_b = v0;
+    } else {
+      // gap g0 - v0 s + aw s^2 / 2 reaches tb (v0 - aw s): smallest root
+      float sroot;
+      if (aw < 1e-6f) {
+        sroot = (g0 - tb * v0) / v0;
+      } else {
+        const float bq = v0 - tb * aw;
+        const float disc = bq * bq - 2.0f * aw * (g0 - tb * v0);
+        // the partial braking alone stops the vehicle first
+        *t_full = t_w + delay + v0 / aw;
+        if (!(disc >= 0.0f) || bq <= 0.0f) return *t_full;
+        sroot = (bq - sqrtf(disc)) / aw;
+        if (sroot * aw >= v0) return *t_full;
+      }
+      t_b = tick(t_w + delay + sroot);
+      v_b = fmaxf(v0 - aw * (t_b - t_w - delay), 0.0f);
+    }
+  }
+  *t_full = t_b;
+  return t_b + predict_stop_time(v_b, kd, c, alim, tau, acmd, dead);
+}
+
 // Inputs of the prep stage: one scenario (uniform) or a batch table.
 struct PrepArgs {
   aeb_scenario s;          // single scenario
@@ -181,20 +229,27 @@ __global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job
     // classify and predict
     const bool limited = !(k.alim < s.a_cmd - 1e-6);
     float td = static_cast<float>(ndl) * static_cast<float>(s.dt);
-    if (a.ctl) {
-      // approach until the full-brake threshold, for the sort only: a
-      // stationary obstacle reached at v0; a lead braking at `lead` from the
-      // ego's speed (closing speed lead t, gap closed by lead t^2 / 2)
+    if (a.ctl && s.obstacle == AEB_OBS_LEAD) {
+      // approach until the full-brake threshold, for the sort only: a lead
+      // braking at `lead` from the ego's speed (closing speed lead t, gap
+      // closed by lead t^2 / 2)
       const float T = static_cast<float>(s.ttc_brake), G = static_cast<float>(gap);
-      const float V = static_cast<float>(v0), A = static_cast<float>(lead);
-      if (s.obstacle == AEB_OBS_LEAD)
-        td += A > 0.0f ? sqrtf(T * T + 2.0f * G / A) - T : static_cast<float>(s.horizon);
-      else
-        td += V > 0.0f ? fmaxf(G / V - T, 0.0f) : 0.0f;
+      const float A = static_cast<float>(lead);
+      td += A > 0.0f ? sqrtf(T * T + 2.0f * G / A) - T : static_cast<float>(s.horizon);
     }
-    const float t = predict_stop_time(static_cast<float>(v0), static_cast<float>(k.kd),
-                                      static_cast<float>(k.c), static_cast<float>(k.alim),
-                                      static_cast<float>(tau), static_cast<float>(s.a_cmd), td);
+    float t, t_full = -1.0f;
+    if (a.ctl && s.obstacle != AEB_OBS_LEAD)
+      t = predict_ctl_stop_time(static_cast<float>(v0), static_cast<float>(gap),
+                                static_cast<float>(s.ttc_warn), static_cast<float>(s.ttc_brake),
+                                -static_cast<float>(s.a_warn), static_cast<float>(s.ctl_period),
+                                static_cast<float>(ndl) * static_cast<float>(s.dt),
+                                static_cast<float>(k.kd), static_cast<float>(k.c),
+                                static_cast<float>(k.alim), static_cast<float>(tau),
+                                static_cast<float>(s.a_cmd), &t_full);
+    else
+      t = predict_stop_time(static_cast<float>(v0), static_cast<float>(k.kd),
+                            static_cast<float>(k.c), static_cast<float>(k.alim),
+                            static_cast<float>(tau), static_cast<float>(s.a_cmd), td);
     float steps = t / static_cast<float>(s.dt);
     if (!(steps < static_cast<float>(nmax))) steps = static_cast<float>(nmax);
     if (!(steps > 0.0f)) steps = 0.0f;
@@ -208,23 +263,14 @@ __global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job
     // levels, then the command step in 16-step bins, so a wavefront's lanes
     // end close together and switch the command within a few steps of each
     // other (each distinct switch step cuts the wavefront's blocks)
-    const uint32_t fine =
+    // with the controller: the tick of the predicted full-braking decision
+    // (modulo 64), so a wavefront's lanes reach the thresholds, where the
+    // noise can decide and the whole wavefront draws it, at the same ticks
+    uint32_t fine =
         a.nds ? (((ud >> 3) & 7u) << 3) | ((static_cast<uint32_t>(ndl) >> 4) & 7u) : ud & 63u;
-    uint32_t key = ((ud >> 6) << 7) | (limited ? 0u : 64u) | fine;
-    if (a.ctl) {
-      // with the controller, lanes are grouped first by when they reach the
-      // TTC thresholds (the approach time, 256 bins over the horizon, latest
-      // first), where the measurement noise can decide and every lane of
-      // the wavefront pays for a draw; then the limited class; then the
-      // braking time after the approach (16 bins, longest first), so the
-      // lanes also end close together
-      const float per = (capf + 1.0f) * (1.0f / 256.0f);
-      const float tds = td / static_cast<float>(s.dt);
-      const float ua = fminf(fmaxf(tds, 0.0f) / per, 255.0f);
-      const float ub = fminf(fmaxf(steps - tds, 0.0f) / (2.0f * per), 15.0f);
-      key = ((255u - static_cast<uint32_t>(ua)) << 5) | (limited ? 0u : 16u) |
-            (15u - static_cast<uint32_t>(ub));
-    }
+    if (t_full >= 0.0f)
+      fine = static_cast<uint32_t>(t_full / static_cast<float>(s.ctl_period) + 0.5f) & 63u;
+    const uint32_t key = ((ud >> 6) << 7) | (limited ? 0u : 64u) | fine;
     keys[i] = key;
     atomicAdd(&hist[key], 1u);
   }
@@ -722,10 +768,15 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
             if (L.active && L.stage < 2) {
               const double gt = LEAD ? (J.gap + L.l.xl) - L.s.x : (J.gap + 0.0) - L.s.x;
               const double cl = LEAD ? L.s.v - L.l.vl : L.s.v - 0.0;
-              // the noise is drawn (a Philox call, log, sqrt, sincos) only
-              // where it can change the decision
+              // the noise is drawn only where it can change the decision,
+              // estimated in single precision with an error box, and
+              // evaluated exactly only where the box straddles a threshold
               int want = ctl_screen(ctx.ca, L.stage, gt, cl);
-              if (want < 0) want = ctl_want(ctx.ca, g, tick, gt, cl);
+              if (want < 0) {
+                const U2 u = uniform2(ctx.ca.seed, ctx.ca.sid, g, AEB_SLOT_CONTROL, tick);
+                want = ctl_fast(ctx.ca, L.stage, gt, cl, u);
+                if (want < 0) want = ctl_exact(ctx.ca, u, gt, cl);
+              }
               if (want > L.stage) {
                 if (want == 2)
                   L.on2 = k + c.nd;

@@ -76,10 +76,11 @@ __device__ inline Ctl ctl_start() {
   return c;
 }
 
-// the stage decision `tick` asks for, from the true gap and closing speed
-__device__ inline int ctl_want(const CtlArgs& A, uint64_t index, uint32_t tick, double gap_true,
-                               double closing) {
-  const U2 u = uniform2(A.seed, A.sid, index, AEB_SLOT_CONTROL, tick);
+// The stage decision asks for from the measurement noise's uniforms u (the
+// cosine and sine Box-Muller normals of one generator call) and the true gap
+// and closing speed: measured TTC below ttc_brake asks for full braking,
+// below ttc_warn for partial braking.
+__device__ inline int ctl_exact(const CtlArgs& A, U2 u, double gap_true, double closing) {
   const double r = sqrt(-2.0 * log(u.a));
   const double ang = 6.283185307179586 * u.b;
   double sn, cs;
@@ -90,30 +91,85 @@ __device__ inline int ctl_want(const CtlArgs& A, uint64_t index, uint32_t tick, 
   return ttc < A.ttc_brake ? 2 : (ttc < A.ttc_warn ? 1 : 0);
 }
 
-// The decision's outcome when the measurement noise cannot change it, else
-// -1.  The Box-Muller radius is below 8.572 (the smallest uniform is 2^-53),
-// so the measured gap and closing speed lie within R = 8.6 noise sds of the
-// true ones; a lane whose measured TTC is above the next threshold for every
-// noise in that box (or below the full-brake threshold for every noise)
-// decides without drawing it.  Margins of 1e-9 cover the rounding of the
-// exact evaluation, so the outcome equals ctl_want's.
-__device__ inline int ctl_screen(const CtlArgs& A, int stage, double gap_true, double closing) {
-  constexpr double R = 8.6;
-  const double eg = A.noise_gap * R, ev = A.noise_v * R;
-  const double g_lo = gap_true - eg, g_hi = gap_true + eg;
-  const double c_lo = closing - ev, c_hi = closing + ev;
+// the stage decision `tick` asks for, from the true gap and closing speed
+__device__ inline int ctl_want(const CtlArgs& A, uint64_t index, uint32_t tick, double gap_true,
+                               double closing) {
+  return ctl_exact(A, uniform2(A.seed, A.sid, index, AEB_SLOT_CONTROL, tick), gap_true, closing);
+}
+
+// The decision's outcome when every measured gap in [g_lo, g_hi] and closing
+// speed in [c_lo, c_hi] gives it, else -1.  The outcome is the new stage when
+// the decision raises it (then it equals ctl_exact's value), and a value at
+// most `stage` when it does not.  Margins of 1e-9 (relative, plus 1e-9
+// absolute) cover the rounding of the exact evaluation.  Thresholds are >= 0.
+__device__ inline int ctl_box(const CtlArgs& A, int stage, double g_lo, double g_hi, double c_lo,
+                              double c_hi) {
   // every measured TTC at or above t (an infinite TTC included)
   auto above = [&](double t) {
     if (c_hi <= 0.0) return true;
     const double b = t * c_hi;
     return g_lo > 0.0 && g_lo >= b + 1e-9 * (fabs(b) + 1.0);
   };
-  const double t_next = stage == 0 ? fmax(A.ttc_warn, A.ttc_brake) : A.ttc_brake;
-  if (above(t_next)) return stage;  // nothing changes: want <= stage
-  // every measured TTC below the full-brake threshold
-  const double b = A.ttc_brake * c_lo;
-  if (c_lo > 0.0 && g_hi <= b - 1e-9 * (fabs(b) + 1.0)) return 2;
+  // every measured TTC below t
+  auto below = [&](double t) {
+    const double b = t * c_lo;
+    return c_lo > 0.0 && g_hi <= b - 1e-9 * (fabs(b) + 1.0);
+  };
+  if (below(A.ttc_brake)) return 2;
+  if (stage >= 1) return above(A.ttc_brake) ? stage : -1;
+  if (above(fmax(A.ttc_warn, A.ttc_brake))) return 0;
+  if (above(A.ttc_brake) && below(A.ttc_warn)) return 1;
   return -1;
+}
+
+// Before any draw: the Box-Muller radius is below 8.572 (the smallest
+// uniform is 2^-53), so the measured gap and closing speed lie within
+// R = 8.6 noise standard deviations of the true ones.
+__device__ inline int ctl_screen(const CtlArgs& A, int stage, double gap_true, double closing) {
+  constexpr double R = 8.6;
+  const double eg = A.noise_gap * R, ev = A.noise_v * R;
+  return ctl_box(A, stage, gap_true - eg, gap_true + eg, closing - ev, closing + ev);
+}
+
+// Bounds on the single-precision hardware approximations the estimate below
+// uses, over every input that reaches them (the device measures the actual
+// maxima exhaustively: aeb_ctl_approx_check):
+//   CTL_EL  |v_log_f32(a) - log2(a)| / max(1, |log2(a)|), a in [2^-53, 1]
+//   CTL_ES  |v_sqrt_f32(x) - sqrt(x)| / sqrt(x), x in [2^-24, 80]
+//   CTL_ET  |v_sin_f32(b) - sin(2 pi b)| and the cosine's, b in [2^-53, 1]
+//           (the instruction's argument is in revolutions)
+constexpr double CTL_EL = 1e-6;
+constexpr double CTL_ES = 1e-6;
+constexpr double CTL_ET = 1e-5;
+
+// After the draw: the noise estimated in single precision with an error box
+// around it, then ctl_box on the box; -1 when the box straddles a threshold
+// (the exact evaluation decides).  Error terms, for the radius r = sqrt(s),
+// s = -2 ln(u.a), and its estimate r' = v_sqrt_f32(s'):
+//   a = float(u.a) moves log2 by at most 2^-24 / ln 2 (< 8.6e-8), so
+//   |s' - s| <= D = 2 ln 2 (CTL_EL + 8.6e-8) + (CTL_EL + 2^-21) s' (the
+//   log's error relative to |log2 a| > 1, and the float constant and
+//   product roundings, 2^-23 s' with room);
+//   |sqrt(s') - r| <= D / max(r', sqrt(D0)) with D0 the absolute part of D,
+//   and |r' - sqrt(s')| <= 2 CTL_ES r';
+//   b = float(u.b) moves the angle by at most 2 pi 2^-24 < 3.8e-7.
+// Then |noise_gap (r cos - r' cos')| <= noise_gap (er + r' et), likewise for
+// the closing speed with the sine.
+__device__ inline int ctl_fast(const CtlArgs& A, int stage, double gap_true, double closing,
+                               U2 u) {
+  const float a = static_cast<float>(u.a), b = static_cast<float>(u.b);
+  const float s2 = fmaxf(-1.3862943611198906f * __builtin_amdgcn_logf(a), 0.0f);
+  const float rf = __builtin_amdgcn_sqrtf(s2);
+  const double r = rf, cs = __builtin_amdgcn_cosf(b), sn = __builtin_amdgcn_sinf(b);
+  constexpr double D0 = 2.0 * 0.6931471805599453 * (CTL_EL + 8.6e-8);
+  const double d = D0 + (CTL_EL + 0x1p-21) * static_cast<double>(s2);
+  const double er = d / fmax(r, 5e-4) + 2.0 * CTL_ES * r;  // 5e-4 < sqrt(D0) = 1.18e-3
+  const double et = CTL_ET + 3.8e-7;
+  const double eg = A.noise_gap * (er + r * et) * 1.0001;
+  const double ev = A.noise_v * (er + r * et) * 1.0001;
+  const double g = gap_true + A.noise_gap * (r * cs);
+  const double c = closing + A.noise_v * (r * sn);
+  return ctl_box(A, stage, g - eg, g + eg, c - ev, c + ev);
 }
 
 __device__ inline void ctl_decide(const CtlArgs& A, Ctl& c, uint64_t index, int64_t step,

@@ -50,6 +50,10 @@ def variants():
         "period_30ms_nofma": W.closed_loop(1500, ctl_period=0.03, nofma=True),
         "lead": dict(W.sweep(n=3000)[100], horizon=15.0, **CTL),
         "dt2ms": W.closed_loop(3000, dt=2e-3),
+        # the decision screen's error box at other noise scales
+        "noise_large": W.closed_loop(3000, noise_gap=2.0, noise_v=1.0),
+        "noise_tiny": W.closed_loop(3000, noise_gap=1e-7, noise_v=1e-7),
+        "noise_gap_only": W.closed_loop(3000, noise_v=0.0),
     }
 
 
@@ -69,6 +73,24 @@ def test_device_rng_fp64(B, orc, name):
 def test_ragged_sizes(B, orc, n, seed):
     d = W.closed_loop(n, seed=seed)
     check_fp64(to_np(plain(B, d)), orc.run(d), exact=True)
+
+
+def test_screen_approximation_bounds(B):
+    """The single-precision log2, sqrt, sin and cos the decision screen
+    estimates the noise with stay within the bounds its error box assumes,
+    over every input that can reach them (measured on the device)."""
+    measured, bounds = B.ctl_approx_check()
+    print("measured", measured, "bounds", bounds)
+    for m, b in zip(measured, bounds):
+        assert 0.0 < m <= b, (measured, bounds)
+
+
+def test_200k_exact(B, orc):
+    """Every sample of a 200,000-sample closed-loop run (persistent chunk
+    claims, thousands of screened and exact decisions) equals the reference
+    bit for bit."""
+    d = W.closed_loop(200_000, seed=17)
+    check_fp64(to_np(plain(B, d)), orc.run(d, threads=orc.host_threads()), exact=True)
 
 
 def test_first_tick_threshold_equals_open_loop_fast_path(B):
