@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "rollouts/sec FP64 vs FP32-comp; p50/p99 latency of 25k-sample requests"
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+FP64_FLOP_PER_CYCLE = 32768       # 1,024 SIMDs x 16 lanes x 2 flop
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # packed FP32; unpacked FP32 issues at the FP64 rate
 EULER_FLOPS_PER_STEP = 11        # 4 fma (2 each) + 3 (v*v, -c, cmd-a)
 FP32C_FLOPS_PER_STEP = 9         # 4 fma + v*v, compensated sums per block not counted
@@ -364,6 +365,7 @@ def control_leg(B, W, torch, n):
     ms_open = kernel_ms(B, torch, d_open, out, "fp64")
     steps_open = int(out["steps"].to(torch.int64).sum().item())
     flops = EULER_FLOPS_PER_STEP * steps
+    prof_ctl = profile_field("rollout_fp64_controller_1M.md", "k_roll_fp64_ctl_avg_us")
     res = {"workload": f"stationary obstacle at N(120 m, 10 m), {n} samples, explicit Euler "
                        "dt=1 ms, T=15 s; 20 Hz controller, partial braking -3 m/s^2 below TTC "
                        "3.0 s, full braking below 2.0 s, measurement noise 0.5 m / 0.3 m/s",
@@ -373,6 +375,9 @@ def control_leg(B, W, torch, n):
            "achieved_tflops": flops / (ms * 1e-3) / 1e12,
            "frac_fp64_peak": flops / (ms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
            "p_collision": st["p_collision"],
+           "profile_kernel_ms": (prof_ctl * 1e-3 if (prof_ctl and n == 1_048_576) else None),
+           "frac_from_profile": (flops / (prof_ctl * 1e-6) / 1e12 / FP64_VECTOR_PEAK_TFLOPS
+                                 if (prof_ctl and n == 1_048_576) else None),
            "open_loop_block_path": {"kernel_ms": ms_open, "steps_per_launch": steps_open,
                                     "step_rate_closed_over_open":
                                         (steps / ms) / (steps_open / ms_open)}}
@@ -795,6 +800,8 @@ def main():
     achieved = flops64 / kavg64 / 1e12
     prof_us = profile_field("rollout_fp64_1M_kernel_stats.md", "k_roll_fp64_avg_us")
     issued = profile_field("rollout_valu_counters_1M.md", "issued_fp64_flop_per_step")
+    cycles = profile_field("rollout_valu_counters_1M.md", "cycles_per_launch")
+    issue = profile_field("rollout_valu_counters_1M.md", "valu_issue_fraction")
     roofline = {
         "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
         "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
@@ -815,6 +822,14 @@ def main():
         "issued_flops_per_step": issued,
         "issued_frac": (issued * steps_total / kavg64 / 1e12 / FP64_VECTOR_PEAK_TFLOPS
                         if issued else None),
+        # the profile's GPU cycles per launch (GRBM_GUI_ACTIVE per XCD): the clock
+        # the kernel ran at, the fraction of the per-cycle FP64 peak (32,768 flop
+        # per cycle) and the share of cycles on which the VALU issued
+        "profile_clock_ghz": (cycles / (prof_us * 1e-6) / 1e9
+                              if (cycles and prof_us and n == 1_048_576) else None),
+        "frac_per_cycle": (flops64 / (cycles * FP64_FLOP_PER_CYCLE)
+                           if (cycles and n == 1_048_576) else None),
+        "valu_issue_fraction": issue if n == 1_048_576 else None,
     }
     if args.headline_only:
         res = {"metric": METRIC, "value": args.steps * n / wall64, "unit": "rollouts/s",
@@ -834,6 +849,7 @@ def main():
     wall32, k32, c32, st32 = time_steps(B, torch, d, params, "fp32c", out32, args.steps,
                                         args.warmup)
     steps32 = int(out32["steps"].to(torch.int64).sum().item())
+    prof32 = profile_field("rollout_fp32c_1M_kernel_stats.md", "k_roll_fp32c_avg_us")
     d64 = out["dist"].cpu().numpy()
     d32 = out32["dist"].cpu().numpy()
     s64 = out["status"].cpu().numpy()
@@ -955,6 +971,7 @@ def main():
             "boundary_samples": int(inband.sum()),
             "collision_flags_equal_fp64_outside_band": flags_equal,
             "speedup_vs_fp64_kernel": kavg64 / kavg32,
+            "profile_kernel_ms": (prof32 * 1e-3 if (prof32 and n == 1_048_576) else None),
         },
         "rk4": rk4,
         "unfused_euler": unfused,
