@@ -376,10 +376,8 @@ __device__ inline Partial block_combine(const Partial* wp) {
   return wave_combine(l < NW ? wp[l] : identity_partial());
 }
 
-__global__ __launch_bounds__(EB) void k_pass1(RSegs S) {
-  int bx;
-  RSeg g;
-  if (!seg_of_block(S, blockIdx.x, bx, g)) return;  // beyond the launch's sets (the whole block)
+// Pass 1 over element-pass block bx of set g (a workgroup of EB threads).
+__device__ inline void pass1_blk(const RSeg& g, int bx) {
   const OutCols o = g.out;
   const long long n = g.n;
   const long long chunk = static_cast<long long>(EB) * CP;
@@ -472,11 +470,16 @@ __global__ __launch_bounds__(EB) void k_pass1(RSegs S) {
   }
 }
 
+__global__ __launch_bounds__(EB) void k_pass1(RSegs S) {
+  int bx;
+  RSeg g;
+  if (!seg_of_block(S, blockIdx.x, bx, g)) return;  // beyond the launch's sets (the whole block)
+  pass1_blk(g, bx);
+}
+
 // Combine the block partials in a fixed order (thread t takes partials
 // t, t+FB, ... in order, then a fixed tree).
-__global__ __launch_bounds__(FB) void k_fin1(RSegs S) {
-  if (static_cast<int>(blockIdx.x) >= seg_count(S)) return;
-  const RSeg g = seg_at(S, blockIdx.x);
+__device__ inline void fin1_set(const RSeg& g) {
   const int weighted = g.out.weight ? 1 : 0;
   const long long n = g.n;
   const RLayout RL = layout(n, 0);
@@ -529,14 +532,16 @@ __global__ __launch_bounds__(FB) void k_fin1(RSegs S) {
   }
 }
 
+__global__ __launch_bounds__(FB) void k_fin1(RSegs S) {
+  if (static_cast<int>(blockIdx.x) >= seg_count(S)) return;
+  fin1_set(seg_at(S, blockIdx.x));
+}
+
 // Sum of squared deviations for the sd, and block-private histograms (LDS,
 // written out without atomics): value bins of the arrays that have targets,
 // and the number of risk-grid headways below each censored distance.
-__global__ __launch_bounds__(EB) void k_pass2(RSegs S, int need_d, int need_m, RReq rq,
-                                              int hw) {
-  int bx;
-  RSeg g;
-  if (!seg_of_block(S, blockIdx.x, bx, g)) return;  // beyond the launch's sets (the whole block)
+__device__ inline void pass2_blk(const RSeg& g, int bx, int need_d, int need_m, const RReq& rq,
+                                 int hw) {
   const OutCols o = g.out;
   const long long n = g.n;
   const long long chunk = static_cast<long long>(EB) * CP;
@@ -596,6 +601,14 @@ __global__ __launch_bounds__(EB) void k_pass2(RSegs S, int need_d, int need_m, R
   }
   unsigned* out = bhist + static_cast<size_t>(bx) * hw;
   for (int j = threadIdx.x; j < hw; j += EB) out[j] = h[j];
+}
+
+__global__ __launch_bounds__(EB) void k_pass2(RSegs S, int need_d, int need_m, RReq rq,
+                                              int hw) {
+  int bx;
+  RSeg g;
+  if (!seg_of_block(S, blockIdx.x, bx, g)) return;  // beyond the launch's sets (the whole block)
+  pass2_blk(g, bx, need_d, need_m, rq, hw);
 }
 
 // ---- importance-sampling sums: exact 128-bit fixed point ----
@@ -742,11 +755,8 @@ __global__ __launch_bounds__(256) void k_bin_totals(RSegs S, int hw) {
 
 // Block 0: the sd and the risk curve.  Block 1 + t: find the value bin
 // holding target t's rank.
-__global__ __launch_bounds__(FB) void k_fin2(RSegs S, RReq rq, int hw) {
+__device__ inline void fin2_blk(const RSeg& g, int bx, const RReq& rq, int hw) {
   const int T1 = 1 + rq.n_risk + rq.n_mq;
-  if (static_cast<int>(blockIdx.x / T1) >= seg_count(S)) return;
-  const RSeg g = seg_at(S, blockIdx.x / T1);
-  const int bx = blockIdx.x % T1;
   const long long n = g.n;
   const int ng = rq.ng;
   const RLayout RL = layout(n, T1 - 1);
@@ -842,13 +852,16 @@ __global__ __launch_bounds__(FB) void k_fin2(RSegs S, RReq rq, int hw) {
   }
 }
 
+__global__ __launch_bounds__(FB) void k_fin2(RSegs S, RReq rq, int hw) {
+  const int T1 = 1 + rq.n_risk + rq.n_mq;
+  if (static_cast<int>(blockIdx.x / T1) >= seg_count(S)) return;
+  fin2_blk(seg_at(S, blockIdx.x / T1), blockIdx.x % T1, rq, hw);
+}
+
 // Collect the keys of every element in a target's bin: block b of the
 // histogram pass's decomposition writes its elements from the offset the bin
 // search computed for it, ranked inside the block by LDS counters.
-__global__ __launch_bounds__(EB) void k_collect(RSegs S, RReq rq) {
-  int bx;
-  RSeg g;
-  if (!seg_of_block(S, blockIdx.x, bx, g)) return;  // beyond the launch's sets (the whole block)
+__device__ inline void collect_blk(const RSeg& g, int bx, const RReq& rq) {
   const OutCols o = g.out;
   const long long n = g.n;
   const long long chunk = static_cast<long long>(EB) * CP;
@@ -915,14 +928,20 @@ __global__ __launch_bounds__(EB) void k_collect(RSegs S, RReq rq) {
   }
 }
 
+__global__ __launch_bounds__(EB) void k_collect(RSegs S, RReq rq) {
+  int bx;
+  RSeg g;
+  if (!seg_of_block(S, blockIdx.x, bx, g)) return;  // beyond the launch's sets (the whole block)
+  collect_blk(g, bx, rq);
+}
+
 // One block per target: the element of rank r among the bin's candidates by
 // a most-significant-digit radix select in LDS, starting at the first byte
 // in which the candidates differ (they share the bin's leading bits).
-__global__ __launch_bounds__(RB) void k_pick(RSegs S, RReq rq) {
+template <int NT>
+__device__ inline void pick_tgt(const RSeg& g, int t, const RReq& rq) {
+  static_assert(NT >= 256 && NT % 64 == 0, "a thread per digit bin at least");
   const int T = rq.n_risk + rq.n_mq;
-  if (static_cast<int>(blockIdx.x / T) >= seg_count(S)) return;
-  const RSeg g = seg_at(S, blockIdx.x / T);
-  const int t = blockIdx.x % T;
   const RLayout RL = layout(g.n, T);
   const Sel* sel = reinterpret_cast<const Sel*>(g.base + RL.off_sel);
   const unsigned long long* cand = reinterpret_cast<const unsigned long long*>(g.base + RL.off_cand);
@@ -930,7 +949,7 @@ __global__ __launch_bounds__(RB) void k_pick(RSegs S, RReq rq) {
   aeb_stats* st = g.st;
   __shared__ unsigned long long key[CAP];
   __shared__ unsigned hist[256];
-  __shared__ unsigned long long wlo[RB / 64], whi[RB / 64];
+  __shared__ unsigned long long wlo[NT / 64], whi[NT / 64];
   __shared__ unsigned long long s_prefix;
   __shared__ unsigned s_rank;
   // the host reads the fallback flag through the statistics' reserved word
@@ -939,7 +958,7 @@ __global__ __launch_bounds__(RB) void k_pick(RSegs S, RReq rq) {
   // every element of the bin was collected (the bin holds at most CAP)
   const unsigned m = sel->bin_count[t] < ccap ? sel->bin_count[t] : ccap;
   unsigned long long lo = ~0ull, hi = 0ull;
-  for (unsigned j = threadIdx.x; j < m; j += RB) {
+  for (unsigned j = threadIdx.x; j < m; j += NT) {
     const unsigned long long k = cand[t * ccap + j];
     key[j] = k;
     lo = k < lo ? k : lo;
@@ -957,7 +976,7 @@ __global__ __launch_bounds__(RB) void k_pick(RSegs S, RReq rq) {
   __syncthreads();
   lo = wlo[0];
   hi = whi[0];
-  for (int w = 1; w < RB / 64; ++w) {
+  for (int w = 1; w < NT / 64; ++w) {
     lo = wlo[w] < lo ? wlo[w] : lo;
     hi = whi[w] > hi ? whi[w] : hi;
   }
@@ -972,9 +991,9 @@ __global__ __launch_bounds__(RB) void k_pick(RSegs S, RReq rq) {
     const int shift = 56 - 8 * pass;
     const unsigned long long mask = pass == 0 ? 0ull : (~0ull << (64 - 8 * pass));
     const unsigned long long pre = s_prefix;
-    hist[threadIdx.x] = 0;  // RB == 256 bins
+    if (threadIdx.x < 256) hist[threadIdx.x] = 0;  // 256 digit bins
     __syncthreads();
-    for (unsigned j = threadIdx.x; j < m; j += RB) {
+    for (unsigned j = threadIdx.x; j < m; j += NT) {
       const unsigned long long k = key[j];
       if ((k & mask) == pre) atomicAdd(&hist[(k >> shift) & 255ull], 1u);
     }
@@ -1013,6 +1032,82 @@ __global__ __launch_bounds__(RB) void k_pick(RSegs S, RReq rq) {
       st->headway[t] = v;
     else
       st->margin_q[t - rq.n_risk] = v;
+  }
+}
+
+__global__ __launch_bounds__(RB) void k_pick(RSegs S, RReq rq) {
+  const int T = rq.n_risk + rq.n_mq;
+  if (static_cast<int>(blockIdx.x / T) >= seg_count(S)) return;
+  pick_tgt<RB>(seg_at(S, blockIdx.x / T), blockIdx.x % T, rq);
+}
+
+// ---- small sets: the sequence in one workgroup per set ----
+// Every pass over a set of at most SMALL_N samples (one element-pass block)
+// run by one workgroup of EB threads with the same per-block arithmetic and
+// the same combination order as the separate kernels, so the statistics are
+// the same bits; the zeroing, the bin totals and the radix select (integer or
+// exact work) are done the workgroup's way.  Two kernels replace eight
+// launches (for such sets the launches, not the elements, set the time): the
+// first runs through the bin search, the second collects the candidates and
+// selects (one kernel for both would keep too many values live for the
+// registers of 1,024 threads).  The kernels take any number of blocks per set,
+// one after another, but beyond one block the separate kernels, whose blocks
+// run side by side, are faster (measured: 0.20 against 0.12 ms per call at
+// 25,000 samples).
+constexpr long long SMALL_N = static_cast<long long>(EB) * CP;
+
+__global__ __launch_bounds__(EB) void k_small(RSegs S, RReq rq, int hw, int need_d,
+                                              int need_m) {
+  if (static_cast<int>(blockIdx.x) >= seg_count(S)) return;
+  const RSeg g = seg_at(S, blockIdx.x);
+  const int T = rq.n_risk + rq.n_mq;
+  const RLayout RL = layout(g.n, 0);
+  {
+    unsigned* a = reinterpret_cast<unsigned*>(g.base + RL.off_sel);
+    const long long na = static_cast<long long>((RL.off_zero_end - RL.off_sel) / 4);
+    for (long long i = threadIdx.x; i < na; i += EB) a[i] = 0u;
+    unsigned* b = reinterpret_cast<unsigned*>(g.st);
+    for (int i = threadIdx.x; i < static_cast<int>(sizeof(aeb_stats) / 4); i += EB) b[i] = 0u;
+  }
+  __syncthreads();
+  for (int bx = 0; bx < RL.nb; ++bx) {
+    pass1_blk(g, bx);
+    __syncthreads();
+  }
+  fin1_set(g);
+  __syncthreads();
+  for (int bx = 0; bx < RL.nb2; ++bx) {
+    pass2_blk(g, bx, need_d, need_m, rq, hw);
+    __syncthreads();
+  }
+  if (hw > 0) {
+    const unsigned* bhist = reinterpret_cast<const unsigned*>(g.base + RL.off_bh);
+    unsigned* btot = reinterpret_cast<unsigned*>(g.base + RL.off_bt);
+    for (int j = threadIdx.x; j < hw; j += EB) {
+      unsigned c = 0;
+      for (int b = 0; b < RL.nb2; ++b) c += bhist[static_cast<size_t>(b) * hw + j];
+      btot[j] = c;
+    }
+  }
+  __syncthreads();
+  for (int j = 0; j <= T; ++j) {
+    fin2_blk(g, j, rq, hw);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(EB) void k_small_select(RSegs S, RReq rq) {
+  if (static_cast<int>(blockIdx.x) >= seg_count(S)) return;
+  const RSeg g = seg_at(S, blockIdx.x);
+  const int T = rq.n_risk + rq.n_mq;
+  const RLayout RL = layout(g.n, 0);
+  for (int bx = 0; bx < RL.nb2; ++bx) {
+    collect_blk(g, bx, rq);
+    __syncthreads();
+  }
+  for (int t = 0; t < T; ++t) {
+    pick_tgt<EB>(g, t, rq);
+    __syncthreads();
   }
 }
 
@@ -1197,17 +1292,27 @@ RSegs table_segs(const TLayout& T, const char* db) {
 }
 
 // The launch sequence over the sets of S (grids from the totals).
-int enqueue_sets(const RSegs& S, int nseg, int tb, int tr, bool weighted,
+int enqueue_sets(const RSegs& S, int nseg, int tb, int tr, bool weighted, int64_t max_n,
                  const aeb_reduce_req& req, hipStream_t st) {
-  // nseg, tb, tr: the grids' capacity of sets, element-pass blocks and rows
+  // nseg, tb, tr: the grids' capacity of sets, element-pass blocks and rows;
+  // max_n: no set holds more samples
   const RReq q = rreq_of(req);
   const int T = n_targets(req);
   const int ng = req.n_grid;
+  // block histograms: the value bins only when some target needs them
+  const int hw0 = ng >= 2 ? HG + ng + 1 : (T > 0 ? HG : 0);
+  if (!weighted && max_n <= SMALL_N) {
+    // every set small: one workgroup per set runs the whole sequence
+    hipLaunchKernelGGL(k_small, dim3(nseg), dim3(EB), 0, st, S, q, hw0, req.n_risk > 0 ? 1 : 0,
+                       req.n_margin_q > 0 ? 1 : 0);
+    if (T > 0) hipLaunchKernelGGL(k_small_select, dim3(nseg), dim3(EB), 0, st, S, q);
+    AEB_HIP(hipGetLastError());
+    return AEB_OK;
+  }
   hipLaunchKernelGGL(k_zero_sets, dim3(32, nseg), dim3(256), 0, st, S);
   hipLaunchKernelGGL(k_pass1, dim3(tb), dim3(EB), 0, st, S);
   hipLaunchKernelGGL(k_fin1, dim3(nseg), dim3(FB), 0, st, S);
-  // block histograms: the value bins only when some target needs them
-  const int hw = ng >= 2 ? HG + ng + 1 : (T > 0 ? HG : 0);
+  const int hw = hw0;
   hipLaunchKernelGGL(k_pass2, dim3(tb), dim3(EB), 0, st, S, req.n_risk > 0 ? 1 : 0,
                      req.n_margin_q > 0 ? 1 : 0, q, hw);
   if (hw > 0)
@@ -1261,7 +1366,7 @@ int reduce_enqueue(const OutCols& out, int64_t n, const aeb_reduce_req& req, voi
   S.one.st = reinterpret_cast<aeb_stats*>(scratch_base);
   S.one.nb = L.nb;
   const int rc = enqueue_sets(S, 1, L.nb, (L.nb2 + BT_ROWS - 1) / BT_ROWS, out.weight != nullptr,
-                              req, st);
+                              n, req, st);
   if (rc != AEB_OK) return rc;
   AEB_HIP(hipMemcpyAsync(host_out, S.one.st, sizeof(aeb_stats), hipMemcpyDeviceToHost, st));
   return AEB_OK;
@@ -1290,8 +1395,10 @@ int reduce_enqueue_sets(const OutCols* outs, const int64_t* ns, int nseg,
   char* db = static_cast<char*>(table_dev);
   char* hb = static_cast<char*>(table_host);
   const bool weighted = fill_table(T, outs, ns, nseg, bases, db, hb);
+  int64_t max_n = 0;
+  for (int j = 0; j < nseg; ++j) max_n = ns[j] > max_n ? ns[j] : max_n;
   AEB_HIP(hipMemcpyAsync(db, hb, T.host_bytes, hipMemcpyHostToDevice, st));
-  const int rc = enqueue_sets(table_segs(T, db), T.cap, T.tb, T.tr, weighted, req, st);
+  const int rc = enqueue_sets(table_segs(T, db), T.cap, T.tb, T.tr, weighted, max_n, req, st);
   if (rc != AEB_OK) return rc;
   AEB_HIP(hipMemcpyAsync(host_out, db + T.off_stats, sizeof(aeb_stats) * nseg,
                          hipMemcpyDeviceToHost, st));
@@ -1316,7 +1423,8 @@ int reduce_enqueue_sets_cap(int cap_sets, int64_t cap_samples, const aeb_reduce_
   const TLayout T = tlayout_cap(cap_sets, cap_samples);
   char* db = static_cast<char*>(table_dev);
   AEB_HIP(hipMemcpyAsync(db, table_host, T.host_bytes, hipMemcpyHostToDevice, st));
-  const int rc = enqueue_sets(table_segs(T, db), T.cap, T.tb, T.tr, weighted, req, st);
+  const int rc = enqueue_sets(table_segs(T, db), T.cap, T.tb, T.tr, weighted, cap_samples, req,
+                              st);
   if (rc != AEB_OK) return rc;
   AEB_HIP(hipMemcpyAsync(host_out, db + T.off_stats, sizeof(aeb_stats) * cap_sets,
                          hipMemcpyDeviceToHost, st));

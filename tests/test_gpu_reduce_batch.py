@@ -134,3 +134,22 @@ def test_radix_fallback_runs_and_matches(B, orc):
     compare_stats(got[1], want)
     same_stats(got[0], got[2])
     same_stats(got[0], B.reduce(other, risk=(0.5, 0.01), margin_q=(0.5,), grid=GRID))
+
+
+@pytest.mark.parametrize("n", [1, 63, 4095, 4096, 4097, 25_000])
+def test_small_set_paths_give_same_bits(B, orc, n):
+    """A set of at most 4,096 samples (one element-pass block) is reduced by
+    one workgroup (two kernels) when every set of the launch is that small,
+    and by the eight element-pass and selection kernels when a larger set
+    shares the launch: the same statistics bit for bit, and equal to the
+    reference's."""
+    d = W.single(n, seed=n, scenario_id=3)
+    small = B.rollout(d)
+    big = B.rollout(W.single(70_000, seed=5))
+    alone = B.reduce(small, risk=RISK, margin_q=MQ, grid=GRID)         # one workgroup
+    pair = B.batch_reduce([small, small], risk=RISK, margin_q=MQ, grid=GRID)
+    mixed = B.batch_reduce([big, small], risk=RISK, margin_q=MQ, grid=GRID)  # eight kernels
+    same_stats(alone, mixed[1])
+    same_stats(alone, pair[0])
+    same_stats(alone, pair[1])
+    compare_stats(alone, orc.reduce(to_np(small), risk=RISK, margin_q=MQ, grid=GRID))
