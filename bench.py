@@ -85,6 +85,21 @@ def cpu_model():
     return None
 
 
+LANES = {}   # lane accounting of the last timed launch of each loop (profiling hooks)
+
+
+def lane_efficiency(B, key, out):
+    """Read the lane accounting of the last timed rollout (timing still on)
+    and keep it under `key`: the fraction of the integration kernel's
+    lane-steps that advanced a sample (the steps output over the wavefront
+    sample-steps)."""
+    wave = B.timing_lanes()
+    lane = int(out["steps"].long().sum().item())
+    LANES[key] = {"wave_sample_steps": wave, "sample_steps": lane,
+                  "lane_efficiency": lane / wave if wave else None}
+    return LANES[key]
+
+
 def time_steps(B, torch, d, params, precision, out, steps, warmup):
     """Warm up, then time `steps` steps of rollout + reduce.  Returns the wall
     time, per-step integration-kernel times (library HIP events around that
@@ -108,6 +123,7 @@ def time_steps(B, torch, d, params, precision, out, steps, warmup):
         kern_ms.append(B.timing_last())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    lane_efficiency(B, (precision, int(d["n_samples"]), bool(d.get("ctl_period"))), out)
     B.timing_enable(False)
     call_ms = [a.elapsed_time(b) for a, b in evs]
     return wall, kern_ms, call_ms, stats
@@ -299,6 +315,7 @@ def kernel_ms(B, torch, d, out, precision="fp64", reps=3):
     for _ in range(reps):
         B.rollout(d, out=out, precision=precision)
         ks.append(B.timing_last())
+    lane_efficiency(B, (precision, int(d["n_samples"]), bool(d.get("ctl_period"))), out)
     B.timing_enable(False)
     return float(np.median(ks))
 
@@ -375,6 +392,7 @@ def control_leg(B, W, torch, n):
            "achieved_tflops": flops / (ms * 1e-3) / 1e12,
            "frac_fp64_peak": flops / (ms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
            "p_collision": st["p_collision"],
+           "lane_efficiency": LANES.get(("fp64", n, True), {}).get("lane_efficiency"),
            "profile_kernel_ms": (prof_ctl * 1e-3 if (prof_ctl and n == 1_048_576) else None),
            "frac_from_profile": (flops / (prof_ctl * 1e-6) / 1e12 / FP64_VECTOR_PEAK_TFLOPS
                                  if (prof_ctl and n == 1_048_576) else None),
@@ -830,6 +848,9 @@ def main():
         "frac_per_cycle": (flops64 / (cycles * FP64_FLOP_PER_CYCLE)
                            if (cycles and n == 1_048_576) else None),
         "valu_issue_fraction": issue if n == 1_048_576 else None,
+        # lane efficiency of the last timed launch (aeb_timing_lanes): the
+        # fraction of the kernel's lane-steps that advanced a sample
+        "lane_efficiency": LANES.get(("fp64", n, False), {}).get("lane_efficiency"),
     }
     if args.headline_only:
         res = {"metric": METRIC, "value": args.steps * n / wall64, "unit": "rollouts/s",
@@ -971,6 +992,7 @@ def main():
             "boundary_samples": int(inband.sum()),
             "collision_flags_equal_fp64_outside_band": flags_equal,
             "speedup_vs_fp64_kernel": kavg64 / kavg32,
+            "lane_efficiency": LANES.get(("fp32c", n, False), {}).get("lane_efficiency"),
             "profile_kernel_ms": (prof32 * 1e-3 if (prof32 and n == 1_048_576) else None),
         },
         "rk4": rk4,

@@ -326,6 +326,7 @@ int aeb_rollout(const aeb_scenario* scn, const aeb_params* params, int precision
  * call made before an earlier one's kernels have run) race and give wrong
  * results: order them on one stream or synchronise between them.  The array
  * keeps the last call's contents; the kernels clear what must start at zero.
+ * The timing hooks (aeb_timing_enable) are off inside this call.
  * Asynchronous on `stream`. */
 #define AEB_NOALLOC_SCRATCH_BYTES (32LL << 20)
 int aeb_rollout_noalloc(const aeb_scenario* scn, const aeb_params* params, int precision,
@@ -369,6 +370,18 @@ int aeb_batch_reduce(const aeb_outputs* outs, int n_scn, const aeb_reduce_req* r
  * the last aeb_rollout call of this thread (AEB_EAGAIN if there was none). */
 int aeb_timing_enable(int on);
 int aeb_timing_last(float* ms);
+
+/* Lane accounting of the last timed aeb_rollout (or aeb_batch_rollout) on
+ * this thread, the measure of the sample-per-lane mapping that the paper's
+ * discussion of divergence from early termination (Sec. V-C) calls for:
+ * *wave_sample_steps = the sum over the integration kernel's wavefront
+ * chunks of the steps the wavefront ran times its sample slots (64, or 128
+ * with two samples per lane).  The sum of the launch's steps output over it
+ * is the lane efficiency, the fraction of lane-steps that advanced a sample.
+ * Waits for that kernel.  AEB_EAGAIN if there was no timed launch, or if it
+ * ran the checked one-sample-per-lane kernel (horizons beyond the block
+ * path), which keeps no such count. */
+int aeb_timing_lanes(uint64_t* wave_sample_steps);
 
 /* Self-check of the closed-loop controller's decision screen (Sec. VIII's
  * controller: measured TTC from noisy gap and closing speed).  Where the

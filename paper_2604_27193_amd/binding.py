@@ -14,7 +14,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libaeb.so")
-ABI_VERSION = 7     # the aeb_version() these structures match
+ABI_VERSION = 8     # the aeb_version() these structures match
 NOALLOC_SCRATCH_BYTES = 32 << 20  # AEB_NOALLOC_SCRATCH_BYTES of aeb.h
 SERVE_EAGER = 1                   # AEB_SERVE_EAGER of aeb.h
 
@@ -37,7 +37,7 @@ END_STOP, END_IMPACT, END_HORIZON, COLLIDED, BOUNDARY = 1, 2, 3, 4, 8
 EXPORTS = ("aeb_last_error", "aeb_version", "aeb_validate", "aeb_uniforms", "aeb_sample_params",
            "aeb_rollout", "aeb_rollout_noalloc", "aeb_reduce", "aeb_batch_rollout",
            "aeb_batch_reduce",
-           "aeb_timing_enable", "aeb_timing_last", "aeb_reduce_fallbacks", "aeb_ctl_approx_check",
+           "aeb_timing_enable", "aeb_timing_last", "aeb_timing_lanes", "aeb_reduce_fallbacks", "aeb_ctl_approx_check",
            "aeb_server_fixed_bytes",
            "aeb_serve_footprint", "aeb_server_create", "aeb_server_destroy", "aeb_serve_submit",
            "aeb_serve_poll", "aeb_server_info_get", "aeb_graph_create", "aeb_graph_create_batch",
@@ -152,6 +152,7 @@ def lib():
         L.aeb_timing_enable.argtypes = [C.c_int]
         L.aeb_timing_last.argtypes = [P(C.c_float)]
         L.aeb_reduce_fallbacks.argtypes = [P(C.c_uint64)]
+        L.aeb_timing_lanes.argtypes = [P(C.c_uint64)]
         L.aeb_ctl_approx_check.argtypes = [P(C.c_double), P(C.c_double), C.c_void_p]
         L.aeb_server_fixed_bytes.argtypes = [P(ServerCfg), P(C.c_uint64)]
         L.aeb_serve_footprint.argtypes = [P(ServerCfg), C.c_int64, P(C.c_uint64)]
@@ -402,6 +403,14 @@ def ctl_approx_check(stream=None):
     b = (C.c_double * 4)()
     _check(lib().aeb_ctl_approx_check(m, b, _stream(stream)))
     return tuple(m), tuple(b)
+
+
+def timing_lanes():
+    """Wavefront sample-steps of the last timed rollout on this thread: the
+    launch's steps output summed over it is the lane efficiency."""
+    w = C.c_uint64()
+    _check(lib().aeb_timing_lanes(C.byref(w)))
+    return w.value
 
 
 def timing_enable(on=True):

@@ -59,6 +59,9 @@ struct Timing {
   bool recorded = false;
   int dev = -1;
   hipEvent_t start = nullptr, stop = nullptr;
+  unsigned long long* lanes = nullptr;  // lane accounting of the timed launch (device)
+  bool lanes_armed = false;  // the next timed launch counts lanes
+  bool lanes_valid = false;  // the last timed launch counted lanes
 };
 thread_local Timing g_timing;
 thread_local ScratchScope* g_scope = nullptr;
@@ -284,18 +287,38 @@ bool timing_suspend(bool off) {
 
 void timing_resume(bool was) { g_timing.on = was; }
 
-void timing_begin(hipStream_t stream) {
+// the events and the lane counters of the current device (made on first use)
+static bool timing_ready() {
   Timing& t = g_timing;
-  if (!t.on) return;
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
   if (t.dev != dev) {
     if (t.start) (void)hipEventDestroy(t.start);
     if (t.stop) (void)hipEventDestroy(t.stop);
+    if (t.lanes) (void)hipFree(t.lanes);
     t.start = t.stop = nullptr;
-    if (hipEventCreate(&t.start) != hipSuccess || hipEventCreate(&t.stop) != hipSuccess) return;
+    t.lanes = nullptr;
+    t.dev = -1;
+    if (hipEventCreate(&t.start) != hipSuccess || hipEventCreate(&t.stop) != hipSuccess ||
+        hipMalloc(&t.lanes, sizeof(unsigned long long)) != hipSuccess)
+      return false;
     t.dev = dev;
   }
+  return true;
+}
+
+unsigned long long* timing_lanes() {
+  if (!g_timing.on || !timing_ready()) return nullptr;
+  g_timing.lanes_armed = true;
+  return g_timing.lanes;
+}
+
+void timing_begin(hipStream_t stream) {
+  Timing& t = g_timing;
+  if (!t.on || !timing_ready()) return;
+  // a launch that did not arm the counters (the checked kernels) has none
+  t.lanes_valid = t.lanes_armed;
+  t.lanes_armed = false;
   (void)hipEventRecord(t.start, stream);
 }
 
@@ -378,11 +401,12 @@ extern "C" {
 
 const char* aeb_last_error(void) { return g_err.c_str(); }
 
-int aeb_version(void) { return 7; }
+int aeb_version(void) { return 8; }
 
 int aeb_timing_enable(int on) {
   g_timing.on = on != 0;
   g_timing.recorded = false;
+  g_timing.lanes_valid = g_timing.lanes_armed = false;
   return AEB_OK;
 }
 
@@ -395,6 +419,19 @@ int aeb_reduce_fallbacks(uint64_t* count) {
 int aeb_ctl_approx_check(double* measured, double* bounds, void* stream) {
   if (!measured || !bounds) return fail(AEB_EINVAL, "aeb_ctl_approx_check: null argument");
   return launch_approx_check(measured, bounds, static_cast<hipStream_t>(stream));
+}
+
+int aeb_timing_lanes(uint64_t* wave_sample_steps) {
+  if (!wave_sample_steps) return fail(AEB_EINVAL, "aeb_timing_lanes: null argument");
+  Timing& t = g_timing;
+  if (!t.recorded || !t.lanes) return fail(AEB_EAGAIN, "no timed rollout on this thread");
+  if (!t.lanes_valid)
+    return fail(AEB_EAGAIN, "the last timed rollout ran a checked kernel (no lane accounting)");
+  AEB_HIP(hipEventSynchronize(t.stop));
+  unsigned long long h = 0;
+  AEB_HIP(hipMemcpy(&h, t.lanes, sizeof(h), hipMemcpyDeviceToHost));
+  *wave_sample_steps = h;
+  return AEB_OK;
 }
 
 int aeb_timing_last(float* ms) {

@@ -57,6 +57,9 @@ inline void* pool_block(size_t bytes, hipStream_t stream) { return scratch_slot(
 
 // events around the integration kernel (aeb_timing_enable)
 void timing_begin(hipStream_t stream);
+// the lane counters the next timed integration kernel accumulates into (null
+// when timing is off)
+unsigned long long* timing_lanes();
 void timing_end(hipStream_t stream);
 // switch the hooks off on this thread (returns the previous state) / back on
 bool timing_suspend(bool off);

@@ -480,7 +480,18 @@ struct Ctx {
   const int32_t* nds;  // per-sample command steps (perception), else null
   CtlArgs ca;          // the closed-loop controller (kernels instantiated for it)
   const BatchHdr* hdr; // a recorded mix: the launch's sample count (else null)
+  // profiling (timing enabled): the sum over chunks of the steps the
+  // wavefront ran times its sample slots (the steps output sums the useful
+  // ones: lane efficiency is their ratio), else null
+  unsigned long long* lanes;
 };
+
+// Lane accounting of one chunk: the wavefront ran k steps for spw sample
+// slots (one atomic per chunk, from its first lane).
+__device__ inline void count_lanes(unsigned long long* lanes, int k, int spw) {
+  if ((threadIdx.x & 63) == 0)
+    atomicAdd(lanes, static_cast<unsigned long long>(k) * static_cast<unsigned long long>(spw));
+}
 
 struct LaneScn {
   double dt, a_cmd;
@@ -931,6 +942,7 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
       }
     }
     if (L.pend) vimp = __builtin_nanf("");  // unreachable; makes a broken replay visible
+    if (ctx.lanes) count_lanes(ctx.lanes, k, 64);
     if (valid) {
       if (!LEAD) {
         const double mg = J.gap - (INTEG == AEB_RK4 ? xmax : dist);
@@ -1224,6 +1236,7 @@ __global__ __launch_bounds__(256) void k_roll_fp64x2(const Job* __restrict__ job
         if (L[q].pend) vimp[q] = __builtin_nanf("");  // unreachable; makes a broken replay visible
       }
     }
+    if (ctx.lanes) count_lanes(ctx.lanes, k, 128);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       if (!valid[q]) continue;
@@ -1567,6 +1580,7 @@ __global__ __launch_bounds__(256) void k_roll_fp32c(const Job* __restrict__ jobs
     } else if (OBS == AEB_OBS_STATIONARY && !L.crossed) {
       boundary = J.gap - dist < band;
     }
+    if (ctx.lanes) count_lanes(ctx.lanes, k, 64);
     if (valid) {
       const double mg = J.gap - dist;
       int64_t i;
@@ -1832,6 +1846,7 @@ __global__ __launch_bounds__(256) void k_roll_fp32c_lead(const Job* __restrict__
     }
     if (L.pend) vimp = __builtin_nanf("");  // unreachable; makes a broken replay visible
     if (!collided) boundary = static_cast<double>(gm_end) < band;
+    if (ctx.lanes) count_lanes(ctx.lanes, k, 64);
     if (valid) {
       int64_t i;
       const OutCols o = lane_out<BATCH>(ctx, J, g, i);
@@ -2004,10 +2019,20 @@ void go32k(int k, const Shape& sh, const Bufs& b, int64_t n, const Ctx& ctx, dou
                        b.jobs, b.perm, n, ctx, band_abs, band_rel, fix, b.counter, sh.persistent);
 }
 
+// With timing enabled, the lane accounting of the launch that follows
+// (zeroed first, by a kernel so that the sequence stays recordable).
+inline void arm_lanes(Ctx& ctx, hipStream_t st) {
+  ctx.lanes = timing_lanes();
+  if (ctx.lanes)
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(ctx.lanes),
+                       int64_t(2));
+}
+
 template <bool BATCH>
-int integrate(const aeb_scenario& s0, int precision, const Bufs& b, int64_t n, const Ctx& ctx,
+int integrate(const aeb_scenario& s0, int precision, const Bufs& b, int64_t n, const Ctx& ctx_in,
               const ParamSrc* src, hipStream_t st) {
   const int obs = s0.obstacle;
+  Ctx ctx = ctx_in;
   const TuneCfg t = tune_get(precision == AEB_FP64 ? AEB_FP64 : AEB_FP32C, obs);
   const Shape sh = shape(t, n);
   if (!BATCH && control_on(s0)) {
@@ -2016,6 +2041,7 @@ int integrate(const aeb_scenario& s0, int precision, const Bufs& b, int64_t n, c
     // where one is built (50 steps: 20 and 10 Hz at 1 ms; 40: 25 Hz), else 48
     // (a 50-step period would take a 48-step and a 2-step block); FP64 only
     const int64_t per = ctl_args(s0).period;
+    arm_lanes(ctx, st);
     timing_begin(st);
     if (s0.integrator == AEB_RK4)
       go64<AEB_OBS_STATIONARY, 16, false, AEB_RK4, true>(sh, b, n, ctx, st);
@@ -2041,6 +2067,7 @@ int integrate(const aeb_scenario& s0, int precision, const Bufs& b, int64_t n, c
   }
   if (precision == AEB_FP64 && s0.integrator == AEB_RK4) {
     // an RK4 step costs about eight Euler steps: short blocks keep the tail small
+    arm_lanes(ctx, st);
     timing_begin(st);
     if (obs == AEB_OBS_STATIONARY)
       go64<AEB_OBS_STATIONARY, 16, BATCH, AEB_RK4>(sh, b, n, ctx, st);
@@ -2052,6 +2079,7 @@ int integrate(const aeb_scenario& s0, int precision, const Bufs& b, int64_t n, c
   }
   if (precision == AEB_FP64 && s0.nofma) {
     // the unfused form: 128-step blocks, the launch shape of the table
+    arm_lanes(ctx, st);
     timing_begin(st);
     if (obs == AEB_OBS_STATIONARY)
       go64<AEB_OBS_STATIONARY, 128, BATCH, EULER_NOFMA>(sh, b, n, ctx, st);
@@ -2066,6 +2094,7 @@ int integrate(const aeb_scenario& s0, int precision, const Bufs& b, int64_t n, c
   if (precision == AEB_FP64 && t.spt == 2 && obs != AEB_OBS_LEAD) {
     // two samples per lane (the tuned FP64 shape)
     const Shape sh2 = shape(t, n, 2);
+    arm_lanes(ctx, st);
     timing_begin(st);
     if (obs == AEB_OBS_STATIONARY)
       go64x2k<AEB_OBS_STATIONARY, BATCH>(t.k, sh2, b, n, ctx, st);
@@ -2076,6 +2105,7 @@ int integrate(const aeb_scenario& s0, int precision, const Bufs& b, int64_t n, c
     return AEB_OK;
   }
   if (precision == AEB_FP64) {
+    arm_lanes(ctx, st);
     timing_begin(st);
     if (obs == AEB_OBS_STATIONARY)
       go64k<AEB_OBS_STATIONARY, BATCH>(t.k, sh, b, n, ctx, st);
@@ -2099,6 +2129,7 @@ int integrate(const aeb_scenario& s0, int precision, const Bufs& b, int64_t n, c
   // long as the distance error stays below that band, every flag outside it
   // equals the FP64 one.
   const double band_abs = 1e-3, band_rel = 1e-4;
+  arm_lanes(ctx, st);
   timing_begin(st);
   if (obs == AEB_OBS_LEAD) {
     if (t.k == 16)

@@ -72,5 +72,10 @@ extern "C" int aeb_rollout_noalloc(const aeb_scenario* scn, const aeb_params* pa
   void* base = nullptr;
   rc = scratch_ptr(&base);
   if (rc != AEB_OK) return rc;
-  return launch_rollout_fast_into(*scn, ps, precision, oc, scn->n_samples, base, st);
+  // the timing hooks (aeb_timing_enable) would create events and a counter
+  // buffer on first use: off inside this call
+  const bool was = timing_suspend(true);
+  rc = launch_rollout_fast_into(*scn, ps, precision, oc, scn->n_samples, base, st);
+  timing_resume(was);
+  return rc;
 }
