@@ -27,6 +27,8 @@
 #include <memory>
 #include <mutex>
 #include <thread>
+
+#include <sys/prctl.h>
 #include <unordered_map>
 #include <vector>
 
@@ -286,6 +288,9 @@ class Scheduler {
  private:
   void loop() {
     ex_->bind_thread();
+    // the polls below sleep a few microseconds; the default timer slack
+    // (50 us) would stretch each into tens of microseconds of latency
+    (void)prctl(PR_SET_TIMERSLACK, 1UL, 0UL, 0UL, 0UL);
     for (;;) {
       bool in_flight;
       {
@@ -300,7 +305,7 @@ class Scheduler {
       }
       if (!step()) {
         // device work in flight or a packing window open: poll again shortly
-        std::this_thread::sleep_for(std::chrono::microseconds(in_flight ? 20 : 50));
+        std::this_thread::sleep_for(std::chrono::microseconds(in_flight ? 10 : 50));
       }
     }
   }
