@@ -44,7 +44,9 @@ namespace {
 // scratch memory (the compiler declined to inline the largest forms).
 #define HOT __device__ __attribute__((always_inline)) inline
 
-constexpr int NBINS = 8192;  // sort keys: 64 coarse x 2 classes x 64 fine
+// sort keys: 64 coarse length bins x 2 classes x 64 fine levels (8,192 keys);
+// with the controller 64 decision ticks x 2 classes x 128 length levels
+constexpr int NBINS = 16384;
 // The sort's kernels (prep, scan, scatter) run in workgroups of one wavefront
 // per SIMD: beside a running integration kernel (four wavefronts per SIMD)
 // each CU has room for one such workgroup, so the next launch's preparation
@@ -263,14 +265,20 @@ __global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job
     // levels, then the command step in 16-step bins, so a wavefront's lanes
     // end close together and switch the command within a few steps of each
     // other (each distinct switch step cuts the wavefront's blocks)
-    // with the controller: the tick of the predicted full-braking decision
-    // (modulo 64), so a wavefront's lanes reach the thresholds, where the
-    // noise can decide and the whole wavefront draws it, at the same ticks
-    uint32_t fine =
+    const uint32_t fine =
         a.nds ? (((ud >> 3) & 7u) << 3) | ((static_cast<uint32_t>(ndl) >> 4) & 7u) : ud & 63u;
-    if (t_full >= 0.0f)
-      fine = static_cast<uint32_t>(t_full / static_cast<float>(s.ctl_period) + 0.5f) & 63u;
-    const uint32_t key = ((ud >> 6) << 7) | (limited ? 0u : 64u) | fine;
+    uint32_t key = ((ud >> 6) << 7) | (limited ? 0u : 64u) | fine;
+    // with the controller: first the tick of the predicted full-braking
+    // decision (modulo 64, latest first), so a wavefront's lanes reach the
+    // thresholds, where the noise can decide and the whole wavefront draws
+    // it, at the same ticks; then the class and the length in 128 levels, so
+    // that they also stop close together (each lane's stop takes the
+    // wavefront down the block ladder)
+    if (t_full >= 0.0f) {
+      const uint32_t tk =
+          static_cast<uint32_t>(t_full / static_cast<float>(s.ctl_period) + 0.5f) & 63u;
+      key = ((63u - tk) << 8) | (limited ? 0u : 128u) | (ud >> 5);
+    }
     keys[i] = key;
     atomicAdd(&hist[key], 1u);
   }
@@ -734,6 +742,9 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
     const double thr_m = static_cast<double>(KM) * c.dt * J.dmax;
     const double thr_s = static_cast<double>(KS) * c.dt * J.dmax;
     const double thr_2 = static_cast<double>(K2) * c.dt * J.dmax;
+    // the smallest block level and its stopping bound
+    constexpr int KMIN = K2 < KS ? K2 : KS;
+    const double thr_min = K2 < KS ? thr_2 : thr_s;
     Lane64 L;
     L.on1 = L.on2 = INT_MAX;
     L.stage = 0;
@@ -837,46 +848,53 @@ __global__ __launch_bounds__(256) void k_roll_fp64(const Job* __restrict__ jobs,
         if (INTEG == AEB_RK4 && L.active) xmax = fmax(xmax, L.s.x);
         k += K2;
       } else {
-        const double cmd = lane_cmd<CTL>(L, c, ctx.ca.a_warn, k);
-        if (L.active) {
-          step64<LEAD, INTEG>(L.s, L.l, J, al, c.dt, cmd);
-          if (INTEG == AEB_RK4) xmax = fmax(xmax, L.s.x);
-          if (k >= first_cmd<CTL>(L, c))
-            L.clamped = L.clamped || (L.limited && L.s.a <= J.alim);
-          bool impact = false;
-          if (LEAD) {
-            const double gk = (J.gap + L.l.xl) - L.s.x;
-            L.l.gmin = fmin(L.l.gmin, gk);
-            impact = gk < 0.0;
-          } else if (OBS == AEB_OBS_STATIONARY) {
-            impact = L.s.x > J.gap;
-          }
-          if (impact && !L.collided) {
-            L.collided = true;
-            vimp = static_cast<float>(LEAD ? L.s.v - L.l.vl : L.s.v);
-          }
-          if (impact && (LEAD || ctx.impact_exit)) {
-            L.active = false;
-            end = AEB_END_IMPACT;
-            steps = k + 1;
-            dist = L.s.x;
-          }
+        // checked single steps, in a loop of their own for as long as no
+        // block level fits (a lane within the smallest level's stopping
+        // bound, or the block limit closer than that level) and no decision
+        // step or block limit is reached
+        do {
+          const double cmd = lane_cmd<CTL>(L, c, ctx.ca.a_warn, k);
           if (L.active) {
-            if (L.s.v <= 0.0) {
+            step64<LEAD, INTEG>(L.s, L.l, J, al, c.dt, cmd);
+            if (INTEG == AEB_RK4) xmax = fmax(xmax, L.s.x);
+            if (k >= first_cmd<CTL>(L, c))
+              L.clamped = L.clamped || (L.limited && L.s.a <= J.alim);
+            bool impact = false;
+            if (LEAD) {
+              const double gk = (J.gap + L.l.xl) - L.s.x;
+              L.l.gmin = fmin(L.l.gmin, gk);
+              impact = gk < 0.0;
+            } else if (OBS == AEB_OBS_STATIONARY) {
+              impact = L.s.x > J.gap;
+            }
+            if (impact && !L.collided) {
+              L.collided = true;
+              vimp = static_cast<float>(LEAD ? L.s.v - L.l.vl : L.s.v);
+            }
+            if (impact && (LEAD || ctx.impact_exit)) {
               L.active = false;
-              end = AEB_END_STOP;
-              steps = k + 1;
-              dist = L.s.x;
-            } else if (k + 1 == c.nmax) {
-              L.active = false;
-              end = AEB_END_HORIZON;
+              end = AEB_END_IMPACT;
               steps = k + 1;
               dist = L.s.x;
             }
+            if (L.active) {
+              if (L.s.v <= 0.0) {
+                L.active = false;
+                end = AEB_END_STOP;
+                steps = k + 1;
+                dist = L.s.x;
+              } else if (k + 1 == c.nmax) {
+                L.active = false;
+                end = AEB_END_HORIZON;
+                steps = k + 1;
+                dist = L.s.x;
+              }
+            }
+            if (LEAD && !L.active) margin = L.l.gmin;
           }
-          if (LEAD && !L.active) margin = L.l.gmin;
-        }
-        k += 1;
+          k += 1;
+        } while (k < wl && !(CTL && k == ktick) && __any(L.active) &&
+                 (k + KMIN > wl || __any(L.active && L.s.v <= thr_min)));
       }
     }
     // replay the block in which each pending lane passed the obstacle.  Inside

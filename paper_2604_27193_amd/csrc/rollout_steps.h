@@ -15,6 +15,7 @@
 #include <cstdint>
 
 #include "aeb_common.h"
+#include "ctl_math.h"
 
 namespace aeb {
 
@@ -80,11 +81,16 @@ __device__ inline Ctl ctl_start() {
 // cosine and sine Box-Muller normals of one generator call) and the true gap
 // and closing speed: measured TTC below ttc_brake asks for full braking,
 // below ttc_warn for partial braking.
+// The logarithm, sine and cosine are ctl_math.h's, written for these
+// arguments (a few registers where a general library routine costs the
+// integration kernel a wavefront per SIMD), accurate to about an ulp like any
+// libm: the outcome equals another FP64 evaluation's unless the measured TTC
+// lies within about 1e-15 (relative) of a threshold.
 __device__ inline int ctl_exact(const CtlArgs& A, U2 u, double gap_true, double closing) {
-  const double r = sqrt(-2.0 * log(u.a));
+  const double r = sqrt(-2.0 * ctl_log(u.a));
   const double ang = 6.283185307179586 * u.b;
   double sn, cs;
-  sincos(ang, &sn, &cs);  // one argument reduction for both (the same bits as cos and sin)
+  ctl_sincos(ang, &sn, &cs);
   const double g = gap_true + A.noise_gap * (r * cs);
   const double cl = closing + A.noise_v * (r * sn);
   const double ttc = cl > 0.0 ? g / cl : INFINITY;
