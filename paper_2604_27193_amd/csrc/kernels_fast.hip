@@ -44,9 +44,12 @@ namespace {
 // scratch memory (the compiler declined to inline the largest forms).
 #define HOT __device__ __attribute__((always_inline)) inline
 
-// sort keys: 64 coarse length bins x 2 classes x 64 fine levels (8,192 keys);
-// with the controller 64 decision ticks x 2 classes x 128 length levels
-constexpr int NBINS = 16384;
+// sort keys: 64 coarse length bins x 2 classes x 64 fine levels; with the
+// controller 64 decision ticks x 2 classes x 128 length levels (the sort's
+// kernels take the key count as a template argument: their per-bin loops
+// cost latency on small launches)
+constexpr int NBINS = 8192;
+constexpr int NBINS_CTL = 16384;
 // The sort's kernels (prep, scan, scatter) run in workgroups of one wavefront
 // per SIMD: beside a running integration kernel (four wavefronts per SIMD)
 // each CU has room for one such workgroup, so the next launch's preparation
@@ -158,7 +161,7 @@ struct PrepArgs {
   int per;                   // samples per thread (prep_per of the launch size)
 };
 
-template <bool DEVRNG, bool BATCH>
+template <bool DEVRNG, bool BATCH, int NB = NBINS>
 __global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job* jobs,
                                                                  LeadJob* leads, uint32_t* keys,
                                                                  uint32_t* ghist) {
@@ -167,8 +170,8 @@ __global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job
   const int64_t n_all = a.hdr ? a.hdr->total : a.n;
   const float capf = a.hdr ? a.hdr->cap : a.cap;
   const int n_scn = a.hdr ? a.hdr->n_scn : a.n_scn;
-  __shared__ uint32_t hist[NBINS];
-  for (int j = threadIdx.x; j < NBINS; j += NT) hist[j] = 0;
+  __shared__ uint32_t hist[NB];
+  for (int j = threadIdx.x; j < NB; j += NT) hist[j] = 0;
   __syncthreads();
   for (int r = 0; r < a.per; ++r) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * (NT * a.per) + r * NT + threadIdx.x;
@@ -283,16 +286,17 @@ __global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job
     atomicAdd(&hist[key], 1u);
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < NBINS; j += NT)
+  for (int j = threadIdx.x; j < NB; j += NT)
     if (hist[j]) atomicAdd(&ghist[j], hist[j]);
 }
 
 // exclusive scan of the key histogram into bucket offsets (one block); also
 // clears the integration kernel's chunk counter
+template <int NB>
 __global__ __launch_bounds__(PREP_BLOCK) void k_scan(uint32_t* hist, unsigned long long* counter) {
   if (threadIdx.x == 0) *counter = 0ull;
   __shared__ uint32_t part[PREP_BLOCK];
-  constexpr int PER = NBINS / PREP_BLOCK;
+  constexpr int PER = NB / PREP_BLOCK;
   uint32_t loc[PER];
   uint32_t sum = 0;
   for (int j = 0; j < PER; ++j) {
@@ -316,24 +320,44 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_scan(uint32_t* hist, unsigned lo
 
 // Placement: each block ranks its samples per key in LDS, reserves one range
 // per key with a single global atomic, then writes the permutation.
+template <int NB>
 __global__ __launch_bounds__(PREP_BLOCK) void k_scatter(const uint32_t* keys, int64_t n,
                                                         uint32_t* offs, uint32_t* perm,
                                                         const BatchHdr* hdr) {
   if (hdr) n = hdr->total;
-  __shared__ uint32_t cnt[NBINS];
-  for (int j = threadIdx.x; j < NBINS; j += PREP_BLOCK) cnt[j] = 0;
+  __shared__ uint32_t cnt[NB];
+  for (int j = threadIdx.x; j < NB; j += PREP_BLOCK) cnt[j] = 0;
   __syncthreads();
   uint32_t key[PREP_PER], rank[PREP_PER];
   const int64_t base_i = static_cast<int64_t>(blockIdx.x) * (PREP_BLOCK * PREP_PER);
+  // every key load in flight before the first LDS rank
+#pragma unroll
   for (int r = 0; r < PREP_PER; ++r) {
     const int64_t i = base_i + r * PREP_BLOCK + threadIdx.x;
     key[r] = i < n ? keys[i] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < PREP_PER; ++r) {
+    const int64_t i = base_i + r * PREP_BLOCK + threadIdx.x;
     rank[r] = i < n ? atomicAdd(&cnt[key[r]], 1u) : 0u;
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < NBINS; j += PREP_BLOCK) {
-    const uint32_t c = cnt[j];
-    cnt[j] = c ? atomicAdd(&offs[j], c) : 0u;
+  // the range reservations, 16 keys of the thread at a time: every atomic of
+  // a group is in flight before the first result is read (one after another
+  // they set the kernel's time on small launches)
+  constexpr int G = 16;
+  static_assert(NB % (G * PREP_BLOCK) == 0, "key count");
+  for (int j0 = threadIdx.x; j0 < NB; j0 += G * PREP_BLOCK) {
+    uint32_t c[G], o[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) c[q] = cnt[j0 + q * PREP_BLOCK];
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      o[q] = 0u;
+      if (c[q]) o[q] = atomicAdd(&offs[j0 + q * PREP_BLOCK], c[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < G; ++q) cnt[j0 + q * PREP_BLOCK] = o[q];
   }
   __syncthreads();
   for (int r = 0; r < PREP_PER; ++r) {
@@ -1959,7 +1983,7 @@ size_t bufs_layout(int64_t n, int n_scn, bool lead, char* base, Bufs* b) {
   const size_t off_nds = up(off_perm + sizeof(uint32_t) * n);
   const size_t off_fix = up(off_nds + sizeof(int32_t) * n);
   const size_t off_hist = up(off_fix + sizeof(uint32_t) * (n + 1));
-  const size_t off_cnt = up(off_hist + sizeof(uint32_t) * NBINS);
+  const size_t off_cnt = up(off_hist + sizeof(uint32_t) * NBINS_CTL);
   const size_t off_tab = up(off_cnt + sizeof(unsigned long long));
   const size_t off_scn = up(off_tab + sizeof(ScnDev) * n_scn);
   const size_t total = up(off_scn + sizeof(aeb_scenario) * n_scn);
@@ -1980,11 +2004,12 @@ size_t bufs_layout(int64_t n, int n_scn, bool lead, char* base, Bufs* b) {
 
 // sort the prepared keys into the permutation (the scan zeroes the claim counter)
 // (hdr: a recorded mix, n its capacity and the actual count on the device)
+template <int NB = NBINS>
 void sort_keys(const Bufs& b, int64_t n, hipStream_t st, const BatchHdr* hdr = nullptr) {
   const unsigned pblk = static_cast<unsigned>((n + PREP_SAMPLES - 1) / PREP_SAMPLES);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(PREP_BLOCK), 0, st, b.hist, b.counter);
-  hipLaunchKernelGGL(k_scatter, dim3(pblk), dim3(PREP_BLOCK), 0, st, b.keys, n, b.hist, b.perm,
-                     hdr);
+  hipLaunchKernelGGL(k_scan<NB>, dim3(1), dim3(PREP_BLOCK), 0, st, b.hist, b.counter);
+  hipLaunchKernelGGL(k_scatter<NB>, dim3(pblk), dim3(PREP_BLOCK), 0, st, b.keys, n, b.hist,
+                     b.perm, hdr);
 }
 
 template <int OBS, int K, bool BATCH, int INTEG = AEB_EULER, bool CTL = false>
@@ -2187,7 +2212,9 @@ int launch_rollout_fast_into(const aeb_scenario& s, const ParamSrc* src, int pre
   Bufs b;
   bufs_layout(n, 0, lead, static_cast<char*>(scratch_base), &b);
   const unsigned pblk = prep_grid(n);
-  hipLaunchKernelGGL(k_zero, dim3(NBINS / 256), dim3(256), 0, st, b.hist, int64_t(NBINS));
+  const bool ctl = control_on(s);
+  const int nb = ctl ? NBINS_CTL : NBINS;
+  hipLaunchKernelGGL(k_zero, dim3(nb / 256), dim3(256), 0, st, b.hist, int64_t(nb));
   PrepArgs pa{};
   pa.s = s;
   pa.src = src ? *src : ParamSrc{};
@@ -2197,15 +2224,25 @@ int launch_rollout_fast_into(const aeb_scenario& s, const ParamSrc* src, int pre
   pa.nmax = static_cast<int>(nmax);
   pa.cap = static_cast<float>(nmax);
   pa.nds = perception_on(s) ? b.nds : nullptr;
-  pa.ctl = control_on(s) ? 1 : 0;
+  pa.ctl = ctl ? 1 : 0;
   pa.weight = out.weight;
-  if (src)
-    hipLaunchKernelGGL((k_prep<false, false>), dim3(pblk), dim3(PREP_BLOCK), 0, st, pa, b.jobs,
-                       b.leads, b.keys, b.hist);
-  else
-    hipLaunchKernelGGL((k_prep<true, false>), dim3(pblk), dim3(PREP_BLOCK), 0, st, pa, b.jobs,
-                       b.leads, b.keys, b.hist);
-  sort_keys(b, n, st);
+  if (ctl) {
+    if (src)
+      hipLaunchKernelGGL((k_prep<false, false, NBINS_CTL>), dim3(pblk), dim3(PREP_BLOCK), 0, st,
+                         pa, b.jobs, b.leads, b.keys, b.hist);
+    else
+      hipLaunchKernelGGL((k_prep<true, false, NBINS_CTL>), dim3(pblk), dim3(PREP_BLOCK), 0, st,
+                         pa, b.jobs, b.leads, b.keys, b.hist);
+    sort_keys<NBINS_CTL>(b, n, st);
+  } else {
+    if (src)
+      hipLaunchKernelGGL((k_prep<false, false>), dim3(pblk), dim3(PREP_BLOCK), 0, st, pa, b.jobs,
+                         b.leads, b.keys, b.hist);
+    else
+      hipLaunchKernelGGL((k_prep<true, false>), dim3(pblk), dim3(PREP_BLOCK), 0, st, pa, b.jobs,
+                         b.leads, b.keys, b.hist);
+    sort_keys(b, n, st);
+  }
   Ctx ctx{};
   ctx.dt = s.dt;
   ctx.a_cmd = s.a_cmd;
