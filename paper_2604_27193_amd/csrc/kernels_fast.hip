@@ -57,16 +57,14 @@ constexpr int NBINS_CTL = 16384;
 constexpr int PREP_BLOCK = 256;
 constexpr int PREP_SAMPLES = 4096;                     // samples per scatter block
 constexpr int PREP_PER = PREP_SAMPLES / PREP_BLOCK;    // samples per scatter thread
-// Samples per thread of the prep kernel: enough workgroups (about 512) to
-// spread the per-sample draws over the chip for small launches, at most 16
-// (a 4,096-sample block) for large ones.
-inline int prep_per(int64_t n) {
-  const int64_t p = (n + PREP_BLOCK * 512 - 1) / (PREP_BLOCK * 512);
-  return static_cast<int>(p < 1 ? 1 : (p > PREP_PER ? PREP_PER : p));
-}
+// The prep kernel takes one sample per thread, and the key histogram is a
+// kernel of its own.  (A loop over several samples per thread, to share a
+// block histogram's flush, let the compiler hoist the constants of the draws'
+// log, sqrt, sine and cosine out of the loop and hold them in registers: 231
+// VGPRs, two wavefronts per SIMD, against 118 without it; and a block
+// histogram per 256 samples costs more than the draws save.)
 inline unsigned prep_grid(int64_t n) {
-  const int64_t per = static_cast<int64_t>(PREP_BLOCK) * prep_per(n);
-  return static_cast<unsigned>((n + per - 1) / per);
+  return static_cast<unsigned>((n + PREP_BLOCK - 1) / PREP_BLOCK);
 }
 template <bool DEVRNG>
 constexpr int prep_threads() { return PREP_BLOCK; }
@@ -158,24 +156,18 @@ struct PrepArgs {
   int ctl;                   // closed-loop controller (single scenario)
   double* weight;            // single scenario: importance-sampling weights out (or null)
   const BatchHdr* hdr;       // batch on device tables: n, cap and n_scn from here (else null)
-  int per;                   // samples per thread (prep_per of the launch size)
 };
 
-template <bool DEVRNG, bool BATCH, int NB = NBINS>
+template <bool DEVRNG, bool BATCH>
 __global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job* jobs,
-                                                                 LeadJob* leads, uint32_t* keys,
-                                                                 uint32_t* ghist) {
+                                                                 LeadJob* leads, uint32_t* keys) {
   constexpr int NT = prep_threads<DEVRNG>();
   // a recorded mix reads its sizes from the device header
   const int64_t n_all = a.hdr ? a.hdr->total : a.n;
   const float capf = a.hdr ? a.hdr->cap : a.cap;
   const int n_scn = a.hdr ? a.hdr->n_scn : a.n_scn;
-  __shared__ uint32_t hist[NB];
-  for (int j = threadIdx.x; j < NB; j += NT) hist[j] = 0;
-  __syncthreads();
-  for (int r = 0; r < a.per; ++r) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * (NT * a.per) + r * NT + threadIdx.x;
-    if (i >= n_all) break;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+  if (i < n_all) {
     // the sample's scenario and its index within it
     uint32_t j = 0;
     int64_t local = i;
@@ -283,10 +275,30 @@ __global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job
       key = ((63u - tk) << 8) | (limited ? 0u : 128u) | (ud >> 5);
     }
     keys[i] = key;
-    atomicAdd(&hist[key], 1u);
   }
+}
+
+// Key histogram: per block of PREP_SAMPLES keys in LDS, then one global
+// atomic per key the block holds.
+template <int NB>
+__global__ __launch_bounds__(PREP_BLOCK) void k_hist(const uint32_t* keys, int64_t n,
+                                                     uint32_t* ghist, const BatchHdr* hdr) {
+  if (hdr) n = hdr->total;
+  __shared__ uint32_t hist[NB];
+  for (int j = threadIdx.x; j < NB; j += PREP_BLOCK) hist[j] = 0;
   __syncthreads();
-  for (int j = threadIdx.x; j < NB; j += NT)
+  uint32_t key[PREP_PER];
+  const int64_t base_i = static_cast<int64_t>(blockIdx.x) * (PREP_BLOCK * PREP_PER);
+#pragma unroll
+  for (int r = 0; r < PREP_PER; ++r) {
+    const int64_t i = base_i + r * PREP_BLOCK + threadIdx.x;
+    key[r] = i < n ? keys[i] : NB;
+  }
+#pragma unroll
+  for (int r = 0; r < PREP_PER; ++r)
+    if (key[r] < NB) atomicAdd(&hist[key[r]], 1u);
+  __syncthreads();
+  for (int j = threadIdx.x; j < NB; j += PREP_BLOCK)
     if (hist[j]) atomicAdd(&ghist[j], hist[j]);
 }
 
@@ -2007,6 +2019,7 @@ size_t bufs_layout(int64_t n, int n_scn, bool lead, char* base, Bufs* b) {
 template <int NB = NBINS>
 void sort_keys(const Bufs& b, int64_t n, hipStream_t st, const BatchHdr* hdr = nullptr) {
   const unsigned pblk = static_cast<unsigned>((n + PREP_SAMPLES - 1) / PREP_SAMPLES);
+  hipLaunchKernelGGL(k_hist<NB>, dim3(pblk), dim3(PREP_BLOCK), 0, st, b.keys, n, b.hist, hdr);
   hipLaunchKernelGGL(k_scan<NB>, dim3(1), dim3(PREP_BLOCK), 0, st, b.hist, b.counter);
   hipLaunchKernelGGL(k_scatter<NB>, dim3(pblk), dim3(PREP_BLOCK), 0, st, b.keys, n, b.hist,
                      b.perm, hdr);
@@ -2219,30 +2232,22 @@ int launch_rollout_fast_into(const aeb_scenario& s, const ParamSrc* src, int pre
   pa.s = s;
   pa.src = src ? *src : ParamSrc{};
   pa.n = n;
-  pa.per = prep_per(n);
   pa.nd = static_cast<int>(nd);
   pa.nmax = static_cast<int>(nmax);
   pa.cap = static_cast<float>(nmax);
   pa.nds = perception_on(s) ? b.nds : nullptr;
   pa.ctl = ctl ? 1 : 0;
   pa.weight = out.weight;
-  if (ctl) {
-    if (src)
-      hipLaunchKernelGGL((k_prep<false, false, NBINS_CTL>), dim3(pblk), dim3(PREP_BLOCK), 0, st,
-                         pa, b.jobs, b.leads, b.keys, b.hist);
-    else
-      hipLaunchKernelGGL((k_prep<true, false, NBINS_CTL>), dim3(pblk), dim3(PREP_BLOCK), 0, st,
-                         pa, b.jobs, b.leads, b.keys, b.hist);
+  if (src)
+    hipLaunchKernelGGL((k_prep<false, false>), dim3(pblk), dim3(PREP_BLOCK), 0, st, pa, b.jobs,
+                       b.leads, b.keys);
+  else
+    hipLaunchKernelGGL((k_prep<true, false>), dim3(pblk), dim3(PREP_BLOCK), 0, st, pa, b.jobs,
+                       b.leads, b.keys);
+  if (ctl)
     sort_keys<NBINS_CTL>(b, n, st);
-  } else {
-    if (src)
-      hipLaunchKernelGGL((k_prep<false, false>), dim3(pblk), dim3(PREP_BLOCK), 0, st, pa, b.jobs,
-                         b.leads, b.keys, b.hist);
-    else
-      hipLaunchKernelGGL((k_prep<true, false>), dim3(pblk), dim3(PREP_BLOCK), 0, st, pa, b.jobs,
-                         b.leads, b.keys, b.hist);
+  else
     sort_keys(b, n, st);
-  }
   Ctx ctx{};
   ctx.dt = s.dt;
   ctx.a_cmd = s.a_cmd;
@@ -2301,7 +2306,6 @@ int launch_batch_fast_into(const aeb_scenario* scns, int n_scn, int precision,
   hipLaunchKernelGGL(k_zero, dim3(NBINS / 256), dim3(256), 0, st, b.hist, int64_t(NBINS));
   PrepArgs pa{};
   pa.n = total;
-  pa.per = prep_per(total);
   pa.cap = static_cast<float>(cap);
   pa.scns = b.scns;
   pa.tab = b.tab;
@@ -2310,7 +2314,7 @@ int launch_batch_fast_into(const aeb_scenario* scns, int n_scn, int precision,
   for (int j = 0; j < n_scn; ++j) perc = perc || perception_on(scns[j]);
   pa.nds = perc ? b.nds : nullptr;
   hipLaunchKernelGGL((k_prep<true, true>), dim3(pblk), dim3(PREP_BLOCK), 0, st, pa, b.jobs,
-                     b.leads, b.keys, b.hist);
+                     b.leads, b.keys);
   sort_keys(b, total, st);
   Ctx ctx{};
   ctx.impact_exit = scns[0].impact_exit;
@@ -2329,7 +2333,6 @@ int launch_batch_fast_dev(const aeb_scenario& kind, bool perception, int precisi
   hipLaunchKernelGGL(k_zero, dim3(NBINS / 256), dim3(256), 0, st, b.hist, int64_t(NBINS));
   PrepArgs pa{};
   pa.n = cap_total;
-  pa.per = prep_per(cap_total);
   pa.cap = 1.0f;
   pa.scns = scns;
   pa.tab = tab;
@@ -2337,7 +2340,7 @@ int launch_batch_fast_dev(const aeb_scenario& kind, bool perception, int precisi
   pa.nds = perception ? b.nds : nullptr;
   pa.hdr = hdr;
   hipLaunchKernelGGL((k_prep<true, true>), dim3(pblk), dim3(PREP_BLOCK), 0, st, pa, b.jobs,
-                     b.leads, b.keys, b.hist);
+                     b.leads, b.keys);
   sort_keys(b, cap_total, st, hdr);
   Ctx ctx{};
   ctx.impact_exit = kind.impact_exit;
