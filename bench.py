@@ -156,6 +156,14 @@ def time_graph_steps_two_streams(B, torch, d, params, precision, outs, steps, wa
     of the last (all must equal)."""
     gs = [B.Graph(d, params=params, precision=precision, out=o, risk=RISK, margin_q=MARGIN_Q,
                   grid=GRID) for o in outs]
+    return pipeline_graphs(torch, gs, steps, warmup)
+
+
+def pipeline_graphs(torch, gs, steps, warmup):
+    """Replays two recorded graphs (own outputs and scratch each) alternately
+    on two streams, launching step k+1 before collecting step k; closes the
+    graphs.  Returns the wall time of `steps` steps, the statistics of the
+    last and whether every step's statistics equal it."""
     ss = [torch.cuda.Stream(), torch.cuda.Stream()]
     for k in range(max(warmup, 2)):
         gs[k % 2].launch(ss[k % 2])
@@ -177,7 +185,10 @@ def time_graph_steps_two_streams(B, torch, d, params, precision, outs, steps, wa
 
 
 def same_stats(a, b):
+    """Equal statistics (NaN equal to NaN); a batch's are lists of them."""
     import numpy as np
+    if isinstance(a, list):
+        return len(a) == len(b) and all(same_stats(x, y) for x, y in zip(a, b))
     for k, v in a.items():
         w = b[k]
         if isinstance(v, np.ndarray):
@@ -562,7 +573,16 @@ def uneven_config_leg(B, W, torch, reps=3):
         graph_ms = (time.perf_counter() - t0) / reps * 1e3
         g.close()
         same = all(same_stats(a, b) for a, b in zip(st_e, st_g))
-        del outs
+        # two such graphs (own outputs and scratch) pipelined on two streams:
+        # one step's prep and sort overlap the other's integration tail and
+        # statistics
+        outs2 = [B.alloc_outputs(int(d["n_samples"])) for d in scns]
+        gs = [B.Graph(scns, precision="fp32c", out=o, risk=RISK, margin_q=MARGIN_Q, grid=GRID,
+                      batch=True) for o in (outs, outs2)]
+        wall2, st_p, p_equal = pipeline_graphs(torch, gs, max(reps, 4), 1)
+        pipe_ms = wall2 / max(reps, 4) * 1e3
+        p_same = p_equal and same_stats(st_e, st_p)
+        del outs, outs2
         torch.cuda.empty_cache()
     finally:
         B.tune_set("fp32c", "stationary", *keep)
@@ -577,7 +597,10 @@ def uneven_config_leg(B, W, torch, reps=3):
                       "candidates": len(ranked), "default_shape_ms": default_ms},
             "eager_ms_per_step": eager_ms, "eager_rollouts_per_s": total / (eager_ms * 1e-3),
             "graph_ms_per_step": graph_ms, "graph_rollouts_per_s": total / (graph_ms * 1e-3),
-            "graph_stats_equal_eager": same}
+            "graph_stats_equal_eager": same,
+            "two_stream_graph_ms_per_step": pipe_ms,
+            "two_stream_rollouts_per_s": total / (pipe_ms * 1e-3),
+            "two_stream_stats_equal_eager": p_same}
 
 
 def serving_leg(B, W, precision, rates, duration, arena_gib=4):
