@@ -315,8 +315,8 @@ int aeb_rollout(const aeb_scenario* scn, const aeb_params* params, int precision
  * fixed library-owned device array of AEB_NOALLOC_SCRATCH_BYTES per device
  * instead of the growable pool.  The array holds the sorted path's per-sample
  * job records, sort keys and permutation, command steps and FP32 fix-up list
- * (80 bytes per sample, 88 with a lead vehicle, plus 33 KB): 32 MiB covers
- * about 381,000 samples with a lead vehicle and 419,000 without.  A scenario
+ * (80 bytes per sample, 88 with a lead vehicle, plus 66 KB): 32 MiB covers
+ * 380,544 samples with a lead vehicle and 418,604 without.  A scenario
  * that needs more returns AEB_ENOMEM (use aeb_rollout); nothing is enqueued
  * then.  The call makes no hipMalloc/hipFree or other allocation and no
  * synchronisation, so it can be captured into a caller's graph.  Each device

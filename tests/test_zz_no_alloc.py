@@ -3,8 +3,9 @@ array, for callers that cannot allocate) against aeb_rollout on the same
 inputs: every output of every sample identical, for two calls in a row on
 one device, the second with fewer samples than the first (the array keeps
 the first call's contents, which the second must not read).  Also: a
-scenario whose scratch exceeds the array is refused before anything runs,
-and a call captured into a HIP graph replays to the same results."""
+scenario whose scratch exceeds the array is refused before anything runs
+(the largest accepted sizes are the ones the header states), and a call
+captured into a HIP graph replays to the same results."""
 import numpy as np
 import pytest
 
@@ -70,6 +71,21 @@ def test_noalloc_refuses_beyond_its_array(B):
     out_big = {k: torch.empty(n, dtype=v.dtype, device="cuda") for k, v in out.items()}
     with pytest.raises(RuntimeError, match="scratch"):
         B.rollout_noalloc(d, out=out_big)
+
+
+@pytest.mark.parametrize("lead, limit", [(False, 418_604), (True, 380_544)],
+                         ids=["stationary", "lead"])
+def test_noalloc_limit_is_the_documented_one(B, lead, limit):
+    """aeb.h states the largest scenario the array takes: that one runs (and
+    equals aeb_rollout), one sample more is refused."""
+    def make(n):
+        return dict(W.sweep(n=n)[37]) if lead else W.single(n, seed=3)
+    d = make(limit)
+    want = to_np(B.rollout(d, precision="fp32c"))
+    same(to_np(B.rollout_noalloc(d, precision="fp32c")), want)
+    out = B.alloc_outputs(limit + 1)
+    with pytest.raises(RuntimeError, match="scratch"):
+        B.rollout_noalloc(make(limit + 1), out=out, precision="fp32c")
 
 
 def test_noalloc_in_captured_graph(B):
