@@ -158,6 +158,120 @@ struct PrepArgs {
   const BatchHdr* hdr;       // batch on device tables: n, cap and n_scn from here (else null)
 };
 
+// One sample: its parameters (drawn, or loaded from the plain method's
+// columns), its job record and its sort key.
+template <bool DEVRNG, bool BATCH>
+HOT uint32_t prep_sample(const PrepArgs& a, int64_t i, float capf, int n_scn, Job* jobs,
+                         LeadJob* leads) {
+  // the sample's scenario and its index within it
+  uint32_t j = 0;
+  int64_t local = i;
+  if (BATCH) {
+    int lo = 0, hi = n_scn - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.tab[mid].off <= i)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    j = static_cast<uint32_t>(lo);
+    local = i - a.tab[lo].off;
+  }
+  const aeb_scenario& s = BATCH ? a.scns[j] : a.s;
+  const int nd = BATCH ? a.tab[j].nd : a.nd;
+  const int nmax = BATCH ? a.tab[j].nmax : a.nmax;
+  double v0, mu, mass, sg, cg, cda, crr, tau, gap, lead, trig, lw;
+  if (DEVRNG) {
+    Sample q = draw_sample(s, static_cast<uint64_t>(local));
+    v0 = q.v0; mu = q.mu; mass = q.mass; sg = q.sin_grade; cg = q.cos_grade;
+    cda = q.cda; crr = q.crr; tau = q.tau; gap = q.gap; lead = q.lead_decel;
+    trig = q.trigger;
+    lw = q.log_w;
+  } else {
+    v0 = a.src.v0[i]; mu = a.src.mu[i]; mass = a.src.mass[i]; sg = a.src.sin_g[i];
+    cg = a.src.cos_g[i]; cda = a.src.cda[i]; crr = a.src.crr[i]; tau = a.src.tau[i];
+    gap = a.src.gap[i]; lead = a.src.lead[i];
+    trig = a.src.trig ? a.src.trig[i] : 0.0;
+    lw = a.src.logw ? a.src.logw[i] : 0.0;
+  }
+  // the importance-sampling weight goes straight to the sample's output
+  double* wout = BATCH ? a.tab[j].out.weight : a.weight;
+  if (wout) wout[local] = exp(lw);
+  // with perception every sample has its own command step
+  int ndl = nd;
+  if (a.nds) {
+    ndl = static_cast<int>(command_step(s, trig, nmax));
+    a.nds[i] = ndl;
+  }
+  const Consts k = derive(s, mu, mass, sg, cg, cda, crr);
+  Job J;
+  J.v0 = v0;
+  J.nkd = -k.kd;
+  J.c = k.c;
+  J.alim = k.alim;
+  J.kt = s.integrator == AEB_RK4 ? 1.0 / tau : s.dt / tau;  // Euler: dt/tau; RK4: 1/tau
+  J.gap = gap;
+  // |acc| <= min(|a_cmd|, |alim|) + kd vmax^2 + |c|, with vmax the largest
+  // speed the sample can reach (only a downhill pull can raise it)
+  const double creach = k.c < 0.0 ? -k.c : 0.0;
+  const double vmax = fabs(v0) + s.horizon * creach;
+  const double brake = fmin(fabs(s.a_cmd), fabs(k.alim));
+  J.dmax = (brake + fabs(k.kd) * vmax * vmax + fabs(k.c)) * 1.0001 + 1e-9;
+  // classify and predict
+  const bool limited = !(k.alim < s.a_cmd - 1e-6);
+  float td = static_cast<float>(ndl) * static_cast<float>(s.dt);
+  if (a.ctl && s.obstacle == AEB_OBS_LEAD) {
+    // approach until the full-brake threshold, for the sort only: a lead
+    // braking at `lead` from the ego's speed (closing speed lead t, gap
+    // closed by lead t^2 / 2)
+    const float T = static_cast<float>(s.ttc_brake), G = static_cast<float>(gap);
+    const float A = static_cast<float>(lead);
+    td += A > 0.0f ? sqrtf(T * T + 2.0f * G / A) - T : static_cast<float>(s.horizon);
+  }
+  float t, t_full = -1.0f;
+  if (a.ctl && s.obstacle != AEB_OBS_LEAD)
+    t = predict_ctl_stop_time(static_cast<float>(v0), static_cast<float>(gap),
+                              static_cast<float>(s.ttc_warn), static_cast<float>(s.ttc_brake),
+                              -static_cast<float>(s.a_warn), static_cast<float>(s.ctl_period),
+                              static_cast<float>(ndl) * static_cast<float>(s.dt),
+                              static_cast<float>(k.kd), static_cast<float>(k.c),
+                              static_cast<float>(k.alim), static_cast<float>(tau),
+                              static_cast<float>(s.a_cmd), &t_full);
+  else
+    t = predict_stop_time(static_cast<float>(v0), static_cast<float>(k.kd),
+                          static_cast<float>(k.c), static_cast<float>(k.alim),
+                          static_cast<float>(tau), static_cast<float>(s.a_cmd), td);
+  float steps = t / static_cast<float>(s.dt);
+  if (!(steps < static_cast<float>(nmax))) steps = static_cast<float>(nmax);
+  if (!(steps > 0.0f)) steps = 0.0f;
+  J.pred = steps;
+  J.scn = j;
+  jobs[i] = J;
+  if (leads) leads[i].decel = lead;
+  const uint32_t u = static_cast<uint32_t>(fminf(steps, capf) * (4096.0f / (capf + 1.0f)));
+  const uint32_t ud = 4095u - (u > 4095u ? 4095u : u);  // longest first
+  // within a coarse length bin: finer length; with perception 8 finer length
+  // levels, then the command step in 16-step bins, so a wavefront's lanes
+  // end close together and switch the command within a few steps of each
+  // other (each distinct switch step cuts the wavefront's blocks)
+  const uint32_t fine =
+      a.nds ? (((ud >> 3) & 7u) << 3) | ((static_cast<uint32_t>(ndl) >> 4) & 7u) : ud & 63u;
+  uint32_t key = ((ud >> 6) << 7) | (limited ? 0u : 64u) | fine;
+  // with the controller: first the tick of the predicted full-braking
+  // decision (modulo 64, latest first), so a wavefront's lanes reach the
+  // thresholds, where the noise can decide and the whole wavefront draws
+  // it, at the same ticks; then the class and the length in 128 levels, so
+  // that they also stop close together (each lane's stop takes the
+  // wavefront down the block ladder)
+  if (t_full >= 0.0f) {
+    const uint32_t tk =
+        static_cast<uint32_t>(t_full / static_cast<float>(s.ctl_period) + 0.5f) & 63u;
+    key = ((63u - tk) << 8) | (limited ? 0u : 128u) | (ud >> 5);
+  }
+  return key;
+}
+
 template <bool DEVRNG, bool BATCH>
 __global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job* jobs,
                                                                  LeadJob* leads, uint32_t* keys) {
@@ -167,115 +281,30 @@ __global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job
   const float capf = a.hdr ? a.hdr->cap : a.cap;
   const int n_scn = a.hdr ? a.hdr->n_scn : a.n_scn;
   const int64_t i = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
-  if (i < n_all) {
-    // the sample's scenario and its index within it
-    uint32_t j = 0;
-    int64_t local = i;
-    if (BATCH) {
-      int lo = 0, hi = n_scn - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (a.tab[mid].off <= i)
-          lo = mid;
-        else
-          hi = mid - 1;
-      }
-      j = static_cast<uint32_t>(lo);
-      local = i - a.tab[lo].off;
-    }
-    const aeb_scenario& s = BATCH ? a.scns[j] : a.s;
-    const int nd = BATCH ? a.tab[j].nd : a.nd;
-    const int nmax = BATCH ? a.tab[j].nmax : a.nmax;
-    double v0, mu, mass, sg, cg, cda, crr, tau, gap, lead, trig, lw;
-    if (DEVRNG) {
-      Sample q = draw_sample(s, static_cast<uint64_t>(local));
-      v0 = q.v0; mu = q.mu; mass = q.mass; sg = q.sin_grade; cg = q.cos_grade;
-      cda = q.cda; crr = q.crr; tau = q.tau; gap = q.gap; lead = q.lead_decel;
-      trig = q.trigger;
-      lw = q.log_w;
-    } else {
-      v0 = a.src.v0[i]; mu = a.src.mu[i]; mass = a.src.mass[i]; sg = a.src.sin_g[i];
-      cg = a.src.cos_g[i]; cda = a.src.cda[i]; crr = a.src.crr[i]; tau = a.src.tau[i];
-      gap = a.src.gap[i]; lead = a.src.lead[i];
-      trig = a.src.trig ? a.src.trig[i] : 0.0;
-      lw = a.src.logw ? a.src.logw[i] : 0.0;
-    }
-    // the importance-sampling weight goes straight to the sample's output
-    double* wout = BATCH ? a.tab[j].out.weight : a.weight;
-    if (wout) wout[local] = exp(lw);
-    // with perception every sample has its own command step
-    int ndl = nd;
-    if (a.nds) {
-      ndl = static_cast<int>(command_step(s, trig, nmax));
-      a.nds[i] = ndl;
-    }
-    const Consts k = derive(s, mu, mass, sg, cg, cda, crr);
-    Job J;
-    J.v0 = v0;
-    J.nkd = -k.kd;
-    J.c = k.c;
-    J.alim = k.alim;
-    J.kt = s.integrator == AEB_RK4 ? 1.0 / tau : s.dt / tau;  // Euler: dt/tau; RK4: 1/tau
-    J.gap = gap;
-    // |acc| <= min(|a_cmd|, |alim|) + kd vmax^2 + |c|, with vmax the largest
-    // speed the sample can reach (only a downhill pull can raise it)
-    const double creach = k.c < 0.0 ? -k.c : 0.0;
-    const double vmax = fabs(v0) + s.horizon * creach;
-    const double brake = fmin(fabs(s.a_cmd), fabs(k.alim));
-    J.dmax = (brake + fabs(k.kd) * vmax * vmax + fabs(k.c)) * 1.0001 + 1e-9;
-    // classify and predict
-    const bool limited = !(k.alim < s.a_cmd - 1e-6);
-    float td = static_cast<float>(ndl) * static_cast<float>(s.dt);
-    if (a.ctl && s.obstacle == AEB_OBS_LEAD) {
-      // approach until the full-brake threshold, for the sort only: a lead
-      // braking at `lead` from the ego's speed (closing speed lead t, gap
-      // closed by lead t^2 / 2)
-      const float T = static_cast<float>(s.ttc_brake), G = static_cast<float>(gap);
-      const float A = static_cast<float>(lead);
-      td += A > 0.0f ? sqrtf(T * T + 2.0f * G / A) - T : static_cast<float>(s.horizon);
-    }
-    float t, t_full = -1.0f;
-    if (a.ctl && s.obstacle != AEB_OBS_LEAD)
-      t = predict_ctl_stop_time(static_cast<float>(v0), static_cast<float>(gap),
-                                static_cast<float>(s.ttc_warn), static_cast<float>(s.ttc_brake),
-                                -static_cast<float>(s.a_warn), static_cast<float>(s.ctl_period),
-                                static_cast<float>(ndl) * static_cast<float>(s.dt),
-                                static_cast<float>(k.kd), static_cast<float>(k.c),
-                                static_cast<float>(k.alim), static_cast<float>(tau),
-                                static_cast<float>(s.a_cmd), &t_full);
-    else
-      t = predict_stop_time(static_cast<float>(v0), static_cast<float>(k.kd),
-                            static_cast<float>(k.c), static_cast<float>(k.alim),
-                            static_cast<float>(tau), static_cast<float>(s.a_cmd), td);
-    float steps = t / static_cast<float>(s.dt);
-    if (!(steps < static_cast<float>(nmax))) steps = static_cast<float>(nmax);
-    if (!(steps > 0.0f)) steps = 0.0f;
-    J.pred = steps;
-    J.scn = j;
-    jobs[i] = J;
-    if (leads) leads[i].decel = lead;
-    const uint32_t u = static_cast<uint32_t>(fminf(steps, capf) * (4096.0f / (capf + 1.0f)));
-    const uint32_t ud = 4095u - (u > 4095u ? 4095u : u);  // longest first
-    // within a coarse length bin: finer length; with perception 8 finer length
-    // levels, then the command step in 16-step bins, so a wavefront's lanes
-    // end close together and switch the command within a few steps of each
-    // other (each distinct switch step cuts the wavefront's blocks)
-    const uint32_t fine =
-        a.nds ? (((ud >> 3) & 7u) << 3) | ((static_cast<uint32_t>(ndl) >> 4) & 7u) : ud & 63u;
-    uint32_t key = ((ud >> 6) << 7) | (limited ? 0u : 64u) | fine;
-    // with the controller: first the tick of the predicted full-braking
-    // decision (modulo 64, latest first), so a wavefront's lanes reach the
-    // thresholds, where the noise can decide and the whole wavefront draws
-    // it, at the same ticks; then the class and the length in 128 levels, so
-    // that they also stop close together (each lane's stop takes the
-    // wavefront down the block ladder)
-    if (t_full >= 0.0f) {
-      const uint32_t tk =
-          static_cast<uint32_t>(t_full / static_cast<float>(s.ctl_period) + 0.5f) & 63u;
-      key = ((63u - tk) << 8) | (limited ? 0u : 128u) | (ud >> 5);
-    }
+  if (i < n_all) keys[i] = prep_sample<DEVRNG, BATCH>(a, i, capf, n_scn, jobs, leads);
+}
+
+// The plain method's prep (parameters from the columns: no draws, so nothing
+// for the compiler to hoist): PREP_PER samples per thread with the key
+// histogram in LDS, flushed with one atomic per key the block holds, so no
+// separate histogram pass.
+template <int NB>
+__global__ __launch_bounds__(PREP_BLOCK) void k_prep_cols(PrepArgs a, Job* jobs, LeadJob* leads,
+                                                          uint32_t* keys, uint32_t* ghist) {
+  __shared__ uint32_t hist[NB];
+  for (int j = threadIdx.x; j < NB; j += PREP_BLOCK) hist[j] = 0;
+  __syncthreads();
+  const int64_t base_i = static_cast<int64_t>(blockIdx.x) * PREP_SAMPLES;
+  for (int r = 0; r < PREP_PER; ++r) {
+    const int64_t i = base_i + r * PREP_BLOCK + threadIdx.x;
+    if (i >= a.n) break;
+    const uint32_t key = prep_sample<false, false>(a, i, a.cap, 0, jobs, leads);
     keys[i] = key;
+    atomicAdd(&hist[key], 1u);
   }
+  __syncthreads();
+  for (int j = threadIdx.x; j < NB; j += PREP_BLOCK)
+    if (hist[j]) atomicAdd(&ghist[j], hist[j]);
 }
 
 // Key histogram: per block of PREP_SAMPLES keys in LDS, then one global
@@ -2016,10 +2045,13 @@ size_t bufs_layout(int64_t n, int n_scn, bool lead, char* base, Bufs* b) {
 
 // sort the prepared keys into the permutation (the scan zeroes the claim counter)
 // (hdr: a recorded mix, n its capacity and the actual count on the device)
+// (hist: the key histogram still to be taken; the plain method's prep takes it)
 template <int NB = NBINS>
-void sort_keys(const Bufs& b, int64_t n, hipStream_t st, const BatchHdr* hdr = nullptr) {
+void sort_keys(const Bufs& b, int64_t n, hipStream_t st, const BatchHdr* hdr = nullptr,
+               bool hist = true) {
   const unsigned pblk = static_cast<unsigned>((n + PREP_SAMPLES - 1) / PREP_SAMPLES);
-  hipLaunchKernelGGL(k_hist<NB>, dim3(pblk), dim3(PREP_BLOCK), 0, st, b.keys, n, b.hist, hdr);
+  if (hist)
+    hipLaunchKernelGGL(k_hist<NB>, dim3(pblk), dim3(PREP_BLOCK), 0, st, b.keys, n, b.hist, hdr);
   hipLaunchKernelGGL(k_scan<NB>, dim3(1), dim3(PREP_BLOCK), 0, st, b.hist, b.counter);
   hipLaunchKernelGGL(k_scatter<NB>, dim3(pblk), dim3(PREP_BLOCK), 0, st, b.keys, n, b.hist,
                      b.perm, hdr);
@@ -2238,16 +2270,20 @@ int launch_rollout_fast_into(const aeb_scenario& s, const ParamSrc* src, int pre
   pa.nds = perception_on(s) ? b.nds : nullptr;
   pa.ctl = ctl ? 1 : 0;
   pa.weight = out.weight;
-  if (src)
-    hipLaunchKernelGGL((k_prep<false, false>), dim3(pblk), dim3(PREP_BLOCK), 0, st, pa, b.jobs,
-                       b.leads, b.keys);
+  const unsigned cblk = static_cast<unsigned>((n + PREP_SAMPLES - 1) / PREP_SAMPLES);
+  if (src && ctl)
+    hipLaunchKernelGGL(k_prep_cols<NBINS_CTL>, dim3(cblk), dim3(PREP_BLOCK), 0, st, pa, b.jobs,
+                       b.leads, b.keys, b.hist);
+  else if (src)
+    hipLaunchKernelGGL(k_prep_cols<NBINS>, dim3(cblk), dim3(PREP_BLOCK), 0, st, pa, b.jobs,
+                       b.leads, b.keys, b.hist);
   else
     hipLaunchKernelGGL((k_prep<true, false>), dim3(pblk), dim3(PREP_BLOCK), 0, st, pa, b.jobs,
                        b.leads, b.keys);
   if (ctl)
-    sort_keys<NBINS_CTL>(b, n, st);
+    sort_keys<NBINS_CTL>(b, n, st, nullptr, !src);
   else
-    sort_keys(b, n, st);
+    sort_keys(b, n, st, nullptr, !src);
   Ctx ctx{};
   ctx.dt = s.dt;
   ctx.a_cmd = s.a_cmd;
