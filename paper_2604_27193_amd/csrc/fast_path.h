@@ -38,7 +38,10 @@ struct BatchHdr {
 struct ScnDev {
   double dt, a_cmd;
   int nd, nmax;
-  long long off;  // first global sample index of the scenario
+  long long off;   // first global sample index of the scenario
+  long long poff;  // its first index in the batched prep's index space, where
+                   // every scenario starts on a multiple of 64 (one scenario
+                   // per wavefront)
   OutCols out;
 };
 

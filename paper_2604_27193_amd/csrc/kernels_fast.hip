@@ -160,24 +160,10 @@ struct PrepArgs {
 
 // One sample: its parameters (drawn, or loaded from the plain method's
 // columns), its job record and its sort key.
+// (i: global index; j, local: its scenario and its index there)
 template <bool DEVRNG, bool BATCH>
-HOT uint32_t prep_sample(const PrepArgs& a, int64_t i, float capf, int n_scn, Job* jobs,
-                         LeadJob* leads) {
-  // the sample's scenario and its index within it
-  uint32_t j = 0;
-  int64_t local = i;
-  if (BATCH) {
-    int lo = 0, hi = n_scn - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (a.tab[mid].off <= i)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    j = static_cast<uint32_t>(lo);
-    local = i - a.tab[lo].off;
-  }
+HOT uint32_t prep_sample(const PrepArgs& a, int64_t i, uint32_t j, int64_t local, float capf,
+                         Job* jobs, LeadJob* leads) {
   const aeb_scenario& s = BATCH ? a.scns[j] : a.s;
   const int nd = BATCH ? a.tab[j].nd : a.nd;
   const int nmax = BATCH ? a.tab[j].nmax : a.nmax;
@@ -280,8 +266,31 @@ __global__ __launch_bounds__(prep_threads<DEVRNG>()) void k_prep(PrepArgs a, Job
   const int64_t n_all = a.hdr ? a.hdr->total : a.n;
   const float capf = a.hdr ? a.hdr->cap : a.cap;
   const int n_scn = a.hdr ? a.hdr->n_scn : a.n_scn;
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
-  if (i < n_all) keys[i] = prep_sample<DEVRNG, BATCH>(a, i, capf, n_scn, jobs, leads);
+  if (!BATCH) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+    if (i < n_all) keys[i] = prep_sample<DEVRNG, false>(a, i, 0u, i, capf, jobs, leads);
+    return;
+  }
+  // A batch: the launch covers an index space where every scenario starts on
+  // a multiple of 64, so each wavefront holds samples of one scenario, found
+  // from the wavefront's first index: its table entry and scenario are then
+  // uniform (scalar loads, no per-lane copies of the scenario in registers).
+  const int64_t pw = static_cast<int64_t>(blockIdx.x) * NT +
+                     __builtin_amdgcn_readfirstlane(threadIdx.x & ~63u);
+  int lo = 0, hi = n_scn - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.tab[mid].poff <= pw)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const uint32_t j = static_cast<uint32_t>(lo);
+  const int64_t off = a.tab[j].off;
+  const int64_t n_j = (lo + 1 < n_scn ? a.tab[lo + 1].off : n_all) - off;
+  const int64_t local = pw - a.tab[j].poff + (threadIdx.x & 63);
+  if (local < n_j) keys[off + local] = prep_sample<DEVRNG, true>(a, off + local, j, local, capf,
+                                                                  jobs, leads);
 }
 
 // The plain method's prep (parameters from the columns: no draws, so nothing
@@ -298,7 +307,7 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_prep_cols(PrepArgs a, Job* jobs,
   for (int r = 0; r < PREP_PER; ++r) {
     const int64_t i = base_i + r * PREP_BLOCK + threadIdx.x;
     if (i >= a.n) break;
-    const uint32_t key = prep_sample<false, false>(a, i, a.cap, 0, jobs, leads);
+    const uint32_t key = prep_sample<false, false>(a, i, 0u, i, a.cap, jobs, leads);
     keys[i] = key;
     atomicAdd(&hist[key], 1u);
   }
@@ -2310,7 +2319,7 @@ size_t batch_scratch_bytes(int64_t total, int n_scn, bool lead) {
 
 int fill_batch_table(const aeb_scenario* scns, int n_scn, const OutCols* outs, ScnDev* tab,
                      int64_t* total_out, int64_t* cap_out) {
-  int64_t total = 0, cap = 1;
+  int64_t total = 0, cap = 1, padded = 0;
   for (int j = 0; j < n_scn; ++j) {
     const int64_t nd = dead_steps(scns[j]), nmax = horizon_steps(scns[j]);
     if (!block_steps_ok(scns[j]))
@@ -2320,8 +2329,10 @@ int fill_batch_table(const aeb_scenario* scns, int n_scn, const OutCols* outs, S
     tab[j].nd = static_cast<int>(nd);
     tab[j].nmax = static_cast<int>(nmax);
     tab[j].off = total;
+    tab[j].poff = padded;
     tab[j].out = outs[j];
     total += scns[j].n_samples;
+    padded += (scns[j].n_samples + 63) & ~int64_t(63);
     if (nmax > cap) cap = nmax;
   }
   if (total > 0xffffffffLL) return fail(AEB_EINVAL, "a batch holds at most 2^32 - 1 samples");
@@ -2338,7 +2349,9 @@ int launch_batch_fast_into(const aeb_scenario* scns, int n_scn, int precision,
   bufs_layout(total, n_scn, lead, static_cast<char*>(scratch_base), &b);
   AEB_HIP(hipMemcpyAsync(b.tab, tab, sizeof(ScnDev) * n_scn, hipMemcpyHostToDevice, st));
   AEB_HIP(hipMemcpyAsync(b.scns, scns, sizeof(aeb_scenario) * n_scn, hipMemcpyHostToDevice, st));
-  const unsigned pblk = prep_grid(total);
+  // the prep's index space: each scenario padded to a multiple of 64 samples
+  const int64_t padded = tab[n_scn - 1].poff + ((scns[n_scn - 1].n_samples + 63) & ~int64_t(63));
+  const unsigned pblk = prep_grid(padded);
   hipLaunchKernelGGL(k_zero, dim3(NBINS / 256), dim3(256), 0, st, b.hist, int64_t(NBINS));
   PrepArgs pa{};
   pa.n = total;
@@ -2365,7 +2378,9 @@ int launch_batch_fast_dev(const aeb_scenario& kind, bool perception, int precisi
   const bool lead = kind.obstacle == AEB_OBS_LEAD;
   Bufs b;
   bufs_layout(cap_total, 0, lead, static_cast<char*>(scratch_base), &b);
-  const unsigned pblk = prep_grid(cap_total);
+  // the prep's index space for any mix within the capacity (each scenario
+  // padded to a multiple of 64 samples)
+  const unsigned pblk = prep_grid(cap_total + 63 * static_cast<int64_t>(cap_scn));
   hipLaunchKernelGGL(k_zero, dim3(NBINS / 256), dim3(256), 0, st, b.hist, int64_t(NBINS));
   PrepArgs pa{};
   pa.n = cap_total;
