@@ -159,12 +159,24 @@ def time_graph_steps_two_streams(B, torch, d, params, precision, outs, steps, wa
     return pipeline_graphs(torch, gs, steps, warmup)
 
 
+_PIPE_STREAMS = []
+
+
+def pipe_streams(torch):
+    """The two streams every pipelined measurement uses: one pair for the
+    process (a pair taken later from torch's pool can share a hardware queue
+    with streams in use before, which serialises the two)."""
+    if not _PIPE_STREAMS:
+        _PIPE_STREAMS.extend([torch.cuda.Stream(), torch.cuda.Stream()])
+    return _PIPE_STREAMS
+
+
 def pipeline_graphs(torch, gs, steps, warmup):
     """Replays two recorded graphs (own outputs and scratch each) alternately
     on two streams, launching step k+1 before collecting step k; closes the
     graphs.  Returns the wall time of `steps` steps, the statistics of the
     last and whether every step's statistics equal it."""
-    ss = [torch.cuda.Stream(), torch.cuda.Stream()]
+    ss = pipe_streams(torch)
     for k in range(max(warmup, 2)):
         gs[k % 2].launch(ss[k % 2])
         gs[k % 2].finish(ss[k % 2])
