@@ -715,7 +715,10 @@ def saturated_leg(B, W, torch, seconds, depth=64):
     form delivers when the device never idles, its latency under that load,
     and the FP32C statistics against the FP64 ones of the same requests."""
     import numpy as np
-    reqs = [(d, dl) for _, d, dl in W.serving_stream(800, duration=120.0, seed=4242)]
+    # enough requests that neither form runs out within the window (800 per
+    # second of arrivals for 30 s per second of window: ~2.2e9 samples per
+    # second of window, above what either form serves)
+    reqs = [(d, dl) for _, d, dl in W.serving_stream(800, duration=30.0 * seconds, seed=4242)]
     res = {"workload": "serving mix, requests back to back, %d in flight" % depth,
            "seconds": seconds}
     stats = {}
@@ -748,7 +751,8 @@ def saturated_leg(B, W, torch, seconds, depth=64):
         lat = np.array([tm["done"] - tm["arrive"] for _, tm in in_window.values()])
         res[prec] = {"requests": len(in_window), "rollouts_per_s": samples / (t_stop - t0),
                      "p50_ms": float(np.percentile(lat, 50) * 1e3),
-                     "p99_ms": float(np.percentile(lat, 99) * 1e3)}
+                     "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                     "requests_ran_out": k >= len(reqs)}
         stats[prec] = {j: st for j, (st, _) in done.items()}
         log(f"bench: saturated {prec}: {res[prec]}")
     common = sorted(set(stats["fp32c"]) & set(stats["fp64"]))
