@@ -57,12 +57,14 @@ constexpr int NBINS_CTL = 16384;
 constexpr int PREP_BLOCK = 256;
 constexpr int PREP_SAMPLES = 4096;                     // samples per scatter block
 constexpr int PREP_PER = PREP_SAMPLES / PREP_BLOCK;    // samples per scatter thread
-// The prep kernel takes one sample per thread, and the key histogram is a
-// kernel of its own.  (A loop over several samples per thread, to share a
-// block histogram's flush, let the compiler hoist the constants of the draws'
-// log, sqrt, sine and cosine out of the loop and hold them in registers: 231
-// VGPRs, two wavefronts per SIMD, against 118 without it; and a block
-// histogram per 256 samples costs more than the draws save.)
+// The drawing prep kernel takes one sample per thread, and its key histogram
+// is a kernel of its own.  (A loop over several samples per thread, to share
+// a block histogram's flush, let the compiler hoist the constants of the
+// draws' log, sqrt, sine and cosine out of the loop and hold them in
+// registers: 231 VGPRs, two wavefronts per SIMD, against 113 without it; and
+// a block histogram per 256 samples costs more than the draws save.)  The
+// plain method's prep, which draws nothing, keeps PREP_PER samples per thread
+// with the histogram fused in (k_prep_cols).
 inline unsigned prep_grid(int64_t n) {
   return static_cast<unsigned>((n + PREP_BLOCK - 1) / PREP_BLOCK);
 }
