@@ -398,6 +398,18 @@ int aeb_timing_lanes(uint64_t* wave_sample_steps);
  * memory; synchronises `stream`. */
 int aeb_ctl_approx_check(double* measured, double* bounds, void* stream);
 
+/* The natural logarithm, sine and cosine that the controller's exact-stage
+ * decision uses (the measurement noise's Box-Muller radius and angle, Sec.
+ * VIII's controller), written for the arguments that reach them (a in
+ * [2^-53, 1], x in [0, 2 pi)) and accurate to within an ulp there.  For i <
+ * n: log_a[i] = log(a[i]), sin_x[i] = sin(x[i]), cos_x[i] = cos(x[i]).  With
+ * on_device the five arrays are device memory and the call is asynchronous on
+ * `stream`; otherwise they are host memory and the host evaluates the same
+ * arithmetic (the results are meant to be the same bits).  n = 0 does
+ * nothing; n < 0 or a null array with n > 0 returns AEB_EINVAL. */
+int aeb_ctl_math(const double* a, const double* x, int64_t n, double* log_a, double* sin_x,
+                 double* cos_x, int on_device, void* stream);
+
 /* Metric of the exact order statistics (Sec. VI-C headways, margin
  * quantiles): the number of reductions (aeb_reduce, aeb_batch_reduce per set,
  * graphs, serving) since the library was loaded whose selection fell back

@@ -14,7 +14,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libaeb.so")
-ABI_VERSION = 8     # the aeb_version() these structures match
+ABI_VERSION = 9     # the aeb_version() these structures match
 NOALLOC_SCRATCH_BYTES = 32 << 20  # AEB_NOALLOC_SCRATCH_BYTES of aeb.h
 SERVE_EAGER = 1                   # AEB_SERVE_EAGER of aeb.h
 
@@ -37,7 +37,7 @@ END_STOP, END_IMPACT, END_HORIZON, COLLIDED, BOUNDARY = 1, 2, 3, 4, 8
 EXPORTS = ("aeb_last_error", "aeb_version", "aeb_validate", "aeb_uniforms", "aeb_sample_params",
            "aeb_rollout", "aeb_rollout_noalloc", "aeb_reduce", "aeb_batch_rollout",
            "aeb_batch_reduce",
-           "aeb_timing_enable", "aeb_timing_last", "aeb_timing_lanes", "aeb_reduce_fallbacks", "aeb_ctl_approx_check",
+           "aeb_timing_enable", "aeb_timing_last", "aeb_timing_lanes", "aeb_reduce_fallbacks", "aeb_ctl_approx_check", "aeb_ctl_math",
            "aeb_server_fixed_bytes",
            "aeb_serve_footprint", "aeb_server_create", "aeb_server_destroy", "aeb_serve_submit",
            "aeb_serve_poll", "aeb_server_info_get", "aeb_graph_create", "aeb_graph_create_batch",
@@ -154,6 +154,8 @@ def lib():
         L.aeb_reduce_fallbacks.argtypes = [P(C.c_uint64)]
         L.aeb_timing_lanes.argtypes = [P(C.c_uint64)]
         L.aeb_ctl_approx_check.argtypes = [P(C.c_double), P(C.c_double), C.c_void_p]
+        L.aeb_ctl_math.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_int, C.c_void_p]
         L.aeb_server_fixed_bytes.argtypes = [P(ServerCfg), P(C.c_uint64)]
         L.aeb_serve_footprint.argtypes = [P(ServerCfg), C.c_int64, P(C.c_uint64)]
         L.aeb_server_create.argtypes = [P(ServerCfg), P(C.c_void_p)]
@@ -403,6 +405,31 @@ def ctl_approx_check(stream=None):
     b = (C.c_double * 4)()
     _check(lib().aeb_ctl_approx_check(m, b, _stream(stream)))
     return tuple(m), tuple(b)
+
+
+def ctl_math(a, x, device=False, stream=None):
+    """The controller exact stage's (log a, sin x, cos x), evaluated by the
+    library on the host (numpy float64 arrays in and out) or on the device
+    (torch float64 CUDA tensors in and out)."""
+    if device:
+        torch = _torch()
+        a = a.contiguous()
+        x = x.contiguous()
+        if a.dtype != torch.float64 or x.dtype != torch.float64 or a.numel() != x.numel():
+            raise ValueError("ctl_math: two float64 tensors of one size")
+        outs = [torch.empty_like(a) for _ in range(3)]
+        _check(lib().aeb_ctl_math(a.data_ptr(), x.data_ptr(), a.numel(),
+                                  *[o.data_ptr() for o in outs], 1, _stream(stream)))
+        return tuple(outs)
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if a.shape != x.shape:
+        raise ValueError("ctl_math: two arrays of one size")
+    outs = [np.empty_like(a) for _ in range(3)]
+    _check(lib().aeb_ctl_math(a.ctypes.data, x.ctypes.data, a.size,
+                              *[o.ctypes.data for o in outs], 0, None))
+    return tuple(outs)
 
 
 def timing_lanes():

@@ -15,6 +15,7 @@
 
 #include "aeb.h"
 #include "aeb_common.h"
+#include "ctl_math.h"
 #include "aeb_runtime.h"
 
 namespace aeb {
@@ -401,7 +402,7 @@ extern "C" {
 
 const char* aeb_last_error(void) { return g_err.c_str(); }
 
-int aeb_version(void) { return 8; }
+int aeb_version(void) { return 9; }
 
 int aeb_timing_enable(int on) {
   g_timing.on = on != 0;
@@ -419,6 +420,19 @@ int aeb_reduce_fallbacks(uint64_t* count) {
 int aeb_ctl_approx_check(double* measured, double* bounds, void* stream) {
   if (!measured || !bounds) return fail(AEB_EINVAL, "aeb_ctl_approx_check: null argument");
   return launch_approx_check(measured, bounds, static_cast<hipStream_t>(stream));
+}
+
+int aeb_ctl_math(const double* a, const double* x, int64_t n, double* log_a, double* sin_x,
+                 double* cos_x, int on_device, void* stream) {
+  if (n < 0 || (n > 0 && (!a || !x || !log_a || !sin_x || !cos_x)))
+    return fail(AEB_EINVAL, "aeb_ctl_math: bad argument");
+  if (on_device)
+    return launch_ctl_math(a, x, n, log_a, sin_x, cos_x, static_cast<hipStream_t>(stream));
+  for (int64_t i = 0; i < n; ++i) {
+    log_a[i] = ctl_log(a[i]);
+    ctl_sincos(x[i], &sin_x[i], &cos_x[i]);
+  }
+  return AEB_OK;
 }
 
 int aeb_timing_lanes(uint64_t* wave_sample_steps) {

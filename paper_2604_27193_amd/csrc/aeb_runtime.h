@@ -91,6 +91,8 @@ struct OutCols {
 // Largest errors of the controller screen's single-precision approximations
 // over their whole input ranges (measured[4]) and the bounds the screen
 // assumes for them (bounds[4]): log2, sqrt, sin, cos.  Synchronises `st`.
+int launch_ctl_math(const double* a, const double* x, int64_t n, double* la, double* sx,
+                    double* cx, hipStream_t st);
 int launch_approx_check(double* measured, double* bounds, hipStream_t st);
 
 int launch_uniforms(uint64_t seed, uint64_t sid, int64_t first, int64_t count, uint32_t slot,

@@ -1,4 +1,5 @@
-// approx_check.hip -- measures, on the device, the largest errors of the
+// approx_check.hip -- self-checks of the controller's decision arithmetic.
+// Measures, on the device, the largest errors of the
 // single-precision hardware approximations the controller's decision screen
 // uses (rollout_steps.h, ctl_fast), over every input that can reach them:
 //   log2:  v_log_f32(a) against log2(a), relative to max(1, |log2 a|), for
@@ -10,6 +11,8 @@
 // References in double precision (log2, sqrt, sinpi and cospi of 2b: no
 // rounded multiple of pi).  One thread per input, grid-stride; the maxima of
 // non-negative doubles are kept as their bit patterns (which order the same).
+// Also evaluates the exact stage's own log, sine and cosine at given
+// arguments, so that a test can hold the device's results against the host's.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -73,7 +76,25 @@ __global__ __launch_bounds__(256) void k_check_sqrt(unsigned long long* out) {
   block_max(er, out + 1);
 }
 
+// the exact stage's log, sine and cosine at given arguments (ctl_math.h)
+__global__ __launch_bounds__(256) void k_ctl_math(const double* a, const double* x, int64_t n,
+                                                  double* la, double* sx, double* cx) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  la[i] = ctl_log(a[i]);
+  ctl_sincos(x[i], &sx[i], &cx[i]);
+}
+
 }  // namespace
+
+int launch_ctl_math(const double* a, const double* x, int64_t n, double* la, double* sx,
+                    double* cx, hipStream_t st) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_ctl_math, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st,
+                       a, x, n, la, sx, cx);
+  AEB_HIP(hipGetLastError());
+  return AEB_OK;
+}
 
 int launch_approx_check(double* measured, double* bounds, hipStream_t st) {
   unsigned long long* d = nullptr;

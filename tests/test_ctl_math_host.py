@@ -34,3 +34,34 @@ def test_ctl_math_within_one_ulp(tmp_path):
     assert set(worst) == {"log", "sin", "cos"}, out.stdout
     for name, e in worst.items():
         assert e < 1.0, (name, out.stdout)
+
+
+def _args(n, seed):
+    """Arguments as the controller draws them: uniforms (k + 1/2) 2^-52 and
+    angles 2 pi u, plus the range ends and the neighbourhoods of 1/2, sqrt(1/2)
+    and the multiples of pi/4."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    k = rng.integers(0, 1 << 52, size=n, dtype=np.uint64)
+    u = (k.astype(np.float64) + 0.5) * 2.0 ** -52
+    edges_a = [2.0 ** -53, 1.0 - 2.0 ** -53, 0.5, np.sqrt(0.5)]
+    edges_a += list(np.nextafter(np.sqrt(0.5), [0.0, 1.0])) + list(np.nextafter(0.5, [0.0, 1.0]))
+    edges_x = [q * np.pi / 4 for q in range(8)] + [np.nextafter(q * np.pi / 4, 7.0) for q in range(1, 8)]
+    a = np.concatenate([u, edges_a])
+    xs = 6.283185307179586 * rng.permutation(u)
+    x = np.concatenate([xs[:n - len(edges_x)], edges_x, np.full(len(edges_a), 1.0)])
+    return a, x
+
+
+def test_library_host_evaluation_within_libm_rounding():
+    """The library's host evaluation (aeb_ctl_math) against numpy's double
+    functions: both round to within an ulp of the true value, so they differ
+    by at most a few ulps anywhere and agree on almost every argument."""
+    import numpy as np
+    from paper_2604_27193_amd import binding as B
+    a, x = _args(200_000, 11)
+    la, sx, cx = B.ctl_math(a, x)
+    for got, want in ((la, np.log(a)), (sx, np.sin(x)), (cx, np.cos(x))):
+        ulps = np.abs(got - want) / np.spacing(np.abs(want))
+        assert np.nanmax(ulps) <= 2.0
+        assert np.mean(got == want) > 0.9
