@@ -410,6 +410,16 @@ int aeb_ctl_approx_check(double* measured, double* bounds, void* stream);
 int aeb_ctl_math(const double* a, const double* x, int64_t n, double* log_a, double* sin_x,
                  double* cos_x, int on_device, void* stream);
 
+/* Diagnostic for the measurement (not the method): a kernel of known
+ * instruction counts, against which the VALU counters of a profiler are
+ * checked before they are read on the rollout kernels.  `threads` lanes (a
+ * multiple of 256) each run `iters` rounds of 8 independent fused
+ * multiply-adds in double precision (fp32 = 0) or single precision (fp32 !=
+ * 0), then add their 8 values up (7 adds, no multiplies); each lane writes
+ * its sum to out[lane] (device memory of `threads` doubles or floats).
+ * Asynchronous on `stream`; AEB_EINVAL for a bad size. */
+int aeb_valu_probe(int fp32, int64_t threads, int iters, void* out, void* stream);
+
 /* Metric of the exact order statistics (Sec. VI-C headways, margin
  * quantiles): the number of reductions (aeb_reduce, aeb_batch_reduce per set,
  * graphs, serving) since the library was loaded whose selection fell back

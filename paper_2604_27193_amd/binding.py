@@ -37,7 +37,7 @@ END_STOP, END_IMPACT, END_HORIZON, COLLIDED, BOUNDARY = 1, 2, 3, 4, 8
 EXPORTS = ("aeb_last_error", "aeb_version", "aeb_validate", "aeb_uniforms", "aeb_sample_params",
            "aeb_rollout", "aeb_rollout_noalloc", "aeb_reduce", "aeb_batch_rollout",
            "aeb_batch_reduce",
-           "aeb_timing_enable", "aeb_timing_last", "aeb_timing_lanes", "aeb_reduce_fallbacks", "aeb_ctl_approx_check", "aeb_ctl_math",
+           "aeb_timing_enable", "aeb_timing_last", "aeb_timing_lanes", "aeb_reduce_fallbacks", "aeb_ctl_approx_check", "aeb_ctl_math", "aeb_valu_probe",
            "aeb_server_fixed_bytes",
            "aeb_serve_footprint", "aeb_server_create", "aeb_server_destroy", "aeb_serve_submit",
            "aeb_serve_poll", "aeb_server_info_get", "aeb_graph_create", "aeb_graph_create_batch",
@@ -156,6 +156,7 @@ def lib():
         L.aeb_ctl_approx_check.argtypes = [P(C.c_double), P(C.c_double), C.c_void_p]
         L.aeb_ctl_math.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                    C.c_void_p, C.c_int, C.c_void_p]
+        L.aeb_valu_probe.argtypes = [C.c_int, C.c_int64, C.c_int, C.c_void_p, C.c_void_p]
         L.aeb_server_fixed_bytes.argtypes = [P(ServerCfg), P(C.c_uint64)]
         L.aeb_serve_footprint.argtypes = [P(ServerCfg), C.c_int64, P(C.c_uint64)]
         L.aeb_server_create.argtypes = [P(ServerCfg), P(C.c_void_p)]
@@ -430,6 +431,15 @@ def ctl_math(a, x, device=False, stream=None):
     _check(lib().aeb_ctl_math(a.ctypes.data, x.ctypes.data, a.size,
                               *[o.ctypes.data for o in outs], 0, None))
     return tuple(outs)
+
+
+def valu_probe(fp32, threads, iters, stream=None):
+    """Runs the counter-check kernel (aeb_valu_probe) and returns its output
+    tensor (one sum per lane)."""
+    torch = _torch()
+    out = torch.empty(threads, dtype=torch.float32 if fp32 else torch.float64, device="cuda")
+    _check(lib().aeb_valu_probe(1 if fp32 else 0, threads, iters, out.data_ptr(), _stream(stream)))
+    return out
 
 
 def timing_lanes():

@@ -435,6 +435,12 @@ int aeb_ctl_math(const double* a, const double* x, int64_t n, double* log_a, dou
   return AEB_OK;
 }
 
+int aeb_valu_probe(int fp32, int64_t threads, int iters, void* out, void* stream) {
+  if (!out || threads <= 0 || threads % 256 != 0 || threads / 256 > 0x7fffffff || iters < 0)
+    return fail(AEB_EINVAL, "aeb_valu_probe: bad argument");
+  return launch_valu_probe(fp32, threads, iters, out, static_cast<hipStream_t>(stream));
+}
+
 int aeb_timing_lanes(uint64_t* wave_sample_steps) {
   if (!wave_sample_steps) return fail(AEB_EINVAL, "aeb_timing_lanes: null argument");
   Timing& t = g_timing;

@@ -91,6 +91,7 @@ struct OutCols {
 // Largest errors of the controller screen's single-precision approximations
 // over their whole input ranges (measured[4]) and the bounds the screen
 // assumes for them (bounds[4]): log2, sqrt, sin, cos.  Synchronises `st`.
+int launch_valu_probe(int fp32, int64_t threads, int iters, void* out, hipStream_t st);
 int launch_ctl_math(const double* a, const double* x, int64_t n, double* la, double* sx,
                     double* cx, hipStream_t st);
 int launch_approx_check(double* measured, double* bounds, hipStream_t st);

@@ -12,7 +12,9 @@
 // rounded multiple of pi).  One thread per input, grid-stride; the maxima of
 // non-negative doubles are kept as their bit patterns (which order the same).
 // Also evaluates the exact stage's own log, sine and cosine at given
-// arguments, so that a test can hold the device's results against the host's.
+// arguments, so that a test can hold the device's results against the host's,
+// and runs a kernel of known instruction counts for checking the VALU
+// counters' accounting.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -85,7 +87,41 @@ __global__ __launch_bounds__(256) void k_ctl_math(const double* a, const double*
   ctl_sincos(x[i], &sx[i], &cx[i]);
 }
 
+// Counter check: a kernel of known instruction counts, to verify how the
+// VALU counters account fused multiply-adds, adds and multiplies before they
+// are used on the rollout kernels.  Every lane runs `iters` rounds of CH
+// independent fused multiply-adds, then adds its CH values up (CH - 1 adds);
+// its initial values are integer conversions, no floating-point arithmetic.
+constexpr int PROBE_CH = 8;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_valu_probe(T* out, int iters, T a, T b) {
+  T x[PROBE_CH];
+#pragma unroll
+  for (int c = 0; c < PROBE_CH; ++c) x[c] = static_cast<T>(static_cast<int>(threadIdx.x) + c);
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int c = 0; c < PROBE_CH; ++c) x[c] = fma(x[c], a, b);
+  }
+  T s = x[0];
+#pragma unroll
+  for (int c = 1; c < PROBE_CH; ++c) s = s + x[c];
+  out[static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x] = s;
+}
+
 }  // namespace
+
+int launch_valu_probe(int fp32, int64_t threads, int iters, void* out, hipStream_t st) {
+  const dim3 grid(static_cast<unsigned>(threads / 256));
+  if (fp32)
+    hipLaunchKernelGGL(k_valu_probe<float>, grid, dim3(256), 0, st, static_cast<float*>(out),
+                       iters, 0.999f, 1e-3f);
+  else
+    hipLaunchKernelGGL(k_valu_probe<double>, grid, dim3(256), 0, st, static_cast<double*>(out),
+                       iters, 0.999, 1e-3);
+  AEB_HIP(hipGetLastError());
+  return AEB_OK;
+}
 
 int launch_ctl_math(const double* a, const double* x, int64_t n, double* la, double* sx,
                     double* cx, hipStream_t st) {

@@ -1,6 +1,8 @@
 """The controller exact stage's log, sine and cosine evaluated on the device
 give the host's bits (aeb_ctl_math both ways): the host test's accuracy
-measurement of that arithmetic then holds for the kernels."""
+measurement of that arithmetic then holds for the kernels.  Also the
+counter-check kernel (aeb_valu_probe) that the VALU counters' accounting is
+verified on."""
 import numpy as np
 import pytest
 
@@ -28,3 +30,21 @@ def test_empty_and_bad_arguments():
     with pytest.raises(ValueError):
         B.ctl_math(torch.zeros(3, dtype=torch.float64, device="cuda"),
                    torch.zeros(4, dtype=torch.float64, device="cuda"), device=True)
+
+
+def test_counter_check_kernel():
+    """aeb_valu_probe (the counter-check kernel) runs in both precisions and
+    computes what its arithmetic says: 8 chains of x <- 0.999 x + 1e-3 from
+    x = lane + c, summed."""
+    import torch
+    from paper_2604_27193_amd import binding as B
+    for fp32 in (False, True):
+        out = B.valu_probe(fp32, 1024, 10).cpu().numpy().astype(np.float64)
+        lane = np.arange(1024) % 256
+        x = np.stack([lane + c for c in range(8)]).astype(np.float64)
+        for _ in range(10):
+            x = 0.999 * x + 1e-3
+        want = x.sum(axis=0)
+        assert np.allclose(out, want, rtol=1e-5 if fp32 else 1e-12)
+    with pytest.raises(B.AebError):
+        B.valu_probe(False, 1000, 1)  # not a multiple of 256
