@@ -857,6 +857,7 @@ def main():
     achieved = flops64 / kavg64 / 1e12
     prof_us = profile_field("rollout_fp64_1M_kernel_stats.md", "k_roll_fp64_avg_us")
     issued = profile_field("rollout_valu_counters_1M.md", "issued_fp64_flop_per_step")
+    arith = profile_field("rollout_valu_counters_1M.md", "fp64_arith_per_lane_step")
     cycles = profile_field("rollout_valu_counters_1M.md", "cycles_per_launch")
     issue = profile_field("rollout_valu_counters_1M.md", "valu_issue_fraction")
     roofline = {
@@ -887,6 +888,12 @@ def main():
         "frac_per_cycle": (flops64 / (cycles * FP64_FLOP_PER_CYCLE)
                            if (cycles and n == 1_048_576) else None),
         "valu_issue_fraction": issue if n == 1_048_576 else None,
+        # the instruction-mix ceiling: 11 flop per step over the FP64 arithmetic
+        # instructions a step issues (counters), against 2 flop per FMA; and
+        # the fraction of that ceiling the kernel reaches
+        "mix_ceiling": (EULER_FLOPS_PER_STEP / (2.0 * arith) if arith else None),
+        "frac_of_mix_ceiling": (achieved / FP64_VECTOR_PEAK_TFLOPS
+                                / (EULER_FLOPS_PER_STEP / (2.0 * arith)) if arith else None),
         # lane efficiency of the last timed launch (aeb_timing_lanes): the
         # fraction of the kernel's lane-steps that advanced a sample
         "lane_efficiency": LANES.get(("fp64", n, False), {}).get("lane_efficiency"),
