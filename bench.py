@@ -573,6 +573,20 @@ def uneven_config_leg(B, W, torch, reps=3):
             st_e = B.batch_reduce(B.batch_rollout(scns, precision="fp32c", outs=outs),
                                   risk=RISK, margin_q=MARGIN_Q, grid=GRID)
         eager_ms = (time.perf_counter() - t0) / reps * 1e3
+        # the batched integration kernel alone (library HIP events) and its
+        # lane accounting: FP32C rate against the unpacked and packed peaks
+        steps_total = sum(int(o["steps"].long().sum().item()) for o in outs)
+        B.timing_enable(True)
+        try:
+            ks = []
+            for _ in range(reps):
+                B.batch_rollout(scns, precision="fp32c", outs=outs)
+                ks.append(B.timing_last())
+            wave = B.timing_lanes()
+        finally:
+            B.timing_enable(False)
+        kern_ms = float(np.median(ks))
+        tflops = FP32C_FLOPS_PER_STEP * steps_total / (kern_ms * 1e-3) / 1e12
         # one recorded graph of the same step
         g = B.Graph(scns, precision="fp32c", out=outs, risk=RISK, margin_q=MARGIN_Q, grid=GRID,
                     batch=True)
@@ -607,6 +621,11 @@ def uneven_config_leg(B, W, torch, reps=3):
                       "runner_up": ({"shape": list(ranked[1][0]), "ms": ranked[1][1]}
                                     if len(ranked) > 1 else None),
                       "candidates": len(ranked), "default_shape_ms": default_ms},
+            "kernel_ms": kern_ms, "kernel_rollouts_per_s": total / (kern_ms * 1e-3),
+            "steps_per_launch": steps_total, "achieved_tflops": tflops,
+            "frac_unpacked_fp32_peak": tflops / FP64_VECTOR_PEAK_TFLOPS,
+            "frac_packed_fp32_peak": tflops / FP32_VECTOR_PEAK_TFLOPS,
+            "lane_efficiency": steps_total / wave if wave else None,
             "eager_ms_per_step": eager_ms, "eager_rollouts_per_s": total / (eager_ms * 1e-3),
             "graph_ms_per_step": graph_ms, "graph_rollouts_per_s": total / (graph_ms * 1e-3),
             "graph_stats_equal_eager": same,
