@@ -601,6 +601,30 @@ __device__ inline LaneScn lane_scn(const Ctx& c, const Job& J, bool valid, uint3
   return r;
 }
 
+// A uniform value passed through an identity DPP move (quad_perm [0,1,2,3]):
+// the same bits, which the compiler then keeps in a vector register as a lane
+// value.  Measured on the compensated FP32 kernel with a stationary obstacle:
+// its scenario constants and limits as lane values (as in a batch) take 79
+// VGPRs instead of 85, six wavefronts per SIMD instead of five, and the
+// single-scenario launch runs 5-6 % faster.
+__device__ inline int lane_value(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, 0xe4, 0xf, 0xf, false);
+}
+
+__device__ inline double lane_value(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = lane_value(static_cast<int>(b)), hi = lane_value(static_cast<int>(b >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+__device__ inline LaneScn lane_values(LaneScn r) {
+  r.dt = lane_value(r.dt);
+  r.a_cmd = lane_value(r.a_cmd);
+  r.nd = lane_value(r.nd);
+  r.nmax = lane_value(r.nmax);
+  return r;
+}
+
 // Output columns and the sample's index in them (read only at the store, so
 // that the pointers are not held through the integration).
 template <bool BATCH>
@@ -1527,9 +1551,12 @@ __global__ __launch_bounds__(256) void k_roll_fp32c(const Job* __restrict__ jobs
     } else {
       J = Job{1.0, 0.0, 0.0, -1.0, 0.5, 1e30, 1.0, 0.0f, 0u};
     }
-    const LaneScn sc = lane_scn<BATCH>(ctx, J, valid, g);
+    // the scenario's constants and limits as lane values, also for one scenario
+    // (the limits then take the per-lane path: the same values in every lane)
+    const LaneScn sc = BATCH ? lane_scn<BATCH>(ctx, J, valid, g)
+                             : lane_values(lane_scn<BATCH>(ctx, J, valid, g));
     const int nd = sc.nd, nmax = sc.nmax;
-    const bool varnd = BATCH || ctx.nds;
+    const bool varnd = true;
     const int wnd = __builtin_amdgcn_readfirstlane(varnd ? wave_min(valid ? nd : INT_MAX) : nd);
     L32 c;  // (the speed read below is base + increment; the increment is 0 without compensation)
     c.dt = static_cast<float>(sc.dt);
