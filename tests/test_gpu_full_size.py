@@ -7,6 +7,8 @@ benchmark uses.
   1e-4 relative distance error, with every sample's absolute distance error
   inside the boundary band the kernel flags with (so that flags agree exactly
   outside the band);
+* the same workload with parameters drawn in the kernel, launched alone and
+  as a one-scenario batch: every output equal bit for bit, FP64 and FP32C;
 * the paper's Sec. IV-B preset (RK4) at 350,000 samples, the largest row of
   Table I, per sample and bit for bit;
 * the 1,000-scenario uneven batch (about 1.4e8 samples in one batched launch)
@@ -77,6 +79,19 @@ def test_full_size_fp32c_against_reference(B, full):
           f"boundary {nb}")
     fix = to_np(B.rollout(d, params=params, precision="fp32c_fixup"))
     check_fp32c(fix, ref, fixup=True)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_full_size_alone_equals_one_scenario_batch(B, prec):
+    """The single-scenario kernels (constants and limits read from the launch,
+    the FP32C form holding them as lane values) and the batched kernels
+    (read per lane from the scenario table) give every output of every sample
+    bit for bit, with the parameters drawn in the kernel."""
+    d = W.single(N_FULL)
+    alone = to_np(B.rollout(d, precision=prec))
+    got = to_np(B.batch_rollout([d], precision=prec)[0])
+    for k in alone:
+        assert np.array_equal(got[k].view(np.uint8), alone[k].view(np.uint8)), (prec, k)
 
 
 def test_paper_preset_rk4_350k_every_sample(B, orc):
